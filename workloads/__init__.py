@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs for the bimanual MPPI hot path.
+
+This module only *generates data*: scene descriptions (robot geometry,
+inertia densities, obstacles, goal), initial states and plan parameters.
+It holds none of the method's arithmetic (no kinematics, dynamics,
+contact, cost or MPPI update); both the FP64 oracle and the HIP library
+consume the plain dictionaries it returns and marshal them on their own.
+
+The scenes stand in for the paper's PerAct2-derived ball-lifting task
+(Sec. IV-B; experimental setup in Sec. V-A): two serial 7-joint arms
+facing each other along x, a free ball on a table plane, static
+axis-aligned boxes and a goal position for the ball.  The paper uses
+MuJoCo models of two UR5e arms that are not available here; the synthetic
+arms below (capsule links, seeded uniform densities) replace them.
+
+Recipe (seeds fixed):
+  * scene seed = 1000*config + index, numpy PCG64;
+  * link densities ~ U[800, 1200] kg/m^3 per link per arm;
+  * boxes: half extents ~ U[0.05, 0.15] per axis, centre x, y ~ U[-0.5, 0.5],
+    resting on the table (z = half height), rejection-sampled clear of the
+    arm/ball corridor at home pose, of the goal and of each other;
+  * noise seed = 0xC0FFEE + config.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Fixed robot description (synthetic 7-joint arm, capsule links).
+# Joint axes in link-local frames: 0 = x, 1 = y, 2 = z.
+ARM_AXES = (2, 1, 2, 1, 2, 1, 2)
+LINK_LEN = (0.15, 0.25, 0.10, 0.25, 0.10, 0.15, 0.06)
+LINK_RAD = (0.05, 0.05, 0.05, 0.05, 0.04, 0.04, 0.04)
+PAD_RAD = 0.04
+BASE_POS = ((-0.55, 0.0, 0.0), (0.55, 0.0, 0.0))
+# base yaw given as (cos, sin) so both consumers see exact values
+BASE_CS = ((1.0, 0.0), (-1.0, 0.0))
+# Home pose (same joint values for both arms; arm 2 is mirrored by its base
+# yaw).  Chosen by hand so that each pad sits ~5 cm outside a 0.1 m ball at
+# the origin, at ball-centre height.
+Q_HOME_ARM = (0.0, -0.093, 0.0, 2.46, 0.0, -0.012, 0.0)
+
+MAX_BOXES = 16
+STATE_DIM = 55  # q[14] qd[14] qdes[14] pb[3] quat[4] vb[3] wb[3]
+NU = 14
+
+# physics defaults (readings of the paper's unstated world model)
+PHYSICS = dict(
+    kp=100.0, kd=20.0, damp=0.5, armature=0.1, tau_max=150.0,
+    gravcomp=1, g=9.81,
+    mu=1.0, kappa=0.2, eps_r=0.01, n_pgs=20, n_cmax=8,
+    u_max=1.5,
+)
+COST = dict(
+    w_goal=1.0, w_eo=1.0, w_l=10.0, w_yz=1.0, w_s=0.01, w_c=10.0,
+    gamma=0.5, m_c=0.05, eps_frac=0.3,
+)
+
+# arm / ball corridor at home pose (xy rectangle boxes must stay clear of)
+_CORRIDOR = (-0.65, 0.65, -0.12, 0.12)
+
+
+def _box_ok(c, hh, boxes, goal, ball_r, clear=0.05):
+    x0, x1, y0, y1 = _CORRIDOR
+    # footprint vs corridor (expanded by `clear`)
+    if (c[0] + hh[0] + clear > x0 and c[0] - hh[0] - clear < x1 and
+            c[1] + hh[1] + clear > y0 and c[1] - hh[1] - clear < y1):
+        return False
+    # goal clearance: the goal point, grown by ball radius + clear, outside box
+    g = np.asarray(goal)
+    if np.all(np.abs(g - c) < hh + ball_r + clear):
+        return False
+    for (c2, h2) in boxes:
+        if np.all(np.abs(c[:2] - c2[:2]) < hh[:2] + h2[:2] + 0.02):
+            return False
+    return True
+
+
+def _sample_boxes(rng, n, goal, ball_r):
+    boxes = []
+    shrink = 1.0
+    tries = 0
+    while len(boxes) < n:
+        hh = rng.uniform(0.05, 0.15, size=3) * shrink
+        c = np.array([rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5), 0.0])
+        c[2] = hh[2]
+        if _box_ok(c, hh, boxes, goal, ball_r):
+            boxes.append((c, hh))
+        tries += 1
+        if tries % 300 == 0:
+            shrink *= 0.9
+        if tries > 20000:
+            raise RuntimeError("box placement failed")
+    return boxes
+
+
+def make_scene(config: int, index: int = 0, *, n_box=None, ball_r=None,
+               ball_m=None, goal=None, h=None, n_sub=None, **overrides):
+    """Seeded scene description for workload `config` (1..5), scene `index`.
+
+    Returns a plain dict of Python floats / lists / numpy arrays.
+    """
+    rng = np.random.Generator(np.random.PCG64(1000 * config + index))
+    density = rng.uniform(800.0, 1200.0, size=(2, 7))
+    if config in (1, 2, 3):
+        r, m = 0.1, 0.5
+        nb = {1: 0, 2: 3, 3: 8}[config]
+        hh, ns = (0.01, 2) if config == 1 else (0.002, 5)
+        if config == 1:
+            g = (0.0, 0.0, r + 0.3)
+        elif config == 2:
+            g = (0.0, 0.5, 0.3)
+        else:
+            ang = rng.uniform(-0.5, 0.5) + (math.pi / 2 if rng.uniform() < 0.5 else -math.pi / 2)
+            g = (0.8 * math.cos(ang), 0.8 * math.sin(ang), 0.25)
+    else:
+        r = rng.uniform(0.06, 0.14)
+        m = rng.uniform(0.2, 1.0)
+        nb = int(rng.integers(0, 13))
+        hh, ns = 0.002, 5
+        ang = rng.uniform(-0.5, 0.5) + (math.pi / 2 if rng.uniform() < 0.5 else -math.pi / 2)
+        dist = rng.uniform(0.3, 0.8)
+        g = (dist * math.cos(ang), dist * math.sin(ang), rng.uniform(0.15, 0.35))
+    if n_box is not None:
+        nb = n_box
+    if ball_r is not None:
+        r = ball_r
+    if ball_m is not None:
+        m = ball_m
+    if goal is not None:
+        g = tuple(goal)
+    if h is not None:
+        hh = h
+    if n_sub is not None:
+        ns = n_sub
+    boxes = _sample_boxes(rng, nb, g, r) if nb > 0 else []
+    scene = dict(
+        base_pos=np.array(BASE_POS, dtype=np.float64),
+        base_cs=np.array(BASE_CS, dtype=np.float64),
+        axes=np.array(ARM_AXES, dtype=np.int32),
+        link_len=np.array(LINK_LEN, dtype=np.float64),
+        link_rad=np.array(LINK_RAD, dtype=np.float64),
+        density=density,
+        pad_rad=PAD_RAD,
+        ball_r=float(r), ball_m=float(m),
+        ball_p0=np.array([0.0, 0.0, float(r)]),
+        n_box=len(boxes),
+        box_c=np.array([b[0] for b in boxes], dtype=np.float64).reshape(-1, 3),
+        box_h=np.array([b[1] for b in boxes], dtype=np.float64).reshape(-1, 3),
+        goal=np.array(g, dtype=np.float64),
+        h=float(hh), n_sub=int(ns),
+        q_home=np.array(Q_HOME_ARM * 2, dtype=np.float64),
+    )
+    scene.update(PHYSICS)
+    scene.update(COST)
+    for k, v in overrides.items():
+        if k not in scene:
+            raise KeyError(k)
+        scene[k] = v
+    return scene
+
+
+def initial_state(scene) -> np.ndarray:
+    """x0 = home pose at rest, PD target = home, ball at rest on the table."""
+    x = np.zeros(STATE_DIM, dtype=np.float64)
+    x[0:14] = scene["q_home"]
+    x[28:42] = scene["q_home"]
+    x[42:45] = scene["ball_p0"]
+    x[45] = 1.0  # quaternion (w, x, y, z)
+    return x
+
+
+PLAN = {
+    1: dict(K=64, H=20, M=5, lam=0.1, sigma=0.3),
+    2: dict(K=1024, H=64, M=10, lam=0.1, sigma=0.3),
+    3: dict(K=4096, H=100, M=10, lam=0.1, sigma=0.3),
+}
+
+
+def plan_params(config: int, **overrides):
+    """Plan parameters (K, H, M, lambda, sigma[14], eta, n_elite, seed)."""
+    if config in PLAN:
+        p = dict(PLAN[config])
+    else:
+        p = dict(K=1024, H=64, M=10, lam=0.1, sigma=0.3)
+    p.update(eta=1.0, n_elite=p["K"], seed=0xC0FFEE + config)
+    p.update(overrides)
+    p["sigma"] = np.full(NU, float(p["sigma"])) if np.ndim(p["sigma"]) == 0 else np.asarray(p["sigma"], dtype=np.float64)
+    return p
+
+
+def packed_scenes(n=32, config=4):
+    """Uneven batch: n independent scenes with K ~ U{256..4096}, H ~ U{32..128}."""
+    out = []
+    for i in range(n):
+        sc = make_scene(config, i)
+        rng = np.random.Generator(np.random.PCG64(77_000 + 1000 * config + i))
+        K = int(rng.integers(256, 4097))
+        H = int(rng.integers(32, 129))
+        out.append((sc, plan_params(config, K=K, H=H, M=10, seed=(0xC0FFEE + config) * 1000 + i)))
+    return out
+
+
+def random_states(scene, n, seed, spread=0.3, vel=0.5):
+    """Random perturbed states near home (for single-step parity tests)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = np.tile(initial_state(scene), (n, 1))
+    X[:, 0:14] += rng.uniform(-spread, spread, size=(n, 14))
+    X[:, 14:28] = rng.uniform(-vel, vel, size=(n, 14))
+    X[:, 28:42] = X[:, 0:14] + rng.uniform(-0.05, 0.05, size=(n, 14))
+    X[:, 42:45] += rng.uniform(-0.02, 0.02, size=(n, 3)) * np.array([1, 1, 0.5])
+    q = rng.normal(size=(n, 4))
+    X[:, 45:49] = q / np.linalg.norm(q, axis=1, keepdims=True)
+    X[:, 49:52] = rng.uniform(-0.2, 0.2, size=(n, 3))
+    X[:, 52:55] = rng.uniform(-1.0, 1.0, size=(n, 3))
+    return X
+
+
+def random_controls(n, H, seed, scale=1.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-scale, scale, size=(n, H, NU))
