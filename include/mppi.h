@@ -1,0 +1,214 @@
+/*
+ * mppi.h -- C ABI of the MI355X (gfx950) MPPI rollout library.
+ *
+ * The library computes the data-parallel hot path of the sampling-based
+ * bimanual planner of Hurova, Dan, Kruusamae and Singh, "Sampling-Based
+ * Optimization with Parallelized Physics Simulator for Bimanual
+ * Manipulation" (arXiv 2511.21264): K joint-velocity sequences are drawn
+ * from N(nu, Sigma) and projected onto the velocity box (Alg. 1, sampling
+ * and QP steps; Eqs. proj_cost/proj_bounds), rolled out through a
+ * rigid-body world (Eq. state_evol; two 7-joint arms, a free ball, static
+ * boxes, a table plane), scored by the ball-task cost (Sec. IV-B, with the
+ * collision cost of Eq. collision_cost), and folded into the exponentially
+ * weighted mean update (Eqs. mean_update, s_formula).
+ *
+ * Conventions shared by every call:
+ *   * Return value: MPPI_OK (0) or a negative MPPI_E_* code; the message of
+ *     the last failure on the calling thread is mppi_last_error().
+ *   * Ownership: the caller owns every array.  With MPPI_DEVICE_PTRS in the
+ *     flags, array arguments are device pointers on the context's device;
+ *     otherwise they are host pointers and the library stages them.
+ *     Scene handles own a device copy of the scene model; contexts own
+ *     scratch buffers, which grow on demand.
+ *   * Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls
+ *     enqueue on it; with host pointers they also synchronize it before
+ *     returning.  Device-pointer calls return once enqueued, except that
+ *     mppi_plan synchronizes when `stats` is non-NULL (to fill it) or when
+ *     MPPI_SYNC is set.
+ *   * State layout (MPPI_NX = 55 floats): q[14], qd[14], q_des[14] (PD
+ *     target), ball p[3], ball quaternion (w, x, y, z)[4], ball v[3], ball
+ *     angular velocity (world frame)[3].  Joint order: arm 1 joints 1..7,
+ *     arm 2 joints 1..7.  Controls are 14 joint velocities.
+ *   * Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef MPPI_H
+#define MPPI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPPI_OK 0
+#define MPPI_E_INVAL (-1)    /* bad argument: NULL, K < 1, H < 1, lambda <= 0, sigma < 0, non-finite input */
+#define MPPI_E_NOMEM (-2)    /* device allocation failed */
+#define MPPI_E_MODEL (-3)    /* bad scene: non-positive mass/density/size, too many boxes */
+#define MPPI_E_DIVERGED (-4) /* every sample non-finite in some iteration; U_new := nominal_U */
+#define MPPI_E_DEVICE (-5)   /* a HIP runtime call failed */
+#define MPPI_E_BUSY (-6)     /* admission refused (serving) */
+
+#define MPPI_NU 14
+#define MPPI_NX 55
+#define MPPI_MAX_BOXES 16
+#define MPPI_MAX_CONTACTS 16
+#define MPPI_MAX_PAIRS (76 + 15 * MPPI_MAX_BOXES)
+#define MPPI_MAX_K (1 << 20)
+#define MPPI_MAX_H 4096
+
+/* flags */
+#define MPPI_DEVICE_PTRS 1u     /* array arguments are device pointers */
+#define MPPI_SIGMA_PER_STEP 2u  /* sigma holds H x 14 values instead of 14 */
+#define MPPI_SYNC 4u            /* synchronize the stream before returning */
+#define MPPI_TIME_KERNELS 8u    /* time every rollout launch with HIP events (fills stats->rollout_ms) */
+#define MPPI_TRAJ 16u           /* mppi_simulate: write every post-step state, not only the last */
+
+/* Global geom ids (pair tables and AABB arrays use them): 0 ball,
+ * 1 table, 2 + 7*arm + g (g = 0..5 capsule of link g+1, g = 6 pad sphere on
+ * link 7), 16 + b box b. */
+#define MPPI_GEOM_BALL 0
+#define MPPI_GEOM_TABLE 1
+#define MPPI_GEOM_ARM 2
+#define MPPI_GEOM_BOX 16
+
+typedef struct mppi_ctx mppi_ctx;
+typedef struct mppi_scene mppi_scene;
+
+/* Scene description: plain data, copied by mppi_scene_create.
+ * Arms: joint i+1 sits link_len[i] along link i's local z axis; joint i
+ * rotates about local axis axes[i] (0 x, 1 y, 2 z); links 1..6 collide as
+ * capsules of radius link_rad[i], link 7 as a pad sphere of radius pad_rad at
+ * its tip; each link's inertia is a solid capsule of density[arm][i].  Arm
+ * bases at base_pos with yaw given as (cos, sin).  Ball: solid sphere.
+ * Boxes: static, axis-aligned (centre, half extents).  Table: plane z = 0.
+ * Physics (the paper fixes none of it; these are the world-model readings):
+ * substep h, n_sub substeps per control step; PD actuators (kp, kd, clamp
+ * tau_max) on an integrated position target, joint damping `damp`, rotor
+ * `armature`; gravcomp = 1 removes gravity from the arms; contacts with
+ * friction mu (4-edge pyramid), Baumgarte rate kappa, regularisation eps_r,
+ * n_pgs Gauss-Seidel sweeps, at most n_cmax (<= MPPI_MAX_CONTACTS)
+ * contacts.  Controls are clamped to |u| <= u_max.  Cost weights: goal
+ * distance, end-effector-to-ball alignment, end-effector distance, planar
+ * alignment, smoothness, collision; gamma of the barrier; m_c distance
+ * saturation; eps = eps_frac * ball_r vertical grasp offset. */
+typedef struct mppi_scene_desc {
+    double base_pos[2][3];
+    double base_cs[2][2];
+    int axes[7];
+    double link_len[7], link_rad[7], density[2][7];
+    double pad_rad;
+    double ball_r, ball_m;
+    int n_box;
+    double box_c[MPPI_MAX_BOXES][3], box_h[MPPI_MAX_BOXES][3];
+    double goal[3];
+    double h;
+    int n_sub;
+    double kp, kd, damp, armature, tau_max;
+    int gravcomp;
+    double g;
+    double mu, kappa, eps_r;
+    int n_pgs, n_cmax;
+    double u_max;
+    double w_goal, w_eo, w_l, w_yz, w_s, w_c, gamma, m_c, eps_frac;
+} mppi_scene_desc;
+
+/* Plan options.  M iterations of Alg. 1; seed of the Philox stream; eta
+ * learning rate of Eq. mean_update (1 = plain MPPI); n_elite elite-set size
+ * (<= 0 or >= K: every sample). */
+typedef struct mppi_opts {
+    int M;
+    uint64_t seed;
+    double eta;
+    int n_elite;
+    unsigned flags;
+} mppi_opts;
+
+/* Statistics of a plan (filled after the stream completes). */
+typedef struct mppi_stats {
+    double ess;            /* effective sample size (sum w)^2 / sum w^2, last iteration */
+    double c_min;          /* lowest finite cost, last iteration */
+    int best;              /* sample index of c_min */
+    int n_nonfinite;       /* samples with a non-finite cost, last iteration */
+    int diverged;          /* 1 if some iteration had no finite sample */
+    int iterations;
+    double cmin_iter[64];  /* c_min per iteration (first 64) */
+    double contacts;       /* total contacts over all substeps, all iterations */
+    double np_tests;       /* narrowphase evaluations (contacts + cost distances) */
+    double box_tests;      /* capsule-box evaluations among them */
+    double overflow;       /* substeps whose contact list hit n_cmax */
+    float rollout_ms;      /* summed rollout kernel time (MPPI_TIME_KERNELS) */
+    int rollout_launches;
+} mppi_stats;
+
+/* Create a context on HIP device `device` (or -1 = current device). */
+int mppi_ctx_create(int device, mppi_ctx **out);
+void mppi_ctx_destroy(mppi_ctx *ctx);
+const char *mppi_last_error(void);
+
+/* Validate `desc` and upload the derived model (link masses and inertias,
+ * candidate-pair table in canonical order) to the context's device.
+ * Errors: MPPI_E_INVAL (NULL), MPPI_E_MODEL (bad values), MPPI_E_NOMEM. */
+int mppi_scene_create(mppi_ctx *ctx, const mppi_scene_desc *desc, mppi_scene **out);
+void mppi_scene_destroy(mppi_scene *scene);
+/* Number of candidate pairs and of collision-cost pairs of a scene. */
+int mppi_scene_num_pairs(const mppi_scene *scene, int *n_pairs, int *n_cost_pairs);
+
+/* One MPPI plan (Alg. 1, M iterations from the same x0).
+ *   x0[MPPI_NX]: start state; nominal_U[H][14]: initial mean nu_0 (warm start);
+ *   K samples, horizon H; lambda: temperature (beta of Eq. s_formula);
+ *   sigma[14] (or [H][14] with MPPI_SIGMA_PER_STEP): per-joint standard
+ *   deviation of the diagonal covariance;
+ *   U_new[H][14]: receives nu_M; costs[K]: the last iteration's costs
+ *   (+INF for non-finite rollouts); stats: optional.
+ * Errors: MPPI_E_INVAL, MPPI_E_NOMEM, MPPI_E_DEVICE, MPPI_E_DIVERGED (only
+ * reported when the call synchronizes; U_new then holds nominal_U). */
+int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+              double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs,
+              mppi_stats *stats, void *stream);
+
+/* Roll out explicit control sequences (Alg. 1 rollout and cost steps).
+ *   X0: [n][MPPI_NX] start states (one per sample), or one state shared by
+ *   all samples when x0_shared != 0; U[n][H][14] controls (used as given,
+ *   not clamped); n_sub: substeps per control step (<= 0: the scene's);
+ *   costs[n] (nullable); terms[n][7] (nullable): unweighted sums of the cost
+ *   terms (goal, eef-obj, distance, planar, smooth, barrier, indicator);
+ *   X_out: [n][MPPI_NX] final states, or [n][H][MPPI_NX] with MPPI_TRAJ
+ *   (nullable). */
+int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0_shared, const float *U, int n,
+                  int H, int n_sub, float *costs, float *terms, float *X_out, unsigned flags, void *stream);
+
+/* The sampled, projected controls of iteration m:
+ *   U[K][H][14] = clamp(nu + sigma * z, +-u_max) with z the Philox normals
+ *   (z_out[K][H][14] nullable); words_out[K][H][16] (nullable) receives the
+ *   raw Philox4x32-10 words of counters (j, k, q, m), q = 0..3, key = seed. */
+int mppi_sample(mppi_ctx *ctx, const mppi_scene *scene, const float *nu, const float *sigma, uint64_t seed, int m,
+                int K, int H, float *U, float *z_out, uint32_t *words_out, unsigned flags, void *stream);
+
+/* The update of Eq. mean_update from given costs: the samples of iteration m
+ * are regenerated from (nu_in, sigma, seed); nu_out[H][14] (float) and
+ * nu_out64 (nullable, double) receive (1 - eta) nu + eta sum_j w_j u_j with
+ * w_j from Eq. s_formula over the n_elite lowest finite costs; weights[K]
+ * (nullable, double) the normalized weights.  Returns MPPI_E_DIVERGED (and
+ * nu_out = nu_in) when no cost is finite. */
+int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, const float *nu_in,
+                const float *sigma, uint64_t seed, int m, int K, int H, double lambda, double eta, int n_elite,
+                float *nu_out, double *nu_out64, double *weights, mppi_stats *stats, unsigned flags,
+                void *stream);
+
+/* Broadphase of the contact pass: for every candidate pair of the scene
+ * (canonical order), flags[p] = 1 when the closed AABBs of its geoms
+ * overlap after growing geom A's box by `margin`.  lo/hi: [n][16 + n_box][3]
+ * AABBs (geom ids above); flags: [n][n_pairs]. */
+int mppi_broadphase(mppi_ctx *ctx, const mppi_scene *scene, const float *lo, const float *hi, int n, float margin,
+                    int *flags, unsigned flags_in, void *stream);
+
+/* Narrowphase of every candidate pair at states X[n][MPPI_NX]: phi[n][P],
+ * normal[n][P][3] (from geom B to geom A), point[n][P][3]; and the geom
+ * AABBs lo/hi[n][16 + n_box][3] (nullable). */
+int mppi_narrowphase(mppi_ctx *ctx, const mppi_scene *scene, const float *X, int n, float *phi, float *normal,
+                     float *point, float *lo, float *hi, unsigned flags, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,325 @@
+"""Python binding of the MI355X MPPI rollout library (libmppi.so, C ABI in include/mppi.h).
+
+Argument marshalling only: every stage of the hot path (noise, projection,
+rollout, cost, weights, update) runs in the HIP kernels of the library.
+Arrays are torch tensors on the GPU (passed as device pointers, launched on
+the current torch stream) or numpy arrays (staged by the library).  The
+library must be built (``__graft_entry__.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from ._build import LIB_PATH, build  # noqa: F401
+
+NU = 14
+NX = 55
+MAX_BOXES = 16
+
+OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5, -6
+DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ = 1, 2, 4, 8, 16
+
+
+class MppiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mppi error {code}: {msg}")
+        self.code = code
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [
+        ("base_pos", C.c_double * 6),
+        ("base_cs", C.c_double * 4),
+        ("axes", C.c_int * 7),
+        ("link_len", C.c_double * 7),
+        ("link_rad", C.c_double * 7),
+        ("density", C.c_double * 14),
+        ("pad_rad", C.c_double),
+        ("ball_r", C.c_double), ("ball_m", C.c_double),
+        ("n_box", C.c_int),
+        ("box_c", C.c_double * (3 * MAX_BOXES)),
+        ("box_h", C.c_double * (3 * MAX_BOXES)),
+        ("goal", C.c_double * 3),
+        ("h", C.c_double), ("n_sub", C.c_int),
+        ("kp", C.c_double), ("kd", C.c_double), ("damp", C.c_double),
+        ("armature", C.c_double), ("tau_max", C.c_double),
+        ("gravcomp", C.c_int), ("g", C.c_double),
+        ("mu", C.c_double), ("kappa", C.c_double), ("eps_r", C.c_double),
+        ("n_pgs", C.c_int), ("n_cmax", C.c_int),
+        ("u_max", C.c_double),
+        ("w_goal", C.c_double), ("w_eo", C.c_double), ("w_l", C.c_double), ("w_yz", C.c_double),
+        ("w_s", C.c_double), ("w_c", C.c_double), ("gamma", C.c_double), ("m_c", C.c_double),
+        ("eps_frac", C.c_double),
+    ]
+
+
+class Opts(C.Structure):
+    _fields_ = [("M", C.c_int), ("seed", C.c_uint64), ("eta", C.c_double), ("n_elite", C.c_int),
+                ("flags", C.c_uint)]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("ess", C.c_double), ("c_min", C.c_double), ("best", C.c_int), ("n_nonfinite", C.c_int),
+        ("diverged", C.c_int), ("iterations", C.c_int), ("cmin_iter", C.c_double * 64),
+        ("contacts", C.c_double), ("np_tests", C.c_double), ("box_tests", C.c_double),
+        ("overflow", C.c_double), ("rollout_ms", C.c_float), ("rollout_launches", C.c_int),
+    ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "cmin_iter"}
+        d["cmin_iter"] = list(self.cmin_iter[: max(0, min(64, self.iterations))])
+        return d
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Load libmppi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "mppi_ctx_create": (C.c_int, [C.c_int, C.POINTER(_P)]),
+            "mppi_ctx_destroy": (None, [_P]),
+            "mppi_last_error": (C.c_char_p, []),
+            "mppi_scene_create": (C.c_int, [_P, C.POINTER(SceneDesc), C.POINTER(_P)]),
+            "mppi_scene_destroy": (None, [_P]),
+            "mppi_scene_num_pairs": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+            "mppi_plan": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts), _P, _P,
+                                    C.POINTER(Stats), _P]),
+            "mppi_simulate": (C.c_int, [_P, _P, _P, C.c_int, _P, C.c_int, C.c_int, C.c_int, _P, _P, _P, C.c_uint,
+                                        _P]),
+            "mppi_sample": (C.c_int, [_P, _P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, _P, _P, _P, C.c_uint,
+                                      _P]),
+            "mppi_update": (C.c_int, [_P, _P, _P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_double,
+                                      C.c_double, C.c_int, _P, _P, _P, C.POINTER(Stats), C.c_uint, _P]),
+            "mppi_broadphase": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_float, _P, C.c_uint, _P]),
+            "mppi_narrowphase": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, _P, _P, _P, C.c_uint, _P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise MppiError(rc, lib().mppi_last_error().decode())
+    return rc
+
+
+def _fill(arr, vals):
+    vals = np.asarray(vals, dtype=np.float64).ravel()
+    for i, v in enumerate(vals):
+        arr[i] = float(v)
+
+
+def scene_desc(sc: dict) -> SceneDesc:
+    """Marshal a scene dictionary (see workloads.make_scene) into mppi_scene_desc."""
+    d = SceneDesc()
+    _fill(d.base_pos, sc["base_pos"])
+    _fill(d.base_cs, sc["base_cs"])
+    for i, a in enumerate(sc["axes"]):
+        d.axes[i] = int(a)
+    _fill(d.link_len, sc["link_len"])
+    _fill(d.link_rad, sc["link_rad"])
+    _fill(d.density, sc["density"])
+    d.pad_rad = float(sc["pad_rad"])
+    d.ball_r, d.ball_m = float(sc["ball_r"]), float(sc["ball_m"])
+    d.n_box = int(sc["n_box"])
+    if d.n_box > MAX_BOXES:
+        raise ValueError("too many boxes")
+    if d.n_box:
+        _fill(d.box_c, sc["box_c"])
+        _fill(d.box_h, sc["box_h"])
+    _fill(d.goal, sc["goal"])
+    d.h, d.n_sub = float(sc["h"]), int(sc["n_sub"])
+    for k in ("kp", "kd", "damp", "armature", "tau_max", "g", "mu", "kappa", "eps_r", "u_max",
+              "w_goal", "w_eo", "w_l", "w_yz", "w_s", "w_c", "gamma", "m_c", "eps_frac"):
+        setattr(d, k, float(sc[k]))
+    d.gravcomp = int(sc["gravcomp"])
+    d.n_pgs = int(sc["n_pgs"])
+    d.n_cmax = int(sc["n_cmax"])
+    return d
+
+
+def _is_dev(a):
+    try:
+        import torch
+        return isinstance(a, torch.Tensor) and a.is_cuda
+    except ImportError:  # pragma: no cover
+        return False
+
+
+def _ptr(a, dtype):
+    """(pointer, on_device) of a contiguous array of `dtype` (numpy dtype)."""
+    if a is None:
+        return None, None
+    if _is_dev(a):
+        import torch
+        tdt = {np.float32: torch.float32, np.float64: torch.float64, np.int32: torch.int32,
+               np.uint32: torch.int32}[dtype]
+        if a.dtype != tdt and not (dtype is np.uint32 and a.dtype == torch.int32):
+            raise TypeError(f"expected {tdt}, got {a.dtype}")
+        if not a.is_contiguous():
+            raise ValueError("device arrays must be contiguous")
+        return a.data_ptr(), True
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags["C_CONTIGUOUS"]):
+        raise TypeError(f"expected a C-contiguous numpy array of {np.dtype(dtype)}")
+    return a.ctypes.data, False
+
+
+def _ptrs(specs):
+    """Marshal [(array, dtype)] that must all live on the same side."""
+    out, side = [], None
+    for a, dt in specs:
+        p, dev = _ptr(a, dt)
+        if p is not None:
+            if side is None:
+                side = dev
+            elif side != dev:
+                raise ValueError("mixing device and host arrays in one call")
+        out.append(p)
+    return out, bool(side)
+
+
+def _stream(dev, stream):
+    if stream is not None:
+        return stream
+    if dev:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self._h = _P()
+        _check(lib().mppi_ctx_create(device, C.byref(self._h)))
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().mppi_ctx_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scene:
+    def __init__(self, ctx: Context, scene: dict):
+        self.ctx = ctx
+        self.dict = scene
+        self.desc = scene_desc(scene)
+        self._h = _P()
+        _check(lib().mppi_scene_create(ctx._h, C.byref(self.desc), C.byref(self._h)))
+        a, b = C.c_int(0), C.c_int(0)
+        _check(lib().mppi_scene_num_pairs(self._h, C.byref(a), C.byref(b)))
+        self.n_pairs, self.n_cost_pairs = a.value, b.value
+        self.n_geoms = 16 + int(scene["n_box"])
+
+    def close(self):
+        if self._h:
+            lib().mppi_scene_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mppi_plan(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, M=1, seed=0, eta=1.0,
+              n_elite=0, sigma_per_step=False, time_kernels=False, want_stats=True, sync=False, stream=None):
+    """One plan (Alg. 1).  Arrays: x0[55], nominal_U[H,14], sigma[14] or [H,14],
+    U_new[H,14] (out), costs[K] (out).  Returns a stats dict (or None)."""
+    (px0, pnom, psig, pU, pc), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32), (sigma, np.float32),
+                                             (U_new, np.float32), (costs, np.float32)])
+    flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | \
+            (TIME_KERNELS if time_kernels else 0) | (SYNC if sync else 0)
+    o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
+    st = Stats()
+    rc = lib().mppi_plan(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), pU, pc,
+                         C.byref(st) if want_stats else None, _stream(dev, stream))
+    if rc == E_DIVERGED:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    _check(rc)
+    if want_stats:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    return None
+
+
+def mppi_simulate(ctx, scene, X0, U, costs=None, terms=None, X_out=None, *, x0_shared=False, n_sub=0, traj=False,
+                  sync=True, stream=None):
+    """Roll out explicit controls U[n,H,14] from X0[n,55] (or one shared state)."""
+    (px0, pU, pc, pt, px), dev = _ptrs([(X0, np.float32), (U, np.float32), (costs, np.float32),
+                                        (terms, np.float32), (X_out, np.float32)])
+    n, H = U.shape[0], U.shape[1]
+    flags = (DEVICE_PTRS if dev else 0) | (TRAJ if traj else 0) | (SYNC if sync else 0)
+    _check(lib().mppi_simulate(ctx._h, scene._h, px0, int(bool(x0_shared)), pU, int(n), int(H), int(n_sub), pc, pt,
+                               px, flags, _stream(dev, stream)))
+
+
+def mppi_sample(ctx, scene, nu, sigma, seed, m, K, U=None, z=None, words=None, *, sigma_per_step=False, sync=True,
+                stream=None):
+    (pnu, psig, pU, pz, pw), dev = _ptrs([(nu, np.float32), (sigma, np.float32), (U, np.float32),
+                                          (z, np.float32), (words, np.uint32)])
+    H = nu.shape[0]
+    flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | (SYNC if sync else 0)
+    _check(lib().mppi_sample(ctx._h, scene._h, pnu, psig, int(seed) & 0xFFFFFFFFFFFFFFFF, int(m), int(K), int(H),
+                             pU, pz, pw, flags, _stream(dev, stream)))
+
+
+def mppi_update(ctx, scene, costs, nu_in, sigma, seed, m, lam, nu_out, nu_out64=None, weights=None, *, eta=1.0,
+                n_elite=0, sigma_per_step=False, stream=None):
+    (pc, pnu, psig, po), dev = _ptrs([(costs, np.float32), (nu_in, np.float32), (sigma, np.float32),
+                                      (nu_out, np.float32)])
+    (po64, pw), dev2 = _ptrs([(nu_out64, np.float64), (weights, np.float64)])
+    if (nu_out64 is not None or weights is not None) and dev2 != dev:
+        raise ValueError("mixing device and host arrays in one call")
+    K, H = costs.shape[0], nu_in.shape[0]
+    flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0)
+    st = Stats()
+    rc = lib().mppi_update(ctx._h, scene._h, pc, pnu, psig, int(seed) & 0xFFFFFFFFFFFFFFFF, int(m), int(K), int(H),
+                           float(lam), float(eta), int(n_elite), po, po64, pw, C.byref(st), flags,
+                           _stream(dev, stream))
+    if rc not in (OK, E_DIVERGED):
+        _check(rc)
+    d = st.as_dict()
+    d["rc"] = rc
+    return d
+
+
+def mppi_broadphase(ctx, scene, lo, hi, flags_out, margin=0.0, *, sync=True, stream=None):
+    (plo, phi, pf), dev = _ptrs([(lo, np.float32), (hi, np.float32), (flags_out, np.int32)])
+    n = lo.shape[0]
+    flags = (DEVICE_PTRS if dev else 0) | (SYNC if sync else 0)
+    _check(lib().mppi_broadphase(ctx._h, scene._h, plo, phi, int(n), float(margin), pf, flags,
+                                 _stream(dev, stream)))
+
+
+def mppi_narrowphase(ctx, scene, X, phi, normal=None, point=None, lo=None, hi=None, *, sync=True, stream=None):
+    (pX, pphi, pn, pp, plo, phi_), dev = _ptrs([(X, np.float32), (phi, np.float32), (normal, np.float32),
+                                                (point, np.float32), (lo, np.float32), (hi, np.float32)])
+    flags = (DEVICE_PTRS if dev else 0) | (SYNC if sync else 0)
+    _check(lib().mppi_narrowphase(ctx._h, scene._h, pX, int(X.shape[0]), pphi, pn, pp, plo, phi_, flags,
+                                  _stream(dev, stream)))

@@ -1,0 +1,631 @@
+// Host side of the C ABI declared in include/mppi.h: argument checks, scene
+// model derivation and upload, device buffers, staging of host arrays and
+// the launch sequence of a plan (M x [rollout -> stats -> update]).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mppi.h"
+#include "kernels.h"
+
+using namespace mppi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(MPPI_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+enum Slot { S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3, S_N };
+
+}  // namespace
+
+struct mppi_ctx {
+    int device = 0;
+    Buf buf[S_N];
+    PlanStats *st = nullptr;
+    std::vector<hipEvent_t> ev;
+};
+
+struct mppi_scene {
+    mppi_ctx *ctx = nullptr;
+    mppi_scene_desc desc;
+    DevModel host;
+    DevModel *dev = nullptr;
+};
+
+namespace {
+
+int ensure(mppi_ctx *c, int slot, size_t bytes, void **out)
+{
+    Buf &b = c->buf[slot];
+    if (bytes == 0) bytes = 16;
+    if (b.cap < bytes) {
+        if (b.p) hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        size_t want = bytes + bytes / 4;
+        if (hipMalloc(&b.p, want) != hipSuccess) {
+            b.p = nullptr;
+            return fail(MPPI_E_NOMEM, "device allocation of %zu bytes failed", want);
+        }
+        b.cap = want;
+    }
+    *out = b.p;
+    return MPPI_OK;
+}
+
+// device view of a caller input: the pointer itself, or a staged copy
+int stage_in(mppi_ctx *c, int slot, const void *src, size_t bytes, bool dev, hipStream_t s, const void **out)
+{
+    if (dev) {
+        *out = src;
+        return MPPI_OK;
+    }
+    void *d;
+    int rc = ensure(c, slot, bytes, &d);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s));
+    *out = d;
+    return MPPI_OK;
+}
+
+int out_ptr(mppi_ctx *c, int slot, void *dst, size_t bytes, bool dev, void **out)
+{
+    if (!dst) {
+        *out = nullptr;
+        return MPPI_OK;
+    }
+    if (dev) {
+        *out = dst;
+        return MPPI_OK;
+    }
+    return ensure(c, slot, bytes, out);
+}
+
+int copy_out(void *dst, const void *src, size_t bytes, bool dev, hipStream_t s)
+{
+    if (!dst || dev || !src) return MPPI_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    return MPPI_OK;
+}
+
+bool all_finite(const float *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// solid capsule: cylinder length L plus two hemispherical caps of radius r
+void capsule_mass_inertia(double rho, double L, double r, double &m, double &ix, double &iz)
+{
+    const double pi = 3.14159265358979323846;
+    const double m_cyl = rho * pi * r * r * L;
+    const double m_sph = rho * (4.0 / 3.0) * pi * r * r * r;
+    m = m_cyl + m_sph;
+    iz = 0.5 * m_cyl * r * r + 0.4 * m_sph * r * r;
+    // caps: sphere inertia about a diameter plus the shift of each half to
+    // the capsule centre (centroid 3r/8 from the flat face at L/2)
+    ix = m_cyl * (L * L / 12.0 + r * r / 4.0) + m_sph * (0.4 * r * r + L * L / 4.0 + 3.0 * L * r / 8.0);
+}
+
+bool finite_desc(const mppi_scene_desc *d)
+{
+    const double *vals[] = {&d->pad_rad, &d->ball_r, &d->ball_m, &d->h, &d->kp, &d->kd, &d->damp, &d->armature,
+                            &d->tau_max, &d->g, &d->mu, &d->kappa, &d->eps_r, &d->u_max, &d->w_goal, &d->w_eo,
+                            &d->w_l, &d->w_yz, &d->w_s, &d->w_c, &d->gamma, &d->m_c, &d->eps_frac};
+    for (const double *v : vals)
+        if (!std::isfinite(*v)) return false;
+    for (int i = 0; i < 7; ++i)
+        if (!std::isfinite(d->link_len[i]) || !std::isfinite(d->link_rad[i]) || !std::isfinite(d->density[0][i]) ||
+            !std::isfinite(d->density[1][i]))
+            return false;
+    return true;
+}
+
+int build_model(const mppi_scene_desc *d, DevModel &m)
+{
+    if (!finite_desc(d)) return fail(MPPI_E_MODEL, "scene description has non-finite values");
+    if (d->n_box < 0 || d->n_box > MPPI_MAX_BOXES) return fail(MPPI_E_MODEL, "n_box %d outside [0, %d]", d->n_box, MPPI_MAX_BOXES);
+    if (!(d->h > 0) || d->n_sub < 1) return fail(MPPI_E_MODEL, "need h > 0 and n_sub >= 1");
+    if (d->n_cmax < 0 || d->n_cmax > MPPI_MAX_CONTACTS) return fail(MPPI_E_MODEL, "n_cmax %d outside [0, %d]", d->n_cmax, MPPI_MAX_CONTACTS);
+    if (d->n_pgs < 0) return fail(MPPI_E_MODEL, "n_pgs < 0");
+    if (!(d->ball_r > 0) || !(d->ball_m > 0) || !(d->pad_rad > 0)) return fail(MPPI_E_MODEL, "ball and pad need positive size and mass");
+    if (!(d->armature > 0)) return fail(MPPI_E_MODEL, "armature must be > 0 (keeps the joint-space inertia SPD)");
+    if (d->kd < 0 || d->damp < 0 || d->kp < 0 || !(d->tau_max > 0)) return fail(MPPI_E_MODEL, "gains must be >= 0, tau_max > 0");
+    if (!(d->u_max > 0) || d->mu < 0 || d->kappa < 0 || d->eps_r < 0) return fail(MPPI_E_MODEL, "bad contact or control bounds");
+    if (!(d->m_c > 0) || !(d->gamma > 0 && d->gamma < 1)) return fail(MPPI_E_MODEL, "need m_c > 0 and 0 < gamma < 1");
+    std::memset(&m, 0, sizeof m);
+    for (int a = 0; a < 2; ++a) {
+        for (int i = 0; i < 3; ++i) m.base_pos[a][i] = (float)d->base_pos[a][i];
+        m.base_cs[a][0] = (float)d->base_cs[a][0];
+        m.base_cs[a][1] = (float)d->base_cs[a][1];
+    }
+    for (int i = 0; i < NJ; ++i) {
+        if (d->axes[i] < 0 || d->axes[i] > 2) return fail(MPPI_E_MODEL, "axes[%d] must be 0, 1 or 2", i);
+        if (!(d->link_len[i] > 0) || !(d->link_rad[i] > 0)) return fail(MPPI_E_MODEL, "link %d needs positive length and radius", i);
+        m.axes[i] = d->axes[i];
+        m.link_len[i] = (float)d->link_len[i];
+        m.link_rad[i] = (float)d->link_rad[i];
+        for (int a = 0; a < 2; ++a) {
+            if (!(d->density[a][i] > 0)) return fail(MPPI_E_MODEL, "density[%d][%d] must be > 0", a, i);
+            double mm, ix, iz;
+            capsule_mass_inertia(d->density[a][i], d->link_len[i], d->link_rad[i], mm, ix, iz);
+            m.m[a][i] = (float)mm;
+            m.Ix[a][i] = (float)ix;
+            m.Iz[a][i] = (float)iz;
+        }
+    }
+    m.pad_rad = (float)d->pad_rad;
+    m.ball_r = (float)d->ball_r;
+    m.ball_m = (float)d->ball_m;
+    m.inv_ball_m = (float)(1.0 / d->ball_m);
+    m.inv_ball_I = (float)(1.0 / (0.4 * d->ball_m * d->ball_r * d->ball_r));
+    m.n_box = d->n_box;
+    for (int b = 0; b < d->n_box; ++b)
+        for (int i = 0; i < 3; ++i) {
+            if (!std::isfinite(d->box_c[b][i]) || !(d->box_h[b][i] > 0)) return fail(MPPI_E_MODEL, "box %d is malformed", b);
+            m.box_c[b][i] = (float)d->box_c[b][i];
+            m.box_h[b][i] = (float)d->box_h[b][i];
+        }
+    m.h = (float)d->h;
+    m.n_sub = d->n_sub;
+    m.kp = (float)d->kp;
+    m.kd = (float)d->kd;
+    m.damp = (float)d->damp;
+    m.tau_max = (float)d->tau_max;
+    m.diag_add = (float)(d->armature + d->h * (d->kd + d->damp));
+    m.gravcomp = d->gravcomp;
+    m.g = (float)d->g;
+    m.mu = (float)d->mu;
+    m.kappa_h = (float)(d->kappa / d->h);
+    m.eps_r = (float)d->eps_r;
+    m.n_pgs = d->n_pgs;
+    m.n_cmax = d->n_cmax;
+    m.u_max = (float)d->u_max;
+    for (int i = 0; i < 3; ++i) m.goal[i] = (float)d->goal[i];
+    m.w_goal = (float)d->w_goal;
+    m.w_eo = (float)d->w_eo;
+    m.w_l = (float)d->w_l;
+    m.w_yz = (float)d->w_yz;
+    m.w_s = (float)d->w_s;
+    m.w_c = (float)d->w_c;
+    m.one_m_gamma = (float)(1.0 - d->gamma);
+    m.m_c = (float)d->m_c;
+    const double eps = d->eps_frac * d->ball_r, rr = d->ball_r + d->pad_rad;
+    if (!(rr > eps) || eps < 0) return fail(MPPI_E_MODEL, "grasp offset eps must lie in [0, r_ball + r_pad)");
+    m.eps = (float)eps;
+    m.l_ball = (float)(2.0 * std::sqrt(rr * rr - eps * eps));
+    // candidate pairs in canonical order
+    int n = 0;
+    auto add = [&](int a, int b) {
+        m.pa[n] = (uint8_t)a;
+        m.pb[n] = (uint8_t)b;
+        ++n;
+    };
+    add(G_BALL, G_TABLE);
+    for (int a = 0; a < 2; ++a) add(G_BALL, G_ARM + 7 * a + 6);
+    for (int a = 0; a < 2; ++a)
+        for (int g = 0; g < 6; ++g) add(G_BALL, G_ARM + 7 * a + g);
+    for (int b = 0; b < d->n_box; ++b) add(G_BALL, G_BOX + b);
+    for (int a = 0; a < 2; ++a)
+        for (int g = 1; g < 7; ++g) add(G_ARM + 7 * a + g, G_TABLE);
+    m.cost_first = n + 0;  // informational: arm-box pairs start here
+    for (int a = 0; a < 2; ++a)
+        for (int g = 0; g < 7; ++g)
+            for (int b = 0; b < d->n_box; ++b) add(G_ARM + 7 * a + g, G_BOX + b);
+    for (int g = 0; g < 7; ++g)
+        for (int g2 = 0; g2 < 7; ++g2) add(G_ARM + g, G_ARM + 7 + g2);
+    m.n_pairs = n;
+    m.n_cost = 14 * d->n_box + 49;
+    return MPPI_OK;
+}
+
+int set_device(mppi_ctx *c)
+{
+    HIPCHK(hipSetDevice(c->device));
+    return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mppi_last_error(void) { return g_err.c_str(); }
+
+int mppi_ctx_create(int device, mppi_ctx **out)
+{
+    if (!out) return fail(MPPI_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIPCHK(hipGetDeviceCount(&n));
+    if (device < 0) HIPCHK(hipGetDevice(&device));
+    if (device >= n) return fail(MPPI_E_INVAL, "device %d not present (%d devices)", device, n);
+    mppi_ctx *c = new mppi_ctx();
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess || hipMalloc((void **)&c->st, sizeof(PlanStats)) != hipSuccess) {
+        delete c;
+        return fail(MPPI_E_NOMEM, "context allocation failed");
+    }
+    *out = c;
+    return MPPI_OK;
+}
+
+void mppi_ctx_destroy(mppi_ctx *c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (auto &b : c->buf)
+        if (b.p) hipFree(b.p);
+    if (c->st) hipFree(c->st);
+    for (auto e : c->ev) hipEventDestroy(e);
+    delete c;
+}
+
+int mppi_scene_create(mppi_ctx *ctx, const mppi_scene_desc *desc, mppi_scene **out)
+{
+    if (!ctx || !desc || !out) return fail(MPPI_E_INVAL, "NULL argument");
+    *out = nullptr;
+    mppi_scene *s = new mppi_scene();
+    s->ctx = ctx;
+    s->desc = *desc;
+    int rc = build_model(desc, s->host);
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    if (set_device(ctx) || hipMalloc((void **)&s->dev, sizeof(DevModel)) != hipSuccess) {
+        delete s;
+        return fail(MPPI_E_NOMEM, "scene allocation failed");
+    }
+    if (hipMemcpy(s->dev, &s->host, sizeof(DevModel), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(s->dev);
+        delete s;
+        return fail(MPPI_E_DEVICE, "scene upload failed");
+    }
+    *out = s;
+    return MPPI_OK;
+}
+
+void mppi_scene_destroy(mppi_scene *s)
+{
+    if (!s) return;
+    hipSetDevice(s->ctx->device);
+    hipDeviceSynchronize();
+    if (s->dev) hipFree(s->dev);
+    delete s;
+}
+
+int mppi_scene_num_pairs(const mppi_scene *s, int *n_pairs, int *n_cost)
+{
+    if (!s) return fail(MPPI_E_INVAL, "NULL scene");
+    if (n_pairs) *n_pairs = s->host.n_pairs;
+    if (n_cost) *n_cost = s->host.n_cost;
+    return MPPI_OK;
+}
+
+int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+              double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs, mppi_stats *stats,
+              void *stream)
+{
+    if (!ctx || !scene || !x0 || !nominal_U || !sigma || !opts || !U_new) return fail(MPPI_E_INVAL, "NULL argument");
+    if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
+    if (K < 1 || K > MPPI_MAX_K || H < 1 || H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "K=%d or H=%d out of range", K, H);
+    if (!(lambda > 0) || !std::isfinite(lambda)) return fail(MPPI_E_INVAL, "lambda must be finite and > 0");
+    if (opts->M < 1 || opts->M > 100000) return fail(MPPI_E_INVAL, "M=%d out of range", opts->M);
+    if (!std::isfinite(opts->eta)) return fail(MPPI_E_INVAL, "eta must be finite");
+    const unsigned fl = opts->flags;
+    const bool dev = fl & MPPI_DEVICE_PTRS;
+    const bool sps = fl & MPPI_SIGMA_PER_STEP;
+    const size_t nsig = sps ? (size_t)H * NU : NU;
+    if (!dev) {
+        if (!all_finite(x0, NX) || !all_finite(nominal_U, (size_t)H * NU) || !all_finite(sigma, nsig))
+            return fail(MPPI_E_INVAL, "non-finite input");
+        for (size_t i = 0; i < nsig; ++i)
+            if (sigma[i] < 0) return fail(MPPI_E_INVAL, "sigma must be >= 0");
+    }
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const void *dx0, *dsig, *dnom;
+    if ((rc = stage_in(ctx, S_X0, x0, NX * sizeof(float), dev, s, &dx0))) return rc;
+    if ((rc = stage_in(ctx, S_SIGMA, sigma, nsig * sizeof(float), dev, s, &dsig))) return rc;
+    if ((rc = stage_in(ctx, S_NOM, nominal_U, (size_t)H * NU * sizeof(float), dev, s, &dnom))) return rc;
+    void *dnu, *dcost, *dw, *dcnt;
+    if ((rc = ensure(ctx, S_NU, (size_t)H * NU * sizeof(float), &dnu))) return rc;
+    if ((rc = ensure(ctx, S_W, (size_t)K * sizeof(double), &dw))) return rc;
+    if ((rc = ensure(ctx, S_CNT, (size_t)K * 4 * sizeof(int), &dcnt))) return rc;
+    if ((rc = out_ptr(ctx, S_COSTS, costs, (size_t)K * sizeof(float), dev, &dcost))) return rc;
+    if (!dcost && (rc = ensure(ctx, S_COSTS, (size_t)K * sizeof(float), &dcost))) return rc;
+    HIPCHK(hipMemcpyAsync(dnu, dnom, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
+    launch_reset_stats(ctx->st, s);
+
+    const bool timing = fl & MPPI_TIME_KERNELS;
+    const int M = opts->M;
+    if (timing) {
+        while ((int)ctx->ev.size() < 2 * M) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ctx->ev.push_back(e);
+        }
+    }
+    const uint32_t k0 = (uint32_t)(opts->seed & 0xffffffffu), k1 = (uint32_t)(opts->seed >> 32);
+    const int n_elite = (opts->n_elite <= 0 || opts->n_elite >= K) ? K : opts->n_elite;
+    for (int m = 0; m < M; ++m) {
+        RolloutArgs ra = {};
+        ra.md = scene->dev;
+        ra.x0 = (const float *)dx0;
+        ra.x0_shared = 1;
+        ra.nu = (const float *)dnu;
+        ra.sigma = (const float *)dsig;
+        ra.sigma_per_step = sps;
+        ra.U = nullptr;
+        ra.key0 = k0;
+        ra.key1 = k1;
+        ra.m = m;
+        ra.K = K;
+        ra.H = H;
+        ra.n_sub = 0;
+        ra.costs = (float *)dcost;
+        ra.counters = (int *)dcnt;
+        ra.diverged = &ctx->st->diverged;
+        if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], s));
+        launch_rollout(ra, scene->host.n_cmax, s);
+        if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], s));
+        StatsArgs sa = {(const float *)dcost, K, 1.0 / lambda, n_elite, (double *)dw, ctx->st, m, (const int *)dcnt};
+        launch_stats(sa, s);
+        UpdateArgs ua = {(const double *)dw, K, H, (const float *)dnu, (const float *)dsig, sps,
+                         scene->host.u_max, k0, k1, m, opts->eta, ctx->st, (float *)dnu, nullptr};
+        launch_update(ua, s);
+    }
+    HIPCHK(hipGetLastError());
+    // outputs
+    if (dev) {
+        HIPCHK(hipMemcpyAsync(U_new, dnu, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
+    } else {
+        HIPCHK(hipMemcpyAsync(U_new, dnu, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToHost, s));
+        if (costs) HIPCHK(hipMemcpyAsync(costs, dcost, (size_t)K * sizeof(float), hipMemcpyDeviceToHost, s));
+    }
+    const bool sync = !dev || stats || (fl & MPPI_SYNC);
+    if (!sync) return MPPI_OK;
+    PlanStats hs;
+    HIPCHK(hipMemcpyAsync(&hs, ctx->st, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->ess = hs.ess;
+        stats->c_min = hs.cmin;
+        stats->best = hs.best;
+        stats->n_nonfinite = K - hs.n_finite;
+        stats->diverged = hs.diverged;
+        stats->iterations = M;
+        for (int i = 0; i < 64 && i < M; ++i) stats->cmin_iter[i] = hs.cmin_iter[i];
+        stats->contacts = (double)hs.counters[0];
+        stats->np_tests = (double)hs.counters[1];
+        stats->box_tests = (double)hs.counters[2];
+        stats->overflow = (double)hs.counters[3];
+        stats->rollout_launches = M;
+        if (timing) {
+            float tot = 0.f;
+            for (int m = 0; m < M; ++m) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2 * m], ctx->ev[2 * m + 1]));
+                tot += ms;
+            }
+            stats->rollout_ms = tot;
+        }
+    }
+    if (hs.diverged) {
+        // every sample of some iteration was non-finite: hand back the nominal sequence
+        if (dev)
+            HIPCHK(hipMemcpyAsync(U_new, dnom, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
+        else
+            std::memcpy(U_new, nominal_U, (size_t)H * NU * sizeof(float));
+        HIPCHK(hipStreamSynchronize(s));
+        return fail(MPPI_E_DIVERGED, "every sample diverged in some iteration");
+    }
+    return MPPI_OK;
+}
+
+int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0_shared, const float *U, int n,
+                  int H, int n_sub, float *costs, float *terms, float *X_out, unsigned flags, void *stream)
+{
+    if (!ctx || !scene || !X0 || !U) return fail(MPPI_E_INVAL, "NULL argument");
+    if (n < 1 || n > MPPI_MAX_K || H < 1 || H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "n=%d or H=%d out of range", n, H);
+    const bool dev = flags & MPPI_DEVICE_PTRS, traj = flags & MPPI_TRAJ;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nx0 = x0_shared ? NX : (size_t)n * NX;
+    if (!dev && (!all_finite(X0, nx0) || !all_finite(U, (size_t)n * H * NU))) return fail(MPPI_E_INVAL, "non-finite input");
+    const void *dx0, *dU;
+    if ((rc = stage_in(ctx, S_IN0, X0, nx0 * sizeof(float), dev, s, &dx0))) return rc;
+    if ((rc = stage_in(ctx, S_IN1, U, (size_t)n * H * NU * sizeof(float), dev, s, &dU))) return rc;
+    void *dc, *dt, *dxo;
+    const size_t nxo = traj ? (size_t)n * H * NX : (size_t)n * NX;
+    if ((rc = out_ptr(ctx, S_OUT0, costs, (size_t)n * sizeof(float), dev, &dc))) return rc;
+    if (!dc && (rc = ensure(ctx, S_OUT0, (size_t)n * sizeof(float), &dc))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT1, terms, (size_t)n * 7 * sizeof(float), dev, &dt))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT2, X_out, nxo * sizeof(float), dev, &dxo))) return rc;
+    RolloutArgs ra = {};
+    ra.md = scene->dev;
+    ra.x0 = (const float *)dx0;
+    ra.x0_shared = x0_shared ? 1 : 0;
+    ra.U = (const float *)dU;
+    ra.K = n;
+    ra.H = H;
+    ra.n_sub = n_sub;
+    ra.costs = (float *)dc;
+    ra.terms = (float *)dt;
+    ra.xout = (float *)dxo;
+    ra.traj = traj;
+    launch_rollout(ra, scene->host.n_cmax, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(costs, dc, (size_t)n * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(terms, dt, (size_t)n * 7 * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(X_out, dxo, nxo * sizeof(float), dev, s))) return rc;
+    if (!dev || (flags & MPPI_SYNC)) HIPCHK(hipStreamSynchronize(s));
+    return MPPI_OK;
+}
+
+int mppi_sample(mppi_ctx *ctx, const mppi_scene *scene, const float *nu, const float *sigma, uint64_t seed, int m,
+                int K, int H, float *U, float *z_out, uint32_t *words_out, unsigned flags, void *stream)
+{
+    if (!ctx || !scene || !nu || !sigma) return fail(MPPI_E_INVAL, "NULL argument");
+    if (K < 1 || K > MPPI_MAX_K || H < 1 || H > MPPI_MAX_H || m < 0) return fail(MPPI_E_INVAL, "K, H or m out of range");
+    const bool dev = flags & MPPI_DEVICE_PTRS, sps = flags & MPPI_SIGMA_PER_STEP;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nsig = sps ? (size_t)H * NU : NU;
+    const void *dnu, *dsig;
+    if ((rc = stage_in(ctx, S_IN0, nu, (size_t)H * NU * sizeof(float), dev, s, &dnu))) return rc;
+    if ((rc = stage_in(ctx, S_IN1, sigma, nsig * sizeof(float), dev, s, &dsig))) return rc;
+    const size_t nu_n = (size_t)K * H * NU;
+    void *dU, *dz, *dw;
+    if ((rc = out_ptr(ctx, S_OUT0, U, nu_n * sizeof(float), dev, &dU))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT1, z_out, nu_n * sizeof(float), dev, &dz))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT2, words_out, (size_t)K * H * 16 * sizeof(uint32_t), dev, &dw))) return rc;
+    launch_sample(scene->dev, (const float *)dnu, (const float *)dsig, sps, (uint32_t)(seed & 0xffffffffu),
+                  (uint32_t)(seed >> 32), m, K, H, (float *)dU, (float *)dz, (uint32_t *)dw, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(U, dU, nu_n * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(z_out, dz, nu_n * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(words_out, dw, (size_t)K * H * 16 * sizeof(uint32_t), dev, s))) return rc;
+    if (!dev || (flags & MPPI_SYNC)) HIPCHK(hipStreamSynchronize(s));
+    return MPPI_OK;
+}
+
+int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, const float *nu_in, const float *sigma,
+                uint64_t seed, int m, int K, int H, double lambda, double eta, int n_elite, float *nu_out,
+                double *nu_out64, double *weights, mppi_stats *stats, unsigned flags, void *stream)
+{
+    if (!ctx || !scene || !costs || !nu_in || !sigma || !nu_out) return fail(MPPI_E_INVAL, "NULL argument");
+    if (K < 1 || K > MPPI_MAX_K || H < 1 || H > MPPI_MAX_H || m < 0) return fail(MPPI_E_INVAL, "K, H or m out of range");
+    if (!(lambda > 0) || !std::isfinite(lambda) || !std::isfinite(eta)) return fail(MPPI_E_INVAL, "bad lambda or eta");
+    const bool dev = flags & MPPI_DEVICE_PTRS, sps = flags & MPPI_SIGMA_PER_STEP;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nsig = sps ? (size_t)H * NU : NU;
+    const void *dc, *dnu, *dsig;
+    if ((rc = stage_in(ctx, S_IN0, costs, (size_t)K * sizeof(float), dev, s, &dc))) return rc;
+    if ((rc = stage_in(ctx, S_IN1, nu_in, (size_t)H * NU * sizeof(float), dev, s, &dnu))) return rc;
+    if ((rc = stage_in(ctx, S_SIGMA, sigma, nsig * sizeof(float), dev, s, &dsig))) return rc;
+    void *dout, *dout64, *dw;
+    if ((rc = out_ptr(ctx, S_OUT0, nu_out, (size_t)H * NU * sizeof(float), dev, &dout))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT1, nu_out64, (size_t)H * NU * sizeof(double), dev, &dout64))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT2, weights, (size_t)K * sizeof(double), dev, &dw))) return rc;
+    if (!dw && (rc = ensure(ctx, S_W, (size_t)K * sizeof(double), &dw))) return rc;
+    const int ne = (n_elite <= 0 || n_elite >= K) ? K : n_elite;
+    launch_reset_stats(ctx->st, s);
+    StatsArgs sa = {(const float *)dc, K, 1.0 / lambda, ne, (double *)dw, ctx->st, 0, nullptr};
+    launch_stats(sa, s);
+    UpdateArgs ua = {(const double *)dw, K, H, (const float *)dnu, (const float *)dsig, sps, scene->host.u_max,
+                     (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), m, eta, ctx->st, (float *)dout,
+                     (double *)dout64};
+    launch_update(ua, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(nu_out, dout, (size_t)H * NU * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(nu_out64, dout64, (size_t)H * NU * sizeof(double), dev, s))) return rc;
+    if ((rc = copy_out(weights, dw, (size_t)K * sizeof(double), dev, s))) return rc;
+    PlanStats hs;
+    HIPCHK(hipMemcpyAsync(&hs, ctx->st, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->ess = hs.ess;
+        stats->c_min = hs.cmin;
+        stats->best = hs.best;
+        stats->n_nonfinite = K - hs.n_finite;
+        stats->diverged = hs.diverged;
+        stats->iterations = 1;
+        stats->cmin_iter[0] = hs.cmin;
+    }
+    if (hs.diverged) return fail(MPPI_E_DIVERGED, "no finite cost");
+    return MPPI_OK;
+}
+
+int mppi_broadphase(mppi_ctx *ctx, const mppi_scene *scene, const float *lo, const float *hi, int n, float margin,
+                    int *flags, unsigned flags_in, void *stream)
+{
+    if (!ctx || !scene || !lo || !hi || !flags) return fail(MPPI_E_INVAL, "NULL argument");
+    if (n < 1 || n > MPPI_MAX_K) return fail(MPPI_E_INVAL, "n out of range");
+    const bool dev = flags_in & MPPI_DEVICE_PTRS;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int ng = G_BOX + scene->host.n_box, np = scene->host.n_pairs;
+    const size_t nb = (size_t)n * ng * 3 * sizeof(float);
+    const void *dlo, *dhi;
+    if ((rc = stage_in(ctx, S_IN0, lo, nb, dev, s, &dlo))) return rc;
+    if ((rc = stage_in(ctx, S_IN1, hi, nb, dev, s, &dhi))) return rc;
+    void *df;
+    if ((rc = out_ptr(ctx, S_OUT0, flags, (size_t)n * np * sizeof(int), dev, &df))) return rc;
+    launch_broadphase(scene->dev, (const float *)dlo, (const float *)dhi, n, ng, margin, (int *)df, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(flags, df, (size_t)n * np * sizeof(int), dev, s))) return rc;
+    if (!dev || (flags_in & MPPI_SYNC)) HIPCHK(hipStreamSynchronize(s));
+    return MPPI_OK;
+}
+
+int mppi_narrowphase(mppi_ctx *ctx, const mppi_scene *scene, const float *X, int n, float *phi, float *normal,
+                     float *point, float *lo, float *hi, unsigned flags, void *stream)
+{
+    if (!ctx || !scene || !X || !phi) return fail(MPPI_E_INVAL, "NULL argument");
+    if (n < 1 || n > MPPI_MAX_K) return fail(MPPI_E_INVAL, "n out of range");
+    if ((lo == nullptr) != (hi == nullptr)) return fail(MPPI_E_INVAL, "lo and hi go together");
+    const bool dev = flags & MPPI_DEVICE_PTRS;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int np = scene->host.n_pairs, ng = G_BOX + scene->host.n_box;
+    const void *dX;
+    if ((rc = stage_in(ctx, S_IN0, X, (size_t)n * NX * sizeof(float), dev, s, &dX))) return rc;
+    void *dphi, *dn, *dp, *dlo, *dhi;
+    if ((rc = out_ptr(ctx, S_OUT0, phi, (size_t)n * np * sizeof(float), dev, &dphi))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT1, normal, (size_t)n * np * 3 * sizeof(float), dev, &dn))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT2, point, (size_t)n * np * 3 * sizeof(float), dev, &dp))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT3, lo, (size_t)2 * n * ng * 3 * sizeof(float), dev, &dlo))) return rc;
+    dhi = nullptr;
+    if (lo) dhi = dev ? (void *)hi : (void *)((float *)dlo + (size_t)n * ng * 3);
+    launch_narrowphase(scene->dev, (const float *)dX, n, (float *)dphi, (float *)dn, (float *)dp, (float *)dlo,
+                       (float *)dhi, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(phi, dphi, (size_t)n * np * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(normal, dn, (size_t)n * np * 3 * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(point, dp, (size_t)n * np * 3 * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(lo, dlo, (size_t)n * ng * 3 * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(hi, dhi, (size_t)n * ng * 3 * sizeof(float), dev, s))) return rc;
+    if (!dev || (flags & MPPI_SYNC)) HIPCHK(hipStreamSynchronize(s));
+    return MPPI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Kernel declarations and the launch-argument records shared by the kernel
+// and host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "devmodel.h"
+
+namespace mppi {
+
+struct RolloutArgs {
+    const DevModel *md;
+    const float *x0;      // [K][NX] or one shared state
+    int x0_shared;
+    const float *nu;      // [H][14] mean (sampling mode)
+    const float *sigma;   // [14] or [H][14]
+    int sigma_per_step;
+    const float *U;       // [K][H][14] explicit controls (simulation mode) or null
+    uint32_t key0, key1;
+    int m, K, H, n_sub;
+    float *costs;         // [K]
+    float *terms;         // [K][7] or null
+    float *xout;          // [K][NX] or [K][H][NX] (traj) or null
+    int traj;
+    int *counters;        // [K][4] or null: contacts, np tests, box tests, overflow
+    const int *diverged;  // sticky flag of the plan (skip work when set) or null
+};
+
+// Per-plan device-side statistics (one record per plan in flight).
+struct PlanStats {
+    double cmin;
+    double wsum;
+    double ess;
+    int best;
+    int n_finite;
+    int diverged;
+    int pad;
+    double cmin_iter[64];
+    unsigned long long counters[4];
+};
+
+struct StatsArgs {
+    const float *costs;
+    int K;
+    double inv_lambda;
+    int n_elite;
+    double *weights;        // [K] normalized weights
+    PlanStats *st;
+    int iter;
+    const int *counters;    // [K][4] or null
+};
+
+struct UpdateArgs {
+    const double *weights;
+    int K, H;
+    const float *nu_in;
+    const float *sigma;
+    int sigma_per_step;
+    float u_max;
+    uint32_t key0, key1;
+    int m;
+    double eta;
+    const PlanStats *st;
+    float *nu_out;
+    double *nu_out64;
+};
+
+void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s);
+void launch_stats(const StatsArgs &a, hipStream_t s);
+void launch_update(const UpdateArgs &a, hipStream_t s);
+void launch_sample(const DevModel *md, const float *nu, const float *sigma, int sps, uint32_t k0, uint32_t k1,
+                   int m, int K, int H, float *U, float *z, uint32_t *words, hipStream_t s);
+void launch_broadphase(const DevModel *md, const float *lo, const float *hi, int n, int ngeom, float margin,
+                       int *flags, hipStream_t s);
+void launch_narrowphase(const DevModel *md, const float *X, int n, float *phi, float *nrm, float *pt, float *lo,
+                        float *hi, hipStream_t s);
+void launch_reset_stats(PlanStats *st, hipStream_t s);
+
+}  // namespace mppi

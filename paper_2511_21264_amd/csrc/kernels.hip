@@ -1,0 +1,389 @@
+// HIP kernels of the MPPI hot path for gfx950.
+//
+//   rollout_kernel  one lane per sample: Philox noise -> projected controls ->
+//                   H control steps x n_sub physics substeps -> task cost
+//                   (Alg. 1 sampling, QP, rollout and cost steps); the state
+//                   stays in registers for the whole horizon, nothing but the
+//                   cost (and optional diagnostics) is written.
+//   stats_kernel    one workgroup: lowest finite cost, elite threshold,
+//                   s_j = exp(-(c_j - c_min) / lambda) in FP64, normalised
+//                   weights and effective sample size (Eq. s_formula), with
+//                   fixed-order tree reductions (deterministic).
+//   update_kernel   one workgroup per control step: regenerates the projected
+//                   samples from the Philox counters and forms
+//                   (1 - eta) nu + eta sum_j w_j u_j in FP64 (Eq. mean_update).
+//   sample / broadphase / narrowphase kernels expose single stages.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cost.h"
+#include "kernels.h"
+#include "philox.h"
+
+namespace mppi {
+
+// projected sample of joint d: clamp(nu + sigma z, +-u_max); one expression
+// shared by the rollout and the update so both see identical bits
+__device__ __forceinline__ void sample_u(const float *nu_k, const float *sig_k, float umax, uint32_t key0,
+                                         uint32_t key1, uint32_t j, uint32_t k, uint32_t m, float u[NU])
+{
+    float z[14];
+    normals14(key0, key1, j, k, m, z);
+#pragma unroll
+    for (int d = 0; d < NU; ++d) u[d] = clampf(fmaf(sig_k[d], z[d], nu_k[d]), -umax, umax);
+}
+
+template <int NC>
+__global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.K) return;
+    const DevModel &md = *a.md;
+    if (a.diverged && *a.diverged) {
+        a.costs[j] = INFINITY;
+        return;
+    }
+    float x[NX];
+    const float *x0 = a.x0 + (a.x0_shared ? 0 : (long)j * NX);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) x[i] = x0[i];
+    const int nsub = a.n_sub > 0 ? a.n_sub : md.n_sub;
+    float dprev[MAXCOST];
+    CostAcc acc;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
+    StepCounters cnt = {0, 0, 0, 0};
+    float uprev[NU];
+#pragma unroll
+    for (int d = 0; d < NU; ++d) uprev[d] = 0.f;
+    for (int k = 0; k < a.H; ++k) {
+        float u[NU];
+        if (a.U) {
+            const float *uk = a.U + ((long)j * a.H + k) * NU;
+#pragma unroll
+            for (int d = 0; d < NU; ++d) u[d] = uk[d];
+        } else {
+            sample_u(a.nu + k * NU, a.sigma + (a.sigma_per_step ? k * NU : 0), md.u_max, a.key0, a.key1, (uint32_t)j,
+                     (uint32_t)k, (uint32_t)a.m, u);
+        }
+        for (int s = 0; s < nsub; ++s) substep<NC>(md, x, u, cnt);
+        stage_cost(md, x, u, uprev, k == 0, dprev, acc, cnt);
+#pragma unroll
+        for (int d = 0; d < NU; ++d) uprev[d] = u[d];
+        if (a.xout && a.traj) {
+            float *o = a.xout + ((long)j * a.H + k) * NX;
+#pragma unroll
+            for (int i = 0; i < NX; ++i) o[i] = x[i];
+        }
+    }
+    float c = md.w_goal * acc.t[0] + md.w_eo * acc.t[1] + md.w_l * acc.t[2] + md.w_yz * acc.t[3] +
+              md.w_s * acc.t[4] + md.w_c * (acc.t[5] + acc.t[6]);
+    bool finite = isfinite(c);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) finite &= isfinite(x[i]);
+    a.costs[j] = finite ? c : INFINITY;
+    if (a.terms) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) a.terms[(long)j * 7 + i] = acc.t[i];
+    }
+    if (a.xout && !a.traj) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) a.xout[(long)j * NX + i] = x[i];
+    }
+    if (a.counters) {
+        a.counters[4 * j + 0] = cnt.contacts;
+        a.counters[4 * j + 1] = cnt.np_tests;
+        a.counters[4 * j + 2] = cnt.box_tests;
+        a.counters[4 * j + 3] = cnt.overflow;
+    }
+}
+
+void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s)
+{
+    const dim3 grid((a.K + 63) / 64), block(64);
+    if (ncmax <= 8)
+        hipLaunchKernelGGL(rollout_kernel<8>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(rollout_kernel<16>, grid, block, 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// statistics and weights (one workgroup of 1024 lanes)
+
+constexpr int SB = 1024;
+
+__device__ __forceinline__ uint32_t ordered_bits(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = SB / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const T r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a)
+{
+    __shared__ double shd[SB];
+    __shared__ unsigned long long shu[SB];
+    __shared__ float shf[SB];
+    __shared__ int shi[SB];
+    const int t = threadIdx.x;
+    // lowest finite cost (ties: lowest index) and finite count
+    float best = INFINITY;
+    int bi = 0x7fffffff, nf = 0;
+    for (int j = t; j < a.K; j += SB) {
+        const float c = a.costs[j];
+        if (isfinite(c)) {
+            ++nf;
+            if (c < best || (c == best && j < bi)) { best = c; bi = j; }
+        }
+    }
+    shf[t] = best;
+    shi[t] = bi;
+    __syncthreads();
+    for (int s = SB / 2; s > 0; s >>= 1) {
+        if (t < s) {
+            const float c2 = shf[t + s];
+            const int i2 = shi[t + s];
+            if (c2 < shf[t] || (c2 == shf[t] && i2 < shi[t])) { shf[t] = c2; shi[t] = i2; }
+        }
+        __syncthreads();
+    }
+    const float cmin = shf[0];
+    const int best_j = shi[0];
+    __syncthreads();
+    const unsigned long long nfin = block_sum<unsigned long long>((unsigned long long)nf, shu);
+    // elite threshold: the n_e-th smallest key (ordered cost bits, index)
+    unsigned long long thr = ~0ull;
+    if (a.n_elite > 0 && (unsigned long long)a.n_elite < nfin) {
+        unsigned long long lo = 0, hi = ~0ull;
+        while (lo < hi) {
+            const unsigned long long mid = lo + (hi - lo) / 2;
+            unsigned long long cnt = 0;
+            for (int j = t; j < a.K; j += SB) {
+                const float c = a.costs[j];
+                if (isfinite(c)) {
+                    const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (uint32_t)j;
+                    cnt += key <= mid;
+                }
+            }
+            cnt = block_sum<unsigned long long>(cnt, shu);
+            if (cnt >= (unsigned long long)a.n_elite) hi = mid; else lo = mid + 1;
+        }
+        thr = lo;
+    }
+    // weights
+    double z = 0.0, z2 = 0.0;
+    for (int j = t; j < a.K; j += SB) {
+        const float c = a.costs[j];
+        double s = 0.0;
+        if (isfinite(c)) {
+            const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (uint32_t)j;
+            if (key <= thr) s = exp(-((double)c - (double)cmin) * a.inv_lambda);
+        }
+        a.weights[j] = s;
+        z += s;
+        z2 += s * s;
+    }
+    z = block_sum<double>(z, shd);
+    z2 = block_sum<double>(z2, shd);
+    const double inv = nfin > 0 ? 1.0 / z : 0.0;
+    for (int j = t; j < a.K; j += SB) a.weights[j] *= inv;
+    // work counters
+    if (a.counters) {
+        for (int c = 0; c < 4; ++c) {
+            unsigned long long v = 0;
+            for (int j = t; j < a.K; j += SB) v += (unsigned long long)a.counters[4 * j + c];
+            v = block_sum<unsigned long long>(v, shu);
+            if (t == 0) a.st->counters[c] += v;
+        }
+    }
+    if (t == 0) {
+        PlanStats *st = a.st;
+        st->cmin = nfin > 0 ? (double)cmin : INFINITY;
+        st->best = nfin > 0 ? best_j : -1;
+        st->n_finite = (int)nfin;
+        st->wsum = z;
+        st->ess = nfin > 0 ? z * z / z2 : 0.0;
+        if (a.iter < 64) st->cmin_iter[a.iter] = st->cmin;
+        if (nfin == 0) st->diverged = 1;
+    }
+}
+
+void launch_stats(const StatsArgs &a, hipStream_t s) { hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(SB), 0, s, a); }
+
+__global__ void reset_stats_kernel(PlanStats *st)
+{
+    const int t = threadIdx.x;
+    if (t < 64) st->cmin_iter[t] = 0.0;
+    if (t < 4) st->counters[t] = 0ull;
+    if (t == 0) {
+        st->cmin = 0.0; st->wsum = 0.0; st->ess = 0.0;
+        st->best = -1; st->n_finite = 0; st->diverged = 0; st->pad = 0;
+    }
+}
+
+void launch_reset_stats(PlanStats *st, hipStream_t s) { hipLaunchKernelGGL(reset_stats_kernel, dim3(1), dim3(64), 0, s, st); }
+
+// ---------------------------------------------------------------------------
+// weighted mean update: one workgroup per control step
+
+constexpr int UB = 256;
+
+__global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a)
+{
+    __shared__ double red[NU][UB];
+    const int k = blockIdx.x, t = threadIdx.x;
+    const bool div = a.st->diverged != 0;
+    double acc[NU];
+#pragma unroll
+    for (int d = 0; d < NU; ++d) acc[d] = 0.0;
+    if (!div) {
+        const float *nu_k = a.nu_in + k * NU;
+        const float *sig_k = a.sigma + (a.sigma_per_step ? k * NU : 0);
+        for (int j = t; j < a.K; j += UB) {
+            const double w = a.weights[j];
+            if (w != 0.0) {
+                float u[NU];
+                sample_u(nu_k, sig_k, a.u_max, a.key0, a.key1, (uint32_t)j, (uint32_t)k, (uint32_t)a.m, u);
+#pragma unroll
+                for (int d = 0; d < NU; ++d) acc[d] = fma(w, (double)u[d], acc[d]);
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < NU; ++d) red[d][t] = acc[d];
+    __syncthreads();
+    for (int s = UB / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int d = 0; d < NU; ++d) red[d][t] += red[d][t + s];
+        }
+        __syncthreads();
+    }
+    if (t < NU) {
+        const double nu0 = (double)a.nu_in[k * NU + t];
+        const double v = div ? nu0 : (1.0 - a.eta) * nu0 + a.eta * red[t][0];
+        a.nu_out[k * NU + t] = (float)v;
+        if (a.nu_out64) a.nu_out64[k * NU + t] = v;
+    }
+}
+
+void launch_update(const UpdateArgs &a, hipStream_t s) { hipLaunchKernelGGL(update_kernel, dim3(a.H), dim3(UB), 0, s, a); }
+
+// ---------------------------------------------------------------------------
+// single-stage kernels
+
+__global__ void sample_kernel(const DevModel *md, const float *nu, const float *sigma, int sps, uint32_t k0,
+                              uint32_t k1, int m, int K, int H, float *U, float *Z, uint32_t *words)
+{
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long)K * H) return;
+    const int j = (int)(id / H), k = (int)(id % H);
+    float u[NU];
+    sample_u(nu + k * NU, sigma + (sps ? k * NU : 0), md->u_max, k0, k1, (uint32_t)j, (uint32_t)k, (uint32_t)m, u);
+    if (U) {
+#pragma unroll
+        for (int d = 0; d < NU; ++d) U[id * NU + d] = u[d];
+    }
+    if (Z) {
+        float z[14];
+        normals14(k0, k1, (uint32_t)j, (uint32_t)k, (uint32_t)m, z);
+#pragma unroll
+        for (int d = 0; d < NU; ++d) Z[id * NU + d] = z[d];
+    }
+    if (words) {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            const U4 w = philox4x32_10(U4{(uint32_t)j, (uint32_t)k, q, (uint32_t)m}, k0, k1);
+            words[id * 16 + 4 * q + 0] = w.x;
+            words[id * 16 + 4 * q + 1] = w.y;
+            words[id * 16 + 4 * q + 2] = w.z;
+            words[id * 16 + 4 * q + 3] = w.w;
+        }
+    }
+}
+
+void launch_sample(const DevModel *md, const float *nu, const float *sigma, int sps, uint32_t k0, uint32_t k1, int m,
+                   int K, int H, float *U, float *z, uint32_t *words, hipStream_t s)
+{
+    const long n = (long)K * H;
+    hipLaunchKernelGGL(sample_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, md, nu, sigma, sps, k0, k1, m,
+                       K, H, U, z, words);
+}
+
+__global__ void broadphase_kernel(const DevModel *md, const float *lo, const float *hi, int n, int ngeom,
+                                  float margin, int *flags)
+{
+    const int np = md->n_pairs;
+    const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (long)n * np) return;
+    const int i = (int)(id / np), p = (int)(id % np);
+    const int ga = md->pa[p], gb = md->pb[p];
+    const float *L = lo + (long)i * ngeom * 3, *Hh = hi + (long)i * ngeom * 3;
+    AABB A, B;
+    A.lo = v3(L[3 * ga], L[3 * ga + 1], L[3 * ga + 2]);
+    A.hi = v3(Hh[3 * ga], Hh[3 * ga + 1], Hh[3 * ga + 2]);
+    B.lo = v3(L[3 * gb], L[3 * gb + 1], L[3 * gb + 2]);
+    B.hi = v3(Hh[3 * gb], Hh[3 * gb + 1], Hh[3 * gb + 2]);
+    flags[id] = aabb_overlap(A, B, margin) ? 1 : 0;
+}
+
+void launch_broadphase(const DevModel *md, const float *lo, const float *hi, int n, int ngeom, float margin, int *flags,
+                       hipStream_t s)
+{
+    const long tot = (long)n * MAXPAIR;
+    hipLaunchKernelGGL(broadphase_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, md, lo, hi, n, ngeom,
+                       margin, flags);
+}
+
+__global__ void narrowphase_kernel(const DevModel *md, const float *X, int n, float *phi, float *nrm, float *pt,
+                                   float *lo, float *hi)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float *x = X + (long)i * NX;
+    ArmKin kin[2];
+    fk_arm(*md, 0, x + XQ, kin[0]);
+    fk_arm(*md, 1, x + XQ + 7, kin[1]);
+    const V3 pb = v3(x[XPB], x[XPB + 1], x[XPB + 2]);
+    const int np = md->n_pairs;
+    for (int p = 0; p < np; ++p) {
+        const Shape A = geom_shape(*md, kin, pb, md->pa[p]);
+        const Shape B = geom_shape(*md, kin, pb, md->pb[p]);
+        const Contact3 c = narrow(A, B);
+        const long o = (long)i * np + p;
+        phi[o] = c.phi;
+        if (nrm) { nrm[3 * o] = c.n.x; nrm[3 * o + 1] = c.n.y; nrm[3 * o + 2] = c.n.z; }
+        if (pt) { pt[3 * o] = c.p.x; pt[3 * o + 1] = c.p.y; pt[3 * o + 2] = c.p.z; }
+    }
+    if (lo && hi) {
+        const int ng = G_BOX + md->n_box;
+        for (int g = 0; g < ng; ++g) {
+            const AABB b = shape_aabb(geom_shape(*md, kin, pb, g));
+            const long o = ((long)i * ng + g) * 3;
+            lo[o] = b.lo.x; lo[o + 1] = b.lo.y; lo[o + 2] = b.lo.z;
+            hi[o] = b.hi.x; hi[o + 1] = b.hi.y; hi[o + 2] = b.hi.z;
+        }
+    }
+}
+
+void launch_narrowphase(const DevModel *md, const float *X, int n, float *phi, float *nrm, float *pt, float *lo,
+                        float *hi, hipStream_t s)
+{
+    hipLaunchKernelGGL(narrowphase_kernel, dim3((n + 63) / 64), dim3(64), 0, s, md, X, n, phi, nrm, pt, lo, hi);
+}
+
+}  // namespace mppi
