@@ -25,19 +25,38 @@ PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
 
-def cpu_baseline(sc, pp, n_samples, threads):
+def cpu_baseline(sc, pp, threads, min_s=10.0, max_plans=5):
+    """The FP64 oracle's full plan of the same workload, repeated until at
+    least min_s seconds of host work (bounded by max_plans)."""
     import numpy as np
     import oracle
     import workloads as W
     o = oracle.Oracle(sc)
     x0 = W.initial_state(sc)
-    U = o.sample(np.zeros((pp["H"], 14)), pp["sigma"], pp["seed"], n_samples, 0)
-    t0 = time.perf_counter()
-    o.rollout_batch(x0, U, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return dict(value=n_samples * pp["H"] / dt, unit="env-steps/s", cores=threads, kind="oracle",
-                sample=f"first {n_samples} samples of iteration 0 of the same plan (rollout + cost), FP64, "
-                       f"{dt:.1f} s on {threads} threads")
+    K, H, M = pp["K"], pp["H"], pp["M"]
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.plan(x0, np.zeros((H, 14)), K, H, pp["lam"], pp["sigma"], M, pp["seed"], nthreads=threads)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_s or n >= max_plans:
+            break
+    return dict(value=n * M * K * H / dt, unit="env-steps/s", cores=threads, kind="oracle",
+                sample=f"{n} full oracle plan(s) of the same workload (K={K}, H={H}, M={M}), FP64, "
+                       f"{dt:.1f} s on {threads} threads", plan_ms=dt / n * 1e3)
+
+
+def calib_copy(mb):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_each_way": n * 4, "copies": 3}), flush=True)
 
 
 def main():
@@ -46,9 +65,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--cpu-samples", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0)
     args = ap.parse_args()
+    if args.calib_copy_mb:
+        calib_copy(args.calib_copy_mb)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -135,7 +157,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        out["cpu_baseline"] = cpu_baseline(sc, pp, args.cpu_samples, threads)
+        out["cpu_baseline"] = cpu_baseline(sc, pp, threads)
     print(json.dumps(out), flush=True)
 
 

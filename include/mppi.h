@@ -51,7 +51,7 @@ extern "C" {
 #define MPPI_NU 14
 #define MPPI_NX 55
 #define MPPI_MAX_BOXES 16
-#define MPPI_MAX_CONTACTS 16
+#define MPPI_MAX_CONTACTS 8
 #define MPPI_MAX_PAIRS (76 + 15 * MPPI_MAX_BOXES)
 #define MPPI_MAX_K (1 << 20)
 #define MPPI_MAX_H 4096

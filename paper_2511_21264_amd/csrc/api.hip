@@ -41,7 +41,7 @@ struct Buf {
     size_t cap = 0;
 };
 
-enum Slot { S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3, S_N };
+enum Slot { S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_DIST, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3, S_N };
 
 }  // namespace
 
@@ -362,6 +362,8 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
     if ((rc = ensure(ctx, S_NU, (size_t)H * NU * sizeof(float), &dnu))) return rc;
     if ((rc = ensure(ctx, S_W, (size_t)K * sizeof(double), &dw))) return rc;
     if ((rc = ensure(ctx, S_CNT, (size_t)K * 4 * sizeof(int), &dcnt))) return rc;
+    void *ddist;
+    if ((rc = ensure(ctx, S_DIST, (size_t)K * MAXCOST * sizeof(float), &ddist))) return rc;
     if ((rc = out_ptr(ctx, S_COSTS, costs, (size_t)K * sizeof(float), dev, &dcost))) return rc;
     if (!dcost && (rc = ensure(ctx, S_COSTS, (size_t)K * sizeof(float), &dcost))) return rc;
     HIPCHK(hipMemcpyAsync(dnu, dnom, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -396,6 +398,7 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
         ra.costs = (float *)dcost;
         ra.counters = (int *)dcnt;
         ra.diverged = &ctx->st->diverged;
+        ra.dist = (float *)ddist;
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], s));
         launch_rollout(ra, scene->host.n_cmax, s);
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], s));
@@ -474,8 +477,11 @@ int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x
     if (!dc && (rc = ensure(ctx, S_OUT0, (size_t)n * sizeof(float), &dc))) return rc;
     if ((rc = out_ptr(ctx, S_OUT1, terms, (size_t)n * 7 * sizeof(float), dev, &dt))) return rc;
     if ((rc = out_ptr(ctx, S_OUT2, X_out, nxo * sizeof(float), dev, &dxo))) return rc;
+    void *ddist;
+    if ((rc = ensure(ctx, S_DIST, (size_t)n * MAXCOST * sizeof(float), &ddist))) return rc;
     RolloutArgs ra = {};
     ra.md = scene->dev;
+    ra.dist = (float *)ddist;
     ra.x0 = (const float *)dx0;
     ra.x0_shared = x0_shared ? 1 : 0;
     ra.U = (const float *)dU;

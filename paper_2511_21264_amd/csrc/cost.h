@@ -7,9 +7,15 @@
 //   smooth    ||u_k - u_{k-1}||^2       (smoothness term, k >= 1)
 //   collision barrier max(-d_k + (1 - gamma) d_{k-1}, 0) and indicator
 //             1{d_k < 0}, elementwise over the arm-box and arm-arm signed
-//             distances saturated at m_c (Eq. collision_cost).  Pairs whose
-//             AABBs (grown by m_c) do not overlap are at distance >= m_c and
-//             take the saturated value without a narrowphase.
+//             distances saturated at m_c (Eq. collision_cost).
+//
+// Saturation makes the collision term sparse: a pair at distance >= m_c now
+// contributes nothing (its barrier is max(-m_c + (1 - gamma) d_{k-1}, 0) = 0),
+// and pairs whose AABBs grown by m_c do not overlap take the saturated value
+// without a narrowphase.  So only pairs closer than m_c need last step's
+// distance: a per-lane bitmask records which pairs were closer than m_c at
+// the previous step and their distances sit in a per-sample global array
+// touched only for those pairs.
 #pragma once
 #include "step.h"
 
@@ -19,18 +25,31 @@ struct CostAcc {
     float t[7];  // goal, eef-obj, distance, planar, smooth, barrier, indicator
 };
 
-__device__ __forceinline__ void dist_term(const DevModel &md, float d, float *dprev, int idx, bool has_prev,
-                                          CostAcc &acc)
+// bit set: pair closer than m_c at the previous control step
+struct DistHist {
+    uint32_t box[14];  // arm geom (7 * arm + g) x box bit b
+    uint32_t aa[2];    // arm 1 geom x arm 2 geom, bit 7 g + g2
+};
+
+__device__ __forceinline__ void dist_term(const DevModel &md, float d, bool has_prev, uint32_t prev_word,
+                                          uint32_t bit, float *slot, uint32_t &new_word, CostAcc &acc)
 {
     const float dh = fminf(d, md.m_c);
-    if (has_prev) acc.t[5] += fmaxf(-dh + md.one_m_gamma * dprev[idx], 0.f);
-    acc.t[6] += dh < 0.f ? 1.f : 0.f;
-    dprev[idx] = dh;
+    if (dh < md.m_c) {
+        if (has_prev) {
+            const float prev = (prev_word & bit) ? *slot : md.m_c;
+            acc.t[5] += fmaxf(-dh + md.one_m_gamma * prev, 0.f);
+        }
+        acc.t[6] += dh < 0.f ? 1.f : 0.f;
+        *slot = dh;
+        new_word |= bit;
+    }
 }
 
-// dprev: per-lane scratch of the previous step's saturated distances
+// dist: per-sample history slots, pair-major with stride `stride` (= lanes of the launch)
 __device__ inline void stage_cost(const DevModel &md, const float x[NX], const float u[NU], const float uprev[NU],
-                                  bool first, float *dprev, CostAcc &acc, StepCounters &cnt)
+                                  bool first, DistHist &hist, float *dist, long stride, CostAcc &acc,
+                                  StepCounters &cnt)
 {
     ArmKin kin[2];
     fk_arm(md, 0, x + XQ, kin[0]);
@@ -66,32 +85,43 @@ __device__ inline void stage_cost(const DevModel &md, const float x[NX], const f
             barm[a][gg] = shape_aabb(arm[a][gg]);
         }
     const int nb = md.n_box;
+    const bool has_prev = !first;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int gg = 0; gg < 7; ++gg)
+        for (int gg = 0; gg < 7; ++gg) {
+            const int row = 7 * a + gg;
+            uint32_t nw = 0u;
             for (int b = 0; b < nb; ++b) {
                 const Shape bx = box_shape(md, b);
-                float d = md.m_c;
                 if (aabb_overlap(barm[a][gg], shape_aabb(bx), md.m_c)) {
                     ++cnt.np_tests;
                     if (gg < 6) ++cnt.box_tests;
-                    d = narrow(arm[a][gg], bx).phi;
+                    const float d = narrow(arm[a][gg], bx).phi;
+                    dist_term(md, d, has_prev, hist.box[row], 1u << b, dist + (long)(row * nb + b) * stride, nw, acc);
                 }
-                dist_term(md, d, dprev, (7 * a + gg) * nb + b, !first, acc);
             }
+            hist.box[row] = nw;
+        }
     const int off = 14 * nb;
+    uint32_t nw0 = 0u, nw1 = 0u;
 #pragma unroll
     for (int gg = 0; gg < 7; ++gg)
 #pragma unroll
         for (int g2 = 0; g2 < 7; ++g2) {
-            float d = md.m_c;
             if (aabb_overlap(barm[0][gg], barm[1][g2], md.m_c)) {
                 ++cnt.np_tests;
-                d = narrow(arm[0][gg], arm[1][g2]).phi;
+                const float d = narrow(arm[0][gg], arm[1][g2]).phi;
+                const int idx = 7 * gg + g2;
+                if (idx < 32)
+                    dist_term(md, d, has_prev, hist.aa[0], 1u << idx, dist + (long)(off + idx) * stride, nw0, acc);
+                else
+                    dist_term(md, d, has_prev, hist.aa[1], 1u << (idx - 32), dist + (long)(off + idx) * stride, nw1,
+                              acc);
             }
-            dist_term(md, d, dprev, off + 7 * gg + g2, !first, acc);
         }
+    hist.aa[0] = nw0;
+    hist.aa[1] = nw1;
 }
 
 }  // namespace mppi

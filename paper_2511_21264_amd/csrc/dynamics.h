@@ -58,6 +58,18 @@ struct ArmKin {
     V3 z[NJ];
 };
 
+// columns j1, j2 of R after a rotation by (c, s) about the third axis
+template <int J1, int J2>
+__device__ __forceinline__ void rot_cols(float R[3][3], float c, float s)
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float c1 = R[r][J1], c2 = R[r][J2];
+        R[r][J1] = c * c1 + s * c2;
+        R[r][J2] = c * c2 - s * c1;
+    }
+}
+
 __device__ inline void fk_arm(const DevModel &md, int arm, const float *q, ArmKin &k)
 {
     float R[3][3] = {{md.base_cs[arm][0], -md.base_cs[arm][1], 0.f},
@@ -66,18 +78,21 @@ __device__ inline void fk_arm(const DevModel &md, int arm, const float *q, ArmKi
     V3 o = v3(md.base_pos[arm][0], md.base_pos[arm][1], md.base_pos[arm][2]);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
-        // rotating about local axis ax mixes the other two columns of R
+        // rotating about local axis ax mixes the other two columns of R; the
+        // axis is uniform across the launch, so the branch is too
         const int ax = md.axes[i];
-        const int j1 = (ax + 1) % 3, j2 = (ax + 2) % 3;
-        k.a[i] = v3(R[0][ax], R[1][ax], R[2][ax]);
         k.o[i] = o;
         float s, c;
         sincosf(q[i], &s, &c);
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const float c1 = R[r][j1], c2 = R[r][j2];
-            R[r][j1] = c * c1 + s * c2;
-            R[r][j2] = c * c2 - s * c1;
+        if (ax == 0) {
+            k.a[i] = v3(R[0][0], R[1][0], R[2][0]);
+            rot_cols<1, 2>(R, c, s);
+        } else if (ax == 1) {
+            k.a[i] = v3(R[0][1], R[1][1], R[2][1]);
+            rot_cols<2, 0>(R, c, s);
+        } else {
+            k.a[i] = v3(R[0][2], R[1][2], R[2][2]);
+            rot_cols<0, 1>(R, c, s);
         }
         k.z[i] = v3(R[0][2], R[1][2], R[2][2]);
         o = fma3(md.link_len[i], k.z[i], o);
@@ -162,42 +177,43 @@ __device__ inline void chol7_solve(const float L[28], float x[NJ])
     }
 }
 
-// bias torques c(q, qd) (+ gravity when gravity != 0), qdd = 0
+// bias torques c(q, qd) (+ gravity when gravity != 0), qdd = 0.  The forward
+// pass keeps only each link's force m a_c and moment I al + w x I w about its
+// centre; the backward pass accumulates them towards the base.
 __device__ inline void rnea_bias_arm(const DevModel &md, int arm, const ArmKin &k, const float *qd, bool gravity,
                                      float tau[NJ])
 {
-    V3 w[NJ], al[NJ], ac[NJ];
+    V3 f[NJ], nm[NJ];
     V3 wp = v3(0.f, 0.f, 0.f), alp = v3(0.f, 0.f, 0.f);
-    V3 aop = v3(0.f, 0.f, gravity ? md.g : 0.f);
+    V3 ao = v3(0.f, 0.f, gravity ? md.g : 0.f);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
-        V3 ao = aop;
         if (i > 0) {
             const V3 d = k.o[i] - k.o[i - 1];
             ao = ao + cross(alp, d) + cross(wp, cross(wp, d));
         }
-        w[i] = fma3(qd[i], k.a[i], wp);
-        al[i] = fma3(qd[i], cross(wp, k.a[i]), alp);
-        const V3 dc = 0.5f * md.link_len[i] * k.z[i];
-        ac[i] = ao + cross(al[i], dc) + cross(w[i], cross(w[i], dc));
-        wp = w[i];
-        alp = al[i];
-        aop = ao;
+        const V3 w = fma3(qd[i], k.a[i], wp);
+        const V3 al = fma3(qd[i], cross(wp, k.a[i]), alp);
+        const V3 z = k.z[i];
+        const V3 dc = 0.5f * md.link_len[i] * z;
+        const V3 ac = ao + cross(al, dc) + cross(w, cross(w, dc));
+        const float ix = md.Ix[arm][i], dz = md.Iz[arm][i] - ix;
+        // I v = ix v + (iz - ix) (z . v) z
+        const V3 Ia = fma3(dz * dot(z, al), z, ix * al);
+        const V3 Iw = fma3(dz * dot(z, w), z, ix * w);
+        f[i] = md.m[arm][i] * ac;
+        nm[i] = Ia + cross(w, Iw);
+        wp = w;
+        alp = al;
     }
     V3 F = v3(0.f, 0.f, 0.f), N = v3(0.f, 0.f, 0.f);
 #pragma unroll
     for (int i = NJ - 1; i >= 0; --i) {
-        const float ix = md.Ix[arm][i], dz = md.Iz[arm][i] - ix;
         const V3 z = k.z[i];
-        // I v = ix v + (iz - ix) (z . v) z
-        const V3 Ia = fma3(dz * dot(z, al[i]), z, ix * al[i]);
-        const V3 Iw = fma3(dz * dot(z, w[i]), z, ix * w[i]);
-        const float mi = md.m[arm][i];
-        const V3 fi = mi * ac[i];
         const V3 dc = 0.5f * md.link_len[i] * z;
         const V3 dn = md.link_len[i] * z;
-        N = Ia + cross(w[i], Iw) + cross(dc, fi) + N + cross(dn, F);
-        F = fi + F;
+        N = nm[i] + cross(dc, f[i]) + N + cross(dn, F);
+        F = f[i] + F;
         tau[i] = dot(k.a[i], N);
     }
 }

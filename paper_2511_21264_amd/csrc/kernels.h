@@ -24,6 +24,7 @@ struct RolloutArgs {
     int traj;
     int *counters;        // [K][4] or null: contacts, np tests, box tests, overflow
     const int *diverged;  // sticky flag of the plan (skip work when set) or null
+    float *dist;          // [n_cost][K] collision-distance history (scratch of the launch)
 };
 
 // Per-plan device-side statistics (one record per plan in flight).

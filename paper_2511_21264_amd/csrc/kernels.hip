@@ -33,9 +33,18 @@ __device__ __forceinline__ void sample_u(const float *nu_k, const float *sig_k, 
     for (int d = 0; d < NU; ++d) u[d] = clampf(fmaf(sig_k[d], z[d], nu_k[d]), -umax, umax);
 }
 
+// The model's words are re-read (scalar cache) inside the horizon loop rather
+// than hoisted: hoisted, ~100 uniform values overflow the SGPRs into VGPRs.
+__device__ __forceinline__ const DevModel &model(const DevModel *p)
+{
+    asm volatile("" : "+s"(p));
+    return *p;
+}
+
 template <int NC>
 __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a)
 {
+    extern __shared__ float lds[];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= a.K) return;
     const DevModel &md = *a.md;
@@ -43,12 +52,18 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a)
         a.costs[j] = INFINITY;
         return;
     }
+    const LaneList LL{lds, (int)threadIdx.x, (int)blockDim.x};
+    const LanePark pk{lds + NC * CL_FIELDS * blockDim.x, (int)threadIdx.x, (int)blockDim.x};
     float x[NX];
     const float *x0 = a.x0 + (a.x0_shared ? 0 : (long)j * NX);
 #pragma unroll
     for (int i = 0; i < NX; ++i) x[i] = x0[i];
     const int nsub = a.n_sub > 0 ? a.n_sub : md.n_sub;
-    float dprev[MAXCOST];
+    DistHist hist;
+#pragma unroll
+    for (int i = 0; i < 14; ++i) hist.box[i] = 0u;
+    hist.aa[0] = hist.aa[1] = 0u;
+    float *dist = a.dist + j;
     CostAcc acc;
 #pragma unroll
     for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
@@ -66,8 +81,8 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a)
             sample_u(a.nu + k * NU, a.sigma + (a.sigma_per_step ? k * NU : 0), md.u_max, a.key0, a.key1, (uint32_t)j,
                      (uint32_t)k, (uint32_t)a.m, u);
         }
-        for (int s = 0; s < nsub; ++s) substep<NC>(md, x, u, cnt);
-        stage_cost(md, x, u, uprev, k == 0, dprev, acc, cnt);
+        for (int s = 0; s < nsub; ++s) substep<NC>(model(a.md), x, u, LL, pk, cnt);
+        stage_cost(model(a.md), x, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
 #pragma unroll
         for (int d = 0; d < NU; ++d) uprev[d] = u[d];
         if (a.xout && a.traj) {
@@ -101,10 +116,12 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a)
 void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s)
 {
     const dim3 grid((a.K + 63) / 64), block(64);
-    if (ncmax <= 8)
-        hipLaunchKernelGGL(rollout_kernel<8>, grid, block, 0, s, a);
+    const int nc = ncmax <= 4 ? 4 : 8;
+    const size_t lds = (size_t)(nc * CL_FIELDS + PK_FIELDS) * 64 * sizeof(float);
+    if (nc == 4)
+        hipLaunchKernelGGL(rollout_kernel<4>, grid, block, lds, s, a);
     else
-        hipLaunchKernelGGL(rollout_kernel<16>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(rollout_kernel<8>, grid, block, lds, s, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -7,14 +7,22 @@
 //   3. contacts of the candidate pairs in canonical order (AABB cull, then
 //      narrowphase), the first n_cmax with phi < 0;
 //   4. projected Gauss-Seidel on the soft LCP (A + R) f + b >= 0, f >= 0 with
-//      four pyramid-edge rows per contact, n_pgs sweeps from f = 0.  The
-//      Delassus matrix A = J Mt^-1 J^T is never formed: the solver keeps the
-//      velocity v = qd_f + Mt^-1 J^T f, and row e's residual is
-//      e . (J_p v) + R_e f_e - kappa max(-phi, 0) / h.  Within a contact the
-//      point velocity J_p v is advanced with the 3x3 block G = J_p Mt^-1 J_p^T
-//      and the impulse is applied to v once per contact, which is the same
-//      Gauss-Seidel sequence as row-by-row updates of v;
-//   5. semi-implicit Euler q += h qd+, p += h v+, r <- normalize(exp(h w+/2) (x) r).
+//      four pyramid-edge rows per contact (e = n +- mu t1, n +- mu t2),
+//      n_pgs sweeps from f = 0, rows in contact order;
+//   5. qd+ = qd_f + Mt^-1 J^T f, semi-implicit Euler q += h qd+, p += h v+,
+//      r <- normalize(exp(h w+/2) (x) r).
+//
+// Layout of the contact solve (impulse space).  A contact's four rows share
+// its 3-row point Jacobian J_s (relative velocity of the touching points), so
+// A is handled as 3x3 blocks G_st = J_s Mt^-1 J_t^T, and the solver keeps per
+// contact the accumulated impulse P_s = sum_q f_q e_q.  Visiting contact s,
+// its point velocity is J_s v = J_s qd_f + sum_t G_st P_t, each row's residual
+// is e_q . (J_s v) + R_q f_q - kappa max(-phi, 0) / h, and a row update moves
+// J_s v by G_ss e_q df: exactly the Gauss-Seidel sequence of the dense
+// formulation.  Joint velocities are formed once at the end (one Cholesky
+// solve of the generalized impulse).  Candidates are appended to a per-lane
+// list in LDS (dynamic slot index); the solver data lives in registers in NC
+// statically indexed slots.
 #pragma once
 #include "collision.h"
 
@@ -38,47 +46,34 @@ struct StepCounters {
     int overflow;   // substeps with a full contact list
 };
 
-// candidate contact from the pair sweep
-template <int NC>
-struct ContactList {
-    int n;
-    int ga[NC], gb[NC];
-    float phi[NC];
-    float nx[NC], ny[NC], nz[NC];
-    float px[NC], py[NC], pz[NC];
+// Per-lane contact list in LDS, layout [slot][field][lane] (lane-contiguous:
+// conflict-free).  Fields: ga, gb (as int bits), phi, n (3), p (3).
+constexpr int CL_FIELDS = 9;
+struct LaneList {
+    float *base;  // workgroup base
+    int lane;
+    int width;    // lanes per workgroup
+    __device__ __forceinline__ float &at(int slot, int f) const { return base[(slot * CL_FIELDS + f) * width + lane]; }
 };
 
-// solver rows of one contact
-template <int NC>
-struct ContactRows {
-    float J[NC][3][14];  // arm part of J_p = J_A(p) - J_B(p)
-    float W[NC][14][3];  // Mt^-1 J^T (arm part)
-    float rb[NC][3];     // ball lever arm p - c (ball is always geom A)
-    float sb[NC];        // 1 if the ball takes part
-    float G[NC][6];      // J_p Mt^-1 J_p^T: xx yy zz xy xz yz
-    float E[NC][4][3];   // pyramid edges
-    float Dinv[NC][4];   // 1 / (A_ee + R_e)
-    float Rr[NC][4];     // R_e
-    float bias[NC];      // kappa max(-phi, 0) / h
-    float lam[NC][4];
-};
-
-template <int NC>
-__device__ __forceinline__ void try_contact(const DevModel &md, ContactList<NC> &cl, StepCounters &cnt, int ga,
+__device__ __forceinline__ void try_contact(const DevModel &md, const LaneList &L, int &n, StepCounters &cnt, int ga,
                                             int gb, const Shape &A, const Shape &B, const AABB &ba, const AABB &bb)
 {
-    if (cl.n < md.n_cmax && aabb_overlap(ba, bb, 0.f)) {
+    if (n < md.n_cmax && aabb_overlap(ba, bb, 0.f)) {
         ++cnt.np_tests;
         if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
         const Contact3 c = narrow(A, B);
         if (c.phi < 0.f) {
-            const int i = cl.n;
-            cl.ga[i] = ga;
-            cl.gb[i] = gb;
-            cl.phi[i] = c.phi;
-            cl.nx[i] = c.n.x; cl.ny[i] = c.n.y; cl.nz[i] = c.n.z;
-            cl.px[i] = c.p.x; cl.py[i] = c.p.y; cl.pz[i] = c.p.z;
-            cl.n = i + 1;
+            L.at(n, 0) = __int_as_float(ga);
+            L.at(n, 1) = __int_as_float(gb);
+            L.at(n, 2) = c.phi;
+            L.at(n, 3) = c.n.x;
+            L.at(n, 4) = c.n.y;
+            L.at(n, 5) = c.n.z;
+            L.at(n, 6) = c.p.x;
+            L.at(n, 7) = c.p.y;
+            L.at(n, 8) = c.p.z;
+            ++n;
         }
     }
 }
@@ -118,12 +113,11 @@ __device__ __forceinline__ Shape ball_shape(const DevModel &md, V3 pb)
     return s;
 }
 
-// sweep every candidate pair in canonical order
-template <int NC>
-__device__ inline void collect_contacts(const DevModel &md, const ArmKin kin[2], V3 pb, ContactList<NC> &cl,
-                                        StepCounters &cnt)
+// sweep every candidate pair in canonical order; returns the contact count
+__device__ inline int collect_contacts(const DevModel &md, const ArmKin kin[2], V3 pb, const LaneList &L,
+                                       StepCounters &cnt)
 {
-    cl.n = 0;
+    int n = 0;
     const Shape ball = ball_shape(md, pb), table = table_shape();
     const AABB bball = shape_aabb(ball), btab = shape_aabb(table);
     Shape arm[2][7];
@@ -136,25 +130,27 @@ __device__ inline void collect_contacts(const DevModel &md, const ArmKin kin[2],
             barm[a][g] = shape_aabb(arm[a][g]);
         }
     // 1 ball-table
-    try_contact(md, cl, cnt, G_BALL, G_TABLE, ball, table, bball, btab);
+    try_contact(md, L, n, cnt, G_BALL, G_TABLE, ball, table, bball, btab);
     // 2 ball-pads
 #pragma unroll
-    for (int a = 0; a < 2; ++a) try_contact(md, cl, cnt, G_BALL, G_ARM + 7 * a + 6, ball, arm[a][6], bball, barm[a][6]);
+    for (int a = 0; a < 2; ++a) try_contact(md, L, n, cnt, G_BALL, G_ARM + 7 * a + 6, ball, arm[a][6], bball, barm[a][6]);
     // 3 ball-links
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int g = 0; g < 6; ++g) try_contact(md, cl, cnt, G_BALL, G_ARM + 7 * a + g, ball, arm[a][g], bball, barm[a][g]);
+        for (int g = 0; g < 6; ++g)
+            try_contact(md, L, n, cnt, G_BALL, G_ARM + 7 * a + g, ball, arm[a][g], bball, barm[a][g]);
     // 4 ball-boxes
     for (int b = 0; b < md.n_box; ++b) {
         const Shape bx = box_shape(md, b);
-        try_contact(md, cl, cnt, G_BALL, G_BOX + b, ball, bx, bball, shape_aabb(bx));
+        try_contact(md, L, n, cnt, G_BALL, G_BOX + b, ball, bx, bball, shape_aabb(bx));
     }
     // 5 arm geoms 2..7 - table
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int g = 1; g < 7; ++g) try_contact(md, cl, cnt, G_ARM + 7 * a + g, G_TABLE, arm[a][g], table, barm[a][g], btab);
+        for (int g = 1; g < 7; ++g)
+            try_contact(md, L, n, cnt, G_ARM + 7 * a + g, G_TABLE, arm[a][g], table, barm[a][g], btab);
     // 6 arm geoms - boxes
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -162,156 +158,298 @@ __device__ inline void collect_contacts(const DevModel &md, const ArmKin kin[2],
         for (int g = 0; g < 7; ++g)
             for (int b = 0; b < md.n_box; ++b) {
                 const Shape bx = box_shape(md, b);
-                try_contact(md, cl, cnt, G_ARM + 7 * a + g, G_BOX + b, arm[a][g], bx, barm[a][g], shape_aabb(bx));
+                try_contact(md, L, n, cnt, G_ARM + 7 * a + g, G_BOX + b, arm[a][g], bx, barm[a][g], shape_aabb(bx));
             }
     // 7 arm 1 - arm 2
 #pragma unroll
     for (int g = 0; g < 7; ++g)
 #pragma unroll
         for (int g2 = 0; g2 < 7; ++g2)
-            try_contact(md, cl, cnt, G_ARM + g, G_ARM + 7 + g2, arm[0][g], arm[1][g2], barm[0][g], barm[1][g2]);
-    if (cl.n >= md.n_cmax) ++cnt.overflow;
-    cnt.contacts += cl.n;
+            try_contact(md, L, n, cnt, G_ARM + g, G_ARM + 7 + g2, arm[0][g], arm[1][g2], barm[0][g], barm[1][g2]);
+    if (n >= md.n_cmax) ++cnt.overflow;
+    cnt.contacts += n;
+    return n;
 }
 
-// build the solver rows of contact c
-template <int NC>
-__device__ inline void build_rows(const DevModel &md, const ArmKin kin[2], const float L[2][28], V3 pb,
-                                  const ContactList<NC> &cl, int c, ContactRows<NC> &cr)
+// Per-lane spill area in LDS for data that only the (rare) arm-contact path
+// re-reads: both arms' Cholesky factors and joint axes.  Layout [field][lane].
+constexpr int PK_L = 0;          // 2 x 28 packed factors
+constexpr int PK_A = 56;         // 2 x 7 x 3 joint axes
+constexpr int PK_FIELDS = 98;
+struct LanePark {
+    float *base;
+    int lane;
+    int width;
+    __device__ __forceinline__ float &at(int f) const { return base[f * width + lane]; }
+};
+
+// bodies touching at a contact, from its geom ids: arm index (-1 none) and link of each side
+struct Sides {
+    int armA, linkA, armB, linkB;
+    bool ball;  // the ball is geom A
+};
+
+__device__ __forceinline__ Sides contact_sides(int gab)
 {
-    const int ga = cl.ga[c], gb = cl.gb[c];
-    const V3 n = v3(cl.nx[c], cl.ny[c], cl.nz[c]);
-    const V3 p = v3(cl.px[c], cl.py[c], cl.pz[c]);
-    // body of each side: arm index (-1 none) and link
-    const bool a_is_arm = (ga >= G_ARM) & (ga < G_BOX);
-    const bool b_is_arm = (gb >= G_ARM) & (gb < G_BOX);
-    const int armA = a_is_arm ? (ga - G_ARM) / 7 : -1, linkA = a_is_arm ? (ga - G_ARM) % 7 : -1;
-    const int armB = b_is_arm ? (gb - G_ARM) / 7 : -1, linkB = b_is_arm ? (gb - G_ARM) % 7 : -1;
-    float J[3][14];
+    const int ga = gab & 0xff, gb = gab >> 8;
+    Sides s;
+    const bool aa = (ga >= G_ARM) & (ga < G_BOX), ab = (gb >= G_ARM) & (gb < G_BOX);
+    s.armA = aa ? (ga - G_ARM) / 7 : -1;
+    s.linkA = aa ? (ga - G_ARM) % 7 : -1;
+    s.armB = ab ? (gb - G_ARM) / 7 : -1;
+    s.linkB = ab ? (gb - G_ARM) % 7 : -1;
+    s.ball = ga == G_BALL;
+    return s;
+}
+
+// coefficient of joint j of arm a in the relative point Jacobian of a contact
+__device__ __forceinline__ float jac_coef(const Sides &s, int a, int j)
+{
+    return (((s.armA == a) & (j <= s.linkA)) ? 1.f : 0.f) - (((s.armB == a) & (j <= s.linkB)) ? 1.f : 0.f);
+}
+
+// arm part of the 3 x 14 relative point Jacobian at p (axes from the park area)
+__device__ __forceinline__ void arm_jac(const ArmKin kin[2], const LanePark &pk, const Sides &s, V3 p, V3 J[14])
+{
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const float coef = (((armA == a) & (j <= linkA)) ? 1.f : 0.f) - (((armB == a) & (j <= linkB)) ? 1.f : 0.f);
-            const V3 col = coef * cross(kin[a].a[j], p - kin[a].o[j]);
-            J[0][7 * a + j] = col.x;
-            J[1][7 * a + j] = col.y;
-            J[2][7 * a + j] = col.z;
+            const int f = PK_A + 3 * (7 * a + j);
+            const V3 ax = v3(pk.at(f), pk.at(f + 1), pk.at(f + 2));
+            J[7 * a + j] = jac_coef(s, a, j) * cross(ax, p - kin[a].o[j]);
         }
-    float W[14][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        float x0[NJ], x1[NJ];
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) { x0[j] = J[r][j]; x1[j] = J[r][7 + j]; }
-        chol7_solve(L[0], x0);
-        chol7_solve(L[1], x1);
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) { W[j][r] = x0[j]; W[7 + j][r] = x1[j]; }
-    }
-    float G[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int d = 0; d < 14; ++d) {
-        G[0] += J[0][d] * W[d][0];
-        G[1] += J[1][d] * W[d][1];
-        G[2] += J[2][d] * W[d][2];
-        G[3] += J[0][d] * W[d][1];
-        G[4] += J[0][d] * W[d][2];
-        G[5] += J[1][d] * W[d][2];
-    }
-    const float sb = ga == G_BALL ? 1.f : 0.f;
-    const V3 r = p - pb;
-    {
-        // ball block: P/m + (|r|^2 P - r (r.P)) / I
-        const float im = md.inv_ball_m * sb, iI = md.inv_ball_I * sb, rr = dot(r, r);
-        G[0] += im + iI * (rr - r.x * r.x);
-        G[1] += im + iI * (rr - r.y * r.y);
-        G[2] += im + iI * (rr - r.z * r.z);
-        G[3] -= iI * r.x * r.y;
-        G[4] -= iI * r.x * r.z;
-        G[5] -= iI * r.y * r.z;
-    }
-    V3 t1, t2;
-    tangents(n, t1, t2);
-    const V3 e[4] = {fma3(md.mu, t1, n), fma3(-md.mu, t1, n), fma3(md.mu, t2, n), fma3(-md.mu, t2, n)};
-    const S3 Gs = {G[0], G[1], G[2], G[3], G[4], G[5]};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float aee = dot(e[q], mul(Gs, e[q]));
-        const float R = md.eps_r * aee;
-        cr.Dinv[c][q] = 1.0f / (aee + R);
-        cr.Rr[c][q] = R;
-        cr.E[c][q][0] = e[q].x; cr.E[c][q][1] = e[q].y; cr.E[c][q][2] = e[q].z;
-        cr.lam[c][q] = 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int d = 0; d < 14; ++d) cr.J[c][i][d] = J[i][d];
-#pragma unroll
-    for (int d = 0; d < 14; ++d)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) cr.W[c][d][i] = W[d][i];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) cr.G[c][i] = G[i];
-    cr.rb[c][0] = r.x; cr.rb[c][1] = r.y; cr.rb[c][2] = r.z;
-    cr.sb[c] = sb;
-    const float pen = cl.phi[c] < 0.f ? -cl.phi[c] : 0.f;
-    cr.bias[c] = md.kappa_h * pen;
 }
 
-template <int NC>
-__device__ inline void pgs(const DevModel &md, int nc, ContactRows<NC> &cr, float v[14], V3 &vb, V3 &wb)
+__device__ __forceinline__ void solve_parked(const LanePark &pk, int a, float x[NJ])
 {
-    for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
-        for (int c = 0; c < nc; ++c) {
-            V3 vel = v3(0.f, 0.f, 0.f);
+    float L[28];
 #pragma unroll
-            for (int d = 0; d < 14; ++d) {
-                vel.x = fmaf(cr.J[c][0][d], v[d], vel.x);
-                vel.y = fmaf(cr.J[c][1][d], v[d], vel.y);
-                vel.z = fmaf(cr.J[c][2][d], v[d], vel.z);
+    for (int i = 0; i < 28; ++i) L[i] = pk.at(PK_L + 28 * a + i);
+    chol7_solve(L, x);
+}
+
+// ball part of G_st: I/m + ((r_s . r_t) I - r_t r_s^T) / I_b (3x3, row-major)
+__device__ __forceinline__ void ball_block(const DevModel &md, V3 rs, V3 rt, float G[9])
+{
+    const float im = md.inv_ball_m, iI = md.inv_ball_I, d = dot(rs, rt);
+    G[0] += im + iI * (d - rt.x * rs.x);
+    G[1] += -iI * rt.x * rs.y;
+    G[2] += -iI * rt.x * rs.z;
+    G[3] += -iI * rt.y * rs.x;
+    G[4] += im + iI * (d - rt.y * rs.y);
+    G[5] += -iI * rt.y * rs.z;
+    G[6] += -iI * rt.z * rs.x;
+    G[7] += -iI * rt.z * rs.y;
+    G[8] += im + iI * (d - rt.z * rs.z);
+}
+
+__device__ __forceinline__ V3 mul9(const float G[9], V3 v)
+{
+    return v3(G[0] * v.x + G[1] * v.y + G[2] * v.z, G[3] * v.x + G[4] * v.y + G[5] * v.z,
+              G[6] * v.x + G[7] * v.y + G[8] * v.z);
+}
+__device__ __forceinline__ V3 mul9t(const float G[9], V3 v)
+{
+    return v3(G[0] * v.x + G[3] * v.y + G[6] * v.z, G[1] * v.x + G[4] * v.y + G[7] * v.z,
+              G[2] * v.x + G[5] * v.y + G[8] * v.z);
+}
+
+// register-resident solver data of up to NC contacts
+template <int NC>
+struct Slots {
+    int gab[NC];          // geom ids ga | gb << 8
+    V3 r[NC];             // contact point relative to the ball centre
+    V3 b[NC];             // J_s qd_f
+    V3 n[NC], t1[NC], t2[NC];
+    V3 ge[NC][4];         // G_ss e_q
+    float dinv[NC][4], rr[NC][4], lam[NC][4];
+    float bias[NC];
+    V3 P[NC];
+    float G[NC][NC][9];   // G_st for s <= t
+};
+
+template <int NC>
+__device__ inline void contact_solve(const DevModel &md, const ArmKin kin[2], const LanePark &pk, V3 pb,
+                                     const LaneList &LL, int nc, float v[14], V3 &vb, V3 &wb)
+{
+    Slots<NC> S;
+    bool any_arm = false;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        if (s < nc) {
+            S.gab[s] = __float_as_int(LL.at(s, 0)) | (__float_as_int(LL.at(s, 1)) << 8);
+            const float phi = LL.at(s, 2);
+            S.n[s] = v3(LL.at(s, 3), LL.at(s, 4), LL.at(s, 5));
+            S.r[s] = v3(LL.at(s, 6), LL.at(s, 7), LL.at(s, 8)) - pb;
+            tangents(S.n[s], S.t1[s], S.t2[s]);
+            S.bias[s] = md.kappa_h * (phi < 0.f ? -phi : 0.f);
+            S.P[s] = v3(0.f, 0.f, 0.f);
+            const Sides sd = contact_sides(S.gab[s]);
+            any_arm |= (sd.armA >= 0) | (sd.armB >= 0);
+        }
+    }
+    // blocks G_st (s <= t) and free point velocities b_s
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+        if (t < nc) {
+            const Sides st = contact_sides(S.gab[t]);
+            const bool arm_t = (st.armA >= 0) | (st.armB >= 0);
+            V3 bt = v3(0.f, 0.f, 0.f);
+            if (st.ball) bt = vb + cross(wb, S.r[t]);
+#pragma unroll
+            for (int s = 0; s <= t; ++s) {
+                if (s < nc) {
+                    float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    const Sides ss = contact_sides(S.gab[s]);
+                    if (ss.ball & st.ball) ball_block(md, S.r[s], S.r[t], G);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) S.G[s][t][i] = G[i];
+                }
             }
-            const float sb = cr.sb[c];
-            const V3 r = v3(cr.rb[c][0], cr.rb[c][1], cr.rb[c][2]);
-            vel = fma3(sb, vb + cross(wb, r), vel);
-            const S3 G = {cr.G[c][0], cr.G[c][1], cr.G[c][2], cr.G[c][3], cr.G[c][4], cr.G[c][5]};
-            V3 P = v3(0.f, 0.f, 0.f);
+            if (arm_t) {
+                // Mt^-1 J_t^T, one column per Cartesian row of J_t
+                float Wx[14], Wy[14], Wz[14];
+                V3 Jt[14];
+                arm_jac(kin, pk, st, S.r[t] + pb, Jt);
+#pragma unroll
+                for (int d = 0; d < 14; ++d) {
+                    Wx[d] = Jt[d].x;
+                    Wy[d] = Jt[d].y;
+                    Wz[d] = Jt[d].z;
+                    bt = fma3(v[d], Jt[d], bt);
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    if ((st.armA == a) | (st.armB == a)) {
+                        solve_parked(pk, a, Wx + 7 * a);
+                        solve_parked(pk, a, Wy + 7 * a);
+                        solve_parked(pk, a, Wz + 7 * a);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j) Wx[7 * a + j] = Wy[7 * a + j] = Wz[7 * a + j] = 0.f;
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s <= t; ++s) {
+                    if (s < nc) {
+                        const Sides ss = contact_sides(S.gab[s]);
+                        if ((ss.armA >= 0) | (ss.armB >= 0)) {
+                            V3 Js[14];
+                            arm_jac(kin, pk, ss, S.r[s] + pb, Js);
+                            float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                            for (int d = 0; d < 14; ++d) {
+                                G[0] += Js[d].x * Wx[d]; G[1] += Js[d].x * Wy[d]; G[2] += Js[d].x * Wz[d];
+                                G[3] += Js[d].y * Wx[d]; G[4] += Js[d].y * Wy[d]; G[5] += Js[d].y * Wz[d];
+                                G[6] += Js[d].z * Wx[d]; G[7] += Js[d].z * Wy[d]; G[8] += Js[d].z * Wz[d];
+                            }
+#pragma unroll
+                            for (int i = 0; i < 9; ++i) S.G[s][t][i] += G[i];
+                        }
+                    }
+                }
+            }
+            S.b[t] = bt;
+        }
+    }
+    // row constants: edges, G_ss e_q, R_q, 1 / (A_qq + R_q)
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        if (s < nc) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const V3 e = v3(cr.E[c][q][0], cr.E[c][q][1], cr.E[c][q][2]);
-                const float lam = cr.lam[c][q];
-                const float res = dot(e, vel) + cr.Rr[c][q] * lam - cr.bias[c];
-                const float nl = fmaxf(lam - res * cr.Dinv[c][q], 0.f);
-                const float dl = nl - lam;
-                cr.lam[c][q] = nl;
-                vel = fma3(dl, mul(G, e), vel);
-                P = fma3(dl, e, P);
+                const V3 t = q < 2 ? S.t1[s] : S.t2[s];
+                const V3 e = fma3((q & 1) ? -md.mu : md.mu, t, S.n[s]);
+                S.ge[s][q] = mul9(S.G[s][s], e);
+                const float aqq = dot(e, S.ge[s][q]);
+                S.rr[s][q] = md.eps_r * aqq;
+                S.dinv[s][q] = 1.0f / (aqq + S.rr[s][q]);
+                S.lam[s][q] = 0.f;
             }
+        }
+    }
+    // Gauss-Seidel sweeps
+    for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
 #pragma unroll
-            for (int d = 0; d < 14; ++d)
-                v[d] = fmaf(cr.W[c][d][0], P.x, fmaf(cr.W[c][d][1], P.y, fmaf(cr.W[c][d][2], P.z, v[d])));
-            vb = fma3(sb * md.inv_ball_m, P, vb);
-            wb = fma3(sb * md.inv_ball_I, cross(r, P), wb);
+        for (int s = 0; s < NC; ++s) {
+            if (s < nc) {
+                V3 vel = S.b[s];
+#pragma unroll
+                for (int t = 0; t < NC; ++t) {
+                    if (t < nc) vel = vel + (s <= t ? mul9(S.G[s][t], S.P[t]) : mul9t(S.G[t][s], S.P[t]));
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const V3 t = q < 2 ? S.t1[s] : S.t2[s];
+                    const V3 e = fma3((q & 1) ? -md.mu : md.mu, t, S.n[s]);
+                    const float lam = S.lam[s][q];
+                    const float res = dot(e, vel) + S.rr[s][q] * lam - S.bias[s];
+                    const float nl = fmaxf(lam - res * S.dinv[s][q], 0.f);
+                    const float dl = nl - lam;
+                    S.lam[s][q] = nl;
+                    vel = fma3(dl, S.ge[s][q], vel);
+                    S.P[s] = fma3(dl, e, S.P[s]);
+                }
+            }
+        }
+    }
+    // apply: qd+ = qd_f + Mt^-1 sum_s J_s^T P_s
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        if (s < nc) {
+            if (contact_sides(S.gab[s]).ball) {
+                vb = fma3(md.inv_ball_m, S.P[s], vb);
+                wb = fma3(md.inv_ball_I, cross(S.r[s], S.P[s]), wb);
+            }
+        }
+    }
+    if (any_arm) {
+        float gimp[14];
+#pragma unroll
+        for (int d = 0; d < 14; ++d) gimp[d] = 0.f;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            if (s < nc) {
+                const Sides ss = contact_sides(S.gab[s]);
+                if ((ss.armA >= 0) | (ss.armB >= 0)) {
+                    V3 Js[14];
+                    arm_jac(kin, pk, ss, S.r[s] + pb, Js);
+#pragma unroll
+                    for (int d = 0; d < 14; ++d) gimp[d] += dot(Js[d], S.P[s]);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            solve_parked(pk, a, gimp + 7 * a);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) v[7 * a + j] += gimp[7 * a + j];
         }
     }
 }
 
 template <int NC>
-__device__ inline void substep(const DevModel &md, float x[NX], const float u[NU], StepCounters &cnt)
+__device__ inline void substep(const DevModel &md, float x[NX], const float u[NU], const LaneList &LL,
+                               const LanePark &pk, StepCounters &cnt)
 {
     const float h = md.h;
 #pragma unroll
     for (int i = 0; i < 14; ++i) x[XQDES + i] = fmaf(h, u[i], x[XQDES + i]);
     ArmKin kin[2];
-    fk_arm(md, 0, x + XQ, kin[0]);
-    fk_arm(md, 1, x + XQ + 7, kin[1]);
-    float L[2][28];
     float v[14];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        crba_arm(md, a, kin[a], L[a]);
-        chol7(L[a]);
+        if (a == 1) {
+            // keep the two arms' dynamics sequential: their live sets would
+            // otherwise be interleaved by the scheduler and double the registers
+#pragma unroll
+            for (int i = 7; i < 14; ++i) asm volatile("" : "+v"(x[XQ + i]) : "v"(v[6]));
+        }
+        fk_arm(md, a, x + XQ + 7 * a, kin[a]);
+        float L[28];
+        crba_arm(md, a, kin[a], L);
+        chol7(L);
         float c[NJ];
         rnea_bias_arm(md, a, kin[a], x + XQD + 7 * a, md.gravcomp == 0, c);
         float rhs[NJ];
@@ -322,21 +460,25 @@ __device__ inline void substep(const DevModel &md, float x[NX], const float u[NU
             const float tau = clampf(md.kp * (x[XQDES + d] - x[XQ + d]) + md.kd * (u[d] - qd), -md.tau_max, md.tau_max);
             rhs[i] = h * (tau - md.damp * qd - c[i]);
         }
-        chol7_solve(L[a], rhs);
+        chol7_solve(L, rhs);
 #pragma unroll
         for (int i = 0; i < NJ; ++i) v[7 * a + i] = x[XQD + 7 * a + i] + rhs[i];
+        // park the factor and the joint axes for the contact path
+#pragma unroll
+        for (int i = 0; i < 28; ++i) pk.at(PK_L + 28 * a + i) = L[i];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            pk.at(PK_A + 3 * (7 * a + j)) = kin[a].a[j].x;
+            pk.at(PK_A + 3 * (7 * a + j) + 1) = kin[a].a[j].y;
+            pk.at(PK_A + 3 * (7 * a + j) + 2) = kin[a].a[j].z;
+        }
     }
     const V3 pb = v3(x[XPB], x[XPB + 1], x[XPB + 2]);
     V3 vb = v3(x[XVB], x[XVB + 1], x[XVB + 2] - h * md.g);
     V3 wb = v3(x[XWB], x[XWB + 1], x[XWB + 2]);
 
-    ContactList<NC> cl;
-    collect_contacts<NC>(md, kin, pb, cl, cnt);
-    if (cl.n > 0) {
-        ContactRows<NC> cr;
-        for (int c = 0; c < cl.n; ++c) build_rows<NC>(md, kin, L, pb, cl, c, cr);
-        pgs<NC>(md, cl.n, cr, v, vb, wb);
-    }
+    const int nc = collect_contacts(md, kin, pb, LL, cnt);
+    if (nc > 0) contact_solve<NC>(md, kin, pk, pb, LL, nc, v, vb, wb);
 
 #pragma unroll
     for (int i = 0; i < 14; ++i) {

@@ -50,7 +50,7 @@ NU = 14
 PHYSICS = dict(
     kp=100.0, kd=20.0, damp=0.5, armature=0.1, tau_max=150.0,
     gravcomp=1, g=9.81,
-    mu=1.0, kappa=0.2, eps_r=0.01, n_pgs=20, n_cmax=8,
+    mu=1.0, kappa=0.2, eps_r=0.01, n_pgs=20, n_cmax=4,
     u_max=1.5,
 )
 COST = dict(
