@@ -62,6 +62,9 @@ extern "C" {
 #define MPPI_SYNC 4u            /* synchronize the stream before returning */
 #define MPPI_TIME_KERNELS 8u    /* time every rollout launch with HIP events (fills stats->rollout_ms) */
 #define MPPI_TRAJ 16u           /* mppi_simulate: write every post-step state, not only the last */
+#define MPPI_MAP_LANE 32u       /* rollout mapping: one lane per sample (throughput at large K) */
+#define MPPI_MAP_TEAM 64u       /* rollout mapping: 16 lanes per sample (latency at small K) */
+                                /* neither: chosen from K (the library's tuning table) */
 
 /* Global geom ids (pair tables and AABB arrays use them): 0 ball,
  * 1 table, 2 + 7*arm + g (g = 0..5 capsule of link g+1, g = 6 pad sphere on

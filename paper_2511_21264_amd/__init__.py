@@ -20,7 +20,8 @@ NX = 55
 MAX_BOXES = 16
 
 OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5, -6
-DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ = 1, 2, 4, 8, 16
+DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ, MAP_LANE, MAP_TEAM = 1, 2, 4, 8, 16, 32, 64
+_MAPS = {None: 0, "auto": 0, "lane": MAP_LANE, "team": MAP_TEAM}
 
 
 class MppiError(RuntimeError):
@@ -245,13 +246,15 @@ class Scene:
 
 
 def mppi_plan(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, M=1, seed=0, eta=1.0,
-              n_elite=0, sigma_per_step=False, time_kernels=False, want_stats=True, sync=False, stream=None):
+              n_elite=0, sigma_per_step=False, time_kernels=False, want_stats=True, sync=False, stream=None,
+              mapping=None):
     """One plan (Alg. 1).  Arrays: x0[55], nominal_U[H,14], sigma[14] or [H,14],
-    U_new[H,14] (out), costs[K] (out).  Returns a stats dict (or None)."""
+    U_new[H,14] (out), costs[K] (out).  mapping: None/"auto", "lane" or "team".
+    Returns a stats dict (or None)."""
     (px0, pnom, psig, pU, pc), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32), (sigma, np.float32),
                                              (U_new, np.float32), (costs, np.float32)])
     flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | \
-            (TIME_KERNELS if time_kernels else 0) | (SYNC if sync else 0)
+            (TIME_KERNELS if time_kernels else 0) | (SYNC if sync else 0) | _MAPS[mapping]
     o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
     st = Stats()
     rc = lib().mppi_plan(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), pU, pc,
@@ -269,12 +272,12 @@ def mppi_plan(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *,
 
 
 def mppi_simulate(ctx, scene, X0, U, costs=None, terms=None, X_out=None, *, x0_shared=False, n_sub=0, traj=False,
-                  sync=True, stream=None):
+                  sync=True, stream=None, mapping=None):
     """Roll out explicit controls U[n,H,14] from X0[n,55] (or one shared state)."""
     (px0, pU, pc, pt, px), dev = _ptrs([(X0, np.float32), (U, np.float32), (costs, np.float32),
                                         (terms, np.float32), (X_out, np.float32)])
     n, H = U.shape[0], U.shape[1]
-    flags = (DEVICE_PTRS if dev else 0) | (TRAJ if traj else 0) | (SYNC if sync else 0)
+    flags = (DEVICE_PTRS if dev else 0) | (TRAJ if traj else 0) | (SYNC if sync else 0) | _MAPS[mapping]
     _check(lib().mppi_simulate(ctx._h, scene._h, px0, int(bool(x0_shared)), pU, int(n), int(H), int(n_sub), pc, pt,
                                px, flags, _stream(dev, stream)))
 

@@ -247,6 +247,13 @@ int build_model(const mppi_scene_desc *d, DevModel &m)
     return MPPI_OK;
 }
 
+int mapping_of(unsigned flags)
+{
+    if (flags & MPPI_MAP_LANE) return MAP_LANE;
+    if (flags & MPPI_MAP_TEAM) return MAP_TEAM;
+    return MAP_AUTO;
+}
+
 int set_device(mppi_ctx *c)
 {
     HIPCHK(hipSetDevice(c->device));
@@ -400,7 +407,7 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
         ra.diverged = &ctx->st->diverged;
         ra.dist = (float *)ddist;
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], s));
-        launch_rollout(ra, scene->host.n_cmax, s);
+        launch_rollout(ra, scene->host.n_cmax, s, mapping_of(fl));
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], s));
         StatsArgs sa = {(const float *)dcost, K, 1.0 / lambda, n_elite, (double *)dw, ctx->st, m, (const int *)dcnt};
         launch_stats(sa, s);
@@ -492,7 +499,7 @@ int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x
     ra.terms = (float *)dt;
     ra.xout = (float *)dxo;
     ra.traj = traj;
-    launch_rollout(ra, scene->host.n_cmax, s);
+    launch_rollout(ra, scene->host.n_cmax, s, mapping_of(flags));
     HIPCHK(hipGetLastError());
     if ((rc = copy_out(costs, dc, (size_t)n * sizeof(float), dev, s))) return rc;
     if ((rc = copy_out(terms, dt, (size_t)n * 7 * sizeof(float), dev, s))) return rc;

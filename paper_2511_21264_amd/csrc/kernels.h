@@ -66,7 +66,10 @@ struct UpdateArgs {
     double *nu_out64;
 };
 
-void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s);
+// sample-to-lane mapping of the rollout
+constexpr int MAP_AUTO = 0, MAP_LANE = 1, MAP_TEAM = 2;
+int pick_mapping(int K, int requested);
+void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping = MAP_AUTO);
 void launch_stats(const StatsArgs &a, hipStream_t s);
 void launch_update(const UpdateArgs &a, hipStream_t s);
 void launch_sample(const DevModel *md, const float *nu, const float *sigma, int sps, uint32_t k0, uint32_t k1,

@@ -19,6 +19,7 @@
 #include "cost.h"
 #include "kernels.h"
 #include "philox.h"
+#include "team.h"
 
 namespace mppi {
 
@@ -113,10 +114,155 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a)
     }
 }
 
-void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s)
+// Team mapping: 16 lanes per sample, 4 samples per 64-lane workgroup.  Teams
+// past K run on a clamped sample index so that every lane reaches every
+// barrier; they write nothing.
+template <int NC>
+__global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a)
 {
-    const dim3 grid((a.K + 63) / 64), block(64);
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x;
+    const int team = lane >> 4;
+    TeamCtx tc;
+    tc.lane = lane;
+    tc.t = lane & 15;
+    tc.arm = tc.t >> 3;
+    tc.jt = tc.t & 7;
+    tc.seg = tc.arm * 8;
+    tc.joint = tc.jt < 7;
+    tc.tl = lds + team * team_lds_floats(NC);
+    tc.LL = LaneList{tc.tl + TG_FIELDS, 0, 1};
+    tc.pk = LanePark{tc.tl + TG_FIELDS + NC * CL_FIELDS, 0, 1};
+    const int j_raw = blockIdx.x * TEAMS_PER_WAVE + team;
+    const bool active = j_raw < a.K;
+    const int j = active ? j_raw : a.K - 1;
+    const DevModel &md0 = *a.md;
+    const bool skip = a.diverged && *a.diverged;
+    if (skip) {
+        if (active && tc.t == 0) a.costs[j] = INFINITY;
+        return;  // uniform over the launch: every lane leaves
+    }
+    const int jj = tc.joint ? tc.jt : 6;
+    const int d = 7 * tc.arm + jj;  // joint index of this lane
+    JointConst jc;
+    jc.ax = md0.axes[jj];
+    jc.len = tc.joint ? md0.link_len[jj] : 0.f;
+    jc.m = md0.m[tc.arm][jj];
+    jc.ix = md0.Ix[tc.arm][jj];
+    jc.iz = md0.Iz[tc.arm][jj];
+    jc.base = v3(md0.base_pos[tc.arm][0], md0.base_pos[tc.arm][1], md0.base_pos[tc.arm][2]);
+    jc.bc = md0.base_cs[tc.arm][0];
+    jc.bs = md0.base_cs[tc.arm][1];
+    const float *x0 = a.x0 + (a.x0_shared ? 0 : (long)j * NX);
+    TeamState S;
+    S.q = x0[XQ + d];
+    S.qd = x0[XQD + d];
+    S.qdes = x0[XQDES + d];
+    S.pb = v3(x0[XPB], x0[XPB + 1], x0[XPB + 2]);
+    S.vb = v3(x0[XVB], x0[XVB + 1], x0[XVB + 2]);
+    S.wb = v3(x0[XWB], x0[XWB + 1], x0[XWB + 2]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.quat[i] = x0[XQUAT + i];
+    const int nsub = a.n_sub > 0 ? a.n_sub : md0.n_sub;
+    uint32_t hist = 0u;
+    float *dist = a.dist + j;
+    CostAcc acc;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
+    StepCounters cnt = {0, 0, 0, 0};
+    float uprev = 0.f;
+    for (int k = 0; k < a.H; ++k) {
+        const DevModel &md = model(a.md);
+        float u = 0.f;
+        if (tc.joint) {
+            if (a.U) {
+                u = a.U[((long)j * a.H + k) * NU + d];
+            } else {
+                const float z = normal_joint(a.key0, a.key1, (uint32_t)j, (uint32_t)k, (uint32_t)a.m, d);
+                const float sg = a.sigma[(a.sigma_per_step ? k * NU : 0) + d];
+                u = clampf(fmaf(sg, z, a.nu[k * NU + d]), -md.u_max, md.u_max);
+            }
+        }
+        for (int s = 0; s < nsub; ++s) team_substep<NC>(model(a.md), jc, tc, S, u, cnt);
+        team_stage_cost(model(a.md), jc, tc, S, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
+        uprev = u;
+        if (a.xout && a.traj && active) {
+            float *o = a.xout + ((long)j * a.H + k) * NX;
+            if (tc.joint) {
+                o[XQ + d] = S.q; o[XQD + d] = S.qd; o[XQDES + d] = S.qdes;
+            } else if (tc.arm == 0) {
+                o[XPB] = S.pb.x; o[XPB + 1] = S.pb.y; o[XPB + 2] = S.pb.z;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[XQUAT + i] = S.quat[i];
+                o[XVB] = S.vb.x; o[XVB + 1] = S.vb.y; o[XVB + 2] = S.vb.z;
+                o[XWB] = S.wb.x; o[XWB + 1] = S.wb.y; o[XWB + 2] = S.wb.z;
+            }
+        }
+    }
+    const DevModel &md = model(a.md);
+    float t[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) t[i] = team_sum(acc.t[i]);
+    float c = md.w_goal * t[0] + md.w_eo * t[1] + md.w_l * t[2] + md.w_yz * t[3] + md.w_s * t[4] +
+              md.w_c * (t[5] + t[6]);
+    float bad = (isfinite(S.q) && isfinite(S.qd) && isfinite(S.qdes)) ? 0.f : 1.f;
+    bad += (isfinite(S.pb.x) && isfinite(S.pb.y) && isfinite(S.pb.z) && isfinite(S.vb.x) && isfinite(S.vb.y) &&
+            isfinite(S.vb.z) && isfinite(S.wb.x) && isfinite(S.wb.y) && isfinite(S.wb.z) && isfinite(S.quat[0]) &&
+            isfinite(S.quat[1]) && isfinite(S.quat[2]) && isfinite(S.quat[3]))
+               ? 0.f
+               : 1.f;
+    bad = team_sum(bad);
+    const bool finite = isfinite(c) && !(bad > 0.f) && bad == bad;
+    const float np = team_sum((float)cnt.np_tests), nbx = team_sum((float)cnt.box_tests);
+    if (!active) return;
+    if (tc.t == 0) {
+        a.costs[j] = finite ? c : INFINITY;
+        if (a.terms) {
+#pragma unroll
+            for (int i = 0; i < 7; ++i) a.terms[(long)j * 7 + i] = t[i];
+        }
+        if (a.counters) {
+            a.counters[4 * j + 0] = cnt.contacts;
+            a.counters[4 * j + 1] = (int)np;
+            a.counters[4 * j + 2] = (int)nbx;
+            a.counters[4 * j + 3] = cnt.overflow;
+        }
+    }
+    if (a.xout && !a.traj) {
+        float *o = a.xout + (long)j * NX;
+        if (tc.joint) {
+            o[XQ + d] = S.q; o[XQD + d] = S.qd; o[XQDES + d] = S.qdes;
+        } else if (tc.arm == 0) {
+            o[XPB] = S.pb.x; o[XPB + 1] = S.pb.y; o[XPB + 2] = S.pb.z;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[XQUAT + i] = S.quat[i];
+            o[XVB] = S.vb.x; o[XVB + 1] = S.vb.y; o[XVB + 2] = S.vb.z;
+            o[XWB] = S.wb.x; o[XWB + 1] = S.wb.y; o[XWB + 2] = S.wb.z;
+        }
+    }
+}
+
+int pick_mapping(int K, int requested)
+{
+    if (requested == MAP_LANE || requested == MAP_TEAM) return requested;
+    // one lane per sample fills the chip only with tens of thousands of
+    // samples; below that a team per sample cuts the per-step latency
+    return K >= 32768 ? MAP_LANE : MAP_TEAM;
+}
+
+void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping)
+{
     const int nc = ncmax <= 4 ? 4 : 8;
+    if (pick_mapping(a.K, mapping) == MAP_TEAM) {
+        const dim3 grid((a.K + TEAMS_PER_WAVE - 1) / TEAMS_PER_WAVE), block(64);
+        const size_t lds = (size_t)TEAMS_PER_WAVE * team_lds_floats(nc) * sizeof(float);
+        if (nc == 4)
+            hipLaunchKernelGGL(rollout_team_kernel<4>, grid, block, lds, s, a);
+        else
+            hipLaunchKernelGGL(rollout_team_kernel<8>, grid, block, lds, s, a);
+        return;
+    }
+    const dim3 grid((a.K + 63) / 64), block(64);
     const size_t lds = (size_t)(nc * CL_FIELDS + PK_FIELDS) * 64 * sizeof(float);
     if (nc == 4)
         hipLaunchKernelGGL(rollout_kernel<4>, grid, block, lds, s, a);

@@ -152,8 +152,9 @@ def _group_close(got, want, rtol):
         assert err <= rtol * scale, (a, b, err, scale)
 
 
+@pytest.mark.parametrize("mapping", ["lane", "team"])
 @pytest.mark.parametrize("cfg,kind", [(1, "random"), (2, "random"), (3, "random"), (1, "contact"), (2, "contact")])
-def test_one_substep_and_one_step(mp, ctx, oracle_mod, cfg, kind):
+def test_one_substep_and_one_step(mp, ctx, oracle_mod, cfg, kind, mapping):
     sc = W.make_scene(cfg)
     scene = mp.Scene(ctx, sc)
     o = oracle_mod.Oracle(sc)
@@ -162,7 +163,7 @@ def test_one_substep_and_one_step(mp, ctx, oracle_mod, cfg, kind):
     U = np.random.default_rng(5).uniform(-1.0, 1.0, (n, 1, 14)).astype(np.float32)
     for nsub in (1, int(sc["n_sub"])):
         Xo = torch.zeros((n, 55), device=DEV)
-        mp.mppi_simulate(ctx, scene, T(X), T(U), X_out=Xo, n_sub=nsub)
+        mp.mppi_simulate(ctx, scene, T(X), T(U), X_out=Xo, n_sub=nsub, mapping=mapping)
         torch.cuda.synchronize()
         got = Xo.cpu().numpy().astype(np.float64)
         want = np.zeros_like(got)
@@ -179,7 +180,8 @@ def test_one_substep_and_one_step(mp, ctx, oracle_mod, cfg, kind):
     scene.close()
 
 
-def test_contact_free_rollout_20_steps(mp, ctx, oracle_mod):
+@pytest.mark.parametrize("mapping", ["lane", "team"])
+def test_contact_free_rollout_20_steps(mp, ctx, oracle_mod, mapping):
     sc = W.make_scene(1)
     scene = mp.Scene(ctx, sc)
     o = oracle_mod.Oracle(sc)
@@ -194,7 +196,7 @@ def test_contact_free_rollout_20_steps(mp, ctx, oracle_mod):
     Xo = torch.zeros((n, H, 55), device=DEV)
     costs = torch.zeros(n, device=DEV)
     terms = torch.zeros((n, 7), device=DEV)
-    mp.mppi_simulate(ctx, scene, T(X), T(U), costs=costs, terms=terms, X_out=Xo, traj=True)
+    mp.mppi_simulate(ctx, scene, T(X), T(U), costs=costs, terms=terms, X_out=Xo, traj=True, mapping=mapping)
     torch.cuda.synchronize()
     got = Xo.cpu().numpy().astype(np.float64)
     for i in range(n):
@@ -253,7 +255,8 @@ def test_update_all_nonfinite_diverges(mp, ctx):
 
 
 # ---------------------------------------------------------------- plan
-def test_plan_equals_its_stages(mp, ctx):
+@pytest.mark.parametrize("mapping", ["lane", "team"])
+def test_plan_equals_its_stages(mp, ctx, mapping):
     """mppi_plan = M x (sample -> simulate -> update) through the single-stage calls."""
     sc = W.make_scene(1)
     scene = mp.Scene(ctx, sc)
@@ -264,13 +267,13 @@ def test_plan_equals_its_stages(mp, ctx):
     nom = T(np.random.default_rng(1).uniform(-0.2, 0.2, (H, 14)))
     Unew = torch.zeros((H, 14), device=DEV)
     costs = torch.zeros(K, device=DEV)
-    st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"])
+    st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"], mapping=mapping)
     nu = nom.clone()
     for m in range(M):
         U = torch.zeros((K, H, 14), device=DEV)
         mp.mppi_sample(ctx, scene, nu, sig, pp["seed"], m, K, U=U)
         c = torch.zeros(K, device=DEV)
-        mp.mppi_simulate(ctx, scene, x0, U, costs=c, x0_shared=True)
+        mp.mppi_simulate(ctx, scene, x0, U, costs=c, x0_shared=True, mapping=mapping)
         nu2 = torch.zeros_like(nu)
         mp.mppi_update(ctx, scene, c, nu, sig, pp["seed"], m, pp["lam"], nu2)
         nu = nu2
@@ -281,13 +284,14 @@ def test_plan_equals_its_stages(mp, ctx):
     # bit-identical on repeat
     U2 = torch.zeros_like(Unew)
     c2 = torch.zeros_like(costs)
-    mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U2, c2, M=M, seed=pp["seed"])
+    mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U2, c2, M=M, seed=pp["seed"], mapping=mapping)
     torch.cuda.synchronize()
     assert torch.equal(U2, Unew) and torch.equal(c2, costs)
     scene.close()
 
 
-def test_plan_c1_against_oracle(mp, ctx, oracle_mod):
+@pytest.mark.parametrize("mapping", ["lane", "team"])
+def test_plan_c1_against_oracle(mp, ctx, oracle_mod, mapping):
     """End-to-end plan at the small workload (K=64, H=20, 5 iterations).  The
     ball rests on the table, so every rollout is in contact; the oracle's
     FP64 plan is compared through its last-iteration costs and U_new."""
@@ -300,13 +304,13 @@ def test_plan_c1_against_oracle(mp, ctx, oracle_mod):
     Unew = torch.zeros((H, 14), device=DEV)
     costs = torch.zeros(K, device=DEV)
     st = mp.mppi_plan(ctx, scene, T(x0), torch.zeros((H, 14), device=DEV), K, H, pp["lam"], T(pp["sigma"]), Unew,
-                      costs, M=M, seed=pp["seed"])
+                      costs, M=M, seed=pp["seed"], mapping=mapping)
     torch.cuda.synchronize()
     r = o.plan(f32(x0), np.zeros((H, 14)), K, H, pp["lam"], f32(pp["sigma"].astype(np.float32)), M, pp["seed"])
     cg = costs.cpu().numpy()
     rel = np.abs(cg - r["costs"]) / np.abs(r["costs"])
     dU = np.abs(Unew.cpu().numpy() - r["nu"]).max()
-    print(f"c1 plan: cost rel err median {np.median(rel):.2e} max {rel.max():.2e}; |dU_new|max {dU:.2e}; "
+    print(f"c1 plan ({mapping}): cost rel err median {np.median(rel):.2e} max {rel.max():.2e}; |dU_new|max {dU:.2e}; "
           f"ess {st['ess']:.2f}")
     assert st["rc"] == 0 and r["rc"] == 0
     assert np.median(rel) < 1e-3
@@ -342,4 +346,24 @@ def test_plan_host_pointers_and_errors(mp, ctx):
     with pytest.raises(mp.MppiError) as e:
         mp.Scene(ctx, bad_sc)
     assert e.value.code == mp.E_MODEL
+    scene.close()
+
+
+def test_lane_and_team_mappings_agree(mp, ctx):
+    """Both mappings roll out the same physics: contact-rich 64-step rollouts
+    of the obstacle workload agree closely (FP32 rounding differs)."""
+    sc = W.make_scene(2)
+    scene = mp.Scene(ctx, sc)
+    n, H = 37, 64
+    x0 = T(W.initial_state(sc))
+    U = T(np.random.default_rng(9).uniform(-1.0, 1.0, (n, H, 14)))
+    out = {}
+    for mapping in ("lane", "team"):
+        c = torch.zeros(n, device=DEV)
+        tm = torch.zeros((n, 7), device=DEV)
+        mp.mppi_simulate(ctx, scene, x0, U, costs=c, terms=tm, x0_shared=True, mapping=mapping)
+        torch.cuda.synchronize()
+        out[mapping] = c.cpu().numpy()
+    rel = np.abs(out["lane"] - out["team"]) / np.abs(out["lane"])
+    assert np.median(rel) < 1e-4 and rel.max() < 1e-2
     scene.close()
