@@ -46,6 +46,57 @@ def cpu_baseline(sc, pp, threads, min_s=10.0, max_plans=5):
                        f"{dt:.1f} s on {threads} threads", plan_ms=dt / n * 1e3)
 
 
+def bench_packed(mp, ctx, steps, warmup, mapping, n_scenes=32):
+    """Uneven batch of independently seeded scenes (K 256..4096, H 32..128,
+    0..12 boxes, M=10): one mppi_plan_batch call per step against the plain
+    form, the same requests planned one after another with mppi_plan."""
+    import numpy as np
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    items = []
+    for sc, pp in W.packed_scenes(n_scenes, 4):
+        H, K = pp["H"], pp["K"]
+        items.append(dict(scene=mp.Scene(ctx, sc), K=K, H=H, lam=pp["lam"], M=pp["M"], seed=pp["seed"],
+                          x0=torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev),
+                          nominal_U=torch.zeros((H, 14), dtype=torch.float32, device=dev),
+                          sigma=torch.tensor(pp["sigma"], dtype=torch.float32, device=dev),
+                          U_new=torch.zeros((H, 14), dtype=torch.float32, device=dev),
+                          costs=torch.zeros(K, dtype=torch.float32, device=dev)))
+    env = sum(it["M"] * it["K"] * it["H"] for it in items)
+
+    def batched():
+        mp.mppi_plan_batch(ctx, items, mapping=mapping)
+
+    def plain():
+        for it in items:
+            mp.mppi_plan(ctx, it["scene"], it["x0"], it["nominal_U"], it["K"], it["H"], it["lam"], it["sigma"],
+                         it["U_new"], it["costs"], M=it["M"], seed=it["seed"], mapping=mapping, want_stats=False,
+                         sync=True)
+
+    out = {"workload": f"{n_scenes} packed scenes: K 256..4096, H 32..128, 0..12 boxes, M=10, seeded",
+           "env_steps_per_batch": env}
+    for name, fn in (("batched", batched), ("plain", plain)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            a = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - a)
+        el = time.perf_counter() - t0
+        out[name] = {"env_steps_per_s": env * steps / el, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p99_ms": float(np.percentile(lat, 99) * 1e3), "steps": steps}
+        print(json.dumps({"packed_leg": name, **out[name]}), file=sys.stderr, flush=True)
+    out["speedup"] = out["batched"]["env_steps_per_s"] / out["plain"]["env_steps_per_s"]
+    for it in items:
+        it["scene"].close()
+    return out
+
+
 def calib_copy(mb):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -67,6 +118,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0)
+    ap.add_argument("--mapping", default="auto", choices=["auto", "lane", "team"])
+    ap.add_argument("--packed-steps", type=int, default=2, help="steps of the packed-batch leg (0: skip)")
     args = ap.parse_args()
     if args.calib_copy_mb:
         calib_copy(args.calib_copy_mb)
@@ -98,7 +151,7 @@ def main():
 
     def plan():
         return mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"],
-                            time_kernels=True)
+                            time_kernels=True, mapping=args.mapping)
 
     for _ in range(args.warmup):
         plan()
@@ -155,6 +208,8 @@ def main():
         "stats": {"ess": st["ess"], "c_min": st["c_min"], "contacts_per_substep":
                   st["contacts"] / (M * K * H * int(sc["n_sub"]))},
     }
+    if args.packed_steps > 0:
+        out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, args.mapping)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(sc, pp, threads)

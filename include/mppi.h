@@ -169,6 +169,34 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
               double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs,
               mppi_stats *stats, void *stream);
 
+/* One request of a packed batch. */
+typedef struct mppi_request {
+    const mppi_scene *scene;  /* scene of this request (same context) */
+    const float *x0;          /* [MPPI_NX] */
+    const float *nominal_U;   /* [H][14] */
+    int K, H;
+    double lambda;
+    const float *sigma;       /* [14], or [H][14] with MPPI_SIGMA_PER_STEP in opts.flags */
+    mppi_opts opts;           /* M, seed, eta, n_elite; of the flags only MPPI_SIGMA_PER_STEP is read */
+    float *U_new;             /* [H][14] out */
+    float *costs;             /* [K] out, nullable */
+    mppi_stats *stats;        /* out, nullable */
+    int status;               /* out: MPPI_OK or MPPI_E_DIVERGED */
+} mppi_request;
+
+/* Uneven batch: n independent plans (different scenes, K, H, M) packed so
+ * that each MPPI iteration is one rollout launch over every request's
+ * samples, one statistics launch and one update launch (requests with fewer
+ * iterations drop out of later launches).  `flags`: MPPI_DEVICE_PTRS (every
+ * array of every request is a device pointer), MPPI_MAP_LANE/MPPI_MAP_TEAM
+ * (one mapping for the whole batch; chosen from the total sample count
+ * otherwise), MPPI_TIME_KERNELS (each request's stats->rollout_ms receives the
+ * batch's summed rollout time).  Results of a request equal its results
+ * planned alone with the same mapping, bit for bit.  Synchronizes `stream`
+ * before returning.  Returns MPPI_OK when the batch ran (per-request status
+ * reports divergence), or MPPI_E_INVAL / MPPI_E_NOMEM / MPPI_E_DEVICE. */
+int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, void *stream);
+
 /* Roll out explicit control sequences (Alg. 1 rollout and cost steps).
  *   X0: [n][MPPI_NX] start states (one per sample), or one state shared by
  *   all samples when x0_shared != 0; U[n][H][14] controls (used as given,

@@ -76,6 +76,14 @@ class Stats(C.Structure):
         return d
 
 
+class Request(C.Structure):
+    _fields_ = [
+        ("scene", C.c_void_p), ("x0", C.c_void_p), ("nominal_U", C.c_void_p), ("K", C.c_int), ("H", C.c_int),
+        ("lam", C.c_double), ("sigma", C.c_void_p), ("opts", Opts), ("U_new", C.c_void_p), ("costs", C.c_void_p),
+        ("stats", C.POINTER(Stats)), ("status", C.c_int),
+    ]
+
+
 _lib = None
 _P = C.c_void_p
 
@@ -98,6 +106,7 @@ def lib():
                                     C.POINTER(Stats), _P]),
             "mppi_simulate": (C.c_int, [_P, _P, _P, C.c_int, _P, C.c_int, C.c_int, C.c_int, _P, _P, _P, C.c_uint,
                                         _P]),
+            "mppi_plan_batch": (C.c_int, [_P, C.c_int, C.POINTER(Request), C.c_uint, _P]),
             "mppi_sample": (C.c_int, [_P, _P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, _P, _P, _P, C.c_uint,
                                       _P]),
             "mppi_update": (C.c_int, [_P, _P, _P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_double,
@@ -326,3 +335,36 @@ def mppi_narrowphase(ctx, scene, X, phi, normal=None, point=None, lo=None, hi=No
     flags = (DEVICE_PTRS if dev else 0) | (SYNC if sync else 0)
     _check(lib().mppi_narrowphase(ctx._h, scene._h, pX, int(X.shape[0]), pphi, pn, pp, plo, phi_, flags,
                                   _stream(dev, stream)))
+
+
+def mppi_plan_batch(ctx, items, *, mapping=None, time_kernels=False, stream=None):
+    """Packed uneven batch.  `items`: list of dicts with keys scene (Scene),
+    x0, nominal_U, K, H, lam, sigma, U_new, costs (optional), M, seed, eta,
+    n_elite, sigma_per_step.  Returns one stats dict (with "status") per item."""
+    n = len(items)
+    reqs = (Request * n)()
+    stats = [Stats() for _ in range(n)]
+    side = None
+    for i, it in enumerate(items):
+        (px0, pnom, psig, pU, pc), dev = _ptrs([(it["x0"], np.float32), (it["nominal_U"], np.float32),
+                                                 (it["sigma"], np.float32), (it["U_new"], np.float32),
+                                                 (it.get("costs"), np.float32)])
+        if side is None:
+            side = dev
+        elif side != dev:
+            raise ValueError("mixing device and host arrays in one batch")
+        r = reqs[i]
+        r.scene = it["scene"]._h
+        r.x0, r.nominal_U, r.sigma, r.U_new, r.costs = px0, pnom, psig, pU, pc
+        r.K, r.H, r.lam = int(it["K"]), int(it["H"]), float(it["lam"])
+        r.opts = Opts(int(it.get("M", 1)), int(it.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF, float(it.get("eta", 1.0)),
+                      int(it.get("n_elite", 0)), SIGMA_PER_STEP if it.get("sigma_per_step") else 0)
+        r.stats = C.pointer(stats[i])
+    flags = (DEVICE_PTRS if side else 0) | (TIME_KERNELS if time_kernels else 0) | _MAPS[mapping]
+    _check(lib().mppi_plan_batch(ctx._h, n, reqs, flags, _stream(bool(side), stream)))
+    out = []
+    for i in range(n):
+        d = stats[i].as_dict()
+        d["status"] = reqs[i].status
+        out.append(d)
+    return out

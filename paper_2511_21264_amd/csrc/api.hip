@@ -3,6 +3,7 @@
 // the launch sequence of a plan (M x [rollout -> stats -> update]).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,7 +42,10 @@ struct Buf {
     size_t cap = 0;
 };
 
-enum Slot { S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_DIST, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3, S_N };
+enum Slot {
+    S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_DIST, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3,
+    S_BTAB, S_BST, S_BIN, S_BNU, S_BCOST, S_BW, S_BCNT, S_BDIST, S_N
+};
 
 }  // namespace
 
@@ -50,6 +54,9 @@ struct mppi_ctx {
     Buf buf[S_N];
     PlanStats *st = nullptr;
     std::vector<hipEvent_t> ev;
+    // pinned host staging of packed-batch tables
+    void *host_tab = nullptr;
+    size_t host_tab_cap = 0;
 };
 
 struct mppi_scene {
@@ -293,6 +300,7 @@ void mppi_ctx_destroy(mppi_ctx *c)
         if (b.p) hipFree(b.p);
     if (c->st) hipFree(c->st);
     for (auto e : c->ev) hipEventDestroy(e);
+    if (c->host_tab) hipHostFree(c->host_tab);
     delete c;
 }
 
@@ -460,6 +468,206 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
             std::memcpy(U_new, nominal_U, (size_t)H * NU * sizeof(float));
         HIPCHK(hipStreamSynchronize(s));
         return fail(MPPI_E_DIVERGED, "every sample diverged in some iteration");
+    }
+    return MPPI_OK;
+}
+
+int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, void *stream)
+{
+    if (!ctx || !reqs || n < 1) return fail(MPPI_E_INVAL, "NULL context/requests or n < 1");
+    const bool dev = flags & MPPI_DEVICE_PTRS, timing = flags & MPPI_TIME_KERNELS;
+    long total_k = 0;
+    int maxM = 0, ncmax = 0;
+    for (int i = 0; i < n; ++i) {
+        mppi_request &r = reqs[i];
+        if (!r.scene || !r.x0 || !r.nominal_U || !r.sigma || !r.U_new) return fail(MPPI_E_INVAL, "request %d: NULL argument", i);
+        if (r.scene->ctx != ctx) return fail(MPPI_E_INVAL, "request %d: scene of another context", i);
+        if (r.K < 1 || r.K > MPPI_MAX_K || r.H < 1 || r.H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "request %d: K or H out of range", i);
+        if (!(r.lambda > 0) || !std::isfinite(r.lambda) || r.opts.M < 1 || r.opts.M > 100000 || !std::isfinite(r.opts.eta))
+            return fail(MPPI_E_INVAL, "request %d: bad lambda, M or eta", i);
+        const size_t nsig = (r.opts.flags & MPPI_SIGMA_PER_STEP) ? (size_t)r.H * NU : NU;
+        if (!dev) {
+            if (!all_finite(r.x0, NX) || !all_finite(r.nominal_U, (size_t)r.H * NU) || !all_finite(r.sigma, nsig))
+                return fail(MPPI_E_INVAL, "request %d: non-finite input", i);
+            for (size_t q = 0; q < nsig; ++q)
+                if (r.sigma[q] < 0) return fail(MPPI_E_INVAL, "request %d: sigma < 0", i);
+        }
+        r.status = MPPI_OK;
+        total_k += r.K;
+        maxM = std::max(maxM, r.opts.M);
+        ncmax = std::max(ncmax, r.scene->host.n_cmax);
+    }
+    if (total_k > MPPI_MAX_K) return fail(MPPI_E_INVAL, "batch has more than %d samples", MPPI_MAX_K);
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int map = pick_mapping((int)total_k, mapping_of(flags));
+    const int per = samples_per_block(map);
+    // requests in order of decreasing M: the ones still iterating form a prefix
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return reqs[a].opts.M > reqs[b].opts.M; });
+    // offsets of every request's slices in the packed buffers
+    std::vector<size_t> o_k(n), o_h(n), o_sig(n), o_x0(n);
+    size_t nk = 0, nh = 0, nsig_tot = 0;
+    for (int i = 0; i < n; ++i) {
+        const mppi_request &r = reqs[ord[i]];
+        o_k[i] = nk;
+        nk += (size_t)r.K;
+        o_h[i] = nh;
+        nh += (size_t)r.H * NU;
+        o_sig[i] = nsig_tot;
+        nsig_tot += (r.opts.flags & MPPI_SIGMA_PER_STEP) ? (size_t)r.H * NU : NU;
+        o_x0[i] = (size_t)i * NX;
+    }
+    // block tables
+    std::vector<int> blk, ublk, blk_prefix(n + 1, 0), ublk_prefix(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        const mppi_request &r = reqs[ord[i]];
+        const int nb = (r.K + per - 1) / per;
+        for (int b = 0; b < nb; ++b) { blk.push_back(i); blk.push_back(b); }
+        for (int k = 0; k < r.H; ++k) { ublk.push_back(i); ublk.push_back(k); }
+        blk_prefix[i + 1] = (int)blk.size() / 2;
+        ublk_prefix[i + 1] = (int)ublk.size() / 2;
+    }
+    // device buffers
+    void *d_nu, *d_cost, *d_w, *d_cnt, *d_dist, *d_st, *d_in;
+    if ((rc = ensure(ctx, S_BNU, nh * sizeof(float), &d_nu))) return rc;
+    if ((rc = ensure(ctx, S_BCOST, nk * sizeof(float), &d_cost))) return rc;
+    if ((rc = ensure(ctx, S_BW, nk * sizeof(double), &d_w))) return rc;
+    if ((rc = ensure(ctx, S_BCNT, nk * 4 * sizeof(int), &d_cnt))) return rc;
+    if ((rc = ensure(ctx, S_BDIST, nk * MAXCOST * sizeof(float), &d_dist))) return rc;
+    if ((rc = ensure(ctx, S_BST, (size_t)n * sizeof(PlanStats), &d_st))) return rc;
+    const size_t in_floats = (size_t)n * NX + nh + nsig_tot;
+    if ((rc = ensure(ctx, S_BIN, in_floats * sizeof(float), &d_in))) return rc;
+    float *d_x0 = (float *)d_in, *d_nom = d_x0 + (size_t)n * NX, *d_sig = d_nom + nh;
+    // stage inputs into the packed buffers
+    for (int i = 0; i < n; ++i) {
+        const mppi_request &r = reqs[ord[i]];
+        const size_t ns = (r.opts.flags & MPPI_SIGMA_PER_STEP) ? (size_t)r.H * NU : NU;
+        const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIPCHK(hipMemcpyAsync(d_x0 + o_x0[i], r.x0, NX * sizeof(float), kind, s));
+        HIPCHK(hipMemcpyAsync(d_nom + o_h[i], r.nominal_U, (size_t)r.H * NU * sizeof(float), kind, s));
+        HIPCHK(hipMemcpyAsync(d_sig + o_sig[i], r.sigma, ns * sizeof(float), kind, s));
+    }
+    HIPCHK(hipMemcpyAsync(d_nu, d_nom, nh * sizeof(float), hipMemcpyDeviceToDevice, s));
+    // argument tables (pinned staging, then one upload)
+    const size_t tab_bytes = (size_t)n * (sizeof(RolloutArgs) + sizeof(StatsArgs) + sizeof(UpdateArgs)) +
+                             (blk.size() + ublk.size()) * sizeof(int) + 256;
+    void *d_tab;
+    if ((rc = ensure(ctx, S_BTAB, tab_bytes, &d_tab))) return rc;
+    HIPCHK(hipStreamSynchronize(s));  // the pinned staging area may still feed a previous upload
+    if (ctx->host_tab_cap < tab_bytes) {
+        if (ctx->host_tab) hipHostFree(ctx->host_tab);
+        ctx->host_tab = nullptr;
+        ctx->host_tab_cap = 0;
+        if (hipHostMalloc(&ctx->host_tab, tab_bytes * 2) != hipSuccess) return fail(MPPI_E_NOMEM, "pinned table allocation failed");
+        ctx->host_tab_cap = tab_bytes * 2;
+    }
+    char *hbase = (char *)ctx->host_tab;
+    RolloutArgs *hr = (RolloutArgs *)hbase;
+    StatsArgs *hs = (StatsArgs *)(hr + n);
+    UpdateArgs *hu = (UpdateArgs *)(hs + n);
+    int *hblk = (int *)(hu + n);
+    int *hublk = hblk + blk.size();
+    PlanStats *st = (PlanStats *)d_st;
+    for (int i = 0; i < n; ++i) {
+        const mppi_request &r = reqs[ord[i]];
+        const uint32_t k0 = (uint32_t)(r.opts.seed & 0xffffffffu), k1 = (uint32_t)(r.opts.seed >> 32);
+        RolloutArgs ra = {};
+        ra.md = r.scene->dev;
+        ra.x0 = d_x0 + o_x0[i];
+        ra.x0_shared = 1;
+        ra.nu = (const float *)d_nu + o_h[i];
+        ra.sigma = d_sig + o_sig[i];
+        ra.sigma_per_step = (r.opts.flags & MPPI_SIGMA_PER_STEP) ? 1 : 0;
+        ra.key0 = k0;
+        ra.key1 = k1;
+        ra.K = r.K;
+        ra.H = r.H;
+        ra.costs = (float *)d_cost + o_k[i];
+        ra.counters = (int *)d_cnt + 4 * o_k[i];
+        ra.diverged = &st[i].diverged;
+        ra.dist = (float *)d_dist + MAXCOST * o_k[i];
+        hr[i] = ra;
+        const int ne = (r.opts.n_elite <= 0 || r.opts.n_elite >= r.K) ? r.K : r.opts.n_elite;
+        hs[i] = StatsArgs{(const float *)d_cost + o_k[i], r.K, 1.0 / r.lambda, ne, (double *)d_w + o_k[i], &st[i], 0,
+                          (const int *)d_cnt + 4 * o_k[i]};
+        hu[i] = UpdateArgs{(const double *)d_w + o_k[i], r.K, r.H, (const float *)d_nu + o_h[i], d_sig + o_sig[i],
+                           ra.sigma_per_step, r.scene->host.u_max, k0, k1, 0, r.opts.eta, &st[i],
+                           (float *)d_nu + o_h[i], nullptr};
+    }
+    std::memcpy(hblk, blk.data(), blk.size() * sizeof(int));
+    std::memcpy(hublk, ublk.data(), ublk.size() * sizeof(int));
+    HIPCHK(hipMemcpyAsync(d_tab, hbase, tab_bytes - 256, hipMemcpyHostToDevice, s));
+    const RolloutArgs *d_rt = (const RolloutArgs *)d_tab;
+    const StatsArgs *d_sst = (const StatsArgs *)(d_rt + n);
+    const UpdateArgs *d_ut = (const UpdateArgs *)(d_sst + n);
+    const int *d_blk = (const int *)(d_ut + n);
+    const int *d_ublk = d_blk + blk.size();
+    launch_reset_stats(st, s, n);
+    if (timing) {
+        while ((int)ctx->ev.size() < 2 * maxM) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ctx->ev.push_back(e);
+        }
+    }
+    for (int m = 0; m < maxM; ++m) {
+        int act = 0;
+        while (act < n && reqs[ord[act]].opts.M > m) ++act;
+        // stats entries carry the iteration index for the per-iteration minima
+        if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], s));
+        launch_rollout_batch(d_rt, d_blk, blk_prefix[act], ncmax, m, map, s);
+        if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], s));
+        launch_stats_batch(d_sst, act, m, s);
+        launch_update_batch(d_ut, d_ublk, ublk_prefix[act], m, s);
+    }
+    HIPCHK(hipGetLastError());
+    // outputs
+    std::vector<PlanStats> hst(n);
+    HIPCHK(hipMemcpyAsync(hst.data(), st, (size_t)n * sizeof(PlanStats), hipMemcpyDeviceToHost, s));
+    for (int i = 0; i < n; ++i) {
+        mppi_request &r = reqs[ord[i]];
+        const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        HIPCHK(hipMemcpyAsync(r.U_new, (const float *)d_nu + o_h[i], (size_t)r.H * NU * sizeof(float), kind, s));
+        if (r.costs) HIPCHK(hipMemcpyAsync(r.costs, (const float *)d_cost + o_k[i], (size_t)r.K * sizeof(float), kind, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    float roll_ms = 0.f;
+    if (timing) {
+        for (int m = 0; m < maxM; ++m) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2 * m], ctx->ev[2 * m + 1]));
+            roll_ms += ms;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        mppi_request &r = reqs[ord[i]];
+        const PlanStats &p = hst[i];
+        if (r.stats) {
+            std::memset(r.stats, 0, sizeof *r.stats);
+            r.stats->ess = p.ess;
+            r.stats->c_min = p.cmin;
+            r.stats->best = p.best;
+            r.stats->n_nonfinite = r.K - p.n_finite;
+            r.stats->diverged = p.diverged;
+            r.stats->iterations = r.opts.M;
+            for (int q = 0; q < 64 && q < r.opts.M; ++q) r.stats->cmin_iter[q] = p.cmin_iter[q];
+            r.stats->contacts = (double)p.counters[0];
+            r.stats->np_tests = (double)p.counters[1];
+            r.stats->box_tests = (double)p.counters[2];
+            r.stats->overflow = (double)p.counters[3];
+            r.stats->rollout_ms = roll_ms;
+            r.stats->rollout_launches = maxM;
+        }
+        if (p.diverged) {
+            r.status = MPPI_E_DIVERGED;
+            if (dev)
+                HIPCHK(hipMemcpy(r.U_new, r.nominal_U, (size_t)r.H * NU * sizeof(float), hipMemcpyDeviceToDevice));
+            else
+                std::memcpy(r.U_new, r.nominal_U, (size_t)r.H * NU * sizeof(float));
+        }
     }
     return MPPI_OK;
 }

@@ -70,6 +70,13 @@ struct UpdateArgs {
 constexpr int MAP_AUTO = 0, MAP_LANE = 1, MAP_TEAM = 2;
 int pick_mapping(int K, int requested);
 void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping = MAP_AUTO);
+int samples_per_block(int mapping);
+// packed launches: tables live in device memory; block b of a rollout launch
+// covers block blk[2b+1] of scene blk[2b]; update blocks are (scene, step) pairs
+void launch_rollout_batch(const RolloutArgs *d_tab, const int *d_blk, int nblk, int ncmax, int m, int mapping,
+                          hipStream_t s);
+void launch_stats_batch(const StatsArgs *d_tab, int n, int m, hipStream_t s);
+void launch_update_batch(const UpdateArgs *d_tab, const int *d_blk, int nblk, int m, hipStream_t s);
 void launch_stats(const StatsArgs &a, hipStream_t s);
 void launch_update(const UpdateArgs &a, hipStream_t s);
 void launch_sample(const DevModel *md, const float *nu, const float *sigma, int sps, uint32_t k0, uint32_t k1,
@@ -78,6 +85,6 @@ void launch_broadphase(const DevModel *md, const float *lo, const float *hi, int
                        int *flags, hipStream_t s);
 void launch_narrowphase(const DevModel *md, const float *X, int n, float *phi, float *nrm, float *pt, float *lo,
                         float *hi, hipStream_t s);
-void launch_reset_stats(PlanStats *st, hipStream_t s);
+void launch_reset_stats(PlanStats *st, hipStream_t s, int n = 1);
 
 }  // namespace mppi

@@ -42,11 +42,28 @@ __device__ __forceinline__ const DevModel &model(const DevModel *p)
     return *p;
 }
 
+// Scene of this workgroup: the single scene of the launch, or an entry of a
+// packed table (uneven batches: block b covers block blk[2b+1] of scene blk[2b]).
+__device__ __forceinline__ void block_scene(const RolloutArgs &a0, const RolloutArgs *tab, const int *blk, int m,
+                                            RolloutArgs &a, int &bid)
+{
+    a = a0;
+    bid = blockIdx.x;
+    if (tab) {
+        a = tab[blk[2 * blockIdx.x]];
+        bid = blk[2 * blockIdx.x + 1];
+        a.m = m;
+    }
+}
+
 template <int NC>
-__global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a)
+__global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a0, const RolloutArgs *tab, const int *blk, int m)
 {
     extern __shared__ float lds[];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    RolloutArgs a;
+    int bid;
+    block_scene(a0, tab, blk, m, a, bid);
+    const int j = bid * blockDim.x + threadIdx.x;
     if (j >= a.K) return;
     const DevModel &md = *a.md;
     if (a.diverged && *a.diverged) {
@@ -118,9 +135,12 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a)
 // past K run on a clamped sample index so that every lane reaches every
 // barrier; they write nothing.
 template <int NC>
-__global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a)
+__global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const RolloutArgs *tab, const int *blk, int m)
 {
     extern __shared__ float lds[];
+    RolloutArgs a;
+    int bid;
+    block_scene(a0, tab, blk, m, a, bid);
     const int lane = threadIdx.x;
     const int team = lane >> 4;
     TeamCtx tc;
@@ -133,7 +153,7 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a)
     tc.tl = lds + team * team_lds_floats(NC);
     tc.LL = LaneList{tc.tl + TG_FIELDS, 0, 1};
     tc.pk = LanePark{tc.tl + TG_FIELDS + NC * CL_FIELDS, 0, 1};
-    const int j_raw = blockIdx.x * TEAMS_PER_WAVE + team;
+    const int j_raw = bid * TEAMS_PER_WAVE + team;
     const bool active = j_raw < a.K;
     const int j = active ? j_raw : a.K - 1;
     const DevModel &md0 = *a.md;
@@ -250,24 +270,40 @@ int pick_mapping(int K, int requested)
     return K >= 32768 ? MAP_LANE : MAP_TEAM;
 }
 
-void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping)
+int samples_per_block(int mapping) { return mapping == MAP_TEAM ? TEAMS_PER_WAVE : 64; }
+
+static void launch_rollout_impl(const RolloutArgs &a, const RolloutArgs *tab, const int *blk, int nblk, int ncmax,
+                                int m, int map, hipStream_t s)
 {
     const int nc = ncmax <= 4 ? 4 : 8;
-    if (pick_mapping(a.K, mapping) == MAP_TEAM) {
-        const dim3 grid((a.K + TEAMS_PER_WAVE - 1) / TEAMS_PER_WAVE), block(64);
+    const dim3 grid(nblk), block(64);
+    if (map == MAP_TEAM) {
         const size_t lds = (size_t)TEAMS_PER_WAVE * team_lds_floats(nc) * sizeof(float);
         if (nc == 4)
-            hipLaunchKernelGGL(rollout_team_kernel<4>, grid, block, lds, s, a);
+            hipLaunchKernelGGL(rollout_team_kernel<4>, grid, block, lds, s, a, tab, blk, m);
         else
-            hipLaunchKernelGGL(rollout_team_kernel<8>, grid, block, lds, s, a);
+            hipLaunchKernelGGL(rollout_team_kernel<8>, grid, block, lds, s, a, tab, blk, m);
         return;
     }
-    const dim3 grid((a.K + 63) / 64), block(64);
     const size_t lds = (size_t)(nc * CL_FIELDS + PK_FIELDS) * 64 * sizeof(float);
     if (nc == 4)
-        hipLaunchKernelGGL(rollout_kernel<4>, grid, block, lds, s, a);
+        hipLaunchKernelGGL(rollout_kernel<4>, grid, block, lds, s, a, tab, blk, m);
     else
-        hipLaunchKernelGGL(rollout_kernel<8>, grid, block, lds, s, a);
+        hipLaunchKernelGGL(rollout_kernel<8>, grid, block, lds, s, a, tab, blk, m);
+}
+
+void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping)
+{
+    const int map = pick_mapping(a.K, mapping);
+    const int per = samples_per_block(map);
+    launch_rollout_impl(a, nullptr, nullptr, (a.K + per - 1) / per, ncmax, a.m, map, s);
+}
+
+void launch_rollout_batch(const RolloutArgs *d_tab, const int *d_blk, int nblk, int ncmax, int m, int map,
+                          hipStream_t s)
+{
+    RolloutArgs dummy = {};
+    launch_rollout_impl(dummy, d_tab, d_blk, nblk, ncmax, m, map, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,8 +332,13 @@ __device__ __forceinline__ T block_sum(T v, T *sh)
     return r;
 }
 
-__global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a)
+__global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a0, const StatsArgs *tab, int m)
 {
+    StatsArgs a = a0;
+    if (tab) {
+        a = tab[blockIdx.x];
+        a.iter = m;
+    }
     __shared__ double shd[SB];
     __shared__ unsigned long long shu[SB];
     __shared__ float shf[SB];
@@ -385,10 +426,20 @@ __global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a)
     }
 }
 
-void launch_stats(const StatsArgs &a, hipStream_t s) { hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(SB), 0, s, a); }
-
-__global__ void reset_stats_kernel(PlanStats *st)
+void launch_stats(const StatsArgs &a, hipStream_t s)
 {
+    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(SB), 0, s, a, (const StatsArgs *)nullptr, a.iter);
+}
+
+void launch_stats_batch(const StatsArgs *d_tab, int n, int m, hipStream_t s)
+{
+    StatsArgs dummy = {};
+    hipLaunchKernelGGL(stats_kernel, dim3(n), dim3(SB), 0, s, dummy, d_tab, m);
+}
+
+__global__ void reset_stats_kernel(PlanStats *st0)
+{
+    PlanStats *st = st0 + blockIdx.x;
     const int t = threadIdx.x;
     if (t < 64) st->cmin_iter[t] = 0.0;
     if (t < 4) st->counters[t] = 0ull;
@@ -398,17 +449,27 @@ __global__ void reset_stats_kernel(PlanStats *st)
     }
 }
 
-void launch_reset_stats(PlanStats *st, hipStream_t s) { hipLaunchKernelGGL(reset_stats_kernel, dim3(1), dim3(64), 0, s, st); }
+void launch_reset_stats(PlanStats *st, hipStream_t s, int n)
+{
+    hipLaunchKernelGGL(reset_stats_kernel, dim3(n), dim3(64), 0, s, st);
+}
 
 // ---------------------------------------------------------------------------
 // weighted mean update: one workgroup per control step
 
 constexpr int UB = 256;
 
-__global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a)
+__global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateArgs *tab, const int *blk, int m)
 {
     __shared__ double red[NU][UB];
-    const int k = blockIdx.x, t = threadIdx.x;
+    UpdateArgs a = a0;
+    int k = blockIdx.x;
+    if (tab) {
+        a = tab[blk[2 * blockIdx.x]];
+        k = blk[2 * blockIdx.x + 1];
+        a.m = m;
+    }
+    const int t = threadIdx.x;
     const bool div = a.st->diverged != 0;
     double acc[NU];
 #pragma unroll
@@ -444,7 +505,17 @@ __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a)
     }
 }
 
-void launch_update(const UpdateArgs &a, hipStream_t s) { hipLaunchKernelGGL(update_kernel, dim3(a.H), dim3(UB), 0, s, a); }
+void launch_update(const UpdateArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(update_kernel, dim3(a.H), dim3(UB), 0, s, a, (const UpdateArgs *)nullptr, (const int *)nullptr,
+                       a.m);
+}
+
+void launch_update_batch(const UpdateArgs *d_tab, const int *d_blk, int nblk, int m, hipStream_t s)
+{
+    UpdateArgs dummy = {};
+    hipLaunchKernelGGL(update_kernel, dim3(nblk), dim3(UB), 0, s, dummy, d_tab, d_blk, m);
+}
 
 // ---------------------------------------------------------------------------
 // single-stage kernels

@@ -367,3 +367,83 @@ def test_lane_and_team_mappings_agree(mp, ctx):
     rel = np.abs(out["lane"] - out["team"]) / np.abs(out["lane"])
     assert np.median(rel) < 1e-4 and rel.max() < 1e-2
     scene.close()
+
+
+# ---------------------------------------------------------------- packed uneven batches
+def _batch_items(mp, ctx, n=5):
+    """Uneven requests: different scenes (box counts), K (ragged vs the block
+    size), H, M, per-step sigma on one of them, one with n_elite."""
+    shapes = [(70, 6, 3), (5, 4, 1), (130, 9, 4), (33, 3, 2), (64, 5, 3)][:n]
+    items = []
+    for i, (K, H, M) in enumerate(shapes):
+        sc = W.make_scene(4, i)
+        pp = W.plan_params(4, K=K, H=H, M=M, seed=1000 + i)
+        sig = pp["sigma"] if i != 2 else np.tile(pp["sigma"], (H, 1)) * np.linspace(0.5, 1.5, H)[:, None]
+        items.append(dict(scene=mp.Scene(ctx, sc), x0=T(W.initial_state(sc)), K=K, H=H, lam=pp["lam"],
+                          sigma=T(sig), sigma_per_step=(i == 2), M=M, seed=pp["seed"],
+                          nominal_U=T(np.random.default_rng(i).uniform(-0.2, 0.2, (H, 14))),
+                          eta=0.8 if i == 3 else 1.0, n_elite=20 if i == 4 else 0,
+                          U_new=torch.zeros((H, 14), device=DEV), costs=torch.zeros(K, device=DEV)))
+    return items
+
+
+@pytest.mark.parametrize("mapping", ["lane", "team"])
+def test_batch_equals_each_plan_alone(mp, ctx, mapping):
+    items = _batch_items(mp, ctx)
+    sts = mp.mppi_plan_batch(ctx, items, mapping=mapping)
+    torch.cuda.synchronize()
+    for it, st in zip(items, sts):
+        U = torch.zeros_like(it["U_new"])
+        c = torch.zeros_like(it["costs"])
+        st1 = mp.mppi_plan(ctx, it["scene"], it["x0"], it["nominal_U"], it["K"], it["H"], it["lam"], it["sigma"], U,
+                           c, M=it["M"], seed=it["seed"], eta=it["eta"], n_elite=it["n_elite"],
+                           sigma_per_step=it["sigma_per_step"], mapping=mapping)
+        torch.cuda.synchronize()
+        assert st["status"] == 0 and st1["rc"] == 0
+        assert torch.equal(c, it["costs"]), f"costs differ for K={it['K']} H={it['H']}"
+        assert torch.equal(U, it["U_new"])
+        assert st["best"] == st1["best"] and st["ess"] == st1["ess"] and st["c_min"] == st1["c_min"]
+        assert st["cmin_iter"] == st1["cmin_iter"] and st["iterations"] == it["M"]
+        assert st["contacts"] == st1["contacts"]
+    for it in items:
+        it["scene"].close()
+
+
+def test_batch_host_pointers_and_divergence(mp, ctx):
+    items = _batch_items(mp, ctx, n=3)
+    dev_items = [dict(it) for it in items]
+    for it in dev_items:
+        it["U_new"] = torch.zeros_like(it["U_new"])
+        it["costs"] = torch.zeros_like(it["costs"])
+    mp.mppi_plan_batch(ctx, dev_items, mapping="team")
+    host = []
+    for it in items:
+        h = dict(it)
+        for k in ("x0", "nominal_U", "sigma"):
+            h[k] = it[k].cpu().numpy()
+        h["U_new"] = np.zeros((it["H"], 14), np.float32)
+        h["costs"] = np.zeros(it["K"], np.float32)
+        host.append(h)
+    mp.mppi_plan_batch(ctx, host, mapping="team")
+    torch.cuda.synchronize()
+    for d, h in zip(dev_items, host):
+        assert np.array_equal(d["U_new"].cpu().numpy(), h["U_new"])
+        assert np.array_equal(d["costs"].cpu().numpy(), h["costs"])
+    # one request diverges (NaN start): it gets its nominal back, the others are untouched
+    bad = [dict(it) for it in dev_items]
+    x0 = bad[1]["x0"].clone()
+    x0[3] = float("nan")
+    bad[1]["x0"] = x0
+    for it in bad:
+        it["U_new"] = torch.zeros_like(it["U_new"])
+        it["costs"] = torch.zeros_like(it["costs"])
+    sts = mp.mppi_plan_batch(ctx, bad, mapping="team")
+    torch.cuda.synchronize()
+    assert [s["status"] for s in sts] == [0, mp.E_DIVERGED, 0]
+    assert torch.equal(bad[1]["U_new"], bad[1]["nominal_U"])
+    assert torch.equal(bad[0]["U_new"], dev_items[0]["U_new"]) and torch.equal(bad[2]["U_new"], dev_items[2]["U_new"])
+    with pytest.raises(mp.MppiError) as e:
+        mp.mppi_plan_batch(ctx, [dict(items[0], K=0)])
+    assert e.value.code == mp.E_INVAL
+    for it in items:
+        it["scene"].close()
