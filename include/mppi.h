@@ -226,6 +226,106 @@ int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, cons
                 float *nu_out, double *nu_out64, double *weights, mppi_stats *stats, unsigned flags,
                 void *stream);
 
+/* ---------------------------------------------------------------- serving
+ * A server replans for many robot cells at once by continuous batching:
+ * a worker thread runs MPPI iterations over every active request in one
+ * packed launch sequence (one rollout, one statistics and one update
+ * launch per iteration, as mppi_plan_batch), admits queued requests at
+ * every iteration boundary as active slots and device memory free up, and
+ * retires requests as their last iteration completes.  Each request is the
+ * plan of Alg. 1 with its own (scene, x0, nominal, K, H, lambda, sigma,
+ * opts); with a pinned mapping (MPPI_MAP_LANE / MPPI_MAP_TEAM in the
+ * server flags) its results equal mppi_plan of the same arguments and
+ * mapping, bit for bit, whatever else is in flight.
+ *
+ * Cells keep a scene, the plant state and the warm-start nominal controls
+ * resident on the device (the receding-horizon warm start of Sec. III-A):
+ * a request for a cell may take x0 and nominal_U from it, and on
+ * completion writes U_new back as the cell's nominal, shifted by `advance`
+ * control steps (the tail repeats the last row), after advancing the cell's
+ * state by the first `advance` steps of U_new in the same world model.
+ * Requests of one cell run one after another, in submission order.
+ *
+ * Thread safety: mppi_submit, mppi_poll, mppi_cancel and mppi_cell_* may be
+ * called from any thread; the server serialises them.  The context must not
+ * be used by other calls while a server on it is alive (the server owns the
+ * context's device for its worker). */
+typedef struct mppi_server mppi_server;
+
+#define MPPI_PENDING 1          /* mppi_poll: not finished yet */
+#define MPPI_E_CANCELLED (-7)   /* request status after mppi_cancel or supersession */
+
+#define MPPI_SUPERSEDE 128u     /* submit: cancel this cell's requests still queued (not yet admitted) */
+
+typedef struct mppi_server_opts {
+    uint64_t mem_budget;  /* device bytes for in-flight requests (0: 1 GiB) */
+    int max_active;       /* requests iterating together (0: 256; at most 4096) */
+    int max_pending;      /* queued requests; mppi_submit returns MPPI_E_BUSY beyond (0: 4096) */
+    unsigned flags;       /* MPPI_MAP_LANE or MPPI_MAP_TEAM: mapping of every launch (else per
+                             iteration by total sample count) */
+} mppi_server_opts;
+
+typedef struct mppi_ticket_info {
+    int status;           /* MPPI_OK, MPPI_E_DIVERGED or MPPI_E_CANCELLED */
+    int iterations;       /* iterations run */
+    double t_submit_ms;   /* host steady clock, ms since the server was created */
+    double t_admit_ms;    /* admitted into the active set (negative if never) */
+    double t_done_ms;     /* completion observed by the worker */
+} mppi_ticket_info;
+
+typedef struct mppi_server_info {
+    uint64_t submitted, completed, cancelled, superseded, rejected;
+    uint64_t iterations;        /* packed iterations launched */
+    uint64_t request_iters;     /* sum over iterations of the active requests */
+    uint64_t env_steps;         /* sum of K * H over request iterations */
+    uint64_t mem_high_water;    /* device bytes */
+    int active, pending;
+} mppi_server_info;
+
+/* Create a server on `ctx` with its own non-blocking stream and worker
+ * thread; the device arena (opts->mem_budget bytes) and a pinned host
+ * arena of the same bound for staging are allocated here, once.
+ * Errors: MPPI_E_INVAL, MPPI_E_NOMEM, MPPI_E_DEVICE. */
+int mppi_server_create(mppi_ctx *ctx, const mppi_server_opts *opts, mppi_server **out);
+/* Cancel everything queued or running, join the worker, free the server. */
+void mppi_server_destroy(mppi_server *srv);
+
+/* A cell: scene (not owned; must outlive the server), horizon H, start
+ * state x0[MPPI_NX] (host), initial nominal[H][14] (host, NULL = zeros).
+ * Returns the cell id in *cell. */
+int mppi_cell_create(mppi_server *srv, const mppi_scene *scene, int H, const float *x0, const float *nominal_U,
+                     int *cell);
+/* Copy a cell's resident state and nominal to host arrays (each nullable),
+ * after waiting until none of its requests is queued or running. */
+int mppi_cell_read(mppi_server *srv, int cell, float *x, float *nominal_U);
+
+/* Queue one request; *ticket identifies it.
+ *   cell < 0: a stand-alone request; every field of *req is used as in
+ *     mppi_plan_batch (inputs copied at submission when host pointers;
+ *     device pointers, with MPPI_DEVICE_PTRS in req->opts.flags, must stay
+ *     valid and unchanged until the request is done).
+ *   cell >= 0: req->scene is NULL or the cell's scene, req->H is 0 or the
+ *     cell's H; req->x0 == NULL takes the cell's state and
+ *     req->nominal_U == NULL the cell's nominal; `advance` in [0, H].
+ *   Outputs (U_new, costs, stats; each nullable for cell requests) are
+ *   written when the request completes and must stay valid until
+ *   mppi_poll reports it done.  `flags`: MPPI_SUPERSEDE.
+ * Errors: MPPI_E_INVAL, MPPI_E_BUSY (queue full or the request can never
+ * fit in the memory budget). */
+int mppi_submit(mppi_server *srv, const mppi_request *req, int cell, int advance, unsigned flags,
+                uint64_t *ticket);
+/* Wait up to timeout_ms (0: do not wait, < 0: no limit) for a request.
+ * Returns MPPI_OK once it is done (info filled, ticket released),
+ * MPPI_PENDING while it is not, MPPI_E_INVAL for an unknown ticket. */
+int mppi_poll(mppi_server *srv, uint64_t ticket, int timeout_ms, mppi_ticket_info *info);
+/* Cancel a request: a queued one is dropped at once, a running one at the
+ * next iteration boundary (its outputs are not written).  Its status
+ * becomes MPPI_E_CANCELLED; it must still be polled.  MPPI_E_INVAL for an
+ * unknown or finished ticket. */
+int mppi_cancel(mppi_server *srv, uint64_t ticket);
+/* Counters of the server since creation. */
+int mppi_server_query(mppi_server *srv, mppi_server_info *info);
+
 /* Broadphase of the contact pass: for every candidate pair of the scene
  * (canonical order), flags[p] = 1 when the closed AABBs of its geoms
  * overlap after growing geom A's box by `margin`.  lo/hi: [n][16 + n_box][3]

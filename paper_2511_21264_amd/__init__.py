@@ -19,8 +19,9 @@ NU = 14
 NX = 55
 MAX_BOXES = 16
 
-OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5, -6
-DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ, MAP_LANE, MAP_TEAM = 1, 2, 4, 8, 16, 32, 64
+OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY, E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
+PENDING = 1
+DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ, MAP_LANE, MAP_TEAM, SUPERSEDE = 1, 2, 4, 8, 16, 32, 64, 128
 _MAPS = {None: 0, "auto": 0, "lane": MAP_LANE, "team": MAP_TEAM}
 
 
@@ -84,6 +85,22 @@ class Request(C.Structure):
     ]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("mem_budget", C.c_uint64), ("max_active", C.c_int), ("max_pending", C.c_int), ("flags", C.c_uint)]
+
+
+class TicketInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("t_submit_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("cancelled", C.c_uint64),
+                ("superseded", C.c_uint64), ("rejected", C.c_uint64), ("iterations", C.c_uint64),
+                ("request_iters", C.c_uint64), ("env_steps", C.c_uint64), ("mem_high_water", C.c_uint64),
+                ("active", C.c_int), ("pending", C.c_int)]
+
+
 _lib = None
 _P = C.c_void_p
 
@@ -107,6 +124,14 @@ def lib():
             "mppi_simulate": (C.c_int, [_P, _P, _P, C.c_int, _P, C.c_int, C.c_int, C.c_int, _P, _P, _P, C.c_uint,
                                         _P]),
             "mppi_plan_batch": (C.c_int, [_P, C.c_int, C.POINTER(Request), C.c_uint, _P]),
+            "mppi_server_create": (C.c_int, [_P, C.POINTER(ServerOpts), C.POINTER(_P)]),
+            "mppi_server_destroy": (None, [_P]),
+            "mppi_cell_create": (C.c_int, [_P, _P, C.c_int, _P, _P, C.POINTER(C.c_int)]),
+            "mppi_cell_read": (C.c_int, [_P, C.c_int, _P, _P]),
+            "mppi_submit": (C.c_int, [_P, C.POINTER(Request), C.c_int, C.c_int, C.c_uint, C.POINTER(C.c_uint64)]),
+            "mppi_poll": (C.c_int, [_P, C.c_uint64, C.c_int, C.POINTER(TicketInfo)]),
+            "mppi_cancel": (C.c_int, [_P, C.c_uint64]),
+            "mppi_server_query": (C.c_int, [_P, C.POINTER(ServerInfo)]),
             "mppi_sample": (C.c_int, [_P, _P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, _P, _P, _P, C.c_uint,
                                       _P]),
             "mppi_update": (C.c_int, [_P, _P, _P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_double,
@@ -368,3 +393,92 @@ def mppi_plan_batch(ctx, items, *, mapping=None, time_kernels=False, stream=None
         d["status"] = reqs[i].status
         out.append(d)
     return out
+
+
+def _request(it, dev_flag):
+    """mppi_request of one item dict (see mppi_plan_batch); returns (Request, keep-alive list)."""
+    (px0, pnom, psig, pU, pc), dev = _ptrs([(it.get("x0"), np.float32), (it.get("nominal_U"), np.float32),
+                                             (it["sigma"], np.float32), (it.get("U_new"), np.float32),
+                                             (it.get("costs"), np.float32)])
+    r = Request()
+    sc = it.get("scene")
+    r.scene = sc._h if sc is not None else None
+    r.x0, r.nominal_U, r.sigma, r.U_new, r.costs = px0, pnom, psig, pU, pc
+    r.K, r.H, r.lam = int(it["K"]), int(it.get("H", 0)), float(it["lam"])
+    fl = (SIGMA_PER_STEP if it.get("sigma_per_step") else 0) | (DEVICE_PTRS if dev else 0)
+    r.opts = Opts(int(it.get("M", 1)), int(it.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF, float(it.get("eta", 1.0)),
+                  int(it.get("n_elite", 0)), fl)
+    return r, dev
+
+
+class Server:
+    """Continuous-batching replanning server (mppi_server_* / mppi_submit / mppi_poll / mppi_cancel).
+    Output arrays and stats of a request are kept alive here until it is polled done."""
+
+    def __init__(self, ctx, mem_budget=0, max_active=0, max_pending=0, mapping=None):
+        self.ctx = ctx
+        self._h = _P()
+        o = ServerOpts(int(mem_budget), int(max_active), int(max_pending), _MAPS[mapping])
+        _check(lib().mppi_server_create(ctx._h, C.byref(o), C.byref(self._h)))
+        self._keep = {}
+
+    def close(self):
+        if self._h:
+            lib().mppi_server_destroy(self._h)
+            self._h = _P()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cell(self, scene, H, x0, nominal_U=None):
+        x0 = np.ascontiguousarray(x0, dtype=np.float32)
+        nom = None if nominal_U is None else np.ascontiguousarray(nominal_U, dtype=np.float32)
+        c = C.c_int(-1)
+        _check(lib().mppi_cell_create(self._h, scene._h, int(H), x0.ctypes.data,
+                                      None if nom is None else nom.ctypes.data, C.byref(c)))
+        return c.value
+
+    def cell_read(self, cell, H):
+        x = np.zeros(NX, np.float32)
+        nu = np.zeros((H, NU), np.float32)
+        _check(lib().mppi_cell_read(self._h, int(cell), x.ctypes.data, nu.ctypes.data))
+        return x, nu
+
+    def submit(self, item, cell=-1, advance=0, supersede=False, want_stats=True):
+        """item: dict as for mppi_plan_batch (x0 / nominal_U may be omitted for cell requests)."""
+        r, _ = _request(item, None)
+        st = Stats() if want_stats else None
+        r.stats = C.pointer(st) if st is not None else None
+        t = C.c_uint64(0)
+        _check(lib().mppi_submit(self._h, C.byref(r), int(cell), int(advance), SUPERSEDE if supersede else 0,
+                                 C.byref(t)))
+        self._keep[t.value] = (item, st, r)
+        return t.value
+
+    def poll(self, ticket, timeout_ms=0):
+        """None while pending; else a dict with status, iterations, times and stats."""
+        info = TicketInfo()
+        rc = lib().mppi_poll(self._h, C.c_uint64(ticket), int(timeout_ms), C.byref(info))
+        if rc == PENDING:
+            return None
+        _check(rc)
+        item, st, _ = self._keep.pop(ticket, (None, None, None))
+        d = {k: getattr(info, k) for k, _ in info._fields_}
+        if st is not None:
+            d["stats"] = st.as_dict()
+        return d
+
+    def wait(self, ticket):
+        return self.poll(ticket, timeout_ms=-1)
+
+    def cancel(self, ticket):
+        _check(lib().mppi_cancel(self._h, C.c_uint64(ticket)))
+
+    def query(self):
+        i = ServerInfo()
+        _check(lib().mppi_server_query(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in i._fields_}

@@ -5,15 +5,15 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libmppi.so")
-SOURCES = ["csrc/kernels.hip", "csrc/api.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/serve.hip"]
 HEADERS = ["csrc/devmodel.h", "csrc/philox.h", "csrc/dynamics.h", "csrc/collision.h", "csrc/step.h",
-           "csrc/cost.h", "csrc/kernels.h", "../include/mppi.h"]
+           "csrc/cost.h", "csrc/team.h", "csrc/kernels.h", "csrc/internal.h", "csrc/sched.h", "../include/mppi.h"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # no packed FP32 instructions (v_pk_*_f32) in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-command-line-argument",
+    "-Wno-unused-command-line-argument", "-pthread",
 ]
 
 

@@ -12,11 +12,12 @@
 #include <vector>
 
 #include "../../include/mppi.h"
-#include "kernels.h"
+#include "internal.h"
 
 using namespace mppi;
+using namespace mppi_host;
 
-namespace {
+namespace mppi_host {
 
 thread_local std::string g_err;
 
@@ -31,40 +32,7 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIPCHK(expr)                                                                                     \
-    do {                                                                                                 \
-        hipError_t e_ = (expr);                                                                          \
-        if (e_ != hipSuccess) return fail(MPPI_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-struct Buf {
-    void *p = nullptr;
-    size_t cap = 0;
-};
-
-enum Slot {
-    S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_DIST, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3,
-    S_BTAB, S_BST, S_BIN, S_BNU, S_BCOST, S_BW, S_BCNT, S_BDIST, S_N
-};
-
-}  // namespace
-
-struct mppi_ctx {
-    int device = 0;
-    Buf buf[S_N];
-    PlanStats *st = nullptr;
-    std::vector<hipEvent_t> ev;
-    // pinned host staging of packed-batch tables
-    void *host_tab = nullptr;
-    size_t host_tab_cap = 0;
-};
-
-struct mppi_scene {
-    mppi_ctx *ctx = nullptr;
-    mppi_scene_desc desc;
-    DevModel host;
-    DevModel *dev = nullptr;
-};
+}  // namespace mppi_host
 
 namespace {
 
@@ -120,13 +88,6 @@ int copy_out(void *dst, const void *src, size_t bytes, bool dev, hipStream_t s)
     if (!dst || dev || !src) return MPPI_OK;
     HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
     return MPPI_OK;
-}
-
-bool all_finite(const float *p, size_t n)
-{
-    for (size_t i = 0; i < n; ++i)
-        if (!std::isfinite(p[i])) return false;
-    return true;
 }
 
 // solid capsule: cylinder length L plus two hemispherical caps of radius r
@@ -254,6 +215,10 @@ int build_model(const mppi_scene_desc *d, DevModel &m)
     return MPPI_OK;
 }
 
+}  // namespace
+
+namespace mppi_host {
+
 int mapping_of(unsigned flags)
 {
     if (flags & MPPI_MAP_LANE) return MAP_LANE;
@@ -267,11 +232,18 @@ int set_device(mppi_ctx *c)
     return MPPI_OK;
 }
 
-}  // namespace
+bool all_finite(const float *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace mppi_host
 
 extern "C" {
 
-const char *mppi_last_error(void) { return g_err.c_str(); }
+const char *mppi_last_error(void) { return mppi_host::g_err.c_str(); }
 
 int mppi_ctx_create(int device, mppi_ctx **out)
 {

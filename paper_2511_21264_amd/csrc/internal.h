@@ -1,0 +1,57 @@
+// Host-side definitions shared by the translation units of the C ABI
+// (api.hip: contexts, scenes, plans; serve.hip: the serving loop).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "../../include/mppi.h"
+#include "kernels.h"
+
+namespace mppi_host {
+
+// records the message of the last failure of the calling thread; returns code
+int fail(int code, const char *fmt, ...);
+
+#define HIPCHK(expr)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(MPPI_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Buf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+enum Slot {
+    S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_DIST, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3,
+    S_BTAB, S_BST, S_BIN, S_BNU, S_BCOST, S_BW, S_BCNT, S_BDIST, S_N
+};
+
+int mapping_of(unsigned flags);
+bool all_finite(const float *p, size_t n);
+
+}  // namespace mppi_host
+
+struct mppi_ctx {
+    int device = 0;
+    mppi_host::Buf buf[mppi_host::S_N];
+    mppi::PlanStats *st = nullptr;
+    std::vector<hipEvent_t> ev;
+    // pinned host staging of packed-batch tables
+    void *host_tab = nullptr;
+    size_t host_tab_cap = 0;
+};
+
+struct mppi_scene {
+    mppi_ctx *ctx = nullptr;
+    mppi_scene_desc desc;
+    mppi::DevModel host;
+    mppi::DevModel *dev = nullptr;
+};
+
+namespace mppi_host {
+int set_device(mppi_ctx *c);
+}

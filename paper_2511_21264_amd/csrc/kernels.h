@@ -66,13 +66,26 @@ struct UpdateArgs {
     double *nu_out64;
 };
 
+// End of a served request: nu := nominal when the plan diverged, copied to
+// the caller's device output and, shifted by `shift` control steps (the tail
+// repeats the last row), to the cell's resident nominal.
+struct FinishArgs {
+    const PlanStats *st;
+    const float *nom;
+    float *nu;
+    float *out;
+    float *cell_nu;
+    int H, shift;
+};
+
 // sample-to-lane mapping of the rollout
 constexpr int MAP_AUTO = 0, MAP_LANE = 1, MAP_TEAM = 2;
 int pick_mapping(int K, int requested);
 void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping = MAP_AUTO);
 int samples_per_block(int mapping);
 // packed launches: tables live in device memory; block b of a rollout launch
-// covers block blk[2b+1] of scene blk[2b]; update blocks are (scene, step) pairs
+// covers block blk[2b+1] of scene blk[2b]; update blocks are (scene, step)
+// pairs; m >= 0 is the iteration of every entry, m < 0 keeps each entry's own
 void launch_rollout_batch(const RolloutArgs *d_tab, const int *d_blk, int nblk, int ncmax, int m, int mapping,
                           hipStream_t s);
 void launch_stats_batch(const StatsArgs *d_tab, int n, int m, hipStream_t s);
@@ -86,5 +99,6 @@ void launch_broadphase(const DevModel *md, const float *lo, const float *hi, int
 void launch_narrowphase(const DevModel *md, const float *X, int n, float *phi, float *nrm, float *pt, float *lo,
                         float *hi, hipStream_t s);
 void launch_reset_stats(PlanStats *st, hipStream_t s, int n = 1);
+void launch_finish_batch(const FinishArgs *d_tab, int n, hipStream_t s);
 
 }  // namespace mppi

@@ -52,7 +52,7 @@ __device__ __forceinline__ void block_scene(const RolloutArgs &a0, const Rollout
     if (tab) {
         a = tab[blk[2 * blockIdx.x]];
         bid = blk[2 * blockIdx.x + 1];
-        a.m = m;
+        if (m >= 0) a.m = m;
     }
 }
 
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a0, const StatsArgs
     StatsArgs a = a0;
     if (tab) {
         a = tab[blockIdx.x];
-        a.iter = m;
+        if (m >= 0) a.iter = m;
     }
     __shared__ double shd[SB];
     __shared__ unsigned long long shu[SB];
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateA
     if (tab) {
         a = tab[blk[2 * blockIdx.x]];
         k = blk[2 * blockIdx.x + 1];
-        a.m = m;
+        if (m >= 0) a.m = m;
     }
     const int t = threadIdx.x;
     const bool div = a.st->diverged != 0;
@@ -515,6 +515,31 @@ void launch_update_batch(const UpdateArgs *d_tab, const int *d_blk, int nblk, in
 {
     UpdateArgs dummy = {};
     hipLaunchKernelGGL(update_kernel, dim3(nblk), dim3(UB), 0, s, dummy, d_tab, d_blk, m);
+}
+
+// one workgroup per finishing request
+__global__ void __launch_bounds__(256) finish_kernel(const FinishArgs *tab)
+{
+    const FinishArgs a = tab[blockIdx.x];
+    const bool div = a.st->diverged != 0;
+    const int n = a.H * NU;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float v = div ? a.nom[i] : a.nu[i];
+        a.nu[i] = v;
+        if (a.out) a.out[i] = v;
+    }
+    __syncthreads();
+    if (!a.cell_nu) return;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int k = i / NU, d = i - k * NU;
+        const int src = min(k + a.shift, a.H - 1);
+        a.cell_nu[i] = a.nu[src * NU + d];
+    }
+}
+
+void launch_finish_batch(const FinishArgs *d_tab, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(256), 0, s, d_tab);
 }
 
 // ---------------------------------------------------------------------------

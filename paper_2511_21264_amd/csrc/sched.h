@@ -1,0 +1,292 @@
+// Host-only core of the serving loop: a first-fit arena over a fixed byte
+// range, and the admission / iteration bookkeeping of continuous batching.
+// Nothing here touches the device; serve.hip maps arena offsets onto its
+// device and pinned regions and launches the work.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <unordered_map>
+#include <vector>
+
+namespace mppi {
+
+constexpr size_t NO_SPACE = ~(size_t)0;
+
+// First-fit allocator over [0, capacity): free ranges kept by offset and
+// merged with their neighbours on release.
+class Arena {
+public:
+    explicit Arena(size_t bytes = 0, size_t align = 256) : align_(align) { reset(bytes); }
+
+    void reset(size_t bytes)
+    {
+        capacity_ = bytes;
+        used_ = high_ = 0;
+        free_.clear();
+        live_.clear();
+        if (bytes) free_[0] = bytes;
+    }
+
+    size_t round(size_t bytes) const { return bytes == 0 ? align_ : (bytes + align_ - 1) / align_ * align_; }
+
+    size_t alloc(size_t bytes)
+    {
+        const size_t n = round(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const size_t off = it->first, rest = it->second - n;
+            free_.erase(it);
+            if (rest) free_[off + n] = rest;
+            live_[off] = n;
+            used_ += n;
+            if (used_ > high_) high_ = used_;
+            return off;
+        }
+        return NO_SPACE;
+    }
+
+    // false for an offset that is not a live block
+    bool release(size_t off)
+    {
+        auto it = live_.find(off);
+        if (it == live_.end()) return false;
+        size_t start = off, n = it->second;
+        live_.erase(it);
+        used_ -= n;
+        auto nx = free_.lower_bound(start);
+        if (nx != free_.end() && start + n == nx->first) {
+            n += nx->second;
+            free_.erase(nx);
+        }
+        auto pv = free_.lower_bound(start);
+        if (pv != free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == start) {
+                start = pv->first;
+                n += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[start] = n;
+        return true;
+    }
+
+    size_t capacity() const { return capacity_; }
+    size_t used() const { return used_; }
+    size_t high_water() const { return high_; }
+    size_t largest_free() const
+    {
+        size_t b = 0;
+        for (auto &f : free_) b = f.second > b ? f.second : b;
+        return b;
+    }
+    size_t n_free_ranges() const { return free_.size(); }
+
+private:
+    size_t align_, capacity_ = 0, used_ = 0, high_ = 0;
+    std::map<size_t, size_t> free_, live_;
+};
+
+enum ReqState { RS_PENDING = 0, RS_ACTIVE = 1, RS_FINISHING = 2, RS_DONE = 3 };
+
+struct SchedReq {
+    uint64_t id = 0;
+    int cell = -1;
+    int M = 1;
+    int m = 0;                 // next iteration to run
+    size_t dev_bytes = 0, host_bytes = 0;
+    size_t dev_off = NO_SPACE, host_off = NO_SPACE;
+    bool cancel = false;
+    int state = RS_PENDING;
+};
+
+// Admission and iteration order of the requests of a server.
+//   * Queue: FIFO.  A request waits while an earlier request of its cell is
+//     queued or active (a cell's requests run in submission order); the
+//     scan stops at the first request that does not fit in memory (no
+//     overtaking on memory, so a large request cannot starve).
+//   * Active set: at most max_active requests; each iteration runs one
+//     MPPI iteration of every active request, each at its own index m.
+//   * A request leaves the active set when its last iteration has been
+//     launched (state FINISHING; its cell may admit its next request, whose
+//     work is ordered after it on the stream); its memory is returned by
+//     release() once that work has completed.
+class Scheduler {
+public:
+    Scheduler(size_t dev_bytes = 0, size_t host_bytes = 0, int max_active = 1, int max_pending = 1)
+        : dev_(dev_bytes), host_(host_bytes), max_active_(max_active), max_pending_(max_pending)
+    {
+    }
+
+    // 0 = queued, 1 = queue full, 2 = can never fit the arenas
+    int enqueue(const SchedReq &r0, bool supersede, std::vector<uint64_t> *superseded)
+    {
+        if (dev_.round(r0.dev_bytes) > dev_.capacity() || host_.round(r0.host_bytes) > host_.capacity()) return 2;
+        if (supersede && r0.cell >= 0) {
+            for (auto it = pending_.begin(); it != pending_.end();) {
+                SchedReq &q = reqs_.at(*it);
+                if (q.cell == r0.cell) {
+                    if (superseded) superseded->push_back(q.id);
+                    q.state = RS_DONE;
+                    q.cancel = true;
+                    it = pending_.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        if ((int)pending_.size() >= max_pending_) return 1;
+        SchedReq r = r0;
+        r.state = RS_PENDING;
+        r.m = 0;
+        r.cancel = false;
+        reqs_[r.id] = r;
+        pending_.push_back(r.id);
+        return 0;
+    }
+
+    // admitted ids, in admission order
+    std::vector<uint64_t> admit()
+    {
+        std::vector<uint64_t> out;
+        std::unordered_map<int, bool> blocked;
+        for (uint64_t a : active_) {
+            const SchedReq &r = reqs_.at(a);
+            if (r.cell >= 0) blocked[r.cell] = true;
+        }
+        for (auto it = pending_.begin(); it != pending_.end();) {
+            if ((int)active_.size() >= max_active_) break;
+            SchedReq &r = reqs_.at(*it);
+            if (r.cell >= 0 && blocked.count(r.cell)) {
+                ++it;
+                continue;
+            }
+            const size_t d = dev_.alloc(r.dev_bytes);
+            if (d == NO_SPACE) break;
+            const size_t h = host_.alloc(r.host_bytes);
+            if (h == NO_SPACE) {
+                dev_.release(d);
+                break;
+            }
+            r.dev_off = d;
+            r.host_off = h;
+            r.state = RS_ACTIVE;
+            if (r.cell >= 0) blocked[r.cell] = true;
+            active_.push_back(r.id);
+            out.push_back(r.id);
+            it = pending_.erase(it);
+        }
+        return out;
+    }
+
+    // 0 = unknown or already finishing/done, 1 = dropped from the queue,
+    // 2 = active: flagged, dropped at the next iteration boundary
+    int cancel(uint64_t id)
+    {
+        auto f = reqs_.find(id);
+        if (f == reqs_.end()) return 0;
+        SchedReq &r = f->second;
+        if (r.state == RS_PENDING) {
+            for (auto it = pending_.begin(); it != pending_.end(); ++it)
+                if (*it == id) {
+                    pending_.erase(it);
+                    break;
+                }
+            r.state = RS_DONE;
+            r.cancel = true;
+            return 1;
+        }
+        if (r.state == RS_ACTIVE) {
+            r.cancel = true;
+            return 2;
+        }
+        return 0;
+    }
+
+    // Active requests of the next iteration, after removing the cancelled
+    // ones (their ids go to *dropped; their memory stays held until
+    // release(), since earlier launches may still use it).
+    std::vector<const SchedReq *> next_iteration(std::vector<uint64_t> *dropped)
+    {
+        std::vector<const SchedReq *> out;
+        for (auto it = active_.begin(); it != active_.end();) {
+            SchedReq &r = reqs_.at(*it);
+            if (r.cancel) {
+                r.state = RS_FINISHING;
+                if (dropped) dropped->push_back(r.id);
+                it = active_.erase(it);
+                continue;
+            }
+            out.push_back(&r);
+            ++it;
+        }
+        return out;
+    }
+
+    // After an iteration was launched over the active set: every active
+    // request moves to its next index; those that ran their last iteration
+    // leave the active set (returned).
+    std::vector<uint64_t> advance()
+    {
+        std::vector<uint64_t> fin;
+        for (auto it = active_.begin(); it != active_.end();) {
+            SchedReq &r = reqs_.at(*it);
+            ++r.m;
+            if (r.m >= r.M) {
+                r.state = RS_FINISHING;
+                fin.push_back(r.id);
+                it = active_.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        return fin;
+    }
+
+    // return the memory of a finishing request and forget it
+    bool release(uint64_t id)
+    {
+        auto f = reqs_.find(id);
+        if (f == reqs_.end()) return false;
+        SchedReq &r = f->second;
+        if (r.state == RS_PENDING || r.state == RS_ACTIVE) return false;
+        if (r.dev_off != NO_SPACE) dev_.release(r.dev_off);
+        if (r.host_off != NO_SPACE) host_.release(r.host_off);
+        reqs_.erase(f);
+        return true;
+    }
+
+    // forget a request that was dropped from the queue (no memory held)
+    void forget(uint64_t id)
+    {
+        auto f = reqs_.find(id);
+        if (f != reqs_.end() && f->second.state == RS_DONE) reqs_.erase(f);
+    }
+
+    const SchedReq *find(uint64_t id) const
+    {
+        auto f = reqs_.find(id);
+        return f == reqs_.end() ? nullptr : &f->second;
+    }
+    bool cell_idle(int cell) const
+    {
+        for (auto &kv : reqs_)
+            if (kv.second.cell == cell && kv.second.state != RS_DONE) return false;
+        return true;
+    }
+    int n_active() const { return (int)active_.size(); }
+    int n_pending() const { return (int)pending_.size(); }
+    const Arena &dev() const { return dev_; }
+    const Arena &host() const { return host_; }
+
+private:
+    Arena dev_, host_;
+    int max_active_, max_pending_;
+    std::deque<uint64_t> pending_;
+    std::vector<uint64_t> active_;
+    std::unordered_map<uint64_t, SchedReq> reqs_;
+};
+
+}  // namespace mppi

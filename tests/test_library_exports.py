@@ -59,6 +59,35 @@ int main(void) {
     assert [int(v) for v in out] == want
 
 
+def test_request_and_server_struct_layouts_match_header():
+    import subprocess
+    import tempfile
+    import paper_2511_21264_amd as mp
+    code = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "mppi.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mppi_request),
+         offsetof(mppi_request, lambda), offsetof(mppi_request, opts), offsetof(mppi_request, U_new),
+         offsetof(mppi_request, status), sizeof(mppi_server_opts), offsetof(mppi_server_opts, flags),
+         sizeof(mppi_ticket_info), offsetof(mppi_ticket_info, t_done_ms), sizeof(mppi_server_info),
+         offsetof(mppi_server_info, mem_high_water), offsetof(mppi_server_info, pending), sizeof(mppi_opts));
+  return 0;
+}'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(code)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    R, O, T, I = mp.Request, mp.ServerOpts, mp.TicketInfo, mp.ServerInfo
+    want = [C.sizeof(R), R.lam.offset, R.opts.offset, R.U_new.offset, R.status.offset, C.sizeof(O), O.flags.offset,
+            C.sizeof(T), T.t_done_ms.offset, C.sizeof(I), I.mem_high_water.offset, I.pending.offset,
+            C.sizeof(mp.Opts)]
+    assert [int(v) for v in out] == want
+
+
 def test_scene_desc_roundtrip():
     import paper_2511_21264_amd as mp
     sc = W.make_scene(3)
