@@ -97,6 +97,103 @@ def bench_packed(mp, ctx, steps, warmup, mapping, n_scenes=32):
     return out
 
 
+def run_trace(mp, ctx, cells, scenes, trace, duration, max_active, mapping, deadline_ms=20.0, advance=2):
+    """Replay an arrival trace against a server: every arrival submits a
+    warm-started cell request (state and nominal resident on the device,
+    plant advanced by `advance` steps per reply, queued requests of the same
+    cell superseded).  Returns latency and throughput figures."""
+    import numpy as np
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    srv = mp.Server(ctx, mapping=mapping, max_active=max_active, max_pending=4096, mem_budget=8 << 30)
+    ids = [srv.cell(scenes[i], c["H"], W.initial_state(c["scene"]).astype(np.float32)) for i, c in enumerate(cells)]
+    sig = [torch.full((14,), 0.3, dtype=torch.float32, device=dev) for _ in cells]
+    torch.cuda.synchronize()
+    out, n_sub = {}, [0] * len(cells)
+    lat, status = [], {"ok": 0, "superseded": 0, "diverged": 0}
+
+    def collect(block=False):
+        for t in list(out):
+            r = srv.poll(t, -1 if block else 0)
+            if r is None:
+                continue
+            out.pop(t)
+            if r["status"] == mp.E_CANCELLED:
+                status["superseded"] += 1
+                continue
+            status["ok" if r["status"] == 0 else "diverged"] += 1
+            lat.append(r["t_done_ms"] - r["t_submit_ms"])
+
+    t0 = time.perf_counter()
+    for (ta, i) in trace:
+        while time.perf_counter() - t0 < ta:
+            collect()
+            time.sleep(0.0002)
+        c = cells[i]
+        item = dict(K=c["K"], lam=0.1, sigma=sig[i], M=c["M"], seed=(i << 20) + n_sub[i])
+        n_sub[i] += 1
+        out[srv.submit(item, cell=ids[i], advance=advance, supersede=True, want_stats=False)] = i
+    wall = time.perf_counter() - t0
+    q = srv.query()
+    # the trace is over: what is still queued or running counts as missed
+    unfinished = 0
+    for t in list(out):
+        try:
+            srv.cancel(t)
+        except mp.MppiError:
+            pass
+    for t in list(out):
+        r = srv.poll(t, -1)
+        out.pop(t)
+        if r["status"] == mp.E_CANCELLED:
+            unfinished += 1
+        else:
+            status["ok" if r["status"] == 0 else "diverged"] += 1
+            lat.append(r["t_done_ms"] - r["t_submit_ms"])
+    srv.close()
+    lat = np.array(lat) if lat else np.array([np.nan])
+    n_req = len(trace)
+    return {"requests": n_req, "completed": status["ok"] + status["diverged"], "superseded": status["superseded"],
+            "unfinished_at_end": unfinished,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "deadline_ms": deadline_ms,
+            "miss_rate": float((np.sum(lat > deadline_ms) + status["superseded"] + unfinished) / max(1, n_req)),
+            "env_steps_per_s": q["env_steps"] / wall, "wall_s": wall, "trace_s": duration,
+            "packed_iterations": q["iterations"], "mean_active": q["request_iters"] / max(1, q["iterations"]),
+            "max_active": max_active}
+
+
+def bench_serving(mp, ctx, duration, mapping, thr_env_steps):
+    """Serving workload: 64 cells (scene seeds 5000 + cell), Poisson arrivals
+    at U[10, 50] Hz per cell, M=10, 20 ms deadline; served by the continuous
+    batching server and by the plain form (one request per launch, FIFO)."""
+    import workloads as W
+    res = {}
+    for shape in ("mixed", "fixed"):
+        cells = W.serving_cells(64, shape)
+        scenes = [mp.Scene(ctx, c["scene"]) for c in cells]
+        offered = sum(c["rate"] * c["M"] * c["K"] * c["H"] for c in cells)
+        legs = {}
+        # as specified, and at a rate scale one GPU sustains (half the measured packed throughput)
+        scale = min(1.0, 0.5 * thr_env_steps / offered)
+        for name, sc in (("spec_rates", 1.0), ("sustainable", scale)):
+            trace = W.poisson_trace([c["rate"] * sc for c in cells], duration, seed=5 + (shape == "fixed"))
+            for form, act in (("batched", 64), ("plain", 1)):
+                r = run_trace(mp, ctx, cells, scenes, trace, duration, act, mapping)
+                r["rate_scale"] = sc
+                r["offered_env_steps_per_s"] = offered * sc
+                legs[f"{name}_{form}"] = r
+                print(json.dumps({"serving": shape, "leg": f"{name}_{form}", **r}), file=sys.stderr, flush=True)
+        for s_ in scenes:
+            s_.close()
+        res[shape] = legs
+    res["workload"] = ("64 cells, scene seeds 5000+cell, Poisson arrivals U[10,50] Hz per cell, M=10, warm start "
+                       "resident, plant advanced 2 steps per reply, stale queued requests superseded; mixed: "
+                       "K~U{256..4096}, H~U{32..128}; fixed: K=1024, H=64")
+    return res
+
+
 def calib_copy(mb):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -118,8 +215,9 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0)
-    ap.add_argument("--mapping", default="auto", choices=["auto", "lane", "team"])
+    ap.add_argument("--mapping", default="auto", choices=["auto", "lane", "team", "wave"])
     ap.add_argument("--packed-steps", type=int, default=2, help="steps of the packed-batch leg (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="trace length of the serving legs (0: skip)")
     args = ap.parse_args()
     if args.calib_copy_mb:
         calib_copy(args.calib_copy_mb)
@@ -210,6 +308,10 @@ def main():
     }
     if args.packed_steps > 0:
         out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, args.mapping)
+    if args.serve_seconds > 0:
+        thr = out.get("packed", {}).get("batched", {}).get("env_steps_per_s", out["value"])
+        out["serving"] = bench_serving(mp, ctx, args.serve_seconds, "team" if args.mapping == "auto" else args.mapping,
+                                       thr)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(sc, pp, threads)

@@ -63,7 +63,9 @@ extern "C" {
 #define MPPI_TIME_KERNELS 8u    /* time every rollout launch with HIP events (fills stats->rollout_ms) */
 #define MPPI_TRAJ 16u           /* mppi_simulate: write every post-step state, not only the last */
 #define MPPI_MAP_LANE 32u       /* rollout mapping: one lane per sample (throughput at large K) */
-#define MPPI_MAP_TEAM 64u       /* rollout mapping: 16 lanes per sample (latency at small K) */
+#define MPPI_MAP_TEAM 64u       /* rollout mapping: 16 lanes per sample, 4 samples per wave */
+#define MPPI_MAP_WAVE 256u      /* rollout mapping: one wave per sample (shortest steps at small K);
+                                   results equal MPPI_MAP_TEAM's bit for bit */
                                 /* neither: chosen from K (the library's tuning table) */
 
 /* Global geom ids (pair tables and AABB arrays use them): 0 ball,
@@ -188,7 +190,7 @@ typedef struct mppi_request {
  * that each MPPI iteration is one rollout launch over every request's
  * samples, one statistics launch and one update launch (requests with fewer
  * iterations drop out of later launches).  `flags`: MPPI_DEVICE_PTRS (every
- * array of every request is a device pointer), MPPI_MAP_LANE/MPPI_MAP_TEAM
+ * array of every request is a device pointer), MPPI_MAP_LANE/_TEAM/_WAVE
  * (one mapping for the whole batch; chosen from the total sample count
  * otherwise), MPPI_TIME_KERNELS (each request's stats->rollout_ms receives the
  * batch's summed rollout time).  Results of a request equal its results
@@ -234,7 +236,7 @@ int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, cons
  * every iteration boundary as active slots and device memory free up, and
  * retires requests as their last iteration completes.  Each request is the
  * plan of Alg. 1 with its own (scene, x0, nominal, K, H, lambda, sigma,
- * opts); with a pinned mapping (MPPI_MAP_LANE / MPPI_MAP_TEAM in the
+ * opts); with a pinned mapping (MPPI_MAP_LANE, _TEAM or _WAVE in the
  * server flags) its results equal mppi_plan of the same arguments and
  * mapping, bit for bit, whatever else is in flight.
  *
@@ -261,7 +263,7 @@ typedef struct mppi_server_opts {
     uint64_t mem_budget;  /* device bytes for in-flight requests (0: 1 GiB) */
     int max_active;       /* requests iterating together (0: 256; at most 4096) */
     int max_pending;      /* queued requests; mppi_submit returns MPPI_E_BUSY beyond (0: 4096) */
-    unsigned flags;       /* MPPI_MAP_LANE or MPPI_MAP_TEAM: mapping of every launch (else per
+    unsigned flags;       /* MPPI_MAP_LANE, _TEAM or _WAVE: mapping of every launch (else per
                              iteration by total sample count) */
 } mppi_server_opts;
 

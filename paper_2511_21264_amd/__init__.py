@@ -22,7 +22,8 @@ MAX_BOXES = 16
 OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY, E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
 PENDING = 1
 DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ, MAP_LANE, MAP_TEAM, SUPERSEDE = 1, 2, 4, 8, 16, 32, 64, 128
-_MAPS = {None: 0, "auto": 0, "lane": MAP_LANE, "team": MAP_TEAM}
+MAP_WAVE = 256
+_MAPS = {None: 0, "auto": 0, "lane": MAP_LANE, "team": MAP_TEAM, "wave": MAP_WAVE}
 
 
 class MppiError(RuntimeError):

@@ -223,6 +223,7 @@ int mapping_of(unsigned flags)
 {
     if (flags & MPPI_MAP_LANE) return MAP_LANE;
     if (flags & MPPI_MAP_TEAM) return MAP_TEAM;
+    if (flags & MPPI_MAP_WAVE) return MAP_WAVE;
     return MAP_AUTO;
 }
 

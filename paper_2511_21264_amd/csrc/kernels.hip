@@ -131,10 +131,12 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a0, const Rollo
     }
 }
 
-// Team mapping: 16 lanes per sample, 4 samples per 64-lane workgroup.  Teams
-// past K run on a clamped sample index so that every lane reaches every
-// barrier; they write nothing.
-template <int NC>
+// Team mappings: 16 lanes per sample.  TPW = 4: four samples per 64-lane
+// workgroup; TPW = 1: one sample per wave, its four 16-lane rows computing
+// the same values and splitting the contact sweep 64 wide.  Teams past K
+// run on a clamped sample index so that every lane reaches every barrier;
+// they write nothing.
+template <int NC, int TPW>
 __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const RolloutArgs *tab, const int *blk, int m)
 {
     extern __shared__ float lds[];
@@ -143,6 +145,8 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
     block_scene(a0, tab, blk, m, a, bid);
     const int lane = threadIdx.x;
     const int team = lane >> 4;
+    const int slot = TPW == 1 ? 0 : team;  // sample slot of this row in the workgroup
+    const bool primary = TPW != 1 || team == 0;  // the row that writes results
     TeamCtx tc;
     tc.lane = lane;
     tc.t = lane & 15;
@@ -150,16 +154,19 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
     tc.jt = tc.t & 7;
     tc.seg = tc.arm * 8;
     tc.joint = tc.jt < 7;
-    tc.tl = lds + team * team_lds_floats(NC);
+    tc.li = TPW == 1 ? lane : tc.t;
+    tc.gshift = TPW == 1 ? 0 : (lane & ~15);
+    tc.count = primary;
+    tc.tl = lds + slot * team_lds_floats(NC);
     tc.LL = LaneList{tc.tl + TG_FIELDS, 0, 1};
     tc.pk = LanePark{tc.tl + TG_FIELDS + NC * CL_FIELDS, 0, 1};
-    const int j_raw = bid * TEAMS_PER_WAVE + team;
+    const int j_raw = bid * TPW + slot;
     const bool active = j_raw < a.K;
     const int j = active ? j_raw : a.K - 1;
     const DevModel &md0 = *a.md;
     const bool skip = a.diverged && *a.diverged;
     if (skip) {
-        if (active && tc.t == 0) a.costs[j] = INFINITY;
+        if (active && primary && tc.t == 0) a.costs[j] = INFINITY;
         return;  // uniform over the launch: every lane leaves
     }
     const int jj = tc.joint ? tc.jt : 6;
@@ -203,10 +210,10 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
                 u = clampf(fmaf(sg, z, a.nu[k * NU + d]), -md.u_max, md.u_max);
             }
         }
-        for (int s = 0; s < nsub; ++s) team_substep<NC>(model(a.md), jc, tc, S, u, cnt);
+        for (int s = 0; s < nsub; ++s) team_substep<NC, TPW == 1 ? 64 : TEAM>(model(a.md), jc, tc, S, u, cnt);
         team_stage_cost(model(a.md), jc, tc, S, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
         uprev = u;
-        if (a.xout && a.traj && active) {
+        if (a.xout && a.traj && active && primary) {
             float *o = a.xout + ((long)j * a.H + k) * NX;
             if (tc.joint) {
                 o[XQ + d] = S.q; o[XQD + d] = S.qd; o[XQDES + d] = S.qdes;
@@ -233,8 +240,11 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
                : 1.f;
     bad = team_sum(bad);
     const bool finite = isfinite(c) && !(bad > 0.f) && bad == bad;
-    const float np = team_sum((float)cnt.np_tests), nbx = team_sum((float)cnt.box_tests);
-    if (!active) return;
+    // narrowphase tests: the contact sweep spreads over the whole wave when
+    // TPW = 1 (the cost pass counts on the primary row only)
+    const float np = TPW == 1 ? wave_sum((float)cnt.np_tests) : team_sum((float)cnt.np_tests);
+    const float nbx = TPW == 1 ? wave_sum((float)cnt.box_tests) : team_sum((float)cnt.box_tests);
+    if (!active || !primary) return;
     if (tc.t == 0) {
         a.costs[j] = finite ? c : INFINITY;
         if (a.terms) {
@@ -264,25 +274,38 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
 
 int pick_mapping(int K, int requested)
 {
-    if (requested == MAP_LANE || requested == MAP_TEAM) return requested;
-    // one lane per sample fills the chip only with tens of thousands of
-    // samples; below that a team per sample cuts the per-step latency
+    if (requested == MAP_LANE || requested == MAP_TEAM || requested == MAP_WAVE) return requested;
+    // the chip holds 1024 SIMDs: up to ~2 samples per SIMD a wave per sample
+    // gives the shortest steps; up to tens of thousands a 16-lane team per
+    // sample; beyond that one lane per sample has the highest throughput
+    if (K <= 2048) return MAP_WAVE;
     return K >= 32768 ? MAP_LANE : MAP_TEAM;
 }
 
-int samples_per_block(int mapping) { return mapping == MAP_TEAM ? TEAMS_PER_WAVE : 64; }
+int samples_per_block(int mapping)
+{
+    return mapping == MAP_TEAM ? TEAMS_PER_WAVE : mapping == MAP_WAVE ? 1 : 64;
+}
 
 static void launch_rollout_impl(const RolloutArgs &a, const RolloutArgs *tab, const int *blk, int nblk, int ncmax,
                                 int m, int map, hipStream_t s)
 {
     const int nc = ncmax <= 4 ? 4 : 8;
     const dim3 grid(nblk), block(64);
-    if (map == MAP_TEAM) {
-        const size_t lds = (size_t)TEAMS_PER_WAVE * team_lds_floats(nc) * sizeof(float);
-        if (nc == 4)
-            hipLaunchKernelGGL(rollout_team_kernel<4>, grid, block, lds, s, a, tab, blk, m);
-        else
-            hipLaunchKernelGGL(rollout_team_kernel<8>, grid, block, lds, s, a, tab, blk, m);
+    if (map == MAP_TEAM || map == MAP_WAVE) {
+        const int tpw = map == MAP_TEAM ? TEAMS_PER_WAVE : 1;
+        const size_t lds = (size_t)tpw * team_lds_floats(nc) * sizeof(float);
+        if (map == MAP_TEAM) {
+            if (nc == 4)
+                hipLaunchKernelGGL((rollout_team_kernel<4, TEAMS_PER_WAVE>), grid, block, lds, s, a, tab, blk, m);
+            else
+                hipLaunchKernelGGL((rollout_team_kernel<8, TEAMS_PER_WAVE>), grid, block, lds, s, a, tab, blk, m);
+        } else {
+            if (nc == 4)
+                hipLaunchKernelGGL((rollout_team_kernel<4, 1>), grid, block, lds, s, a, tab, blk, m);
+            else
+                hipLaunchKernelGGL((rollout_team_kernel<8, 1>), grid, block, lds, s, a, tab, blk, m);
+        }
         return;
     }
     const size_t lds = (size_t)(nc * CL_FIELDS + PK_FIELDS) * 64 * sizeof(float);

@@ -12,14 +12,30 @@
 //                       angular acceleration and joint-origin acceleration and
 //                       suffix sums for the propagated force and moment;
 //   Cholesky / solves   replicated on the 8 lanes of an arm segment;
-//   pair sweep          candidate pairs dealt 16-wide in canonical order,
-//                       contacts compacted by ballot so the list keeps the
-//                       canonical order (first n_cmax kept);
-//   contact solve       replicated on all 16 lanes (identical data, identical
-//                       arithmetic to the lane mapping);
+//   pair sweep          geom AABBs published once per substep; candidate
+//                       pairs AABB-tested G-wide (G = 16, or 64 when one
+//                       wave carries one sample) and the overlapping ones
+//                       compacted by ballot into an LDS list in canonical
+//                       order; narrowphase runs over that list only, and
+//                       contacts are compacted the same way (first n_cmax
+//                       kept);
+//   contact solve       the soft LCP in row space (pyramid-edge rows, as the
+//                       problem is stated): joint lane d forms its own
+//                       Jacobian columns J_s[d] and, when an arm is in
+//                       contact, row d of Mt^-1 from the parked factor;
+//                       Delassus blocks J_s Mt^-1 J_t^T are team sums; the
+//                       row matrix A = E^T G E, b, R and 1/(A_rr + R_r) sit
+//                       in the team's LDS, the Gauss-Seidel sweeps run
+//                       replicated from there, and the impulses return
+//                       through the same columns;
 //   collision cost      cost pairs dealt 16-wide, each lane owns the history
 //                       bits of its pairs.
 // Composite quantities use coordinates relative to the arm base.
+//
+// Wave-per-sample variant: the four 16-lane rows of a wave carry the same
+// sample and compute identical values (one shared LDS block, identical
+// writes); they only split the pair sweep, four times wider.  Every
+// per-sample result equals the 4-teams-per-wave form bit for bit.
 #pragma once
 #include "cost.h"
 #include "philox.h"
@@ -32,8 +48,17 @@ constexpr int TEAMS_PER_WAVE = 4;
 // per-team LDS block (floats): geometry, contact list, park area
 constexpr int TG_PTS = 0;             // 2 arms x 8 points x 3: joint origins o_0..o_6 and tip
 constexpr int TG_BALL = 48;           // ball centre
-constexpr int TG_FIELDS = 52;
-constexpr int team_lds_floats(int nc) { return TG_FIELDS + nc * CL_FIELDS + PK_FIELDS; }
+constexpr int TG_AABB = 52;           // dynamic geoms 0..15: lo[3], hi[3] (entry 1, the table, unused)
+constexpr int TG_CAND = TG_AABB + 96; // candidate pair indices of the sweep
+constexpr int TG_FIELDS = TG_CAND + ((MPPI_MAX_PAIRS + 3) / 4) * 4;
+// contact-solve area (after the park area; every offset a multiple of 4
+// floats so rows of A load as float4): per contact 20 floats (edges
+// e_q, offset r from the ball centre, bias, free velocity b_s), Delassus
+// blocks G_st (NC x NC x 9), row matrix A (4NC x 4NC), b, 1/(A_rr + R_r), R,
+// and the multipliers when several contacts are active
+constexpr int tcs_fields(int nc) { return 20 * nc + 9 * nc * nc + 16 * nc * nc + 16 * nc; }
+constexpr int PK_FIELDS4 = (PK_FIELDS + 3) / 4 * 4;  // park area rounded to 16 bytes
+constexpr int team_lds_floats(int nc) { return TG_FIELDS + nc * CL_FIELDS + PK_FIELDS4 + tcs_fields(nc); }
 
 template <int S>
 __device__ __forceinline__ float dpp_shr(float v)
@@ -83,6 +108,14 @@ __device__ __forceinline__ float team_sum(float x)
     x += __shfl_xor(x, 2, TEAM);
     x += __shfl_xor(x, 4, TEAM);
     x += __shfl_xor(x, 8, TEAM);
+    return x;
+}
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+    x = team_sum(x);
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
     return x;
 }
 
@@ -311,34 +344,86 @@ __device__ __forceinline__ void team_kin_from_lds(const float *tl, ArmKin kin[2]
         }
 }
 
-// candidate pairs dealt over the team's 16 lanes in canonical order;
-// contacts land in the team's LDS list in canonical order; returns the count
-__device__ inline int team_collect(const DevModel &md, const float *tl, const LaneList &LL, int t, int lane_in_wave,
+// AABBs of the dynamic geoms (ball, arm links, pads) from the published
+// geometry; lane t of each row writes geom t (rows write identical values)
+__device__ __forceinline__ void team_publish_aabb(float *tl, const DevModel &md, int t)
+{
+    if (t != G_TABLE) {
+        const AABB b = shape_aabb(team_geom(tl, md, t));
+        float *o = tl + TG_AABB + 6 * t;
+        o[0] = b.lo.x; o[1] = b.lo.y; o[2] = b.lo.z;
+        o[3] = b.hi.x; o[4] = b.hi.y; o[5] = b.hi.z;
+    }
+}
+
+// AABB test of candidate pair p (geom A is always dynamic) after growing A
+// by margin; the same comparisons as aabb_overlap on the geoms' boxes
+__device__ __forceinline__ bool pair_overlap(const float *tl, const DevModel &md, int ga, int gb, float margin)
+{
+    const float *A = tl + TG_AABB + 6 * ga;
+    if (gb == G_TABLE) return A[2] - margin <= 0.f;
+    AABB a, b;
+    a.lo = v3(A[0], A[1], A[2]);
+    a.hi = v3(A[3], A[4], A[5]);
+    if (gb >= G_BOX) {
+        const Shape bx = box_shape(md, gb - G_BOX);
+        b.lo = bx.p0 - bx.p1;
+        b.hi = bx.p0 + bx.p1;
+    } else {
+        const float *B = tl + TG_AABB + 6 * gb;
+        b.lo = v3(B[0], B[1], B[2]);
+        b.hi = v3(B[3], B[4], B[5]);
+    }
+    return aabb_overlap(a, b, margin);
+}
+
+// bits of the sweeping group (G lanes starting at wave lane gshift)
+template <int G>
+__device__ __forceinline__ uint64_t group_bits(uint64_t wm, int gshift)
+{
+    return G == 64 ? wm : (wm >> gshift) & ((1ull << G) - 1ull);
+}
+
+// Contact pass of one substep: AABB pre-pass over every candidate pair,
+// compaction of the overlapping ones, narrowphase over those; contacts land
+// in the team's LDS list in canonical order; returns the count.  li: lane
+// index within the sweeping group of G lanes.
+template <int G>
+__device__ inline int team_collect(const DevModel &md, float *tl, const LaneList &LL, int li, int gshift,
                                    StepCounters &cnt)
 {
-    int n = 0;
     const int np = md.n_pairs;
-    const int team_shift = lane_in_wave & ~(TEAM - 1);
-    for (int base = 0; base < np; base += TEAM) {
-        const int p = base + t;
+    int *cand = (int *)(tl + TG_CAND);
+    int ncand = 0;
+    for (int base = 0; base < np; base += G) {
+        const int p = base + li;
+        const bool ov = p < np && pair_overlap(tl, md, md.pa[p], md.pb[p], 0.f);
+        const uint64_t gm = group_bits<G>(__ballot(ov), gshift);
+        if (ov) cand[ncand + __popcll(gm & ((1ull << li) - 1ull))] = p;
+        ncand += __popcll(gm);
+    }
+    __syncthreads();
+    int n = 0;
+    for (int c0 = 0;; c0 += G) {
+        const bool live = c0 < ncand && n < md.n_cmax;
+        if (__ballot(live) == 0ull) break;
+        const int i = c0 + li;
         bool hit = false;
         Contact3 c;
         int ga = 0, gb = 0;
-        if (p < np && n < md.n_cmax) {
+        if (live && i < ncand) {
+            const int p = cand[i];
             ga = md.pa[p];
             gb = md.pb[p];
             const Shape A = team_geom(tl, md, ga), B = team_geom(tl, md, gb);
-            if (aabb_overlap(shape_aabb(A), shape_aabb(B), 0.f)) {
-                ++cnt.np_tests;
-                if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
-                c = narrow(A, B);
-                hit = c.phi < 0.f;
-            }
+            ++cnt.np_tests;
+            if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
+            c = narrow(A, B);
+            hit = c.phi < 0.f;
         }
-        const unsigned long long wm = __ballot(hit);
-        const uint32_t tm = (uint32_t)(wm >> team_shift) & 0xffffu;
+        const uint64_t gm = group_bits<G>(__ballot(hit), gshift);
         if (hit) {
-            const int slot = n + __popc(tm & ((1u << t) - 1u));
+            const int slot = n + __popcll(gm & ((1ull << li) - 1ull));
             if (slot < md.n_cmax) {
                 LL.at(slot, 0) = __int_as_float(ga);
                 LL.at(slot, 1) = __int_as_float(gb);
@@ -347,9 +432,270 @@ __device__ inline int team_collect(const DevModel &md, const float *tl, const La
                 LL.at(slot, 6) = c.p.x; LL.at(slot, 7) = c.p.y; LL.at(slot, 8) = c.p.z;
             }
         }
-        n = min(n + __popc(tm), md.n_cmax);
+        n = min(n + (int)__popcll(gm), md.n_cmax);
     }
     return n;
+}
+
+struct TeamCtx {
+    int t, arm, jt, seg, lane;
+    int li, gshift;  // lane within the contact sweep's group, group offset in the wave
+    bool count;      // this row counts the collision-cost narrowphase tests
+    bool joint;
+    float *tl;
+    LaneList LL;
+    LanePark pk;
+};
+
+// LDS writes of this wave become visible to its other lanes; no barrier,
+// so it may sit under control flow that differs between the teams of a wave
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ V3 team_sum3(V3 x) { return v3(team_sum(x.x), team_sum(x.y), team_sum(x.z)); }
+
+// Contact solve of one team (nc >= 1 contacts in the team's list, nc uniform
+// over the team).  k: this lane's joint kinematics at the contact positions;
+// v: this lane's joint velocity (free on entry, post-contact on exit); vb, wb:
+// the ball's free velocity and angular velocity, updated in place.
+template <int NC>
+__device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc, const JointKin &k, V3 pb, int nc,
+                                          float &v, V3 &vb, V3 &wb)
+{
+    constexpr int MR = 4 * NC;
+    float *E = tc.tl + TG_FIELDS + NC * CL_FIELDS + PK_FIELDS4;  // 16-byte aligned
+    float *Gb = E + 20 * NC;
+    float *A = Gb + 9 * NC * NC;
+    float *Bv = A + MR * MR;
+    float *Dv = Bv + MR;
+    float *Rv = Dv + MR;
+    const LaneList &LL = tc.LL;
+    const int m = 4 * nc;
+    // contact frames: edges n +- mu t1, n +- mu t2, offset, bias (identical on every lane)
+    int side_word = 0;  // bit s: contact s touches an arm; bit 8 + s: the ball is geom A
+    for (int s = 0; s < nc; ++s) {
+        const int ga = __float_as_int(LL.at(s, 0)), gb = __float_as_int(LL.at(s, 1));
+        const Sides sd = contact_sides(ga | (gb << 8));
+        side_word |= (((sd.armA >= 0) | (sd.armB >= 0)) ? 1 : 0) << s;
+        side_word |= (sd.ball ? 1 : 0) << (8 + s);
+        const V3 n = v3(LL.at(s, 3), LL.at(s, 4), LL.at(s, 5));
+        const V3 p = v3(LL.at(s, 6), LL.at(s, 7), LL.at(s, 8));
+        V3 t1, t2;
+        tangents(n, t1, t2);
+        float *e = E + 20 * s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const V3 t = q < 2 ? t1 : t2;
+            const V3 eq = fma3((q & 1) ? -md.mu : md.mu, t, n);
+            e[3 * q] = eq.x; e[3 * q + 1] = eq.y; e[3 * q + 2] = eq.z;
+        }
+        const V3 r = p - pb;
+        e[12] = r.x; e[13] = r.y; e[14] = r.z;
+        const float phi = LL.at(s, 2);
+        e[15] = md.kappa_h * (phi < 0.f ? -phi : 0.f);
+    }
+    const bool any_arm = (side_word & 0xff) != 0;
+    // this lane's Jacobian columns and the free contact velocities b_s
+    V3 Jc[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        Jc[s] = v3(0.f, 0.f, 0.f);
+        if (s < nc) {
+            const int ga = __float_as_int(LL.at(s, 0)), gb = __float_as_int(LL.at(s, 1));
+            const Sides sd = contact_sides(ga | (gb << 8));
+            const V3 p = v3(LL.at(s, 6), LL.at(s, 7), LL.at(s, 8));
+            const float coef = tc.joint ? jac_coef(sd, tc.arm, tc.jt) : 0.f;
+            if (coef != 0.f) Jc[s] = coef * cross(k.a, p - k.o);
+            V3 b = (side_word >> s) & 1 ? team_sum3(v * Jc[s]) : v3(0.f, 0.f, 0.f);
+            if ((side_word >> (8 + s)) & 1) {
+                const V3 r = p - pb;
+                b = b + vb + cross(wb, r);
+            }
+            float *e = E + 20 * s;
+            e[16] = b.x; e[17] = b.y; e[18] = b.z;
+        }
+    }
+    // row d of Mt^-1 of this lane's arm (only when an arm is in contact)
+    float Minv[NJ];
+#pragma unroll
+    for (int e = 0; e < NJ; ++e) Minv[e] = 0.f;
+    if (any_arm) {
+        float Lf[28];
+#pragma unroll
+        for (int i = 0; i < 28; ++i) Lf[i] = tc.pk.at(PK_L + 28 * tc.arm + i);
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) Minv[e] = (tc.joint && e == tc.jt) ? 1.f : 0.f;
+        chol7_solve(Lf, Minv);
+        if (!tc.joint) {
+#pragma unroll
+            for (int e = 0; e < NJ; ++e) Minv[e] = 0.f;
+        }
+    }
+    wave_lds_sync();
+    // Delassus blocks G_st = J_s Mt^-1 J_t^T (+ the ball's), s <= t
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+        if (t < nc) {
+            const bool arm_t = (side_word >> t) & 1, ball_t = (side_word >> (8 + t)) & 1;
+            V3 W = v3(0.f, 0.f, 0.f);  // row d of Mt^-1 J_t^T
+            if (arm_t) {
+#pragma unroll
+                for (int e = 0; e < NJ; ++e) W = fma3(Minv[e], tbc3(Jc[t], tc.seg + e), W);
+            }
+            const V3 rt = v3(E[20 * t + 12], E[20 * t + 13], E[20 * t + 14]);
+#pragma unroll
+            for (int s = 0; s <= t; ++s) {
+                if (s < nc) {
+                    float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    if (arm_t && ((side_word >> s) & 1)) {
+                        const V3 J = Jc[s];
+                        G[0] = team_sum(J.x * W.x); G[1] = team_sum(J.x * W.y); G[2] = team_sum(J.x * W.z);
+                        G[3] = team_sum(J.y * W.x); G[4] = team_sum(J.y * W.y); G[5] = team_sum(J.y * W.z);
+                        G[6] = team_sum(J.z * W.x); G[7] = team_sum(J.z * W.y); G[8] = team_sum(J.z * W.z);
+                    }
+                    if (ball_t && ((side_word >> (8 + s)) & 1)) {
+                        const V3 rs = v3(E[20 * s + 12], E[20 * s + 13], E[20 * s + 14]);
+                        ball_block(md, rs, rt, G);
+                    }
+                    float *g = Gb + 9 * (s * NC + t);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) g[i] = G[i];
+                }
+            }
+        }
+    }
+    wave_lds_sync();
+    // row matrix A[4s+q][4t+r] = e_sq . G_st e_tr, split over the team's lanes
+    for (int idx = tc.t; idx < m * m; idx += TEAM) {
+        const int r = idx / m, c = idx - r * m;
+        const int s = r >> 2, q = r & 3, t = c >> 2, w = c & 3;
+        const float *es = E + 20 * s + 3 * q, *et = E + 20 * t + 3 * w;
+        const V3 eq = v3(es[0], es[1], es[2]), er = v3(et[0], et[1], et[2]);
+        V3 ge;
+        if (s <= t) {
+            float G[9];
+            const float *g = Gb + 9 * (s * NC + t);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) G[i] = g[i];
+            ge = mul9(G, er);
+        } else {
+            float G[9];
+            const float *g = Gb + 9 * (t * NC + s);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) G[i] = g[i];
+            ge = mul9t(G, er);
+        }
+        A[r * MR + c] = dot(eq, ge);
+    }
+    wave_lds_sync();
+    for (int r = tc.t; r < m; r += TEAM) {
+        const int s = r >> 2, q = r & 3;
+        const float *es = E + 20 * s;
+        const V3 eq = v3(es[3 * q], es[3 * q + 1], es[3 * q + 2]);
+        const float arr = A[r * MR + r];
+        const float rr = md.eps_r * arr;
+        Rv[r] = rr;
+        Dv[r] = 1.0f / (arr + rr);
+        Bv[r] = dot(eq, v3(es[16], es[17], es[18])) - es[15];
+    }
+    wave_lds_sync();
+    // projected Gauss-Seidel sweeps, rows in order, f = 0 at the start
+    float f[MR];
+#pragma unroll
+    for (int r = 0; r < MR; ++r) f[r] = 0.f;
+    if (nc == 1) {
+        float a[16], b[4], rr[4], dd[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            b[r] = Bv[r];
+            rr[r] = Rv[r];
+            dd[r] = Dv[r];
+            const float4 a4 = *reinterpret_cast<const float4 *>(A + r * MR);
+            a[4 * r] = a4.x; a[4 * r + 1] = a4.y; a[4 * r + 2] = a4.z; a[4 * r + 3] = a4.w;
+        }
+        for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float res = fmaf(rr[r], f[r], b[r]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) res = fmaf(a[4 * r + c], f[c], res);
+                f[r] = fmaxf(f[r] - res * dd[r], 0.f);
+            }
+        }
+    } else if constexpr (NC <= 4) {
+        // several contacts: multipliers in registers, rows of A read from LDS
+        // four at a time (independent of the sweep's dependency chain)
+        for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
+#pragma unroll
+            for (int r = 0; r < MR; ++r) {
+                if (r < m) {
+                    const float4 *ar = reinterpret_cast<const float4 *>(A + r * MR);
+                    float res = fmaf(Rv[r], f[r], Bv[r]);
+#pragma unroll
+                    for (int t = 0; t < NC; ++t) {
+                        if (t < nc) {
+                            const float4 a4 = ar[t];
+                            res = fmaf(a4.x, f[4 * t], res);
+                            res = fmaf(a4.y, f[4 * t + 1], res);
+                            res = fmaf(a4.z, f[4 * t + 2], res);
+                            res = fmaf(a4.w, f[4 * t + 3], res);
+                        }
+                    }
+                    f[r] = fmaxf(f[r] - res * Dv[r], 0.f);
+                }
+            }
+        }
+    } else {
+        // up to MPPI_MAX_CONTACTS contacts: the multipliers live in the team's
+        // LDS (every lane computes and writes the same values)
+        float *F = Rv + MR;
+        for (int r = 0; r < m; ++r) F[r] = 0.f;
+        for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
+            for (int r = 0; r < m; ++r) {
+                const float fr = F[r];
+                float res = fmaf(Rv[r], fr, Bv[r]);
+                const float4 *ar = reinterpret_cast<const float4 *>(A + r * MR);
+                const float4 *f4 = reinterpret_cast<const float4 *>(F);
+                for (int t = 0; t < nc; ++t) {
+                    const float4 a4 = ar[t], x4 = f4[t];
+                    res = fmaf(a4.x, x4.x, res);
+                    res = fmaf(a4.y, x4.y, res);
+                    res = fmaf(a4.z, x4.z, res);
+                    res = fmaf(a4.w, x4.w, res);
+                }
+                F[r] = fmaxf(fr - res * Dv[r], 0.f);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < MR; ++r)
+            if (r < m) f[r] = F[r];
+    }
+    // impulses back: ball (geom A) directly, joints through Mt^-1 J^T
+    float g = 0.f;  // generalized impulse of this lane's joint
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        if (s < nc) {
+            const float *es = E + 20 * s;
+            V3 P = v3(0.f, 0.f, 0.f);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) P = fma3(f[4 * s + q], v3(es[3 * q], es[3 * q + 1], es[3 * q + 2]), P);
+            if ((side_word >> (8 + s)) & 1) {
+                vb = fma3(md.inv_ball_m, P, vb);
+                wb = fma3(md.inv_ball_I, cross(v3(es[12], es[13], es[14]), P), wb);
+            }
+            g += dot(Jc[s], P);
+        }
+    }
+    if (any_arm) {
+        float dv = 0.f;
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) dv = fmaf(Minv[e], tbc(g, tc.seg + e), dv);
+        if (tc.joint) v += dv;
+    }
 }
 
 // normal z_d of joint d for (j, k, m): the same arithmetic as normals14
@@ -362,15 +708,8 @@ __device__ __forceinline__ float normal_joint(uint32_t key0, uint32_t key1, uint
     return (d & 1) ? z1 : z0;
 }
 
-struct TeamCtx {
-    int t, arm, jt, seg, lane;
-    bool joint;
-    float *tl;
-    LaneList LL;
-    LanePark pk;
-};
 
-template <int NC>
+template <int NC, int G>
 __device__ inline void team_substep(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
                                     float u, StepCounters &cnt)
 {
@@ -402,33 +741,22 @@ __device__ inline void team_substep(const DevModel &md, const JointConst &jc, co
         tc.pk.at(f) = k.a.x;
         tc.pk.at(f + 1) = k.a.y;
         tc.pk.at(f + 2) = k.a.z;
+        // the factor is replicated on the segment: its first lane parks it
+        if (jt == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float val = Lp[0];
-#pragma unroll
-            for (int e = 1; e < 28; ++e) val = (e == 4 * jt + i) ? Lp[e] : val;
-            tc.pk.at(PK_L + 28 * tc.arm + 4 * jt + i) = val;
+            for (int e = 0; e < 28; ++e) tc.pk.at(PK_L + 28 * tc.arm + e) = Lp[e];
         }
     }
     __syncthreads();
-    const int nc = team_collect(md, tc.tl, tc.LL, tc.t, tc.lane, cnt);
+    team_publish_aabb(tc.tl, md, tc.t);
+    __syncthreads();
+    const int nc = team_collect<G>(md, tc.tl, tc.LL, tc.li, tc.gshift, cnt);
     if (tc.t == 0) {
         cnt.contacts += nc;
         if (nc >= md.n_cmax) ++cnt.overflow;
     }
     __syncthreads();
-    if (nc > 0) {
-        ArmKin kin[2];
-        team_kin_from_lds(tc.tl, kin);
-        float vall[14];
-#pragma unroll
-        for (int i = 0; i < 14; ++i) vall[i] = tbc(v, (i / 7) * 8 + (i % 7));
-        contact_solve<NC>(md, kin, tc.pk, pb, tc.LL, nc, vall, vb, wb);
-        float mine = vall[0];
-#pragma unroll
-        for (int i = 1; i < 14; ++i) mine = (i == 7 * tc.arm + jt) ? vall[i] : mine;
-        v = tc.joint ? mine : v;
-    }
+    if (nc > 0) team_contact_solve<NC>(md, tc, k, pb, nc, v, vb, wb);
     S.q = fmaf(h, v, S.q);
     S.qd = v;
     S.pb = fma3(h, vb, pb);
@@ -468,6 +796,8 @@ __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc,
     team_fk(jc, S.q, tc.jt, k);
     team_publish_geom(tc.tl, k, S.pb, tc.arm, tc.jt);
     __syncthreads();
+    team_publish_aabb(tc.tl, md, tc.t);
+    __syncthreads();
     const float *tl = tc.tl;
     if (tc.t == 0) {
         const V3 p1 = v3(tl[TG_PTS + 21], tl[TG_PTS + 22], tl[TG_PTS + 23]);
@@ -490,10 +820,13 @@ __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc,
     uint32_t nw = 0u;
     for (int i = tc.t, r = 0; i < nd; i += TEAM, ++r) {
         const int p = first_pair + i;
-        const Shape A = team_geom(tl, md, md.pa[p]), B = team_geom(tl, md, md.pb[p]);
-        if (aabb_overlap(shape_aabb(A), shape_aabb(B), md.m_c)) {
-            ++cnt.np_tests;
-            if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
+        const int ga = md.pa[p], gb = md.pb[p];
+        if (pair_overlap(tl, md, ga, gb, md.m_c)) {
+            const Shape A = team_geom(tl, md, ga), B = team_geom(tl, md, gb);
+            if (tc.count) {
+                ++cnt.np_tests;
+                if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
+            }
             const float d = narrow(A, B).phi;
             dist_term(md, d, !first, hist, 1u << r, dist + (long)i * stride, nw, acc);
         }

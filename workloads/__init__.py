@@ -221,3 +221,35 @@ def random_states(scene, n, seed, spread=0.3, vel=0.5):
 def random_controls(n, H, seed, scale=1.0):
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-scale, scale, size=(n, H, NU))
+
+
+def serving_cells(n=64, shape="mixed"):
+    """Cells of the serving workload: cell i is scene make_scene(5, i) with a
+    per-cell request rate ~ U[10, 50] Hz.  shape "mixed": K ~ U{256..4096},
+    H ~ U{32..128} per cell (seeded); shape "fixed": K=1024, H=64."""
+    out = []
+    for i in range(n):
+        rng = np.random.Generator(np.random.PCG64(55_000 + i))
+        K = int(rng.integers(256, 4097))
+        H = int(rng.integers(32, 129))
+        rate = float(rng.uniform(10.0, 50.0))
+        if shape == "fixed":
+            K, H = 1024, 64
+        out.append(dict(scene=make_scene(5, i), K=K, H=H, rate=rate, M=10))
+    return out
+
+
+def poisson_trace(rates, duration, seed=0):
+    """Merged Poisson arrivals: list of (time_s, cell) sorted by time, cell i
+    arriving at rates[i] per second over [0, duration)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ev = []
+    for i, r in enumerate(rates):
+        if r <= 0:
+            continue
+        t = rng.exponential(1.0 / r)
+        while t < duration:
+            ev.append((t, i))
+            t += rng.exponential(1.0 / r)
+    ev.sort()
+    return ev
