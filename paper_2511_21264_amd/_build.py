@@ -13,6 +13,10 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # no packed FP32 instructions (v_pk_*_f32) in any generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP32 division and square root from the hardware reciprocal / square
+    # root (about 1 ulp) instead of the correctly rounded sequences: these
+    # sit on the per-step dependency chains (Cholesky pivots, distances)
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-Wno-unused-command-line-argument", "-pthread",
 ]
 

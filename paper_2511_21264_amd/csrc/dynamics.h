@@ -137,7 +137,8 @@ __device__ inline void crba_arm(const DevModel &md, int arm, const ArmKin &k, fl
 }
 
 // in-place Cholesky of a packed SPD 7x7 (lower); pivots stay > 0 because
-// the armature is on the diagonal
+// the armature is on the diagonal.  The diagonal slots receive 1 / L_jj, so
+// that the solves multiply instead of dividing.
 __device__ inline void chol7(float L[28])
 {
 #pragma unroll
@@ -145,9 +146,8 @@ __device__ inline void chol7(float L[28])
         float d = L[tri(j, j)];
 #pragma unroll
         for (int k2 = 0; k2 < j; ++k2) d -= L[tri(j, k2)] * L[tri(j, k2)];
-        const float dj = sqrtf(d);
-        const float inv = 1.0f / dj;
-        L[tri(j, j)] = dj;
+        const float inv = 1.0f / sqrtf(d);
+        L[tri(j, j)] = inv;
 #pragma unroll
         for (int i = j + 1; i < NJ; ++i) {
             float v = L[tri(i, j)];
@@ -158,7 +158,7 @@ __device__ inline void chol7(float L[28])
     }
 }
 
-// x = (L L^T)^-1 b, in place
+// x = (L L^T)^-1 b, in place (L from chol7: reciprocal diagonal)
 __device__ inline void chol7_solve(const float L[28], float x[NJ])
 {
 #pragma unroll
@@ -166,14 +166,14 @@ __device__ inline void chol7_solve(const float L[28], float x[NJ])
         float v = x[i];
 #pragma unroll
         for (int k2 = 0; k2 < i; ++k2) v -= L[tri(i, k2)] * x[k2];
-        x[i] = v / L[tri(i, i)];
+        x[i] = v * L[tri(i, i)];
     }
 #pragma unroll
     for (int i = NJ - 1; i >= 0; --i) {
         float v = x[i];
 #pragma unroll
         for (int k2 = i + 1; k2 < NJ; ++k2) v -= L[tri(k2, i)] * x[k2];
-        x[i] = v / L[tri(i, i)];
+        x[i] = v * L[tri(i, i)];
     }
 }
 

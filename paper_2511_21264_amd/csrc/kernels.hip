@@ -157,7 +157,8 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
     tc.li = TPW == 1 ? lane : tc.t;
     tc.gshift = TPW == 1 ? 0 : (lane & ~15);
     tc.count = primary;
-    tc.tl = lds + slot * team_lds_floats(NC);
+    tc.hd = lds;
+    tc.tl = lds + HD_FIELDS + slot * team_lds_floats(NC);
     tc.LL = LaneList{tc.tl + TG_FIELDS, 0, 1};
     tc.pk = LanePark{tc.tl + TG_FIELDS + NC * CL_FIELDS, 0, 1};
     const int j_raw = bid * TPW + slot;
@@ -169,6 +170,8 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
         if (active && primary && tc.t == 0) a.costs[j] = INFINITY;
         return;  // uniform over the launch: every lane leaves
     }
+    stage_header(lds, md0, lane, 64);
+    __syncthreads();
     const int jj = tc.joint ? tc.jt : 6;
     const int d = 7 * tc.arm + jj;  // joint index of this lane
     JointConst jc;
@@ -294,7 +297,7 @@ static void launch_rollout_impl(const RolloutArgs &a, const RolloutArgs *tab, co
     const dim3 grid(nblk), block(64);
     if (map == MAP_TEAM || map == MAP_WAVE) {
         const int tpw = map == MAP_TEAM ? TEAMS_PER_WAVE : 1;
-        const size_t lds = (size_t)tpw * team_lds_floats(nc) * sizeof(float);
+        const size_t lds = (size_t)(HD_FIELDS + tpw * team_lds_floats(nc)) * sizeof(float);
         if (map == MAP_TEAM) {
             if (nc == 4)
                 hipLaunchKernelGGL((rollout_team_kernel<4, TEAMS_PER_WAVE>), grid, block, lds, s, a, tab, blk, m);

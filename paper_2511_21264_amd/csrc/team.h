@@ -37,6 +37,7 @@
 // writes); they only split the pair sweep, four times wider.  Every
 // per-sample result equals the 4-teams-per-wave form bit for bit.
 #pragma once
+#include <utility>
 #include "cost.h"
 #include "philox.h"
 
@@ -51,6 +52,15 @@ constexpr int TG_BALL = 48;           // ball centre
 constexpr int TG_AABB = 52;           // dynamic geoms 0..15: lo[3], hi[3] (entry 1, the table, unused)
 constexpr int TG_CAND = TG_AABB + 96; // candidate pair indices of the sweep
 constexpr int TG_FIELDS = TG_CAND + ((MPPI_MAX_PAIRS + 3) / 4) * 4;
+
+// per-workgroup LDS header (one scene per workgroup), staged once per
+// launch: candidate pairs (ga | gb << 8), box AABBs, box centres and half
+// extents, link radii, pad and ball radius
+constexpr int HD_PAIR = 0;
+constexpr int HD_BOXAB = HD_PAIR + ((MPPI_MAX_PAIRS + 3) / 4) * 4;
+constexpr int HD_BOXCH = HD_BOXAB + 6 * MPPI_MAX_BOXES;
+constexpr int HD_RAD = HD_BOXCH + 6 * MPPI_MAX_BOXES;  // link_rad[0..6], pad_rad, ball_r
+constexpr int HD_FIELDS = HD_RAD + 12;
 // contact-solve area (after the park area; every offset a multiple of 4
 // floats so rows of A load as float4): per contact 20 floats (edges
 // e_q, offset r from the ball centre, bias, free velocity b_s), Delassus
@@ -71,9 +81,36 @@ __device__ __forceinline__ float dpp_shl(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + S, 0xF, 0xF, true));
 }
 
-// value of team lane src (0..15)
-__device__ __forceinline__ float tbc(float v, int src) { return __shfl(v, src, TEAM); }
-__device__ __forceinline__ V3 tbc3(V3 v, int src) { return v3(tbc(v.x, src), tbc(v.y, src), tbc(v.z, src)); }
+// value of lane N of this lane's 16-lane row (DPP row broadcast: no LDS trip)
+template <int N>
+__device__ __forceinline__ float row_bcast(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + N, 0xF, 0xF, false));
+}
+// value of lane I of this lane's arm segment (team lane 8 * arm1 + I)
+template <int I>
+__device__ __forceinline__ float segb(float v, bool arm1)
+{
+    const float a = row_bcast<I>(v), b = row_bcast<8 + I>(v);
+    return arm1 ? b : a;
+}
+template <int I>
+__device__ __forceinline__ V3 segb3(V3 v, bool arm1)
+{
+    return v3(segb<I>(v.x, arm1), segb<I>(v.y, arm1), segb<I>(v.z, arm1));
+}
+
+// compile-time loop: f(std::integral_constant<int, i>) for i = 0 .. N-1
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // inclusive prefix sum over the 8-lane arm segment
 __device__ __forceinline__ float seg_prefix(float x, int jt)
@@ -101,14 +138,15 @@ __device__ __forceinline__ float seg_suffix(float x, int jt)
 }
 __device__ __forceinline__ V3 seg_suffix3(V3 v, int jt) { return v3(seg_suffix(v.x, jt), seg_suffix(v.y, jt), seg_suffix(v.z, jt)); }
 
-// sum over the 16 lanes of a team, result in every lane
+// sum over the 16 lanes of a team (inclusive DPP scan of the row, then a
+// broadcast of its last lane): the same value, bit for bit, in every lane
 __device__ __forceinline__ float team_sum(float x)
 {
-    x += __shfl_xor(x, 1, TEAM);
-    x += __shfl_xor(x, 2, TEAM);
-    x += __shfl_xor(x, 4, TEAM);
-    x += __shfl_xor(x, 8, TEAM);
-    return x;
+    x += dpp_shr<1>(x);
+    x += dpp_shr<2>(x);
+    x += dpp_shr<4>(x);
+    x += dpp_shr<8>(x);
+    return row_bcast<15>(x);
 }
 
 __device__ __forceinline__ float wave_sum(float x)
@@ -196,7 +234,7 @@ __device__ inline void team_fk(const JointConst &jc, float q, int jt, JointKin &
     k.o = k.o1 - d;
 }
 
-// row jt of Mt = M + diag(diag_add) (full row, 7 entries) on joint lanes
+// row jt of Mt = M + diag(diag_add), entries c <= jt (the rest 0), on joint lanes
 __device__ inline void team_crba(const DevModel &md, const JointConst &jc, const JointKin &k, int jt, int seg,
                                  float row[NJ])
 {
@@ -225,13 +263,14 @@ __device__ inline void team_crba(const DevModel &md, const JointConst &jc, const
     const V3 L = Mc * cross(k.a, cc - ob);
     const V3 K = mul(Ic, k.a) + cross(cc, L);
     const V3 mo = cross(k.a, ob);
-    // row jt: column i >= jt from the composite of i, i < jt from symmetry
-#pragma unroll
-    for (int i = 0; i < NJ; ++i) {
-        const int src = seg + i;
-        const V3 Ki = tbc3(K, src), Li = tbc3(L, src), ai = tbc3(k.a, src), mi = tbc3(mo, src);
-        row[i] = i >= jt ? dot(k.a, Ki) - dot(mo, Li) : dot(ai, K) - dot(mi, L);
-    }
+    // row jt, entries c <= jt (the lower triangle the factorisation reads):
+    // M_{jt,c} = a_c . K_jt - mo_c . L_jt from the composite of link jt
+    const bool arm1 = seg != 0;
+    static_for<NJ>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const V3 ai = segb3<i>(k.a, arm1), mi = segb3<i>(mo, arm1);
+        row[i] = i <= jt ? dot(ai, K) - dot(mi, L) : 0.f;
+    });
 #pragma unroll
     for (int i = 0; i < NJ; ++i)
         if (i == jt) row[i] += md.diag_add;
@@ -240,10 +279,12 @@ __device__ inline void team_crba(const DevModel &md, const JointConst &jc, const
 // gather the packed lower triangle of the arm's Mt on every lane of its segment
 __device__ __forceinline__ void team_gather_tri(const float row[NJ], int seg, float Lp[28])
 {
+    const bool arm1 = seg != 0;
+    static_for<NJ>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
 #pragma unroll
-    for (int r = 0; r < NJ; ++r)
-#pragma unroll
-        for (int c = 0; c <= r; ++c) Lp[tri(r, c)] = tbc(row[c], seg + r);
+        for (int c = 0; c <= r; ++c) Lp[tri(r, c)] = segb<r>(row[c], arm1);
+    });
 }
 
 // bias torque of the lane's joint: c(q, qd) (+ gravity when gravity)
@@ -290,18 +331,22 @@ struct TeamState {
     float quat[4];
 };
 
-__device__ __forceinline__ Shape team_geom(const float *tl, const DevModel &md, int gid)
+__device__ __forceinline__ Shape team_geom(const float *tl, const float *hd, int gid)
 {
     Shape s;
     if (gid == G_BALL) {
         s.type = SH_SPHERE;
         s.p0 = v3(tl[TG_BALL], tl[TG_BALL + 1], tl[TG_BALL + 2]);
         s.p1 = s.p0;
-        s.r = md.ball_r;
+        s.r = hd[HD_RAD + 8];
     } else if (gid == G_TABLE) {
         s = table_shape();
     } else if (gid >= G_BOX) {
-        s = box_shape(md, gid - G_BOX);
+        const float *bx = hd + HD_BOXCH + 6 * (gid - G_BOX);
+        s.type = SH_BOX;
+        s.p0 = v3(bx[0], bx[1], bx[2]);
+        s.p1 = v3(bx[3], bx[4], bx[5]);
+        s.r = 0.f;
     } else {
         const int arm = (gid - G_ARM) / 7, g = (gid - G_ARM) % 7;
         const float *p = tl + TG_PTS + 24 * arm;
@@ -309,15 +354,30 @@ __device__ __forceinline__ Shape team_geom(const float *tl, const DevModel &md, 
             s.type = SH_CAPSULE;
             s.p0 = v3(p[3 * g], p[3 * g + 1], p[3 * g + 2]);
             s.p1 = v3(p[3 * g + 3], p[3 * g + 4], p[3 * g + 5]);
-            s.r = md.link_rad[g];
         } else {
             s.type = SH_SPHERE;
             s.p0 = v3(p[21], p[22], p[23]);
             s.p1 = s.p0;
-            s.r = md.pad_rad;
         }
+        s.r = hd[HD_RAD + g];  // g = 6: the pad radius
     }
     return s;
+}
+
+// stage the scene's pair table, boxes and radii in the workgroup header
+__device__ inline void stage_header(float *hd, const DevModel &md, int lane, int width)
+{
+    for (int i = lane; i < md.n_pairs; i += width) hd[HD_PAIR + i] = __int_as_float(md.pa[i] | (md.pb[i] << 8));
+    for (int b = lane; b < md.n_box; b += width) {
+        float *ab = hd + HD_BOXAB + 6 * b, *ch = hd + HD_BOXCH + 6 * b;
+        const Shape bx = box_shape(md, b);
+        const V3 lo = bx.p0 - bx.p1, hi = bx.p0 + bx.p1;
+        ab[0] = lo.x; ab[1] = lo.y; ab[2] = lo.z; ab[3] = hi.x; ab[4] = hi.y; ab[5] = hi.z;
+        ch[0] = bx.p0.x; ch[1] = bx.p0.y; ch[2] = bx.p0.z; ch[3] = bx.p1.x; ch[4] = bx.p1.y; ch[5] = bx.p1.z;
+    }
+    if (lane < 6) hd[HD_RAD + lane] = md.link_rad[lane];
+    if (lane == 6) hd[HD_RAD + 6] = md.pad_rad;
+    if (lane == 7) hd[HD_RAD + 8] = md.ball_r;
 }
 
 // publish the joint origins, tip and ball centre of the team to LDS
@@ -346,10 +406,10 @@ __device__ __forceinline__ void team_kin_from_lds(const float *tl, ArmKin kin[2]
 
 // AABBs of the dynamic geoms (ball, arm links, pads) from the published
 // geometry; lane t of each row writes geom t (rows write identical values)
-__device__ __forceinline__ void team_publish_aabb(float *tl, const DevModel &md, int t)
+__device__ __forceinline__ void team_publish_aabb(float *tl, const float *hd, int t)
 {
     if (t != G_TABLE) {
-        const AABB b = shape_aabb(team_geom(tl, md, t));
+        const AABB b = shape_aabb(team_geom(tl, hd, t));
         float *o = tl + TG_AABB + 6 * t;
         o[0] = b.lo.x; o[1] = b.lo.y; o[2] = b.lo.z;
         o[3] = b.hi.x; o[4] = b.hi.y; o[5] = b.hi.z;
@@ -358,7 +418,7 @@ __device__ __forceinline__ void team_publish_aabb(float *tl, const DevModel &md,
 
 // AABB test of candidate pair p (geom A is always dynamic) after growing A
 // by margin; the same comparisons as aabb_overlap on the geoms' boxes
-__device__ __forceinline__ bool pair_overlap(const float *tl, const DevModel &md, int ga, int gb, float margin)
+__device__ __forceinline__ bool pair_overlap(const float *tl, const float *hd, int ga, int gb, float margin)
 {
     const float *A = tl + TG_AABB + 6 * ga;
     if (gb == G_TABLE) return A[2] - margin <= 0.f;
@@ -366,9 +426,9 @@ __device__ __forceinline__ bool pair_overlap(const float *tl, const DevModel &md
     a.lo = v3(A[0], A[1], A[2]);
     a.hi = v3(A[3], A[4], A[5]);
     if (gb >= G_BOX) {
-        const Shape bx = box_shape(md, gb - G_BOX);
-        b.lo = bx.p0 - bx.p1;
-        b.hi = bx.p0 + bx.p1;
+        const float *B = hd + HD_BOXAB + 6 * (gb - G_BOX);
+        b.lo = v3(B[0], B[1], B[2]);
+        b.hi = v3(B[3], B[4], B[5]);
     } else {
         const float *B = tl + TG_AABB + 6 * gb;
         b.lo = v3(B[0], B[1], B[2]);
@@ -389,15 +449,17 @@ __device__ __forceinline__ uint64_t group_bits(uint64_t wm, int gshift)
 // in the team's LDS list in canonical order; returns the count.  li: lane
 // index within the sweeping group of G lanes.
 template <int G>
-__device__ inline int team_collect(const DevModel &md, float *tl, const LaneList &LL, int li, int gshift,
-                                   StepCounters &cnt)
+__device__ inline int team_collect(const DevModel &md, float *tl, const float *hd, const LaneList &LL, int li,
+                                   int gshift, StepCounters &cnt)
 {
     const int np = md.n_pairs;
     int *cand = (int *)(tl + TG_CAND);
     int ncand = 0;
     for (int base = 0; base < np; base += G) {
         const int p = base + li;
-        const bool ov = p < np && pair_overlap(tl, md, md.pa[p], md.pb[p], 0.f);
+        int gab = 0;
+        if (p < np) gab = __float_as_int(hd[HD_PAIR + p]);
+        const bool ov = p < np && pair_overlap(tl, hd, gab & 0xff, gab >> 8, 0.f);
         const uint64_t gm = group_bits<G>(__ballot(ov), gshift);
         if (ov) cand[ncand + __popcll(gm & ((1ull << li) - 1ull))] = p;
         ncand += __popcll(gm);
@@ -413,9 +475,10 @@ __device__ inline int team_collect(const DevModel &md, float *tl, const LaneList
         int ga = 0, gb = 0;
         if (live && i < ncand) {
             const int p = cand[i];
-            ga = md.pa[p];
-            gb = md.pb[p];
-            const Shape A = team_geom(tl, md, ga), B = team_geom(tl, md, gb);
+            const int gab = __float_as_int(hd[HD_PAIR + p]);
+            ga = gab & 0xff;
+            gb = gab >> 8;
+            const Shape A = team_geom(tl, hd, ga), B = team_geom(tl, hd, gb);
             ++cnt.np_tests;
             if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
             c = narrow(A, B);
@@ -443,6 +506,7 @@ struct TeamCtx {
     bool count;      // this row counts the collision-cost narrowphase tests
     bool joint;
     float *tl;
+    const float *hd;  // workgroup header (scene tables)
     LaneList LL;
     LanePark pk;
 };
@@ -457,6 +521,73 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 __device__ __forceinline__ V3 team_sum3(V3 x) { return v3(team_sum(x.x), team_sum(x.y), team_sum(x.z)); }
+
+// Projected Gauss-Seidel on four rows (one contact), f = 0 at the start:
+// row r takes res = b_r + R_r f_r + sum_c A_rc f_c, f_r <- max(f_r - res / (A_rr + R_r), 0).
+// The sums are regrouped so that each row's partial sum over values already
+// known is formed off the dependency chain: only one FMA per row waits for
+// the row before it (a single wave per SIMD runs latency-bound).
+__device__ __forceinline__ void pgs4(const float a[16], const float b[4], const float rr[4], const float dd[4],
+                                     int n_pgs, float f[4])
+{
+    float ad[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ad[r] = a[5 * r] + rr[r];  // A_rr + R_r multiplies f_r itself
+    for (int sweep = 0; sweep < n_pgs; ++sweep) {
+        // contributions of the values this sweep has not touched yet
+        const float p0 = fmaf(a[3], f[3], fmaf(a[2], f[2], fmaf(a[1], f[1], fmaf(ad[0], f[0], b[0]))));
+        const float p1 = fmaf(a[7], f[3], fmaf(a[6], f[2], fmaf(ad[1], f[1], b[1])));
+        const float p2 = fmaf(a[11], f[3], fmaf(ad[2], f[2], b[2]));
+        const float p3 = fmaf(ad[3], f[3], b[3]);
+        f[0] = fmaxf(fmaf(-p0, dd[0], f[0]), 0.f);
+        const float q1 = fmaf(a[4], f[0], p1);
+        const float q2 = fmaf(a[8], f[0], p2);
+        const float q3 = fmaf(a[12], f[0], p3);
+        f[1] = fmaxf(fmaf(-q1, dd[1], f[1]), 0.f);
+        const float s2 = fmaf(a[9], f[1], q2);
+        const float s3 = fmaf(a[13], f[1], q3);
+        f[2] = fmaxf(fmaf(-s2, dd[2], f[2]), 0.f);
+        const float t3 = fmaf(a[14], f[2], s3);
+        f[3] = fmaxf(fmaf(-t3, dd[3], f[3]), 0.f);
+    }
+}
+
+// One contact of the ball with a static body (table or box), the common case:
+// the whole solve in registers, identically on every lane.
+__device__ inline void ball_contact_solve(const DevModel &md, const LaneList &LL, V3 pb, V3 &vb, V3 &wb)
+{
+    const V3 n = v3(LL.at(0, 3), LL.at(0, 4), LL.at(0, 5));
+    const V3 r = v3(LL.at(0, 6), LL.at(0, 7), LL.at(0, 8)) - pb;
+    const float phi = LL.at(0, 2);
+    V3 t1, t2;
+    tangents(n, t1, t2);
+    V3 e[4], ge[4];
+    float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    ball_block(md, r, r, G);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        e[q] = fma3((q & 1) ? -md.mu : md.mu, q < 2 ? t1 : t2, n);
+        ge[q] = mul9(G, e[q]);
+    }
+    const V3 bfree = vb + cross(wb, r);
+    const float bias = md.kappa_h * (phi < 0.f ? -phi : 0.f);
+    float a[16], b[4], rr[4], dd[4], f[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[4 * q + c] = dot(e[q], ge[c]);
+        rr[q] = md.eps_r * a[5 * q];
+        dd[q] = 1.0f / (a[5 * q] + rr[q]);
+        b[q] = dot(e[q], bfree) - bias;
+        f[q] = 0.f;
+    }
+    pgs4(a, b, rr, dd, md.n_pgs, f);
+    V3 P = v3(0.f, 0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P = fma3(f[q], e[q], P);
+    vb = fma3(md.inv_ball_m, P, vb);
+    wb = fma3(md.inv_ball_I, cross(r, P), wb);
+}
 
 // Contact solve of one team (nc >= 1 contacts in the team's list, nc uniform
 // over the team).  k: this lane's joint kinematics at the contact positions;
@@ -543,8 +674,10 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
             const bool arm_t = (side_word >> t) & 1, ball_t = (side_word >> (8 + t)) & 1;
             V3 W = v3(0.f, 0.f, 0.f);  // row d of Mt^-1 J_t^T
             if (arm_t) {
-#pragma unroll
-                for (int e = 0; e < NJ; ++e) W = fma3(Minv[e], tbc3(Jc[t], tc.seg + e), W);
+                static_for<NJ>([&](auto ec) {
+                    constexpr int e = decltype(ec)::value;
+                    W = fma3(Minv[e], segb3<e>(Jc[t], tc.arm != 0), W);
+                });
             }
             const V3 rt = v3(E[20 * t + 12], E[20 * t + 13], E[20 * t + 14]);
 #pragma unroll
@@ -617,15 +750,10 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
             const float4 a4 = *reinterpret_cast<const float4 *>(A + r * MR);
             a[4 * r] = a4.x; a[4 * r + 1] = a4.y; a[4 * r + 2] = a4.z; a[4 * r + 3] = a4.w;
         }
-        for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
+        float f4[4] = {0.f, 0.f, 0.f, 0.f};
+        pgs4(a, b, rr, dd, md.n_pgs, f4);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float res = fmaf(rr[r], f[r], b[r]);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) res = fmaf(a[4 * r + c], f[c], res);
-                f[r] = fmaxf(f[r] - res * dd[r], 0.f);
-            }
-        }
+        for (int r = 0; r < 4; ++r) f[r] = f4[r];
     } else if constexpr (NC <= 4) {
         // several contacts: multipliers in registers, rows of A read from LDS
         // four at a time (independent of the sweep's dependency chain)
@@ -692,8 +820,10 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
     }
     if (any_arm) {
         float dv = 0.f;
-#pragma unroll
-        for (int e = 0; e < NJ; ++e) dv = fmaf(Minv[e], tbc(g, tc.seg + e), dv);
+        static_for<NJ>([&](auto ec) {
+            constexpr int e = decltype(ec)::value;
+            dv = fmaf(Minv[e], segb<e>(g, tc.arm != 0), dv);
+        });
         if (tc.joint) v += dv;
     }
 }
@@ -727,8 +857,10 @@ __device__ inline void team_substep(const DevModel &md, const JointConst &jc, co
     const float tau = clampf(md.kp * (S.qdes - S.q) + md.kd * (u - S.qd), -md.tau_max, md.tau_max);
     const float rhs = h * (tau - md.damp * S.qd - c);
     float xs[NJ];
-#pragma unroll
-    for (int i = 0; i < NJ; ++i) xs[i] = tbc(rhs, seg + i);
+    static_for<NJ>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        xs[i] = segb<i>(rhs, seg != 0);
+    });
     chol7_solve(Lp, xs);
     float v = S.qd + pick7(xs, jt);
     const V3 pb = S.pb;
@@ -748,15 +880,19 @@ __device__ inline void team_substep(const DevModel &md, const JointConst &jc, co
         }
     }
     __syncthreads();
-    team_publish_aabb(tc.tl, md, tc.t);
+    team_publish_aabb(tc.tl, tc.hd, tc.t);
     __syncthreads();
-    const int nc = team_collect<G>(md, tc.tl, tc.LL, tc.li, tc.gshift, cnt);
+    const int nc = team_collect<G>(md, tc.tl, tc.hd, tc.LL, tc.li, tc.gshift, cnt);
     if (tc.t == 0) {
         cnt.contacts += nc;
         if (nc >= md.n_cmax) ++cnt.overflow;
     }
     __syncthreads();
-    if (nc > 0) team_contact_solve<NC>(md, tc, k, pb, nc, v, vb, wb);
+    if (nc == 1 && __float_as_int(tc.LL.at(0, 0)) == G_BALL &&
+        (__float_as_int(tc.LL.at(0, 1)) == G_TABLE || __float_as_int(tc.LL.at(0, 1)) >= G_BOX))
+        ball_contact_solve(md, tc.LL, pb, vb, wb);
+    else if (nc > 0)
+        team_contact_solve<NC>(md, tc, k, pb, nc, v, vb, wb);
     S.q = fmaf(h, v, S.q);
     S.qd = v;
     S.pb = fma3(h, vb, pb);
@@ -796,7 +932,7 @@ __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc,
     team_fk(jc, S.q, tc.jt, k);
     team_publish_geom(tc.tl, k, S.pb, tc.arm, tc.jt);
     __syncthreads();
-    team_publish_aabb(tc.tl, md, tc.t);
+    team_publish_aabb(tc.tl, tc.hd, tc.t);
     __syncthreads();
     const float *tl = tc.tl;
     if (tc.t == 0) {
@@ -820,9 +956,10 @@ __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc,
     uint32_t nw = 0u;
     for (int i = tc.t, r = 0; i < nd; i += TEAM, ++r) {
         const int p = first_pair + i;
-        const int ga = md.pa[p], gb = md.pb[p];
-        if (pair_overlap(tl, md, ga, gb, md.m_c)) {
-            const Shape A = team_geom(tl, md, ga), B = team_geom(tl, md, gb);
+        const int gab = __float_as_int(tc.hd[HD_PAIR + p]);
+        const int ga = gab & 0xff, gb = gab >> 8;
+        if (pair_overlap(tl, tc.hd, ga, gb, md.m_c)) {
+            const Shape A = team_geom(tl, tc.hd, ga), B = team_geom(tl, tc.hd, gb);
             if (tc.count) {
                 ++cnt.np_tests;
                 if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
