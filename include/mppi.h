@@ -67,6 +67,13 @@ extern "C" {
 #define MPPI_MAP_WAVE 256u      /* rollout mapping: one wave per sample (shortest steps at small K);
                                    results equal MPPI_MAP_TEAM's bit for bit */
                                 /* neither: chosen from K (the library's tuning table) */
+#define MPPI_FP32_WEIGHTS 512u  /* mppi_plan, mppi_update: the weights of Eq. s_formula, their sums and the
+                                   weighted mean of Eq. mean_update in FP32 instead of FP64 (precision
+                                   study; the default keeps them in FP64) */
+#define MPPI_GRAPH 1024u        /* mppi_plan: run the plan's launch sequence (nu = nominal, then M x
+                                   rollout, statistics, update) as a HIP graph captured on first use and
+                                   replayed while shapes, scalars and device buffers stay the same (a
+                                   small per-context cache); MPPI_TIME_KERNELS is then ignored */
 
 /* Global geom ids (pair tables and AABB arrays use them): 0 ball,
  * 1 table, 2 + 7*arm + g (g = 0..5 capsule of link g+1, g = 6 pad sphere on

@@ -22,7 +22,7 @@ MAX_BOXES = 16
 OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY, E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
 PENDING = 1
 DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ, MAP_LANE, MAP_TEAM, SUPERSEDE = 1, 2, 4, 8, 16, 32, 64, 128
-MAP_WAVE = 256
+MAP_WAVE, FP32_WEIGHTS, GRAPH = 256, 512, 1024
 _MAPS = {None: 0, "auto": 0, "lane": MAP_LANE, "team": MAP_TEAM, "wave": MAP_WAVE}
 
 
@@ -282,14 +282,15 @@ class Scene:
 
 def mppi_plan(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, M=1, seed=0, eta=1.0,
               n_elite=0, sigma_per_step=False, time_kernels=False, want_stats=True, sync=False, stream=None,
-              mapping=None):
+              mapping=None, fp32_weights=False, graph=False):
     """One plan (Alg. 1).  Arrays: x0[55], nominal_U[H,14], sigma[14] or [H,14],
     U_new[H,14] (out), costs[K] (out).  mapping: None/"auto", "lane" or "team".
     Returns a stats dict (or None)."""
     (px0, pnom, psig, pU, pc), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32), (sigma, np.float32),
                                              (U_new, np.float32), (costs, np.float32)])
     flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | \
-            (TIME_KERNELS if time_kernels else 0) | (SYNC if sync else 0) | _MAPS[mapping]
+            (TIME_KERNELS if time_kernels else 0) | (SYNC if sync else 0) | _MAPS[mapping] | \
+            (FP32_WEIGHTS if fp32_weights else 0) | (GRAPH if graph else 0)
     o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
     st = Stats()
     rc = lib().mppi_plan(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), pU, pc,
@@ -328,14 +329,15 @@ def mppi_sample(ctx, scene, nu, sigma, seed, m, K, U=None, z=None, words=None, *
 
 
 def mppi_update(ctx, scene, costs, nu_in, sigma, seed, m, lam, nu_out, nu_out64=None, weights=None, *, eta=1.0,
-                n_elite=0, sigma_per_step=False, stream=None):
+                n_elite=0, sigma_per_step=False, stream=None, fp32_weights=False):
     (pc, pnu, psig, po), dev = _ptrs([(costs, np.float32), (nu_in, np.float32), (sigma, np.float32),
                                       (nu_out, np.float32)])
     (po64, pw), dev2 = _ptrs([(nu_out64, np.float64), (weights, np.float64)])
     if (nu_out64 is not None or weights is not None) and dev2 != dev:
         raise ValueError("mixing device and host arrays in one call")
     K, H = costs.shape[0], nu_in.shape[0]
-    flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0)
+    flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | \
+        (FP32_WEIGHTS if fp32_weights else 0)
     st = Stats()
     rc = lib().mppi_update(ctx._h, scene._h, pc, pnu, psig, int(seed) & 0xFFFFFFFFFFFFFFFF, int(m), int(K), int(H),
                            float(lam), float(eta), int(n_elite), po, po64, pw, C.byref(st), flags,

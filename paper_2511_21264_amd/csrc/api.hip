@@ -274,6 +274,11 @@ void mppi_ctx_destroy(mppi_ctx *c)
     if (c->st) hipFree(c->st);
     for (auto e : c->ev) hipEventDestroy(e);
     if (c->host_tab) hipHostFree(c->host_tab);
+    for (auto &g : c->graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        if (g.graph) hipGraphDestroy(g.graph);
+    }
+    if (c->capture) hipStreamDestroy(c->capture);
     delete c;
 }
 
@@ -354,10 +359,8 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
     if ((rc = ensure(ctx, S_DIST, (size_t)K * MAXCOST * sizeof(float), &ddist))) return rc;
     if ((rc = out_ptr(ctx, S_COSTS, costs, (size_t)K * sizeof(float), dev, &dcost))) return rc;
     if (!dcost && (rc = ensure(ctx, S_COSTS, (size_t)K * sizeof(float), &dcost))) return rc;
-    HIPCHK(hipMemcpyAsync(dnu, dnom, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
-    launch_reset_stats(ctx->st, s);
-
-    const bool timing = fl & MPPI_TIME_KERNELS;
+    const bool use_graph = fl & MPPI_GRAPH;
+    const bool timing = (fl & MPPI_TIME_KERNELS) && !use_graph;
     const int M = opts->M;
     if (timing) {
         while ((int)ctx->ev.size() < 2 * M) {
@@ -368,33 +371,95 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
     }
     const uint32_t k0 = (uint32_t)(opts->seed & 0xffffffffu), k1 = (uint32_t)(opts->seed >> 32);
     const int n_elite = (opts->n_elite <= 0 || opts->n_elite >= K) ? K : opts->n_elite;
-    for (int m = 0; m < M; ++m) {
-        RolloutArgs ra = {};
-        ra.md = scene->dev;
-        ra.x0 = (const float *)dx0;
-        ra.x0_shared = 1;
-        ra.nu = (const float *)dnu;
-        ra.sigma = (const float *)dsig;
-        ra.sigma_per_step = sps;
-        ra.U = nullptr;
-        ra.key0 = k0;
-        ra.key1 = k1;
-        ra.m = m;
-        ra.K = K;
-        ra.H = H;
-        ra.n_sub = 0;
-        ra.costs = (float *)dcost;
-        ra.counters = (int *)dcnt;
-        ra.diverged = &ctx->st->diverged;
-        ra.dist = (float *)ddist;
-        if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], s));
-        launch_rollout(ra, scene->host.n_cmax, s, mapping_of(fl));
-        if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], s));
-        StatsArgs sa = {(const float *)dcost, K, 1.0 / lambda, n_elite, (double *)dw, ctx->st, m, (const int *)dcnt};
-        launch_stats(sa, s);
-        UpdateArgs ua = {(const double *)dw, K, H, (const float *)dnu, (const float *)dsig, sps,
-                         scene->host.u_max, k0, k1, m, opts->eta, ctx->st, (float *)dnu, nullptr};
-        launch_update(ua, s);
+    const int f32 = (fl & MPPI_FP32_WEIGHTS) ? 1 : 0;
+    const int mapping = mapping_of(fl);
+    // the launch sequence of the plan: nu = nominal, stats reset, M x (rollout, stats, update)
+    auto enqueue = [&](hipStream_t q) -> int {
+        HIPCHK(hipMemcpyAsync(dnu, dnom, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, q));
+        launch_reset_stats(ctx->st, q);
+        for (int m = 0; m < M; ++m) {
+            RolloutArgs ra = {};
+            ra.md = scene->dev;
+            ra.x0 = (const float *)dx0;
+            ra.x0_shared = 1;
+            ra.nu = (const float *)dnu;
+            ra.sigma = (const float *)dsig;
+            ra.sigma_per_step = sps;
+            ra.U = nullptr;
+            ra.key0 = k0;
+            ra.key1 = k1;
+            ra.m = m;
+            ra.K = K;
+            ra.H = H;
+            ra.n_sub = 0;
+            ra.costs = (float *)dcost;
+            ra.counters = (int *)dcnt;
+            ra.diverged = &ctx->st->diverged;
+            ra.dist = (float *)ddist;
+            if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], q));
+            launch_rollout(ra, scene->host.n_cmax, q, mapping);
+            if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], q));
+            StatsArgs sa = {(const float *)dcost, K, 1.0 / lambda, n_elite, (double *)dw, ctx->st, m,
+                            (const int *)dcnt, f32};
+            launch_stats(sa, q);
+            UpdateArgs ua = {(const double *)dw, K, H, (const float *)dnu, (const float *)dsig, sps,
+                             scene->host.u_max, k0, k1, m, opts->eta, ctx->st, (float *)dnu, nullptr, f32};
+            launch_update(ua, q);
+        }
+        HIPCHK(hipGetLastError());
+        return MPPI_OK;
+    };
+    if (!use_graph) {
+        if ((rc = enqueue(s))) return rc;
+    } else {
+        // everything the captured nodes bake in: shapes, scalars and pointers
+        double lam_bits = lambda, eta_bits = opts->eta;
+        uintptr_t lb, eb;
+        std::memcpy(&lb, &lam_bits, sizeof lb);
+        std::memcpy(&eb, &eta_bits, sizeof eb);
+        const std::vector<uintptr_t> key = {(uintptr_t)scene->dev, (uintptr_t)K, (uintptr_t)H, (uintptr_t)M, lb, eb,
+                                            (uintptr_t)opts->seed, (uintptr_t)n_elite, (uintptr_t)sps,
+                                            (uintptr_t)mapping, (uintptr_t)f32, (uintptr_t)scene->host.n_cmax,
+                                            (uintptr_t)dx0, (uintptr_t)dsig, (uintptr_t)dnom, (uintptr_t)dnu,
+                                            (uintptr_t)dcost, (uintptr_t)dw, (uintptr_t)dcnt, (uintptr_t)ddist,
+                                            (uintptr_t)ctx->st};
+        PlanGraph *pg = nullptr;
+        for (auto &g : ctx->graphs)
+            if (g.key == key) pg = &g;
+        if (!pg) {
+            if (!ctx->capture) HIPCHK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+            // the capture stream must not run ahead of work already queued on s
+            HIPCHK(hipStreamSynchronize(s));
+            PlanGraph g;
+            g.key = key;
+            HIPCHK(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+            const int rc2 = enqueue(ctx->capture);
+            hipGraph_t graph = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(ctx->capture, &graph);
+            if (rc2) {
+                if (graph) hipGraphDestroy(graph);
+                return rc2;
+            }
+            if (e2 != hipSuccess) return fail(MPPI_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e2));
+            g.graph = graph;
+            if (hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                hipGraphDestroy(graph);
+                return fail(MPPI_E_DEVICE, "graph instantiation failed");
+            }
+            if (ctx->graphs.size() >= 8) {
+                // evict the least recently used graph
+                size_t lru = 0;
+                for (size_t i = 1; i < ctx->graphs.size(); ++i)
+                    if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
+                hipGraphExecDestroy(ctx->graphs[lru].exec);
+                hipGraphDestroy(ctx->graphs[lru].graph);
+                ctx->graphs.erase(ctx->graphs.begin() + lru);
+            }
+            ctx->graphs.push_back(g);
+            pg = &ctx->graphs.back();
+        }
+        pg->last_use = ++ctx->graph_clock;
+        HIPCHK(hipGraphLaunch(pg->exec, s));
     }
     HIPCHK(hipGetLastError());
     // outputs
@@ -740,11 +805,12 @@ int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, cons
     if (!dw && (rc = ensure(ctx, S_W, (size_t)K * sizeof(double), &dw))) return rc;
     const int ne = (n_elite <= 0 || n_elite >= K) ? K : n_elite;
     launch_reset_stats(ctx->st, s);
-    StatsArgs sa = {(const float *)dc, K, 1.0 / lambda, ne, (double *)dw, ctx->st, 0, nullptr};
+    const int f32 = (flags & MPPI_FP32_WEIGHTS) ? 1 : 0;
+    StatsArgs sa = {(const float *)dc, K, 1.0 / lambda, ne, (double *)dw, ctx->st, 0, nullptr, f32};
     launch_stats(sa, s);
     UpdateArgs ua = {(const double *)dw, K, H, (const float *)dnu, (const float *)dsig, sps, scene->host.u_max,
                      (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), m, eta, ctx->st, (float *)dout,
-                     (double *)dout64};
+                     (double *)dout64, f32};
     launch_update(ua, s);
     HIPCHK(hipGetLastError());
     if ((rc = copy_out(nu_out, dout, (size_t)H * NU * sizeof(float), dev, s))) return rc;

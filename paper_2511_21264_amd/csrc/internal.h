@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 #include <vector>
 
 #include "../../include/mppi.h"
@@ -35,8 +36,19 @@ bool all_finite(const float *p, size_t n);
 
 }  // namespace mppi_host
 
+// an instantiated HIP graph of one plan's launch sequence and what it baked in
+struct PlanGraph {
+    std::vector<uintptr_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long last_use = 0;
+};
+
 struct mppi_ctx {
     int device = 0;
+    std::vector<PlanGraph> graphs;  // small LRU cache (MPPI_GRAPH)
+    hipStream_t capture = nullptr;  // private stream the plan graphs are captured on
+    unsigned long long graph_clock = 0;
     mppi_host::Buf buf[mppi_host::S_N];
     mppi::PlanStats *st = nullptr;
     std::vector<hipEvent_t> ev;

@@ -49,6 +49,7 @@ struct StatsArgs {
     PlanStats *st;
     int iter;
     const int *counters;    // [K][4] or null
+    int fp32;               // weights and their sums in FP32 (precision study) instead of FP64
 };
 
 struct UpdateArgs {
@@ -64,6 +65,7 @@ struct UpdateArgs {
     const PlanStats *st;
     float *nu_out;
     double *nu_out64;
+    int fp32;               // weighted mean accumulated in FP32 instead of FP64
 };
 
 // End of a served request: nu := nominal when the plan diverged, copied to

@@ -6,7 +6,8 @@
 //                   stays in registers for the whole horizon, nothing but the
 //                   cost (and optional diagnostics) is written.
 //   stats_kernel    one workgroup: lowest finite cost, elite threshold,
-//                   s_j = exp(-(c_j - c_min) / lambda) in FP64, normalised
+//                   s_j = exp(-(c_j - c_min) / lambda) in FP64 (FP32 for the
+//                   precision study), normalised
 //                   weights and effective sample size (Eq. s_formula), with
 //                   fixed-order tree reductions (deterministic).
 //   update_kernel   one workgroup per control step: regenerates the projected
@@ -358,6 +359,11 @@ __device__ __forceinline__ T block_sum(T v, T *sh)
     return r;
 }
 
+__device__ __forceinline__ float exp_t(float x) { return expf(x); }
+__device__ __forceinline__ double exp_t(double x) { return exp(x); }
+
+// T: precision of the weights, their sums and the effective sample size
+template <typename T>
 __global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a0, const StatsArgs *tab, int m)
 {
     StatsArgs a = a0;
@@ -415,22 +421,23 @@ __global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a0, const StatsArgs
         thr = lo;
     }
     // weights
-    double z = 0.0, z2 = 0.0;
+    T *shT = sizeof(T) == sizeof(double) ? (T *)shd : (T *)shf;
+    T z = 0, z2 = 0;
     for (int j = t; j < a.K; j += SB) {
         const float c = a.costs[j];
-        double s = 0.0;
+        T s = 0;
         if (isfinite(c)) {
             const unsigned long long key = ((unsigned long long)ordered_bits(c) << 32) | (uint32_t)j;
-            if (key <= thr) s = exp(-((double)c - (double)cmin) * a.inv_lambda);
+            if (key <= thr) s = exp_t(-((T)c - (T)cmin) * (T)a.inv_lambda);
         }
-        a.weights[j] = s;
+        a.weights[j] = (double)s;
         z += s;
         z2 += s * s;
     }
-    z = block_sum<double>(z, shd);
-    z2 = block_sum<double>(z2, shd);
-    const double inv = nfin > 0 ? 1.0 / z : 0.0;
-    for (int j = t; j < a.K; j += SB) a.weights[j] *= inv;
+    z = block_sum<T>(z, shT);
+    z2 = block_sum<T>(z2, shT);
+    const T inv = nfin > 0 ? T(1) / z : T(0);
+    for (int j = t; j < a.K; j += SB) a.weights[j] = (double)((T)a.weights[j] * inv);
     // work counters
     if (a.counters) {
         for (int c = 0; c < 4; ++c) {
@@ -445,8 +452,8 @@ __global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a0, const StatsArgs
         st->cmin = nfin > 0 ? (double)cmin : INFINITY;
         st->best = nfin > 0 ? best_j : -1;
         st->n_finite = (int)nfin;
-        st->wsum = z;
-        st->ess = nfin > 0 ? z * z / z2 : 0.0;
+        st->wsum = (double)z;
+        st->ess = nfin > 0 ? (double)(z * z / z2) : 0.0;
         if (a.iter < 64) st->cmin_iter[a.iter] = st->cmin;
         if (nfin == 0) st->diverged = 1;
     }
@@ -454,13 +461,16 @@ __global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a0, const StatsArgs
 
 void launch_stats(const StatsArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(SB), 0, s, a, (const StatsArgs *)nullptr, a.iter);
+    if (a.fp32)
+        hipLaunchKernelGGL(stats_kernel<float>, dim3(1), dim3(SB), 0, s, a, (const StatsArgs *)nullptr, a.iter);
+    else
+        hipLaunchKernelGGL(stats_kernel<double>, dim3(1), dim3(SB), 0, s, a, (const StatsArgs *)nullptr, a.iter);
 }
 
 void launch_stats_batch(const StatsArgs *d_tab, int n, int m, hipStream_t s)
 {
     StatsArgs dummy = {};
-    hipLaunchKernelGGL(stats_kernel, dim3(n), dim3(SB), 0, s, dummy, d_tab, m);
+    hipLaunchKernelGGL(stats_kernel<double>, dim3(n), dim3(SB), 0, s, dummy, d_tab, m);
 }
 
 __global__ void reset_stats_kernel(PlanStats *st0)
@@ -485,9 +495,10 @@ void launch_reset_stats(PlanStats *st, hipStream_t s, int n)
 
 constexpr int UB = 256;
 
+template <typename T>
 __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateArgs *tab, const int *blk, int m)
 {
-    __shared__ double red[NU][UB];
+    __shared__ T red[NU][UB];
     UpdateArgs a = a0;
     int k = blockIdx.x;
     if (tab) {
@@ -497,19 +508,19 @@ __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateA
     }
     const int t = threadIdx.x;
     const bool div = a.st->diverged != 0;
-    double acc[NU];
+    T acc[NU];
 #pragma unroll
-    for (int d = 0; d < NU; ++d) acc[d] = 0.0;
+    for (int d = 0; d < NU; ++d) acc[d] = 0;
     if (!div) {
         const float *nu_k = a.nu_in + k * NU;
         const float *sig_k = a.sigma + (a.sigma_per_step ? k * NU : 0);
         for (int j = t; j < a.K; j += UB) {
-            const double w = a.weights[j];
-            if (w != 0.0) {
+            const T w = (T)a.weights[j];
+            if (w != T(0)) {
                 float u[NU];
                 sample_u(nu_k, sig_k, a.u_max, a.key0, a.key1, (uint32_t)j, (uint32_t)k, (uint32_t)a.m, u);
 #pragma unroll
-                for (int d = 0; d < NU; ++d) acc[d] = fma(w, (double)u[d], acc[d]);
+                for (int d = 0; d < NU; ++d) acc[d] = fma(w, (T)u[d], acc[d]);
             }
         }
     }
@@ -524,23 +535,28 @@ __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateA
         __syncthreads();
     }
     if (t < NU) {
-        const double nu0 = (double)a.nu_in[k * NU + t];
-        const double v = div ? nu0 : (1.0 - a.eta) * nu0 + a.eta * red[t][0];
+        const T nu0 = (T)a.nu_in[k * NU + t];
+        const T eta = (T)a.eta;
+        const T v = div ? nu0 : (T(1) - eta) * nu0 + eta * red[t][0];
         a.nu_out[k * NU + t] = (float)v;
-        if (a.nu_out64) a.nu_out64[k * NU + t] = v;
+        if (a.nu_out64) a.nu_out64[k * NU + t] = (double)v;
     }
 }
 
 void launch_update(const UpdateArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(update_kernel, dim3(a.H), dim3(UB), 0, s, a, (const UpdateArgs *)nullptr, (const int *)nullptr,
-                       a.m);
+    if (a.fp32)
+        hipLaunchKernelGGL(update_kernel<float>, dim3(a.H), dim3(UB), 0, s, a, (const UpdateArgs *)nullptr,
+                           (const int *)nullptr, a.m);
+    else
+        hipLaunchKernelGGL(update_kernel<double>, dim3(a.H), dim3(UB), 0, s, a, (const UpdateArgs *)nullptr,
+                           (const int *)nullptr, a.m);
 }
 
 void launch_update_batch(const UpdateArgs *d_tab, const int *d_blk, int nblk, int m, hipStream_t s)
 {
     UpdateArgs dummy = {};
-    hipLaunchKernelGGL(update_kernel, dim3(nblk), dim3(UB), 0, s, dummy, d_tab, d_blk, m);
+    hipLaunchKernelGGL(update_kernel<double>, dim3(nblk), dim3(UB), 0, s, dummy, d_tab, d_blk, m);
 }
 
 // one workgroup per finishing request

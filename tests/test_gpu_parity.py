@@ -479,3 +479,79 @@ def test_team_and_wave_mappings_bit_identical(mp, ctx):
     assert np.array_equal(res["team"][0], res["wave"][0]) and np.array_equal(res["team"][1], res["wave"][1])
     assert res["team"][2] == res["wave"][2]
     scene.close()
+
+
+def test_precision_study_weights_fp64_vs_fp32(mp, ctx, oracle_mod):
+    """The obstacle-course workload's update size (K=4096, H=100) from
+    identical costs: weights, log-sum-exp normaliser and weighted mean in
+    FP64 (the default) agree with the FP64 oracle to the FP32 rounding of
+    the samples; the FP32 variant is bounded and never closer."""
+    sc = W.make_scene(3)
+    scene = mp.Scene(ctx, sc)
+    o = oracle_mod.Oracle(sc)
+    K, H, lam, seed, m = 4096, 100, 0.1, 99, 2
+    rng = np.random.default_rng(3)
+    nu = rng.uniform(-0.5, 0.5, (H, 14)).astype(np.float32)
+    sig = np.full(14, 0.3, np.float32)
+    costs = (40.0 + rng.gamma(2.0, 2.0, K)).astype(np.float32)
+    Uo = o.sample(f32(nu), f32(sig), seed, K, m)
+    ref, nf, ess = o.update(Uo, f32(costs), lam, f32(nu))
+    out = {}
+    for fp32 in (False, True):
+        nu_out = torch.zeros((H, 14), device=DEV)
+        nu64 = torch.zeros((H, 14), dtype=torch.float64, device=DEV)
+        st = mp.mppi_update(ctx, scene, T(costs), T(nu), T(sig), seed, m, lam, nu_out, nu64, fp32_weights=fp32)
+        torch.cuda.synchronize()
+        assert st["rc"] == 0
+        out[fp32] = (np.abs(nu64.cpu().numpy() - ref).max(), st["ess"])
+    err64, err32 = out[False][0], out[True][0]
+    print(f"precision study K={K} H={H}: max |nu - oracle| FP64 weights {err64:.3e}, FP32 weights {err32:.3e}; "
+          f"ESS {ess:.2f}")
+    assert err64 < 2e-6
+    assert err32 < 1e-3 and err32 >= err64 * 0.5
+    assert out[False][1] == pytest.approx(ess, rel=1e-9)
+    scene.close()
+
+
+@pytest.mark.parametrize("mapping", ["wave", "lane"])
+def test_plan_graph_replays_equal_eager(mp, ctx, mapping):
+    """MPPI_GRAPH: the captured plan replays bit-identically to the eager
+    plan, on every replay, with eager work and synchronisations between the
+    replays, and follows new contents of the same device buffers."""
+    sc = W.make_scene(2)
+    scene = mp.Scene(ctx, sc)
+    pp = W.plan_params(2, K=96, H=10, M=3)
+    K, H, M = pp["K"], pp["H"], pp["M"]
+    x0 = T(W.initial_state(sc))
+    sig = T(pp["sigma"])
+    nom = T(np.random.default_rng(5).uniform(-0.2, 0.2, (H, 14)))
+
+    Ub = torch.zeros((H, 14), device=DEV)  # fixed output buffers: the graph replays
+    cb = torch.zeros(K, device=DEV)
+
+    def plan(graph):
+        U = Ub if graph else torch.zeros((H, 14), device=DEV)
+        c = cb if graph else torch.zeros(K, device=DEV)
+        U.zero_()
+        c.zero_()
+        st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U, c, M=M, seed=pp["seed"], mapping=mapping,
+                          graph=graph)
+        torch.cuda.synchronize()
+        return U.clone(), c.clone(), st
+
+    Ue, ce, ste = plan(False)
+    for rep in range(4):
+        Ug, cg, stg = plan(True)
+        assert torch.equal(Ug, Ue) and torch.equal(cg, ce), f"replay {rep} differs"
+        assert stg["best"] == ste["best"] and stg["cmin_iter"] == ste["cmin_iter"]
+        # eager work in between
+        _ = plan(False)
+        torch.cuda.synchronize()
+    # new contents of the same buffers: the graph sees them
+    x0.copy_(T(W.random_states(sc, 1, seed=8, spread=0.1)[0]))
+    nom.mul_(0.5)
+    Ue2, ce2, _ = plan(False)
+    Ug2, cg2, _ = plan(True)
+    assert torch.equal(Ug2, Ue2) and torch.equal(cg2, ce2)
+    assert not torch.equal(ce2, ce)
+    scene.close()
