@@ -194,6 +194,137 @@ def bench_serving(mp, ctx, duration, mapping, thr_env_steps):
     return res
 
 
+def bench_precision(mp, ctx, n_check=16):
+    """Precision study on the 8-box obstacle course (K=4096, H=100): FP32
+    rollouts; weights, normaliser and weighted mean in FP64 (default) and in
+    FP32, each against the FP64 oracle's update from the same GPU costs; and
+    the GPU's FP32 rollout costs against the oracle's FP64 rollouts on the
+    first n_check samples.  Rollouts are chaotic under contact, so the cost
+    error is a statement about the world model's FP32 sensitivity."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads as W
+    dev = torch.device("cuda:0")
+    sc = W.make_scene(3)
+    pp = W.plan_params(3)
+    K, H = pp["K"], pp["H"]
+    scene = mp.Scene(ctx, sc)
+    o = oracle.Oracle(sc)
+    x0 = W.initial_state(sc).astype(np.float32)
+    sig = pp["sigma"].astype(np.float32)
+    nom = np.zeros((H, 14), np.float32)
+    U = torch.zeros((H, 14), device=dev)
+    c = torch.zeros(K, device=dev)
+    mp.mppi_plan(ctx, scene, torch.tensor(x0, device=dev), torch.tensor(nom, device=dev), K, H, pp["lam"],
+                 torch.tensor(sig, device=dev), U, c, M=1, seed=pp["seed"])
+    torch.cuda.synchronize()
+    costs = c.cpu().numpy()
+    Uo = o.sample(nom.astype(np.float64), sig.astype(np.float64), pp["seed"], K, 0)
+    ref, _, ess = o.update(Uo, costs.astype(np.float64), pp["lam"], nom.astype(np.float64))
+    res = {"workload": f"8-box obstacle course, K={K}, H={H}, first iteration from a zero nominal", "ess": ess}
+    for fp32 in (False, True):
+        out = torch.zeros((H, 14), device=dev)
+        out64 = torch.zeros((H, 14), dtype=torch.float64, device=dev)
+        mp.mppi_update(ctx, scene, c, torch.tensor(nom, device=dev), torch.tensor(sig, device=dev), pp["seed"], 0,
+                       pp["lam"], out, out64, fp32_weights=fp32)
+        torch.cuda.synchronize()
+        err = np.abs(out64.cpu().numpy() - ref)
+        res["fp32_weights" if fp32 else "fp64_weights"] = {"max_abs_err_nu": float(err.max()),
+                                                          "rel_err_nu": float(err.max() / np.abs(ref).max())}
+    co = o.rollout_batch(x0.astype(np.float64), Uo[:n_check])
+    co = np.asarray(co[0] if isinstance(co, tuple) else co, dtype=np.float64)
+    rel = np.abs(costs[:n_check] - co) / np.abs(co)
+    res["rollout_cost_rel_err"] = {"samples": n_check, "median": float(np.median(rel)), "max": float(rel.max())}
+    scene.close()
+    return res
+
+
+def traffic_per_launch(mapping, K, H, M):
+    """HBM bytes per rollout launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), or
+    None when the kernel sources changed since the counters were taken or
+    the summary is for another mapping or shape."""
+    path = os.path.join(ROOT, "profiles", "rollout_traffic_c2.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("sources_sha256") != sources_hash() or rec.get("mapping") != mapping or \
+            rec.get("K") != K or rec.get("H") != H:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def sources_hash():
+    import hashlib
+    d = os.path.join(ROOT, "paper_2511_21264_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def summarize_profiles(base):
+    """Turn rocprofv3 result folders (trace/, fetch/, write/, cfetch/,
+    cwrite/ under `base`) into the profiles/ summaries: kernel-time table and
+    the counter-based HBM traffic per rollout launch."""
+    import sqlite3
+    import glob
+
+    def db(sub):
+        f = glob.glob(os.path.join(base, sub, "**", "*results.db"), recursive=True)
+        return sqlite3.connect(f[0]) if f else None
+
+    meta = json.load(open(os.path.join(base, "meta.json")))
+    lines = []
+    tr = db("trace")
+    if tr:
+        rows = tr.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                          "order by total_duration desc limit 12").fetchall()
+        # rocprofv3 stores these durations in microseconds
+        lines += ["| kernel | calls | total ms | avg ms | % |", "|---|---|---|---|---|"]
+        for n, calls, tot, avg, pct in rows:
+            lines.append(f"| {n[:90]} | {calls} | {tot / 1e3:.3f} | {avg / 1e3:.3f} | {pct:.2f} |")
+
+    def counter(sub, name, like):
+        c = db(sub)
+        if not c:
+            return None
+        r = c.execute("select avg(value), count(*) from counters_collection where counter_name = ? and "
+                      "kernel_name like ?", (name, like)).fetchone()
+        return r
+
+    like = meta["kernel_like"]
+    fetch = counter("fetch", "FETCH_SIZE", like)
+    write = counter("write", "WRITE_SIZE", like)
+    cf = counter("cfetch", "FETCH_SIZE", "%copyBuffer%")
+    cw = counter("cwrite", "WRITE_SIZE", "%copyBuffer%")
+    rec = None
+    if fetch and write and cf and cw and fetch[0] is not None and cf[0]:
+        copy_kib = meta["calib_copy_bytes"] / 1024.0
+        f_scale = copy_kib / cf[0]  # bytes the copy reads, over what the counter says
+        w_scale = copy_kib / cw[0]
+        hbm = fetch[0] * f_scale * 1024 + write[0] * w_scale * 1024
+        rec = {"mapping": meta["mapping"], "K": meta["K"], "H": meta["H"], "kernel_like": like,
+               "fetch_kib_per_dispatch": fetch[0], "write_kib_per_dispatch": write[0],
+               "fetch_scale": f_scale, "write_scale": w_scale, "hbm_bytes_per_launch": hbm,
+               "sources_sha256": sources_hash(), "commands": meta["commands"]}
+        json.dump(rec, open(os.path.join(ROOT, "profiles", "rollout_traffic_c2.json"), "w"), indent=1)
+    md = [f"# {meta['title']}", ""]
+    md += ["Commands (run from the repository root, TMPDIR=/tmp):", ""]
+    md += [f"    {c}" for c in meta["commands"]]
+    md += ["", "## Kernel time (rocprofv3 --kernel-trace --stats)", ""] + lines
+    if rec:
+        md += ["", "## HBM traffic of the rollout kernel (per dispatch)", "",
+               f"FETCH_SIZE {rec['fetch_kib_per_dispatch']:.1f} KiB x {rec['fetch_scale']:.3f}, "
+               f"WRITE_SIZE {rec['write_kib_per_dispatch']:.1f} KiB x {rec['write_scale']:.3f} "
+               f"(scale = bytes a {meta['calib_copy_bytes'] >> 20} MiB device copy moves / what the counter "
+               f"reports for it) = {rec['hbm_bytes_per_launch'] / 1e6:.2f} MB per launch."]
+    open(os.path.join(ROOT, "profiles", meta["file"]), "w").write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def calib_copy(mb):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -218,9 +349,16 @@ def main():
     ap.add_argument("--mapping", default="auto", choices=["auto", "lane", "team", "wave"])
     ap.add_argument("--packed-steps", type=int, default=2, help="steps of the packed-batch leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="trace length of the serving legs (0: skip)")
+    ap.add_argument("--no-precision", dest="precision", action="store_false",
+                    help="skip the FP64-vs-FP32 weights study on the 8-box workload")
+    ap.add_argument("--summarize-profiles", default="",
+                    help="read rocprofv3 result folders under this path and write the profiles/ summaries")
     args = ap.parse_args()
     if args.calib_copy_mb:
         calib_copy(args.calib_copy_mb)
+        return
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -247,9 +385,20 @@ def main():
     Unew = torch.zeros((H, 14), dtype=torch.float32, device=dev)
     costs = torch.zeros(K, dtype=torch.float32, device=dev)
 
+    tuned = None
+    if args.mapping == "auto":
+        # the measured mapping for this K (the context keeps it for later calls)
+        name, ms = mp.mppi_autotune(ctx, scene, W.initial_state(sc), pp["sigma"], K, H)
+        tuned = {"K": K, "chosen": name, "rollout_ms": ms}
+    mapping = None if args.mapping == "auto" else args.mapping
+    used = tuned["chosen"] if tuned else args.mapping
+    nc = 4 if int(sc["n_cmax"]) <= 4 else 8
+    kernel_name = {"lane": f"rollout_kernel<{nc}>", "team": f"rollout_team_kernel<{nc}, 4>",
+                   "wave": f"rollout_team_kernel<{nc}, 1>"}[used]
+
     def plan():
         return mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"],
-                            time_kernels=True, mapping=args.mapping)
+                            time_kernels=True, mapping=mapping)
 
     for _ in range(args.warmup):
         plan()
@@ -292,26 +441,39 @@ def main():
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "physics_substeps_per_s": env_steps * int(sc["n_sub"]) / elapsed,
         "roofline": {
-            "kernel": "rollout_kernel",
+            "kernel": kernel_name,
             "bound": "alu",
             "achieved": achieved / 1e12,
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32,
-            "traffic": None,
+            "traffic": traffic_per_launch(used, K, H, M),
             "peak_nonpacked": PEAK_FP32_NONPACKED / 1e12,
             "avg_launch_ms": avg_launch_s * 1e3,
             "flop_per_launch": float(np.mean(flops)),
         },
         "stats": {"ess": st["ess"], "c_min": st["c_min"], "contacts_per_substep":
                   st["contacts"] / (M * K * H * int(sc["n_sub"]))},
+        "mapping": used,
+        "autotune": tuned,
     }
+    if args.mapping == "auto" and (args.packed_steps > 0 or args.serve_seconds > 0):
+        # size classes of single requests (256..4096 samples) and of packed
+        # launches (up to 2^17 samples), measured once on this context
+        sc5 = W.make_scene(4, 0)
+        s5 = mp.Scene(ctx, sc5)
+        out["autotune_classes"] = {}
+        for c in range(8, 18):
+            name, ms = mp.mppi_autotune(ctx, s5, W.initial_state(sc5), pp["sigma"], 1 << c, 16)
+            out["autotune_classes"][str(1 << c)] = name
+        s5.close()
     if args.packed_steps > 0:
-        out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, args.mapping)
+        out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, mapping)
     if args.serve_seconds > 0:
         thr = out.get("packed", {}).get("batched", {}).get("env_steps_per_s", out["value"])
-        out["serving"] = bench_serving(mp, ctx, args.serve_seconds, "team" if args.mapping == "auto" else args.mapping,
-                                       thr)
+        out["serving"] = bench_serving(mp, ctx, args.serve_seconds, mapping, thr)
+    if args.precision:
+        out["precision"] = bench_precision(mp, ctx)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(sc, pp, threads)

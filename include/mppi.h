@@ -66,7 +66,8 @@ extern "C" {
 #define MPPI_MAP_TEAM 64u       /* rollout mapping: 16 lanes per sample, 4 samples per wave */
 #define MPPI_MAP_WAVE 256u      /* rollout mapping: one wave per sample (shortest steps at small K);
                                    results equal MPPI_MAP_TEAM's bit for bit */
-                                /* neither: chosen from K (the library's tuning table) */
+                                /* none of the three: the mapping mppi_autotune measured for K's size
+                                   class on this context, else chosen from K */
 #define MPPI_FP32_WEIGHTS 512u  /* mppi_plan, mppi_update: the weights of Eq. s_formula, their sums and the
                                    weighted mean of Eq. mean_update in FP32 instead of FP64 (precision
                                    study; the default keeps them in FP64) */
@@ -334,6 +335,17 @@ int mppi_poll(mppi_server *srv, uint64_t ticket, int timeout_ms, mppi_ticket_inf
 int mppi_cancel(mppi_server *srv, uint64_t ticket);
 /* Counters of the server since creation. */
 int mppi_server_query(mppi_server *srv, mppi_server_info *info);
+
+/* Autotuner of the sample-to-lane mapping: times one rollout launch of K
+ * samples over H control steps of `scene` (from state x0[MPPI_NX], mean 0,
+ * sigma[14]; host arrays) with each mapping (lane, team, wave; best of two
+ * after a warm-up launch) and records the fastest for K's size class
+ * (ceil(log2 K)) in the context.  Later calls on the context that pin no
+ * mapping use the recorded one for that class.  *mapping (nullable)
+ * receives the MPPI_MAP_* flag chosen, ms[3] (nullable) the times of the
+ * lane, team and wave launches.  Synchronous; uses a private stream. */
+int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *sigma, int K, int H,
+                  int *mapping, float *ms);
 
 /* Broadphase of the contact pass: for every candidate pair of the scene
  * (canonical order), flags[p] = 1 when the closed AABBs of its geoms

@@ -137,6 +137,7 @@ def lib():
                                       _P]),
             "mppi_update": (C.c_int, [_P, _P, _P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_double,
                                       C.c_double, C.c_int, _P, _P, _P, C.POINTER(Stats), C.c_uint, _P]),
+            "mppi_autotune": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.POINTER(C.c_int), _P]),
             "mppi_broadphase": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_float, _P, C.c_uint, _P]),
             "mppi_narrowphase": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, _P, _P, _P, C.c_uint, _P]),
         }
@@ -485,3 +486,18 @@ class Server:
         i = ServerInfo()
         _check(lib().mppi_server_query(self._h, C.byref(i)))
         return {k: getattr(i, k) for k, _ in i._fields_}
+
+
+_MAP_NAMES = {MAP_LANE: "lane", MAP_TEAM: "team", MAP_WAVE: "wave"}
+
+
+def mppi_autotune(ctx, scene, x0, sigma, K, H):
+    """Time the lane, team and wave mappings on one rollout launch; the
+    context remembers the fastest for K's size class.  Returns (name, ms dict)."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float32)
+    sigma = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float32), (14,)))
+    m = C.c_int(0)
+    ms = (C.c_float * 3)()
+    _check(lib().mppi_autotune(ctx._h, scene._h, x0.ctypes.data, sigma.ctypes.data, int(K), int(H), C.byref(m),
+                               ms))
+    return _MAP_NAMES[m.value], {"lane": ms[0], "team": ms[1], "wave": ms[2]}

@@ -227,6 +227,22 @@ int mapping_of(unsigned flags)
     return MAP_AUTO;
 }
 
+int k_class(long K)
+{
+    int b = 0;
+    while (b < 20 && (1L << b) < K) ++b;
+    return b;
+}
+
+int resolve_mapping(const mppi_ctx *c, long K, unsigned flags)
+{
+    const int pinned = mapping_of(flags);
+    if (pinned != MAP_AUTO) return pinned;
+    const int Kc = (int)std::min<long>(K, MPPI_MAX_K);
+    if (c && c->tuned_map[k_class(Kc)]) return c->tuned_map[k_class(Kc)];
+    return pick_mapping(Kc, MAP_AUTO);
+}
+
 int set_device(mppi_ctx *c)
 {
     HIPCHK(hipSetDevice(c->device));
@@ -372,7 +388,7 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
     const uint32_t k0 = (uint32_t)(opts->seed & 0xffffffffu), k1 = (uint32_t)(opts->seed >> 32);
     const int n_elite = (opts->n_elite <= 0 || opts->n_elite >= K) ? K : opts->n_elite;
     const int f32 = (fl & MPPI_FP32_WEIGHTS) ? 1 : 0;
-    const int mapping = mapping_of(fl);
+    const int mapping = resolve_mapping(ctx, K, fl);
     // the launch sequence of the plan: nu = nominal, stats reset, M x (rollout, stats, update)
     auto enqueue = [&](hipStream_t q) -> int {
         HIPCHK(hipMemcpyAsync(dnu, dnom, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, q));
@@ -539,7 +555,7 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const int map = pick_mapping((int)total_k, mapping_of(flags));
+    const int map = resolve_mapping(ctx, total_k, flags);
     const int per = samples_per_block(map);
     // requests in order of decreasing M: the ones still iterating form a prefix
     std::vector<int> ord(n);
@@ -745,7 +761,7 @@ int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x
     ra.terms = (float *)dt;
     ra.xout = (float *)dxo;
     ra.traj = traj;
-    launch_rollout(ra, scene->host.n_cmax, s, mapping_of(flags));
+    launch_rollout(ra, scene->host.n_cmax, s, resolve_mapping(ctx, n, flags));
     HIPCHK(hipGetLastError());
     if ((rc = copy_out(costs, dc, (size_t)n * sizeof(float), dev, s))) return rc;
     if ((rc = copy_out(terms, dt, (size_t)n * 7 * sizeof(float), dev, s))) return rc;
@@ -831,6 +847,75 @@ int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, cons
     }
     if (hs.diverged) return fail(MPPI_E_DIVERGED, "no finite cost");
     return MPPI_OK;
+}
+
+int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *sigma, int K, int H,
+                  int *mapping, float *ms)
+{
+    if (!ctx || !scene || !x0 || !sigma) return fail(MPPI_E_INVAL, "NULL argument");
+    if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
+    if (K < 1 || K > MPPI_MAX_K || H < 1 || H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "K=%d or H=%d out of range", K, H);
+    if (!all_finite(x0, NX) || !all_finite(sigma, NU)) return fail(MPPI_E_INVAL, "non-finite input");
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](int code) {
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        hipStreamDestroy(s);
+        return code;
+    };
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return done(fail(MPPI_E_DEVICE, "event creation failed"));
+    const void *dx0, *dsig;
+    void *dnu, *dcost, *ddist;
+    if ((rc = stage_in(ctx, S_X0, x0, NX * sizeof(float), false, s, &dx0)) ||
+        (rc = stage_in(ctx, S_SIGMA, sigma, NU * sizeof(float), false, s, &dsig)) ||
+        (rc = ensure(ctx, S_NU, (size_t)H * NU * sizeof(float), &dnu)) ||
+        (rc = ensure(ctx, S_COSTS, (size_t)K * sizeof(float), &dcost)) ||
+        (rc = ensure(ctx, S_DIST, (size_t)K * MAXCOST * sizeof(float), &ddist)))
+        return done(rc);
+    if (hipMemsetAsync(dnu, 0, (size_t)H * NU * sizeof(float), s) != hipSuccess)
+        return done(fail(MPPI_E_DEVICE, "clearing the mean failed"));
+    RolloutArgs ra = {};
+    ra.md = scene->dev;
+    ra.x0 = (const float *)dx0;
+    ra.x0_shared = 1;
+    ra.nu = (const float *)dnu;
+    ra.sigma = (const float *)dsig;
+    ra.key0 = 0x5eed;
+    ra.K = K;
+    ra.H = H;
+    ra.costs = (float *)dcost;
+    ra.dist = (float *)ddist;
+    const int maps[3] = {MAP_LANE, MAP_TEAM, MAP_WAVE};
+    const unsigned flag_of[3] = {MPPI_MAP_LANE, MPPI_MAP_TEAM, MPPI_MAP_WAVE};
+    float best = 0.f;
+    int bi = 0;
+    for (int i = 0; i < 3; ++i) {
+        float t = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            ra.m = rep;
+            if (hipEventRecord(e0, s) != hipSuccess) return done(fail(MPPI_E_DEVICE, "event record failed"));
+            launch_rollout(ra, scene->host.n_cmax, s, maps[i]);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return done(fail(MPPI_E_DEVICE, "timing launch failed"));
+            float ms1 = 0.f;
+            if (hipEventElapsedTime(&ms1, e0, e1) != hipSuccess) return done(fail(MPPI_E_DEVICE, "event timing failed"));
+            if (rep > 0) t = rep == 1 ? ms1 : std::min(t, ms1);  // the first launch warms up
+        }
+        if (ms) ms[i] = t;
+        if (i == 0 || t < best) {
+            best = t;
+            bi = i;
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return done(fail(MPPI_E_DEVICE, "rollout launch failed"));
+    ctx->tuned_map[k_class(K)] = maps[bi];
+    if (mapping) *mapping = (int)flag_of[bi];
+    return done(MPPI_OK);
 }
 
 int mppi_broadphase(mppi_ctx *ctx, const mppi_scene *scene, const float *lo, const float *hi, int n, float margin,

@@ -32,6 +32,10 @@ enum Slot {
 };
 
 int mapping_of(unsigned flags);
+// the mapping of a launch over K samples: pinned by the flags, else the
+// context's measured choice for K's class, else the built-in rule
+int resolve_mapping(const mppi_ctx *c, long K, unsigned flags);
+int k_class(long K);
 bool all_finite(const float *p, size_t n);
 
 }  // namespace mppi_host
@@ -46,6 +50,9 @@ struct PlanGraph {
 
 struct mppi_ctx {
     int device = 0;
+    // measured rollout mapping per sample-count class (MPPI_MAP_* of the
+    // fastest launch); index: ceil(log2 K)), 0 = not tuned
+    int tuned_map[21] = {0};
     std::vector<PlanGraph> graphs;  // small LRU cache (MPPI_GRAPH)
     hipStream_t capture = nullptr;  // private stream the plan graphs are captured on
     unsigned long long graph_clock = 0;

@@ -253,7 +253,7 @@ int launch_iteration(mppi_server *S, int b, const std::vector<Req *> &act, const
         total_k += R->K;
         ncmax = std::max(ncmax, R->scene->host.n_cmax);
     }
-    const int map = pick_mapping((int)std::min<long>(total_k, MPPI_MAX_K), mapping_of(S->o.flags));
+    const int map = resolve_mapping(S->ctx, total_k, S->o.flags);
     const int per = samples_per_block(map);
     std::vector<int> blk, ublk, ablk;
     for (int i = 0; i < n; ++i) {

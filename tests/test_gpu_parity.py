@@ -555,3 +555,29 @@ def test_plan_graph_replays_equal_eager(mp, ctx, mapping):
     assert torch.equal(Ug2, Ue2) and torch.equal(cg2, ce2)
     assert not torch.equal(ce2, ce)
     scene.close()
+
+
+def test_autotune_records_the_mapping_auto_uses(mp, ctx):
+    """mppi_autotune times the three mappings; afterwards a plan that pins no
+    mapping runs with the recorded one (equal to pinning it, bit for bit)."""
+    sc = W.make_scene(2)
+    scene = mp.Scene(ctx, sc)
+    c2 = mp.Context(0)  # a fresh context: nothing recorded yet
+    scene2 = mp.Scene(c2, sc)
+    K, H = 600, 8
+    pp = W.plan_params(2, K=K, H=H, M=2)
+    name, ms = mp.mppi_autotune(c2, scene2, W.initial_state(sc), pp["sigma"], K, H)
+    assert name in ("lane", "team", "wave") and all(v > 0 for v in ms.values())
+    assert ms[name] == min(ms.values())
+    x0, nom, sig = T(W.initial_state(sc)), torch.zeros((H, 14), device=DEV), T(pp["sigma"])
+    res = []
+    for cx, scn, mapping in ((c2, scene2, None), (ctx, scene, name)):
+        U = torch.zeros((H, 14), device=DEV)
+        c = torch.zeros(K, device=DEV)
+        mp.mppi_plan(cx, scn, x0, nom, K, H, pp["lam"], sig, U, c, M=2, seed=pp["seed"], mapping=mapping)
+        torch.cuda.synchronize()
+        res.append((U, c))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    scene2.close()
+    c2.close()
+    scene.close()
