@@ -552,6 +552,55 @@ __device__ __forceinline__ void pgs4(const float a[16], const float b[4], const 
     }
 }
 
+// The same sweeps on MM = 4 * contacts rows (A row-major with stride `stride`
+// in LDS).  Each row's sum over values the sweep has not reached is formed
+// first; every new f_c is then folded into the later rows' sums at once, so
+// the chain from one row to the next is one FMA, one FMA and a max.  Up to
+// 8 rows keep A in registers; beyond, its entries are re-read from LDS in a
+// fully unrolled body (independent loads the compiler can issue early).
+template <int MM>
+__device__ inline void pgs_rows(const float *A, int stride, const float *Bv, const float *Rv, const float *Dv,
+                                int n_pgs, float f[MM])
+{
+    constexpr bool in_regs = MM <= 8;
+    float a[in_regs ? MM * MM : 1];
+    float b[MM], ad[MM], dd[MM];
+#pragma unroll
+    for (int r = 0; r < MM; ++r) {
+        b[r] = Bv[r];
+        dd[r] = Dv[r];
+        ad[r] = A[r * stride + r] + Rv[r];
+        if constexpr (in_regs) {
+#pragma unroll
+            for (int c = 0; c < MM; c += 4) {
+                const float4 a4 = *reinterpret_cast<const float4 *>(A + r * stride + c);
+                a[r * MM + c] = a4.x; a[r * MM + c + 1] = a4.y; a[r * MM + c + 2] = a4.z; a[r * MM + c + 3] = a4.w;
+            }
+        }
+    }
+    auto Arc = [&](int r, int c) -> float {
+        if constexpr (in_regs) return a[r * MM + c];
+        else return A[r * stride + c];
+    };
+    for (int sweep = 0; sweep < n_pgs; ++sweep) {
+        if constexpr (!in_regs) asm volatile("" : "+v"(A));  // re-read A every sweep instead of holding it
+        float p[MM];
+#pragma unroll
+        for (int r = 0; r < MM; ++r) {
+            float acc = fmaf(ad[r], f[r], b[r]);
+#pragma unroll
+            for (int c = r + 1; c < MM; ++c) acc = fmaf(Arc(r, c), f[c], acc);
+            p[r] = acc;
+        }
+#pragma unroll
+        for (int r = 0; r < MM; ++r) {
+            f[r] = fmaxf(fmaf(-p[r], dd[r], f[r]), 0.f);
+#pragma unroll
+            for (int q = r + 1; q < MM; ++q) p[q] = fmaf(Arc(q, r), f[r], p[q]);
+        }
+    }
+}
+
 // One contact of the ball with a static body (table or box), the common case:
 // the whole solve in registers, identically on every lane.
 __device__ inline void ball_contact_solve(const DevModel &md, const LaneList &LL, V3 pb, V3 &vb, V3 &wb)
@@ -598,6 +647,7 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
                                           float &v, V3 &vb, V3 &wb)
 {
     constexpr int MR = 4 * NC;
+    static_assert(MR >= 16, "the specialised sweeps write up to 16 multipliers");
     float *E = tc.tl + TG_FIELDS + NC * CL_FIELDS + PK_FIELDS4;  // 16-byte aligned
     float *Gb = E + 20 * NC;
     float *A = Gb + 9 * NC * NC;
@@ -754,29 +804,25 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
         pgs4(a, b, rr, dd, md.n_pgs, f4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) f[r] = f4[r];
-    } else if constexpr (NC <= 4) {
-        // several contacts: multipliers in registers, rows of A read from LDS
-        // four at a time (independent of the sweep's dependency chain)
-        for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
+    } else if (nc == 2) {
+        float f8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        pgs_rows<8>(A, MR, Bv, Rv, Dv, md.n_pgs, f8);
 #pragma unroll
-            for (int r = 0; r < MR; ++r) {
-                if (r < m) {
-                    const float4 *ar = reinterpret_cast<const float4 *>(A + r * MR);
-                    float res = fmaf(Rv[r], f[r], Bv[r]);
+        for (int r = 0; r < 8; ++r) f[r] = f8[r];
+    } else if (nc == 3) {
+        float f12[12];
 #pragma unroll
-                    for (int t = 0; t < NC; ++t) {
-                        if (t < nc) {
-                            const float4 a4 = ar[t];
-                            res = fmaf(a4.x, f[4 * t], res);
-                            res = fmaf(a4.y, f[4 * t + 1], res);
-                            res = fmaf(a4.z, f[4 * t + 2], res);
-                            res = fmaf(a4.w, f[4 * t + 3], res);
-                        }
-                    }
-                    f[r] = fmaxf(f[r] - res * Dv[r], 0.f);
-                }
-            }
-        }
+        for (int r = 0; r < 12; ++r) f12[r] = 0.f;
+        pgs_rows<12>(A, MR, Bv, Rv, Dv, md.n_pgs, f12);
+#pragma unroll
+        for (int r = 0; r < 12; ++r) f[r] = f12[r];
+    } else if (nc == 4) {
+        float f16[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) f16[r] = 0.f;
+        pgs_rows<16>(A, MR, Bv, Rv, Dv, md.n_pgs, f16);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) f[r] = f16[r];
     } else {
         // up to MPPI_MAX_CONTACTS contacts: the multipliers live in the team's
         // LDS (every lane computes and writes the same values)
