@@ -346,7 +346,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0)
-    ap.add_argument("--mapping", default="auto", choices=["auto", "lane", "team", "wave"])
+    ap.add_argument("--mapping", default="auto", choices=["auto", "lane", "team", "wave", "split"])
     ap.add_argument("--packed-steps", type=int, default=2, help="steps of the packed-batch leg (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="trace length of the serving legs (0: skip)")
     ap.add_argument("--no-precision", dest="precision", action="store_false",
@@ -394,7 +394,7 @@ def main():
     used = tuned["chosen"] if tuned else args.mapping
     nc = 4 if int(sc["n_cmax"]) <= 4 else 8
     kernel_name = {"lane": f"rollout_kernel<{nc}>", "team": f"rollout_team_kernel<{nc}, 4>",
-                   "wave": f"rollout_team_kernel<{nc}, 1>"}[used]
+                   "wave": f"rollout_team_kernel<{nc}, 1>", "split": f"rollout_split_kernel<{nc}>"}[used]
 
     def plan():
         return mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"],

@@ -64,8 +64,11 @@ extern "C" {
 #define MPPI_TRAJ 16u           /* mppi_simulate: write every post-step state, not only the last */
 #define MPPI_MAP_LANE 32u       /* rollout mapping: one lane per sample (throughput at large K) */
 #define MPPI_MAP_TEAM 64u       /* rollout mapping: 16 lanes per sample, 4 samples per wave */
-#define MPPI_MAP_WAVE 256u      /* rollout mapping: one wave per sample (shortest steps at small K);
+#define MPPI_MAP_WAVE 256u      /* rollout mapping: one wave per sample (short steps at small K);
                                    results equal MPPI_MAP_TEAM's bit for bit */
+#define MPPI_MAP_SPLIT 2048u    /* rollout mapping: two waves per sample, dynamics and contact sweep /
+                                   cost concurrently (shortest steps at small K); results equal
+                                   MPPI_MAP_WAVE's bit for bit */
                                 /* none of the three: the mapping mppi_autotune measured for K's size
                                    class on this context, else chosen from K */
 #define MPPI_FP32_WEIGHTS 512u  /* mppi_plan, mppi_update: the weights of Eq. s_formula, their sums and the
@@ -271,7 +274,7 @@ typedef struct mppi_server_opts {
     uint64_t mem_budget;  /* device bytes for in-flight requests (0: 1 GiB) */
     int max_active;       /* requests iterating together (0: 256; at most 4096) */
     int max_pending;      /* queued requests; mppi_submit returns MPPI_E_BUSY beyond (0: 4096) */
-    unsigned flags;       /* MPPI_MAP_LANE, _TEAM or _WAVE: mapping of every launch (else per
+    unsigned flags;       /* MPPI_MAP_LANE, _TEAM, _WAVE or _SPLIT: mapping of every launch (else per
                              iteration by total sample count) */
 } mppi_server_opts;
 
@@ -338,12 +341,12 @@ int mppi_server_query(mppi_server *srv, mppi_server_info *info);
 
 /* Autotuner of the sample-to-lane mapping: times one rollout launch of K
  * samples over H control steps of `scene` (from state x0[MPPI_NX], mean 0,
- * sigma[14]; host arrays) with each mapping (lane, team, wave; best of two
+ * sigma[14]; host arrays) with each mapping (lane, team, wave, split; best of two
  * after a warm-up launch) and records the fastest for K's size class
  * (ceil(log2 K)) in the context.  Later calls on the context that pin no
  * mapping use the recorded one for that class.  *mapping (nullable)
- * receives the MPPI_MAP_* flag chosen, ms[3] (nullable) the times of the
- * lane, team and wave launches.  Synchronous; uses a private stream. */
+ * receives the MPPI_MAP_* flag chosen, ms[4] (nullable) the times of the
+ * lane, team, wave and split launches.  Synchronous; uses a private stream. */
 int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *sigma, int K, int H,
                   int *mapping, float *ms);
 

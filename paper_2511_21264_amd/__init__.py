@@ -22,8 +22,8 @@ MAX_BOXES = 16
 OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY, E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
 PENDING = 1
 DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ, MAP_LANE, MAP_TEAM, SUPERSEDE = 1, 2, 4, 8, 16, 32, 64, 128
-MAP_WAVE, FP32_WEIGHTS, GRAPH = 256, 512, 1024
-_MAPS = {None: 0, "auto": 0, "lane": MAP_LANE, "team": MAP_TEAM, "wave": MAP_WAVE}
+MAP_WAVE, FP32_WEIGHTS, GRAPH, MAP_SPLIT = 256, 512, 1024, 2048
+_MAPS = {None: 0, "auto": 0, "lane": MAP_LANE, "team": MAP_TEAM, "wave": MAP_WAVE, "split": MAP_SPLIT}
 
 
 class MppiError(RuntimeError):
@@ -488,16 +488,16 @@ class Server:
         return {k: getattr(i, k) for k, _ in i._fields_}
 
 
-_MAP_NAMES = {MAP_LANE: "lane", MAP_TEAM: "team", MAP_WAVE: "wave"}
+_MAP_NAMES = {MAP_LANE: "lane", MAP_TEAM: "team", MAP_WAVE: "wave", MAP_SPLIT: "split"}
 
 
 def mppi_autotune(ctx, scene, x0, sigma, K, H):
-    """Time the lane, team and wave mappings on one rollout launch; the
+    """Time the lane, team, wave and split mappings on one rollout launch; the
     context remembers the fastest for K's size class.  Returns (name, ms dict)."""
     x0 = np.ascontiguousarray(x0, dtype=np.float32)
     sigma = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float32), (14,)))
     m = C.c_int(0)
-    ms = (C.c_float * 3)()
+    ms = (C.c_float * 4)()
     _check(lib().mppi_autotune(ctx._h, scene._h, x0.ctypes.data, sigma.ctypes.data, int(K), int(H), C.byref(m),
                                ms))
-    return _MAP_NAMES[m.value], {"lane": ms[0], "team": ms[1], "wave": ms[2]}
+    return _MAP_NAMES[m.value], {"lane": ms[0], "team": ms[1], "wave": ms[2], "split": ms[3]}

@@ -224,6 +224,7 @@ int mapping_of(unsigned flags)
     if (flags & MPPI_MAP_LANE) return MAP_LANE;
     if (flags & MPPI_MAP_TEAM) return MAP_TEAM;
     if (flags & MPPI_MAP_WAVE) return MAP_WAVE;
+    if (flags & MPPI_MAP_SPLIT) return MAP_SPLIT;
     return MAP_AUTO;
 }
 
@@ -890,11 +891,11 @@ int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const
     ra.H = H;
     ra.costs = (float *)dcost;
     ra.dist = (float *)ddist;
-    const int maps[3] = {MAP_LANE, MAP_TEAM, MAP_WAVE};
-    const unsigned flag_of[3] = {MPPI_MAP_LANE, MPPI_MAP_TEAM, MPPI_MAP_WAVE};
+    const int maps[4] = {MAP_LANE, MAP_TEAM, MAP_WAVE, MAP_SPLIT};
+    const unsigned flag_of[4] = {MPPI_MAP_LANE, MPPI_MAP_TEAM, MPPI_MAP_WAVE, MPPI_MAP_SPLIT};
     float best = 0.f;
     int bi = 0;
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < 4; ++i) {
         float t = 0.f;
         for (int rep = 0; rep < 3; ++rep) {
             ra.m = rep;

@@ -81,7 +81,7 @@ struct FinishArgs {
 };
 
 // sample-to-lane mapping of the rollout
-constexpr int MAP_AUTO = 0, MAP_LANE = 1, MAP_TEAM = 2, MAP_WAVE = 3;
+constexpr int MAP_AUTO = 0, MAP_LANE = 1, MAP_TEAM = 2, MAP_WAVE = 3, MAP_SPLIT = 4;
 int pick_mapping(int K, int requested);
 void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping = MAP_AUTO);
 int samples_per_block(int mapping);

@@ -276,9 +276,193 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
     }
 }
 
+// Split mapping: two waves per sample.  Wave 0 (dynamics) owns the state and
+// runs the kinematics, inertia, factorisation, bias forces and free
+// velocities, then the contact solve and the integration; wave 1 (geometry)
+// runs, concurrently with wave 0's dynamics, the kinematics again, the geom
+// AABBs and the contact sweep, and during wave 0's contact solve the cost of
+// the previous control step.  Two workgroup barriers per substep hand the
+// positions to wave 1 (B1) and the contact list to wave 0 (B2); both waves run
+// the same loop nest, so they meet every barrier the same number of times.
+// Every value equals the wave-per-sample mapping's bit for bit.
+constexpr int SPLIT_SA = 24;  // state handoff: q[14], ball centre[3], contact count, finite flag
+template <int NC>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) rollout_split_kernel(RolloutArgs a0, const RolloutArgs *tab, const int *blk,
+                                                             int m)
+{
+    extern __shared__ float lds[];
+    RolloutArgs a;
+    int bid;
+    block_scene(a0, tab, blk, m, a, bid);
+    const int wave = threadIdx.x >> 6;
+    const bool geo = wave == 1;
+    const int lane = threadIdx.x & 63;
+    const int row = lane >> 4;
+    float *blockD = lds + HD_FIELDS, *blockG = blockD + team_lds_floats(NC);
+    float *SA = blockG + team_lds_floats(NC);
+    TeamCtx tc;
+    tc.lane = lane;
+    tc.t = lane & 15;
+    tc.arm = tc.t >> 3;
+    tc.jt = tc.t & 7;
+    tc.seg = tc.arm * 8;
+    tc.joint = tc.jt < 7;
+    tc.li = lane;
+    tc.gshift = 0;
+    tc.count = geo && row == 0;
+    tc.hd = lds;
+    tc.tl = geo ? blockG : blockD;
+    tc.LL = LaneList{blockG + TG_FIELDS, 0, 1};  // the contact list lives in the geometry wave's block
+    tc.pk = LanePark{tc.tl + TG_FIELDS + NC * CL_FIELDS, 0, 1};
+    const int j = bid;
+    if (j >= a.K) return;  // uniform over the workgroup
+    const DevModel &md0 = *a.md;
+    const bool skip = a.diverged && *a.diverged;
+    if (skip) {
+        if (geo && lane == 0) a.costs[j] = INFINITY;
+        return;  // uniform over the launch
+    }
+    stage_header(lds, md0, threadIdx.x, 128);
+    __syncthreads();
+    const int jj = tc.joint ? tc.jt : 6;
+    const int d = 7 * tc.arm + jj;
+    JointConst jc;
+    jc.ax = md0.axes[jj];
+    jc.len = tc.joint ? md0.link_len[jj] : 0.f;
+    jc.m = md0.m[tc.arm][jj];
+    jc.ix = md0.Ix[tc.arm][jj];
+    jc.iz = md0.Iz[tc.arm][jj];
+    jc.base = v3(md0.base_pos[tc.arm][0], md0.base_pos[tc.arm][1], md0.base_pos[tc.arm][2]);
+    jc.bc = md0.base_cs[tc.arm][0];
+    jc.bs = md0.base_cs[tc.arm][1];
+    const float *x0 = a.x0 + (a.x0_shared ? 0 : (long)j * NX);
+    TeamState S;
+    S.q = x0[XQ + d];
+    S.qd = x0[XQD + d];
+    S.qdes = x0[XQDES + d];
+    S.pb = v3(x0[XPB], x0[XPB + 1], x0[XPB + 2]);
+    S.vb = v3(x0[XVB], x0[XVB + 1], x0[XVB + 2]);
+    S.wb = v3(x0[XWB], x0[XWB + 1], x0[XWB + 2]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S.quat[i] = x0[XQUAT + i];
+    const int nsub = a.n_sub > 0 ? a.n_sub : md0.n_sub;
+    uint32_t hist = 0u;
+    float *dist = a.dist + j;
+    CostAcc acc;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
+    StepCounters cnt = {0, 0, 0, 0};
+    float u1 = 0.f, u2 = 0.f;  // controls of the previous two steps (geometry wave's cost)
+    for (int k = 0; k < a.H; ++k) {
+        const DevModel &md = model(a.md);
+        float u = 0.f;
+        if (tc.joint) {
+            if (a.U) {
+                u = a.U[((long)j * a.H + k) * NU + d];
+            } else {
+                const float z = normal_joint(a.key0, a.key1, (uint32_t)j, (uint32_t)k, (uint32_t)a.m, d);
+                const float sg = a.sigma[(a.sigma_per_step ? k * NU : 0) + d];
+                u = clampf(fmaf(sg, z, a.nu[k * NU + d]), -md.u_max, md.u_max);
+            }
+        }
+        for (int s = 0; s < nsub; ++s) {
+            JointKin kk;
+            float v = 0.f;
+            V3 vb, wb;
+            __syncthreads();  // B1: positions of this substep are in SA
+            if (geo) {
+                if (k > 0 || s > 0) {
+                    if (tc.joint) S.q = SA[d];
+                    S.pb = v3(SA[14], SA[15], SA[16]);
+                }
+                team_fk(jc, S.q, tc.jt, kk);
+                const int nc = team_contacts<64>(model(a.md), tc, kk, S.pb, cnt);
+                if (lane == 0) SA[17] = __int_as_float(nc);
+            } else {
+                team_dynamics(model(a.md), jc, tc, S, u, kk, v, vb, wb);
+            }
+            __syncthreads();  // B2: the contact list and its count are in LDS
+            if (!geo) {
+                const int nc = __float_as_int(SA[17]);
+                team_finish<NC>(model(a.md), tc, S, kk, nc, v, vb, wb);
+                if (tc.joint) SA[d] = S.q;
+                if (lane == 0) { SA[14] = S.pb.x; SA[15] = S.pb.y; SA[16] = S.pb.z; }
+                if (s == nsub - 1 && a.xout && a.traj && row == 0) {
+                    float *o = a.xout + ((long)j * a.H + k) * NX;
+                    if (tc.joint) {
+                        o[XQ + d] = S.q; o[XQD + d] = S.qd; o[XQDES + d] = S.qdes;
+                    } else if (tc.arm == 0) {
+                        o[XPB] = S.pb.x; o[XPB + 1] = S.pb.y; o[XPB + 2] = S.pb.z;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) o[XQUAT + i] = S.quat[i];
+                        o[XVB] = S.vb.x; o[XVB + 1] = S.vb.y; o[XVB + 2] = S.vb.z;
+                        o[XWB] = S.wb.x; o[XWB + 1] = S.wb.y; o[XWB + 2] = S.wb.z;
+                    }
+                }
+            } else if (s == 0 && k > 0) {
+                // cost of step k - 1 at its post-step state (this substep's positions)
+                team_stage_cost(model(a.md), jc, tc, S, u1, u2, k - 1 == 0, hist, dist, a.K, acc, cnt);
+            }
+        }
+        u2 = u1;
+        u1 = u;
+    }
+    // the final state: dynamics wave publishes it with its finiteness
+    const DevModel &md = model(a.md);
+    if (!geo) {
+        float bad = (isfinite(S.q) && isfinite(S.qd) && isfinite(S.qdes)) ? 0.f : 1.f;
+        bad += (isfinite(S.pb.x) && isfinite(S.pb.y) && isfinite(S.pb.z) && isfinite(S.vb.x) && isfinite(S.vb.y) &&
+                isfinite(S.vb.z) && isfinite(S.wb.x) && isfinite(S.wb.y) && isfinite(S.wb.z) &&
+                isfinite(S.quat[0]) && isfinite(S.quat[1]) && isfinite(S.quat[2]) && isfinite(S.quat[3]))
+                   ? 0.f
+                   : 1.f;
+        bad = team_sum(bad);
+        if (lane == 0) SA[18] = bad;
+        if (a.xout && !a.traj && row == 0) {
+            float *o = a.xout + (long)j * NX;
+            if (tc.joint) {
+                o[XQ + d] = S.q; o[XQD + d] = S.qd; o[XQDES + d] = S.qdes;
+            } else if (tc.arm == 0) {
+                o[XPB] = S.pb.x; o[XPB + 1] = S.pb.y; o[XPB + 2] = S.pb.z;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[XQUAT + i] = S.quat[i];
+                o[XVB] = S.vb.x; o[XVB + 1] = S.vb.y; o[XVB + 2] = S.vb.z;
+                o[XWB] = S.wb.x; o[XWB + 1] = S.wb.y; o[XWB + 2] = S.wb.z;
+            }
+        }
+    }
+    __syncthreads();  // final positions and the finiteness flag are in SA
+    if (!geo) return;
+    if (tc.joint) S.q = SA[d];
+    S.pb = v3(SA[14], SA[15], SA[16]);
+    team_stage_cost(md, jc, tc, S, u1, u2, a.H - 1 == 0, hist, dist, a.K, acc, cnt);
+    float t[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) t[i] = team_sum(acc.t[i]);
+    const float c = md.w_goal * t[0] + md.w_eo * t[1] + md.w_l * t[2] + md.w_yz * t[3] + md.w_s * t[4] +
+                    md.w_c * (t[5] + t[6]);
+    const float bad = SA[18];
+    const bool finite = isfinite(c) && !(bad > 0.f) && bad == bad;
+    const float np = wave_sum((float)cnt.np_tests), nbx = wave_sum((float)cnt.box_tests);
+    if (lane == 0) {
+        a.costs[j] = finite ? c : INFINITY;
+        if (a.terms) {
+#pragma unroll
+            for (int i = 0; i < 7; ++i) a.terms[(long)j * 7 + i] = t[i];
+        }
+        if (a.counters) {
+            a.counters[4 * j + 0] = cnt.contacts;
+            a.counters[4 * j + 1] = (int)np;
+            a.counters[4 * j + 2] = (int)nbx;
+            a.counters[4 * j + 3] = cnt.overflow;
+        }
+    }
+}
+
 int pick_mapping(int K, int requested)
 {
-    if (requested == MAP_LANE || requested == MAP_TEAM || requested == MAP_WAVE) return requested;
+    if (requested == MAP_LANE || requested == MAP_TEAM || requested == MAP_WAVE || requested == MAP_SPLIT)
+        return requested;
     // the chip holds 1024 SIMDs: up to ~2 samples per SIMD a wave per sample
     // gives the shortest steps; up to tens of thousands a 16-lane team per
     // sample; beyond that one lane per sample has the highest throughput
@@ -288,7 +472,7 @@ int pick_mapping(int K, int requested)
 
 int samples_per_block(int mapping)
 {
-    return mapping == MAP_TEAM ? TEAMS_PER_WAVE : mapping == MAP_WAVE ? 1 : 64;
+    return mapping == MAP_TEAM ? TEAMS_PER_WAVE : (mapping == MAP_WAVE || mapping == MAP_SPLIT) ? 1 : 64;
 }
 
 static void launch_rollout_impl(const RolloutArgs &a, const RolloutArgs *tab, const int *blk, int nblk, int ncmax,
@@ -296,6 +480,14 @@ static void launch_rollout_impl(const RolloutArgs &a, const RolloutArgs *tab, co
 {
     const int nc = ncmax <= 4 ? 4 : 8;
     const dim3 grid(nblk), block(64);
+    if (map == MAP_SPLIT) {
+        const size_t lds = (size_t)(HD_FIELDS + 2 * team_lds_floats(nc) + SPLIT_SA) * sizeof(float);
+        if (nc == 4)
+            hipLaunchKernelGGL(rollout_split_kernel<4>, grid, dim3(128), lds, s, a, tab, blk, m);
+        else
+            hipLaunchKernelGGL(rollout_split_kernel<8>, grid, dim3(128), lds, s, a, tab, blk, m);
+        return;
+    }
     if (map == MAP_TEAM || map == MAP_WAVE) {
         const int tpw = map == MAP_TEAM ? TEAMS_PER_WAVE : 1;
         const size_t lds = (size_t)(HD_FIELDS + tpw * team_lds_floats(nc)) * sizeof(float);

@@ -429,6 +429,74 @@ __device__ inline void contact_solve(const DevModel &md, const ArmKin kin[2], co
     }
 }
 
+// Projected Gauss-Seidel on four rows (one contact), f = 0 at the start:
+// row r takes res = b_r + R_r f_r + sum_c A_rc f_c, f_r <- max(f_r - res / (A_rr + R_r), 0).
+// The sums are regrouped so that each row's partial sum over values already
+// known is formed off the dependency chain: only one FMA per row waits for
+// the row before it (a single wave per SIMD runs latency-bound).
+__device__ __forceinline__ void pgs4(const float a[16], const float b[4], const float rr[4], const float dd[4],
+                                     int n_pgs, float f[4])
+{
+    float ad[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ad[r] = a[5 * r] + rr[r];  // A_rr + R_r multiplies f_r itself
+    for (int sweep = 0; sweep < n_pgs; ++sweep) {
+        // contributions of the values this sweep has not touched yet
+        const float p0 = fmaf(a[3], f[3], fmaf(a[2], f[2], fmaf(a[1], f[1], fmaf(ad[0], f[0], b[0]))));
+        const float p1 = fmaf(a[7], f[3], fmaf(a[6], f[2], fmaf(ad[1], f[1], b[1])));
+        const float p2 = fmaf(a[11], f[3], fmaf(ad[2], f[2], b[2]));
+        const float p3 = fmaf(ad[3], f[3], b[3]);
+        f[0] = fmaxf(fmaf(-p0, dd[0], f[0]), 0.f);
+        const float q1 = fmaf(a[4], f[0], p1);
+        const float q2 = fmaf(a[8], f[0], p2);
+        const float q3 = fmaf(a[12], f[0], p3);
+        f[1] = fmaxf(fmaf(-q1, dd[1], f[1]), 0.f);
+        const float s2 = fmaf(a[9], f[1], q2);
+        const float s3 = fmaf(a[13], f[1], q3);
+        f[2] = fmaxf(fmaf(-s2, dd[2], f[2]), 0.f);
+        const float t3 = fmaf(a[14], f[2], s3);
+        f[3] = fmaxf(fmaf(-t3, dd[3], f[3]), 0.f);
+    }
+}
+
+// One contact of the ball with a static body (table or box), the common case:
+// the whole solve in registers (in the team mappings identically on every
+// lane of the team).
+__device__ inline void ball_contact_solve(const DevModel &md, const LaneList &LL, V3 pb, V3 &vb, V3 &wb)
+{
+    const V3 n = v3(LL.at(0, 3), LL.at(0, 4), LL.at(0, 5));
+    const V3 r = v3(LL.at(0, 6), LL.at(0, 7), LL.at(0, 8)) - pb;
+    const float phi = LL.at(0, 2);
+    V3 t1, t2;
+    tangents(n, t1, t2);
+    V3 e[4], ge[4];
+    float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    ball_block(md, r, r, G);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        e[q] = fma3((q & 1) ? -md.mu : md.mu, q < 2 ? t1 : t2, n);
+        ge[q] = mul9(G, e[q]);
+    }
+    const V3 bfree = vb + cross(wb, r);
+    const float bias = md.kappa_h * (phi < 0.f ? -phi : 0.f);
+    float a[16], b[4], rr[4], dd[4], f[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[4 * q + c] = dot(e[q], ge[c]);
+        rr[q] = md.eps_r * a[5 * q];
+        dd[q] = 1.0f / (a[5 * q] + rr[q]);
+        b[q] = dot(e[q], bfree) - bias;
+        f[q] = 0.f;
+    }
+    pgs4(a, b, rr, dd, md.n_pgs, f);
+    V3 P = v3(0.f, 0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P = fma3(f[q], e[q], P);
+    vb = fma3(md.inv_ball_m, P, vb);
+    wb = fma3(md.inv_ball_I, cross(r, P), wb);
+}
+
 template <int NC>
 __device__ inline void substep(const DevModel &md, float x[NX], const float u[NU], const LaneList &LL,
                                const LanePark &pk, StepCounters &cnt)
@@ -478,7 +546,11 @@ __device__ inline void substep(const DevModel &md, float x[NX], const float u[NU
     V3 wb = v3(x[XWB], x[XWB + 1], x[XWB + 2]);
 
     const int nc = collect_contacts(md, kin, pb, LL, cnt);
-    if (nc > 0) contact_solve<NC>(md, kin, pk, pb, LL, nc, v, vb, wb);
+    if (nc == 1 && __float_as_int(LL.at(0, 0)) == G_BALL &&
+        (__float_as_int(LL.at(0, 1)) == G_TABLE || __float_as_int(LL.at(0, 1)) >= G_BOX))
+        ball_contact_solve(md, LL, pb, vb, wb);
+    else if (nc > 0)
+        contact_solve<NC>(md, kin, pk, pb, LL, nc, v, vb, wb);
 
 #pragma unroll
     for (int i = 0; i < 14; ++i) {

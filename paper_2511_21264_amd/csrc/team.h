@@ -149,6 +149,15 @@ __device__ __forceinline__ float team_sum(float x)
     return row_bcast<15>(x);
 }
 
+// LDS writes of this wave become visible to its other lanes; no barrier,
+// so it may sit under control flow that differs between the teams of a wave
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ __forceinline__ float wave_sum(float x)
 {
     x = team_sum(x);
@@ -464,7 +473,7 @@ __device__ inline int team_collect(const DevModel &md, float *tl, const float *h
         if (ov) cand[ncand + __popcll(gm & ((1ull << li) - 1ull))] = p;
         ncand += __popcll(gm);
     }
-    __syncthreads();
+    wave_lds_sync();
     int n = 0;
     for (int c0 = 0;; c0 += G) {
         const bool live = c0 < ncand && n < md.n_cmax;
@@ -511,46 +520,7 @@ struct TeamCtx {
     LanePark pk;
 };
 
-// LDS writes of this wave become visible to its other lanes; no barrier,
-// so it may sit under control flow that differs between the teams of a wave
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 __device__ __forceinline__ V3 team_sum3(V3 x) { return v3(team_sum(x.x), team_sum(x.y), team_sum(x.z)); }
-
-// Projected Gauss-Seidel on four rows (one contact), f = 0 at the start:
-// row r takes res = b_r + R_r f_r + sum_c A_rc f_c, f_r <- max(f_r - res / (A_rr + R_r), 0).
-// The sums are regrouped so that each row's partial sum over values already
-// known is formed off the dependency chain: only one FMA per row waits for
-// the row before it (a single wave per SIMD runs latency-bound).
-__device__ __forceinline__ void pgs4(const float a[16], const float b[4], const float rr[4], const float dd[4],
-                                     int n_pgs, float f[4])
-{
-    float ad[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) ad[r] = a[5 * r] + rr[r];  // A_rr + R_r multiplies f_r itself
-    for (int sweep = 0; sweep < n_pgs; ++sweep) {
-        // contributions of the values this sweep has not touched yet
-        const float p0 = fmaf(a[3], f[3], fmaf(a[2], f[2], fmaf(a[1], f[1], fmaf(ad[0], f[0], b[0]))));
-        const float p1 = fmaf(a[7], f[3], fmaf(a[6], f[2], fmaf(ad[1], f[1], b[1])));
-        const float p2 = fmaf(a[11], f[3], fmaf(ad[2], f[2], b[2]));
-        const float p3 = fmaf(ad[3], f[3], b[3]);
-        f[0] = fmaxf(fmaf(-p0, dd[0], f[0]), 0.f);
-        const float q1 = fmaf(a[4], f[0], p1);
-        const float q2 = fmaf(a[8], f[0], p2);
-        const float q3 = fmaf(a[12], f[0], p3);
-        f[1] = fmaxf(fmaf(-q1, dd[1], f[1]), 0.f);
-        const float s2 = fmaf(a[9], f[1], q2);
-        const float s3 = fmaf(a[13], f[1], q3);
-        f[2] = fmaxf(fmaf(-s2, dd[2], f[2]), 0.f);
-        const float t3 = fmaf(a[14], f[2], s3);
-        f[3] = fmaxf(fmaf(-t3, dd[3], f[3]), 0.f);
-    }
-}
 
 // The same sweeps on MM = 4 * contacts rows (A row-major with stride `stride`
 // in LDS).  Each row's sum over values the sweep has not reached is formed
@@ -599,43 +569,6 @@ __device__ inline void pgs_rows(const float *A, int stride, const float *Bv, con
             for (int q = r + 1; q < MM; ++q) p[q] = fmaf(Arc(q, r), f[r], p[q]);
         }
     }
-}
-
-// One contact of the ball with a static body (table or box), the common case:
-// the whole solve in registers, identically on every lane.
-__device__ inline void ball_contact_solve(const DevModel &md, const LaneList &LL, V3 pb, V3 &vb, V3 &wb)
-{
-    const V3 n = v3(LL.at(0, 3), LL.at(0, 4), LL.at(0, 5));
-    const V3 r = v3(LL.at(0, 6), LL.at(0, 7), LL.at(0, 8)) - pb;
-    const float phi = LL.at(0, 2);
-    V3 t1, t2;
-    tangents(n, t1, t2);
-    V3 e[4], ge[4];
-    float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    ball_block(md, r, r, G);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        e[q] = fma3((q & 1) ? -md.mu : md.mu, q < 2 ? t1 : t2, n);
-        ge[q] = mul9(G, e[q]);
-    }
-    const V3 bfree = vb + cross(wb, r);
-    const float bias = md.kappa_h * (phi < 0.f ? -phi : 0.f);
-    float a[16], b[4], rr[4], dd[4], f[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) a[4 * q + c] = dot(e[q], ge[c]);
-        rr[q] = md.eps_r * a[5 * q];
-        dd[q] = 1.0f / (a[5 * q] + rr[q]);
-        b[q] = dot(e[q], bfree) - bias;
-        f[q] = 0.f;
-    }
-    pgs4(a, b, rr, dd, md.n_pgs, f);
-    V3 P = v3(0.f, 0.f, 0.f);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) P = fma3(f[q], e[q], P);
-    vb = fma3(md.inv_ball_m, P, vb);
-    wb = fma3(md.inv_ball_I, cross(r, P), wb);
 }
 
 // Contact solve of one team (nc >= 1 contacts in the team's list, nc uniform
@@ -885,14 +818,16 @@ __device__ __forceinline__ float normal_joint(uint32_t key0, uint32_t key1, uint
 }
 
 
-template <int NC, int G>
-__device__ inline void team_substep(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
-                                    float u, StepCounters &cnt)
+// Dynamics half of a substep (before contacts): PD target, kinematics,
+// joint-space inertia and its factor (parked for the contact path), bias
+// forces and the free velocities (v of this lane's joint; ball vb with
+// gravity; wb).  k receives this lane's kinematics at the current positions.
+__device__ inline void team_dynamics(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
+                                     float u, JointKin &k, float &v, V3 &vb, V3 &wb)
 {
     const float h = md.h;
     const int jt = tc.jt, seg = tc.seg;
     S.qdes = fmaf(h, u, S.qdes);
-    JointKin k;
     team_fk(jc, S.q, jt, k);
     float row[NJ];
     team_crba(md, jc, k, jt, seg, row);
@@ -908,12 +843,10 @@ __device__ inline void team_substep(const DevModel &md, const JointConst &jc, co
         xs[i] = segb<i>(rhs, seg != 0);
     });
     chol7_solve(Lp, xs);
-    float v = S.qd + pick7(xs, jt);
-    const V3 pb = S.pb;
-    V3 vb = v3(S.vb.x, S.vb.y, S.vb.z - h * md.g);
-    V3 wb = S.wb;
-    // publish geometry and the contact path's factor and axes
-    team_publish_geom(tc.tl, k, pb, tc.arm, jt);
+    v = S.qd + pick7(xs, jt);
+    vb = v3(S.vb.x, S.vb.y, S.vb.z - h * md.g);
+    wb = S.wb;
+    // park the contact path's factor and axes
     if (tc.joint) {
         const int f = PK_A + 3 * (7 * tc.arm + jt);
         tc.pk.at(f) = k.a.x;
@@ -925,15 +858,34 @@ __device__ inline void team_substep(const DevModel &md, const JointConst &jc, co
             for (int e = 0; e < 28; ++e) tc.pk.at(PK_L + 28 * tc.arm + e) = Lp[e];
         }
     }
-    __syncthreads();
+}
+
+// Geometry half: publish the kinematics and ball centre, the geom AABBs, and
+// sweep the candidate pairs into the contact list (tc.LL); returns the count.
+template <int G>
+__device__ inline int team_contacts(const DevModel &md, const TeamCtx &tc, const JointKin &k, V3 pb,
+                                    StepCounters &cnt)
+{
+    team_publish_geom(tc.tl, k, pb, tc.arm, tc.jt);
+    wave_lds_sync();
     team_publish_aabb(tc.tl, tc.hd, tc.t);
-    __syncthreads();
+    wave_lds_sync();
     const int nc = team_collect<G>(md, tc.tl, tc.hd, tc.LL, tc.li, tc.gshift, cnt);
     if (tc.t == 0) {
         cnt.contacts += nc;
         if (nc >= md.n_cmax) ++cnt.overflow;
     }
-    __syncthreads();
+    wave_lds_sync();
+    return nc;
+}
+
+// Contact solve and semi-implicit Euler: the end of a substep.
+template <int NC>
+__device__ inline void team_finish(const DevModel &md, const TeamCtx &tc, TeamState &S, const JointKin &k, int nc,
+                                   float v, V3 vb, V3 wb)
+{
+    const float h = md.h;
+    const V3 pb = S.pb;
     if (nc == 1 && __float_as_int(tc.LL.at(0, 0)) == G_BALL &&
         (__float_as_int(tc.LL.at(0, 1)) == G_TABLE || __float_as_int(tc.LL.at(0, 1)) >= G_BOX))
         ball_contact_solve(md, tc.LL, pb, vb, wb);
@@ -968,6 +920,19 @@ __device__ inline void team_substep(const DevModel &md, const JointConst &jc, co
     S.quat[3] = nv.z * inv;
 }
 
+// One physics substep of a team: dynamics, contacts, solve, integration.
+template <int NC, int G>
+__device__ inline void team_substep(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
+                                    float u, StepCounters &cnt)
+{
+    JointKin k;
+    float v;
+    V3 vb, wb;
+    team_dynamics(md, jc, tc, S, u, k, v, vb, wb);
+    const int nc = team_contacts<G>(md, tc, k, S.pb, cnt);
+    team_finish<NC>(md, tc, S, k, nc, v, vb, wb);
+}
+
 // per-control-step cost at the post-step state; lane 0 accumulates the stage
 // terms, joint lanes the smoothness, every lane its share of the cost pairs
 __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc, const TeamCtx &tc,
@@ -977,9 +942,9 @@ __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc,
     JointKin k;
     team_fk(jc, S.q, tc.jt, k);
     team_publish_geom(tc.tl, k, S.pb, tc.arm, tc.jt);
-    __syncthreads();
+    wave_lds_sync();
     team_publish_aabb(tc.tl, tc.hd, tc.t);
-    __syncthreads();
+    wave_lds_sync();
     const float *tl = tc.tl;
     if (tc.t == 0) {
         const V3 p1 = v3(tl[TG_PTS + 21], tl[TG_PTS + 22], tl[TG_PTS + 23]);

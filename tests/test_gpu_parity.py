@@ -152,7 +152,7 @@ def _group_close(got, want, rtol):
         assert err <= rtol * scale, (a, b, err, scale)
 
 
-@pytest.mark.parametrize("mapping", ["lane", "team", "wave"])
+@pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split"])
 @pytest.mark.parametrize("cfg,kind", [(1, "random"), (2, "random"), (3, "random"), (1, "contact"), (2, "contact")])
 def test_one_substep_and_one_step(mp, ctx, oracle_mod, cfg, kind, mapping):
     sc = W.make_scene(cfg)
@@ -180,7 +180,7 @@ def test_one_substep_and_one_step(mp, ctx, oracle_mod, cfg, kind, mapping):
     scene.close()
 
 
-@pytest.mark.parametrize("mapping", ["lane", "team", "wave"])
+@pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split"])
 def test_contact_free_rollout_20_steps(mp, ctx, oracle_mod, mapping):
     sc = W.make_scene(1)
     scene = mp.Scene(ctx, sc)
@@ -255,7 +255,7 @@ def test_update_all_nonfinite_diverges(mp, ctx):
 
 
 # ---------------------------------------------------------------- plan
-@pytest.mark.parametrize("mapping", ["lane", "team", "wave"])
+@pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split"])
 def test_plan_equals_its_stages(mp, ctx, mapping):
     """mppi_plan = M x (sample -> simulate -> update) through the single-stage calls."""
     sc = W.make_scene(1)
@@ -290,7 +290,7 @@ def test_plan_equals_its_stages(mp, ctx, mapping):
     scene.close()
 
 
-@pytest.mark.parametrize("mapping", ["lane", "team", "wave"])
+@pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split"])
 def test_plan_c1_against_oracle(mp, ctx, oracle_mod, mapping):
     """End-to-end plan at the small workload (K=64, H=20, 5 iterations).  The
     ball rests on the table, so every rollout is in contact; the oracle's
@@ -387,7 +387,7 @@ def _batch_items(mp, ctx, n=5):
     return items
 
 
-@pytest.mark.parametrize("mapping", ["lane", "team", "wave"])
+@pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split"])
 def test_batch_equals_each_plan_alone(mp, ctx, mapping):
     items = _batch_items(mp, ctx)
     sts = mp.mppi_plan_batch(ctx, items, mapping=mapping)
@@ -449,35 +449,38 @@ def test_batch_host_pointers_and_divergence(mp, ctx):
         it["scene"].close()
 
 
-def test_team_and_wave_mappings_bit_identical(mp, ctx):
-    """One wave per sample splits only the contact sweep across its rows:
-    costs, cost terms and final states equal the four-teams-per-wave form bit
-    for bit, on contact-rich rollouts of the obstacle workload."""
+def test_team_wave_split_mappings_bit_identical(mp, ctx):
+    """One wave per sample splits only the contact sweep across its rows; two
+    waves per sample run the dynamics and the contact sweep / cost
+    concurrently: costs, cost terms and states equal the four-teams-per-wave
+    form bit for bit, on contact-rich rollouts of the obstacle workload."""
     sc = W.make_scene(3)
     scene = mp.Scene(ctx, sc)
     n, H = 23, 40
     X0 = T(_contact_states(sc, n, 77))
     U = T(np.random.default_rng(10).uniform(-1.5, 1.5, (n, H, 14)))
     out = {}
-    for mapping in ("team", "wave"):
+    for mapping in ("team", "wave", "split"):
         c = torch.zeros(n, device=DEV)
         tm = torch.zeros((n, 7), device=DEV)
         xo = torch.zeros((n, H, 55), device=DEV)
         mp.mppi_simulate(ctx, scene, X0, U, costs=c, terms=tm, X_out=xo, traj=True, mapping=mapping)
         torch.cuda.synchronize()
         out[mapping] = (c.cpu().numpy(), tm.cpu().numpy(), xo.cpu().numpy())
-    for a, b in zip(out["team"], out["wave"]):
-        assert np.array_equal(a, b)
+    for other in ("wave", "split"):
+        for a, b in zip(out["team"], out[other]):
+            assert np.array_equal(a, b), other
     pp = W.plan_params(2, K=37, H=12, M=3)
     res = {}
-    for mapping in ("team", "wave"):
+    for mapping in ("team", "wave", "split"):
         Un = torch.zeros((12, 14), device=DEV)
         cc = torch.zeros(37, device=DEV)
         st = mp.mppi_plan(ctx, scene, T(W.initial_state(sc)), torch.zeros((12, 14), device=DEV), 37, 12, pp["lam"],
                           T(pp["sigma"]), Un, cc, M=3, seed=pp["seed"], mapping=mapping)
         res[mapping] = (Un.cpu().numpy(), cc.cpu().numpy(), st["contacts"], st["np_tests"])
-    assert np.array_equal(res["team"][0], res["wave"][0]) and np.array_equal(res["team"][1], res["wave"][1])
-    assert res["team"][2] == res["wave"][2]
+    for other in ("wave", "split"):
+        assert np.array_equal(res["team"][0], res[other][0]) and np.array_equal(res["team"][1], res[other][1])
+        assert res["team"][2] == res[other][2] and res["team"][3] == res[other][3]
     scene.close()
 
 
@@ -567,7 +570,7 @@ def test_autotune_records_the_mapping_auto_uses(mp, ctx):
     K, H = 600, 8
     pp = W.plan_params(2, K=K, H=H, M=2)
     name, ms = mp.mppi_autotune(c2, scene2, W.initial_state(sc), pp["sigma"], K, H)
-    assert name in ("lane", "team", "wave") and all(v > 0 for v in ms.values())
+    assert name in ("lane", "team", "wave", "split") and all(v > 0 for v in ms.values())
     assert ms[name] == min(ms.values())
     x0, nom, sig = T(W.initial_state(sc)), torch.zeros((H, 14), device=DEV), T(pp["sigma"])
     res = []

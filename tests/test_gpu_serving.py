@@ -55,7 +55,7 @@ def _items(mp, ctx, shapes, base=0):
     return out
 
 
-@pytest.mark.parametrize("mapping", ["team", "lane", "wave"])
+@pytest.mark.parametrize("mapping", ["team", "lane", "wave", "split"])
 def test_served_requests_equal_plans_alone(mp, ctx, mapping):
     items = _items(mp, ctx, [(70, 6, 3), (5, 4, 1), (130, 9, 4), (33, 3, 2), (64, 5, 6), (200, 7, 2)])
     srv = mp.Server(ctx, mapping=mapping)
