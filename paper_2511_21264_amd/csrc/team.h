@@ -522,53 +522,43 @@ struct TeamCtx {
 
 __device__ __forceinline__ V3 team_sum3(V3 x) { return v3(team_sum(x.x), team_sum(x.y), team_sum(x.z)); }
 
-// The same sweeps on MM = 4 * contacts rows (A row-major with stride `stride`
-// in LDS).  Each row's sum over values the sweep has not reached is formed
-// first; every new f_c is then folded into the later rows' sums at once, so
-// the chain from one row to the next is one FMA, one FMA and a max.  Up to
-// 8 rows keep A in registers; beyond, its entries are re-read from LDS in a
-// fully unrolled body (independent loads the compiler can issue early).
-template <int MM>
-__device__ inline void pgs_rows(const float *A, int stride, const float *Bv, const float *Rv, const float *Dv,
-                                int n_pgs, float f[MM])
+// Gauss-Seidel over m <= 16 rows spread over the team's lanes: lane q keeps
+// row q of A + R and the residual of row q, res_q = b_q + R_q f_q + sum_c
+// A_qc f_c, current after every update.  Row r: lane r forms its new
+// multiplier, the change is broadcast from lane r (DPP) and every lane folds
+// it into its residual.  Five dependent instructions per row, whatever m.
+// On return f[r], r < m, holds the multipliers on every lane.
+__device__ inline void pgs_team(const float *A, int stride, const float *Bv, const float *Rv, const float *Dv, int m,
+                                int q, int n_pgs, float f[16])
 {
-    constexpr bool in_regs = MM <= 8;
-    float a[in_regs ? MM * MM : 1];
-    float b[MM], ad[MM], dd[MM];
+    const bool mine = q < m;
+    float arow[16];
 #pragma unroll
-    for (int r = 0; r < MM; ++r) {
-        b[r] = Bv[r];
-        dd[r] = Dv[r];
-        ad[r] = A[r * stride + r] + Rv[r];
-        if constexpr (in_regs) {
-#pragma unroll
-            for (int c = 0; c < MM; c += 4) {
-                const float4 a4 = *reinterpret_cast<const float4 *>(A + r * stride + c);
-                a[r * MM + c] = a4.x; a[r * MM + c + 1] = a4.y; a[r * MM + c + 2] = a4.z; a[r * MM + c + 3] = a4.w;
-            }
-        }
+    for (int c = 0; c < 16; c += 4) {
+        const float4 a4 = *reinterpret_cast<const float4 *>(A + q * stride + c);
+        arow[c] = a4.x; arow[c + 1] = a4.y; arow[c + 2] = a4.z; arow[c + 3] = a4.w;
     }
-    auto Arc = [&](int r, int c) -> float {
-        if constexpr (in_regs) return a[r * MM + c];
-        else return A[r * stride + c];
-    };
+    const float rq = mine ? Rv[q] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) arow[c] += c == q ? rq : 0.f;
+    float res = mine ? Bv[q] : 0.f;
+    const float d = mine ? Dv[q] : 0.f;
+    float fq = 0.f;
     for (int sweep = 0; sweep < n_pgs; ++sweep) {
-        if constexpr (!in_regs) asm volatile("" : "+v"(A));  // re-read A every sweep instead of holding it
-        float p[MM];
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-            float acc = fmaf(ad[r], f[r], b[r]);
-#pragma unroll
-            for (int c = r + 1; c < MM; ++c) acc = fmaf(Arc(r, c), f[c], acc);
-            p[r] = acc;
-        }
-#pragma unroll
-        for (int r = 0; r < MM; ++r) {
-            f[r] = fmaxf(fmaf(-p[r], dd[r], f[r]), 0.f);
-#pragma unroll
-            for (int q = r + 1; q < MM; ++q) p[q] = fmaf(Arc(q, r), f[r], p[q]);
-        }
+        static_for<16>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            if (r < m) {
+                const float fn = fmaxf(fmaf(-res, d, fq), 0.f);
+                const float delta = fn - fq;
+                fq = q == r ? fn : fq;
+                res = fmaf(arow[r], row_bcast<r>(delta), res);
+            }
+        });
     }
+    static_for<16>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        f[r] = r < m ? row_bcast<r>(fq) : 0.f;
+    });
 }
 
 // Contact solve of one team (nc >= 1 contacts in the team's list, nc uniform
@@ -580,7 +570,7 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
                                           float &v, V3 &vb, V3 &wb)
 {
     constexpr int MR = 4 * NC;
-    static_assert(MR >= 16, "the specialised sweeps write up to 16 multipliers");
+    static_assert(MR >= 16, "the lane-parallel sweeps read 16 rows of A");
     float *E = tc.tl + TG_FIELDS + NC * CL_FIELDS + PK_FIELDS4;  // 16-byte aligned
     float *Gb = E + 20 * NC;
     float *A = Gb + 9 * NC * NC;
@@ -737,23 +727,9 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
         pgs4(a, b, rr, dd, md.n_pgs, f4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) f[r] = f4[r];
-    } else if (nc == 2) {
-        float f8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        pgs_rows<8>(A, MR, Bv, Rv, Dv, md.n_pgs, f8);
-#pragma unroll
-        for (int r = 0; r < 8; ++r) f[r] = f8[r];
-    } else if (nc == 3) {
-        float f12[12];
-#pragma unroll
-        for (int r = 0; r < 12; ++r) f12[r] = 0.f;
-        pgs_rows<12>(A, MR, Bv, Rv, Dv, md.n_pgs, f12);
-#pragma unroll
-        for (int r = 0; r < 12; ++r) f[r] = f12[r];
-    } else if (nc == 4) {
+    } else if (nc <= 4) {
         float f16[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) f16[r] = 0.f;
-        pgs_rows<16>(A, MR, Bv, Rv, Dv, md.n_pgs, f16);
+        pgs_team(A, MR, Bv, Rv, Dv, m, tc.t, md.n_pgs, f16);
 #pragma unroll
         for (int r = 0; r < 16; ++r) f[r] = f16[r];
     } else {
