@@ -523,32 +523,21 @@ struct TeamCtx {
 __device__ __forceinline__ V3 team_sum3(V3 x) { return v3(team_sum(x.x), team_sum(x.y), team_sum(x.z)); }
 
 // Gauss-Seidel over m <= 16 rows spread over the team's lanes: lane q keeps
-// row q of A + R and the residual of row q, res_q = b_q + R_q f_q + sum_c
-// A_qc f_c, current after every update.  Row r: lane r forms its new
-// multiplier, the change is broadcast from lane r (DPP) and every lane folds
-// it into its residual.  Five dependent instructions per row, whatever m.
-// On return f[r], r < m, holds the multipliers on every lane.
-__device__ inline void pgs_team(const float *A, int stride, const float *Bv, const float *Rv, const float *Dv, int m,
-                                int q, int n_pgs, float f[16])
+// row q of A + R (arow, with R_q already on the diagonal) and the residual of
+// row q, res_q = b_q + R_q f_q + sum_c A_qc f_c, current after every update.
+// Row r: lane r forms its new multiplier (dq = 1 / (A_qq + R_q)), the change
+// is broadcast from lane r (DPP) and every lane folds it into its residual:
+// five dependent instructions per row, whatever m.  On return f[r], r < m,
+// holds the multipliers on every lane.
+__device__ inline void pgs_team(const float arow[16], float bq, float dq, int m, int q, int n_pgs, float f[16])
 {
-    const bool mine = q < m;
-    float arow[16];
-#pragma unroll
-    for (int c = 0; c < 16; c += 4) {
-        const float4 a4 = *reinterpret_cast<const float4 *>(A + q * stride + c);
-        arow[c] = a4.x; arow[c + 1] = a4.y; arow[c + 2] = a4.z; arow[c + 3] = a4.w;
-    }
-    const float rq = mine ? Rv[q] : 0.f;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) arow[c] += c == q ? rq : 0.f;
-    float res = mine ? Bv[q] : 0.f;
-    const float d = mine ? Dv[q] : 0.f;
+    float res = bq;
     float fq = 0.f;
     for (int sweep = 0; sweep < n_pgs; ++sweep) {
         static_for<16>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
             if (r < m) {
-                const float fn = fmaxf(fmaf(-res, d, fq), 0.f);
+                const float fn = fmaxf(fmaf(-res, dq, fq), 0.f);
                 const float delta = fn - fq;
                 fq = q == r ? fn : fq;
                 res = fmaf(arow[r], row_bcast<r>(delta), res);
@@ -675,66 +664,73 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
         }
     }
     wave_lds_sync();
-    // row matrix A[4s+q][4t+r] = e_sq . G_st e_tr, split over the team's lanes
-    for (int idx = tc.t; idx < m * m; idx += TEAM) {
-        const int r = idx / m, c = idx - r * m;
-        const int s = r >> 2, q = r & 3, t = c >> 2, w = c & 3;
-        const float *es = E + 20 * s + 3 * q, *et = E + 20 * t + 3 * w;
-        const V3 eq = v3(es[0], es[1], es[2]), er = v3(et[0], et[1], et[2]);
-        V3 ge;
-        if (s <= t) {
-            float G[9];
-            const float *g = Gb + 9 * (s * NC + t);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) G[i] = g[i];
-            ge = mul9(G, er);
-        } else {
-            float G[9];
-            const float *g = Gb + 9 * (t * NC + s);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) G[i] = g[i];
-            ge = mul9t(G, er);
-        }
-        A[r * MR + c] = dot(eq, ge);
-    }
-    wave_lds_sync();
-    for (int r = tc.t; r < m; r += TEAM) {
-        const int s = r >> 2, q = r & 3;
-        const float *es = E + 20 * s;
-        const V3 eq = v3(es[3 * q], es[3 * q + 1], es[3 * q + 2]);
-        const float arr = A[r * MR + r];
-        const float rr = md.eps_r * arr;
-        Rv[r] = rr;
-        Dv[r] = 1.0f / (arr + rr);
-        Bv[r] = dot(eq, v3(es[16], es[17], es[18])) - es[15];
-    }
-    wave_lds_sync();
-    // projected Gauss-Seidel sweeps, rows in order, f = 0 at the start
     float f[MR];
 #pragma unroll
     for (int r = 0; r < MR; ++r) f[r] = 0.f;
-    if (nc == 1) {
-        float a[16], b[4], rr[4], dd[4];
+    if (nc <= 4) {
+        // lane q builds row q of A = E^T G E (+ R_q on the diagonal), its b_q
+        // and 1 / (A_qq + R_q) in registers; lanes q >= m carry unused rows
+        const int q = tc.t, sq = q >> 2;
+        const float *es = E + 20 * sq;
+        const V3 eq = v3(es[3 * (q & 3)], es[3 * (q & 3) + 1], es[3 * (q & 3) + 2]);
+        float arow[16];
+        float aqq = 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            b[r] = Bv[r];
-            rr[r] = Rv[r];
-            dd[r] = Dv[r];
-            const float4 a4 = *reinterpret_cast<const float4 *>(A + r * MR);
-            a[4 * r] = a4.x; a[4 * r + 1] = a4.y; a[4 * r + 2] = a4.z; a[4 * r + 3] = a4.w;
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) arow[4 * u + w] = 0.f;
+            if (u < nc) {
+                float G[9];
+                const bool up = sq <= u;  // G_{sq,u} = G_{u,sq}^T below the diagonal
+                const float *g = Gb + 9 * (up ? sq * NC + u : u * NC + sq);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) G[i] = g[i];
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const float *eu = E + 20 * u + 3 * w;
+                    const V3 er = v3(eu[0], eu[1], eu[2]);
+                    const V3 ge = up ? mul9(G, er) : mul9t(G, er);
+                    arow[4 * u + w] = dot(eq, ge);
+                    aqq = (4 * u + w == q) ? arow[4 * u + w] : aqq;
+                }
+            }
         }
-        float f4[4] = {0.f, 0.f, 0.f, 0.f};
-        pgs4(a, b, rr, dd, md.n_pgs, f4);
+        const float rq = md.eps_r * aqq;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) f[r] = f4[r];
-    } else if (nc <= 4) {
+        for (int c = 0; c < 16; ++c) arow[c] += c == q ? rq : 0.f;
+        const float dq = 1.0f / (aqq + rq);
+        const float bq = dot(eq, v3(es[16], es[17], es[18])) - es[15];
         float f16[16];
-        pgs_team(A, MR, Bv, Rv, Dv, m, tc.t, md.n_pgs, f16);
+        pgs_team(arow, bq, dq, m, q, md.n_pgs, f16);
 #pragma unroll
         for (int r = 0; r < 16; ++r) f[r] = f16[r];
     } else {
-        // up to MPPI_MAX_CONTACTS contacts: the multipliers live in the team's
-        // LDS (every lane computes and writes the same values)
+        // up to MPPI_MAX_CONTACTS contacts: A, b, R, 1 / (A_rr + R_r) and the
+        // multipliers in the team's LDS (rows of A split over the lanes)
+        for (int idx = tc.t; idx < m * m; idx += TEAM) {
+            const int r = idx / m, c = idx - r * m;
+            const int s = r >> 2, q = r & 3, t = c >> 2, w = c & 3;
+            const float *es = E + 20 * s + 3 * q, *et = E + 20 * t + 3 * w;
+            const V3 eq = v3(es[0], es[1], es[2]), er = v3(et[0], et[1], et[2]);
+            float G[9];
+            const float *g = Gb + 9 * (s <= t ? s * NC + t : t * NC + s);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) G[i] = g[i];
+            const V3 ge = s <= t ? mul9(G, er) : mul9t(G, er);
+            A[r * MR + c] = dot(eq, ge);
+        }
+        wave_lds_sync();
+        for (int r = tc.t; r < m; r += TEAM) {
+            const int s = r >> 2, q = r & 3;
+            const float *es = E + 20 * s;
+            const V3 eq = v3(es[3 * q], es[3 * q + 1], es[3 * q + 2]);
+            const float arr = A[r * MR + r];
+            const float rr = md.eps_r * arr;
+            Rv[r] = rr;
+            Dv[r] = 1.0f / (arr + rr);
+            Bv[r] = dot(eq, v3(es[16], es[17], es[18])) - es[15];
+        }
+        wave_lds_sync();
         float *F = Rv + MR;
         for (int r = 0; r < m; ++r) F[r] = 0.f;
         for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
