@@ -70,22 +70,24 @@ constexpr int tcs_fields(int nc) { return 20 * nc + 9 * nc * nc + 16 * nc * nc +
 constexpr int PK_FIELDS4 = (PK_FIELDS + 3) / 4 * 4;  // park area rounded to 16 bytes
 constexpr int team_lds_floats(int nc) { return TG_FIELDS + nc * CL_FIELDS + PK_FIELDS4 + tcs_fields(nc); }
 
+// DPP moves within 16-lane rows; lanes whose source falls outside the row
+// read 0 (bound_ctrl)
 template <int S>
 __device__ __forceinline__ float dpp_shr(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + S, 0xF, 0xF, true));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x110 + S, 0xF, 0xF, true));
 }
 template <int S>
 __device__ __forceinline__ float dpp_shl(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + S, 0xF, 0xF, true));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x100 + S, 0xF, 0xF, true));
 }
 
 // value of lane N of this lane's 16-lane row (DPP row broadcast: no LDS trip)
 template <int N>
 __device__ __forceinline__ float row_bcast(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + N, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xF, 0xF, true));
 }
 // value of lane I of this lane's arm segment (team lane 8 * arm1 + I)
 template <int I>
@@ -529,21 +531,45 @@ __device__ __forceinline__ V3 team_sum3(V3 x) { return v3(team_sum(x.x), team_su
 // is broadcast from lane r (DPP) and every lane folds it into its residual:
 // five dependent instructions per row, whatever m.  On return f[r], r < m,
 // holds the multipliers on every lane.
-__device__ inline void pgs_team(const float arow[16], float bq, float dq, int m, int q, int n_pgs, float f[16])
+template <int MW>
+__device__ inline float pgs_team_rows(const float arow[16], float res, float d, int q, int n_pgs)
 {
-    float res = bq;
     float fq = 0.f;
     for (int sweep = 0; sweep < n_pgs; ++sweep) {
-        static_for<16>([&](auto rc) {
+        int qo = q;
+        asm volatile("" : "+v"(qo));  // keeps each row's lane test in the loop (not 16 hoisted masks)
+        static_for<MW>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
-            if (r < m) {
-                const float fn = fmaxf(fmaf(-res, dq, fq), 0.f);
-                const float delta = fn - fq;
-                fq = q == r ? fn : fq;
-                res = fmaf(arow[r], row_bcast<r>(delta), res);
-            }
+            const float fn = fmaxf(fmaf(-res, d, fq), 0.f);
+            const float delta = fn - fq;
+            fq = qo == r ? fn : fq;
+            res = fmaf(arow[r], row_bcast<r>(delta), res);
         });
     }
+    return fq;
+}
+
+__device__ inline void pgs_team(const float arow_in[16], float bq, float dq, int m, int q, int n_pgs, float f[16])
+{
+    // rows run up to the wave's largest m; a team with fewer rows carries
+    // zeros there (its extra rows change nothing), so the sweep has no
+    // per-lane branches
+    const int mw = __builtin_amdgcn_readfirstlane(__ballot(m > 12) ? 16 : __ballot(m > 8) ? 12 : __ballot(m > 4) ? 8 : 4);
+    const bool mine = q < m;
+    float arow[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) arow[c] = (mine && c < m) ? arow_in[c] : 0.f;
+    const float res = mine ? bq : 0.f;
+    const float d = mine ? dq : 0.f;
+    float fq;
+    if (mw == 4)
+        fq = pgs_team_rows<4>(arow, res, d, q, n_pgs);
+    else if (mw == 8)
+        fq = pgs_team_rows<8>(arow, res, d, q, n_pgs);
+    else if (mw == 12)
+        fq = pgs_team_rows<12>(arow, res, d, q, n_pgs);
+    else
+        fq = pgs_team_rows<16>(arow, res, d, q, n_pgs);
     static_for<16>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
         f[r] = r < m ? row_bcast<r>(fq) : 0.f;
