@@ -400,8 +400,9 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
                     }
                 }
             } else if (s == 0 && k > 0) {
-                // cost of step k - 1 at its post-step state (this substep's positions)
-                team_stage_cost(model(a.md), jc, tc, S, u1, u2, k - 1 == 0, hist, dist, a.K, acc, cnt);
+                // cost of step k - 1 at its post-step state: this substep's positions,
+                // whose geometry and AABBs the contact sweep has just published
+                team_stage_cost<true>(model(a.md), jc, tc, S, u1, u2, k - 1 == 0, hist, dist, a.K, acc, cnt);
             }
         }
         u2 = u1;

@@ -524,30 +524,59 @@ struct TeamCtx {
 
 __device__ __forceinline__ V3 team_sum3(V3 x) { return v3(team_sum(x.x), team_sum(x.y), team_sum(x.z)); }
 
-// Gauss-Seidel over m <= 16 rows spread over the team's lanes: lane q keeps
-// row q of A + R (arow, with R_q already on the diagonal) and the residual of
-// row q, res_q = b_q + R_q f_q + sum_c A_qc f_c, current after every update.
-// Row r: lane r forms its new multiplier (dq = 1 / (A_qq + R_q)), the change
-// is broadcast from lane r (DPP) and every lane folds it into its residual:
-// five dependent instructions per row, whatever m.  On return f[r], r < m,
-// holds the multipliers on every lane.
+// Gauss-Seidel over m <= 16 rows spread over the team's lanes.  With
+// d_q = 1 / (A_qq + R_q), the update of row q is f_q <- max(u_q, 0) where
+// u_q = -d_q (b_q + sum_{c != q} A_qc f_c) does not depend on f_q itself.
+// Lane q keeps u_q and its row of C = -d_q A with a zero diagonal; row r:
+// every lane forms max(u, 0) and its change, lane r keeps it as its new f_r,
+// and every lane adds C_qr times lane r's change to u_q.  One sweep is one
+// asm block of five instructions a row: the lane test of the next row (VCC)
+// sits between the change and its DPP broadcast, which rides on the
+// multiply-add, so the two wait states that the broadcast and the VCC read
+// need cost nothing.  On return f[r], r < m, holds the multipliers on every
+// lane.
+#define PGS_ROW(R, RN)                                                                  \
+    "v_max_f32_e32 %[fn], 0, %[u]\n\t"                                                  \
+    "v_sub_f32_e32 %[dl], %[fn], %[fq]\n\t"                                             \
+    "v_cndmask_b32_e32 %[fq], %[fq], %[fn], vcc\n\t"                                    \
+    "v_cmp_eq_u32_e32 vcc, " #RN ", %[qo]\n\t"                                          \
+    "v_fmac_f32_dpp %[u], %[dl], %[c" #R "] row_newbcast:" #R " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+#define PGS_ROWS4(a, b, c, d, e) PGS_ROW(a, b) PGS_ROW(b, c) PGS_ROW(c, d) PGS_ROW(d, e)
+#define PGS_HEAD "v_cmp_eq_u32_e32 vcc, 0, %[qo]\n\ts_nop 1\n\t"
+#define PGS_IO [u] "+v"(u), [fq] "+v"(fq), [fn] "=&v"(fn), [dl] "=&v"(dl)
+#define PGS_C4 [qo] "v"(q), [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3])
+#define PGS_C8 PGS_C4, [c4] "v"(c[4]), [c5] "v"(c[5]), [c6] "v"(c[6]), [c7] "v"(c[7])
+#define PGS_C12 PGS_C8, [c8] "v"(c[8]), [c9] "v"(c[9]), [c10] "v"(c[10]), [c11] "v"(c[11])
+#define PGS_C16 PGS_C12, [c12] "v"(c[12]), [c13] "v"(c[13]), [c14] "v"(c[14]), [c15] "v"(c[15])
+
 template <int MW>
-__device__ inline float pgs_team_rows(const float arow[16], float res, float d, int q, int n_pgs)
+__device__ inline float pgs_team_rows(const float c[16], float u, int q, int n_pgs)
 {
-    float fq = 0.f;
-    for (int sweep = 0; sweep < n_pgs; ++sweep) {
-        int qo = q;
-        asm volatile("" : "+v"(qo));  // keeps each row's lane test in the loop (not 16 hoisted masks)
-        static_for<MW>([&](auto rc) {
-            constexpr int r = decltype(rc)::value;
-            const float fn = fmaxf(fmaf(-res, d, fq), 0.f);
-            const float delta = fn - fq;
-            fq = qo == r ? fn : fq;
-            res = fmaf(arow[r], row_bcast<r>(delta), res);
-        });
+    float fq = 0.f, fn, dl;
+    const int ns = __builtin_amdgcn_readfirstlane(n_pgs);  // uniform: a scalar loop
+    for (int sweep = 0; sweep < ns; ++sweep) {
+        if constexpr (MW == 4)
+            asm volatile(PGS_HEAD PGS_ROWS4(0, 1, 2, 3, 4) : PGS_IO : PGS_C4 : "vcc");
+        else if constexpr (MW == 8)
+            asm volatile(PGS_HEAD PGS_ROWS4(0, 1, 2, 3, 4) PGS_ROWS4(4, 5, 6, 7, 8) : PGS_IO : PGS_C8 : "vcc");
+        else if constexpr (MW == 12)
+            asm volatile(PGS_HEAD PGS_ROWS4(0, 1, 2, 3, 4) PGS_ROWS4(4, 5, 6, 7, 8) PGS_ROWS4(8, 9, 10, 11, 12)
+                         : PGS_IO : PGS_C12 : "vcc");
+        else
+            asm volatile(PGS_HEAD PGS_ROWS4(0, 1, 2, 3, 4) PGS_ROWS4(4, 5, 6, 7, 8) PGS_ROWS4(8, 9, 10, 11, 12)
+                             PGS_ROWS4(12, 13, 14, 15, 16)
+                         : PGS_IO : PGS_C16 : "vcc");
     }
     return fq;
 }
+#undef PGS_ROW
+#undef PGS_ROWS4
+#undef PGS_HEAD
+#undef PGS_IO
+#undef PGS_C4
+#undef PGS_C8
+#undef PGS_C12
+#undef PGS_C16
 
 __device__ inline void pgs_team(const float arow_in[16], float bq, float dq, int m, int q, int n_pgs, float f[16])
 {
@@ -556,20 +585,20 @@ __device__ inline void pgs_team(const float arow_in[16], float bq, float dq, int
     // per-lane branches
     const int mw = __builtin_amdgcn_readfirstlane(__ballot(m > 12) ? 16 : __ballot(m > 8) ? 12 : __ballot(m > 4) ? 8 : 4);
     const bool mine = q < m;
-    float arow[16];
+    const float nd = mine ? -dq : 0.f;
+    float crow[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) arow[c] = (mine && c < m) ? arow_in[c] : 0.f;
-    const float res = mine ? bq : 0.f;
-    const float d = mine ? dq : 0.f;
+    for (int c = 0; c < 16; ++c) crow[c] = (c < m && c != q) ? nd * arow_in[c] : 0.f;
+    const float u = nd * bq;
     float fq;
     if (mw == 4)
-        fq = pgs_team_rows<4>(arow, res, d, q, n_pgs);
+        fq = pgs_team_rows<4>(crow, u, q, n_pgs);
     else if (mw == 8)
-        fq = pgs_team_rows<8>(arow, res, d, q, n_pgs);
+        fq = pgs_team_rows<8>(crow, u, q, n_pgs);
     else if (mw == 12)
-        fq = pgs_team_rows<12>(arow, res, d, q, n_pgs);
+        fq = pgs_team_rows<12>(crow, u, q, n_pgs);
     else
-        fq = pgs_team_rows<16>(arow, res, d, q, n_pgs);
+        fq = pgs_team_rows<16>(crow, u, q, n_pgs);
     static_for<16>([&](auto rc) {
         constexpr int r = decltype(rc)::value;
         f[r] = r < m ? row_bcast<r>(fq) : 0.f;
@@ -877,25 +906,19 @@ __device__ inline int team_contacts(const DevModel &md, const TeamCtx &tc, const
     return nc;
 }
 
-// Contact solve and semi-implicit Euler: the end of a substep.
-template <int NC>
-__device__ inline void team_finish(const DevModel &md, const TeamCtx &tc, TeamState &S, const JointKin &k, int nc,
-                                   float v, V3 vb, V3 wb)
+// Semi-implicit Euler of the ball with its post-contact velocities: centre
+// by h vb, orientation by the exponential map of h wb (world frame).
+__device__ __forceinline__ void integrate_ball(const DevModel &md, TeamState &S, V3 vb, V3 wb)
 {
+    // Every product and sum is spelt out, with contraction off, so the update
+    // rounds the same wherever it is inlined (either wave of the split mapping).
+#pragma clang fp contract(off)
     const float h = md.h;
-    const V3 pb = S.pb;
-    if (nc == 1 && __float_as_int(tc.LL.at(0, 0)) == G_BALL &&
-        (__float_as_int(tc.LL.at(0, 1)) == G_TABLE || __float_as_int(tc.LL.at(0, 1)) >= G_BOX))
-        ball_contact_solve(md, tc.LL, pb, vb, wb);
-    else if (nc > 0)
-        team_contact_solve<NC>(md, tc, k, pb, nc, v, vb, wb);
-    S.q = fmaf(h, v, S.q);
-    S.qd = v;
-    S.pb = fma3(h, vb, pb);
+    S.pb = fma3(h, vb, S.pb);
     S.vb = vb;
     S.wb = wb;
     const V3 th = h * wb;
-    const float ang = sqrtf(dot(th, th));
+    const float ang = sqrtf(fmaf(th.x, th.x, fmaf(th.y, th.y, th.z * th.z)));
     float dw, dsc;
     if (ang < 1e-8f) {
         dw = 1.0f;
@@ -909,13 +932,39 @@ __device__ inline void team_finish(const DevModel &md, const TeamCtx &tc, TeamSt
     const V3 dv = dsc * th;
     const float qw = S.quat[0];
     const V3 qv = v3(S.quat[1], S.quat[2], S.quat[3]);
-    const float nw = dw * qw - dot(dv, qv);
-    const V3 nv = dw * qv + qw * dv + cross(dv, qv);
-    const float inv = 1.0f / sqrtf(nw * nw + dot(nv, nv));
+    // (dw, dv) * (qw, qv): scalar part dw qw - dv.qv, vector part dw qv + qw dv + dv x qv
+    const float nw = fmaf(dw, qw, -fmaf(dv.x, qv.x, fmaf(dv.y, qv.y, dv.z * qv.z)));
+    const V3 nv = v3(fmaf(dw, qv.x, fmaf(qw, dv.x, fmaf(dv.y, qv.z, -(dv.z * qv.y)))),
+                     fmaf(dw, qv.y, fmaf(qw, dv.y, fmaf(dv.z, qv.x, -(dv.x * qv.z)))),
+                     fmaf(dw, qv.z, fmaf(qw, dv.z, fmaf(dv.x, qv.y, -(dv.y * qv.x)))));
+    const float inv = 1.0f / sqrtf(fmaf(nw, nw, fmaf(nv.x, nv.x, fmaf(nv.y, nv.y, nv.z * nv.z))));
     S.quat[0] = nw * inv;
     S.quat[1] = nv.x * inv;
     S.quat[2] = nv.y * inv;
     S.quat[3] = nv.z * inv;
+}
+
+// true when the substep's only contact is the ball against the table or a
+// box: the arms are untouched and the ball's solve needs no arm data
+__device__ __forceinline__ bool ball_only_contact(const LaneList &LL, int nc)
+{
+    return nc == 1 && __float_as_int(LL.at(0, 0)) == G_BALL &&
+           (__float_as_int(LL.at(0, 1)) == G_TABLE || __float_as_int(LL.at(0, 1)) >= G_BOX);
+}
+
+// Contact solve and semi-implicit Euler: the end of a substep.
+template <int NC>
+__device__ inline void team_finish(const DevModel &md, const TeamCtx &tc, TeamState &S, const JointKin &k, int nc,
+                                   float v, V3 vb, V3 wb)
+{
+    const float h = md.h;
+    if (ball_only_contact(tc.LL, nc))
+        ball_contact_solve(md, tc.LL, S.pb, vb, wb);
+    else if (nc > 0)
+        team_contact_solve<NC>(md, tc, k, S.pb, nc, v, vb, wb);
+    S.q = fmaf(h, v, S.q);
+    S.qd = v;
+    integrate_ball(md, S, vb, wb);
 }
 
 // One physics substep of a team: dynamics, contacts, solve, integration.
@@ -932,17 +981,22 @@ __device__ inline void team_substep(const DevModel &md, const JointConst &jc, co
 }
 
 // per-control-step cost at the post-step state; lane 0 accumulates the stage
-// terms, joint lanes the smoothness, every lane its share of the cost pairs
+// terms, joint lanes the smoothness, every lane its share of the cost pairs.
+// PUBLISHED: the team's geometry and AABBs in LDS already belong to this
+// state (a contact sweep at the same positions wrote them).
+template <bool PUBLISHED = false>
 __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc, const TeamCtx &tc,
                                        const TeamState &S, float u, float uprev, bool first, uint32_t &hist,
                                        float *dist, long stride, CostAcc &acc, StepCounters &cnt)
 {
-    JointKin k;
-    team_fk(jc, S.q, tc.jt, k);
-    team_publish_geom(tc.tl, k, S.pb, tc.arm, tc.jt);
-    wave_lds_sync();
-    team_publish_aabb(tc.tl, tc.hd, tc.t);
-    wave_lds_sync();
+    if (!PUBLISHED) {
+        JointKin k;
+        team_fk(jc, S.q, tc.jt, k);
+        team_publish_geom(tc.tl, k, S.pb, tc.arm, tc.jt);
+        wave_lds_sync();
+        team_publish_aabb(tc.tl, tc.hd, tc.t);
+        wave_lds_sync();
+    }
     const float *tl = tc.tl;
     if (tc.t == 0) {
         const V3 p1 = v3(tl[TG_PTS + 21], tl[TG_PTS + 22], tl[TG_PTS + 23]);
