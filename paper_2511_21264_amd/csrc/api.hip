@@ -41,7 +41,7 @@ int ensure(mppi_ctx *c, int slot, size_t bytes, void **out)
     Buf &b = c->buf[slot];
     if (bytes == 0) bytes = 16;
     if (b.cap < bytes) {
-        if (b.p) hipFree(b.p);
+        if (b.p) (void)hipFree(b.p);
         b.p = nullptr;
         b.cap = 0;
         size_t want = bytes + bytes / 4;
@@ -284,18 +284,18 @@ int mppi_ctx_create(int device, mppi_ctx **out)
 void mppi_ctx_destroy(mppi_ctx *c)
 {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
     for (auto &b : c->buf)
-        if (b.p) hipFree(b.p);
-    if (c->st) hipFree(c->st);
-    for (auto e : c->ev) hipEventDestroy(e);
-    if (c->host_tab) hipHostFree(c->host_tab);
+        if (b.p) (void)hipFree(b.p);
+    if (c->st) (void)hipFree(c->st);
+    for (auto e : c->ev) (void)hipEventDestroy(e);
+    if (c->host_tab) (void)hipHostFree(c->host_tab);
     for (auto &g : c->graphs) {
-        if (g.exec) hipGraphExecDestroy(g.exec);
-        if (g.graph) hipGraphDestroy(g.graph);
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
     }
-    if (c->capture) hipStreamDestroy(c->capture);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
     delete c;
 }
 
@@ -316,7 +316,7 @@ int mppi_scene_create(mppi_ctx *ctx, const mppi_scene_desc *desc, mppi_scene **o
         return fail(MPPI_E_NOMEM, "scene allocation failed");
     }
     if (hipMemcpy(s->dev, &s->host, sizeof(DevModel), hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(s->dev);
+        (void)hipFree(s->dev);
         delete s;
         return fail(MPPI_E_DEVICE, "scene upload failed");
     }
@@ -327,9 +327,9 @@ int mppi_scene_create(mppi_ctx *ctx, const mppi_scene_desc *desc, mppi_scene **o
 void mppi_scene_destroy(mppi_scene *s)
 {
     if (!s) return;
-    hipSetDevice(s->ctx->device);
-    hipDeviceSynchronize();
-    if (s->dev) hipFree(s->dev);
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (s->dev) (void)hipFree(s->dev);
     delete s;
 }
 
@@ -454,13 +454,13 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
             hipGraph_t graph = nullptr;
             const hipError_t e2 = hipStreamEndCapture(ctx->capture, &graph);
             if (rc2) {
-                if (graph) hipGraphDestroy(graph);
+                if (graph) (void)hipGraphDestroy(graph);
                 return rc2;
             }
             if (e2 != hipSuccess) return fail(MPPI_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e2));
             g.graph = graph;
             if (hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-                hipGraphDestroy(graph);
+                (void)hipGraphDestroy(graph);
                 return fail(MPPI_E_DEVICE, "graph instantiation failed");
             }
             if (ctx->graphs.size() >= 8) {
@@ -468,8 +468,8 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
                 size_t lru = 0;
                 for (size_t i = 1; i < ctx->graphs.size(); ++i)
                     if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
-                hipGraphExecDestroy(ctx->graphs[lru].exec);
-                hipGraphDestroy(ctx->graphs[lru].graph);
+                (void)hipGraphExecDestroy(ctx->graphs[lru].exec);
+                (void)hipGraphDestroy(ctx->graphs[lru].graph);
                 ctx->graphs.erase(ctx->graphs.begin() + lru);
             }
             ctx->graphs.push_back(g);
@@ -613,7 +613,7 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
     if ((rc = ensure(ctx, S_BTAB, tab_bytes, &d_tab))) return rc;
     HIPCHK(hipStreamSynchronize(s));  // the pinned staging area may still feed a previous upload
     if (ctx->host_tab_cap < tab_bytes) {
-        if (ctx->host_tab) hipHostFree(ctx->host_tab);
+        if (ctx->host_tab) (void)hipHostFree(ctx->host_tab);
         ctx->host_tab = nullptr;
         ctx->host_tab_cap = 0;
         if (hipHostMalloc(&ctx->host_tab, tab_bytes * 2) != hipSuccess) return fail(MPPI_E_NOMEM, "pinned table allocation failed");
@@ -863,9 +863,9 @@ int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const
     HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto done = [&](int code) {
-        if (e0) hipEventDestroy(e0);
-        if (e1) hipEventDestroy(e1);
-        hipStreamDestroy(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamDestroy(s);
         return code;
     };
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

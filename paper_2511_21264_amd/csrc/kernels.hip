@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
                 u = clampf(fmaf(sg, z, a.nu[k * NU + d]), -md.u_max, md.u_max);
             }
         }
-        for (int s = 0; s < nsub; ++s) team_substep<NC, TPW == 1 ? 64 : TEAM>(model(a.md), jc, tc, S, u, cnt);
+        for (int s = 0; s < nsub; ++s) team_substep<NC, TPW == 1 ? 64 : TEAM, TPW == 1>(model(a.md), jc, tc, S, u, cnt);
         team_stage_cost(model(a.md), jc, tc, S, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
         uprev = u;
         if (a.xout && a.traj && active && primary) {
@@ -379,12 +379,12 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
                 const int nc = team_contacts<64>(model(a.md), tc, kk, S.pb, cnt);
                 if (lane == 0) SA[17] = __int_as_float(nc);
             } else {
-                team_dynamics(model(a.md), jc, tc, S, u, kk, v, vb, wb);
+                team_dynamics<NC, true>(model(a.md), jc, tc, S, u, kk, v, vb, wb);
             }
             __syncthreads();  // B2: the contact list and its count are in LDS
             if (!geo) {
                 const int nc = __float_as_int(SA[17]);
-                team_finish<NC>(model(a.md), tc, S, kk, nc, v, vb, wb);
+                team_finish<NC, true>(model(a.md), tc, S, kk, nc, v, vb, wb);
                 if (tc.joint) SA[d] = S.q;
                 if (lane == 0) { SA[14] = S.pb.x; SA[15] = S.pb.y; SA[16] = S.pb.z; }
                 if (s == nsub - 1 && a.xout && a.traj && row == 0) {

@@ -479,11 +479,11 @@ int mppi_server_create(mppi_ctx *ctx, const mppi_server_opts *opts, mppi_server 
     ok = ok && hipEventCreateWithFlags(&S->ev[0], hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&S->ev[1], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
-        if (S->dbase) hipFree(S->dbase);
-        if (S->hbase) hipHostFree(S->hbase);
-        if (S->s) hipStreamDestroy(S->s);
+        if (S->dbase) (void)hipFree(S->dbase);
+        if (S->hbase) (void)hipHostFree(S->hbase);
+        if (S->s) (void)hipStreamDestroy(S->s);
         for (auto e : S->ev)
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
         delete S;
         return fail(MPPI_E_NOMEM, "server allocation failed");
     }
@@ -512,20 +512,20 @@ void mppi_server_destroy(mppi_server *S)
         S->cv_work.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
-    hipSetDevice(S->ctx->device);
-    hipStreamSynchronize(S->s);
+    (void)hipSetDevice(S->ctx->device);
+    (void)hipStreamSynchronize(S->s);
     for (auto &c : S->cells) {
-        if (c->x) hipFree(c->x);
-        if (c->nu) hipFree(c->nu);
+        if (c->x) (void)hipFree(c->x);
+        if (c->nu) (void)hipFree(c->nu);
     }
     for (int b = 0; b < 2; ++b) {
-        if (S->dtab[b]) hipFree(S->dtab[b]);
-        if (S->htab[b]) hipHostFree(S->htab[b]);
-        if (S->ev[b]) hipEventDestroy(S->ev[b]);
+        if (S->dtab[b]) (void)hipFree(S->dtab[b]);
+        if (S->htab[b]) (void)hipHostFree(S->htab[b]);
+        if (S->ev[b]) (void)hipEventDestroy(S->ev[b]);
     }
-    hipFree(S->dbase);
-    hipHostFree(S->hbase);
-    hipStreamDestroy(S->s);
+    (void)hipFree(S->dbase);
+    (void)hipHostFree(S->hbase);
+    (void)hipStreamDestroy(S->s);
     delete S;
 }
 
@@ -545,7 +545,7 @@ int mppi_cell_create(mppi_server *S, const mppi_scene *scene, int H, const float
     c.H = H;
     const size_t nH = (size_t)H * NU * sizeof(float);
     if (hipMalloc((void **)&c.x, NX * sizeof(float)) != hipSuccess || hipMalloc((void **)&c.nu, nH) != hipSuccess) {
-        if (c.x) hipFree(c.x);
+        if (c.x) (void)hipFree(c.x);
         return fail(MPPI_E_NOMEM, "cell allocation failed");
     }
     std::vector<float> z((size_t)H * NU, 0.f);

@@ -245,9 +245,11 @@ __device__ inline void team_fk(const JointConst &jc, float q, int jt, JointKin &
     k.o = k.o1 - d;
 }
 
-// row jt of Mt = M + diag(diag_add), entries c <= jt (the rest 0), on joint lanes
-__device__ inline void team_crba(const DevModel &md, const JointConst &jc, const JointKin &k, int jt, int seg,
-                                 float row[NJ])
+// composite-rigid-body terms of link jt: with the composite of links jt..6
+// (mass Mc, centre cc, inertia Ic about it), L = Mc a x (cc - o) and
+// K = Ic a + cc x L (base-relative), and the moment arm mo = a x o
+__device__ inline void team_composite(const DevModel &md, const JointConst &jc, const JointKin &k, int jt, V3 &K, V3 &L,
+                                      V3 &mo)
 {
     const bool joint = jt < 7;
     const V3 cr = fma3(0.5f * jc.len, k.z, k.o) - jc.base;  // link centre, base-relative
@@ -271,20 +273,79 @@ __device__ inline void team_crba(const DevModel &md, const JointConst &jc, const
     const S3 Ic = {I[0] - Mc * (c2 - cc.x * cc.x), I[1] - Mc * (c2 - cc.y * cc.y), I[2] - Mc * (c2 - cc.z * cc.z),
                    I[3] + Mc * cc.x * cc.y,        I[4] + Mc * cc.x * cc.z,        I[5] + Mc * cc.y * cc.z};
     const V3 ob = k.o - jc.base;
-    const V3 L = Mc * cross(k.a, cc - ob);
-    const V3 K = mul(Ic, k.a) + cross(cc, L);
-    const V3 mo = cross(k.a, ob);
-    // row jt, entries c <= jt (the lower triangle the factorisation reads):
-    // M_{jt,c} = a_c . K_jt - mo_c . L_jt from the composite of link jt
+    L = Mc * cross(k.a, cc - ob);
+    K = mul(Ic, k.a) + cross(cc, L);
+    mo = cross(k.a, ob);
+}
+
+// entry (r, c), c <= r, of Mt from lane c's axis and moment arm and lane r's
+// composite (K, L): a_c . K_r - mo_c . L_r (+ the diagonal term)
+__device__ __forceinline__ float mass_entry(const DevModel &md, V3 ac, V3 moc, V3 K, V3 L, bool diag)
+{
+    float e = dot(ac, K) - dot(moc, L);
+    if (diag) e += md.diag_add;
+    return e;
+}
+
+// row jt of Mt = M + diag(diag_add), entries c <= jt (the rest 0), on joint lanes
+__device__ inline void team_crba(const DevModel &md, const JointConst &jc, const JointKin &k, int jt, int seg,
+                                 float row[NJ])
+{
+    V3 K, L, mo;
+    team_composite(md, jc, k, jt, K, L, mo);
+    // row jt, entries c <= jt (the lower triangle the factorisation reads)
     const bool arm1 = seg != 0;
     static_for<NJ>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const V3 ai = segb3<i>(k.a, arm1), mi = segb3<i>(mo, arm1);
-        row[i] = i <= jt ? dot(ai, K) - dot(mi, L) : 0.f;
+        row[i] = i <= jt ? mass_entry(md, ai, mi, K, L, i == jt) : 0.f;
     });
+}
+
+// packed row index r of lower-triangle entry e = tri(r, c), e < 28, 4 bits each
+constexpr uint64_t tri_rows(int lo)
+{
+    uint64_t t = 0;
+    for (int r = 0, e = 0; r < 7; ++r)
+        for (int c = 0; c <= r; ++c, ++e)
+            if (e >= lo && e < lo + 16) t |= (uint64_t)r << (4 * (e - lo));
+    return t;
+}
+
+// The arm's packed lower triangle of Mt on every lane of its segment, for a
+// wave whose four 16-lane rows carry one team: each lane parks its axis,
+// moment arm and composite in LDS (X, 16-byte aligned, 248 floats), lane l <
+// 56 forms entry l mod 28 of arm l / 28, and every lane reads its arm's 28
+// back.  The entries are those of team_crba bit for bit.
+// (t: the lane's index in the team, lane: its index in the wave)
+__device__ inline void team_mass_rows(const DevModel &md, const JointConst &jc, const JointKin &k, int jt, int t,
+                                      int arm, int lane, float *X, float Lp[28])
+{
+    V3 K, L, mo;
+    team_composite(md, jc, k, jt, K, L, mo);
+    float4 *xl = reinterpret_cast<float4 *>(X + 12 * t);
+    xl[0] = make_float4(k.a.x, k.a.y, k.a.z, mo.x);
+    xl[1] = make_float4(mo.y, mo.z, K.x, K.y);
+    xl[2] = make_float4(K.z, L.x, L.y, L.z);
+    wave_lds_sync();
+    float *T = X + 192;
+    const int l = lane;
+    if (l < 56) {
+        const int ar = l >= 28, e = l - 28 * ar;
+        constexpr uint64_t R0 = tri_rows(0), R1 = tri_rows(16);
+        const int r = (int)((e < 16 ? R0 >> (4 * e) : R1 >> (4 * (e - 16))) & 15ull);
+        const int c = e - r * (r + 1) / 2;
+        const float *xc = X + 12 * (8 * ar + c), *xr = X + 12 * (8 * ar + r);
+        T[l] = mass_entry(md, v3(xc[0], xc[1], xc[2]), v3(xc[3], xc[4], xc[5]), v3(xr[6], xr[7], xr[8]),
+                          v3(xr[9], xr[10], xr[11]), r == c);
+    }
+    wave_lds_sync();
+    const float4 *tr = reinterpret_cast<const float4 *>(T + 28 * arm);
 #pragma unroll
-    for (int i = 0; i < NJ; ++i)
-        if (i == jt) row[i] += md.diag_add;
+    for (int i = 0; i < 7; ++i) {
+        const float4 t4 = tr[i];
+        Lp[4 * i] = t4.x; Lp[4 * i + 1] = t4.y; Lp[4 * i + 2] = t4.z; Lp[4 * i + 3] = t4.w;
+    }
 }
 
 // gather the packed lower triangle of the arm's Mt on every lane of its segment
@@ -327,12 +388,21 @@ __device__ inline float team_rnea(const DevModel &md, const JointConst &jc, cons
     return dot(k.a, S - cross(k.o - jc.base, F));
 }
 
+// v ^ x, where the compiler no longer sees v as an element of an array: a
+// chain of selects over array elements keyed on one index would otherwise
+// become a dynamically indexed access, which goes through scratch memory
+__device__ __forceinline__ float opaque(float v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
 // component jt of a 7-vector held identically by the segment
 __device__ __forceinline__ float pick7(const float v[NJ], int jt)
 {
     float r = v[0];
 #pragma unroll
-    for (int i = 1; i < NJ; ++i) r = jt == i ? v[i] : r;
+    for (int i = 1; i < NJ; ++i) r = jt == i ? opaque(v[i]) : r;
     return r;
 }
 
@@ -849,17 +919,31 @@ __device__ __forceinline__ float normal_joint(uint32_t key0, uint32_t key1, uint
 // joint-space inertia and its factor (parked for the contact path), bias
 // forces and the free velocities (v of this lane's joint; ball vb with
 // gravity; wb).  k receives this lane's kinematics at the current positions.
+// the team's contact-solve area: per-contact frames E, then Delassus blocks,
+// then the row matrix A (its first 248 floats double as the mass-matrix
+// exchange of team_mass_rows, which runs before any solve of the substep)
+template <int NC>
+__device__ __forceinline__ float *team_solve_area(float *tl) { return tl + TG_FIELDS + NC * CL_FIELDS + PK_FIELDS4; }
+template <int NC>
+__device__ __forceinline__ float *team_row_area(float *tl) { return team_solve_area<NC>(tl) + 20 * NC + 9 * NC * NC; }
+
+template <int NC, bool ROWS = false>
 __device__ inline void team_dynamics(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
                                      float u, JointKin &k, float &v, V3 &vb, V3 &wb)
 {
+    static_assert(16 * NC * NC >= 248, "the row area holds the mass-matrix exchange");
     const float h = md.h;
     const int jt = tc.jt, seg = tc.seg;
     S.qdes = fmaf(h, u, S.qdes);
     team_fk(jc, S.q, jt, k);
-    float row[NJ];
-    team_crba(md, jc, k, jt, seg, row);
     float Lp[28];
-    team_gather_tri(row, seg, Lp);
+    if (ROWS) {
+        team_mass_rows(md, jc, k, jt, tc.t, tc.arm, tc.lane, team_row_area<NC>(tc.tl), Lp);
+    } else {
+        float row[NJ];
+        team_crba(md, jc, k, jt, seg, row);
+        team_gather_tri(row, seg, Lp);
+    }
     chol7(Lp);
     const float c = team_rnea(md, jc, k, S.qd, jt, md.gravcomp == 0);
     const float tau = clampf(md.kp * (S.qdes - S.q) + md.kd * (u - S.qd), -md.tau_max, md.tau_max);
@@ -952,14 +1036,240 @@ __device__ __forceinline__ bool ball_only_contact(const LaneList &LL, int nc)
            (__float_as_int(LL.at(0, 1)) == G_TABLE || __float_as_int(LL.at(0, 1)) >= G_BOX);
 }
 
-// Contact solve and semi-implicit Euler: the end of a substep.
+// element i of a register array (i uniform over a 16-lane row)
+template <int N>
+__device__ __forceinline__ V3 pick_v3(const V3 (&a)[N], int i)
+{
+    V3 r = a[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) r = i == k ? v3(opaque(a[k].x), opaque(a[k].y), opaque(a[k].z)) : r;
+    return r;
+}
+
+// bit s of the side word from lane 16 s of a wave ballot (s < 4)
+__device__ __forceinline__ int row_bits(uint64_t b)
+{
+    return (int)((b & 1ull) | ((b >> 15) & 2ull) | ((b >> 30) & 4ull) | ((b >> 45) & 8ull));
+}
+
+// The same solve for a wave whose four 16-lane rows all carry one team (one
+// sample a wave), nc <= 4: the per-contact and per-pair work is spread over
+// the rows instead of repeated on each.  Row s builds contact s's frame and
+// free velocity, row t the product Mt^-1 J_t^T; the Delassus blocks (s <= t,
+// t-major) go to the rows four at a time; row u builds columns 4u..4u+3 of
+// every lane's row of A, which the lanes read back whole.  Every value is
+// formed by the same operations as in team_contact_solve, so the two agree
+// bit for bit.
 template <int NC>
+__device__ inline void team_contact_solve_rows(const DevModel &md, const TeamCtx &tc, const JointKin &k, V3 pb, int nc,
+                                               float &v, V3 &vb, V3 &wb)
+{
+    constexpr int MR = 4 * NC;
+    static_assert(MR >= 16, "the lane-parallel sweeps read 16 rows of A");
+    float *E = tc.tl + TG_FIELDS + NC * CL_FIELDS + PK_FIELDS4;  // 16-byte aligned
+    float *Gb = E + 20 * NC;
+    float *A = Gb + 9 * NC * NC;  // first Mt^-1 J_t^T by contact and lane, then the rows of A
+    const LaneList &LL = tc.LL;
+    const int m = 4 * nc;
+    const int row = tc.lane >> 4;
+    // contact frames: row s builds contact s
+    int side_word;
+    {
+        const int s = row;
+        bool arm_s = false, ball_s = false;
+        if (s < nc) {
+            const int ga = __float_as_int(LL.at(s, 0)), gb = __float_as_int(LL.at(s, 1));
+            const Sides sd = contact_sides(ga | (gb << 8));
+            arm_s = (sd.armA >= 0) | (sd.armB >= 0);
+            ball_s = sd.ball;
+            const V3 n = v3(LL.at(s, 3), LL.at(s, 4), LL.at(s, 5));
+            const V3 p = v3(LL.at(s, 6), LL.at(s, 7), LL.at(s, 8));
+            V3 t1, t2;
+            tangents(n, t1, t2);
+            float *e = E + 20 * s;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const V3 t = q < 2 ? t1 : t2;
+                const V3 eq = fma3((q & 1) ? -md.mu : md.mu, t, n);
+                e[3 * q] = eq.x; e[3 * q + 1] = eq.y; e[3 * q + 2] = eq.z;
+            }
+            const V3 r = p - pb;
+            e[12] = r.x; e[13] = r.y; e[14] = r.z;
+            const float phi = LL.at(s, 2);
+            e[15] = md.kappa_h * (phi < 0.f ? -phi : 0.f);
+        }
+        side_word = row_bits(__ballot(arm_s)) | (row_bits(__ballot(ball_s)) << 8);
+    }
+    const bool any_arm = (side_word & 0xff) != 0;
+    // this lane's Jacobian columns
+    V3 Jc[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        Jc[s] = v3(0.f, 0.f, 0.f);
+        if (s < nc) {
+            const int ga = __float_as_int(LL.at(s, 0)), gb = __float_as_int(LL.at(s, 1));
+            const Sides sd = contact_sides(ga | (gb << 8));
+            const V3 p = v3(LL.at(s, 6), LL.at(s, 7), LL.at(s, 8));
+            const float coef = tc.joint ? jac_coef(sd, tc.arm, tc.jt) : 0.f;
+            if (coef != 0.f) Jc[s] = coef * cross(k.a, p - k.o);
+        }
+    }
+    // free contact velocity b_s: row s
+    {
+        const int s = row;
+        if (s < nc) {
+            V3 b = (side_word >> s) & 1 ? team_sum3(v * pick_v3(Jc, s)) : v3(0.f, 0.f, 0.f);
+            if ((side_word >> (8 + s)) & 1) {
+                const V3 p = v3(LL.at(s, 6), LL.at(s, 7), LL.at(s, 8));
+                const V3 r = p - pb;
+                b = b + vb + cross(wb, r);
+            }
+            float *e = E + 20 * s;
+            e[16] = b.x; e[17] = b.y; e[18] = b.z;
+        }
+    }
+    // row d of Mt^-1 of this lane's arm (only when an arm is in contact)
+    float Minv[NJ];
+#pragma unroll
+    for (int e = 0; e < NJ; ++e) Minv[e] = 0.f;
+    if (any_arm) {
+        float Lf[28];
+#pragma unroll
+        for (int i = 0; i < 28; ++i) Lf[i] = tc.pk.at(PK_L + 28 * tc.arm + i);
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) Minv[e] = (tc.joint && e == tc.jt) ? 1.f : 0.f;
+        chol7_solve(Lf, Minv);
+        if (!tc.joint) {
+#pragma unroll
+            for (int e = 0; e < NJ; ++e) Minv[e] = 0.f;
+        }
+    }
+    // row t: row d of Mt^-1 J_t^T, parked by contact and lane
+    {
+        const int t = row;
+        V3 W = v3(0.f, 0.f, 0.f);
+        if (t < nc && ((side_word >> t) & 1)) {
+            const V3 Jt = pick_v3(Jc, t);
+            static_for<NJ>([&](auto ec) {
+                constexpr int e = decltype(ec)::value;
+                W = fma3(Minv[e], segb3<e>(Jt, tc.arm != 0), W);
+            });
+        }
+        float *w = A + 4 * (16 * t + tc.t);
+        w[0] = W.x; w[1] = W.y; w[2] = W.z;
+    }
+    wave_lds_sync();
+    // Delassus blocks G_st = J_s Mt^-1 J_t^T (+ the ball's), s <= t: pair p
+    // (t-major) on row p mod 4
+    {
+        constexpr uint32_t PS = 0u | (0u << 2) | (1u << 4) | (0u << 6) | (1u << 8) | (2u << 10) | (0u << 12) | (1u << 14) |
+                                (2u << 16) | (3u << 18);
+        constexpr uint32_t PT = 0u | (1u << 2) | (1u << 4) | (2u << 6) | (2u << 8) | (2u << 10) | (3u << 12) | (3u << 14) |
+                                (3u << 16) | (3u << 18);
+        const int np = nc * (nc + 1) / 2;
+        for (int p0 = 0; p0 < np; p0 += 4) {
+            const int p = p0 + row;
+            if (p < np) {
+                const int s = (PS >> (2 * p)) & 3, t = (PT >> (2 * p)) & 3;
+                float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if (((side_word >> t) & 1) && ((side_word >> s) & 1)) {
+                    const float *w = A + 4 * (16 * t + tc.t);
+                    const V3 W = v3(w[0], w[1], w[2]);
+                    const V3 J = pick_v3(Jc, s);
+                    G[0] = team_sum(J.x * W.x); G[1] = team_sum(J.x * W.y); G[2] = team_sum(J.x * W.z);
+                    G[3] = team_sum(J.y * W.x); G[4] = team_sum(J.y * W.y); G[5] = team_sum(J.y * W.z);
+                    G[6] = team_sum(J.z * W.x); G[7] = team_sum(J.z * W.y); G[8] = team_sum(J.z * W.z);
+                }
+                if (((side_word >> (8 + t)) & 1) && ((side_word >> (8 + s)) & 1)) {
+                    const V3 rs = v3(E[20 * s + 12], E[20 * s + 13], E[20 * s + 14]);
+                    const V3 rt = v3(E[20 * t + 12], E[20 * t + 13], E[20 * t + 14]);
+                    ball_block(md, rs, rt, G);
+                }
+                float *g = Gb + 9 * (s * NC + t);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) g[i] = G[i];
+            }
+        }
+    }
+    wave_lds_sync();
+    // row u: columns 4u..4u+3 of lane q's row of A = E^T G E
+    const int q = tc.t, sq = q >> 2;
+    const float *es = E + 20 * sq;
+    const V3 eq = v3(es[3 * (q & 3)], es[3 * (q & 3) + 1], es[3 * (q & 3) + 2]);
+    {
+        const int u = row;
+        float a4[4] = {0.f, 0.f, 0.f, 0.f};
+        if (u < nc) {
+            float G[9];
+            const bool up = sq <= u;  // G_{sq,u} = G_{u,sq}^T below the diagonal
+            const float *g = Gb + 9 * (up ? sq * NC + u : u * NC + sq);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) G[i] = g[i];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const float *eu = E + 20 * u + 3 * w;
+                const V3 er = v3(eu[0], eu[1], eu[2]);
+                const V3 ge = up ? mul9(G, er) : mul9t(G, er);
+                a4[w] = dot(eq, ge);
+            }
+        }
+        *reinterpret_cast<float4 *>(A + 16 * q + 4 * u) = make_float4(a4[0], a4[1], a4[2], a4[3]);
+    }
+    wave_lds_sync();
+    float arow[16];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float4 a4 = *reinterpret_cast<const float4 *>(A + 16 * q + 4 * c);
+        arow[4 * c] = a4.x; arow[4 * c + 1] = a4.y; arow[4 * c + 2] = a4.z; arow[4 * c + 3] = a4.w;
+    }
+    float aqq = 0.f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) aqq = c == q ? arow[c] : aqq;
+    const float rq = md.eps_r * aqq;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) arow[c] += c == q ? rq : 0.f;
+    const float dq = 1.0f / (aqq + rq);
+    const float bq = dot(eq, v3(es[16], es[17], es[18])) - es[15];
+    float f[16];
+    pgs_team(arow, bq, dq, m, q, md.n_pgs, f);
+    // impulses back: ball (geom A) directly, joints through Mt^-1 J^T
+    float g = 0.f;  // generalized impulse of this lane's joint
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        if (s < nc) {
+            const float *e = E + 20 * s;
+            V3 P = v3(0.f, 0.f, 0.f);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) P = fma3(f[4 * s + qq], v3(e[3 * qq], e[3 * qq + 1], e[3 * qq + 2]), P);
+            if ((side_word >> (8 + s)) & 1) {
+                vb = fma3(md.inv_ball_m, P, vb);
+                wb = fma3(md.inv_ball_I, cross(v3(e[12], e[13], e[14]), P), wb);
+            }
+            g += dot(Jc[s], P);
+        }
+    }
+    if (any_arm) {
+        float dv = 0.f;
+        static_for<NJ>([&](auto ec) {
+            constexpr int e = decltype(ec)::value;
+            dv = fmaf(Minv[e], segb<e>(g, tc.arm != 0), dv);
+        });
+        if (tc.joint) v += dv;
+    }
+}
+
+// Contact solve and semi-implicit Euler: the end of a substep.  ROWS: the
+// wave's four 16-lane rows carry one team, so a solve of up to four contacts
+// spreads its per-contact work over them.
+template <int NC, bool ROWS = false>
 __device__ inline void team_finish(const DevModel &md, const TeamCtx &tc, TeamState &S, const JointKin &k, int nc,
                                    float v, V3 vb, V3 wb)
 {
     const float h = md.h;
     if (ball_only_contact(tc.LL, nc))
         ball_contact_solve(md, tc.LL, S.pb, vb, wb);
+    else if (ROWS && nc > 0 && nc <= 4)
+        team_contact_solve_rows<NC>(md, tc, k, S.pb, nc, v, vb, wb);
     else if (nc > 0)
         team_contact_solve<NC>(md, tc, k, S.pb, nc, v, vb, wb);
     S.q = fmaf(h, v, S.q);
@@ -968,16 +1278,16 @@ __device__ inline void team_finish(const DevModel &md, const TeamCtx &tc, TeamSt
 }
 
 // One physics substep of a team: dynamics, contacts, solve, integration.
-template <int NC, int G>
+template <int NC, int G, bool ROWS = false>
 __device__ inline void team_substep(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
                                     float u, StepCounters &cnt)
 {
     JointKin k;
     float v;
     V3 vb, wb;
-    team_dynamics(md, jc, tc, S, u, k, v, vb, wb);
+    team_dynamics<NC, ROWS>(md, jc, tc, S, u, k, v, vb, wb);
     const int nc = team_contacts<G>(md, tc, k, S.pb, cnt);
-    team_finish<NC>(md, tc, S, k, nc, v, vb, wb);
+    team_finish<NC, ROWS>(md, tc, S, k, nc, v, vb, wb);
 }
 
 // per-control-step cost at the post-step state; lane 0 accumulates the stage
