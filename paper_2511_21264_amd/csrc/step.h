@@ -431,32 +431,30 @@ __device__ inline void contact_solve(const DevModel &md, const ArmKin kin[2], co
 
 // Projected Gauss-Seidel on four rows (one contact), f = 0 at the start:
 // row r takes res = b_r + R_r f_r + sum_c A_rc f_c, f_r <- max(f_r - res / (A_rr + R_r), 0).
-// The sums are regrouped so that each row's partial sum over values already
-// known is formed off the dependency chain: only one FMA per row waits for
-// the row before it (a single wave per SIMD runs latency-bound).
+// With d_r = 1 / (A_rr + R_r) that is f_r <- max(u_r, 0) where
+// u_r = -d_r (b_r + sum_{c != r} A_rc f_c) does not involve f_r, so each row is
+// three multiply-adds with the scaled row C = -d_r A and a max; the value
+// changed last enters last, so one multiply-add per row waits for the row
+// before it.
 __device__ __forceinline__ void pgs4(const float a[16], const float b[4], const float rr[4], const float dd[4],
                                      int n_pgs, float f[4])
 {
-    float ad[4];
+    (void)rr;  // R_r sits only on the diagonal, which u_r leaves out
+    float c[16], ub[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) ad[r] = a[5 * r] + rr[r];  // A_rr + R_r multiplies f_r itself
-    for (int sweep = 0; sweep < n_pgs; ++sweep) {
-        // contributions of the values this sweep has not touched yet
-        const float p0 = fmaf(a[3], f[3], fmaf(a[2], f[2], fmaf(a[1], f[1], fmaf(ad[0], f[0], b[0]))));
-        const float p1 = fmaf(a[7], f[3], fmaf(a[6], f[2], fmaf(ad[1], f[1], b[1])));
-        const float p2 = fmaf(a[11], f[3], fmaf(ad[2], f[2], b[2]));
-        const float p3 = fmaf(ad[3], f[3], b[3]);
-        f[0] = fmaxf(fmaf(-p0, dd[0], f[0]), 0.f);
-        const float q1 = fmaf(a[4], f[0], p1);
-        const float q2 = fmaf(a[8], f[0], p2);
-        const float q3 = fmaf(a[12], f[0], p3);
-        f[1] = fmaxf(fmaf(-q1, dd[1], f[1]), 0.f);
-        const float s2 = fmaf(a[9], f[1], q2);
-        const float s3 = fmaf(a[13], f[1], q3);
-        f[2] = fmaxf(fmaf(-s2, dd[2], f[2]), 0.f);
-        const float t3 = fmaf(a[14], f[2], s3);
-        f[3] = fmaxf(fmaf(-t3, dd[3], f[3]), 0.f);
+    for (int r = 0; r < 4; ++r) {
+        ub[r] = -dd[r] * b[r];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[4 * r + k] = -dd[r] * a[4 * r + k];
     }
+    float f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
+    for (int sweep = 0; sweep < n_pgs; ++sweep) {
+        f0 = fmaxf(fmaf(c[3], f3, fmaf(c[2], f2, fmaf(c[1], f1, ub[0]))), 0.f);
+        f1 = fmaxf(fmaf(c[4], f0, fmaf(c[7], f3, fmaf(c[6], f2, ub[1]))), 0.f);
+        f2 = fmaxf(fmaf(c[9], f1, fmaf(c[8], f0, fmaf(c[11], f3, ub[2]))), 0.f);
+        f3 = fmaxf(fmaf(c[14], f2, fmaf(c[13], f1, fmaf(c[12], f0, ub[3]))), 0.f);
+    }
+    f[0] = f0; f[1] = f1; f[2] = f2; f[3] = f3;
 }
 
 // One contact of the ball with a static body (table or box), the common case:
