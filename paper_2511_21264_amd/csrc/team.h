@@ -69,6 +69,10 @@ constexpr int HD_FIELDS = HD_RAD + 12;
 constexpr int tcs_fields(int nc) { return 20 * nc + 9 * nc * nc + 16 * nc * nc + 16 * nc; }
 constexpr int PK_FIELDS4 = (PK_FIELDS + 3) / 4 * 4;  // park area rounded to 16 bytes
 constexpr int team_lds_floats(int nc) { return TG_FIELDS + nc * CL_FIELDS + PK_FIELDS4 + tcs_fields(nc); }
+// 16-byte alignment of the park and solve areas (float4 reads and writes)
+static_assert(HD_FIELDS % 4 == 0 && TG_FIELDS % 4 == 0 && (4 * CL_FIELDS) % 4 == 0 && PK_L % 4 == 0 &&
+                  team_lds_floats(4) % 4 == 0 && team_lds_floats(8) % 4 == 0,
+              "team LDS blocks keep 16-byte alignment");
 
 // DPP moves within 16-lane rows; lanes whose source falls outside the row
 // read 0 (bound_ctrl)
@@ -473,6 +477,46 @@ __device__ __forceinline__ void team_publish_geom(float *tl, const JointKin &k, 
     }
 }
 
+// team_publish_geom and the AABBs of the team's geoms in one pass: lane
+// (arm, jt) boxes arm geom jt (capsule jt from its own joint origin to the
+// next lane's, or the pad sphere at the tip for jt = 6), arm 0's spare lane
+// the ball; the values equal shape_aabb of the published shapes bit for bit,
+// and one wave-local sync covers both
+__device__ __forceinline__ void team_publish_geom_aabb(float *tl, const float *hd, const JointKin &k, V3 pb, int arm,
+                                                       int jt)
+{
+    const V3 onext = v3(dpp_shl<1>(k.o.x), dpp_shl<1>(k.o.y), dpp_shl<1>(k.o.z));  // next lane's joint origin
+    team_publish_geom(tl, k, pb, arm, jt);
+    if (jt < 7 || arm == 0) {
+        Shape sh;
+        int gid;
+        if (jt < 6) {
+            sh.type = SH_CAPSULE;
+            sh.p0 = k.o;
+            sh.p1 = onext;
+            sh.r = hd[HD_RAD + jt];
+            gid = G_ARM + 7 * arm + jt;
+        } else if (jt == 6) {
+            sh.type = SH_SPHERE;
+            sh.p0 = k.o1;
+            sh.p1 = k.o1;
+            sh.r = hd[HD_RAD + 6];
+            gid = G_ARM + 7 * arm + 6;
+        } else {
+            sh.type = SH_SPHERE;
+            sh.p0 = pb;
+            sh.p1 = pb;
+            sh.r = hd[HD_RAD + 8];
+            gid = G_BALL;
+        }
+        const AABB b = shape_aabb(sh);
+        float *o = tl + TG_AABB + 6 * gid;
+        o[0] = b.lo.x; o[1] = b.lo.y; o[2] = b.lo.z;
+        o[3] = b.hi.x; o[4] = b.hi.y; o[5] = b.hi.z;
+    }
+    wave_lds_sync();
+}
+
 // ArmKin of both arms from the published geometry (joint axes are in the park area)
 __device__ __forceinline__ void team_kin_from_lds(const float *tl, ArmKin kin[2])
 {
@@ -483,18 +527,6 @@ __device__ __forceinline__ void team_kin_from_lds(const float *tl, ArmKin kin[2]
             const float *p = tl + TG_PTS + 24 * a + 3 * i;
             kin[a].o[i] = v3(p[0], p[1], p[2]);
         }
-}
-
-// AABBs of the dynamic geoms (ball, arm links, pads) from the published
-// geometry; lane t of each row writes geom t (rows write identical values)
-__device__ __forceinline__ void team_publish_aabb(float *tl, const float *hd, int t)
-{
-    if (t != G_TABLE) {
-        const AABB b = shape_aabb(team_geom(tl, hd, t));
-        float *o = tl + TG_AABB + 6 * t;
-        o[0] = b.lo.x; o[1] = b.lo.y; o[2] = b.lo.z;
-        o[3] = b.hi.x; o[4] = b.hi.y; o[5] = b.hi.z;
-    }
 }
 
 // AABB test of candidate pair p (geom A is always dynamic) after growing A
@@ -534,16 +566,23 @@ __device__ inline int team_collect(const DevModel &md, float *tl, const float *h
                                    int gshift, StepCounters &cnt)
 {
     const int np = md.n_pairs;
-    int *cand = (int *)(tl + TG_CAND);
+    int *cand = (int *)(tl + TG_CAND);  // pair words (ga | gb << 8) of the candidates
     int ncand = 0;
-    for (int base = 0; base < np; base += G) {
-        const int p = base + li;
-        int gab = 0;
-        if (p < np) gab = __float_as_int(hd[HD_PAIR + p]);
-        const bool ov = p < np && pair_overlap(tl, hd, gab & 0xff, gab >> 8, 0.f);
-        const uint64_t gm = group_bits<G>(__ballot(ov), gshift);
-        if (ov) cand[ncand + __popcll(gm & ((1ull << li) - 1ull))] = p;
-        ncand += __popcll(gm);
+    // two blocks of G pairs at a time, so that their LDS reads overlap; the
+    // candidates still land in pair order
+    for (int base = 0; base < np; base += 2 * G) {
+        const int p0 = base + li, p1 = p0 + G;
+        int g0 = 0, g1 = 0;
+        if (p0 < np) g0 = __float_as_int(hd[HD_PAIR + p0]);
+        if (p1 < np) g1 = __float_as_int(hd[HD_PAIR + p1]);
+        const bool ov0 = p0 < np && pair_overlap(tl, hd, g0 & 0xff, g0 >> 8, 0.f);
+        const bool ov1 = p1 < np && pair_overlap(tl, hd, g1 & 0xff, g1 >> 8, 0.f);
+        const uint64_t below = (1ull << li) - 1ull;
+        const uint64_t m0 = group_bits<G>(__ballot(ov0), gshift), m1 = group_bits<G>(__ballot(ov1), gshift);
+        if (ov0) cand[ncand + __popcll(m0 & below)] = g0;
+        ncand += __popcll(m0);
+        if (ov1) cand[ncand + __popcll(m1 & below)] = g1;
+        ncand += __popcll(m1);
     }
     wave_lds_sync();
     int n = 0;
@@ -555,8 +594,7 @@ __device__ inline int team_collect(const DevModel &md, float *tl, const float *h
         Contact3 c;
         int ga = 0, gb = 0;
         if (live && i < ncand) {
-            const int p = cand[i];
-            const int gab = __float_as_int(hd[HD_PAIR + p]);
+            const int gab = cand[i];
             ga = gab & 0xff;
             gb = gab >> 8;
             const Shape A = team_geom(tl, hd, ga), B = team_geom(tl, hd, gb);
@@ -579,6 +617,17 @@ __device__ inline int team_collect(const DevModel &md, float *tl, const float *h
         n = min(n + (int)__popcll(gm), md.n_cmax);
     }
     return n;
+}
+
+// the arm's parked factor (parked by team_dynamics)
+__device__ __forceinline__ void team_parked_factor(const LanePark &pk, int arm, float Lf[28])
+{
+    const float4 *o = reinterpret_cast<const float4 *>(&pk.at(PK_L + 28 * arm));
+#pragma unroll
+    for (int e = 0; e < 7; ++e) {
+        const float4 f4 = o[e];
+        Lf[4 * e] = f4.x; Lf[4 * e + 1] = f4.y; Lf[4 * e + 2] = f4.z; Lf[4 * e + 3] = f4.w;
+    }
 }
 
 struct TeamCtx {
@@ -743,8 +792,7 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
     for (int e = 0; e < NJ; ++e) Minv[e] = 0.f;
     if (any_arm) {
         float Lf[28];
-#pragma unroll
-        for (int i = 0; i < 28; ++i) Lf[i] = tc.pk.at(PK_L + 28 * tc.arm + i);
+        team_parked_factor(tc.pk, tc.arm, Lf);
 #pragma unroll
         for (int e = 0; e < NJ; ++e) Minv[e] = (tc.joint && e == tc.jt) ? 1.f : 0.f;
         chol7_solve(Lf, Minv);
@@ -957,19 +1005,15 @@ __device__ inline void team_dynamics(const DevModel &md, const JointConst &jc, c
     v = S.qd + pick7(xs, jt);
     vb = v3(S.vb.x, S.vb.y, S.vb.z - h * md.g);
     wb = S.wb;
-    // park the contact path's factor and axes
-    if (tc.joint) {
-        const int f = PK_A + 3 * (7 * tc.arm + jt);
-        tc.pk.at(f) = k.a.x;
-        tc.pk.at(f + 1) = k.a.y;
-        tc.pk.at(f + 2) = k.a.z;
-        // the factor is replicated on the segment: its first lane parks it
-        if (jt == 0) {
+    // park the factor for the contact solve (the team keeps the joint axes in
+    // registers); it is replicated on the segment: its first lane parks it
+    if (jt == 0) {
+        float4 *o = reinterpret_cast<float4 *>(&tc.pk.at(PK_L + 28 * tc.arm));
 #pragma unroll
-            for (int e = 0; e < 28; ++e) tc.pk.at(PK_L + 28 * tc.arm + e) = Lp[e];
-        }
+        for (int e = 0; e < 7; ++e) o[e] = make_float4(Lp[4 * e], Lp[4 * e + 1], Lp[4 * e + 2], Lp[4 * e + 3]);
     }
 }
+
 
 // Geometry half: publish the kinematics and ball centre, the geom AABBs, and
 // sweep the candidate pairs into the contact list (tc.LL); returns the count.
@@ -977,10 +1021,7 @@ template <int G>
 __device__ inline int team_contacts(const DevModel &md, const TeamCtx &tc, const JointKin &k, V3 pb,
                                     StepCounters &cnt)
 {
-    team_publish_geom(tc.tl, k, pb, tc.arm, tc.jt);
-    wave_lds_sync();
-    team_publish_aabb(tc.tl, tc.hd, tc.t);
-    wave_lds_sync();
+    team_publish_geom_aabb(tc.tl, tc.hd, k, pb, tc.arm, tc.jt);
     const int nc = team_collect<G>(md, tc.tl, tc.hd, tc.LL, tc.li, tc.gshift, cnt);
     if (tc.t == 0) {
         cnt.contacts += nc;
@@ -1134,8 +1175,7 @@ __device__ inline void team_contact_solve_rows(const DevModel &md, const TeamCtx
     for (int e = 0; e < NJ; ++e) Minv[e] = 0.f;
     if (any_arm) {
         float Lf[28];
-#pragma unroll
-        for (int i = 0; i < 28; ++i) Lf[i] = tc.pk.at(PK_L + 28 * tc.arm + i);
+        team_parked_factor(tc.pk, tc.arm, Lf);
 #pragma unroll
         for (int e = 0; e < NJ; ++e) Minv[e] = (tc.joint && e == tc.jt) ? 1.f : 0.f;
         chol7_solve(Lf, Minv);
@@ -1302,10 +1342,7 @@ __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc,
     if (!PUBLISHED) {
         JointKin k;
         team_fk(jc, S.q, tc.jt, k);
-        team_publish_geom(tc.tl, k, S.pb, tc.arm, tc.jt);
-        wave_lds_sync();
-        team_publish_aabb(tc.tl, tc.hd, tc.t);
-        wave_lds_sync();
+        team_publish_geom_aabb(tc.tl, tc.hd, k, S.pb, tc.arm, tc.jt);
     }
     const float *tl = tc.tl;
     if (tc.t == 0) {
