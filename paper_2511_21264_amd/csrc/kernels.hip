@@ -35,12 +35,16 @@ __device__ __forceinline__ void sample_u(const float *nu_k, const float *sig_k, 
     for (int d = 0; d < NU; ++d) u[d] = clampf(fmaf(sig_k[d], z[d], nu_k[d]), -umax, umax);
 }
 
-// The model's words are re-read (scalar cache) inside the horizon loop rather
-// than hoisted: hoisted, ~100 uniform values overflow the SGPRs into VGPRs.
+// The model's words are re-read inside the horizon loop rather than hoisted:
+// hoisted, ~100 uniform values overflow the SGPRs into VGPRs.  The pointer is
+// opaque (so the reads stay where they are) and goes through the constant
+// address space: the model is read-only during a launch, so uniform reads
+// become scalar loads through the scalar cache instead of vector loads.
 __device__ __forceinline__ const DevModel &model(const DevModel *p)
 {
-    asm volatile("" : "+s"(p));
-    return *p;
+    const __attribute__((address_space(4))) DevModel *c = (const __attribute__((address_space(4))) DevModel *)p;
+    asm volatile("" : "+s"(c));
+    return *(const DevModel *)c;
 }
 
 // Scene of this workgroup: the single scene of the launch, or an entry of a

@@ -560,12 +560,57 @@ __device__ __forceinline__ uint64_t group_bits(uint64_t wm, int gshift)
 // Contact pass of one substep: AABB pre-pass over every candidate pair,
 // compaction of the overlapping ones, narrowphase over those; contacts land
 // in the team's LDS list in canonical order; returns the count.  li: lane
-// index within the sweeping group of G lanes.
+// index within the sweeping group of G lanes.  A whole wave (G = 64) skips
+// the candidate list.
 template <int G>
 __device__ inline int team_collect(const DevModel &md, float *tl, const float *hd, const LaneList &LL, int li,
                                    int gshift, StepCounters &cnt)
 {
     const int np = md.n_pairs;
+    if constexpr (G == 64) {
+        // one sweep a wave: each lane runs the narrowphase of its own
+        // overlapping pairs right away (no candidate list), block by block in
+        // pair order, and the hits are compacted into the contact list; the
+        // same contacts, in the same order, as the two-pass form below
+        int n = 0;
+        const uint64_t below = (1ull << li) - 1ull;
+        auto narrow_block = [&](bool ov, int gab) {
+            if (__ballot(ov) == 0ull) return;
+            bool hit = false;
+            Contact3 c;
+            const int ga = gab & 0xff, gb = gab >> 8;
+            if (ov) {
+                const Shape A = team_geom(tl, hd, ga), B = team_geom(tl, hd, gb);
+                ++cnt.np_tests;
+                if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
+                c = narrow(A, B);
+                hit = c.phi < 0.f;
+            }
+            const uint64_t gm = __ballot(hit);
+            if (hit) {
+                const int slot = n + __popcll(gm & below);
+                if (slot < md.n_cmax) {
+                    LL.at(slot, 0) = __int_as_float(ga);
+                    LL.at(slot, 1) = __int_as_float(gb);
+                    LL.at(slot, 2) = c.phi;
+                    LL.at(slot, 3) = c.n.x; LL.at(slot, 4) = c.n.y; LL.at(slot, 5) = c.n.z;
+                    LL.at(slot, 6) = c.p.x; LL.at(slot, 7) = c.p.y; LL.at(slot, 8) = c.p.z;
+                }
+            }
+            n = min(n + (int)__popcll(gm), md.n_cmax);
+        };
+        for (int base = 0; base < np; base += 2 * G) {
+            const int p0 = base + li, p1 = p0 + G;
+            int g0 = 0, g1 = 0;
+            if (p0 < np) g0 = __float_as_int(hd[HD_PAIR + p0]);
+            if (p1 < np) g1 = __float_as_int(hd[HD_PAIR + p1]);
+            const bool ov0 = p0 < np && pair_overlap(tl, hd, g0 & 0xff, g0 >> 8, 0.f);
+            const bool ov1 = p1 < np && pair_overlap(tl, hd, g1 & 0xff, g1 >> 8, 0.f);
+            narrow_block(ov0, g0);
+            narrow_block(ov1, g1);
+        }
+        return n;
+    }
     int *cand = (int *)(tl + TG_CAND);  // pair words (ga | gb << 8) of the candidates
     int ncand = 0;
     // two blocks of G pairs at a time, so that their LDS reads overlap; the
