@@ -41,9 +41,23 @@ def cpu_baseline(sc, pp, threads, min_s=10.0, max_plans=5):
         dt = time.perf_counter() - t0
         if dt >= min_s or n >= max_plans:
             break
+    # one thread, on a bounded sample: the first 64 samples of the same plan
+    K1, t1 = 64, time.perf_counter()
+    o.plan(x0, np.zeros((H, 14)), K1, H, pp["lam"], pp["sigma"], M, pp["seed"], nthreads=1)
+    dt1 = time.perf_counter() - t1
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=n * M * K * H / dt, unit="env-steps/s", cores=threads, kind="oracle",
                 sample=f"{n} full oracle plan(s) of the same workload (K={K}, H={H}, M={M}), FP64, "
-                       f"{dt:.1f} s on {threads} threads", plan_ms=dt / n * 1e3)
+                       f"{dt:.1f} s on {threads} threads", plan_ms=dt / n * 1e3, cpu_model=cpu,
+                single_thread={"value": M * K1 * H / dt1, "unit": "env-steps/s",
+                               "sample": f"one oracle plan with K={K1}, H={H}, M={M} on 1 thread, {dt1:.1f} s"})
 
 
 def bench_packed(mp, ctx, steps, warmup, mapping, n_scenes=32):
@@ -92,9 +106,60 @@ def bench_packed(mp, ctx, steps, warmup, mapping, n_scenes=32):
                      "p99_ms": float(np.percentile(lat, 99) * 1e3), "steps": steps}
         print(json.dumps({"packed_leg": name, **out[name]}), file=sys.stderr, flush=True)
     out["speedup"] = out["batched"]["env_steps_per_s"] / out["plain"]["env_steps_per_s"]
+    # alone vs mix: the same requests through one packed launch and one by
+    # one, with the mapping fixed (the automatic choice depends on the launch
+    # size, and the per-lane mapping rounds differently from the team ones)
+    mp.mppi_plan_batch(ctx, items, mapping="lane")
+    torch.cuda.synchronize()
+    mixed = [it["U_new"].clone() for it in items]
+    for it in items:
+        mp.mppi_plan(ctx, it["scene"], it["x0"], it["nominal_U"], it["K"], it["H"], it["lam"], it["sigma"],
+                     it["U_new"], it["costs"], M=it["M"], seed=it["seed"], mapping="lane", want_stats=False,
+                     sync=True)
+    torch.cuda.synchronize()
+    diff = max(float((it["U_new"] - u).abs().max()) for it, u in zip(items, mixed))
+    out["alone_equals_mix"] = {"mapping": "lane", "bit_identical": diff == 0.0, "max_abs_diff": diff}
     for it in items:
         it["scene"].close()
     return out
+
+
+def bench_replan(mp, ctx, sc, pp, n=200, warmup=5, advance=2, mapping=None):
+    """Receding-horizon latency on the main workload: each replan starts from
+    the plant state the previous reply produced (its first `advance` controls
+    executed in the GPU simulator) and from the previous plan shifted by
+    `advance` steps; the latency is the plan call, U_new ready on return."""
+    import numpy as np
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    scene = mp.Scene(ctx, sc)
+    K, H, M = pp["K"], pp["H"], pp["M"]
+    x = torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev)
+    nom = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    sig = torch.tensor(pp["sigma"], dtype=torch.float32, device=dev)
+    Unew = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    costs = torch.zeros(K, dtype=torch.float32, device=dev)
+    xn = torch.zeros((1, x.numel()), dtype=torch.float32, device=dev)
+    lat = []
+    for i in range(warmup + n):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        mp.mppi_plan(ctx, scene, x, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"] + i,
+                     mapping=mapping, want_stats=False, sync=True)
+        if i >= warmup:
+            lat.append(time.perf_counter() - a)
+        # the executor: first `advance` controls in the simulator, plan shifted
+        mp.mppi_simulate(ctx, scene, x.view(1, -1), Unew[:advance].reshape(1, advance, 14).contiguous(),
+                         X_out=xn, mapping=mapping)
+        x = xn.view(-1).clone()
+        nom = torch.cat([Unew[advance:], Unew[-1:].expand(advance, 14)]).contiguous()
+    scene.close()
+    lat_ms = np.array(lat) * 1e3
+    return {"workload": f"config 2, {n} warm-started replans (K={K}, H={H}, M={M}), plant advanced {advance} "
+                        f"steps per reply in the GPU simulator, plan shifted by {advance}",
+            "replans": n, "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+            "mean_ms": float(lat_ms.mean()), "env_steps_per_s": M * K * H / float(lat_ms.mean() * 1e-3)}
 
 
 def run_trace(mp, ctx, cells, scenes, trace, duration, max_active, mapping, deadline_ms=20.0, advance=2):
@@ -255,6 +320,23 @@ def traffic_per_launch(mapping, K, H, M):
     return rec["hbm_bytes_per_launch"]
 
 
+def counter_flops_per_launch(mapping, K, H):
+    """FP32 operations per rollout launch as the hardware counted them
+    (SQ_INSTS_VALU_FLOPS_FP32 in the committed summary), under the same
+    conditions as traffic_per_launch."""
+    path = os.path.join(ROOT, "profiles", "rollout_traffic_c2.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("sources_sha256") != sources_hash() or rec.get("mapping") != mapping or \
+            rec.get("K") != K or rec.get("H") != H:
+        return None
+    v = rec.get("valu_flops_fp32_per_dispatch")
+    # the counter adds each issued wave instruction's FP32 operations once;
+    # a wave instruction runs on 64 lanes
+    return None if v is None else 64.0 * v
+
+
 def sources_hash():
     import hashlib
     d = os.path.join(ROOT, "paper_2511_21264_amd", "csrc")
@@ -310,6 +392,12 @@ def summarize_profiles(base):
                "fetch_kib_per_dispatch": fetch[0], "write_kib_per_dispatch": write[0],
                "fetch_scale": f_scale, "write_scale": w_scale, "hbm_bytes_per_launch": hbm,
                "sources_sha256": sources_hash(), "commands": meta["commands"]}
+        # FP32 operations the hardware counted (issued wave instructions, all 64 lanes)
+        vf = counter("valu", "SQ_INSTS_VALU_FLOPS_FP32", like)
+        vi = counter("valu", "SQ_INSTS_VALU", like)
+        if vf and vf[0] is not None:
+            rec["valu_flops_fp32_per_dispatch"] = vf[0]
+            rec["valu_insts_per_dispatch"] = vi[0] if vi else None
         json.dump(rec, open(os.path.join(ROOT, "profiles", "rollout_traffic_c2.json"), "w"), indent=1)
     md = [f"# {meta['title']}", ""]
     md += ["Commands (run from the repository root, TMPDIR=/tmp):", ""]
@@ -321,6 +409,14 @@ def summarize_profiles(base):
                f"WRITE_SIZE {rec['write_kib_per_dispatch']:.1f} KiB x {rec['write_scale']:.3f} "
                f"(scale = bytes a {meta['calib_copy_bytes'] >> 20} MiB device copy moves / what the counter "
                f"reports for it) = {rec['hbm_bytes_per_launch'] / 1e6:.2f} MB per launch."]
+        if rec.get("valu_flops_fp32_per_dispatch") is not None:
+            md += ["", "## FP32 operations the hardware counted (per dispatch)", "",
+                   f"SQ_INSTS_VALU_FLOPS_FP32 {rec['valu_flops_fp32_per_dispatch'] / 1e9:.2f} G "
+                   f"(SQ_INSTS_VALU {rec['valu_insts_per_dispatch'] / 1e6:.2f} M wave instructions). The counter "
+                   f"adds each issued wave instruction's FP32 operations once, so x 64 lanes = "
+                   f"{64 * rec['valu_flops_fp32_per_dispatch'] / 1e9:.1f} G lane operations issued per launch, "
+                   f"against the work model's algorithmic count: lanes that repeat a team's work or sit "
+                   f"idle under a mask are in the issued figure."]
     open(os.path.join(ROOT, "profiles", meta["file"]), "w").write("\n".join(md) + "\n")
     print("\n".join(md))
 
@@ -343,6 +439,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--replans", type=int, default=200,
+                    help="warm-started replans of the main workload for the receding-horizon latency (0: skip)")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0)
@@ -418,6 +516,7 @@ def main():
     lat_ms = np.array(lat) * 1e3
     avg_launch_s = float(np.mean(roll_ms)) * 1e-3
     achieved = float(np.mean(flops)) / avg_launch_s
+    cf_launch = counter_flops_per_launch(used, K, H)
     out = {
         "metric": METRIC,
         "value": env_steps / elapsed,
@@ -449,6 +548,9 @@ def main():
             "frac": achieved / PEAK_FP32,
             "traffic": traffic_per_launch(used, K, H, M),
             "peak_nonpacked": PEAK_FP32_NONPACKED / 1e12,
+            "counter_flop_per_launch": cf_launch,
+            "counter_achieved": None if cf_launch is None else cf_launch / avg_launch_s / 1e12,
+            "counter_frac": None if cf_launch is None else cf_launch / avg_launch_s / PEAK_FP32,
             "avg_launch_ms": avg_launch_s * 1e3,
             "flop_per_launch": float(np.mean(flops)),
         },
@@ -467,6 +569,9 @@ def main():
             name, ms = mp.mppi_autotune(ctx, s5, W.initial_state(sc5), pp["sigma"], 1 << c, 16)
             out["autotune_classes"][str(1 << c)] = name
         s5.close()
+    if args.replans > 0:
+        out["replan"] = bench_replan(mp, ctx, sc, pp, n=args.replans, mapping=mapping)
+        print(json.dumps({"replan": out["replan"]}), file=sys.stderr, flush=True)
     if args.packed_steps > 0:
         out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, mapping)
     if args.serve_seconds > 0:
