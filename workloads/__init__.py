@@ -253,3 +253,14 @@ def poisson_trace(rates, duration, seed=0):
             t += rng.exponential(1.0 / r)
     ev.sort()
     return ev
+
+
+def qp_params(config: int = 2, **overrides):
+    """Bounds and solver settings of the QP smoothing of sampled sequences:
+    commanded joint positions within 1.5 rad of the home pose, velocity box
+    from the scene (u_max), acceleration and jerk limits, ADMM penalty,
+    over-relaxation and iteration count."""
+    home = np.array(Q_HOME_ARM * 2, dtype=np.float64)
+    p = dict(pos_lo=home - 1.5, pos_hi=home + 1.5, acc_max=4.0, jerk_max=60.0, rho=3.0, alpha=1.6, iters=60)
+    p.update(overrides)
+    return p
