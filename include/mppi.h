@@ -239,6 +239,47 @@ int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, cons
                 float *nu_out, double *nu_out64, double *weights, mppi_stats *stats, unsigned flags,
                 void *stream);
 
+/* ------------------------------------------------------------ QP smoothing
+ * Alg. 1's sampling step followed by its QP based smoothing: every sampled
+ * sequence is projected onto the bounds of Eq. proj_bounds on the joint
+ * trajectory and its first three derivatives, with the objective of Eq.
+ * proj_cost.  Each joint is one QP over the horizon in the H control-step
+ * velocities v_0..v_{H-1} (dt = n_sub * h):
+ *   r = 0: q_des0 + dt (v_0 + .. + v_k) in [pos_lo, pos_hi], q_des0 the
+ *          commanded joint position of the start state;
+ *   r = 1: |v_k| <= u_max (the scene's velocity box);
+ *   r = 2: |v_k - v_{k-1}| <= acc_max dt, k >= 1;
+ *   r = 3: |v_k - 2 v_{k-1} + v_{k-2}| <= jerk_max dt^2, k >= 2.
+ * Solver: `iters` iterations of ADMM with penalty rho and over-relaxation
+ * alpha on the stacked operator [I; D1; D2; prefix sums], started from
+ * z = clip(A v~), w = 0; the result is clipped to the velocity box (r = 1
+ * holds exactly, the other bounds to the solver's accuracy).  H <= 64. */
+typedef struct mppi_qp {
+    double pos_lo[14], pos_hi[14]; /* commanded-position bounds per joint (rad) */
+    double acc_max;                /* rad/s^2 */
+    double jerk_max;               /* rad/s^3 */
+    double rho;                    /* ADMM penalty, > 0 */
+    double alpha;                  /* over-relaxation, in (0, 2) */
+    int iters;                     /* ADMM iterations, 1..10000 */
+} mppi_qp;
+
+/* Project U_in[K][H][14] into U_out[K][H][14] (the same array is allowed).
+ *   X0: [K][MPPI_NX] start states (their commanded positions q_des), or one
+ *   state for every sample when x0_shared != 0.  flags: MPPI_DEVICE_PTRS,
+ *   MPPI_SYNC.  Errors: MPPI_E_INVAL (NULL, K < 1, H < 1 or H > 64, bad qp
+ *   values), MPPI_E_NOMEM, MPPI_E_DEVICE. */
+int mppi_project(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0_shared, const float *U_in,
+                 float *U_out, int K, int H, const mppi_qp *qp, unsigned flags, void *stream);
+
+/* mppi_plan with the QP smoothing of every sample: in each iteration the
+ * samples nu + sigma * z (the Philox normals of mppi_sample, not clamped)
+ * are projected as by mppi_project, rolled out as given, and the update of
+ * Eq. mean_update averages the projected samples.  Arguments and errors as
+ * mppi_plan, plus qp (H <= 64).  MPPI_GRAPH is ignored. */
+int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                 double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp, float *U_new,
+                 float *costs, mppi_stats *stats, void *stream);
+
 /* ---------------------------------------------------------------- serving
  * A server replans for many robot cells at once by continuous batching:
  * a worker thread runs MPPI iterations over every active request in one

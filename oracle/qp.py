@@ -50,9 +50,10 @@ def operators(H: int):
 
 def bounds(q0, dt, u_max, pos_lo, pos_hi, acc_max, jerk_max, H):
     """Lower and upper bounds of A v for one joint (q0: commanded start position)."""
-    lo = np.concatenate([np.full(H, -u_max), np.full(H - 1, -acc_max * dt), np.full(H - 2, -jerk_max * dt * dt),
+    n1, n2 = max(H - 1, 0), max(H - 2, 0)  # difference rows exist only for k >= 1 and k >= 2
+    lo = np.concatenate([np.full(H, -u_max), np.full(n1, -acc_max * dt), np.full(n2, -jerk_max * dt * dt),
                          np.full(H, (pos_lo - q0) / dt)])
-    hi = np.concatenate([np.full(H, u_max), np.full(H - 1, acc_max * dt), np.full(H - 2, jerk_max * dt * dt),
+    hi = np.concatenate([np.full(H, u_max), np.full(n1, acc_max * dt), np.full(n2, jerk_max * dt * dt),
                          np.full(H, (pos_hi - q0) / dt)])
     return lo, hi
 

@@ -64,6 +64,23 @@ class Opts(C.Structure):
                 ("flags", C.c_uint)]
 
 
+class QP(C.Structure):
+    """mppi_qp: bounds and solver settings of the QP smoothing."""
+    _fields_ = [("pos_lo", C.c_double * 14), ("pos_hi", C.c_double * 14), ("acc_max", C.c_double),
+                ("jerk_max", C.c_double), ("rho", C.c_double), ("alpha", C.c_double), ("iters", C.c_int)]
+
+
+def make_qp(params):
+    """An mppi_qp from a dict with pos_lo[14], pos_hi[14], acc_max, jerk_max, rho, alpha, iters."""
+    q = QP()
+    for d in range(14):
+        q.pos_lo[d] = float(params["pos_lo"][d])
+        q.pos_hi[d] = float(params["pos_hi"][d])
+    q.acc_max, q.jerk_max = float(params["acc_max"]), float(params["jerk_max"])
+    q.rho, q.alpha, q.iters = float(params["rho"]), float(params["alpha"]), int(params["iters"])
+    return q
+
+
 class Stats(C.Structure):
     _fields_ = [
         ("ess", C.c_double), ("c_min", C.c_double), ("best", C.c_int), ("n_nonfinite", C.c_int),
@@ -138,6 +155,9 @@ def lib():
             "mppi_update": (C.c_int, [_P, _P, _P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_double,
                                       C.c_double, C.c_int, _P, _P, _P, C.POINTER(Stats), C.c_uint, _P]),
             "mppi_autotune": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.POINTER(C.c_int), _P]),
+            "mppi_project": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, C.c_int, C.c_int, C.POINTER(QP), C.c_uint, _P]),
+            "mppi_plan_qp": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts),
+                                       C.POINTER(QP), _P, _P, C.POINTER(Stats), _P]),
             "mppi_broadphase": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_float, _P, C.c_uint, _P]),
             "mppi_narrowphase": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, _P, _P, _P, C.c_uint, _P]),
         }
@@ -306,6 +326,44 @@ def mppi_plan(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *,
         d["rc"] = rc
         return d
     return None
+
+
+def mppi_plan_qp(ctx, scene, x0, nominal_U, K, H, lam, sigma, qp, U_new, costs=None, *, M=1, seed=0, eta=1.0,
+                 n_elite=0, sigma_per_step=False, time_kernels=False, want_stats=True, sync=False, stream=None,
+                 mapping=None, fp32_weights=False):
+    """mppi_plan with the QP smoothing of every sample; qp: a dict for make_qp
+    or a QP structure.  Returns a stats dict (or None)."""
+    q = qp if isinstance(qp, QP) else make_qp(qp)
+    (px0, pnom, psig, pU, pc), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32), (sigma, np.float32),
+                                             (U_new, np.float32), (costs, np.float32)])
+    flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | \
+            (TIME_KERNELS if time_kernels else 0) | (SYNC if sync else 0) | _MAPS[mapping] | \
+            (FP32_WEIGHTS if fp32_weights else 0)
+    o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
+    st = Stats()
+    rc = lib().mppi_plan_qp(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), C.byref(q),
+                            pU, pc, C.byref(st) if want_stats else None, _stream(dev, stream))
+    if rc == E_DIVERGED:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    _check(rc)
+    if want_stats:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    return None
+
+
+def mppi_project(ctx, scene, X0, U_in, U_out, qp, *, x0_shared=False, sync=True, stream=None):
+    """QP smoothing of U_in[K,H,14] into U_out[K,H,14] from the start states
+    X0[K,55] (or one shared state)."""
+    q = qp if isinstance(qp, QP) else make_qp(qp)
+    (px0, pin, pout), dev = _ptrs([(X0, np.float32), (U_in, np.float32), (U_out, np.float32)])
+    K, H = U_in.shape[0], U_in.shape[1]
+    flags = (DEVICE_PTRS if dev else 0) | (SYNC if sync else 0)
+    _check(lib().mppi_project(ctx._h, scene._h, px0, int(bool(x0_shared)), pin, pout, int(K), int(H), C.byref(q),
+                              flags, _stream(dev, stream)))
 
 
 def mppi_simulate(ctx, scene, X0, U, costs=None, terms=None, X_out=None, *, x0_shared=False, n_sub=0, traj=False,

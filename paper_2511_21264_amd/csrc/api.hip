@@ -341,9 +341,106 @@ int mppi_scene_num_pairs(const mppi_scene *s, int *n_pairs, int *n_cost)
     return MPPI_OK;
 }
 
-int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
-              double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs, mppi_stats *stats,
-              void *stream)
+// Checks of the QP smoothing's parameters for horizon H.
+static int qp_check(const mppi_qp *qp, int H)
+{
+    if (!qp) return fail(MPPI_E_INVAL, "NULL qp");
+    if (H > 64) return fail(MPPI_E_INVAL, "QP smoothing supports H <= 64 (H=%d)", H);
+    if (!(qp->rho > 0) || !std::isfinite(qp->rho)) return fail(MPPI_E_INVAL, "qp rho must be finite and > 0");
+    if (!(qp->alpha > 0 && qp->alpha < 2)) return fail(MPPI_E_INVAL, "qp alpha must lie in (0, 2)");
+    if (qp->iters < 1 || qp->iters > 10000) return fail(MPPI_E_INVAL, "qp iters=%d out of range", qp->iters);
+    if (!(qp->acc_max > 0) || !std::isfinite(qp->acc_max) || !(qp->jerk_max > 0) || !std::isfinite(qp->jerk_max))
+        return fail(MPPI_E_INVAL, "qp acc_max and jerk_max must be finite and > 0");
+    for (int d = 0; d < NU; ++d)
+        if (!std::isfinite(qp->pos_lo[d]) || !std::isfinite(qp->pos_hi[d]) || !(qp->pos_lo[d] < qp->pos_hi[d]))
+            return fail(MPPI_E_INVAL, "qp position bounds of joint %d must be finite with lo < hi", d);
+    return MPPI_OK;
+}
+
+// (I + rho A^T A)^-1 for A = [I; D1; D2; L] on H steps, in double, stored as
+// float rows of stride S (zero padded) in the context's QP slot.
+static int qp_matrix(mppi_ctx *ctx, int H, double rho, const float **out, int *S)
+{
+    const int st = ((H + 3) & ~3) + 4;
+    void *dp;
+    int rc;
+    if ((rc = ensure(ctx, S_QPP, (size_t)H * st * sizeof(float), &dp))) return rc;
+    if (ctx->qp_H != H || ctx->qp_rho != rho || ctx->qp_S != st) {
+        std::vector<double> M((size_t)H * H, 0.0);
+        auto add_row = [&](const std::vector<std::pair<int, double>> &row) {
+            for (auto &a : row)
+                for (auto &b : row) M[(size_t)a.first * H + b.first] += rho * a.second * b.second;
+        };
+        for (int k = 0; k < H; ++k) add_row({{k, 1.0}});
+        for (int k = 1; k < H; ++k) add_row({{k, 1.0}, {k - 1, -1.0}});
+        for (int k = 2; k < H; ++k) add_row({{k, 1.0}, {k - 1, -2.0}, {k - 2, 1.0}});
+        for (int i = 0; i < H; ++i)  // prefix sums: (L^T L)_ij = H - max(i, j)
+            for (int j = 0; j < H; ++j) M[(size_t)i * H + j] += rho * (double)(H - std::max(i, j));
+        for (int i = 0; i < H; ++i) M[(size_t)i * H + i] += 1.0;
+        // Cholesky M = C C^T, then the inverse column by column
+        std::vector<double> C((size_t)H * H, 0.0);
+        for (int j = 0; j < H; ++j) {
+            double dsum = M[(size_t)j * H + j];
+            for (int k = 0; k < j; ++k) dsum -= C[(size_t)j * H + k] * C[(size_t)j * H + k];
+            if (!(dsum > 0)) return fail(MPPI_E_INVAL, "QP system not positive definite");
+            const double cjj = std::sqrt(dsum);
+            C[(size_t)j * H + j] = cjj;
+            for (int i = j + 1; i < H; ++i) {
+                double v = M[(size_t)i * H + j];
+                for (int k = 0; k < j; ++k) v -= C[(size_t)i * H + k] * C[(size_t)j * H + k];
+                C[(size_t)i * H + j] = v / cjj;
+            }
+        }
+        std::vector<float> P((size_t)H * st, 0.f);
+        std::vector<double> x(H);
+        for (int c = 0; c < H; ++c) {
+            for (int i = 0; i < H; ++i) {  // C y = e_c
+                double v = i == c ? 1.0 : 0.0;
+                for (int k = 0; k < i; ++k) v -= C[(size_t)i * H + k] * x[k];
+                x[i] = v / C[(size_t)i * H + i];
+            }
+            for (int i = H - 1; i >= 0; --i) {  // C^T z = y
+                double v = x[i];
+                for (int k = i + 1; k < H; ++k) v -= C[(size_t)k * H + i] * x[k];
+                x[i] = v / C[(size_t)i * H + i];
+            }
+            for (int i = 0; i < H; ++i) P[(size_t)i * st + c] = (float)x[i];
+        }
+        HIPCHK(hipMemcpy(dp, P.data(), P.size() * sizeof(float), hipMemcpyHostToDevice));
+        ctx->qp_H = H;
+        ctx->qp_rho = rho;
+        ctx->qp_S = st;
+    }
+    *out = (const float *)dp;
+    *S = st;
+    return MPPI_OK;
+}
+
+static void qp_args(ProjectArgs &pa, const mppi_scene *scene, const mppi_qp *qp, const float *P, int S, int K, int H)
+{
+    const double dt = scene->host.h * scene->host.n_sub;
+    pa.P = P;
+    pa.S = S;
+    pa.K = K;
+    pa.H = H;
+    pa.dt = (float)dt;
+    pa.u_max = scene->host.u_max;
+    pa.dacc = (float)(qp->acc_max * dt);
+    pa.djerk = (float)(qp->jerk_max * dt * dt);
+    for (int d = 0; d < NU; ++d) {
+        pa.pos_lo[d] = (float)qp->pos_lo[d];
+        pa.pos_hi[d] = (float)qp->pos_hi[d];
+    }
+    pa.rho = (float)qp->rho;
+    pa.alpha = (float)qp->alpha;
+    pa.iters = qp->iters;
+}
+
+// mppi_plan and mppi_plan_qp (qp non-null: the samples are projected and
+// stored, the rollout and the update read them)
+static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                     double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp, float *U_new,
+                     float *costs, mppi_stats *stats, void *stream)
 {
     if (!ctx || !scene || !x0 || !nominal_U || !sigma || !opts || !U_new) return fail(MPPI_E_INVAL, "NULL argument");
     if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
@@ -376,7 +473,14 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
     if ((rc = ensure(ctx, S_DIST, (size_t)K * MAXCOST * sizeof(float), &ddist))) return rc;
     if ((rc = out_ptr(ctx, S_COSTS, costs, (size_t)K * sizeof(float), dev, &dcost))) return rc;
     if (!dcost && (rc = ensure(ctx, S_COSTS, (size_t)K * sizeof(float), &dcost))) return rc;
-    const bool use_graph = fl & MPPI_GRAPH;
+    const float *dP = nullptr;
+    int qpS = 0;
+    void *dqu = nullptr;
+    if (qp) {
+        if ((rc = qp_matrix(ctx, H, qp->rho, &dP, &qpS))) return rc;
+        if ((rc = ensure(ctx, S_QPU, (size_t)K * H * NU * sizeof(float), &dqu))) return rc;
+    }
+    const bool use_graph = (fl & MPPI_GRAPH) && !qp;
     const bool timing = (fl & MPPI_TIME_KERNELS) && !use_graph;
     const int M = opts->M;
     if (timing) {
@@ -413,6 +517,22 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
             ra.counters = (int *)dcnt;
             ra.diverged = &ctx->st->diverged;
             ra.dist = (float *)ddist;
+            if (qp) {
+                // this iteration's samples, projected, then rolled out as given
+                ProjectArgs pa = {};
+                qp_args(pa, scene, qp, dP, qpS, K, H);
+                pa.U_out = (float *)dqu;
+                pa.x0 = (const float *)dx0;
+                pa.x0_shared = 1;
+                pa.nu = (const float *)dnu;
+                pa.sigma = (const float *)dsig;
+                pa.sigma_per_step = sps;
+                pa.key0 = k0;
+                pa.key1 = k1;
+                pa.m = m;
+                launch_project(pa, q);
+                ra.U = (const float *)dqu;
+            }
             if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], q));
             launch_rollout(ra, scene->host.n_cmax, q, mapping);
             if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], q));
@@ -420,7 +540,8 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
                             (const int *)dcnt, f32};
             launch_stats(sa, q);
             UpdateArgs ua = {(const double *)dw, K, H, (const float *)dnu, (const float *)dsig, sps,
-                             scene->host.u_max, k0, k1, m, opts->eta, ctx->st, (float *)dnu, nullptr, f32};
+                             scene->host.u_max, k0, k1, m, opts->eta, ctx->st, (float *)dnu, nullptr, f32,
+                             (const float *)dqu};
             launch_update(ua, q);
         }
         HIPCHK(hipGetLastError());
@@ -524,6 +645,56 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
         HIPCHK(hipStreamSynchronize(s));
         return fail(MPPI_E_DIVERGED, "every sample diverged in some iteration");
     }
+    return MPPI_OK;
+}
+
+int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+              double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs, mppi_stats *stats,
+              void *stream)
+{
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, nullptr, U_new, costs, stats, stream);
+}
+
+int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                 double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp, float *U_new,
+                 float *costs, mppi_stats *stats, void *stream)
+{
+    int rc;
+    if ((rc = qp_check(qp, H))) return rc;
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, U_new, costs, stats, stream);
+}
+
+int mppi_project(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0_shared, const float *U_in,
+                 float *U_out, int K, int H, const mppi_qp *qp, unsigned flags, void *stream)
+{
+    if (!ctx || !scene || !X0 || !U_in || !U_out) return fail(MPPI_E_INVAL, "NULL argument");
+    if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
+    if (K < 1 || K > MPPI_MAX_K || H < 1) return fail(MPPI_E_INVAL, "K=%d or H=%d out of range", K, H);
+    int rc;
+    if ((rc = qp_check(qp, H))) return rc;
+    const bool dev = flags & MPPI_DEVICE_PTRS;
+    const size_t nx0 = x0_shared ? NX : (size_t)K * NX, nu_n = (size_t)K * H * NU;
+    if (!dev && (!all_finite(X0, nx0) || !all_finite(U_in, nu_n))) return fail(MPPI_E_INVAL, "non-finite input");
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const float *dP;
+    int S;
+    if ((rc = qp_matrix(ctx, H, qp->rho, &dP, &S))) return rc;
+    const void *dx0, *dU;
+    if ((rc = stage_in(ctx, S_IN0, X0, nx0 * sizeof(float), dev, s, &dx0))) return rc;
+    if ((rc = stage_in(ctx, S_IN1, U_in, nu_n * sizeof(float), dev, s, &dU))) return rc;
+    void *dout;
+    if ((rc = out_ptr(ctx, S_OUT0, U_out, nu_n * sizeof(float), dev, &dout))) return rc;
+    ProjectArgs pa = {};
+    qp_args(pa, scene, qp, dP, S, K, H);
+    pa.U_in = (const float *)dU;
+    pa.U_out = (float *)dout;
+    pa.x0 = (const float *)dx0;
+    pa.x0_shared = x0_shared ? 1 : 0;
+    launch_project(pa, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(U_out, dout, nu_n * sizeof(float), dev, s))) return rc;
+    if (!dev || (flags & MPPI_SYNC)) HIPCHK(hipStreamSynchronize(s));
     return MPPI_OK;
 }
 

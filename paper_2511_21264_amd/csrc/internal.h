@@ -28,7 +28,7 @@ struct Buf {
 
 enum Slot {
     S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_DIST, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3,
-    S_BTAB, S_BST, S_BIN, S_BNU, S_BCOST, S_BW, S_BCNT, S_BDIST, S_N
+    S_BTAB, S_BST, S_BIN, S_BNU, S_BCOST, S_BW, S_BCNT, S_BDIST, S_QPP, S_QPU, S_N
 };
 
 int mapping_of(unsigned flags);
@@ -62,6 +62,10 @@ struct mppi_ctx {
     // pinned host staging of packed-batch tables
     void *host_tab = nullptr;
     size_t host_tab_cap = 0;
+    // the QP smoothing's (I + rho A^T A)^-1 in buf[S_QPP], for this horizon and penalty
+    int qp_H = 0;
+    double qp_rho = 0.0;
+    int qp_S = 0;
 };
 
 struct mppi_scene {

@@ -66,6 +66,7 @@ struct UpdateArgs {
     float *nu_out;
     double *nu_out64;
     int fp32;               // weighted mean accumulated in FP32 instead of FP64
+    const float *U;         // [K][H][14] the samples as given (QP-smoothed plans), or null: regenerated
 };
 
 // End of a served request: nu := nominal when the plan diverged, copied to
@@ -93,6 +94,27 @@ void launch_rollout_batch(const RolloutArgs *d_tab, const int *d_blk, int nblk, 
 void launch_stats_batch(const StatsArgs *d_tab, int n, int m, hipStream_t s);
 void launch_update_batch(const UpdateArgs *d_tab, const int *d_blk, int nblk, int m, hipStream_t s);
 void launch_stats(const StatsArgs &a, hipStream_t s);
+// QP smoothing of sampled sequences (one workgroup per sample, one wave per
+// joint, one horizon step per lane; H <= 64)
+struct ProjectArgs {
+    const float *P;         // [H][S] (I + rho A^T A)^-1, rows padded with zeros to S floats
+    int S;                  // row stride of P: a multiple of 4, >= H rounded up to 4
+    const float *U_in;      // [K][H][14] samples, or null: nu + sigma * z from the Philox counters
+    float *U_out;           // [K][H][14] projected samples
+    const float *x0;        // [K][NX] start states (commanded positions), or one shared
+    int x0_shared;
+    const float *nu, *sigma;
+    int sigma_per_step;
+    uint32_t key0, key1;
+    int m;
+    int K, H;
+    float dt, u_max, dacc, djerk;  // control step, velocity box, acc_max dt, jerk_max dt^2
+    float pos_lo[NU], pos_hi[NU];
+    float rho, alpha;
+    int iters;
+};
+void launch_project(const ProjectArgs &a, hipStream_t s);
+
 void launch_update(const UpdateArgs &a, hipStream_t s);
 void launch_sample(const DevModel *md, const float *nu, const float *sigma, int sps, uint32_t k0, uint32_t k1,
                    int m, int K, int H, float *U, float *z, uint32_t *words, hipStream_t s);

@@ -715,7 +715,12 @@ __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateA
             const T w = (T)a.weights[j];
             if (w != T(0)) {
                 float u[NU];
-                sample_u(nu_k, sig_k, a.u_max, a.key0, a.key1, (uint32_t)j, (uint32_t)k, (uint32_t)a.m, u);
+                if (a.U) {
+#pragma unroll
+                    for (int d = 0; d < NU; ++d) u[d] = a.U[((long)j * a.H + k) * NU + d];
+                } else {
+                    sample_u(nu_k, sig_k, a.u_max, a.key0, a.key1, (uint32_t)j, (uint32_t)k, (uint32_t)a.m, u);
+                }
 #pragma unroll
                 for (int d = 0; d < NU; ++d) acc[d] = fma(w, (T)u[d], acc[d]);
             }

@@ -88,6 +88,30 @@ int main(void) {
     assert [int(v) for v in out] == want
 
 
+def test_qp_struct_layout_matches_header():
+    import subprocess
+    import tempfile
+    import paper_2511_21264_amd as mp
+    code = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "mppi.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mppi_qp), offsetof(mppi_qp, pos_hi), offsetof(mppi_qp, acc_max),
+         offsetof(mppi_qp, rho), offsetof(mppi_qp, alpha), offsetof(mppi_qp, iters));
+  return 0;
+}'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(code)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    Q = mp.QP
+    assert [int(v) for v in out] == [C.sizeof(Q), Q.pos_hi.offset, Q.acc_max.offset, Q.rho.offset, Q.alpha.offset,
+                                     Q.iters.offset]
+
+
 def test_scene_desc_roundtrip():
     import paper_2511_21264_amd as mp
     sc = W.make_scene(3)

@@ -121,3 +121,17 @@ def test_production_settings_on_sampled_sequences():
         assert np.all(np.abs(v) <= UMAX)
         # smoothing: the projected sequence's steps are far smaller than the noise's
         assert np.abs(np.diff(v)).max() < 0.2 * np.abs(np.diff(vt)).max()
+
+
+def test_single_step_is_the_clamp_to_both_intervals():
+    """H = 1: no difference rows exist, and the velocity row and the one
+    position row bound the same scalar, so the projection is the clamp to
+    the intersection of [-u_max, u_max] and [(pos_lo - q0)/dt, (pos_hi - q0)/dt]."""
+    q0, lo_p, hi_p = 0.3, 0.29, 0.305
+    lo, hi = qp.bounds(q0, DT, UMAX, lo_p, hi_p, 4.0, 60.0, 1)
+    assert lo.shape == hi.shape == (2,)
+    for vt in (-2.0, -0.7, 0.2, 0.45, 3.0):
+        ref = min(max(vt, -UMAX, (lo_p - q0) / DT), UMAX, (hi_p - q0) / DT)
+        args = (q0, DT, UMAX, lo_p, hi_p, 4.0, 60.0)
+        assert abs(qp.project_exact(np.array([vt]), *args)[0] - ref) < 1e-7
+        assert abs(qp.project_admm(np.array([vt]), *args, rho=1.0, iters=500)[0] - ref) < 1e-9
