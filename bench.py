@@ -259,6 +259,68 @@ def bench_serving(mp, ctx, duration, mapping, thr_env_steps):
     return res
 
 
+def bench_qp(mp, ctx, sc, pp, config, plain_ms, n_launch=20, n_plan=5):
+    """The QP smoothing of the samples (Alg. 1 projection step): the
+    projection kernel alone on K sampled sequences of the main workload
+    (one launch = K x 14 joint QPs, `iters` ADMM iterations each), and whole
+    plans with the projection in every iteration against the plain plan."""
+    import numpy as np
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    p = W.qp_params(config)
+    K, H, M = pp["K"], pp["H"], pp["M"]
+    scene = mp.Scene(ctx, sc)
+    x0 = torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(5)
+    U = torch.tensor(rng.normal(0, float(pp["sigma"][0]), (K, H, 14)), dtype=torch.float32, device=dev)
+    out = torch.empty_like(U)
+    for _ in range(3):
+        mp.mppi_project(ctx, scene, x0, U, out, p, x0_shared=True, sync=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n_launch):
+        mp.mppi_project(ctx, scene, x0, U, out, p, x0_shared=True, sync=False)
+    e1.record()
+    torch.cuda.synchronize()
+    launch_ms = e0.elapsed_time(e1) / n_launch
+    # algorithmic flops: the product with (I + rho A^T A)^-1, 2 H^2 per joint
+    # and iteration (the O(H) shuffles, scans and clips are not counted)
+    flop = K * 14 * p["iters"] * 2.0 * H * H
+    nom = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    sig = torch.tensor(pp["sigma"], dtype=torch.float32, device=dev)
+    Un = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    costs = torch.zeros(K, dtype=torch.float32, device=dev)
+
+    def plan():
+        return mp.mppi_plan_qp(ctx, scene, x0, nom, K, H, pp["lam"], sig, p, Un, costs, M=M, seed=pp["seed"])
+
+    for _ in range(2):
+        plan()
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(n_plan):
+        a = time.perf_counter()
+        st = plan()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+    scene.close()
+    return {
+        "kernel": "project_kernel",
+        "iters": p["iters"], "rho": p["rho"], "alpha": p["alpha"],
+        "launch": f"K={K} samples x 14 joints, H={H}",
+        "project_ms_per_launch": launch_ms,
+        "project_flop_per_launch": flop,
+        "project_tflops": flop / (launch_ms * 1e-3) / 1e12,
+        "project_frac_fp32": flop / (launch_ms * 1e-3) / PEAK_FP32,
+        "plan_qp_ms": float(np.median(lat)),
+        "plan_ms": plain_ms,
+        "plan_qp_env_steps_per_s": K * H * M / (float(np.median(lat)) * 1e-3),
+        "ess": st["ess"], "c_min": st["c_min"],
+    }
+
+
 def bench_precision(mp, ctx, n_check=16):
     """Precision study on the 8-box obstacle course (K=4096, H=100): FP32
     rollouts; weights, normaliser and weighted mean in FP64 (default) and in
@@ -449,6 +511,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="trace length of the serving legs (0: skip)")
     ap.add_argument("--no-precision", dest="precision", action="store_false",
                     help="skip the FP64-vs-FP32 weights study on the 8-box workload")
+    ap.add_argument("--no-qp", dest="qp", action="store_false",
+                    help="skip the QP-smoothing leg (projection kernel and plans with the projection)")
     ap.add_argument("--summarize-profiles", default="",
                     help="read rocprofv3 result folders under this path and write the profiles/ summaries")
     args = ap.parse_args()
@@ -572,6 +636,9 @@ def main():
     if args.replans > 0:
         out["replan"] = bench_replan(mp, ctx, sc, pp, n=args.replans, mapping=mapping)
         print(json.dumps({"replan": out["replan"]}), file=sys.stderr, flush=True)
+    if args.qp:
+        out["qp"] = bench_qp(mp, ctx, sc, pp, args.config, out["ms_per_step"])
+        print(json.dumps({"qp": out["qp"]}), file=sys.stderr, flush=True)
     if args.packed_steps > 0:
         out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, mapping)
     if args.serve_seconds > 0:

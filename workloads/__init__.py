@@ -264,3 +264,13 @@ def qp_params(config: int = 2, **overrides):
     p = dict(pos_lo=home - 1.5, pos_hi=home + 1.5, acc_max=4.0, jerk_max=60.0, rho=3.0, alpha=1.6, iters=60)
     p.update(overrides)
     return p
+
+
+def cov_params(config: int = 2, **overrides):
+    """Settings of the plan with covariance adaptation: the learning rate eta
+    shared by the mean and covariance updates, and eps, the variance added
+    to the diagonal after each covariance update ((rad/s)^2; 1e-4 is a
+    standard deviation of 0.01 rad/s against the sampling sigma of 0.3)."""
+    p = dict(eta=0.5, eps=1e-4)
+    p.update(overrides)
+    return p
