@@ -280,6 +280,65 @@ int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const 
                  double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp, float *U_new,
                  float *costs, mppi_stats *stats, void *stream);
 
+/* --------------------------------------------------- covariance adaptation
+ * Alg. 1 samples from N(nu_m, Sigma_m) with a full covariance over the whole
+ * sequence and updates it by Eq. cov_update.  A sequence is the vector of
+ * its n = 14 H joint velocities in step-major order (index 14 k + d, the
+ * [H][14] layout flattened); Sigma is n x n, row-major, double.
+ *   samples:  u_j = clip(nu_m + L_m z_j, +-u_max), L_m the lower Cholesky
+ *             factor of Sigma_m, z_j[14 k + d] the Philox normals of
+ *             mppi_sample (so a diagonal Sigma gives mppi_sample's samples);
+ *   update:   Sigma_{m+1} = (1 - eta) Sigma_m + eta Delta Sigma + eps I,
+ *             Delta Sigma = sum_j w_j (u_j - nu_{m+1})(u_j - nu_{m+1})^T
+ *             / sum_j w_j over the weights of Eq. s_formula (elite set), about
+ *             the updated mean nu_{m+1}; eps >= 0 keeps Sigma positive
+ *             definite when few samples carry weight (the paper adds none).
+ *             With no positive weight (no finite cost) Sigma is kept.
+ * n <= MPPI_COV_MAX_N. */
+#define MPPI_COV_MAX_N 3584
+#define MPPI_E_NOTPD (-8) /* Cholesky: a pivot is not positive (Sigma not positive definite) */
+
+typedef struct mppi_cov {
+    const double *Sigma0; /* [n][n] Sigma_0, or NULL: diag(sigma^2) from the sigma argument */
+    double *Sigma_out;    /* [n][n] receives Sigma_M (nullable) */
+    double eps;           /* >= 0, added to the diagonal after every update */
+} mppi_cov;
+
+/* Sigma_out = (1 - eta) Sigma_in + eta Delta Sigma + eps I from the samples
+ * U[K][n] (float), weights w[K] (double, >= 0, any scale: divided by their
+ * sum) and nu_new[n] (double).  Only the lower triangle of Sigma_in is read;
+ * Sigma_out is written whole and may be Sigma_in.  flags: MPPI_DEVICE_PTRS,
+ * MPPI_SYNC.  Errors: MPPI_E_INVAL (NULL, K < 1, n < 1 or n > MPPI_COV_MAX_N,
+ * eta or eps out of range, negative or non-finite weights in host arrays),
+ * MPPI_E_NOMEM, MPPI_E_DEVICE. */
+int mppi_cov_update(mppi_ctx *ctx, const float *U, const double *w, const double *nu_new, const double *Sigma_in,
+                    double eta, double eps, double *Sigma_out, int K, int n, unsigned flags, void *stream);
+
+/* L (n x n, double, upper triangle zeroed) with L L^T = Sigma; only the
+ * lower triangle of Sigma is read and L may be Sigma.  Synchronises the
+ * stream.  Errors: MPPI_E_NOTPD (the message names the first failing
+ * column; L is then not a factor), MPPI_E_INVAL, MPPI_E_NOMEM,
+ * MPPI_E_DEVICE. */
+int mppi_cholesky(mppi_ctx *ctx, const double *Sigma, double *L, int n, unsigned flags, void *stream);
+
+/* U[K][H][14] = clip(nu + L z_j, +-u_max) for iteration m of `seed`, with
+ * L (n x n, n = 14 H, double, lower triangle read) and nu[H][14] (float);
+ * the product runs in single precision.  Errors: MPPI_E_INVAL,
+ * MPPI_E_NOMEM, MPPI_E_DEVICE. */
+int mppi_sample_full(mppi_ctx *ctx, const float *nu, const double *L, uint64_t seed, int m, int K, int H,
+                     float u_max, float *U, unsigned flags, void *stream);
+
+/* mppi_plan with the full covariance: in each iteration Sigma_m is factored,
+ * the samples clip(nu_m + L_m z_j) are drawn (and smoothed as by
+ * mppi_project when qp is not NULL), rolled out and weighted; nu and Sigma
+ * are updated with opts->eta (0 < eta <= 1).  cov->Sigma0 and
+ * cov->Sigma_out follow MPPI_DEVICE_PTRS like the other arrays.  Arguments
+ * and errors as mppi_plan, plus MPPI_E_NOTPD (some Sigma_m could not be
+ * factored) and n = 14 H <= MPPI_COV_MAX_N.  MPPI_GRAPH is ignored. */
+int mppi_plan_cov(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                  double lambda, const float *sigma, const mppi_opts *opts, const mppi_cov *cov, const mppi_qp *qp,
+                  float *U_new, float *costs, mppi_stats *stats, void *stream);
+
 /* ---------------------------------------------------------------- serving
  * A server replans for many robot cells at once by continuous batching:
  * a worker thread runs MPPI iterations over every active request in one

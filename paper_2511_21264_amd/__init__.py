@@ -20,6 +20,8 @@ NX = 55
 MAX_BOXES = 16
 
 OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY, E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
+E_NOTPD = -8
+COV_MAX_N = 3584
 PENDING = 1
 DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ, MAP_LANE, MAP_TEAM, SUPERSEDE = 1, 2, 4, 8, 16, 32, 64, 128
 MAP_WAVE, FP32_WEIGHTS, GRAPH, MAP_SPLIT = 256, 512, 1024, 2048
@@ -79,6 +81,10 @@ def make_qp(params):
     q.acc_max, q.jerk_max = float(params["acc_max"]), float(params["jerk_max"])
     q.rho, q.alpha, q.iters = float(params["rho"]), float(params["alpha"]), int(params["iters"])
     return q
+
+
+class Cov(C.Structure):
+    _fields_ = [("Sigma0", C.c_void_p), ("Sigma_out", C.c_void_p), ("eps", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -158,6 +164,13 @@ def lib():
             "mppi_project": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, C.c_int, C.c_int, C.POINTER(QP), C.c_uint, _P]),
             "mppi_plan_qp": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts),
                                        C.POINTER(QP), _P, _P, C.POINTER(Stats), _P]),
+            "mppi_cov_update": (C.c_int, [_P, _P, _P, _P, _P, C.c_double, C.c_double, _P, C.c_int, C.c_int,
+                                          C.c_uint, _P]),
+            "mppi_cholesky": (C.c_int, [_P, _P, _P, C.c_int, C.c_uint, _P]),
+            "mppi_sample_full": (C.c_int, [_P, _P, _P, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_float, _P,
+                                           C.c_uint, _P]),
+            "mppi_plan_cov": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts),
+                                        C.POINTER(Cov), C.POINTER(QP), _P, _P, C.POINTER(Stats), _P]),
             "mppi_broadphase": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_float, _P, C.c_uint, _P]),
             "mppi_narrowphase": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, _P, _P, _P, C.c_uint, _P]),
         }
@@ -353,6 +366,65 @@ def mppi_plan_qp(ctx, scene, x0, nominal_U, K, H, lam, sigma, qp, U_new, costs=N
         d["rc"] = rc
         return d
     return None
+
+
+def mppi_plan_cov(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, eps=0.0, Sigma0=None,
+                  Sigma_out=None, qp=None, M=1, seed=0, eta=1.0, n_elite=0, sigma_per_step=False, want_stats=True,
+                  stream=None, mapping=None):
+    """mppi_plan with the full covariance over the sequence (Sigma0[n, n] or
+    None for diag(sigma^2); Sigma_out[n, n] receives Sigma_M), optionally
+    with the QP smoothing (qp: dict or QP).  Synchronises.  Returns a stats
+    dict."""
+    q = None if qp is None else (qp if isinstance(qp, QP) else make_qp(qp))
+    (px0, pnom, psig, pU, pc, pS0, pSo), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32),
+                                                      (sigma, np.float32), (U_new, np.float32), (costs, np.float32),
+                                                      (Sigma0, np.float64), (Sigma_out, np.float64)])
+    flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | _MAPS[mapping]
+    o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
+    cv = Cov(pS0, pSo, float(eps))
+    st = Stats()
+    rc = lib().mppi_plan_cov(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), C.byref(cv),
+                             C.byref(q) if q is not None else None, pU, pc, C.byref(st) if want_stats else None,
+                             _stream(dev, stream))
+    if rc == E_DIVERGED:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    _check(rc)
+    if want_stats:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    return None
+
+
+def mppi_cov_update(ctx, U, w, nu_new, Sigma_in, Sigma_out, eta, eps=0.0, *, sync=True, stream=None):
+    """Sigma_out = (1 - eta) Sigma_in + eta Delta Sigma + eps I from the samples
+    U[K, n] (or [K, H, 14]), weights w[K] and the updated mean nu_new[n]."""
+    K = U.shape[0]
+    n = int(np.prod(U.shape[1:]))
+    (pU, pw, pnu, pSi, pSo), dev = _ptrs([(U, np.float32), (w, np.float64), (nu_new, np.float64),
+                                           (Sigma_in, np.float64), (Sigma_out, np.float64)])
+    flags = (DEVICE_PTRS if dev else 0) | (SYNC if sync else 0)
+    _check(lib().mppi_cov_update(ctx._h, pU, pw, pnu, pSi, float(eta), float(eps), pSo, int(K), n, flags,
+                                 _stream(dev, stream)))
+
+
+def mppi_cholesky(ctx, Sigma, L, *, stream=None):
+    """L (lower, upper zeroed) with L L^T = Sigma; raises MppiError(E_NOTPD)
+    when a pivot is not positive."""
+    n = Sigma.shape[0]
+    (pS, pL), dev = _ptrs([(Sigma, np.float64), (L, np.float64)])
+    _check(lib().mppi_cholesky(ctx._h, pS, pL, int(n), DEVICE_PTRS if dev else 0, _stream(dev, stream)))
+
+
+def mppi_sample_full(ctx, nu, L, seed, m, K, U, u_max, *, sync=True, stream=None):
+    """U[K, H, 14] = clip(nu + L z_j, +-u_max) for iteration m of `seed`."""
+    H = nu.shape[0]
+    (pnu, pL, pU), dev = _ptrs([(nu, np.float32), (L, np.float64), (U, np.float32)])
+    flags = (DEVICE_PTRS if dev else 0) | (SYNC if sync else 0)
+    _check(lib().mppi_sample_full(ctx._h, pnu, pL, int(seed) & 0xFFFFFFFFFFFFFFFF, int(m), int(K), int(H),
+                                  float(u_max), pU, flags, _stream(dev, stream)))
 
 
 def mppi_project(ctx, scene, X0, U_in, U_out, qp, *, x0_shared=False, sync=True, stream=None):

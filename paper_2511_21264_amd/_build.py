@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libmppi.so")
-SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/serve.hip", "csrc/qp.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/serve.hip", "csrc/qp.hip", "csrc/cov.hip"]
 HEADERS = ["csrc/devmodel.h", "csrc/philox.h", "csrc/dynamics.h", "csrc/collision.h", "csrc/step.h",
            "csrc/cost.h", "csrc/team.h", "csrc/kernels.h", "csrc/internal.h", "csrc/sched.h", "../include/mppi.h"]
 

@@ -436,11 +436,13 @@ static void qp_args(ProjectArgs &pa, const mppi_scene *scene, const mppi_qp *qp,
     pa.iters = qp->iters;
 }
 
-// mppi_plan and mppi_plan_qp (qp non-null: the samples are projected and
-// stored, the rollout and the update read them)
+// mppi_plan, mppi_plan_qp and mppi_plan_cov (qp non-null: the samples are
+// projected and stored, the rollout and the update read them; cov non-null:
+// they are drawn with the factor of the full covariance, which is updated
+// after the mean)
 static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
-                     double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp, float *U_new,
-                     float *costs, mppi_stats *stats, void *stream)
+                     double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp,
+                     const mppi_cov *cov, float *U_new, float *costs, mppi_stats *stats, void *stream)
 {
     if (!ctx || !scene || !x0 || !nominal_U || !sigma || !opts || !U_new) return fail(MPPI_E_INVAL, "NULL argument");
     if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
@@ -480,7 +482,26 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
         if ((rc = qp_matrix(ctx, H, qp->rho, &dP, &qpS))) return rc;
         if ((rc = ensure(ctx, S_QPU, (size_t)K * H * NU * sizeof(float), &dqu))) return rc;
     }
-    const bool use_graph = (fl & MPPI_GRAPH) && !qp;
+    const int n = H * NU;
+    void *dS = nullptr, *dA = nullptr, *dL = nullptr, *dL32 = nullptr, *dLi = nullptr, *dZ = nullptr,
+         *dUc = nullptr, *dnu64 = nullptr;
+    if (cov) {
+        const size_t nn = (size_t)n * n;
+        if ((rc = ensure(ctx, S_COVS, nn * sizeof(double), &dS)) || (rc = ensure(ctx, S_COVA, nn * sizeof(double), &dA)) ||
+            (rc = ensure(ctx, S_COVL, nn * sizeof(double), &dL)) || (rc = ensure(ctx, S_COVL32, nn * sizeof(float), &dL32)) ||
+            (rc = ensure(ctx, S_COVLI, 32 * 32 * sizeof(double) + 256, &dLi)) ||
+            (rc = ensure(ctx, S_COVZ, (size_t)K * n * sizeof(float), &dZ)) ||
+            (rc = ensure(ctx, S_COVU, (size_t)K * n * sizeof(float), &dUc)) ||
+            (rc = ensure(ctx, S_NU64, (size_t)n * sizeof(double), &dnu64)))
+            return rc;
+        if (cov->Sigma0)
+            HIPCHK(hipMemcpyAsync(dS, cov->Sigma0, nn * sizeof(double),
+                                  dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        else
+            launch_diag_sigma((const float *)dsig, sps, n, (double *)dS, s);
+    }
+    int *dflag = cov ? (int *)((char *)dLi + 32 * 32 * sizeof(double)) : nullptr;
+    const bool use_graph = (fl & MPPI_GRAPH) && !qp && !cov;
     const bool timing = (fl & MPPI_TIME_KERNELS) && !use_graph;
     const int M = opts->M;
     if (timing) {
@@ -517,6 +538,18 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
             ra.counters = (int *)dcnt;
             ra.diverged = &ctx->st->diverged;
             ra.dist = (float *)ddist;
+            const float *Ucur = nullptr;
+            if (cov) {
+                // factor Sigma_m, then draw clip(nu_m + L_m z_j) for every sample
+                CholArgs ca = {(const double *)dS, (double *)dA, (double *)dL, (float *)dL32, (double *)dLi, dflag,
+                               n, m == 0 ? 1 : 0};
+                launch_cholesky(ca, q);
+                SampleFullArgs sf = {(float *)dZ, (const float *)dL32, (const float *)dnu, (float *)dUc, K, n, k0, k1,
+                                     m, scene->host.u_max};
+                launch_sample_full(sf, q);
+                Ucur = (const float *)dUc;
+                ra.U = Ucur;
+            }
             if (qp) {
                 // this iteration's samples, projected, then rolled out as given
                 ProjectArgs pa = {};
@@ -530,8 +563,10 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
                 pa.key0 = k0;
                 pa.key1 = k1;
                 pa.m = m;
+                pa.U_in = Ucur;
                 launch_project(pa, q);
-                ra.U = (const float *)dqu;
+                Ucur = (const float *)dqu;
+                ra.U = Ucur;
             }
             if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], q));
             launch_rollout(ra, scene->host.n_cmax, q, mapping);
@@ -540,9 +575,15 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
                             (const int *)dcnt, f32};
             launch_stats(sa, q);
             UpdateArgs ua = {(const double *)dw, K, H, (const float *)dnu, (const float *)dsig, sps,
-                             scene->host.u_max, k0, k1, m, opts->eta, ctx->st, (float *)dnu, nullptr, f32,
-                             (const float *)dqu};
+                             scene->host.u_max, k0, k1, m, opts->eta, ctx->st, (float *)dnu, (double *)dnu64, f32,
+                             Ucur};
             launch_update(ua, q);
+            if (cov) {
+                // Sigma_{m+1} about nu_{m+1}, in place
+                CovArgs cv = {Ucur, (const double *)dw, (const double *)dnu64, (const double *)dS, (double *)dS, K, n,
+                              opts->eta, cov->eps};
+                launch_cov_update(cv, q);
+            }
         }
         HIPCHK(hipGetLastError());
         return MPPI_OK;
@@ -607,11 +648,19 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
         HIPCHK(hipMemcpyAsync(U_new, dnu, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToHost, s));
         if (costs) HIPCHK(hipMemcpyAsync(costs, dcost, (size_t)K * sizeof(float), hipMemcpyDeviceToHost, s));
     }
-    const bool sync = !dev || stats || (fl & MPPI_SYNC);
+    int flag_h = n;
+    if (cov) {
+        if (cov->Sigma_out)
+            HIPCHK(hipMemcpyAsync(cov->Sigma_out, dS, (size_t)n * n * sizeof(double),
+                                  dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&flag_h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
+    const bool sync = !dev || stats || (fl & MPPI_SYNC) || cov;
     if (!sync) return MPPI_OK;
     PlanStats hs;
     HIPCHK(hipMemcpyAsync(&hs, ctx->st, sizeof hs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (flag_h < n) return fail(MPPI_E_NOTPD, "covariance not positive definite at column %d", flag_h);
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
         stats->ess = hs.ess;
@@ -652,7 +701,8 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
               double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs, mppi_stats *stats,
               void *stream)
 {
-    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, nullptr, U_new, costs, stats, stream);
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, nullptr, nullptr, U_new, costs, stats,
+                     stream);
 }
 
 int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
@@ -661,7 +711,129 @@ int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const 
 {
     int rc;
     if ((rc = qp_check(qp, H))) return rc;
-    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, U_new, costs, stats, stream);
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, nullptr, U_new, costs, stats, stream);
+}
+
+static int cov_check_n(int n)
+{
+    if (n < 1 || n > MPPI_COV_MAX_N) return fail(MPPI_E_INVAL, "n=%d out of range (1..%d)", n, MPPI_COV_MAX_N);
+    return MPPI_OK;
+}
+
+int mppi_plan_cov(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                  double lambda, const float *sigma, const mppi_opts *opts, const mppi_cov *cov, const mppi_qp *qp,
+                  float *U_new, float *costs, mppi_stats *stats, void *stream)
+{
+    int rc;
+    if (!cov || !opts) return fail(MPPI_E_INVAL, "NULL argument");
+    if (H < 1 || (rc = cov_check_n(H * NU))) return H < 1 ? fail(MPPI_E_INVAL, "H=%d out of range", H) : rc;
+    if (!(cov->eps >= 0) || !std::isfinite(cov->eps)) return fail(MPPI_E_INVAL, "eps must be finite and >= 0");
+    if (!(opts->eta > 0 && opts->eta <= 1)) return fail(MPPI_E_INVAL, "eta must be in (0, 1] with the covariance update");
+    if (qp && (rc = qp_check(qp, H))) return rc;
+    if (cov->Sigma0 && !(opts->flags & MPPI_DEVICE_PTRS)) {
+        const size_t nn = (size_t)H * NU * H * NU;
+        for (size_t i = 0; i < nn; ++i)
+            if (!std::isfinite(cov->Sigma0[i])) return fail(MPPI_E_INVAL, "non-finite Sigma0");
+    }
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, cov, U_new, costs, stats, stream);
+}
+
+int mppi_cov_update(mppi_ctx *ctx, const float *U, const double *w, const double *nu_new, const double *Sigma_in,
+                    double eta, double eps, double *Sigma_out, int K, int n, unsigned flags, void *stream)
+{
+    if (!ctx || !U || !w || !nu_new || !Sigma_in || !Sigma_out) return fail(MPPI_E_INVAL, "NULL argument");
+    int rc;
+    if ((rc = cov_check_n(n))) return rc;
+    if (K < 1 || K > MPPI_MAX_K) return fail(MPPI_E_INVAL, "K=%d out of range", K);
+    if (!(eta >= 0 && eta <= 1)) return fail(MPPI_E_INVAL, "eta must be in [0, 1]");
+    if (!(eps >= 0) || !std::isfinite(eps)) return fail(MPPI_E_INVAL, "eps must be finite and >= 0");
+    const bool dev = flags & MPPI_DEVICE_PTRS;
+    const size_t nn = (size_t)n * n;
+    if (!dev) {
+        for (int j = 0; j < K; ++j)
+            if (!(w[j] >= 0) || !std::isfinite(w[j])) return fail(MPPI_E_INVAL, "weights must be finite and >= 0");
+        if (!all_finite(U, (size_t)K * n)) return fail(MPPI_E_INVAL, "non-finite samples");
+    }
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const void *dU, *dw, *dnu, *dSin;
+    if ((rc = stage_in(ctx, S_IN0, U, (size_t)K * n * sizeof(float), dev, s, &dU)) ||
+        (rc = stage_in(ctx, S_IN1, w, (size_t)K * sizeof(double), dev, s, &dw)) ||
+        (rc = stage_in(ctx, S_NU64, nu_new, (size_t)n * sizeof(double), dev, s, &dnu)) ||
+        (rc = stage_in(ctx, S_COVA, Sigma_in, nn * sizeof(double), dev, s, &dSin)))
+        return rc;
+    void *dout;
+    if ((rc = out_ptr(ctx, S_COVS, Sigma_out, nn * sizeof(double), dev, &dout))) return rc;
+    CovArgs cv = {(const float *)dU, (const double *)dw, (const double *)dnu, (const double *)dSin, (double *)dout, K,
+                  n, eta, eps};
+    launch_cov_update(cv, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(Sigma_out, dout, nn * sizeof(double), dev, s))) return rc;
+    if (!dev || (flags & MPPI_SYNC)) HIPCHK(hipStreamSynchronize(s));
+    return MPPI_OK;
+}
+
+int mppi_cholesky(mppi_ctx *ctx, const double *Sigma, double *L, int n, unsigned flags, void *stream)
+{
+    if (!ctx || !Sigma || !L) return fail(MPPI_E_INVAL, "NULL argument");
+    int rc;
+    if ((rc = cov_check_n(n))) return rc;
+    const bool dev = flags & MPPI_DEVICE_PTRS;
+    const size_t nn = (size_t)n * n;
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const void *dS;
+    if ((rc = stage_in(ctx, S_COVS, Sigma, nn * sizeof(double), dev, s, &dS))) return rc;
+    void *dA, *dLi, *dL;
+    if ((rc = ensure(ctx, S_COVA, nn * sizeof(double), &dA)) ||
+        (rc = ensure(ctx, S_COVLI, 32 * 32 * sizeof(double) + 256, &dLi)))
+        return rc;
+    if ((rc = out_ptr(ctx, S_COVL, L, nn * sizeof(double), dev, &dL))) return rc;
+    int *dflag = (int *)((char *)dLi + 32 * 32 * sizeof(double));
+    CholArgs ca = {(const double *)dS, (double *)dA, (double *)dL, nullptr, (double *)dLi, dflag, n, 1};
+    launch_cholesky(ca, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(L, dL, nn * sizeof(double), dev, s))) return rc;
+    int flag_h = n;
+    HIPCHK(hipMemcpyAsync(&flag_h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flag_h < n) return fail(MPPI_E_NOTPD, "matrix not positive definite at column %d", flag_h);
+    return MPPI_OK;
+}
+
+int mppi_sample_full(mppi_ctx *ctx, const float *nu, const double *L, uint64_t seed, int m, int K, int H,
+                     float u_max, float *U, unsigned flags, void *stream)
+{
+    if (!ctx || !nu || !L || !U) return fail(MPPI_E_INVAL, "NULL argument");
+    int rc;
+    if (H < 1) return fail(MPPI_E_INVAL, "H=%d out of range", H);
+    const int n = H * NU;
+    if ((rc = cov_check_n(n))) return rc;
+    if (K < 1 || K > MPPI_MAX_K) return fail(MPPI_E_INVAL, "K=%d out of range", K);
+    if (!(u_max > 0) || !std::isfinite(u_max)) return fail(MPPI_E_INVAL, "u_max must be finite and > 0");
+    const bool dev = flags & MPPI_DEVICE_PTRS;
+    const size_t nn = (size_t)n * n;
+    if ((rc = set_device(ctx))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const void *dnu, *dL;
+    if ((rc = stage_in(ctx, S_IN0, nu, (size_t)n * sizeof(float), dev, s, &dnu)) ||
+        (rc = stage_in(ctx, S_COVL, L, nn * sizeof(double), dev, s, &dL)))
+        return rc;
+    void *dL32, *dZ, *dout;
+    if ((rc = ensure(ctx, S_COVL32, nn * sizeof(float), &dL32)) ||
+        (rc = ensure(ctx, S_COVZ, (size_t)K * n * sizeof(float), &dZ)))
+        return rc;
+    if ((rc = out_ptr(ctx, S_COVU, U, (size_t)K * n * sizeof(float), dev, &dout))) return rc;
+    // the upper triangle of L is not read: it becomes zero in the single-precision copy
+    launch_to_f32((const double *)dL, (float *)dL32, (long)nn, s);
+    launch_lower_f32((float *)dL32, n, s);
+    SampleFullArgs sf = {(float *)dZ, (const float *)dL32, (const float *)dnu, (float *)dout, K, n,
+                         (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), m, u_max};
+    launch_sample_full(sf, s);
+    HIPCHK(hipGetLastError());
+    if ((rc = copy_out(U, dout, (size_t)K * n * sizeof(float), dev, s))) return rc;
+    if (!dev || (flags & MPPI_SYNC)) HIPCHK(hipStreamSynchronize(s));
+    return MPPI_OK;
 }
 
 int mppi_project(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0_shared, const float *U_in,

@@ -1,0 +1,361 @@
+// Covariance adaptation and full-covariance sampling (Alg. 1: sampling from
+// N(nu_m, Sigma_m); Eqs. mean_update and cov_update with the weights of
+// Eq. s_formula).  A sequence is the n = 14 H vector of its joint velocities
+// in step-major order (index 14 k + d), so Sigma is n x n, row-major, FP64.
+//
+//   cov_syrk_kernel    Sigma' = (1 - eta) Sigma + eta sum_j w_j D_j D_j^T / sum w
+//                      + eps I with D_j = u_j - nu_{m+1}: one workgroup per
+//                      32 x 32 lower tile, the four waves split the samples,
+//                      FP64 MFMA 16x16x4 with the deviation and the weight
+//                      formed in the operand load; each symmetric pair is
+//                      written by one lane (so the update may run in place)
+//   chol_*_kernel      blocked Cholesky in FP64, 32-wide block columns: the
+//                      diagonal block is factored and inverted in LDS by one
+//                      workgroup; then every trailing lower tile (r, c) forms
+//                      the panel blocks A_rb L_bb^-T and A_cb L_bb^-T itself and
+//                      subtracts their product (the tile (r, r) also stores
+//                      its panel block as the factor)
+//   sample_full_kernel U = clip(nu + Z L^T, +-u_max): FP32 MFMA 16x16x4 over
+//                      64 x 64 tiles staged through LDS, skipping the zero
+//                      upper triangle of L
+//
+// MFMA 16x16x4 operand layout: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; result element v of lane l is D[4 (l / 16) + v][l % 16]
+// for f32 and D[l / 16 + 4 v][l % 16] for f64 (measured on gfx950).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "team.h"
+
+namespace mppi {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int CT = 32;  // covariance output tile edge
+constexpr int CB = 32;  // Cholesky block edge
+
+// t -> (row, col) of the t-th lower tile, enumerated row by row
+__device__ __forceinline__ void tri_index(int t, int &row, int &col)
+{
+    int b = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+    while (b * (b + 1) / 2 > t) --b;
+    while ((b + 1) * (b + 2) / 2 <= t) ++b;
+    row = b;
+    col = t - b * (b + 1) / 2;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ covariance update
+__global__ void __launch_bounds__(256) cov_syrk_kernel(CovArgs a)
+{
+    __shared__ double red[4][CT][CT + 1];
+    __shared__ double wred[4];
+    int bi, bl;
+    tri_index(blockIdx.x, bi, bl);
+    const int n = a.n, K = a.K;
+    const int i0 = bi * CT, l0 = bl * CT;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int ia0 = i0 + r, ia1 = ia0 + 16, lb0 = l0 + r, lb1 = lb0 + 16;
+    const double na0 = ia0 < n ? a.nu[ia0] : 0.0, na1 = ia1 < n ? a.nu[ia1] : 0.0;
+    const double nl0 = lb0 < n ? a.nu[lb0] : 0.0, nl1 = lb1 < n ? a.nu[lb1] : 0.0;
+    d4 c00 = {0.0, 0.0, 0.0, 0.0}, c01 = c00, c10 = c00, c11 = c00;
+    double ws = 0.0;
+    // wave wv takes the groups of four samples j0 = 4 wv, 4 wv + 16, ...
+    for (int j0 = 4 * wv; j0 < K; j0 += 16) {
+        const int j = j0 + q;
+        const double w = j < K ? a.w[j] : 0.0;
+        if (r == 0) ws += w;
+        if (__ballot(w != 0.0) == 0) continue;  // no weight in this group (elites only)
+        double x0 = 0.0, x1 = 0.0, y0 = 0.0, y1 = 0.0;
+        if (w != 0.0) {
+            const float *u = a.U + (long)j * n;
+            if (ia0 < n) x0 = (double)u[ia0] - na0;
+            if (ia1 < n) x1 = (double)u[ia1] - na1;
+            if (lb0 < n) y0 = w * ((double)u[lb0] - nl0);
+            if (lb1 < n) y1 = w * ((double)u[lb1] - nl1);
+        }
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, c01, 0, 0, 0);
+        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, c10, 0, 0, 0);
+        c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, c11, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        red[wv][q + 4 * v][r] = c00[v];
+        red[wv][q + 4 * v][16 + r] = c01[v];
+        red[wv][16 + q + 4 * v][r] = c10[v];
+        red[wv][16 + q + 4 * v][16 + r] = c11[v];
+    }
+    ws = wave_sum_f64(ws);
+    if (lane == 0) wred[wv] = ws;
+    __syncthreads();
+    const double wsum = ((wred[0] + wred[1]) + wred[2]) + wred[3];
+    for (int e = threadIdx.x; e < CT * CT; e += 256) {
+        const int ti = e / CT, tl = e % CT;
+        const int i = i0 + ti, l = l0 + tl;
+        if (i >= n || l >= n || (bi == bl && ti < tl)) continue;
+        const double g = ((red[0][ti][tl] + red[1][ti][tl]) + red[2][ti][tl]) + red[3][ti][tl];
+        const double s_old = a.S_in[(long)i * n + l];
+        // no weight at all (no finite cost): Sigma is kept, as the mean is
+        double v = s_old;
+        if (wsum > 0.0) {
+            v = (1.0 - a.eta) * s_old + a.eta * (g / wsum);
+            if (i == l) v += a.eps;
+        }
+        a.S_out[(long)i * n + l] = v;
+        if (i != l) a.S_out[(long)l * n + i] = v;
+    }
+}
+
+void launch_cov_update(const CovArgs &a, hipStream_t s)
+{
+    const int nt = (a.n + CT - 1) / CT;
+    hipLaunchKernelGGL(cov_syrk_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, a);
+}
+
+// ------------------------------------------------------------------ Cholesky
+__global__ void __launch_bounds__(256) chol_init_kernel(CholArgs a)
+{
+    const long n = a.n, N = n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, l = e - i * n;
+        if (l <= i) {
+            a.A[e] = a.S[e];
+        } else {
+            a.L[e] = 0.0;
+            if (a.L32) a.L32[e] = 0.f;
+        }
+    }
+    if (a.reset_flag && blockIdx.x == 0 && threadIdx.x == 0) *a.flag = a.n;
+}
+
+__global__ void __launch_bounds__(1024) chol_diag_kernel(CholArgs a, int b)
+{
+    __shared__ double s[CB][CB + 1];
+    __shared__ double xi[CB][CB + 1];
+    const int n = a.n, c0 = b * CB, nbk = min(CB, n - c0);
+    const int t = threadIdx.x, r = t >> 5, q = t & 31;
+    // rows and columns past n are padded with the identity
+    double v;
+    if (r < nbk && q < nbk)
+        v = q <= r ? a.A[(long)(c0 + r) * n + c0 + q] : 0.0;
+    else
+        v = r == q ? 1.0 : 0.0;
+    s[r][q] = v;
+    __syncthreads();
+    int bad = -1;
+    for (int c = 0; c < CB; ++c) {
+        const double p = s[c][c];
+        if (bad < 0 && !(p > 0.0 && p < INFINITY)) bad = c;
+        const double d = sqrt(p);
+        const double lrc = s[r][c] / d, lqc = s[q][c] / d;
+        __syncthreads();
+        if (q == c && r >= c)
+            s[r][c] = r == c ? d : lrc;
+        else if (q > c && q <= r)
+            s[r][q] -= lrc * lqc;
+        __syncthreads();
+    }
+    if (t == 0 && bad >= 0 && bad < nbk && *a.flag == n) *a.flag = c0 + bad;
+    // the inverse of the factored block, one column per thread
+    if (t < CB) {
+        const int col = t;
+        for (int rr = 0; rr < CB; ++rr) {
+            double acc = rr == col ? 1.0 : 0.0;
+            for (int p = col; p < rr; ++p) acc -= s[rr][p] * xi[p][col];
+            xi[rr][col] = rr < col ? 0.0 : acc / s[rr][rr];
+        }
+    }
+    __syncthreads();
+    a.Linv[r * CB + q] = xi[r][q];
+    if (r < nbk && q <= r) {
+        const long e = (long)(c0 + r) * n + c0 + q;
+        a.L[e] = s[r][q];
+        if (a.L32) a.L32[e] = (float)s[r][q];
+    }
+}
+
+__global__ void __launch_bounds__(256) chol_step_kernel(CholArgs a, int b)
+{
+    __shared__ double li[CB][CB + 1];
+    __shared__ double ar[CB][CB + 1];
+    __shared__ double ac[CB][CB + 1];
+    __shared__ double pr[CB][CB + 1];
+    __shared__ double pc[CB][CB + 1];
+    int rr, cc;
+    tri_index(blockIdx.x, rr, cc);
+    const int rb = b + 1 + rr, cb = b + 1 + cc;
+    const int n = a.n, c0 = b * CB, R0 = rb * CB, C0 = cb * CB;
+    const bool diag = rb == cb;
+    for (int e = threadIdx.x; e < CB * CB; e += 256) {
+        const int x = e / CB, y = e % CB;
+        li[x][y] = a.Linv[e];
+        // block column b is whole: b < the last block column
+        ar[x][y] = R0 + x < n ? a.A[(long)(R0 + x) * n + c0 + y] : 0.0;
+        if (!diag) ac[x][y] = C0 + x < n ? a.A[(long)(C0 + x) * n + c0 + y] : 0.0;
+    }
+    __syncthreads();
+    // panel blocks P = A_blk L_bb^-T: P[x][y] = sum_{p <= y} A_blk[x][p] Linv[y][p]
+    for (int e = threadIdx.x; e < CB * CB; e += 256) {
+        const int x = e / CB, y = e % CB;
+        double s1 = 0.0, s2 = 0.0;
+        for (int p = 0; p <= y; ++p) {
+            s1 = fma(ar[x][p], li[y][p], s1);
+            if (!diag) s2 = fma(ac[x][p], li[y][p], s2);
+        }
+        pr[x][y] = s1;
+        if (!diag) pc[x][y] = s2;
+    }
+    __syncthreads();
+    double(*pcc)[CB + 1] = diag ? pr : pc;
+    for (int e = threadIdx.x; e < CB * CB; e += 256) {
+        const int x = e / CB, y = e % CB;
+        if (R0 + x >= n) continue;
+        if (diag) {
+            const long eL = (long)(R0 + x) * n + c0 + y;
+            a.L[eL] = pr[x][y];
+            if (a.L32) a.L32[eL] = (float)pr[x][y];
+        }
+        if (C0 + y >= n || (diag && y > x)) continue;
+        double s1 = 0.0;
+        for (int p = 0; p < CB; ++p) s1 = fma(pr[x][p], pcc[y][p], s1);
+        a.A[(long)(R0 + x) * n + C0 + y] -= s1;
+    }
+}
+
+void launch_cholesky(const CholArgs &a, hipStream_t s)
+{
+    const long N = (long)a.n * a.n;
+    const int g = (int)std::min<long>((N + 255) / 256, 4096);
+    hipLaunchKernelGGL(chol_init_kernel, dim3(g), dim3(256), 0, s, a);
+    const int nb = (a.n + CB - 1) / CB;
+    for (int b = 0; b < nb; ++b) {
+        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(1024), 0, s, a, b);
+        const int T = nb - b - 1;
+        if (T > 0) hipLaunchKernelGGL(chol_step_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, s, a, b);
+    }
+}
+
+// ------------------------------------------------------------------ sampling
+__global__ void __launch_bounds__(256) normals_kernel(SampleFullArgs a)
+{
+    const long n = a.n, N = (long)a.K * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
+        const long j = e / n;
+        const int i = (int)(e - j * n);
+        a.Z[e] = normal_joint(a.key0, a.key1, (uint32_t)j, (uint32_t)(i / NU), (uint32_t)a.m, i % NU);
+    }
+}
+
+__global__ void __launch_bounds__(256) sample_full_kernel(SampleFullArgs a)
+{
+    __shared__ float zs[64][17];
+    __shared__ float ls[64][17];
+    const int n = a.n, K = a.K;
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63, r = lane & 15, q = lane >> 4;
+    const int wj = wv >> 1, wi = wv & 1;
+    f4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
+    const int pend = min(n, i0 + 64);  // L is lower: columns past the tile's last row are zero
+    const int row = t >> 2, cc = (t & 3) * 4;
+    for (int p0 = 0; p0 < pend; p0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = p0 + cc + u;
+            zs[row][cc + u] = (j0 + row < K && p < n) ? a.Z[(long)(j0 + row) * n + p] : 0.f;
+            ls[row][cc + u] = (i0 + row < n && p < n) ? a.L32[(long)(i0 + row) * n + p] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const float x0 = zs[wj * 32 + r][4 * kk + q], x1 = zs[wj * 32 + 16 + r][4 * kk + q];
+            const float y0 = ls[wi * 32 + r][4 * kk + q], y1 = ls[wi * 32 + 16 + r][4 * kk + q];
+            c00 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y0, c00, 0, 0, 0);
+            c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y1, c01, 0, 0, 0);
+            c10 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y0, c10, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y1, c11, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int ib0 = i0 + wi * 32 + r, ib1 = ib0 + 16;
+    const float nu0 = ib0 < n ? a.nu[ib0] : 0.f, nu1 = ib1 < n ? a.nu[ib1] : 0.f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int ja = j0 + wj * 32 + 4 * q + v, jb = ja + 16;
+        if (ja < K && ib0 < n) a.U[(long)ja * n + ib0] = fminf(fmaxf(nu0 + c00[v], -a.u_max), a.u_max);
+        if (ja < K && ib1 < n) a.U[(long)ja * n + ib1] = fminf(fmaxf(nu1 + c01[v], -a.u_max), a.u_max);
+        if (jb < K && ib0 < n) a.U[(long)jb * n + ib0] = fminf(fmaxf(nu0 + c10[v], -a.u_max), a.u_max);
+        if (jb < K && ib1 < n) a.U[(long)jb * n + ib1] = fminf(fmaxf(nu1 + c11[v], -a.u_max), a.u_max);
+    }
+}
+
+void launch_sample_full(const SampleFullArgs &a, hipStream_t s)
+{
+    const long N = (long)a.K * a.n;
+    const int g = (int)std::min<long>((N + 255) / 256, 8192);
+    hipLaunchKernelGGL(normals_kernel, dim3(g), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sample_full_kernel, dim3((a.n + 63) / 64, (a.K + 63) / 64), dim3(256), 0, s, a);
+}
+
+__global__ void __launch_bounds__(256) diag_sigma_kernel(const float *sigma, int sps, int n, double *S)
+{
+    const long N = (long)n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, l = e - i * n;
+        double v = 0.0;
+        if (i == l) {
+            const double sg = sigma[sps ? i : i % NU];
+            v = sg * sg;
+        }
+        S[e] = v;
+    }
+}
+
+void launch_diag_sigma(const float *sigma, int sps, int n, double *S, hipStream_t s)
+{
+    const long N = (long)n * n;
+    const int g = (int)std::min<long>((N + 255) / 256, 4096);
+    hipLaunchKernelGGL(diag_sigma_kernel, dim3(g), dim3(256), 0, s, sigma, sps, n, S);
+}
+
+__global__ void __launch_bounds__(256) to_f32_kernel(const double *src, float *dst, long N)
+{
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x)
+        dst[e] = (float)src[e];
+}
+
+void launch_to_f32(const double *src, float *dst, long N, hipStream_t s)
+{
+    const int g = (int)std::min<long>((N + 255) / 256, 4096);
+    hipLaunchKernelGGL(to_f32_kernel, dim3(g), dim3(256), 0, s, src, dst, N);
+}
+
+__global__ void __launch_bounds__(256) lower_f32_kernel(float *L, int n)
+{
+    const long N = (long)n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
+        const long i = e / n, l = e - i * n;
+        if (l > i) L[e] = 0.f;
+    }
+}
+
+void launch_lower_f32(float *L, int n, hipStream_t s)
+{
+    const long N = (long)n * n;
+    const int g = (int)std::min<long>((N + 255) / 256, 4096);
+    hipLaunchKernelGGL(lower_f32_kernel, dim3(g), dim3(256), 0, s, L, n);
+}
+
+}  // namespace mppi

@@ -115,6 +115,47 @@ struct ProjectArgs {
 };
 void launch_project(const ProjectArgs &a, hipStream_t s);
 
+// Covariance adaptation and full-covariance sampling over the n = 14 H
+// vector of a sequence (step-major: index 14 k + d)
+struct CovArgs {
+    const float *U;         // [K][n] the samples as rolled out
+    const double *w;        // [K] weights (any positive scale; normalised by their sum)
+    const double *nu;       // [n] the updated mean nu_{m+1}
+    const double *S_in;     // [n][n] Sigma_m (lower triangle read)
+    double *S_out;          // [n][n] Sigma_{m+1}, full symmetric (may be S_in)
+    int K, n;
+    double eta, eps;
+};
+void launch_cov_update(const CovArgs &a, hipStream_t s);
+
+struct CholArgs {
+    const double *S;  // [n][n] (lower triangle read)
+    double *A;        // [n][n] work copy (lower), updated in place
+    double *L;        // [n][n] factor (upper triangle zeroed); may be S
+    float *L32;       // [n][n] the factor in single precision (nullable)
+    double *Linv;     // [32][32] inverse of the current diagonal block
+    int *flag;        // first column with a non-positive pivot, n if none
+    int n;
+    int reset_flag;   // set *flag = n first (else failures of earlier calls stay recorded)
+};
+void launch_cholesky(const CholArgs &a, hipStream_t s);
+
+struct SampleFullArgs {
+    float *Z;           // [K][n] scratch: the Philox normals of iteration m
+    const float *L32;   // [n][n] lower factor, upper triangle zero
+    const float *nu;    // [n] mean
+    float *U;           // [K][n] clip(nu + L z_j)
+    int K, n;
+    uint32_t key0, key1;
+    int m;
+    float u_max;
+};
+void launch_sample_full(const SampleFullArgs &a, hipStream_t s);
+// Sigma = diag(sigma^2) over n = 14 H (sigma[14] or [H][14])
+void launch_diag_sigma(const float *sigma, int sps, int n, double *S, hipStream_t s);
+void launch_to_f32(const double *src, float *dst, long n, hipStream_t s);
+void launch_lower_f32(float *L, int n, hipStream_t s);  // zero the upper triangle
+
 void launch_update(const UpdateArgs &a, hipStream_t s);
 void launch_sample(const DevModel *md, const float *nu, const float *sigma, int sps, uint32_t k0, uint32_t k1,
                    int m, int K, int H, float *U, float *z, uint32_t *words, hipStream_t s);

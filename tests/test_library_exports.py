@@ -112,6 +112,29 @@ int main(void) {
                                      Q.iters.offset]
 
 
+def test_cov_struct_layout_and_constants_match_header():
+    import subprocess
+    import tempfile
+    import paper_2511_21264_amd as mp
+    code = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "mppi.h"
+int main(void) {
+  printf("%zu %zu %zu %d %d\n", sizeof(mppi_cov), offsetof(mppi_cov, Sigma_out), offsetof(mppi_cov, eps),
+         MPPI_COV_MAX_N, MPPI_E_NOTPD);
+  return 0;
+}'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(code)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    V = mp.Cov
+    assert [int(v) for v in out] == [C.sizeof(V), V.Sigma_out.offset, V.eps.offset, mp.COV_MAX_N, mp.E_NOTPD]
+
+
 def test_scene_desc_roundtrip():
     import paper_2511_21264_amd as mp
     sc = W.make_scene(3)
