@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 METRIC = "rollout env-steps/s (K*H) + p50/p99 MPPI replan latency, batched vs plain"
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP64 = 78.6e12           # MI355X FP64 (vector and MFMA), FLOP/s
 
 
 def cpu_baseline(sc, pp, threads, min_s=10.0, max_plans=5):
@@ -321,6 +322,83 @@ def bench_qp(mp, ctx, sc, pp, config, plain_ms, n_launch=20, n_plan=5):
     }
 
 
+def bench_cov(mp, ctx, sc, pp, config, plain_ms, n_launch=20, n_plan=3):
+    """Covariance adaptation and full-covariance sampling at the main
+    workload's sizes (n = 14 H): each step of the path timed alone with
+    algorithmic flops (the covariance update K n (n + 1) in FP64, the
+    triangular sampling product K n (n + 1) in FP32, the Cholesky n^3 / 3
+    in FP64), and whole plans with the full covariance against the plain
+    plan (same K, H, M; eta and eps of the workload)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    cp = W.cov_params(config)
+    K, H, M = pp["K"], pp["H"], pp["M"]
+    n = 14 * H
+    rng = np.random.default_rng(9)
+    U = torch.tensor(rng.normal(0, 0.3, (K, H, 14)), dtype=torch.float32, device=dev)
+    w = torch.tensor(rng.exponential(1.0, K), dtype=torch.float64, device=dev)
+    nu64 = torch.tensor(rng.normal(0, 0.1, n), dtype=torch.float64, device=dev)
+    A = rng.normal(size=(n, n)) / np.sqrt(n)
+    S = torch.tensor(0.09 * (A @ A.T + 0.1 * np.eye(n)), dtype=torch.float64, device=dev)
+    S2 = torch.empty_like(S)
+    L = torch.empty_like(S)
+    nu = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    Us = torch.empty_like(U)
+    u_max = float(sc["u_max"])
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    upd_ms = timed(lambda: mp.mppi_cov_update(ctx, U, w, nu64, S, S2, cp["eta"], cp["eps"], sync=False), n_launch)
+    chol_ms = timed(lambda: mp.mppi_cholesky(ctx, S, L), max(3, n_launch // 4))
+    samp_ms = timed(lambda: mp.mppi_sample_full(ctx, nu, L, 1, 0, K, Us, u_max, sync=False), n_launch)
+    f_upd = float(K) * n * (n + 1)
+    f_samp = float(K) * n * (n + 1)
+    f_chol = n ** 3 / 3.0
+    scene = mp.Scene(ctx, sc)
+    x0 = torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev)
+    nom = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    sig = torch.tensor(pp["sigma"], dtype=torch.float32, device=dev)
+    Un = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    costs = torch.zeros(K, dtype=torch.float32, device=dev)
+    Sout = torch.zeros((n, n), dtype=torch.float64, device=dev)
+
+    def plan():
+        return mp.mppi_plan_cov(ctx, scene, x0, nom, K, H, pp["lam"], sig, Un, costs, eps=cp["eps"], Sigma_out=Sout,
+                                M=M, seed=pp["seed"], eta=cp["eta"])
+
+    plan()
+    lat = []
+    for _ in range(n_plan):
+        a = time.perf_counter()
+        st = plan()
+        lat.append((time.perf_counter() - a) * 1e3)
+    scene.close()
+    return {
+        "n": n, "eta": cp["eta"], "eps": cp["eps"],
+        "cov_update_ms": upd_ms, "cov_update_flop": f_upd,
+        "cov_update_frac_fp64": f_upd / (upd_ms * 1e-3) / PEAK_FP64,
+        "cholesky_ms": chol_ms, "cholesky_flop": f_chol,
+        "sample_full_ms": samp_ms, "sample_full_flop": f_samp,
+        "sample_full_frac_fp32": f_samp / (samp_ms * 1e-3) / PEAK_FP32,
+        "plan_cov_ms": float(np.median(lat)),
+        "plan_ms": plain_ms,
+        "plan_cov_env_steps_per_s": K * H * M / (float(np.median(lat)) * 1e-3),
+        "ess": st["ess"], "c_min": st["c_min"],
+        "note": "cholesky_ms is wall time of a call that synchronises (it reads back the pivot flag)",
+    }
+
+
 def bench_precision(mp, ctx, n_check=16):
     """Precision study on the 8-box obstacle course (K=4096, H=100): FP32
     rollouts; weights, normaliser and weighted mean in FP64 (default) and in
@@ -513,6 +591,8 @@ def main():
                     help="skip the FP64-vs-FP32 weights study on the 8-box workload")
     ap.add_argument("--no-qp", dest="qp", action="store_false",
                     help="skip the QP-smoothing leg (projection kernel and plans with the projection)")
+    ap.add_argument("--no-cov", dest="cov", action="store_false",
+                    help="skip the covariance-adaptation leg (its kernels alone and plans with the full covariance)")
     ap.add_argument("--summarize-profiles", default="",
                     help="read rocprofv3 result folders under this path and write the profiles/ summaries")
     args = ap.parse_args()
@@ -639,6 +719,9 @@ def main():
     if args.qp:
         out["qp"] = bench_qp(mp, ctx, sc, pp, args.config, out["ms_per_step"])
         print(json.dumps({"qp": out["qp"]}), file=sys.stderr, flush=True)
+    if args.cov:
+        out["cov"] = bench_cov(mp, ctx, sc, pp, args.config, out["ms_per_step"])
+        print(json.dumps({"cov": out["cov"]}), file=sys.stderr, flush=True)
     if args.packed_steps > 0:
         out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, mapping)
     if args.serve_seconds > 0:

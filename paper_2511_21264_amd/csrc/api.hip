@@ -489,7 +489,7 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
         const size_t nn = (size_t)n * n;
         if ((rc = ensure(ctx, S_COVS, nn * sizeof(double), &dS)) || (rc = ensure(ctx, S_COVA, nn * sizeof(double), &dA)) ||
             (rc = ensure(ctx, S_COVL, nn * sizeof(double), &dL)) || (rc = ensure(ctx, S_COVL32, nn * sizeof(float), &dL32)) ||
-            (rc = ensure(ctx, S_COVLI, 32 * 32 * sizeof(double) + 256, &dLi)) ||
+            (rc = ensure(ctx, S_COVLI, 2 * 32 * 32 * sizeof(double) + 256, &dLi)) ||
             (rc = ensure(ctx, S_COVZ, (size_t)K * n * sizeof(float), &dZ)) ||
             (rc = ensure(ctx, S_COVU, (size_t)K * n * sizeof(float), &dUc)) ||
             (rc = ensure(ctx, S_NU64, (size_t)n * sizeof(double), &dnu64)))
@@ -500,7 +500,7 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
         else
             launch_diag_sigma((const float *)dsig, sps, n, (double *)dS, s);
     }
-    int *dflag = cov ? (int *)((char *)dLi + 32 * 32 * sizeof(double)) : nullptr;
+    int *dflag = cov ? (int *)((char *)dLi + 2 * 32 * 32 * sizeof(double)) : nullptr;
     const bool use_graph = (fl & MPPI_GRAPH) && !qp && !cov;
     const bool timing = (fl & MPPI_TIME_KERNELS) && !use_graph;
     const int M = opts->M;
@@ -786,10 +786,10 @@ int mppi_cholesky(mppi_ctx *ctx, const double *Sigma, double *L, int n, unsigned
     if ((rc = stage_in(ctx, S_COVS, Sigma, nn * sizeof(double), dev, s, &dS))) return rc;
     void *dA, *dLi, *dL;
     if ((rc = ensure(ctx, S_COVA, nn * sizeof(double), &dA)) ||
-        (rc = ensure(ctx, S_COVLI, 32 * 32 * sizeof(double) + 256, &dLi)))
+        (rc = ensure(ctx, S_COVLI, 2 * 32 * 32 * sizeof(double) + 256, &dLi)))
         return rc;
     if ((rc = out_ptr(ctx, S_COVL, L, nn * sizeof(double), dev, &dL))) return rc;
-    int *dflag = (int *)((char *)dLi + 32 * 32 * sizeof(double));
+    int *dflag = (int *)((char *)dLi + 2 * 32 * 32 * sizeof(double));
     CholArgs ca = {(const double *)dS, (double *)dA, (double *)dL, nullptr, (double *)dLi, dflag, n, 1};
     launch_cholesky(ca, s);
     HIPCHK(hipGetLastError());

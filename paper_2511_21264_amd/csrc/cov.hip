@@ -9,12 +9,13 @@
 //                      FP64 MFMA 16x16x4 with the deviation and the weight
 //                      formed in the operand load; each symmetric pair is
 //                      written by one lane (so the update may run in place)
-//   chol_*_kernel      blocked Cholesky in FP64, 32-wide block columns: the
-//                      diagonal block is factored and inverted in LDS by one
-//                      workgroup; then every trailing lower tile (r, c) forms
-//                      the panel blocks A_rb L_bb^-T and A_cb L_bb^-T itself and
-//                      subtracts their product (the tile (r, r) also stores
-//                      its panel block as the factor)
+//   chol_*_kernel      blocked right-looking Cholesky in FP64, 32-wide block
+//                      columns, one launch per block column: every trailing
+//                      lower tile (r, c) forms the panel blocks A_rb L_bb^-T
+//                      and A_cb L_bb^-T itself and subtracts their product
+//                      (FP64 MFMA); the tile (r, r) also stores its panel block
+//                      as the factor, and the workgroup of the next diagonal
+//                      tile factors and inverts it in LDS once updated
 //   sample_full_kernel U = clip(nu + Z L^T, +-u_max): FP32 MFMA 16x16x4 over
 //                      64 x 64 tiles staged through LDS, skipping the zero
 //                      upper triangle of L
@@ -141,52 +142,89 @@ __global__ void __launch_bounds__(256) chol_init_kernel(CholArgs a)
     if (a.reset_flag && blockIdx.x == 0 && threadIdx.x == 0) *a.flag = a.n;
 }
 
-__global__ void __launch_bounds__(1024) chol_diag_kernel(CholArgs a, int b)
+// Factor the diagonal block held in s (lower triangle valid for rows and
+// columns < nbk) in place, invert it into xi, and store the factor block of
+// columns c0.. into L (and L32) and the inverse into Linv.  256 threads:
+// thread t owns column t % 32 of rows t / 32 + 8 k.
+__device__ void factor_block(double (*s)[CB + 1], double (*xi)[CB + 1], int nbk, int c0, const CholArgs &a,
+                             double *Linv)
 {
-    __shared__ double s[CB][CB + 1];
-    __shared__ double xi[CB][CB + 1];
-    const int n = a.n, c0 = b * CB, nbk = min(CB, n - c0);
-    const int t = threadIdx.x, r = t >> 5, q = t & 31;
-    // rows and columns past n are padded with the identity
-    double v;
-    if (r < nbk && q < nbk)
-        v = q <= r ? a.A[(long)(c0 + r) * n + c0 + q] : 0.0;
-    else
-        v = r == q ? 1.0 : 0.0;
-    s[r][q] = v;
+    const int t = threadIdx.x, q = t & 31, r0 = t >> 5;
+    const int n = a.n;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int r = r0 + 8 * k;
+        if (r >= nbk || q >= nbk)
+            s[r][q] = r == q ? 1.0 : 0.0;  // rows and columns past n: the identity
+        else if (q > r)
+            s[r][q] = 0.0;
+    }
+    __syncthreads();
+    // one sweep over the columns: column c of L, and row c of X = L^-1 by
+    // forward elimination of L X = I (row c of X is final once the columns
+    // before c have been eliminated from it)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xi[r0 + 8 * k][q] = r0 + 8 * k == q ? 1.0 : 0.0;
     __syncthreads();
     int bad = -1;
     for (int c = 0; c < CB; ++c) {
         const double p = s[c][c];
         if (bad < 0 && !(p > 0.0 && p < INFINITY)) bad = c;
-        const double d = sqrt(p);
-        const double lrc = s[r][c] / d, lqc = s[q][c] / d;
+        const double inv = rsqrt(p), d = p * inv;
+        const double lq = s[q][c] * inv;
+        const double xc = xi[c][q] * inv;
+        double lr[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lr[k] = s[r0 + 8 * k][c] * inv;
         __syncthreads();
-        if (q == c && r >= c)
-            s[r][c] = r == c ? d : lrc;
-        else if (q > c && q <= r)
-            s[r][q] -= lrc * lqc;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = r0 + 8 * k;
+            if (q == c && r >= c)
+                s[r][c] = r == c ? d : lr[k];
+            else if (q > c && q <= r)
+                s[r][q] -= lr[k] * lq;
+            if (r == c)
+                xi[c][q] = xc;
+            else if (r > c)
+                xi[r][q] -= lr[k] * xc;
+        }
         __syncthreads();
     }
     if (t == 0 && bad >= 0 && bad < nbk && *a.flag == n) *a.flag = c0 + bad;
-    // the inverse of the factored block, one column per thread
-    if (t < CB) {
-        const int col = t;
-        for (int rr = 0; rr < CB; ++rr) {
-            double acc = rr == col ? 1.0 : 0.0;
-            for (int p = col; p < rr; ++p) acc -= s[rr][p] * xi[p][col];
-            xi[rr][col] = rr < col ? 0.0 : acc / s[rr][rr];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int r = r0 + 8 * k;
+        Linv[r * CB + q] = xi[r][q];
+        if (r < nbk && q <= r) {
+            const long e = (long)(c0 + r) * n + c0 + q;
+            a.L[e] = s[r][q];
+            if (a.L32) a.L32[e] = (float)s[r][q];
         }
-    }
-    __syncthreads();
-    a.Linv[r * CB + q] = xi[r][q];
-    if (r < nbk && q <= r) {
-        const long e = (long)(c0 + r) * n + c0 + q;
-        a.L[e] = s[r][q];
-        if (a.L32) a.L32[e] = (float)s[r][q];
     }
 }
 
+// the first diagonal block (the others are factored by the step before them)
+__global__ void __launch_bounds__(256) chol_diag_kernel(CholArgs a)
+{
+    __shared__ double s[CB][CB + 1];
+    __shared__ double xi[CB][CB + 1];
+    const int n = a.n, nbk = min(CB, n);
+    for (int e = threadIdx.x; e < CB * CB; e += 256) {
+        const int r = e / CB, q = e % CB;
+        if (r < nbk && q <= r) s[r][q] = a.A[(long)r * n + q];
+    }
+    __syncthreads();
+    factor_block(s, xi, nbk, 0, a, a.Linv);
+}
+
+// Step b of the right-looking factorization over the trailing lower tiles
+// (rb, cb), b < cb <= rb: P = A_blk L_bb^-T for block rows rb and cb, then
+// A_{rb,cb} -= P_rb P_cb^T (FP64 MFMA, wave w: output block (w / 2, w % 2)).
+// The tile (rb, rb) stores P_rb as the factor; the tile (b + 1, b + 1),
+// complete after this update, is factored and inverted right away.  The
+// inverse of block b is read from Linv[b & 1] and that of b + 1 written to
+// the other half, so no workgroup of this launch reads what another writes.
 __global__ void __launch_bounds__(256) chol_step_kernel(CholArgs a, int b)
 {
     __shared__ double li[CB][CB + 1];
@@ -199,39 +237,58 @@ __global__ void __launch_bounds__(256) chol_step_kernel(CholArgs a, int b)
     const int rb = b + 1 + rr, cb = b + 1 + cc;
     const int n = a.n, c0 = b * CB, R0 = rb * CB, C0 = cb * CB;
     const bool diag = rb == cb;
+    const double *Li = a.Linv + (b & 1) * CB * CB;
     for (int e = threadIdx.x; e < CB * CB; e += 256) {
         const int x = e / CB, y = e % CB;
-        li[x][y] = a.Linv[e];
+        li[x][y] = Li[e];
         // block column b is whole: b < the last block column
         ar[x][y] = R0 + x < n ? a.A[(long)(R0 + x) * n + c0 + y] : 0.0;
         if (!diag) ac[x][y] = C0 + x < n ? a.A[(long)(C0 + x) * n + c0 + y] : 0.0;
     }
     __syncthreads();
-    // panel blocks P = A_blk L_bb^-T: P[x][y] = sum_{p <= y} A_blk[x][p] Linv[y][p]
-    for (int e = threadIdx.x; e < CB * CB; e += 256) {
-        const int x = e / CB, y = e % CB;
-        double s1 = 0.0, s2 = 0.0;
-        for (int p = 0; p <= y; ++p) {
-            s1 = fma(ar[x][p], li[y][p], s1);
-            if (!diag) s2 = fma(ac[x][p], li[y][p], s2);
-        }
-        pr[x][y] = s1;
-        if (!diag) pc[x][y] = s2;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const int ba = 16 * (wv >> 1), bb = 16 * (wv & 1);
+    d4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1;
+#pragma unroll
+    for (int kk = 0; kk < CB; kk += 4) {
+        const double y = li[bb + lr][kk + lq];
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[ba + lr][kk + lq], y, c1, 0, 0, 0);
+        if (!diag) c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[ba + lr][kk + lq], y, c2, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        pr[ba + lq + 4 * v][bb + lr] = c1[v];
+        if (!diag) pc[ba + lq + 4 * v][bb + lr] = c2[v];
     }
     __syncthreads();
     double(*pcc)[CB + 1] = diag ? pr : pc;
-    for (int e = threadIdx.x; e < CB * CB; e += 256) {
-        const int x = e / CB, y = e % CB;
-        if (R0 + x >= n) continue;
-        if (diag) {
+    d4 cu = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < CB; kk += 4)
+        cu = __builtin_amdgcn_mfma_f64_16x16x4f64(pr[ba + lr][kk + lq], pcc[bb + lr][kk + lq], cu, 0, 0, 0);
+    const bool next = diag && rb == b + 1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int x = ba + lq + 4 * v, y = bb + lr;
+        if (R0 + x < n && C0 + y < n && (!diag || y <= x)) {
+            const long e = (long)(R0 + x) * n + C0 + y;
+            const double nv = a.A[e] - cu[v];
+            a.A[e] = nv;
+            if (next) ar[x][y] = nv;  // ar is no longer read: the products above are done
+        }
+    }
+    if (diag) {
+        for (int e = threadIdx.x; e < CB * CB; e += 256) {
+            const int x = e / CB, y = e % CB;
+            if (R0 + x >= n) continue;
             const long eL = (long)(R0 + x) * n + c0 + y;
             a.L[eL] = pr[x][y];
             if (a.L32) a.L32[eL] = (float)pr[x][y];
         }
-        if (C0 + y >= n || (diag && y > x)) continue;
-        double s1 = 0.0;
-        for (int p = 0; p < CB; ++p) s1 = fma(pr[x][p], pcc[y][p], s1);
-        a.A[(long)(R0 + x) * n + C0 + y] -= s1;
+    }
+    if (next) {
+        __syncthreads();
+        factor_block(ar, ac, min(CB, n - R0), R0, a, a.Linv + ((b + 1) & 1) * CB * CB);
     }
 }
 
@@ -240,11 +297,11 @@ void launch_cholesky(const CholArgs &a, hipStream_t s)
     const long N = (long)a.n * a.n;
     const int g = (int)std::min<long>((N + 255) / 256, 4096);
     hipLaunchKernelGGL(chol_init_kernel, dim3(g), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, a);
     const int nb = (a.n + CB - 1) / CB;
-    for (int b = 0; b < nb; ++b) {
-        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(1024), 0, s, a, b);
+    for (int b = 0; b + 1 < nb; ++b) {
         const int T = nb - b - 1;
-        if (T > 0) hipLaunchKernelGGL(chol_step_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, s, a, b);
+        hipLaunchKernelGGL(chol_step_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, s, a, b);
     }
 }
 

@@ -133,7 +133,7 @@ struct CholArgs {
     double *A;        // [n][n] work copy (lower), updated in place
     double *L;        // [n][n] factor (upper triangle zeroed); may be S
     float *L32;       // [n][n] the factor in single precision (nullable)
-    double *Linv;     // [32][32] inverse of the current diagonal block
+    double *Linv;     // [2][32][32] inverses of the diagonal blocks (block b in half b & 1)
     int *flag;        // first column with a non-positive pivot, n if none
     int n;
     int reset_flag;   // set *flag = n first (else failures of earlier calls stay recorded)
