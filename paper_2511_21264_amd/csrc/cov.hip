@@ -15,7 +15,7 @@
 //                      and A_cb L_bb^-T itself and subtracts their product
 //                      (FP64 MFMA); the tile (r, r) also stores its panel block
 //                      as the factor, and the workgroup of the next diagonal
-//                      tile factors and inverts it in LDS once updated
+//                      tile factors and inverts it in registers once updated
 //   sample_full_kernel U = clip(nu + Z L^T, +-u_max): FP32 MFMA 16x16x4 over
 //                      64 x 64 tiles staged through LDS, skipping the zero
 //                      upper triangle of L
@@ -143,63 +143,70 @@ __global__ void __launch_bounds__(256) chol_init_kernel(CholArgs a)
 }
 
 // Factor the diagonal block held in s (lower triangle valid for rows and
-// columns < nbk) in place, invert it into xi, and store the factor block of
-// columns c0.. into L (and L32) and the inverse into Linv.  256 threads:
-// thread t owns column t % 32 of rows t / 32 + 8 k.
-__device__ void factor_block(double (*s)[CB + 1], double (*xi)[CB + 1], int nbk, int c0, const CholArgs &a,
-                             double *Linv)
+// columns < nbk), invert it, and store the factor block of columns c0.. into
+// L (and L32) and the inverse into Linv.  256 threads: thread t keeps the
+// entries (t / 32 + 8 k, t % 32), k = 0..3, of the block and of its inverse
+// in registers.  Column c: its owners publish it (and row c of the inverse)
+// to LDS, one barrier, then every thread scales and eliminates its entries;
+// the published vectors alternate between two buffers, so one barrier per
+// column suffices.  Row c of X = L^-1 comes from forward elimination of
+// L X = I and is final once the columns before c have been eliminated.
+__device__ void factor_block(const double (*s)[CB + 1], double (*cbuf)[CB], double (*xbuf)[CB], int nbk, int c0,
+                             const CholArgs &a, double *Linv)
 {
     const int t = threadIdx.x, q = t & 31, r0 = t >> 5;
     const int n = a.n;
+    double sv[4], xv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int r = r0 + 8 * k;
         if (r >= nbk || q >= nbk)
-            s[r][q] = r == q ? 1.0 : 0.0;  // rows and columns past n: the identity
-        else if (q > r)
-            s[r][q] = 0.0;
+            sv[k] = r == q ? 1.0 : 0.0;  // rows and columns past n: the identity
+        else
+            sv[k] = q <= r ? s[r][q] : 0.0;
+        xv[k] = r == q ? 1.0 : 0.0;
     }
-    __syncthreads();
-    // one sweep over the columns: column c of L, and row c of X = L^-1 by
-    // forward elimination of L X = I (row c of X is final once the columns
-    // before c have been eliminated from it)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) xi[r0 + 8 * k][q] = r0 + 8 * k == q ? 1.0 : 0.0;
-    __syncthreads();
     int bad = -1;
-    for (int c = 0; c < CB; ++c) {
-        const double p = s[c][c];
-        if (bad < 0 && !(p > 0.0 && p < INFINITY)) bad = c;
-        const double inv = rsqrt(p), d = p * inv;
-        const double lq = s[q][c] * inv;
-        const double xc = xi[c][q] * inv;
-        double lr[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) lr[k] = s[r0 + 8 * k][c] * inv;
-        __syncthreads();
+    for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll 1
+        for (int j = 0; j < 8; ++j) {
+            const int c = 8 * cb + j, par = c & 1;
+            if (q == c) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int r = r0 + 8 * k;
-            if (q == c && r >= c)
-                s[r][c] = r == c ? d : lr[k];
-            else if (q > c && q <= r)
-                s[r][q] -= lr[k] * lq;
-            if (r == c)
-                xi[c][q] = xc;
-            else if (r > c)
-                xi[r][q] -= lr[k] * xc;
+                for (int k = 0; k < 4; ++k) cbuf[par][r0 + 8 * k] = sv[k];
+            }
+            if (r0 == j) xbuf[par][q] = xv[cb];
+            __syncthreads();
+            // every read first (one wait), then a straight-line update by selects
+            const double p = cbuf[par][c], cq = cbuf[par][q], xq = xbuf[par][q];
+            double cr[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cr[k] = cbuf[par][r0 + 8 * k];
+            if (bad < 0 && !(p > 0.0 && p < INFINITY)) bad = c;
+            const double inv = rsqrt(p), d = p * inv;
+            const double lq = cq * inv, xc = xq * inv;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int r = r0 + 8 * k;
+                const double lr = cr[k] * inv;
+                const double su = fma(-lr, lq, sv[k]), xu = fma(-lr, xc, xv[k]);
+                double ns = (q > c && q <= r) ? su : sv[k];
+                ns = (q == c && r >= c) ? (r == c ? d : lr) : ns;
+                sv[k] = ns;
+                xv[k] = r == c ? xc : (r > c ? xu : xv[k]);
+            }
         }
-        __syncthreads();
     }
     if (t == 0 && bad >= 0 && bad < nbk && *a.flag == n) *a.flag = c0 + bad;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int r = r0 + 8 * k;
-        Linv[r * CB + q] = xi[r][q];
+        Linv[r * CB + q] = xv[k];
         if (r < nbk && q <= r) {
             const long e = (long)(c0 + r) * n + c0 + q;
-            a.L[e] = s[r][q];
-            if (a.L32) a.L32[e] = (float)s[r][q];
+            a.L[e] = sv[k];
+            if (a.L32) a.L32[e] = (float)sv[k];
         }
     }
 }
@@ -208,14 +215,14 @@ __device__ void factor_block(double (*s)[CB + 1], double (*xi)[CB + 1], int nbk,
 __global__ void __launch_bounds__(256) chol_diag_kernel(CholArgs a)
 {
     __shared__ double s[CB][CB + 1];
-    __shared__ double xi[CB][CB + 1];
+    __shared__ double cbuf[2][CB], xbuf[2][CB];
     const int n = a.n, nbk = min(CB, n);
     for (int e = threadIdx.x; e < CB * CB; e += 256) {
         const int r = e / CB, q = e % CB;
         if (r < nbk && q <= r) s[r][q] = a.A[(long)r * n + q];
     }
     __syncthreads();
-    factor_block(s, xi, nbk, 0, a, a.Linv);
+    factor_block(s, cbuf, xbuf, nbk, 0, a, a.Linv);
 }
 
 // Step b of the right-looking factorization over the trailing lower tiles
@@ -232,6 +239,7 @@ __global__ void __launch_bounds__(256) chol_step_kernel(CholArgs a, int b)
     __shared__ double ac[CB][CB + 1];
     __shared__ double pr[CB][CB + 1];
     __shared__ double pc[CB][CB + 1];
+    __shared__ double cbuf[2][CB], xbuf[2][CB];
     int rr, cc;
     tri_index(blockIdx.x, rr, cc);
     const int rb = b + 1 + rr, cb = b + 1 + cc;
@@ -288,7 +296,7 @@ __global__ void __launch_bounds__(256) chol_step_kernel(CholArgs a, int b)
     }
     if (next) {
         __syncthreads();
-        factor_block(ar, ac, min(CB, n - R0), R0, a, a.Linv + ((b + 1) & 1) * CB * CB);
+        factor_block(ar, cbuf, xbuf, min(CB, n - R0), R0, a, a.Linv + ((b + 1) & 1) * CB * CB);
     }
 }
 
