@@ -280,6 +280,64 @@ int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const 
                  double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp, float *U_new,
                  float *costs, mppi_stats *stats, void *stream);
 
+/* mppi_plan that also returns the best sequence: U_best[H][14] receives the
+ * lowest-cost sample of the final iteration (Alg. 1 returns it with nu_M),
+ * or that iteration's mean when no sample had a finite cost.  U_best lives
+ * on the same side as U_new.  Arguments, flags and errors as mppi_plan
+ * (MPPI_GRAPH is ignored). */
+int mppi_plan_best(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                   double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *U_best, float *costs,
+                   mppi_stats *stats, void *stream);
+
+/* ----------------------------------------------- closed-loop ball transport
+ * Receding-horizon execution of the planner on the ball task (the pick and
+ * move phases of Sec. IV-B; the experiments' success metric).  Replan r:
+ * plan from the plant state with the phase's scene (`pick`: a scene whose
+ * object-to-target weight is 0; `move`: every term), seed opts->seed + r,
+ * warm-started with the previous mean shifted by n_exec control steps (the
+ * last row repeated); average the first n_avg steps of the best sequence
+ * and execute that command for n_exec control steps in the simulator (the
+ * plant, with the physics of `move`).  After every executed step, in order:
+ *   an arm-arm or arm-box pair at negative distance -> failure (collision);
+ *   pick -> move once |pad midpoint - (p_ball - (0,0,eps))| < grasp_tol and
+ *     | |p1 - p2| - l_ball | < width_tol;
+ *   in move: the ball above lift_z marks it lifted; lifted and below drop_z
+ *     -> failure (fallen); |p_ball - goal| < goal_tol -> success;
+ *   simulated time >= t_max -> failure (timeout).
+ * Host arrays only (x0[MPPI_NX], sigma, x_final[MPPI_NX] nullable; u_exec
+ * [max_replans][14] and x_hist[max_replans][MPPI_NX], nullable, receive each
+ * replan's executed command and the state after its execution and need
+ * max_replans > 0).  opts: M, seed, eta, n_elite, sigma-per-step and mapping
+ * flags.  Errors: MPPI_E_INVAL, and those of mppi_plan_best and
+ * mppi_simulate. */
+typedef struct mppi_episode_opts {
+    int n_avg;        /* leading steps of the best sequence averaged, 1..H */
+    int n_exec;       /* control steps the averaged command runs, 1..H */
+    int max_replans;  /* cap on replans (0: until an outcome) */
+    int pad;
+    double grasp_tol, width_tol, goal_tol; /* m */
+    double lift_z, drop_z;                 /* m */
+    double t_max;                          /* s */
+} mppi_episode_opts;
+
+typedef struct mppi_episode_result {
+    int status;     /* 1 success, -1 collision, -2 timeout, -3 ball fell, 0 replan cap reached first */
+    int phase;      /* 0 pick, 1 move, at the end */
+    int n_replans;
+    int n_steps;    /* executed control steps */
+    double t_end;   /* simulated time at the end (s): the task time of a success */
+    double t_switch; /* simulated time of the pick -> move switch, -1 if none */
+    double t_comp_mean_ms, t_comp_std_ms, t_comp_max_ms; /* wall time per replan (synchronised plan call) */
+    double goal_dist_min; /* closest approach of the ball to the goal (m) */
+    double ball_final[3];
+    int n_diverged; /* replans in which no sample had a finite cost */
+    int pad2;
+} mppi_episode_result;
+
+int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_scene *move, const float *x0, int K, int H,
+                 double lambda, const float *sigma, const mppi_opts *opts, const mppi_episode_opts *eo,
+                 float *x_final, float *u_exec, float *x_hist, mppi_episode_result *res, void *stream);
+
 /* --------------------------------------------------- covariance adaptation
  * Alg. 1 samples from N(nu_m, Sigma_m) with a full covariance over the whole
  * sequence and updates it by Eq. cov_update.  A sequence is the vector of

@@ -87,6 +87,27 @@ class Cov(C.Structure):
     _fields_ = [("Sigma0", C.c_void_p), ("Sigma_out", C.c_void_p), ("eps", C.c_double)]
 
 
+class EpisodeOpts(C.Structure):
+    _fields_ = [("n_avg", C.c_int), ("n_exec", C.c_int), ("max_replans", C.c_int), ("pad", C.c_int),
+                ("grasp_tol", C.c_double), ("width_tol", C.c_double), ("goal_tol", C.c_double),
+                ("lift_z", C.c_double), ("drop_z", C.c_double), ("t_max", C.c_double)]
+
+
+class EpisodeResult(C.Structure):
+    _fields_ = [("status", C.c_int), ("phase", C.c_int), ("n_replans", C.c_int), ("n_steps", C.c_int),
+                ("t_end", C.c_double), ("t_switch", C.c_double), ("t_comp_mean_ms", C.c_double),
+                ("t_comp_std_ms", C.c_double), ("t_comp_max_ms", C.c_double), ("goal_dist_min", C.c_double),
+                ("ball_final", C.c_double * 3), ("n_diverged", C.c_int), ("pad2", C.c_int)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("pad")}
+        d["ball_final"] = list(self.ball_final)
+        return d
+
+
+EPISODE_STATUS = {1: "success", -1: "collision", -2: "timeout", -3: "ball fell", 0: "replan cap"}
+
+
 class Stats(C.Structure):
     _fields_ = [
         ("ess", C.c_double), ("c_min", C.c_double), ("best", C.c_int), ("n_nonfinite", C.c_int),
@@ -171,6 +192,10 @@ def lib():
                                            C.c_uint, _P]),
             "mppi_plan_cov": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts),
                                         C.POINTER(Cov), C.POINTER(QP), _P, _P, C.POINTER(Stats), _P]),
+            "mppi_plan_best": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts), _P, _P,
+                                         _P, C.POINTER(Stats), _P]),
+            "mppi_episode": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts),
+                                       C.POINTER(EpisodeOpts), _P, _P, _P, C.POINTER(EpisodeResult), _P]),
             "mppi_broadphase": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_float, _P, C.c_uint, _P]),
             "mppi_narrowphase": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, _P, _P, _P, C.c_uint, _P]),
         }
@@ -366,6 +391,66 @@ def mppi_plan_qp(ctx, scene, x0, nominal_U, K, H, lam, sigma, qp, U_new, costs=N
         d["rc"] = rc
         return d
     return None
+
+
+def mppi_plan_best(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, U_best, costs=None, *, M=1, seed=0, eta=1.0,
+                   n_elite=0, sigma_per_step=False, want_stats=True, sync=False, stream=None, mapping=None):
+    """mppi_plan that also returns the best sequence of the final iteration
+    in U_best[H, 14].  Returns a stats dict (or None)."""
+    (px0, pnom, psig, pU, pB, pc), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32), (sigma, np.float32),
+                                                 (U_new, np.float32), (U_best, np.float32), (costs, np.float32)])
+    flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | (SYNC if sync else 0) | \
+        _MAPS[mapping]
+    o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
+    st = Stats()
+    rc = lib().mppi_plan_best(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), pU, pB, pc,
+                              C.byref(st) if want_stats else None, _stream(dev, stream))
+    if rc == E_DIVERGED:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    _check(rc)
+    if want_stats:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    return None
+
+
+def make_episode_opts(params):
+    """An mppi_episode_opts from a dict (see workloads.episode_params)."""
+    e = EpisodeOpts()
+    for f, _ in EpisodeOpts._fields_:
+        if f != "pad":
+            setattr(e, f, params[f])
+    return e
+
+
+def mppi_episode(ctx, pick, move, x0, K, H, lam, sigma, eo, *, M=1, seed=0, eta=1.0, n_elite=0,
+                 sigma_per_step=False, mapping=None, record=False, stream=None):
+    """Closed-loop run of the ball task (host arrays).  eo: dict or
+    EpisodeOpts.  Returns the result dict, with x_final and, when `record`,
+    u_exec[n_replans, 14] and x_hist[n_replans, NX] (needs max_replans > 0)."""
+    e = eo if isinstance(eo, EpisodeOpts) else make_episode_opts(eo)
+    x0 = np.ascontiguousarray(x0, dtype=np.float32)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float32)
+    xf = np.zeros(NX, np.float32)
+    ue = np.zeros((max(e.max_replans, 1), 14), np.float32) if record else None
+    xh = np.zeros((max(e.max_replans, 1), NX), np.float32) if record else None
+    flags = (SIGMA_PER_STEP if sigma_per_step else 0) | _MAPS[mapping]
+    o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
+    r = EpisodeResult()
+    _check(lib().mppi_episode(ctx._h, pick._h, move._h, x0.ctypes.data, int(K), int(H), float(lam),
+                              sigma.ctypes.data, C.byref(o), C.byref(e), xf.ctypes.data,
+                              ue.ctypes.data if record else None, xh.ctypes.data if record else None, C.byref(r),
+                              stream))
+    d = r.as_dict()
+    d["outcome"] = EPISODE_STATUS.get(d["status"], "?")
+    d["x_final"] = xf
+    if record:
+        d["u_exec"] = ue[:r.n_replans]
+        d["x_hist"] = xh[:r.n_replans]
+    return d
 
 
 def mppi_plan_cov(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, eps=0.0, Sigma0=None,

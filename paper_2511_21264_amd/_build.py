@@ -5,9 +5,10 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libmppi.so")
-SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/serve.hip", "csrc/qp.hip", "csrc/cov.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/api.hip", "csrc/serve.hip", "csrc/qp.hip", "csrc/cov.hip", "csrc/episode.hip"]
 HEADERS = ["csrc/devmodel.h", "csrc/philox.h", "csrc/dynamics.h", "csrc/collision.h", "csrc/step.h",
-           "csrc/cost.h", "csrc/team.h", "csrc/kernels.h", "csrc/internal.h", "csrc/sched.h", "../include/mppi.h"]
+           "csrc/cost.h", "csrc/team.h", "csrc/kernels.h", "csrc/internal.h", "csrc/sched.h", "csrc/episode.h",
+           "../include/mppi.h"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

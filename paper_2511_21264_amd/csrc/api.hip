@@ -442,7 +442,8 @@ static void qp_args(ProjectArgs &pa, const mppi_scene *scene, const mppi_qp *qp,
 // after the mean)
 static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
                      double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp,
-                     const mppi_cov *cov, float *U_new, float *costs, mppi_stats *stats, void *stream)
+                     const mppi_cov *cov, float *U_new, float *costs, mppi_stats *stats, void *stream,
+                     float *U_best)
 {
     if (!ctx || !scene || !x0 || !nominal_U || !sigma || !opts || !U_new) return fail(MPPI_E_INVAL, "NULL argument");
     if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
@@ -501,7 +502,10 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
             launch_diag_sigma((const float *)dsig, sps, n, (double *)dS, s);
     }
     int *dflag = cov ? (int *)((char *)dLi + 2 * 32 * 32 * sizeof(double)) : nullptr;
-    const bool use_graph = (fl & MPPI_GRAPH) && !qp && !cov;
+    // the best sequence of the last iteration goes to U_best (same side as U_new)
+    void *dbest = nullptr;
+    if (U_best && (rc = out_ptr(ctx, S_OUT3, U_best, (size_t)H * NU * sizeof(float), dev, &dbest))) return rc;
+    const bool use_graph = (fl & MPPI_GRAPH) && !qp && !cov && !U_best;
     const bool timing = (fl & MPPI_TIME_KERNELS) && !use_graph;
     const int M = opts->M;
     if (timing) {
@@ -574,6 +578,11 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
             StatsArgs sa = {(const float *)dcost, K, 1.0 / lambda, n_elite, (double *)dw, ctx->st, m,
                             (const int *)dcnt, f32};
             launch_stats(sa, q);
+            if (dbest && m == M - 1) {
+                BestArgs ba = {ctx->st, Ucur, (const float *)dnu, (const float *)dsig, sps, scene->host.u_max, k0, k1,
+                               m, H, (float *)dbest};
+                launch_best(ba, q);
+            }
             UpdateArgs ua = {(const double *)dw, K, H, (const float *)dnu, (const float *)dsig, sps,
                              scene->host.u_max, k0, k1, m, opts->eta, ctx->st, (float *)dnu, (double *)dnu64, f32,
                              Ucur};
@@ -648,6 +657,7 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
         HIPCHK(hipMemcpyAsync(U_new, dnu, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToHost, s));
         if (costs) HIPCHK(hipMemcpyAsync(costs, dcost, (size_t)K * sizeof(float), hipMemcpyDeviceToHost, s));
     }
+    if (dbest && (rc = copy_out(U_best, dbest, (size_t)H * NU * sizeof(float), dev, s))) return rc;
     int flag_h = n;
     if (cov) {
         if (cov->Sigma_out)
@@ -702,7 +712,16 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
               void *stream)
 {
     return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, nullptr, nullptr, U_new, costs, stats,
-                     stream);
+                     stream, nullptr);
+}
+
+int mppi_plan_best(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                   double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *U_best, float *costs,
+                   mppi_stats *stats, void *stream)
+{
+    if (!U_best) return fail(MPPI_E_INVAL, "NULL argument");
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, nullptr, nullptr, U_new, costs, stats,
+                     stream, U_best);
 }
 
 int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
@@ -711,7 +730,8 @@ int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const 
 {
     int rc;
     if ((rc = qp_check(qp, H))) return rc;
-    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, nullptr, U_new, costs, stats, stream);
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, nullptr, U_new, costs, stats, stream,
+                     nullptr);
 }
 
 static int cov_check_n(int n)
@@ -735,7 +755,8 @@ int mppi_plan_cov(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const
         for (size_t i = 0; i < nn; ++i)
             if (!std::isfinite(cov->Sigma0[i])) return fail(MPPI_E_INVAL, "non-finite Sigma0");
     }
-    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, cov, U_new, costs, stats, stream);
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, cov, U_new, costs, stats, stream,
+                     nullptr);
 }
 
 int mppi_cov_update(mppi_ctx *ctx, const float *U, const double *w, const double *nu_new, const double *Sigma_in,

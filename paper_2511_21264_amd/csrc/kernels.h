@@ -156,6 +156,23 @@ void launch_diag_sigma(const float *sigma, int sps, int n, double *S, hipStream_
 void launch_to_f32(const double *src, float *dst, long n, hipStream_t s);
 void launch_lower_f32(float *L, int n, hipStream_t s);  // zero the upper triangle
 
+// The best sample's sequence of an iteration (Alg. 1 returns the lowest-cost
+// sequence of the final iteration): row st->best of the stored samples, or
+// regenerated from (nu, sigma, the Philox counters); the mean when no sample
+// had a finite cost
+struct BestArgs {
+    const PlanStats *st;
+    const float *U;      // [K][H][14] stored samples, or null
+    const float *nu;     // [H][14] the mean the samples were drawn around
+    const float *sigma;
+    int sigma_per_step;
+    float u_max;
+    uint32_t key0, key1;
+    int m, H;
+    float *out;          // [H][14]
+};
+void launch_best(const BestArgs &a, hipStream_t s);
+
 void launch_update(const UpdateArgs &a, hipStream_t s);
 void launch_sample(const DevModel *md, const float *nu, const float *sigma, int sps, uint32_t k0, uint32_t k1,
                    int m, int K, int H, float *U, float *z, uint32_t *words, hipStream_t s);

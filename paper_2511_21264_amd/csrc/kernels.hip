@@ -745,6 +745,31 @@ __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateA
     }
 }
 
+__global__ void __launch_bounds__(64) best_kernel(BestArgs a)
+{
+    const int j = a.st->best;
+    for (int k = threadIdx.x; k < a.H; k += 64) {
+        float u[NU];
+        if (j < 0) {
+#pragma unroll
+            for (int d = 0; d < NU; ++d) u[d] = a.nu[k * NU + d];
+        } else if (a.U) {
+#pragma unroll
+            for (int d = 0; d < NU; ++d) u[d] = a.U[((long)j * a.H + k) * NU + d];
+        } else {
+            sample_u(a.nu + k * NU, a.sigma + (a.sigma_per_step ? k * NU : 0), a.u_max, a.key0, a.key1, (uint32_t)j,
+                     (uint32_t)k, (uint32_t)a.m, u);
+        }
+#pragma unroll
+        for (int d = 0; d < NU; ++d) a.out[k * NU + d] = u[d];
+    }
+}
+
+void launch_best(const BestArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(best_kernel, dim3(1), dim3(64), 0, s, a);
+}
+
 void launch_update(const UpdateArgs &a, hipStream_t s)
 {
     if (a.fp32)

@@ -135,6 +135,31 @@ int main(void) {
     assert [int(v) for v in out] == [C.sizeof(V), V.Sigma_out.offset, V.eps.offset, mp.COV_MAX_N, mp.E_NOTPD]
 
 
+def test_episode_struct_layouts_match_header():
+    import subprocess
+    import tempfile
+    import paper_2511_21264_amd as mp
+    code = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "mppi.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mppi_episode_opts), offsetof(mppi_episode_opts, grasp_tol),
+         offsetof(mppi_episode_opts, t_max), sizeof(mppi_episode_result), offsetof(mppi_episode_result, t_end),
+         offsetof(mppi_episode_result, ball_final), offsetof(mppi_episode_result, n_diverged));
+  return 0;
+}'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(code)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    E, R = mp.EpisodeOpts, mp.EpisodeResult
+    assert [int(v) for v in out] == [C.sizeof(E), E.grasp_tol.offset, E.t_max.offset, C.sizeof(R), R.t_end.offset,
+                                     R.ball_final.offset, R.n_diverged.offset]
+
+
 def test_scene_desc_roundtrip():
     import paper_2511_21264_amd as mp
     sc = W.make_scene(3)

@@ -274,3 +274,29 @@ def cov_params(config: int = 2, **overrides):
     p = dict(eta=0.5, eps=1e-4)
     p.update(overrides)
     return p
+
+
+def episode_scenes(config: int = 2, index: int = 0, **overrides):
+    """The two cost configurations of the closed-loop ball task (Sec. IV-B
+    phases): pick, without the object-to-target term (w_goal = 0), and move,
+    with every term; same world, same physics."""
+    move = make_scene(config, index, **overrides)
+    pick = dict(move)
+    pick["w_goal"] = 0.0
+    return pick, move
+
+
+def episode_params(config: int = 2, **overrides):
+    """Executor settings of the closed-loop ball task: the first n_avg steps
+    of the best sequence averaged and run for n_exec control steps per
+    replan; grasp detected within 3 cm of the grasp point and 2 cm of the
+    pad distance; success within 5 cm of the goal; the ball counts as lifted
+    5 cm above its resting height and as fallen back below 1 cm above it;
+    timeout t_max (the experiments use 120 s; shorter here); iterations M
+    per warm-started replan."""
+    sc = make_scene(config)
+    r = float(sc["ball_r"])
+    p = dict(n_avg=2, n_exec=2, max_replans=0, grasp_tol=0.03, width_tol=0.02, goal_tol=0.05,
+             lift_z=r + 0.05, drop_z=r + 0.01, t_max=10.0, M=3)
+    p.update(overrides)
+    return p
