@@ -399,6 +399,52 @@ def bench_cov(mp, ctx, sc, pp, config, plain_ms, n_launch=20, n_plan=3):
     }
 
 
+def bench_episode(mp, ctx, runs=((2, 8), (3, 4)), t_max=10.0):
+    """Closed-loop ball transport (receding-horizon execution; pick and move
+    phases; the experiments' success metric: collision, timeout or a fallen
+    ball fail a run): for each (config, n) the first n seeded scenes of the
+    workload at its K and H, M warm-started iterations per replan.  Success
+    rate, task time (simulated seconds to the goal) over the successes, and
+    the compute time per replan pooled over every replan (mean, std)."""
+    import numpy as np
+    import workloads as W
+    out = {}
+    for cfg, n in runs:
+        pp = W.plan_params(cfg)
+        ep = W.episode_params(cfg, t_max=t_max)
+        res = []
+        for i in range(n):
+            pk, mv = W.episode_scenes(cfg, i)
+            spk, smv = mp.Scene(ctx, pk), mp.Scene(ctx, mv)
+            r = mp.mppi_episode(ctx, spk, smv, W.initial_state(mv), pp["K"], pp["H"], pp["lam"], pp["sigma"], ep,
+                                M=ep["M"], seed=1000 * cfg + i)
+            spk.close()
+            smv.close()
+            res.append(r)
+            print(json.dumps({"episode": cfg, "scene": i, "outcome": r["outcome"], "t_end": r["t_end"],
+                              "replans": r["n_replans"], "t_comp_mean_ms": r["t_comp_mean_ms"]}),
+                  file=sys.stderr, flush=True)
+        ok = [r for r in res if r["status"] == 1]
+        nrep = np.array([r["n_replans"] for r in res], dtype=float)
+        mu = np.array([r["t_comp_mean_ms"] for r in res])
+        sd = np.array([r["t_comp_std_ms"] for r in res])
+        m_all = float((nrep * mu).sum() / nrep.sum())
+        v_all = float((nrep * (sd ** 2 + mu ** 2)).sum() / nrep.sum() - m_all ** 2)
+        tt = np.array([r["t_end"] for r in ok])
+        out[f"config{cfg}"] = {
+            "runs": n, "K": pp["K"], "H": pp["H"], "M_per_replan": ep["M"], "n_avg": ep["n_avg"],
+            "n_exec": ep["n_exec"], "t_max_s": t_max,
+            "success_rate": len(ok) / n,
+            "outcomes": {o: sum(r["outcome"] == o for r in res) for o in sorted({r["outcome"] for r in res})},
+            "task_time_mean_s": float(tt.mean()) if len(tt) else None,
+            "task_time_std_s": float(tt.std()) if len(tt) else None,
+            "t_comp_mean_ms": m_all, "t_comp_std_ms": float(np.sqrt(max(v_all, 0.0))),
+            "t_comp_max_ms": float(max(r["t_comp_max_ms"] for r in res)),
+            "replans_total": int(nrep.sum()),
+        }
+    return out
+
+
 def bench_precision(mp, ctx, n_check=16):
     """Precision study on the 8-box obstacle course (K=4096, H=100): FP32
     rollouts; weights, normaliser and weighted mean in FP64 (default) and in
@@ -487,10 +533,86 @@ def sources_hash():
     return h.hexdigest()
 
 
+# bench.py arguments of the profiled runs: the main workload alone (the
+# rollout kernel's time, traffic and issued operations), and the QP and
+# covariance legs (their kernels' times)
+PROFILE_ARGS_MAIN = ("--steps 3 --warmup 1 --no-cpu-baseline --packed-steps 0 --serve-seconds 0 --no-precision "
+                     "--replans 0 --no-qp --no-cov --no-episodes")
+PROFILE_ARGS_NEXT = ("--steps 1 --warmup 0 --no-cpu-baseline --packed-steps 0 --serve-seconds 0 --no-precision "
+                     "--replans 0 --no-episodes")
+
+
+def profile_meta():
+    b = f"python3 bench.py {PROFILE_ARGS_MAIN}"
+    bn = f"python3 bench.py {PROFILE_ARGS_NEXT}"
+    return {
+        "title": "rollout_split_kernel<4> (two waves per sample), K=1024, H=64 obstacle workload: kernel time and "
+                 "HBM traffic",
+        "file": "rollout_split_c2.md", "mapping": "split", "K": 1024, "H": 64,
+        "kernel_like": "%rollout_split_kernel<4>%", "calib_copy_bytes": 256 << 20,
+        "commands": [
+            f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run -- {b}",
+            f"timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/fetch -o run -- {b}",
+            f"timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/write -o run -- {b}",
+            f"timeout -s KILL 120 rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU -d gpurun_out/prof/valu "
+            f"-o run -- {b}",
+            "timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/cfetch -o run -- python3 bench.py "
+            "--calib-copy-mb 256",
+            "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/cwrite -o run -- python3 bench.py "
+            "--calib-copy-mb 256",
+            "python3 bench.py --summarize-profiles gpurun_out/prof",
+        ],
+        "next_commands": [
+            f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace_next -o run -- {bn}",
+            "python3 bench.py --summarize-profiles gpurun_out/prof",
+        ],
+    }
+
+
+def summarize_next(base, meta):
+    """Kernel times of the QP and covariance legs (K=1024, H=64: n = 896)
+    with each kernel's algorithmic flops against its peak."""
+    import sqlite3
+    import glob
+    f = glob.glob(os.path.join(base, "trace_next", "**", "*results.db"), recursive=True)
+    if not f:
+        return
+    con = sqlite3.connect(f[0])
+    rows = con.execute("select name, total_calls, total_duration, average from top_kernels "
+                       "order by total_duration desc").fetchall()
+    K, H, n, iters = 1024, 64, 896, 60
+    model = {  # kernel -> (flops per launch, peak, label)
+        "project_kernel": (K * 14 * iters * 2.0 * H * H, PEAK_FP32, "FP32 (product with P only)"),
+        "cov_syrk_kernel": (float(K) * n * (n + 1), PEAK_FP64, "FP64 MFMA"),
+        "sample_full_kernel": (float(K) * n * (n + 1), PEAK_FP32, "FP32 MFMA"),
+    }
+    md = ["# QP smoothing and covariance kernels, K=1024, H=64 (n = 896): kernel time", "",
+          "Commands (run from the repository root, TMPDIR=/tmp):", ""]
+    md += [f"    {c}" for c in meta["next_commands"]]
+    md += ["", "| kernel | calls | avg us | algorithmic GFLOP per launch | TFLOP/s | fraction of peak |",
+           "|---|---|---|---|---|---|"]
+    for name, calls, tot, avg in rows:
+        short = name.split("(")[0].replace("mppi::", "").replace("void ", "")
+        if short.startswith(("rollout", "stats", "update", "reset", "at::", "__amd")):
+            continue
+        fl = model.get(short)
+        if fl:
+            tf = fl[0] / (avg * 1e-6) / 1e12
+            md.append(f"| {short} | {calls} | {avg:.1f} | {fl[0] / 1e9:.2f} | {tf:.1f} | {tf * 1e12 / fl[1]:.3f} "
+                      f"({fl[2]}) |")
+        else:
+            md.append(f"| {short} | {calls} | {avg:.1f} | | | |")
+    md += ["", "The Cholesky of n = 896 is one `chol_diag_kernel` and 27 `chol_step_kernel` launches in sequence "
+           "(n^3/3 = 0.24 GFLOP in FP64); its time is the chain of 896 column steps, not arithmetic."]
+    open(os.path.join(ROOT, "profiles", "qp_cov_kernels_c2.md"), "w").write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def summarize_profiles(base):
     """Turn rocprofv3 result folders (trace/, fetch/, write/, cfetch/,
-    cwrite/ under `base`) into the profiles/ summaries: kernel-time table and
-    the counter-based HBM traffic per rollout launch."""
+    cwrite/, valu/, trace_next/ under `base`) into the profiles/ summaries:
+    kernel-time tables, the counter-based HBM traffic and issued FP32
+    operations per rollout launch."""
     import sqlite3
     import glob
 
@@ -498,7 +620,8 @@ def summarize_profiles(base):
         f = glob.glob(os.path.join(base, sub, "**", "*results.db"), recursive=True)
         return sqlite3.connect(f[0]) if f else None
 
-    meta = json.load(open(os.path.join(base, "meta.json")))
+    meta = profile_meta()
+    summarize_next(base, meta)
     lines = []
     tr = db("trace")
     if tr:
@@ -593,6 +716,8 @@ def main():
                     help="skip the QP-smoothing leg (projection kernel and plans with the projection)")
     ap.add_argument("--no-cov", dest="cov", action="store_false",
                     help="skip the covariance-adaptation leg (its kernels alone and plans with the full covariance)")
+    ap.add_argument("--no-episodes", dest="episodes", action="store_false",
+                    help="skip the closed-loop ball-transport leg (success rate, task and compute time)")
     ap.add_argument("--summarize-profiles", default="",
                     help="read rocprofv3 result folders under this path and write the profiles/ summaries")
     args = ap.parse_args()
@@ -722,6 +847,9 @@ def main():
     if args.cov:
         out["cov"] = bench_cov(mp, ctx, sc, pp, args.config, out["ms_per_step"])
         print(json.dumps({"cov": out["cov"]}), file=sys.stderr, flush=True)
+    if args.episodes:
+        out["episode"] = bench_episode(mp, ctx)
+        print(json.dumps({"episode": out["episode"]}), file=sys.stderr, flush=True)
     if args.packed_steps > 0:
         out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, mapping)
     if args.serve_seconds > 0:
