@@ -14,10 +14,12 @@
 //
 // Mapping: one workgroup per sample, one wave per joint (14 waves), one
 // horizon step per lane (H <= 64).  A v and A^T y are wave-wide shuffles and
-// scans (neighbour differences, prefix and suffix sums); the dense product
-// with P, which is the same for every joint and sample, reads P from LDS
-// (rows padded to S floats) and the wave's right-hand side broadcast from
-// LDS, four columns per load.
+// scans (neighbour differences, prefix and suffix sums).  The dense product
+// with P, the same for every joint and sample, is one 64 x 64 by 64 x 16
+// product per iteration on FP32 MFMA: the waves publish their right-hand
+// sides to LDS, waves 0..3 each hold a 16-row block of P in registers for
+// the whole kernel and multiply (16 steps of 16x16x4), and every wave reads
+// its column of the result back.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -29,21 +31,61 @@ namespace {
 
 __device__ __forceinline__ float clipf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
 
+// Wave-wide scans without an LDS trip: DPP shifts within 16-lane rows (lanes
+// whose source lies outside the row read 0), then the row totals from
+// v_readlane.  Every lane of the wave is active wherever these run.
+template <int S>
+__device__ __forceinline__ float shr_row(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x110 + S, 0xF, 0xF, true));
+}
+template <int S>
+__device__ __forceinline__ float shl_row(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x100 + S, 0xF, 0xF, true));
+}
+template <int L>
+__device__ __forceinline__ float lane_of(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
+}
+
+// inclusive prefix sum over the wave
+__device__ __forceinline__ float prefix64(float x, int k)
+{
+    x += shr_row<1>(x);
+    x += shr_row<2>(x);
+    x += shr_row<4>(x);
+    x += shr_row<8>(x);
+    const float t0 = lane_of<15>(x), t1 = lane_of<31>(x), t2 = lane_of<47>(x);
+    const int row = k >> 4;
+    const float off = row == 0 ? 0.f : (row == 1 ? t0 : (row == 2 ? t0 + t1 : (t0 + t1) + t2));
+    return x + off;
+}
+// inclusive suffix sum over the wave
+__device__ __forceinline__ float suffix64(float x, int k)
+{
+    x += shl_row<1>(x);
+    x += shl_row<2>(x);
+    x += shl_row<4>(x);
+    x += shl_row<8>(x);
+    const float t1 = lane_of<16>(x), t2 = lane_of<32>(x), t3 = lane_of<48>(x);
+    const int row = k >> 4;
+    const float off = row == 3 ? 0.f : (row == 2 ? t3 : (row == 1 ? t3 + t2 : (t3 + t2) + t1));
+    return x + off;
+}
+
 // A v for the sequence held one element per lane (lane k: step k); rows that
 // do not exist (first difference at k = 0, second at k < 2, any k >= H) are 0
 __device__ __forceinline__ void apply_A(float v, int k, bool act, float &aI, float &a1, float &a2, float &aL)
 {
-    const float vm1 = __shfl_up(v, 1), vm2 = __shfl_up(v, 2);
-    aI = act ? v : 0.f;
-    a1 = (act && k >= 1) ? v - vm1 : 0.f;
-    a2 = (act && k >= 2) ? (v - 2.f * vm1) + vm2 : 0.f;
-    float x = act ? v : 0.f;
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const float y = __shfl_up(x, s);
-        if (k >= s) x += y;
-    }
-    aL = act ? x : 0.f;  // lanes past the horizon hold no row (their w must stay 0)
+    const float x = act ? v : 0.f;
+    const float vm1 = __shfl_up(x, 1), vm2 = __shfl_up(x, 2);  // masked below where they wrap
+    aI = x;
+    a1 = (act && k >= 1) ? x - vm1 : 0.f;
+    a2 = (act && k >= 2) ? (x - 2.f * vm1) + vm2 : 0.f;
+    const float p = prefix64(x, k);
+    aL = act ? p : 0.f;  // lanes past the horizon hold no row (their w must stay 0)
 }
 
 // A^T y at lane k (y of absent rows are 0): y_I + (y1_k - y1_{k+1}) +
@@ -52,32 +94,32 @@ __device__ __forceinline__ float apply_At(float yI, float y1, float y2, float yL
 {
     // every lane takes part in each shuffle; the end of the wave is masked after
     const float t1 = __shfl_down(y1, 1), t2 = __shfl_down(y2, 1), t3 = __shfl_down(y2, 2);
-    const float y1n = k + 1 < 64 ? t1 : 0.f;
-    const float y2n = k + 1 < 64 ? t2 : 0.f;
-    const float y2nn = k + 2 < 64 ? t3 : 0.f;
-    float x = yL;
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) {
-        const float y = __shfl_down(x, s);
-        if (k + s < 64) x += y;
-    }
-    return yI + (y1 - y1n) + ((y2 - 2.f * y2n) + y2nn) + x;
+    const float y1n = k + 1 < 64 ? t1 : 0.f, y2n = k + 1 < 64 ? t2 : 0.f, y2nn = k + 2 < 64 ? t3 : 0.f;
+    return yI + (y1 - y1n) + ((y2 - 2.f * y2n) + y2nn) + suffix64(yL, k);
 }
 
 }  // namespace
 
+constexpr int QS = 68;  // LDS row stride of the right-hand sides and results (floats)
+
 __global__ void __launch_bounds__(14 * 64) project_kernel(ProjectArgs a)
 {
-    extern __shared__ float lds[];
+    __shared__ __align__(16) float R[16][QS];  // right-hand sides, one row per joint (rows 14, 15: zero)
+    __shared__ __align__(16) float V[16][QS];  // P times them
     const int H = a.H, S = a.S;
-    float *P = lds;
-    float *R = lds + H * S;  // one right-hand side per wave
-    for (int i = threadIdx.x; i < H * S; i += blockDim.x) P[i] = a.P[i];
-    __syncthreads();
     const int j = blockIdx.x;
     const int d = threadIdx.x >> 6, k = threadIdx.x & 63;
-    float *r = R + 64 * d;
     const bool act = k < H;
+    if (d < 2) R[14 + d][k] = 0.f;
+    // waves 0..3 keep rows 16 w .. 16 w + 15 of P as MFMA A operands:
+    // pa[s] = P[16 w + l % 16][4 s + l / 16]
+    const int lr = k & 15, lq = k >> 4;
+    float pa[16];
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+        const int row = 16 * d + lr, col = 4 * st + lq;
+        pa[st] = (d < 4 && row < H && col < H) ? a.P[row * S + col] : 0.f;
+    }
     const float *x0 = a.x0 + (a.x0_shared ? 0 : (long)j * NX);
     const float q0 = x0[XQDES + d];
     float vt = 0.f;
@@ -106,24 +148,24 @@ __global__ void __launch_bounds__(14 * 64) project_kernel(ProjectArgs a)
     float zL = clipf(tL, loL, hiL);
     float wI = 0.f, w1 = 0.f, w2 = 0.f, wL = 0.f;
     const float rho = a.rho, alpha = a.alpha, beta = 1.f - a.alpha;
-    const int H4 = (H + 3) & ~3;
-    const float *prow = P + (act ? k : 0) * S;
+    const int nst = (H + 3) >> 2;  // k-steps of the product that touch columns < H
     float v = vt;
     for (int it = 0; it < a.iters; ++it) {
         const float rhs = rho * apply_At((zI - wI) - tI, (z1 - w1) - t1, (z2 - w2) - t2, (zL - wL) - tL, k);
-        r[k] = act ? rhs : 0.f;
-        wave_lds_sync();
-        float acc = 0.f;
-        for (int i = 0; i < H4; i += 4) {
-            const float4 p4 = *reinterpret_cast<const float4 *>(prow + i);
-            const float4 r4 = *reinterpret_cast<const float4 *>(r + i);
-            acc = fmaf(p4.x, r4.x, acc);
-            acc = fmaf(p4.y, r4.y, acc);
-            acc = fmaf(p4.z, r4.z, acc);
-            acc = fmaf(p4.w, r4.w, acc);
+        R[d][k] = act ? rhs : 0.f;
+        __syncthreads();
+        if (d < 4) {
+            // V[16 d + row][joint] = sum_i P[16 d + row][i] R[joint][i]; result
+            // element e of lane l is row 4 (l / 16) + e, joint l % 16
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 16; ++st)
+                if (st < nst) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[st], R[lr][4 * st + lq], acc, 0, 0, 0);
+            *reinterpret_cast<f4 *>(&V[lr][16 * d + 4 * lq]) = acc;
         }
-        v = act ? vt + acc : 0.f;
-        wave_lds_sync();  // every lane has read r before the next iteration writes it
+        __syncthreads();
+        v = act ? vt + V[d][k] : 0.f;
         float aI, a1, a2, aL;
         apply_A(v, k, act, aI, a1, a2, aL);
         aI = fmaf(alpha, aI, beta * zI);
@@ -148,8 +190,7 @@ __global__ void __launch_bounds__(14 * 64) project_kernel(ProjectArgs a)
 
 void launch_project(const ProjectArgs &a, hipStream_t s)
 {
-    const size_t lds = (size_t)(a.H * a.S + 14 * 64) * sizeof(float);
-    hipLaunchKernelGGL(project_kernel, dim3(a.K), dim3(14 * 64), lds, s, a);
+    hipLaunchKernelGGL(project_kernel, dim3(a.K), dim3(14 * 64), 0, s, a);
 }
 
 }  // namespace mppi

@@ -81,6 +81,28 @@ def test_project_matches_oracle(mp, ctx, qpo, K, H):
     scene.close()
 
 
+def test_project_full_size_launch_on_sampled_sequences(mp, ctx, qpo):
+    """The launch the bench times (K = 1024 samples, H = 64, the workload's
+    settings): 24 sampled sequences (every joint) against the oracle, and
+    the velocity box on every output."""
+    sc = W.make_scene(2)
+    scene = mp.Scene(ctx, sc)
+    p = W.qp_params(2)
+    K, H = 1024, 64
+    U, X0 = _inputs(sc, K, H, 2024)
+    out = torch.zeros((K, H, 14), device=DEV)
+    mp.mppi_project(ctx, scene, T(X0), T(U), out, p)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    idx = np.random.default_rng(5).choice(K, 24, replace=False)
+    ref = _oracle(qpo, sc, U[idx], X0[idx], p)
+    err = np.abs(got[idx] - ref).max()
+    print(f"project K={K} H={H} (24 sampled): max |gpu - oracle| {err:.2e}")
+    assert err < ATOL
+    assert np.all(np.abs(got) <= float(sc["u_max"]) * (1 + 1e-6))
+    scene.close()
+
+
 def test_project_feasible_sequences_are_kept(mp, ctx):
     sc = W.make_scene(2)
     scene = mp.Scene(ctx, sc)
