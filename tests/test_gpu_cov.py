@@ -232,3 +232,35 @@ def test_plan_cov_with_qp_against_oracle(mp, ctx, cov):
     assert np.median(rel) < 1e-3
     assert dU < 0.05 * pp["sigma"][0]
     assert dS < 2e-3
+
+
+def test_plan_cov_full_size_first_iteration_and_sigma(mp, ctx):
+    """The workload the bench times (K = 1024, H = 64): from Sigma_0 =
+    diag(sigma^2) the first iteration draws the diagonal sampler's samples
+    (up to one rounding), so its mean equals the plain plan's to FP32
+    rounding propagated through the rollouts; Sigma_1 is symmetric and
+    positive definite, with the eps floor under its spectrum."""
+    sc = W.make_scene(2)
+    scene = mp.Scene(ctx, sc)
+    pp = W.plan_params(2)
+    cp = W.cov_params(2)
+    K, H = pp["K"], pp["H"]
+    n = 14 * H
+    x0 = Td(W.initial_state(sc), torch.float32)
+    sig = Td(pp["sigma"], torch.float32)
+    nom = torch.zeros((H, 14), device=DEV)
+    U1, U2 = torch.zeros((H, 14), device=DEV), torch.zeros((H, 14), device=DEV)
+    S1 = torch.zeros((n, n), dtype=torch.float64, device=DEV)
+    st = mp.mppi_plan_cov(ctx, scene, x0, nom, K, H, pp["lam"], sig, U1, eps=cp["eps"], Sigma_out=S1, M=1,
+                          seed=pp["seed"], eta=cp["eta"])
+    mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U2, M=1, seed=pp["seed"], eta=cp["eta"], sync=True)
+    torch.cuda.synchronize()
+    d = np.abs(U1.cpu().numpy() - U2.cpu().numpy()).max()
+    S = S1.cpu().numpy()
+    ev = np.linalg.eigvalsh(S)
+    print(f"plan cov K={K} H={H} M=1: |nu - nu_plain| {d:.2e}, Sigma eigenvalues [{ev.min():.2e}, {ev.max():.2e}]")
+    assert st["rc"] == 0
+    assert d < 1e-3 * pp["sigma"][0]
+    assert np.array_equal(S, S.T)
+    assert ev.min() > 0.5 * cp["eps"]
+    scene.close()
