@@ -359,7 +359,7 @@ static int qp_check(const mppi_qp *qp, int H)
 
 // (I + rho A^T A)^-1 for A = [I; D1; D2; L] on H steps, in double, stored as
 // float rows of stride S (zero padded) in the context's QP slot.
-static int qp_matrix(mppi_ctx *ctx, int H, double rho, const float **out, int *S)
+static int qp_matrix(mppi_ctx *ctx, int H, double rho, hipStream_t stream, const float **out, int *S)
 {
     const int st = ((H + 3) & ~3) + 4;
     void *dp;
@@ -406,6 +406,8 @@ static int qp_matrix(mppi_ctx *ctx, int H, double rho, const float **out, int *S
             }
             for (int i = 0; i < H; ++i) P[(size_t)i * st + c] = (float)x[i];
         }
+        // work queued on this stream may still read the previous matrix
+        HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipMemcpy(dp, P.data(), P.size() * sizeof(float), hipMemcpyHostToDevice));
         ctx->qp_H = H;
         ctx->qp_rho = rho;
@@ -480,7 +482,7 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
     int qpS = 0;
     void *dqu = nullptr;
     if (qp) {
-        if ((rc = qp_matrix(ctx, H, qp->rho, &dP, &qpS))) return rc;
+        if ((rc = qp_matrix(ctx, H, qp->rho, s, &dP, &qpS))) return rc;
         if ((rc = ensure(ctx, S_QPU, (size_t)K * H * NU * sizeof(float), &dqu))) return rc;
     }
     const int n = H * NU;
@@ -872,7 +874,7 @@ int mppi_project(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0
     hipStream_t s = (hipStream_t)stream;
     const float *dP;
     int S;
-    if ((rc = qp_matrix(ctx, H, qp->rho, &dP, &S))) return rc;
+    if ((rc = qp_matrix(ctx, H, qp->rho, s, &dP, &S))) return rc;
     const void *dx0, *dU;
     if ((rc = stage_in(ctx, S_IN0, X0, nx0 * sizeof(float), dev, s, &dx0))) return rc;
     if ((rc = stage_in(ctx, S_IN1, U_in, nu_n * sizeof(float), dev, s, &dU))) return rc;
