@@ -171,7 +171,7 @@ def test_sample_full_with_diagonal_factor_is_the_diagonal_sampler(mp, ctx, cov):
     scene.close()
 
 
-def _plan_case(mp, ctx, cov, qp_params=None):
+def _plan_case(mp, ctx, cov, qp_params=None, n_elite=None):
     import oracle
     sc = W.make_scene(1)
     scene = mp.Scene(ctx, sc)
@@ -187,7 +187,7 @@ def _plan_case(mp, ctx, cov, qp_params=None):
     Sout = torch.zeros((n, n), dtype=torch.float64, device=DEV)
     st = mp.mppi_plan_cov(ctx, scene, Td(x0, torch.float32), torch.zeros((H, 14), device=DEV), K, H, pp["lam"],
                           Td(sig, torch.float32), Unew, costs, eps=cp["eps"], Sigma_out=Sout, qp=qp_params, M=M,
-                          seed=pp["seed"], eta=cp["eta"])
+                          seed=pp["seed"], eta=cp["eta"], n_elite=n_elite or 0)
     project = None
     if qp_params is not None:
         from oracle import qp as qpo
@@ -202,7 +202,7 @@ def _plan_case(mp, ctx, cov, qp_params=None):
                                          qp_params["iters"], qp_params["alpha"])
     r = cov.plan(o, x0.astype(np.float64), np.zeros((H, 14)), K, H, pp["lam"],
                  cov.diagonal_sigma(sig.astype(np.float64), H), M, pp["seed"], cp["eta"], cp["eps"],
-                 float(sc["u_max"]), project=project)
+                 float(sc["u_max"]), n_elite=n_elite, project=project)
     cg = costs.cpu().numpy()
     rel = np.abs(cg - r["costs"]) / np.abs(r["costs"])
     dU = np.abs(Unew.cpu().numpy() - r["nu"]).max()
@@ -224,6 +224,17 @@ def test_plan_cov_against_oracle(mp, ctx, cov):
     assert dU < 0.05 * pp["sigma"][0]
     assert dS < 2e-3
     assert np.linalg.eigvalsh(Sg).min() > 0
+
+
+def test_plan_cov_with_elite_set_against_oracle(mp, ctx, cov):
+    """Alg. 1's elite set: only the 8 lowest costs carry weight in both
+    updates (the covariance update skips the groups of samples without
+    weight)."""
+    st, rel, dU, dS, pp, Sg = _plan_case(mp, ctx, cov, n_elite=8)
+    assert st["rc"] == 0
+    assert np.median(rel) < 1e-3
+    assert dU < 0.05 * pp["sigma"][0]
+    assert dS < 2e-3
 
 
 def test_plan_cov_with_qp_against_oracle(mp, ctx, cov):
