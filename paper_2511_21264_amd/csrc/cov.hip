@@ -142,17 +142,26 @@ __global__ void __launch_bounds__(256) chol_init_kernel(CholArgs a)
     if (a.reset_flag && blockIdx.x == 0 && threadIdx.x == 0) *a.flag = a.n;
 }
 
+// element i (0..3) of a four-vector without dynamic indexing (sum of
+// selects: no lookup table, no scratch)
+__device__ __forceinline__ double pick4(const double v[4], int i)
+{
+    return (i == 0 ? v[0] : 0.0) + (i == 1 ? v[1] : 0.0) + (i == 2 ? v[2] : 0.0) + (i == 3 ? v[3] : 0.0);
+}
+
 // Factor the diagonal block held in s (lower triangle valid for rows and
 // columns < nbk), invert it, and store the factor block of columns c0.. into
 // L (and L32) and the inverse into Linv.  256 threads: thread t keeps the
 // entries (t / 32 + 8 k, t % 32), k = 0..3, of the block and of its inverse
-// in registers.  Column c: its owners publish it (and row c of the inverse)
-// to LDS, one barrier, then every thread scales and eliminates its entries;
-// the published vectors alternate between two buffers, so one barrier per
-// column suffices.  Row c of X = L^-1 comes from forward elimination of
-// L X = I and is final once the columns before c have been eliminated.
-__device__ void factor_block(const double (*s)[CB + 1], double (*cbuf)[CB], double (*xbuf)[CB], int nbk, int c0,
-                             const CholArgs &a, double *Linv)
+// in registers.  Columns go four at a time: their owners publish them (and
+// the four matching rows of the inverse) to LDS, one barrier, then every
+// thread factors the 4 x 4 diagonal block itself, forms its rows of the
+// panel by forward substitution and applies the rank-4 update to its
+// entries; rows of X = L^-1 follow by forward elimination of L X = I.  The
+// published panels alternate between two buffers, so one barrier per four
+// columns suffices.
+__device__ void factor_block(const double (*s)[CB + 1], double (*cbuf)[4][CB], double (*xbuf)[4][CB], int nbk,
+                             int c0b, const CholArgs &a, double *Linv)
 {
     const int t = threadIdx.x, q = t & 31, r0 = t >> 5;
     const int n = a.n;
@@ -168,43 +177,87 @@ __device__ void factor_block(const double (*s)[CB + 1], double (*cbuf)[CB], doub
     }
     int bad = -1;
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-#pragma unroll 1
-        for (int j = 0; j < 8; ++j) {
-            const int c = 8 * cb + j, par = c & 1;
-            if (q == c) {
+    for (int i = 0; i < 8; ++i) {
+        const int c0 = 4 * i, par = i & 1, kb = i >> 1;  // rows c0..c0+3 are k = kb of threads r0 = c0 & 7 ..
+        if (q >= c0 && q < c0 + 4) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) cbuf[par][r0 + 8 * k] = sv[k];
+            for (int k = 0; k < 4; ++k) cbuf[par][q - c0][r0 + 8 * k] = sv[k];
+        }
+        {
+            const int rr = r0 + 8 * kb;
+            if (rr >= c0 && rr < c0 + 4) xbuf[par][rr - c0][q] = xv[kb];
+        }
+        __syncthreads();
+        // the 4 x 4 diagonal block, factored (left-looking) by every thread
+        double L4[4][4], id[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double p = cbuf[par][u][c0 + u];
+#pragma unroll
+            for (int w = 0; w < u; ++w) p -= L4[u][w] * L4[u][w];
+            if (bad < 0 && !(p > 0.0 && p < INFINITY)) bad = c0 + u;
+            id[u] = rsqrt(p);
+            L4[u][u] = p * id[u];
+#pragma unroll
+            for (int v = u + 1; v < 4; ++v) {
+                double x = cbuf[par][u][c0 + v];
+#pragma unroll
+                for (int w = 0; w < u; ++w) x -= L4[v][w] * L4[u][w];
+                L4[v][u] = x * id[u];
             }
-            if (r0 == j) xbuf[par][q] = xv[cb];
-            __syncthreads();
-            // every read first (one wait), then a straight-line update by selects
-            const double p = cbuf[par][c], cq = cbuf[par][q], xq = xbuf[par][q];
-            double cr[4];
+        }
+        // panel row r: l[u] = (a_r[u] - sum_{w<u} l[w] L4[u][w]) / L4[u][u]
+        auto panel = [&](int r, double l[4]) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) cr[k] = cbuf[par][r0 + 8 * k];
-            if (bad < 0 && !(p > 0.0 && p < INFINITY)) bad = c;
-            const double inv = rsqrt(p), d = p * inv;
-            const double lq = cq * inv, xc = xq * inv;
+            for (int u = 0; u < 4; ++u) {
+                double x = cbuf[par][u][r];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int r = r0 + 8 * k;
-                const double lr = cr[k] * inv;
-                const double su = fma(-lr, lq, sv[k]), xu = fma(-lr, xc, xv[k]);
-                double ns = (q > c && q <= r) ? su : sv[k];
-                ns = (q == c && r >= c) ? (r == c ? d : lr) : ns;
-                sv[k] = ns;
-                xv[k] = r == c ? xc : (r > c ? xu : xv[k]);
+                for (int w = 0; w < u; ++w) x -= l[w] * L4[u][w];
+                l[u] = x * id[u];
+            }
+        };
+        double lq[4], xc[4];
+        panel(q, lq);
+        // rows c0..c0+3 of X at column q
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            double x = xbuf[par][u][q];
+#pragma unroll
+            for (int w = 0; w < u; ++w) x -= L4[u][w] * xc[w];
+            xc[u] = x * id[u];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = r0 + 8 * k;
+            double lr[4];
+            panel(r, lr);
+            if (r >= c0 + 4) {
+                const double upd = ((sv[k] - lr[0] * lq[0]) - lr[1] * lq[1]) - lr[2] * lq[2] - lr[3] * lq[3];
+                if (q >= c0 + 4 && q <= r)
+                    sv[k] = upd;
+                else if (q >= c0 && q < c0 + 4)
+                    sv[k] = pick4(lr, q - c0);
+                xv[k] = (((xv[k] - lr[0] * xc[0]) - lr[1] * xc[1]) - lr[2] * xc[2]) - lr[3] * xc[3];
+            } else if (r >= c0) {
+                const int u = r - c0;
+                if (q >= c0 && q <= r) {
+                    // L4[u][q - c0]: row u of the lower factor (entries above the diagonal are not read)
+                    const double lu[4] = {u == 0 ? L4[0][0] : (u == 1 ? L4[1][0] : (u == 2 ? L4[2][0] : L4[3][0])),
+                                          u == 1 ? L4[1][1] : (u == 2 ? L4[2][1] : L4[3][1]),
+                                          u == 2 ? L4[2][2] : L4[3][2], L4[3][3]};
+                    sv[k] = pick4(lu, q - c0);
+                }
+                xv[k] = pick4(xc, u);
             }
         }
     }
-    if (t == 0 && bad >= 0 && bad < nbk && *a.flag == n) *a.flag = c0 + bad;
+    if (t == 0 && bad >= 0 && bad < nbk && *a.flag == n) *a.flag = c0b + bad;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int r = r0 + 8 * k;
         Linv[r * CB + q] = xv[k];
         if (r < nbk && q <= r) {
-            const long e = (long)(c0 + r) * n + c0 + q;
+            const long e = (long)(c0b + r) * n + c0b + q;
             a.L[e] = sv[k];
             if (a.L32) a.L32[e] = (float)sv[k];
         }
@@ -215,7 +268,7 @@ __device__ void factor_block(const double (*s)[CB + 1], double (*cbuf)[CB], doub
 __global__ void __launch_bounds__(256) chol_diag_kernel(CholArgs a)
 {
     __shared__ double s[CB][CB + 1];
-    __shared__ double cbuf[2][CB], xbuf[2][CB];
+    __shared__ double cbuf[2][4][CB], xbuf[2][4][CB];
     const int n = a.n, nbk = min(CB, n);
     for (int e = threadIdx.x; e < CB * CB; e += 256) {
         const int r = e / CB, q = e % CB;
@@ -239,7 +292,7 @@ __global__ void __launch_bounds__(256) chol_step_kernel(CholArgs a, int b)
     __shared__ double ac[CB][CB + 1];
     __shared__ double pr[CB][CB + 1];
     __shared__ double pc[CB][CB + 1];
-    __shared__ double cbuf[2][CB], xbuf[2][CB];
+    __shared__ double cbuf[2][4][CB], xbuf[2][4][CB];
     int rr, cc;
     tri_index(blockIdx.x, rr, cc);
     const int rb = b + 1 + rr, cb = b + 1 + cc;
