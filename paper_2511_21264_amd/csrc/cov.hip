@@ -17,8 +17,8 @@
 //                      as the factor, and the workgroup of the next diagonal
 //                      tile factors and inverts it in registers once updated
 //   sample_full_kernel U = clip(nu + Z L^T, +-u_max): FP32 MFMA 16x16x4 over
-//                      64 x 64 tiles staged through LDS, skipping the zero
-//                      upper triangle of L
+//                      16 x 64 tiles staged through LDS in 32-wide chunks,
+//                      skipping the zero upper triangle of L
 //
 // MFMA 16x16x4 operand layout: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; result element v of lane l is D[4 (l / 16) + v][l % 16]
@@ -73,24 +73,32 @@ __global__ void __launch_bounds__(256) cov_syrk_kernel(CovArgs a)
     const double nl0 = lb0 < n ? a.nu[lb0] : 0.0, nl1 = lb1 < n ? a.nu[lb1] : 0.0;
     d4 c00 = {0.0, 0.0, 0.0, 0.0}, c01 = c00, c10 = c00, c11 = c00;
     double ws = 0.0;
-    // wave wv takes the groups of four samples j0 = 4 wv, 4 wv + 16, ...
-    for (int j0 = 4 * wv; j0 < K; j0 += 16) {
-        const int j = j0 + q;
-        const double w = j < K ? a.w[j] : 0.0;
-        if (r == 0) ws += w;
-        if (__ballot(w != 0.0) == 0) continue;  // no weight in this group (elites only)
-        double x0 = 0.0, x1 = 0.0, y0 = 0.0, y1 = 0.0;
-        if (w != 0.0) {
-            const float *u = a.U + (long)j * n;
-            if (ia0 < n) x0 = (double)u[ia0] - na0;
-            if (ia1 < n) x1 = (double)u[ia1] - na1;
-            if (lb0 < n) y0 = w * ((double)u[lb0] - nl0);
-            if (lb1 < n) y1 = w * ((double)u[lb1] - nl1);
+    // wave wv takes the groups of four samples j0 = 4 wv, 4 wv + 16, ..., two
+    // groups per step so that their loads are in flight together
+    for (int j0 = 4 * wv; j0 < K; j0 += 32) {
+        double x0[2], x1[2], y0[2], y1[2], w[2];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const int j = j0 + 16 * g + q;
+            w[g] = j < K ? a.w[j] : 0.0;
+            if (r == 0) ws += w[g];
+            x0[g] = x1[g] = y0[g] = y1[g] = 0.0;
+            if (w[g] != 0.0) {
+                const float *u = a.U + (long)j * n;
+                if (ia0 < n) x0[g] = (double)u[ia0] - na0;
+                if (ia1 < n) x1[g] = (double)u[ia1] - na1;
+                if (lb0 < n) y0[g] = w[g] * ((double)u[lb0] - nl0);
+                if (lb1 < n) y1[g] = w[g] * ((double)u[lb1] - nl1);
+            }
         }
-        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, c01, 0, 0, 0);
-        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, c10, 0, 0, 0);
-        c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, c11, 0, 0, 0);
+        if (__ballot(w[0] != 0.0 || w[1] != 0.0) == 0) continue;  // no weight in either group (elites only)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[g], y0[g], c00, 0, 0, 0);
+            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[g], y1[g], c01, 0, 0, 0);
+            c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[g], y0[g], c10, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[g], y1[g], c11, 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -377,45 +385,46 @@ __global__ void __launch_bounds__(256) normals_kernel(SampleFullArgs a)
     }
 }
 
+// output tile: 16 samples (j) x 64 sequence entries (i); wave w owns entries
+// i0 + 16 w .. + 15 (one 16x16 MFMA block); the sum over p runs in chunks of
+// 32 columns staged through LDS.  Small tiles keep several workgroups per
+// CU, whose loads overlap.
+constexpr int SJ = 16, SI = 64, SP = 32;
+
 __global__ void __launch_bounds__(256) sample_full_kernel(SampleFullArgs a)
 {
-    __shared__ float zs[64][17];
-    __shared__ float ls[64][17];
+    __shared__ float zs[SJ][SP + 1];
+    __shared__ float ls[SI][SP + 1];
     const int n = a.n, K = a.K;
-    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int i0 = blockIdx.x * SI, j0 = blockIdx.y * SJ;
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63, r = lane & 15, q = lane >> 4;
-    const int wj = wv >> 1, wi = wv & 1;
-    f4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
-    const int pend = min(n, i0 + 64);  // L is lower: columns past the tile's last row are zero
-    const int row = t >> 2, cc = (t & 3) * 4;
-    for (int p0 = 0; p0 < pend; p0 += 16) {
+    f4 c0 = {0.f, 0.f, 0.f, 0.f};
+    const int pend = min(n, i0 + SI);  // L is lower: columns past the tile's last row are zero
+    for (int p0 = 0; p0 < pend; p0 += SP) {
+        // stage Z[j0.., p0..] (16 x 32) and L[i0.., p0..] (64 x 32): thread t takes column t % 32
+        const int pc = t & 31, rw = t >> 5, p = p0 + pc;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int p = p0 + cc + u;
-            zs[row][cc + u] = (j0 + row < K && p < n) ? a.Z[(long)(j0 + row) * n + p] : 0.f;
-            ls[row][cc + u] = (i0 + row < n && p < n) ? a.L32[(long)(i0 + row) * n + p] : 0.f;
+        for (int u = 0; u < SJ / 8; ++u) {
+            const int row = rw + 8 * u;
+            zs[row][pc] = (j0 + row < K && p < n) ? a.Z[(long)(j0 + row) * n + p] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < SI / 8; ++u) {
+            const int row = rw + 8 * u;
+            ls[row][pc] = (i0 + row < n && p < n) ? a.L32[(long)(i0 + row) * n + p] : 0.f;
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const float x0 = zs[wj * 32 + r][4 * kk + q], x1 = zs[wj * 32 + 16 + r][4 * kk + q];
-            const float y0 = ls[wi * 32 + r][4 * kk + q], y1 = ls[wi * 32 + 16 + r][4 * kk + q];
-            c00 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y0, c00, 0, 0, 0);
-            c01 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y1, c01, 0, 0, 0);
-            c10 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y0, c10, 0, 0, 0);
-            c11 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y1, c11, 0, 0, 0);
-        }
+        for (int kk = 0; kk < SP / 4; ++kk)
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(zs[r][4 * kk + q], ls[16 * wv + r][4 * kk + q], c0, 0, 0, 0);
         __syncthreads();
     }
-    const int ib0 = i0 + wi * 32 + r, ib1 = ib0 + 16;
-    const float nu0 = ib0 < n ? a.nu[ib0] : 0.f, nu1 = ib1 < n ? a.nu[ib1] : 0.f;
+    const int ib = i0 + 16 * wv + r;
+    const float nui = ib < n ? a.nu[ib] : 0.f;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int ja = j0 + wj * 32 + 4 * q + v, jb = ja + 16;
-        if (ja < K && ib0 < n) a.U[(long)ja * n + ib0] = fminf(fmaxf(nu0 + c00[v], -a.u_max), a.u_max);
-        if (ja < K && ib1 < n) a.U[(long)ja * n + ib1] = fminf(fmaxf(nu1 + c01[v], -a.u_max), a.u_max);
-        if (jb < K && ib0 < n) a.U[(long)jb * n + ib0] = fminf(fmaxf(nu0 + c10[v], -a.u_max), a.u_max);
-        if (jb < K && ib1 < n) a.U[(long)jb * n + ib1] = fminf(fmaxf(nu1 + c11[v], -a.u_max), a.u_max);
+        const int ja = j0 + 4 * q + v;
+        if (ja < K && ib < n) a.U[(long)ja * n + ib] = fminf(fmaxf(nui + c0[v], -a.u_max), a.u_max);
     }
 }
 
@@ -424,7 +433,7 @@ void launch_sample_full(const SampleFullArgs &a, hipStream_t s)
     const long N = (long)a.K * a.n;
     const int g = (int)std::min<long>((N + 255) / 256, 8192);
     hipLaunchKernelGGL(normals_kernel, dim3(g), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(sample_full_kernel, dim3((a.n + 63) / 64, (a.K + 63) / 64), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sample_full_kernel, dim3((a.n + SI - 1) / SI, (a.K + SJ - 1) / SJ), dim3(256), 0, s, a);
 }
 
 __global__ void __launch_bounds__(256) diag_sigma_kernel(const float *sigma, int sps, int n, double *S)
