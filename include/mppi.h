@@ -314,10 +314,12 @@ typedef struct mppi_episode_opts {
     int n_avg;        /* leading steps of the best sequence averaged, 1..H */
     int n_exec;       /* control steps the averaged command runs, 1..H */
     int max_replans;  /* cap on replans (0: until an outcome) */
-    int pad;
+    int use_cov;      /* 1: plan with the full covariance (mppi_plan_cov), warm-started with Sigma_M shifted like
+                         the mean (the freed tail: diag(sigma^2), no cross-covariance); opts->eta in (0, 1] */
     double grasp_tol, width_tol, goal_tol; /* m */
     double lift_z, drop_z;                 /* m */
     double t_max;                          /* s */
+    double cov_eps;                        /* eps of the covariance update when use_cov */
 } mppi_episode_opts;
 
 typedef struct mppi_episode_result {
@@ -358,8 +360,9 @@ int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_scene *move, 
 
 typedef struct mppi_cov {
     const double *Sigma0; /* [n][n] Sigma_0, or NULL: diag(sigma^2) from the sigma argument */
-    double *Sigma_out;    /* [n][n] receives Sigma_M (nullable) */
+    double *Sigma_out;    /* [n][n] receives Sigma_M (nullable; may be Sigma0) */
     double eps;           /* >= 0, added to the diagonal after every update */
+    float *U_best;        /* [H][14] receives the best sequence of the final iteration (nullable) */
 } mppi_cov;
 
 /* Sigma_out = (1 - eta) Sigma_in + eta Delta Sigma + eps I from the samples

@@ -19,7 +19,8 @@ listed with the design notes):
   printed equation indexes s but sums s_j).
 * Sigma_{m+1} = (1 - eta) Sigma_m + eta Delta Sigma + eps I.  The paper adds
   no regulariser; eps >= 0 keeps Sigma positive definite when eta = 1 and
-  only a few samples carry weight (Delta Sigma has rank <= n_e).
+  only a few samples carry weight (Delta Sigma has rank <= n_e).  With no
+  positive weight (no finite cost) Sigma is kept, as the mean is.
 * Samples: u_j = clip(nu_m + L_m z_j, -u_max, u_max) with L_m the lower
   Cholesky factor of Sigma_m and z_j the Philox normals of the diagonal
   sampler (z_j[14 k + d]); for a diagonal Sigma this is the diagonal sampler.
@@ -66,6 +67,8 @@ def cov_update(U, w, nu_new, Sigma, eta, eps=0.0):
     Delta Sigma = sum_j w_j (u_j - nu_new)(u_j - nu_new)^T / sum_j w_j."""
     X = flat(U)
     w = np.asarray(w, dtype=np.float64)
+    if not w.sum() > 0:
+        return np.asarray(Sigma, dtype=np.float64).copy()  # no sample carries weight: Sigma is kept
     D = X - np.asarray(nu_new, dtype=np.float64).reshape(-1)[None, :]
     dS = (D * w[:, None]).T @ D / w.sum()
     n = X.shape[1]
@@ -98,11 +101,11 @@ def plan(o, x0, nominal, K, H, beta, Sigma0, M, seed, eta, eps, u_max, n_elite=N
     (`project(U[K,H,14]) -> U`), roll them out, weight them, update nu then
     Sigma.  nu is rounded through `nu_rounding` before sampling, as a
     single-precision mean is stored between iterations.  Returns nu[H,14],
-    Sigma, the last costs and the last weights."""
+    Sigma, the last costs, weights and samples."""
     nu = np.asarray(nominal, dtype=np.float64).reshape(-1).copy()
     S = np.asarray(Sigma0, dtype=np.float64).copy()
     x0 = np.asarray(x0, dtype=np.float64)
-    c = w = None
+    c = w = U = None
     for m in range(M):
         z = o.noise(seed, K, H, m)
         nus = nu.astype(nu_rounding).astype(np.float64) if nu_rounding else nu
@@ -114,4 +117,4 @@ def plan(o, x0, nominal, K, H, beta, Sigma0, M, seed, eta, eps, u_max, n_elite=N
         w = weights(c, beta, n_elite)
         nu = mean_update(U, w, nus, eta)
         S = cov_update(U, w, nu, S, eta, eps)
-    return dict(nu=nu.reshape(H, 14), Sigma=S, costs=c, weights=w)
+    return dict(nu=nu.reshape(H, 14), Sigma=S, costs=c, weights=w, U=U)

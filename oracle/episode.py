@@ -15,7 +15,9 @@ distance's error; the ball has fallen when, in the move phase and after it
 was lifted above lift_z, it is below drop_z; checks after every executed
 control step in the order collision, phase rule, timeout; the warm start is
 the mean shifted by the executed steps with its last row repeated; plan
-seeds are seed + replan index.  FP64 throughout, on the C oracle.
+seeds are seed + replan index; with the full covariance, Sigma_M is
+shifted like the mean and the freed tail is diag(sigma^2).  FP64
+throughout, on the C oracle.
 """
 from __future__ import annotations
 
@@ -66,19 +68,55 @@ def best_sequence(o, x, nominal, K, H, lam, sigma, M, seed, eta=1.0, n_elite=Non
     return r["nu"], o.sample(nu_prev, sigma, seed, K, M - 1)[r["best"]]
 
 
+def shift_sigma(S, sigma, H, n_exec):
+    """Warm start of the full covariance: the entries whose two steps stay
+    inside the horizon move up by the executed steps; the freed tail is
+    diag(sigma^2) with no cross-covariance."""
+    from oracle import cov
+    D = cov.diagonal_sigma(sigma, H)
+    n = 14 * H
+    sh = 14 * n_exec
+    out = D.copy()
+    if sh < n:
+        out[:n - sh, :n - sh] = S[sh:, sh:]
+    return out
+
+
+def best_sequence_cov(o, x, nominal, K, H, lam, Sigma, M, seed, eta, eps, u_max, n_elite=None):
+    """(nu_M, best sequence of the final iteration, Sigma_M) of the plan with
+    the full covariance."""
+    from oracle import cov
+    r = cov.plan(o, x, nominal, K, H, lam, Sigma, M, seed, eta, eps, u_max, n_elite=n_elite)
+    c = np.asarray(r["costs"], dtype=np.float64)
+    fin = np.isfinite(c)
+    best = int(np.flatnonzero(fin)[np.argmin(c[fin])]) if fin.any() else -1
+    ub = r["U"][best] if best >= 0 else r["nu"]
+    return r["nu"], np.asarray(ub).reshape(H, 14), r["Sigma"]
+
+
 def run(o_pick, o_move, x0, K, H, lam, sigma, M, seed, ep, eta=1.0, n_elite=None, max_replans=None):
     """One closed-loop run; ep: the executor settings (n_avg, n_exec,
-    tolerances, heights, t_max).  Returns the outcome, the executed commands
-    and the state after each replan's execution."""
+    tolerances, heights, t_max; use_cov and cov_eps for the plan with the
+    full covariance, warm-started with Sigma_M shifted like the mean).
+    Returns the outcome, the executed commands and the state after each
+    replan's execution."""
     rules = Rules(ep["grasp_tol"], ep["width_tol"], ep["goal_tol"], ep["lift_z"], ep["drop_z"], ep["t_max"])
     dt = o_move.scene["h"] * o_move.scene["n_sub"]
     x = np.asarray(x0, dtype=np.float64).copy()
     nom = np.zeros((H, 14))
+    use_cov = bool(ep.get("use_cov", 0))
+    if use_cov:
+        from oracle import cov
+        S = cov.diagonal_sigma(sigma, H)
     t, u_exec, x_hist = 0.0, [], []
     r = 0
     while max_replans is None or r < max_replans:
         o = o_pick if rules.phase == PICK else o_move
-        nu, ub = best_sequence(o, x, nom, K, H, lam, sigma, M, seed + r, eta, n_elite)
+        if use_cov:
+            nu, ub, S = best_sequence_cov(o, x, nom, K, H, lam, S, M, seed + r, eta, ep["cov_eps"],
+                                          float(o_move.scene["u_max"]), n_elite)
+        else:
+            nu, ub = best_sequence(o, x, nom, K, H, lam, sigma, M, seed + r, eta, n_elite)
         u = ub[:ep["n_avg"]].mean(axis=0)
         u_exec.append(u)
         for _ in range(ep["n_exec"]):
@@ -93,5 +131,7 @@ def run(o_pick, o_move, x0, K, H, lam, sigma, M, seed, ep, eta=1.0, n_elite=None
         if rules.status != RUNNING:
             break
         nom = np.concatenate([nu[ep["n_exec"]:], np.repeat(nu[-1:], min(ep["n_exec"], H), axis=0)])[:H]
+        if use_cov:
+            S = shift_sigma(S, sigma, H, ep["n_exec"])
     return dict(status=rules.status, phase=rules.phase, t_end=rules.t_end if rules.t_end >= 0 else t,
                 t_switch=rules.t_switch, n_replans=r, u_exec=np.array(u_exec), x_hist=np.array(x_hist))

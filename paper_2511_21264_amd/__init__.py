@@ -84,13 +84,13 @@ def make_qp(params):
 
 
 class Cov(C.Structure):
-    _fields_ = [("Sigma0", C.c_void_p), ("Sigma_out", C.c_void_p), ("eps", C.c_double)]
+    _fields_ = [("Sigma0", C.c_void_p), ("Sigma_out", C.c_void_p), ("eps", C.c_double), ("U_best", C.c_void_p)]
 
 
 class EpisodeOpts(C.Structure):
-    _fields_ = [("n_avg", C.c_int), ("n_exec", C.c_int), ("max_replans", C.c_int), ("pad", C.c_int),
+    _fields_ = [("n_avg", C.c_int), ("n_exec", C.c_int), ("max_replans", C.c_int), ("use_cov", C.c_int),
                 ("grasp_tol", C.c_double), ("width_tol", C.c_double), ("goal_tol", C.c_double),
-                ("lift_z", C.c_double), ("drop_z", C.c_double), ("t_max", C.c_double)]
+                ("lift_z", C.c_double), ("drop_z", C.c_double), ("t_max", C.c_double), ("cov_eps", C.c_double)]
 
 
 class EpisodeResult(C.Structure):
@@ -421,7 +421,9 @@ def make_episode_opts(params):
     """An mppi_episode_opts from a dict (see workloads.episode_params)."""
     e = EpisodeOpts()
     for f, _ in EpisodeOpts._fields_:
-        if f != "pad":
+        if f in ("use_cov", "cov_eps"):
+            setattr(e, f, params.get(f, 0))
+        else:
             setattr(e, f, params[f])
     return e
 
@@ -454,19 +456,20 @@ def mppi_episode(ctx, pick, move, x0, K, H, lam, sigma, eo, *, M=1, seed=0, eta=
 
 
 def mppi_plan_cov(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, eps=0.0, Sigma0=None,
-                  Sigma_out=None, qp=None, M=1, seed=0, eta=1.0, n_elite=0, sigma_per_step=False, want_stats=True,
-                  stream=None, mapping=None):
+                  Sigma_out=None, U_best=None, qp=None, M=1, seed=0, eta=1.0, n_elite=0, sigma_per_step=False,
+                  want_stats=True, stream=None, mapping=None):
     """mppi_plan with the full covariance over the sequence (Sigma0[n, n] or
     None for diag(sigma^2); Sigma_out[n, n] receives Sigma_M), optionally
     with the QP smoothing (qp: dict or QP).  Synchronises.  Returns a stats
     dict."""
     q = None if qp is None else (qp if isinstance(qp, QP) else make_qp(qp))
-    (px0, pnom, psig, pU, pc, pS0, pSo), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32),
-                                                      (sigma, np.float32), (U_new, np.float32), (costs, np.float32),
-                                                      (Sigma0, np.float64), (Sigma_out, np.float64)])
+    (px0, pnom, psig, pU, pc, pS0, pSo, pB), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32),
+                                                          (sigma, np.float32), (U_new, np.float32),
+                                                          (costs, np.float32), (Sigma0, np.float64),
+                                                          (Sigma_out, np.float64), (U_best, np.float32)])
     flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | _MAPS[mapping]
     o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
-    cv = Cov(pS0, pSo, float(eps))
+    cv = Cov(pS0, pSo, float(eps), pB)
     st = Stats()
     rc = lib().mppi_plan_cov(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), C.byref(cv),
                              C.byref(q) if q is not None else None, pU, pc, C.byref(st) if want_stats else None,

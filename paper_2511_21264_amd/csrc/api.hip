@@ -758,7 +758,7 @@ int mppi_plan_cov(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const
             if (!std::isfinite(cov->Sigma0[i])) return fail(MPPI_E_INVAL, "non-finite Sigma0");
     }
     return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, cov, U_new, costs, stats, stream,
-                     nullptr);
+                     cov->U_best);
 }
 
 int mppi_cov_update(mppi_ctx *ctx, const float *U, const double *w, const double *nu_new, const double *Sigma_in,

@@ -37,6 +37,21 @@ extern "C" int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_sc
     if (pick->desc.h != move->desc.h || pick->desc.n_sub != move->desc.n_sub)
         return fail(MPPI_E_INVAL, "pick and move scenes must share the time step");
     const double dt = move->desc.h * move->desc.n_sub;  // the control step, from the description (double)
+    const int n = H * NU;
+    const bool sps = opts->flags & MPPI_SIGMA_PER_STEP;
+    std::vector<double> Sg, Sn;  // the full covariance carried between replans (use_cov)
+    auto sig2 = [&](int i) {
+        const double sg = sigma[sps ? i : i % NU];
+        return sg * sg;
+    };
+    if (eo->use_cov) {
+        if (n > MPPI_COV_MAX_N) return fail(MPPI_E_INVAL, "n = 14 H = %d above MPPI_COV_MAX_N", n);
+        if (!(opts->eta > 0 && opts->eta <= 1)) return fail(MPPI_E_INVAL, "eta must be in (0, 1] with use_cov");
+        if (!(eo->cov_eps >= 0) || !std::isfinite(eo->cov_eps)) return fail(MPPI_E_INVAL, "cov_eps must be >= 0");
+        Sg.assign((size_t)n * n, 0.0);
+        Sn.assign((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i) Sg[(size_t)i * n + i] = sig2(i);
+    }
     const mppi::EpRule rule = {eo->grasp_tol, eo->width_tol, eo->goal_tol, eo->lift_z, eo->drop_z, eo->t_max};
     mppi::EpState es;
     std::vector<float> x(x0, x0 + NX), xo(NX), nom((size_t)H * NU, 0.f), unew((size_t)H * NU),
@@ -52,8 +67,15 @@ extern "C" int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_sc
         const mppi_scene *sc = es.phase == mppi::EP_PICK ? pick : move;
         mppi_stats ps;
         const auto t0 = std::chrono::steady_clock::now();
-        int rc = mppi_plan_best(ctx, sc, x.data(), nom.data(), K, H, lambda, sigma, &o, unew.data(), ubest.data(),
+        int rc;
+        if (eo->use_cov) {
+            mppi_cov cv = {Sg.data(), Sg.data(), eo->cov_eps, ubest.data()};
+            rc = mppi_plan_cov(ctx, sc, x.data(), nom.data(), K, H, lambda, sigma, &o, &cv, nullptr, unew.data(),
+                               nullptr, &ps, stream);
+        } else {
+            rc = mppi_plan_best(ctx, sc, x.data(), nom.data(), K, H, lambda, sigma, &o, unew.data(), ubest.data(),
                                 nullptr, &ps, stream);
+        }
         tcomp.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         if (rc == MPPI_E_DIVERGED)
             ++n_div;
@@ -86,6 +108,16 @@ extern "C" int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_sc
         for (int k = 0; k < H; ++k) {
             const int src = std::min(k + eo->n_exec, H - 1);
             std::copy(unew.begin() + (size_t)src * NU, unew.begin() + (size_t)(src + 1) * NU, nom.begin() + (size_t)k * NU);
+        }
+        // and the covariance shifted alike: entries whose two steps stay inside
+        // the horizon move up; the freed tail is diag(sigma^2)
+        if (eo->use_cov) {
+            const int sh = eo->n_exec * NU;
+            for (int i = 0; i < n; ++i)
+                for (int l = 0; l < n; ++l)
+                    Sn[(size_t)i * n + l] = (i + sh < n && l + sh < n) ? Sg[(size_t)(i + sh) * n + l + sh]
+                                                                        : (i == l ? sig2(i) : 0.0);
+            Sg.swap(Sn);
         }
     }
     double mean = 0.0, mx = 0.0;

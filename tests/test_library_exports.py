@@ -121,8 +121,8 @@ def test_cov_struct_layout_and_constants_match_header():
 #include <stdio.h>
 #include "mppi.h"
 int main(void) {
-  printf("%zu %zu %zu %d %d\n", sizeof(mppi_cov), offsetof(mppi_cov, Sigma_out), offsetof(mppi_cov, eps),
-         MPPI_COV_MAX_N, MPPI_E_NOTPD);
+  printf("%zu %zu %zu %zu %d %d\n", sizeof(mppi_cov), offsetof(mppi_cov, Sigma_out), offsetof(mppi_cov, eps),
+         offsetof(mppi_cov, U_best), MPPI_COV_MAX_N, MPPI_E_NOTPD);
   return 0;
 }'''
     with tempfile.TemporaryDirectory() as d:
@@ -132,7 +132,8 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     V = mp.Cov
-    assert [int(v) for v in out] == [C.sizeof(V), V.Sigma_out.offset, V.eps.offset, mp.COV_MAX_N, mp.E_NOTPD]
+    assert [int(v) for v in out] == [C.sizeof(V), V.Sigma_out.offset, V.eps.offset, V.U_best.offset, mp.COV_MAX_N,
+                                     mp.E_NOTPD]
 
 
 def test_episode_struct_layouts_match_header():
@@ -144,9 +145,10 @@ def test_episode_struct_layouts_match_header():
 #include <stdio.h>
 #include "mppi.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mppi_episode_opts), offsetof(mppi_episode_opts, grasp_tol),
-         offsetof(mppi_episode_opts, t_max), sizeof(mppi_episode_result), offsetof(mppi_episode_result, t_end),
-         offsetof(mppi_episode_result, ball_final), offsetof(mppi_episode_result, n_diverged));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mppi_episode_opts), offsetof(mppi_episode_opts, grasp_tol),
+         offsetof(mppi_episode_opts, t_max), offsetof(mppi_episode_opts, cov_eps), sizeof(mppi_episode_result),
+         offsetof(mppi_episode_result, t_end), offsetof(mppi_episode_result, ball_final),
+         offsetof(mppi_episode_result, n_diverged));
   return 0;
 }'''
     with tempfile.TemporaryDirectory() as d:
@@ -156,8 +158,8 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     E, R = mp.EpisodeOpts, mp.EpisodeResult
-    assert [int(v) for v in out] == [C.sizeof(E), E.grasp_tol.offset, E.t_max.offset, C.sizeof(R), R.t_end.offset,
-                                     R.ball_final.offset, R.n_diverged.offset]
+    assert [int(v) for v in out] == [C.sizeof(E), E.grasp_tol.offset, E.t_max.offset, E.cov_eps.offset, C.sizeof(R),
+                                     R.t_end.offset, R.ball_final.offset, R.n_diverged.offset]
 
 
 def test_scene_desc_roundtrip():

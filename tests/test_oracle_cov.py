@@ -71,6 +71,13 @@ def test_eta_zero_keeps_sigma_and_eps_adds_to_the_diagonal():
                                rtol=0, atol=1e-13)
 
 
+def test_no_weight_keeps_sigma():
+    U = _data(seed=14)
+    K, n = U.shape[0], U[0].size
+    S0 = np.diag(np.linspace(0.1, 0.2, n))
+    np.testing.assert_array_equal(cov.cov_update(U, np.zeros(K), np.zeros(n), S0, 0.5, eps=1e-3), S0)
+
+
 def test_update_is_symmetric_psd_with_rank_at_most_the_weighted_samples():
     U = _data(K=30, H=4, seed=7)
     K, n = U.shape[0], U[0].size
