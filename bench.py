@@ -399,29 +399,33 @@ def bench_cov(mp, ctx, sc, pp, config, plain_ms, n_launch=20, n_plan=3):
     }
 
 
-def bench_episode(mp, ctx, runs=((2, 8), (3, 4)), t_max=10.0):
+def bench_episode(mp, ctx, runs=((2, 8, False), (2, 8, True), (3, 4, False)), t_max=10.0):
     """Closed-loop ball transport (receding-horizon execution; pick and move
     phases; the experiments' success metric: collision, timeout or a fallen
-    ball fail a run): for each (config, n) the first n seeded scenes of the
-    workload at its K and H, M warm-started iterations per replan.  Success
-    rate, task time (simulated seconds to the goal) over the successes, and
-    the compute time per replan pooled over every replan (mean, std)."""
+    ball fail a run): for each (config, n, full covariance) the first n
+    seeded scenes of the workload at its K and H, M warm-started iterations
+    per replan (with the full covariance: eta and eps of the covariance
+    workload, Sigma_M warm-started).  Success rate, task time (simulated
+    seconds to the goal) over the successes, and the compute time per replan
+    pooled over every replan (mean, std)."""
     import numpy as np
     import workloads as W
     out = {}
-    for cfg, n in runs:
+    for cfg, n, use_cov in runs:
         pp = W.plan_params(cfg)
-        ep = W.episode_params(cfg, t_max=t_max)
+        cp = W.cov_params(cfg)
+        ep = W.episode_params(cfg, t_max=t_max, use_cov=int(use_cov), cov_eps=cp["eps"])
+        eta = cp["eta"] if use_cov else pp["eta"]
         res = []
         for i in range(n):
             pk, mv = W.episode_scenes(cfg, i)
             spk, smv = mp.Scene(ctx, pk), mp.Scene(ctx, mv)
             r = mp.mppi_episode(ctx, spk, smv, W.initial_state(mv), pp["K"], pp["H"], pp["lam"], pp["sigma"], ep,
-                                M=ep["M"], seed=1000 * cfg + i)
+                                M=ep["M"], seed=1000 * cfg + i, eta=eta)
             spk.close()
             smv.close()
             res.append(r)
-            print(json.dumps({"episode": cfg, "scene": i, "outcome": r["outcome"], "t_end": r["t_end"],
+            print(json.dumps({"episode": cfg, "cov": use_cov, "scene": i, "outcome": r["outcome"], "t_end": r["t_end"],
                               "replans": r["n_replans"], "t_comp_mean_ms": r["t_comp_mean_ms"]}),
                   file=sys.stderr, flush=True)
         ok = [r for r in res if r["status"] == 1]
@@ -431,8 +435,9 @@ def bench_episode(mp, ctx, runs=((2, 8), (3, 4)), t_max=10.0):
         m_all = float((nrep * mu).sum() / nrep.sum())
         v_all = float((nrep * (sd ** 2 + mu ** 2)).sum() / nrep.sum() - m_all ** 2)
         tt = np.array([r["t_end"] for r in ok])
-        out[f"config{cfg}"] = {
+        out[f"config{cfg}" + ("_cov" if use_cov else "")] = {
             "runs": n, "K": pp["K"], "H": pp["H"], "M_per_replan": ep["M"], "n_avg": ep["n_avg"],
+            "covariance": {"eta": eta, "eps": cp["eps"]} if use_cov else None,
             "n_exec": ep["n_exec"], "t_max_s": t_max,
             "success_rate": len(ok) / n,
             "outcomes": {o: sum(r["outcome"] == o for r in res) for o in sorted({r["outcome"] for r in res})},
