@@ -253,7 +253,7 @@ int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, cons
  * Solver: `iters` iterations of ADMM with penalty rho and over-relaxation
  * alpha on the stacked operator [I; D1; D2; prefix sums], started from
  * z = clip(A v~), w = 0; the result is clipped to the velocity box (r = 1
- * holds exactly, the other bounds to the solver's accuracy).  H <= 64. */
+ * holds exactly, the other bounds to the solver's accuracy).  H <= 128. */
 typedef struct mppi_qp {
     double pos_lo[14], pos_hi[14]; /* commanded-position bounds per joint (rad) */
     double acc_max;                /* rad/s^2 */
@@ -266,7 +266,7 @@ typedef struct mppi_qp {
 /* Project U_in[K][H][14] into U_out[K][H][14] (the same array is allowed).
  *   X0: [K][MPPI_NX] start states (their commanded positions q_des), or one
  *   state for every sample when x0_shared != 0.  flags: MPPI_DEVICE_PTRS,
- *   MPPI_SYNC.  Errors: MPPI_E_INVAL (NULL, K < 1, H < 1 or H > 64, bad qp
+ *   MPPI_SYNC.  Errors: MPPI_E_INVAL (NULL, K < 1, H < 1 or H > 128, bad qp
  *   values), MPPI_E_NOMEM, MPPI_E_DEVICE. */
 int mppi_project(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0_shared, const float *U_in,
                  float *U_out, int K, int H, const mppi_qp *qp, unsigned flags, void *stream);
@@ -275,7 +275,7 @@ int mppi_project(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0
  * samples nu + sigma * z (the Philox normals of mppi_sample, not clamped)
  * are projected as by mppi_project, rolled out as given, and the update of
  * Eq. mean_update averages the projected samples.  Arguments and errors as
- * mppi_plan, plus qp (H <= 64).  MPPI_GRAPH is ignored. */
+ * mppi_plan, plus qp (H <= 128).  MPPI_GRAPH is ignored. */
 int mppi_plan_qp(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
                  double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp, float *U_new,
                  float *costs, mppi_stats *stats, void *stream);

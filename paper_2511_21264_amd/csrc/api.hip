@@ -345,7 +345,7 @@ int mppi_scene_num_pairs(const mppi_scene *s, int *n_pairs, int *n_cost)
 static int qp_check(const mppi_qp *qp, int H)
 {
     if (!qp) return fail(MPPI_E_INVAL, "NULL qp");
-    if (H > 64) return fail(MPPI_E_INVAL, "QP smoothing supports H <= 64 (H=%d)", H);
+    if (H > 128) return fail(MPPI_E_INVAL, "QP smoothing supports H <= 128 (H=%d)", H);
     if (!(qp->rho > 0) || !std::isfinite(qp->rho)) return fail(MPPI_E_INVAL, "qp rho must be finite and > 0");
     if (!(qp->alpha > 0 && qp->alpha < 2)) return fail(MPPI_E_INVAL, "qp alpha must lie in (0, 2)");
     if (qp->iters < 1 || qp->iters > 10000) return fail(MPPI_E_INVAL, "qp iters=%d out of range", qp->iters);

@@ -13,13 +13,14 @@
 // from z = clip(A v~), w = 0; the output is v clipped to the velocity box.
 //
 // Mapping: one workgroup per sample, one wave per joint (14 waves), one
-// horizon step per lane (H <= 64).  A v and A^T y are wave-wide shuffles and
+// horizon step per lane for H <= 64 and two (steps k and k + 64) for
+// H <= 128.  A v and A^T y are wave-wide shuffles and
 // scans (neighbour differences, prefix and suffix sums).  The dense product
 // with P, the same for every joint and sample, is one 64 x 64 by 64 x 16
 // product per iteration on FP32 MFMA: the waves publish their right-hand
-// sides to LDS, waves 0..3 each hold a 16-row block of P in registers for
-// the whole kernel and multiply (16 steps of 16x16x4), and every wave reads
-// its column of the result back.
+// sides to LDS, waves 0..4 NH - 1 each hold a 16-row block of P in registers
+// for the whole kernel and multiply (16 NH steps of 16x16x4), and every wave
+// reads its column of the result back.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -98,99 +99,187 @@ __device__ __forceinline__ float apply_At(float yI, float y1, float y2, float yL
     return yI + (y1 - y1n) + ((y2 - 2.f * y2n) + y2nn) + suffix64(yL, k);
 }
 
+// Two steps per lane (64 < H <= 128): lane k holds steps k (half 0) and
+// k + 64 (half 1); the halves join at the boundary through v_readlane of
+// lanes 63 and 0.
+__device__ __forceinline__ void apply_A2(const float v[2], int k, const bool act[2], float aI[2], float a1[2],
+                                         float a2[2], float aL[2])
+{
+    const float x0 = act[0] ? v[0] : 0.f, x1 = act[1] ? v[1] : 0.f;
+    const float e62 = lane_of<62>(x0), e63 = lane_of<63>(x0);
+    const float u0 = __shfl_up(x0, 1), w0 = __shfl_up(x0, 2), u1 = __shfl_up(x1, 1), w1 = __shfl_up(x1, 2);
+    const float vm1_0 = u0, vm2_0 = w0;                                  // used for k >= 1 / k >= 2
+    const float vm1_1 = k >= 1 ? u1 : e63, vm2_1 = k >= 2 ? w1 : (k == 1 ? e63 : e62);
+    aI[0] = x0;
+    aI[1] = x1;
+    a1[0] = (act[0] && k >= 1) ? x0 - vm1_0 : 0.f;
+    a2[0] = (act[0] && k >= 2) ? (x0 - 2.f * vm1_0) + vm2_0 : 0.f;
+    a1[1] = act[1] ? x1 - vm1_1 : 0.f;
+    a2[1] = act[1] ? (x1 - 2.f * vm1_1) + vm2_1 : 0.f;
+    const float p0 = prefix64(x0, k);
+    const float p1 = prefix64(x1, k) + lane_of<63>(p0);
+    aL[0] = act[0] ? p0 : 0.f;
+    aL[1] = act[1] ? p1 : 0.f;
+}
+
+__device__ __forceinline__ void apply_At2(const float yI[2], const float y1[2], const float y2[2], const float yL[2],
+                                          int k, float out[2])
+{
+    const float b10 = lane_of<0>(y1[1]), b20 = lane_of<0>(y2[1]), b21 = lane_of<1>(y2[1]);
+    const float s1_0 = __shfl_down(y1[0], 1), s2_0 = __shfl_down(y2[0], 1), s22_0 = __shfl_down(y2[0], 2);
+    const float s1_1 = __shfl_down(y1[1], 1), s2_1 = __shfl_down(y2[1], 1), s22_1 = __shfl_down(y2[1], 2);
+    // half 0: steps k + 1, k + 2 may lie in half 1
+    const float y1n0 = k + 1 < 64 ? s1_0 : b10, y2n0 = k + 1 < 64 ? s2_0 : b20;
+    const float y2nn0 = k + 2 < 64 ? s22_0 : (k == 62 ? b20 : b21);
+    // half 1: nothing past step 127
+    const float y1n1 = k + 1 < 64 ? s1_1 : 0.f, y2n1 = k + 1 < 64 ? s2_1 : 0.f, y2nn1 = k + 2 < 64 ? s22_1 : 0.f;
+    const float q1 = suffix64(yL[1], k);
+    const float q0 = suffix64(yL[0], k) + lane_of<0>(q1);
+    out[0] = yI[0] + (y1[0] - y1n0) + ((y2[0] - 2.f * y2n0) + y2nn0) + q0;
+    out[1] = yI[1] + (y1[1] - y1n1) + ((y2[1] - 2.f * y2n1) + y2nn1) + q1;
+}
+
 }  // namespace
 
-constexpr int QS = 68;  // LDS row stride of the right-hand sides and results (floats)
-
+// NH horizon steps per lane (1: H <= 64, 2: H <= 128); waves 0 .. 4 NH - 1
+// hold the 16-row blocks of P
+template <int NH>
 __global__ void __launch_bounds__(14 * 64) project_kernel(ProjectArgs a)
 {
+    constexpr int QS = 64 * NH + 4;  // LDS row stride of the right-hand sides and results (floats)
+    constexpr int NST = 16 * NH;     // k-steps of the product
     __shared__ __align__(16) float R[16][QS];  // right-hand sides, one row per joint (rows 14, 15: zero)
     __shared__ __align__(16) float V[16][QS];  // P times them
     const int H = a.H, S = a.S;
     const int j = blockIdx.x;
     const int d = threadIdx.x >> 6, k = threadIdx.x & 63;
-    const bool act = k < H;
-    if (d < 2) R[14 + d][k] = 0.f;
-    // waves 0..3 keep rows 16 w .. 16 w + 15 of P as MFMA A operands:
+    bool act[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) act[h] = k + 64 * h < H;
+    if (d < 2) {
+#pragma unroll
+        for (int h = 0; h < NH; ++h) R[14 + d][k + 64 * h] = 0.f;
+    }
+    // waves 0 .. 4 NH - 1 keep rows 16 w .. 16 w + 15 of P as MFMA A operands:
     // pa[s] = P[16 w + l % 16][4 s + l / 16]
     const int lr = k & 15, lq = k >> 4;
-    float pa[16];
+    float pa[NST];
 #pragma unroll
-    for (int st = 0; st < 16; ++st) {
+    for (int st = 0; st < NST; ++st) {
         const int row = 16 * d + lr, col = 4 * st + lq;
-        pa[st] = (d < 4 && row < H && col < H) ? a.P[row * S + col] : 0.f;
+        pa[st] = (d < 4 * NH && row < H && col < H) ? a.P[row * S + col] : 0.f;
     }
     const float *x0 = a.x0 + (a.x0_shared ? 0 : (long)j * NX);
     const float q0 = x0[XQDES + d];
-    float vt = 0.f;
-    if (act) {
-        if (a.U_in) {
-            vt = a.U_in[((long)j * H + k) * NU + d];
-        } else {
-            const float z = normal_joint(a.key0, a.key1, (uint32_t)j, (uint32_t)k, (uint32_t)a.m, d);
-            vt = fmaf(a.sigma[(a.sigma_per_step ? k * NU : 0) + d], z, a.nu[k * NU + d]);
+    float vt[NH], loI[NH], hiI[NH], lo1[NH], hi1[NH], lo2[NH], hi2[NH], loL[NH], hiL[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        const int st = k + 64 * h;  // this lane's step in half h
+        vt[h] = 0.f;
+        if (act[h]) {
+            if (a.U_in) {
+                vt[h] = a.U_in[((long)j * H + st) * NU + d];
+            } else {
+                const float z = normal_joint(a.key0, a.key1, (uint32_t)j, (uint32_t)st, (uint32_t)a.m, d);
+                vt[h] = fmaf(a.sigma[(a.sigma_per_step ? st * NU : 0) + d], z, a.nu[st * NU + d]);
+            }
         }
+        // the bounds of the four rows this lane holds (absent rows: [0, 0])
+        loI[h] = act[h] ? -a.u_max : 0.f;
+        hiI[h] = act[h] ? a.u_max : 0.f;
+        lo1[h] = (act[h] && st >= 1) ? -a.dacc : 0.f;
+        hi1[h] = (act[h] && st >= 1) ? a.dacc : 0.f;
+        lo2[h] = (act[h] && st >= 2) ? -a.djerk : 0.f;
+        hi2[h] = (act[h] && st >= 2) ? a.djerk : 0.f;
+        loL[h] = act[h] ? (a.pos_lo[d] - q0) / a.dt : 0.f;
+        hiL[h] = act[h] ? (a.pos_hi[d] - q0) / a.dt : 0.f;
     }
-    // the bounds of the four rows this lane holds (absent rows: [0, 0])
-    const float loI = act ? -a.u_max : 0.f, hiI = act ? a.u_max : 0.f;
-    const float lo1 = (act && k >= 1) ? -a.dacc : 0.f, hi1 = (act && k >= 1) ? a.dacc : 0.f;
-    const float lo2 = (act && k >= 2) ? -a.djerk : 0.f, hi2 = (act && k >= 2) ? a.djerk : 0.f;
-    const float loL = act ? (a.pos_lo[d] - q0) / a.dt : 0.f, hiL = act ? (a.pos_hi[d] - q0) / a.dt : 0.f;
     // A v~ is kept: the v-update is evaluated as v~ + rho P A^T (z - w - A v~),
     // the same value as P (v~ + rho A^T (z - w)) since P (I + rho A^T A) = I,
     // but without the cancellation of two large terms (the prefix-sum rows
     // of rho A^T A v~ are hundreds of times larger than v~ at H = 64)
-    float tI, t1, t2, tL;
-    apply_A(vt, k, act, tI, t1, t2, tL);
-    float zI = clipf(tI, loI, hiI);
-    float z1 = clipf(t1, lo1, hi1);
-    float z2 = clipf(t2, lo2, hi2);
-    float zL = clipf(tL, loL, hiL);
-    float wI = 0.f, w1 = 0.f, w2 = 0.f, wL = 0.f;
+    float tI[NH], t1[NH], t2[NH], tL[NH];
+    if constexpr (NH == 1)
+        apply_A(vt[0], k, act[0], tI[0], t1[0], t2[0], tL[0]);
+    else
+        apply_A2(vt, k, act, tI, t1, t2, tL);
+    float zI[NH], z1[NH], z2[NH], zL[NH], wI[NH], w1[NH], w2[NH], wL[NH], v[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        zI[h] = clipf(tI[h], loI[h], hiI[h]);
+        z1[h] = clipf(t1[h], lo1[h], hi1[h]);
+        z2[h] = clipf(t2[h], lo2[h], hi2[h]);
+        zL[h] = clipf(tL[h], loL[h], hiL[h]);
+        wI[h] = w1[h] = w2[h] = wL[h] = 0.f;
+        v[h] = vt[h];
+    }
     const float rho = a.rho, alpha = a.alpha, beta = 1.f - a.alpha;
     const int nst = (H + 3) >> 2;  // k-steps of the product that touch columns < H
-    float v = vt;
     for (int it = 0; it < a.iters; ++it) {
-        const float rhs = rho * apply_At((zI - wI) - tI, (z1 - w1) - t1, (z2 - w2) - t2, (zL - wL) - tL, k);
-        R[d][k] = act ? rhs : 0.f;
+        float yI[NH], y1[NH], y2[NH], yL[NH], rhs[NH];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            yI[h] = (zI[h] - wI[h]) - tI[h];
+            y1[h] = (z1[h] - w1[h]) - t1[h];
+            y2[h] = (z2[h] - w2[h]) - t2[h];
+            yL[h] = (zL[h] - wL[h]) - tL[h];
+        }
+        if constexpr (NH == 1)
+            rhs[0] = apply_At(yI[0], y1[0], y2[0], yL[0], k);
+        else
+            apply_At2(yI, y1, y2, yL, k, rhs);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) R[d][k + 64 * h] = act[h] ? rho * rhs[h] : 0.f;
         __syncthreads();
-        if (d < 4) {
+        if (d < 4 * NH) {
             // V[16 d + row][joint] = sum_i P[16 d + row][i] R[joint][i]; result
             // element e of lane l is row 4 (l / 16) + e, joint l % 16
             typedef float f4 __attribute__((ext_vector_type(4)));
             f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int st = 0; st < 16; ++st)
+            for (int st = 0; st < NST; ++st)
                 if (st < nst) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[st], R[lr][4 * st + lq], acc, 0, 0, 0);
             *reinterpret_cast<f4 *>(&V[lr][16 * d + 4 * lq]) = acc;
         }
         __syncthreads();
-        v = act ? vt + V[d][k] : 0.f;
-        float aI, a1, a2, aL;
-        apply_A(v, k, act, aI, a1, a2, aL);
-        aI = fmaf(alpha, aI, beta * zI);
-        a1 = fmaf(alpha, a1, beta * z1);
-        a2 = fmaf(alpha, a2, beta * z2);
-        aL = fmaf(alpha, aL, beta * zL);
-        float zn = clipf(aI + wI, loI, hiI);
-        wI += aI - zn;
-        zI = zn;
-        zn = clipf(a1 + w1, lo1, hi1);
-        w1 += a1 - zn;
-        z1 = zn;
-        zn = clipf(a2 + w2, lo2, hi2);
-        w2 += a2 - zn;
-        z2 = zn;
-        zn = clipf(aL + wL, loL, hiL);
-        wL += aL - zn;
-        zL = zn;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) v[h] = act[h] ? vt[h] + V[d][k + 64 * h] : 0.f;
+        float aI[NH], a1[NH], a2[NH], aL[NH];
+        if constexpr (NH == 1)
+            apply_A(v[0], k, act[0], aI[0], a1[0], a2[0], aL[0]);
+        else
+            apply_A2(v, k, act, aI, a1, a2, aL);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            aI[h] = fmaf(alpha, aI[h], beta * zI[h]);
+            a1[h] = fmaf(alpha, a1[h], beta * z1[h]);
+            a2[h] = fmaf(alpha, a2[h], beta * z2[h]);
+            aL[h] = fmaf(alpha, aL[h], beta * zL[h]);
+            float zn = clipf(aI[h] + wI[h], loI[h], hiI[h]);
+            wI[h] += aI[h] - zn;
+            zI[h] = zn;
+            zn = clipf(a1[h] + w1[h], lo1[h], hi1[h]);
+            w1[h] += a1[h] - zn;
+            z1[h] = zn;
+            zn = clipf(a2[h] + w2[h], lo2[h], hi2[h]);
+            w2[h] += a2[h] - zn;
+            z2[h] = zn;
+            zn = clipf(aL[h] + wL[h], loL[h], hiL[h]);
+            wL[h] += aL[h] - zn;
+            zL[h] = zn;
+        }
     }
-    if (act) a.U_out[((long)j * H + k) * NU + d] = clipf(v, -a.u_max, a.u_max);
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+        if (act[h]) a.U_out[((long)j * H + k + 64 * h) * NU + d] = clipf(v[h], -a.u_max, a.u_max);
 }
 
 void launch_project(const ProjectArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(project_kernel, dim3(a.K), dim3(14 * 64), 0, s, a);
+    if (a.H <= 64)
+        hipLaunchKernelGGL(project_kernel<1>, dim3(a.K), dim3(14 * 64), 0, s, a);
+    else
+        hipLaunchKernelGGL(project_kernel<2>, dim3(a.K), dim3(14 * 64), 0, s, a);
 }
 
 }  // namespace mppi

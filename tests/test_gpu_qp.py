@@ -63,7 +63,7 @@ def _oracle(qpo, sc, U, X0, p):
                                  p["acc_max"], p["jerk_max"], p["rho"], p["iters"], p["alpha"])
 
 
-@pytest.mark.parametrize("K,H", [(8, 64), (5, 17), (3, 3), (2, 2), (4, 1)])
+@pytest.mark.parametrize("K,H", [(8, 64), (5, 17), (3, 3), (2, 2), (4, 1), (4, 65), (6, 100), (3, 128)])
 def test_project_matches_oracle(mp, ctx, qpo, K, H):
     sc = W.make_scene(2)
     scene = mp.Scene(ctx, sc)
@@ -98,6 +98,27 @@ def test_project_full_size_launch_on_sampled_sequences(mp, ctx, qpo):
     ref = _oracle(qpo, sc, U[idx], X0[idx], p)
     err = np.abs(got[idx] - ref).max()
     print(f"project K={K} H={H} (24 sampled): max |gpu - oracle| {err:.2e}")
+    assert err < ATOL
+    assert np.all(np.abs(got) <= float(sc["u_max"]) * (1 + 1e-6))
+    scene.close()
+
+
+def test_project_two_steps_per_lane_full_size_sampled(mp, ctx, qpo):
+    """The 8-box workload's sizes (K = 4096, H = 100: two horizon steps per
+    lane): 12 sampled sequences against the oracle."""
+    sc = W.make_scene(3)
+    scene = mp.Scene(ctx, sc)
+    p = W.qp_params(3)
+    K, H = 4096, 100
+    U, X0 = _inputs(sc, K, H, 3100)
+    out = torch.zeros((K, H, 14), device=DEV)
+    mp.mppi_project(ctx, scene, T(X0), T(U), out, p)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    idx = np.random.default_rng(6).choice(K, 12, replace=False)
+    ref = _oracle(qpo, sc, U[idx], X0[idx], p)
+    err = np.abs(got[idx] - ref).max()
+    print(f"project K={K} H={H} (12 sampled): max |gpu - oracle| {err:.2e}")
     assert err < ATOL
     assert np.all(np.abs(got) <= float(sc["u_max"]) * (1 + 1e-6))
     scene.close()
@@ -146,8 +167,8 @@ def test_project_rejects_bad_arguments(mp, ctx):
         with pytest.raises(mp.MppiError):
             mp.mppi_project(ctx, scene, x0, np.zeros((2, 8, 14), np.float32), np.zeros((2, 8, 14), np.float32),
                             {**p, **bad}, x0_shared=True)
-    with pytest.raises(mp.MppiError):  # longer than the kernel's one step per lane
-        mp.mppi_project(ctx, scene, x0, np.zeros((1, 65, 14), np.float32), np.zeros((1, 65, 14), np.float32), p,
+    with pytest.raises(mp.MppiError):  # longer than the kernel's two steps per lane
+        mp.mppi_project(ctx, scene, x0, np.zeros((1, 129, 14), np.float32), np.zeros((1, 129, 14), np.float32), p,
                         x0_shared=True)
     lo = np.array(p["pos_lo"])
     with pytest.raises(mp.MppiError):
