@@ -404,8 +404,9 @@ def bench_episode(mp, ctx, runs=((2, 8, False), (2, 8, True), (3, 4, False)), t_
     phases; the experiments' success metric: collision, timeout or a fallen
     ball fail a run): for each (config, n, full covariance) the first n
     seeded scenes of the workload at its K and H, M warm-started iterations
-    per replan (with the full covariance: eta and eps of the covariance
-    workload, Sigma_M warm-started).  Success rate, task time (simulated
+    per replan with the elite set and learning rate of the executor settings
+    (with the full covariance: Sigma_M warm-started, the settings' variance
+    floor).  Success rate, task time (simulated
     seconds to the goal) over the successes, and the compute time per replan
     pooled over every replan (mean, std)."""
     import numpy as np
@@ -413,15 +414,14 @@ def bench_episode(mp, ctx, runs=((2, 8, False), (2, 8, True), (3, 4, False)), t_
     out = {}
     for cfg, n, use_cov in runs:
         pp = W.plan_params(cfg)
-        cp = W.cov_params(cfg)
-        ep = W.episode_params(cfg, t_max=t_max, use_cov=int(use_cov), cov_eps=cp["eps"])
-        eta = cp["eta"] if use_cov else pp["eta"]
+        ep = W.episode_params(cfg, t_max=t_max, use_cov=int(use_cov))
+        eta = ep["eta"]
         res = []
         for i in range(n):
             pk, mv = W.episode_scenes(cfg, i)
             spk, smv = mp.Scene(ctx, pk), mp.Scene(ctx, mv)
             r = mp.mppi_episode(ctx, spk, smv, W.initial_state(mv), pp["K"], pp["H"], pp["lam"], pp["sigma"], ep,
-                                M=ep["M"], seed=1000 * cfg + i, eta=eta)
+                                M=ep["M"], seed=1000 * cfg + i, eta=eta, n_elite=ep["n_elite"])
             spk.close()
             smv.close()
             res.append(r)
@@ -437,7 +437,7 @@ def bench_episode(mp, ctx, runs=((2, 8, False), (2, 8, True), (3, 4, False)), t_
         tt = np.array([r["t_end"] for r in ok])
         out[f"config{cfg}" + ("_cov" if use_cov else "")] = {
             "runs": n, "K": pp["K"], "H": pp["H"], "M_per_replan": ep["M"], "n_avg": ep["n_avg"],
-            "covariance": {"eta": eta, "eps": cp["eps"]} if use_cov else None,
+            "n_elite": ep["n_elite"], "eta": eta, "covariance": {"eps": ep["cov_eps"]} if use_cov else None,
             "n_exec": ep["n_exec"], "t_max_s": t_max,
             "success_rate": len(ok) / n,
             "outcomes": {o: sum(r["outcome"] == o for r in res) for o in sorted({r["outcome"] for r in res})},

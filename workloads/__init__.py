@@ -293,10 +293,13 @@ def episode_params(config: int = 2, **overrides):
     pad distance; success within 5 cm of the goal; the ball counts as lifted
     5 cm above its resting height and as fallen back below 1 cm above it;
     timeout t_max (the experiments use 120 s; shorter here); iterations M
-    per warm-started replan."""
+    per warm-started replan; the elite set n_elite and learning rate eta of
+    each replan; cov_eps, the variance floor of the covariance update when
+    the full covariance is carried between replans (0.01 (rad/s)^2: a
+    standard deviation of 0.1 against the sampling sigma of 0.3)."""
     sc = make_scene(config)
     r = float(sc["ball_r"])
     p = dict(n_avg=2, n_exec=2, max_replans=0, grasp_tol=0.03, width_tol=0.02, goal_tol=0.05,
-             lift_z=r + 0.05, drop_z=r + 0.01, t_max=10.0, M=3)
+             lift_z=r + 0.05, drop_z=r + 0.01, t_max=10.0, M=3, n_elite=32, eta=0.8, use_cov=0, cov_eps=0.01)
     p.update(overrides)
     return p
