@@ -399,33 +399,36 @@ def bench_cov(mp, ctx, sc, pp, config, plain_ms, n_launch=20, n_plan=3):
     }
 
 
-def bench_episode(mp, ctx, runs=((2, 8, False), (2, 8, True), (3, 4, False)), t_max=10.0):
+def bench_episode(mp, ctx, runs=((2, 8, "diag"), (2, 8, "qp"), (2, 8, "cov"), (3, 4, "diag")), t_max=10.0):
     """Closed-loop ball transport (receding-horizon execution; pick and move
     phases; the experiments' success metric: collision, timeout or a fallen
-    ball fail a run): for each (config, n, full covariance) the first n
-    seeded scenes of the workload at its K and H, M warm-started iterations
-    per replan with the elite set and learning rate of the executor settings
-    (with the full covariance: Sigma_M warm-started, the settings' variance
-    floor).  Success rate, task time (simulated
+    ball fail a run): for each (config, n, variant) the first n seeded scenes
+    of the workload at its K and H, M warm-started iterations per replan with
+    the elite set and learning rate of the executor settings; variant "diag"
+    samples with the diagonal sigma, "qp" also smooths every sample by the
+    QP of the workload, "cov" carries the full covariance (Sigma_M
+    warm-started, the settings' variance floor).  Success rate, task time (simulated
     seconds to the goal) over the successes, and the compute time per replan
     pooled over every replan (mean, std)."""
     import numpy as np
     import workloads as W
     out = {}
-    for cfg, n, use_cov in runs:
+    for cfg, n, variant in runs:
         pp = W.plan_params(cfg)
+        use_cov = variant == "cov"
         ep = W.episode_params(cfg, t_max=t_max, use_cov=int(use_cov))
+        qp = W.qp_params(cfg) if variant == "qp" else None
         eta = ep["eta"]
         res = []
         for i in range(n):
             pk, mv = W.episode_scenes(cfg, i)
             spk, smv = mp.Scene(ctx, pk), mp.Scene(ctx, mv)
             r = mp.mppi_episode(ctx, spk, smv, W.initial_state(mv), pp["K"], pp["H"], pp["lam"], pp["sigma"], ep,
-                                M=ep["M"], seed=1000 * cfg + i, eta=eta, n_elite=ep["n_elite"])
+                                qp=qp, M=ep["M"], seed=1000 * cfg + i, eta=eta, n_elite=ep["n_elite"])
             spk.close()
             smv.close()
             res.append(r)
-            print(json.dumps({"episode": cfg, "cov": use_cov, "scene": i, "outcome": r["outcome"], "t_end": r["t_end"],
+            print(json.dumps({"episode": cfg, "variant": variant, "scene": i, "outcome": r["outcome"], "t_end": r["t_end"],
                               "replans": r["n_replans"], "t_comp_mean_ms": r["t_comp_mean_ms"]}),
                   file=sys.stderr, flush=True)
         ok = [r for r in res if r["status"] == 1]
@@ -435,9 +438,10 @@ def bench_episode(mp, ctx, runs=((2, 8, False), (2, 8, True), (3, 4, False)), t_
         m_all = float((nrep * mu).sum() / nrep.sum())
         v_all = float((nrep * (sd ** 2 + mu ** 2)).sum() / nrep.sum() - m_all ** 2)
         tt = np.array([r["t_end"] for r in ok])
-        out[f"config{cfg}" + ("_cov" if use_cov else "")] = {
+        out[f"config{cfg}" + ("" if variant == "diag" else "_" + variant)] = {
             "runs": n, "K": pp["K"], "H": pp["H"], "M_per_replan": ep["M"], "n_avg": ep["n_avg"],
             "n_elite": ep["n_elite"], "eta": eta, "covariance": {"eps": ep["cov_eps"]} if use_cov else None,
+            "qp_smoothing": variant == "qp",
             "n_exec": ep["n_exec"], "t_max_s": t_max,
             "success_rate": len(ok) / n,
             "outcomes": {o: sum(r["outcome"] == o for r in res) for o in sorted({r["outcome"] for r in res})},

@@ -304,6 +304,8 @@ int mppi_plan_best(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, cons
  *   in move: the ball above lift_z marks it lifted; lifted and below drop_z
  *     -> failure (fallen); |p_ball - goal| < goal_tol -> success;
  *   simulated time >= t_max -> failure (timeout).
+ * qp (nullable): every replan's samples are smoothed as by mppi_plan_qp
+ * (H <= 128) before their rollouts.
  * Host arrays only (x0[MPPI_NX], sigma, x_final[MPPI_NX] nullable; u_exec
  * [max_replans][14] and x_hist[max_replans][MPPI_NX], nullable, receive each
  * replan's executed command and the state after its execution and need
@@ -338,7 +340,8 @@ typedef struct mppi_episode_result {
 
 int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_scene *move, const float *x0, int K, int H,
                  double lambda, const float *sigma, const mppi_opts *opts, const mppi_episode_opts *eo,
-                 float *x_final, float *u_exec, float *x_hist, mppi_episode_result *res, void *stream);
+                 const mppi_qp *qp, float *x_final, float *u_exec, float *x_hist, mppi_episode_result *res,
+                 void *stream);
 
 /* --------------------------------------------------- covariance adaptation
  * Alg. 1 samples from N(nu_m, Sigma_m) with a full covariance over the whole

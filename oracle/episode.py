@@ -94,10 +94,31 @@ def best_sequence_cov(o, x, nominal, K, H, lam, Sigma, M, seed, eta, eps, u_max,
     return r["nu"], np.asarray(ub).reshape(H, 14), r["Sigma"]
 
 
-def run(o_pick, o_move, x0, K, H, lam, sigma, M, seed, ep, eta=1.0, n_elite=None, max_replans=None):
+def best_sequence_qp(o, x, nominal, K, H, lam, sigma, M, seed, eta, n_elite, project):
+    """(nu_M, best sequence of the final iteration) of the plan whose samples
+    nu + sigma z are smoothed by `project` before their rollouts."""
+    from oracle import cov
+    nu = np.asarray(nominal, dtype=np.float64).reshape(H, 14).copy()
+    sig = np.broadcast_to(np.asarray(sigma, dtype=np.float64).reshape(-1, 14), (H, 14))
+    U = c = None
+    for m in range(M):
+        nus = nu.astype(np.float32).astype(np.float64)
+        U = project(nus[None] + sig.astype(np.float32).astype(np.float64)[None] * o.noise(seed, K, H, m))
+        c = o.rollout_batch(x, U)
+        c = c[0] if isinstance(c, tuple) else c
+        w = cov.weights(c, lam, n_elite)
+        nu = cov.mean_update(U, w, nus, eta).reshape(H, 14)
+    c = np.asarray(c, dtype=np.float64)
+    fin = np.isfinite(c)
+    best = int(np.flatnonzero(fin)[np.argmin(c[fin])]) if fin.any() else -1
+    return nu, (U[best] if best >= 0 else nu)
+
+
+def run(o_pick, o_move, x0, K, H, lam, sigma, M, seed, ep, eta=1.0, n_elite=None, max_replans=None, project=None):
     """One closed-loop run; ep: the executor settings (n_avg, n_exec,
     tolerances, heights, t_max; use_cov and cov_eps for the plan with the
-    full covariance, warm-started with Sigma_M shifted like the mean).
+    full covariance, warm-started with Sigma_M shifted like the mean);
+    project(U, x): the QP smoothing of a replan's samples from state x.
     Returns the outcome, the executed commands and the state after each
     replan's execution."""
     rules = Rules(ep["grasp_tol"], ep["width_tol"], ep["goal_tol"], ep["lift_z"], ep["drop_z"], ep["t_max"])
@@ -115,6 +136,9 @@ def run(o_pick, o_move, x0, K, H, lam, sigma, M, seed, ep, eta=1.0, n_elite=None
         if use_cov:
             nu, ub, S = best_sequence_cov(o, x, nom, K, H, lam, S, M, seed + r, eta, ep["cov_eps"],
                                           float(o_move.scene["u_max"]), n_elite)
+        elif project is not None:
+            nu, ub = best_sequence_qp(o, x, nom, K, H, lam, sigma, M, seed + r, eta, n_elite,
+                                      lambda U, x=x: project(U, x))
         else:
             nu, ub = best_sequence(o, x, nom, K, H, lam, sigma, M, seed + r, eta, n_elite)
         u = ub[:ep["n_avg"]].mean(axis=0)

@@ -195,7 +195,8 @@ def lib():
             "mppi_plan_best": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts), _P, _P,
                                          _P, C.POINTER(Stats), _P]),
             "mppi_episode": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts),
-                                       C.POINTER(EpisodeOpts), _P, _P, _P, C.POINTER(EpisodeResult), _P]),
+                                       C.POINTER(EpisodeOpts), C.POINTER(QP), _P, _P, _P, C.POINTER(EpisodeResult),
+                                       _P]),
             "mppi_broadphase": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_float, _P, C.c_uint, _P]),
             "mppi_narrowphase": (C.c_int, [_P, _P, _P, C.c_int, _P, _P, _P, _P, _P, C.c_uint, _P]),
         }
@@ -428,12 +429,14 @@ def make_episode_opts(params):
     return e
 
 
-def mppi_episode(ctx, pick, move, x0, K, H, lam, sigma, eo, *, M=1, seed=0, eta=1.0, n_elite=0,
+def mppi_episode(ctx, pick, move, x0, K, H, lam, sigma, eo, *, qp=None, M=1, seed=0, eta=1.0, n_elite=0,
                  sigma_per_step=False, mapping=None, record=False, stream=None):
     """Closed-loop run of the ball task (host arrays).  eo: dict or
-    EpisodeOpts.  Returns the result dict, with x_final and, when `record`,
-    u_exec[n_replans, 14] and x_hist[n_replans, NX] (needs max_replans > 0)."""
+    EpisodeOpts; qp: dict or QP for the smoothing of every replan's samples.
+    Returns the result dict, with x_final and, when `record`, u_exec[n_replans,
+    14] and x_hist[n_replans, NX] (needs max_replans > 0)."""
     e = eo if isinstance(eo, EpisodeOpts) else make_episode_opts(eo)
+    q = None if qp is None else (qp if isinstance(qp, QP) else make_qp(qp))
     x0 = np.ascontiguousarray(x0, dtype=np.float32)
     sigma = np.ascontiguousarray(sigma, dtype=np.float32)
     xf = np.zeros(NX, np.float32)
@@ -443,7 +446,8 @@ def mppi_episode(ctx, pick, move, x0, K, H, lam, sigma, eo, *, M=1, seed=0, eta=
     o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
     r = EpisodeResult()
     _check(lib().mppi_episode(ctx._h, pick._h, move._h, x0.ctypes.data, int(K), int(H), float(lam),
-                              sigma.ctypes.data, C.byref(o), C.byref(e), xf.ctypes.data,
+                              sigma.ctypes.data, C.byref(o), C.byref(e), C.byref(q) if q is not None else None,
+                              xf.ctypes.data,
                               ue.ctypes.data if record else None, xh.ctypes.data if record else None, C.byref(r),
                               stream))
     d = r.as_dict()

@@ -1341,3 +1341,20 @@ int mppi_narrowphase(mppi_ctx *ctx, const mppi_scene *scene, const float *X, int
 }
 
 }  // extern "C"
+
+int mppi_host::plan_with(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                         double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp,
+                         const mppi_cov *cov, float *U_new, float *U_best, float *costs, mppi_stats *stats,
+                         void *stream)
+{
+    int rc;
+    if (qp && (rc = qp_check(qp, H))) return rc;
+    if (cov) {
+        mppi_cov c = *cov;
+        c.U_best = U_best;
+        return mppi_plan_cov(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, &c, qp, U_new, costs, stats,
+                             stream);
+    }
+    return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, qp, nullptr, U_new, costs, stats, stream,
+                     U_best);
+}

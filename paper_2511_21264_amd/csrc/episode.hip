@@ -2,7 +2,8 @@
 // planner (Alg. 1's output executed as the paper describes: the first steps
 // of the best sequence averaged and run, the next plan warm-started), with
 // the phase machine and termination rules of episode.h.  Host code over the
-// library's own entry points (mppi_plan_best, mppi_simulate).
+// library's own plan (optionally with the QP smoothing and the full
+// covariance) and mppi_simulate.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,8 +18,8 @@ using mppi_host::fail;
 
 extern "C" int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_scene *move, const float *x0, int K,
                             int H, double lambda, const float *sigma, const mppi_opts *opts,
-                            const mppi_episode_opts *eo, float *x_final, float *u_exec, float *x_hist,
-                            mppi_episode_result *res, void *stream)
+                            const mppi_episode_opts *eo, const mppi_qp *qp, float *x_final, float *u_exec,
+                            float *x_hist, mppi_episode_result *res, void *stream)
 {
     using mppi::NU;
     using mppi::NX;
@@ -67,15 +68,10 @@ extern "C" int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_sc
         const mppi_scene *sc = es.phase == mppi::EP_PICK ? pick : move;
         mppi_stats ps;
         const auto t0 = std::chrono::steady_clock::now();
-        int rc;
-        if (eo->use_cov) {
-            mppi_cov cv = {Sg.data(), Sg.data(), eo->cov_eps, ubest.data()};
-            rc = mppi_plan_cov(ctx, sc, x.data(), nom.data(), K, H, lambda, sigma, &o, &cv, nullptr, unew.data(),
-                               nullptr, &ps, stream);
-        } else {
-            rc = mppi_plan_best(ctx, sc, x.data(), nom.data(), K, H, lambda, sigma, &o, unew.data(), ubest.data(),
-                                nullptr, &ps, stream);
-        }
+        mppi_cov cv = {Sg.data(), Sg.data(), eo->cov_eps, nullptr};
+        int rc = mppi_host::plan_with(ctx, sc, x.data(), nom.data(), K, H, lambda, sigma, &o, qp,
+                                      eo->use_cov ? &cv : nullptr, unew.data(), ubest.data(), nullptr, &ps,
+                                      stream);
         tcomp.push_back(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         if (rc == MPPI_E_DIVERGED)
             ++n_div;

@@ -78,4 +78,9 @@ struct mppi_scene {
 
 namespace mppi_host {
 int set_device(mppi_ctx *c);
+// a plan with any of the options (qp, cov nullable) and the best sequence of
+// the final iteration in U_best (nullable), as the public entry points run it
+int plan_with(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+              double lambda, const float *sigma, const mppi_opts *opts, const mppi_qp *qp, const mppi_cov *cov,
+              float *U_new, float *U_best, float *costs, mppi_stats *stats, void *stream);
 }
