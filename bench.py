@@ -399,7 +399,8 @@ def bench_cov(mp, ctx, sc, pp, config, plain_ms, n_launch=20, n_plan=3):
     }
 
 
-def bench_episode(mp, ctx, runs=((2, 8, "diag"), (2, 8, "qp"), (2, 8, "cov"), (3, 4, "diag")), t_max=10.0):
+def bench_episode(mp, ctx, runs=((2, 8, "diag"), (2, 8, "qp"), (2, 8, "cov"), (3, 4, "diag"), (2, 8, "qp", 256),
+                                 (2, 8, "qp", 512), (2, 8, "qp", 2048)), t_max=10.0):
     """Closed-loop ball transport (receding-horizon execution; pick and move
     phases; the experiments' success metric: collision, timeout or a fallen
     ball fail a run): for each (config, n, variant) the first n seeded scenes
@@ -407,14 +408,18 @@ def bench_episode(mp, ctx, runs=((2, 8, "diag"), (2, 8, "qp"), (2, 8, "cov"), (3
     the elite set and learning rate of the executor settings; variant "diag"
     samples with the diagonal sigma, "qp" also smooths every sample by the
     QP of the workload, "cov" carries the full covariance (Sigma_M
-    warm-started, the settings' variance floor).  Success rate, task time (simulated
+    warm-started, the settings' variance floor); a fourth entry overrides
+    K (the batch-size sweep of the closed loop).  Success rate, task time (simulated
     seconds to the goal) over the successes, and the compute time per replan
     pooled over every replan (mean, std)."""
     import numpy as np
     import workloads as W
     out = {}
-    for cfg, n, variant in runs:
+    for run in runs:
+        cfg, n, variant = run[:3]
         pp = W.plan_params(cfg)
+        if len(run) > 3:
+            pp["K"] = run[3]
         use_cov = variant == "cov"
         ep = W.episode_params(cfg, t_max=t_max, use_cov=int(use_cov))
         qp = W.qp_params(cfg) if variant == "qp" else None
@@ -438,7 +443,7 @@ def bench_episode(mp, ctx, runs=((2, 8, "diag"), (2, 8, "qp"), (2, 8, "cov"), (3
         m_all = float((nrep * mu).sum() / nrep.sum())
         v_all = float((nrep * (sd ** 2 + mu ** 2)).sum() / nrep.sum() - m_all ** 2)
         tt = np.array([r["t_end"] for r in ok])
-        out[f"config{cfg}" + ("" if variant == "diag" else "_" + variant)] = {
+        out[f"config{cfg}" + ("" if variant == "diag" else "_" + variant) + (f"_K{run[3]}" if len(run) > 3 else "")] = {
             "runs": n, "K": pp["K"], "H": pp["H"], "M_per_replan": ep["M"], "n_avg": ep["n_avg"],
             "n_elite": ep["n_elite"], "eta": eta, "covariance": {"eps": ep["cov_eps"]} if use_cov else None,
             "qp_smoothing": variant == "qp",
