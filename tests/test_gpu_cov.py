@@ -275,3 +275,34 @@ def test_plan_cov_full_size_first_iteration_and_sigma(mp, ctx):
     assert np.array_equal(S, S.T)
     assert ev.min() > 0.5 * cp["eps"]
     scene.close()
+
+
+def test_cov_entry_points_reject_bad_arguments(mp, ctx):
+    sc = W.make_scene(1)
+    scene = mp.Scene(ctx, sc)
+    pp = W.plan_params(1)
+    H = pp["H"]
+    n = 14 * H
+    x0 = W.initial_state(sc).astype(np.float32)
+    sig = pp["sigma"].astype(np.float32)
+    U = np.zeros((H, 14), np.float32)
+    for kw in (dict(eps=-1.0), dict(eps=np.inf), dict(eta=0.0), dict(eta=1.5)):
+        args = dict(eps=1e-4, eta=0.5)
+        args.update(kw)
+        with pytest.raises(mp.MppiError):
+            mp.mppi_plan_cov(ctx, scene, x0, U, 8, H, pp["lam"], sig, U, eps=args["eps"], eta=args["eta"])
+    with pytest.raises(mp.MppiError):  # n = 14 H above the covariance limit
+        Hb = mp.COV_MAX_N // 14 + 1
+        mp.mppi_plan_cov(ctx, scene, x0, np.zeros((Hb, 14), np.float32), 8, Hb, pp["lam"], sig,
+                         np.zeros((Hb, 14), np.float32), eps=1e-4, eta=0.5)
+    with pytest.raises(mp.MppiError):  # a host Sigma_0 with a non-finite entry
+        S0 = np.eye(n)
+        S0[3, 3] = np.nan
+        mp.mppi_plan_cov(ctx, scene, x0, U, 8, H, pp["lam"], sig, U, eps=1e-4, eta=0.5, Sigma0=S0)
+    L = np.eye(14)
+    with pytest.raises(mp.MppiError):  # u_max must be positive
+        mp.mppi_sample_full(ctx, np.zeros((1, 14), np.float32), L, 1, 0, 4, np.zeros((4, 1, 14), np.float32), 0.0)
+    with pytest.raises(mp.MppiError):  # n above the limit
+        m = mp.COV_MAX_N + 1
+        mp.mppi_cholesky(ctx, np.eye(m), np.zeros((m, m)))
+    scene.close()
