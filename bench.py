@@ -578,6 +578,8 @@ def profile_meta():
         ],
         "next_commands": [
             f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace_next -o run -- {bn}",
+            f"timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/fetch_next -o run -- {bn}",
+            f"timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/write_next -o run -- {bn}",
             "python3 bench.py --summarize-profiles gpurun_out/prof",
         ],
     }
@@ -600,24 +602,57 @@ def summarize_next(base, meta):
         "cov_syrk_kernel": (float(K) * n * (n + 1), PEAK_FP64, "FP64 MFMA"),
         "sample_full_kernel": (float(K) * n * (n + 1), PEAK_FP32, "FP32 MFMA"),
     }
+    # algorithmic HBM bytes per launch: inputs read once, outputs written once
+    alg_bytes = {
+        "project_kernel": K * H * 14 * 4 * 2 + H * (H + 4) * 4,   # samples in and out, P
+        "cov_syrk_kernel": K * n * 4 + K * 8 + n * 8 + 2 * n * n * 8,  # samples, weights, mean, Sigma in and out
+        "sample_full_kernel": 2 * K * n * 4 + n * n * 4 // 2,    # normals in, samples out, lower factor
+        "chol_step_kernel": None, "chol_diag_kernel": None,
+    }
+
+    def counter_avg(sub, name):
+        g = glob.glob(os.path.join(base, sub, "**", "*results.db"), recursive=True)
+        if not g:
+            return {}
+        c = sqlite3.connect(g[0])
+        rows = c.execute("select kernel_name, avg(value) from counters_collection where counter_name = ? "
+                         "group by kernel_name", (name,)).fetchall()
+        return {k.split("(")[0].replace("mppi::", "").replace("void ", ""): v for k, v in rows}
+
+    fetch, write = counter_avg("fetch_next", "FETCH_SIZE"), counter_avg("write_next", "WRITE_SIZE")
+    cf, cw = counter_avg("cfetch", "FETCH_SIZE"), counter_avg("cwrite", "WRITE_SIZE")
+    copy_kib = (256 << 20) / 1024.0
+    f_scale = copy_kib / cf["__amd_rocclr_copyBuffer"] if cf.get("__amd_rocclr_copyBuffer") else None
+    w_scale = copy_kib / cw["__amd_rocclr_copyBuffer"] if cw.get("__amd_rocclr_copyBuffer") else None
     md = ["# QP smoothing and covariance kernels, K=1024, H=64 (n = 896): kernel time", "",
           "Commands (run from the repository root, TMPDIR=/tmp):", ""]
     md += [f"    {c}" for c in meta["next_commands"]]
-    md += ["", "| kernel | calls | avg us | algorithmic GFLOP per launch | TFLOP/s | fraction of peak |",
-           "|---|---|---|---|---|---|"]
+    md += ["", "| kernel | calls | avg us | algorithmic GFLOP per launch | TFLOP/s | fraction of peak | "
+               "HBM MB per launch (counters) | algorithmic MB |",
+           "|---|---|---|---|---|---|---|---|"]
     for name, calls, tot, avg in rows:
         short = name.split("(")[0].replace("mppi::", "").replace("void ", "")
+        short = short.split("<")[0] if short.startswith("project_kernel") else short
         if short.startswith(("rollout", "stats", "update", "reset", "at::", "__amd")):
             continue
+        key = next((k for k in fetch if k.split("<")[0] == short), None)
+        traffic = ""
+        if key and f_scale and w_scale and key in write:
+            traffic = f"{(fetch[key] * f_scale + write[key] * w_scale) * 1024 / 1e6:.2f}"
+        ab = alg_bytes.get(short)
+        ab = f"{ab / 1e6:.2f}" if ab else ""
         fl = model.get(short)
         if fl:
             tf = fl[0] / (avg * 1e-6) / 1e12
             md.append(f"| {short} | {calls} | {avg:.1f} | {fl[0] / 1e9:.2f} | {tf:.1f} | {tf * 1e12 / fl[1]:.3f} "
-                      f"({fl[2]}) |")
+                      f"({fl[2]}) | {traffic} | {ab} |")
         else:
-            md.append(f"| {short} | {calls} | {avg:.1f} | | | |")
+            md.append(f"| {short} | {calls} | {avg:.1f} | | | | {traffic} | {ab} |")
     md += ["", "The Cholesky of n = 896 is one `chol_diag_kernel` and 27 `chol_step_kernel` launches in sequence "
-           "(n^3/3 = 0.24 GFLOP in FP64); its time is the chain of 896 column steps, not arithmetic."]
+           "(n^3/3 = 0.24 GFLOP in FP64); its time is the chain of 896 column steps, not arithmetic.",
+           "", "HBM bytes from FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the counters read for a "
+           "256 MiB device copy (the calibration of the rollout profile); the QP and covariance legs include "
+           "whole plans, so the averages mix launches of the plan sizes with the legs' own."]
     open(os.path.join(ROOT, "profiles", "qp_cov_kernels_c2.md"), "w").write("\n".join(md) + "\n")
     print("\n".join(md))
 
