@@ -48,6 +48,16 @@ __device__ __forceinline__ void tri_index(int t, int &row, int &col)
     col = t - b * (b + 1) / 2;
 }
 
+// Workgroups are dealt to the eight XCDs (each with its own L2) in turn by
+// their index b; this maps b to a logical tile so that every XCD takes one
+// contiguous range of tiles (a bijection on 0 .. nb - 1): tiles that share
+// input rows then share an L2.
+__device__ __forceinline__ int xcd_order(int b, int nb)
+{
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 __device__ __forceinline__ double wave_sum_f64(double x)
 {
 #pragma unroll
@@ -58,12 +68,14 @@ __device__ __forceinline__ double wave_sum_f64(double x)
 }  // namespace
 
 // ------------------------------------------------------------ covariance update
+constexpr int CG = 8;  // groups of four samples per wave and step
+
 __global__ void __launch_bounds__(256) cov_syrk_kernel(CovArgs a)
 {
     __shared__ double red[4][CT][CT + 1];
     __shared__ double wred[4];
     int bi, bl;
-    tri_index(blockIdx.x, bi, bl);
+    tri_index(xcd_order(blockIdx.x, gridDim.x), bi, bl);  // consecutive rows of tiles share an XCD
     const int n = a.n, K = a.K;
     const int i0 = bi * CT, l0 = bl * CT;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -73,31 +85,53 @@ __global__ void __launch_bounds__(256) cov_syrk_kernel(CovArgs a)
     const double nl0 = lb0 < n ? a.nu[lb0] : 0.0, nl1 = lb1 < n ? a.nu[lb1] : 0.0;
     d4 c00 = {0.0, 0.0, 0.0, 0.0}, c01 = c00, c10 = c00, c11 = c00;
     double ws = 0.0;
-    // wave wv takes the groups of four samples j0 = 4 wv, 4 wv + 16, ..., two
-    // groups per step so that their loads are in flight together
-    for (int j0 = 4 * wv; j0 < K; j0 += 32) {
-        double x0[2], x1[2], y0[2], y1[2], w[2];
+    // wave wv takes the groups of four samples j0 = 4 wv, 4 wv + 16, ...,
+    // CG groups per step; the loads of step s + 1 are issued before the
+    // products of step s.  Sample values do not wait on their weight: a
+    // weightless sample is dropped by a select afterwards (so a non-finite
+    // entry in it still contributes nothing).
+    float uc[CG][4], un[CG][4] = {};
+    double wc[CG], wn[CG] = {};
+    auto load = [&](int j0, float (&u4)[CG][4], double (&w2)[CG]) {
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < CG; ++g) {
             const int j = j0 + 16 * g + q;
-            w[g] = j < K ? a.w[j] : 0.0;
-            if (r == 0) ws += w[g];
-            x0[g] = x1[g] = y0[g] = y1[g] = 0.0;
-            if (w[g] != 0.0) {
-                const float *u = a.U + (long)j * n;
-                if (ia0 < n) x0[g] = (double)u[ia0] - na0;
-                if (ia1 < n) x1[g] = (double)u[ia1] - na1;
-                if (lb0 < n) y0[g] = w[g] * ((double)u[lb0] - nl0);
-                if (lb1 < n) y1[g] = w[g] * ((double)u[lb1] - nl1);
+            const bool ok = j < K;
+            const float *u = a.U + (long)(ok ? j : 0) * n;
+            w2[g] = ok ? a.w[j] : 0.0;
+            u4[g][0] = (ok && ia0 < n) ? u[ia0] : 0.f;
+            u4[g][1] = (ok && ia1 < n) ? u[ia1] : 0.f;
+            u4[g][2] = (ok && lb0 < n) ? u[lb0] : 0.f;
+            u4[g][3] = (ok && lb1 < n) ? u[lb1] : 0.f;
+        }
+    };
+    load(4 * wv, uc, wc);
+    for (int j0 = 4 * wv; j0 < K; j0 += 16 * CG) {
+        if (j0 + 16 * CG < K) load(j0 + 16 * CG, un, wn);
+        bool any = false;
+#pragma unroll
+        for (int g = 0; g < CG; ++g) {
+            if (r == 0) ws += wc[g];
+            any = any || wc[g] != 0.0;
+        }
+        if (__ballot(any) != 0) {  // skipped when no group of the step carries weight
+#pragma unroll
+            for (int g = 0; g < CG; ++g) {
+                const bool on = wc[g] != 0.0;
+                const double x0 = on ? (double)uc[g][0] - na0 : 0.0, x1 = on ? (double)uc[g][1] - na1 : 0.0;
+                const double y0 = on ? wc[g] * ((double)uc[g][2] - nl0) : 0.0;
+                const double y1 = on ? wc[g] * ((double)uc[g][3] - nl1) : 0.0;
+                c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, c00, 0, 0, 0);
+                c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, c01, 0, 0, 0);
+                c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, c10, 0, 0, 0);
+                c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, c11, 0, 0, 0);
             }
         }
-        if (__ballot(w[0] != 0.0 || w[1] != 0.0) == 0) continue;  // no weight in either group (elites only)
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[g], y0[g], c00, 0, 0, 0);
-            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[g], y1[g], c01, 0, 0, 0);
-            c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[g], y0[g], c10, 0, 0, 0);
-            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[g], y1[g], c11, 0, 0, 0);
+        for (int g = 0; g < CG; ++g) {
+            wc[g] = wn[g];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) uc[g][e] = un[g][e];
         }
     }
 #pragma unroll
@@ -124,7 +158,15 @@ __global__ void __launch_bounds__(256) cov_syrk_kernel(CovArgs a)
             if (i == l) v += a.eps;
         }
         a.S_out[(long)i * n + l] = v;
-        if (i != l) a.S_out[(long)l * n + i] = v;
+        red[0][ti][tl] = v;  // read above by this thread only
+    }
+    __syncthreads();
+    // the mirrored upper half, written along its rows
+    for (int e = threadIdx.x; e < CT * CT; e += 256) {
+        const int tl = e / CT, ti = e % CT;
+        const int i = i0 + ti, l = l0 + tl;
+        if (i >= n || l >= n || i == l || (bi == bl && ti < tl)) continue;
+        a.S_out[(long)l * n + i] = red[0][ti][tl];
     }
 }
 
@@ -396,24 +438,38 @@ __global__ void __launch_bounds__(256) sample_full_kernel(SampleFullArgs a)
     __shared__ float zs[SJ][SP + 1];
     __shared__ float ls[SI][SP + 1];
     const int n = a.n, K = a.K;
-    const int i0 = blockIdx.x * SI, j0 = blockIdx.y * SJ;
+    // all column tiles of a block of samples on one XCD (their normals share its L2)
+    const int ni = (n + SI - 1) / SI, tile = xcd_order(blockIdx.x, gridDim.x);
+    const int i0 = (tile % ni) * SI, j0 = (tile / ni) * SJ;
     const int t = threadIdx.x, wv = t >> 6, lane = t & 63, r = lane & 15, q = lane >> 4;
     f4 c0 = {0.f, 0.f, 0.f, 0.f};
     const int pend = min(n, i0 + SI);  // L is lower: columns past the tile's last row are zero
-    for (int p0 = 0; p0 < pend; p0 += SP) {
-        // stage Z[j0.., p0..] (16 x 32) and L[i0.., p0..] (64 x 32): thread t takes column t % 32
-        const int pc = t & 31, rw = t >> 5, p = p0 + pc;
+    // chunk p0 holds Z[j0.., p0..] (16 x 32) and L[i0.., p0..] (64 x 32):
+    // thread t takes column t % 32; the next chunk is loaded into registers
+    // while the current one is multiplied
+    const int pc = t & 31, rw = t >> 5;
+    float zr[SJ / 8], lr[SI / 8];
+    auto load = [&](int p0) {
+        const int p = p0 + pc;
 #pragma unroll
         for (int u = 0; u < SJ / 8; ++u) {
             const int row = rw + 8 * u;
-            zs[row][pc] = (j0 + row < K && p < n) ? a.Z[(long)(j0 + row) * n + p] : 0.f;
+            zr[u] = (j0 + row < K && p < n) ? a.Z[(long)(j0 + row) * n + p] : 0.f;
         }
 #pragma unroll
         for (int u = 0; u < SI / 8; ++u) {
             const int row = rw + 8 * u;
-            ls[row][pc] = (i0 + row < n && p < n) ? a.L32[(long)(i0 + row) * n + p] : 0.f;
+            lr[u] = (i0 + row < n && p < n) ? a.L32[(long)(i0 + row) * n + p] : 0.f;
         }
+    };
+    load(0);
+    for (int p0 = 0; p0 < pend; p0 += SP) {
+#pragma unroll
+        for (int u = 0; u < SJ / 8; ++u) zs[rw + 8 * u][pc] = zr[u];
+#pragma unroll
+        for (int u = 0; u < SI / 8; ++u) ls[rw + 8 * u][pc] = lr[u];
         __syncthreads();
+        if (p0 + SP < pend) load(p0 + SP);
 #pragma unroll
         for (int kk = 0; kk < SP / 4; ++kk)
             c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(zs[r][4 * kk + q], ls[16 * wv + r][4 * kk + q], c0, 0, 0, 0);
@@ -433,7 +489,7 @@ void launch_sample_full(const SampleFullArgs &a, hipStream_t s)
     const long N = (long)a.K * a.n;
     const int g = (int)std::min<long>((N + 255) / 256, 8192);
     hipLaunchKernelGGL(normals_kernel, dim3(g), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(sample_full_kernel, dim3((a.n + SI - 1) / SI, (a.K + SJ - 1) / SJ), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sample_full_kernel, dim3(((a.n + SI - 1) / SI) * ((a.K + SJ - 1) / SJ)), dim3(256), 0, s, a);
 }
 
 __global__ void __launch_bounds__(256) diag_sigma_kernel(const float *sigma, int sps, int n, double *S)
