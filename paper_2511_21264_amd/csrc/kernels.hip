@@ -300,6 +300,10 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
     block_scene(a0, tab, blk, m, a, bid);
     const int wave = threadIdx.x >> 6;
     const bool geo = wave == 1;
+    // the dynamics wave carries each substep's critical path: it issues
+    // ahead of the geometry waves that share its SIMD (priority 2 inside the
+    // general contact solve)
+    if (!geo) __builtin_amdgcn_s_setprio(1);
     const int lane = threadIdx.x & 63;
     const int row = lane >> 4;
     float *blockD = lds + HD_FIELDS, *blockG = blockD + team_lds_floats(NC);
@@ -388,7 +392,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
             __syncthreads();  // B2: the contact list and its count are in LDS
             if (!geo) {
                 const int nc = __float_as_int(SA[17]);
-                team_finish<NC, true>(model(a.md), tc, S, kk, nc, v, vb, wb);
+                team_finish<NC, true, true>(model(a.md), tc, S, kk, nc, v, vb, wb);
                 if (tc.joint) SA[d] = S.q;
                 if (lane == 0) { SA[14] = S.pb.x; SA[15] = S.pb.y; SA[16] = S.pb.z; }
                 if (s == nsub - 1 && a.xout && a.traj && row == 0) {

@@ -14,7 +14,7 @@
 //
 // Mapping: one workgroup per sample, one wave per joint (14 waves), one
 // horizon step per lane for H <= 64 and two (steps k and k + 64) for
-// H <= 128.  A v and A^T y are wave-wide shuffles and
+// H <= 128.  A v and A^T y are DPP whole-wave shifts and
 // scans (neighbour differences, prefix and suffix sums).  The dense product
 // with P, the same for every joint and sample, is one 64 x 64 by 64 x 16
 // product per iteration on FP32 MFMA: the waves publish their right-hand
@@ -45,23 +45,35 @@ __device__ __forceinline__ float shl_row(float v)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x100 + S, 0xF, 0xF, true));
 }
+// whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane k reads
+// lane k - 1 / k + 1; lane 0 / 63 reads 0
+__device__ __forceinline__ float wave_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float wave_shl1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
 template <int L>
 __device__ __forceinline__ float lane_of(float v)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
 }
 
-// inclusive prefix sum over the wave
-__device__ __forceinline__ float prefix64(float x, int k)
+// inclusive prefix sum over the wave: scans within the rows, then the row
+// totals carried by DPP row_bcast:15 (lane 15 of each row into the next row;
+// rows 1 and 3 take it) and row_bcast:31 (lane 31 into rows 2 and 3); lanes
+// of the rows a broadcast leaves out add 0
+__device__ __forceinline__ float prefix64(float x, int)
 {
     x += shr_row<1>(x);
     x += shr_row<2>(x);
     x += shr_row<4>(x);
     x += shr_row<8>(x);
-    const float t0 = lane_of<15>(x), t1 = lane_of<31>(x), t2 = lane_of<47>(x);
-    const int row = k >> 4;
-    const float off = row == 0 ? 0.f : (row == 1 ? t0 : (row == 2 ? t0 + t1 : (t0 + t1) + t2));
-    return x + off;
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xA, 0xF, true));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xC, 0xF, true));
+    return x;
 }
 // inclusive suffix sum over the wave
 __device__ __forceinline__ float suffix64(float x, int k)
@@ -81,7 +93,7 @@ __device__ __forceinline__ float suffix64(float x, int k)
 __device__ __forceinline__ void apply_A(float v, int k, bool act, float &aI, float &a1, float &a2, float &aL)
 {
     const float x = act ? v : 0.f;
-    const float vm1 = __shfl_up(x, 1), vm2 = __shfl_up(x, 2);  // masked below where they wrap
+    const float vm1 = wave_shr1(x), vm2 = wave_shr1(vm1);  // 0 before step 0
     aI = x;
     a1 = (act && k >= 1) ? x - vm1 : 0.f;
     a2 = (act && k >= 2) ? (x - 2.f * vm1) + vm2 : 0.f;
@@ -93,9 +105,8 @@ __device__ __forceinline__ void apply_A(float v, int k, bool act, float &aI, flo
 // (y2_k - 2 y2_{k+1} + y2_{k+2}) + sum_{i >= k} yL_i
 __device__ __forceinline__ float apply_At(float yI, float y1, float y2, float yL, int k)
 {
-    // every lane takes part in each shuffle; the end of the wave is masked after
-    const float t1 = __shfl_down(y1, 1), t2 = __shfl_down(y2, 1), t3 = __shfl_down(y2, 2);
-    const float y1n = k + 1 < 64 ? t1 : 0.f, y2n = k + 1 < 64 ? t2 : 0.f, y2nn = k + 2 < 64 ? t3 : 0.f;
+    // the shifts read 0 past the end of the wave
+    const float y1n = wave_shl1(y1), y2n = wave_shl1(y2), y2nn = wave_shl1(y2n);
     return yI + (y1 - y1n) + ((y2 - 2.f * y2n) + y2nn) + suffix64(yL, k);
 }
 
@@ -107,7 +118,7 @@ __device__ __forceinline__ void apply_A2(const float v[2], int k, const bool act
 {
     const float x0 = act[0] ? v[0] : 0.f, x1 = act[1] ? v[1] : 0.f;
     const float e62 = lane_of<62>(x0), e63 = lane_of<63>(x0);
-    const float u0 = __shfl_up(x0, 1), w0 = __shfl_up(x0, 2), u1 = __shfl_up(x1, 1), w1 = __shfl_up(x1, 2);
+    const float u0 = wave_shr1(x0), w0 = wave_shr1(u0), u1 = wave_shr1(x1), w1 = wave_shr1(u1);
     const float vm1_0 = u0, vm2_0 = w0;                                  // used for k >= 1 / k >= 2
     const float vm1_1 = k >= 1 ? u1 : e63, vm2_1 = k >= 2 ? w1 : (k == 1 ? e63 : e62);
     aI[0] = x0;
@@ -126,13 +137,13 @@ __device__ __forceinline__ void apply_At2(const float yI[2], const float y1[2], 
                                           int k, float out[2])
 {
     const float b10 = lane_of<0>(y1[1]), b20 = lane_of<0>(y2[1]), b21 = lane_of<1>(y2[1]);
-    const float s1_0 = __shfl_down(y1[0], 1), s2_0 = __shfl_down(y2[0], 1), s22_0 = __shfl_down(y2[0], 2);
-    const float s1_1 = __shfl_down(y1[1], 1), s2_1 = __shfl_down(y2[1], 1), s22_1 = __shfl_down(y2[1], 2);
+    const float s1_0 = wave_shl1(y1[0]), s2_0 = wave_shl1(y2[0]), s22_0 = wave_shl1(s2_0);
+    const float s1_1 = wave_shl1(y1[1]), s2_1 = wave_shl1(y2[1]), s22_1 = wave_shl1(s2_1);
     // half 0: steps k + 1, k + 2 may lie in half 1
     const float y1n0 = k + 1 < 64 ? s1_0 : b10, y2n0 = k + 1 < 64 ? s2_0 : b20;
     const float y2nn0 = k + 2 < 64 ? s22_0 : (k == 62 ? b20 : b21);
     // half 1: nothing past step 127
-    const float y1n1 = k + 1 < 64 ? s1_1 : 0.f, y2n1 = k + 1 < 64 ? s2_1 : 0.f, y2nn1 = k + 2 < 64 ? s22_1 : 0.f;
+    const float y1n1 = s1_1, y2n1 = s2_1, y2nn1 = s22_1;  // the shifts read 0 past lane 63
     const float q1 = suffix64(yL[1], k);
     const float q0 = suffix64(yL[0], k) + lane_of<0>(q1);
     out[0] = yI[0] + (y1[0] - y1n0) + ((y2[0] - 2.f * y2n0) + y2nn0) + q0;
@@ -236,9 +247,15 @@ __global__ void __launch_bounds__(14 * 64) project_kernel(ProjectArgs a)
             // element e of lane l is row 4 (l / 16) + e, joint l % 16
             typedef float f4 __attribute__((ext_vector_type(4)));
             f4 acc = {0.f, 0.f, 0.f, 0.f};
+            if (nst == NST) {  // full horizon: one unguarded chain
 #pragma unroll
-            for (int st = 0; st < NST; ++st)
-                if (st < nst) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[st], R[lr][4 * st + lq], acc, 0, 0, 0);
+                for (int st = 0; st < NST; ++st)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[st], R[lr][4 * st + lq], acc, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int st = 0; st < NST; ++st)
+                    if (st < nst) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[st], R[lr][4 * st + lq], acc, 0, 0, 0);
+            }
             *reinterpret_cast<f4 *>(&V[lr][16 * d + 4 * lq]) = acc;
         }
         __syncthreads();

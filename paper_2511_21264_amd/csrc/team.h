@@ -1345,17 +1345,22 @@ __device__ inline void team_contact_solve_rows(const DevModel &md, const TeamCtx
 
 // Contact solve and semi-implicit Euler: the end of a substep.  ROWS: the
 // wave's four 16-lane rows carry one team, so a solve of up to four contacts
-// spreads its per-contact work over them.
-template <int NC, bool ROWS = false>
+// spreads its per-contact work over them.  PRIO: the caller runs at wave
+// priority 1 and the general solve at 2 (issue priority only; the results
+// do not change): a launch lasts as long as its slowest samples, which are
+// the ones that spend many substeps in this solve.
+template <int NC, bool ROWS = false, bool PRIO = false>
 __device__ inline void team_finish(const DevModel &md, const TeamCtx &tc, TeamState &S, const JointKin &k, int nc,
                                    float v, V3 vb, V3 wb)
 {
     const float h = md.h;
-    if (ball_only_contact(tc.LL, nc))
+    if (ball_only_contact(tc.LL, nc)) {
         ball_contact_solve(md, tc.LL, S.pb, vb, wb);
-    else if (ROWS && nc > 0 && nc <= 4)
+    } else if (ROWS && nc > 0 && nc <= 4) {
+        if (PRIO) __builtin_amdgcn_s_setprio(2);
         team_contact_solve_rows<NC>(md, tc, k, S.pb, nc, v, vb, wb);
-    else if (nc > 0)
+        if (PRIO) __builtin_amdgcn_s_setprio(1);
+    } else if (nc > 0)
         team_contact_solve<NC>(md, tc, k, S.pb, nc, v, vb, wb);
     S.q = fmaf(h, v, S.q);
     S.qd = v;
