@@ -56,7 +56,7 @@ def _spd(n, seed, scale=0.09):
     return scale * (A @ A.T + 0.1 * np.eye(n))
 
 
-@pytest.mark.parametrize("K,H,eta", [(64, 20, 1.0), (1024, 64, 0.5), (37, 3, 0.3), (5, 1, 1.0)])
+@pytest.mark.parametrize("K,H,eta", [(64, 20, 1.0), (1024, 64, 0.5), (37, 3, 0.3), (5, 1, 1.0), (32, 256, 0.7)])
 def test_cov_update_matches_oracle(mp, ctx, cov, K, H, eta):
     n = 14 * H
     rng = np.random.default_rng(K + H)
@@ -108,7 +108,7 @@ def test_cov_update_rejects_bad_arguments(mp, ctx):
         mp.mppi_cov_update(ctx, U, np.array([1.0, -1.0, 0.0, 0.0]), np.zeros(14), S, np.zeros_like(S), 0.5)
 
 
-@pytest.mark.parametrize("n", [14, 33, 280, 896, 1400])
+@pytest.mark.parametrize("n", [14, 33, 280, 896, 1400, 3584])
 def test_cholesky_matches_oracle(mp, ctx, cov, n):
     S = _spd(n, n)
     ref = cov.factor(S)
@@ -137,7 +137,7 @@ def test_cholesky_in_place_host_and_not_positive_definite(mp, ctx, cov):
     assert e.value.code == mp.E_NOTPD and "column 40" in str(e.value)
 
 
-@pytest.mark.parametrize("K,H", [(64, 20), (1024, 64), (70, 3), (1, 100)])
+@pytest.mark.parametrize("K,H", [(64, 20), (1024, 64), (70, 3), (1, 100), (8, 256)])
 def test_sample_full_matches_oracle(mp, ctx, cov, K, H):
     import oracle
     sc = W.make_scene(1)
