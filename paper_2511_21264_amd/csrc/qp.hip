@@ -32,9 +32,10 @@ namespace {
 
 __device__ __forceinline__ float clipf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
 
-// Wave-wide scans without an LDS trip: DPP shifts within 16-lane rows (lanes
-// whose source lies outside the row read 0), then the row totals from
-// v_readlane.  Every lane of the wave is active wherever these run.
+// Wave-wide shifts and scans without an LDS trip: DPP shifts within 16-lane
+// rows (lanes whose source lies outside the row read 0), then the row totals
+// carried across rows (DPP row broadcasts for the prefix sum, v_readlane for
+// the suffix sum).  Every lane of the wave is active wherever these run.
 template <int S>
 __device__ __forceinline__ float shr_row(float v)
 {
