@@ -24,6 +24,9 @@ METRIC = "rollout env-steps/s (K*H) + p50/p99 MPPI replan latency, batched vs pl
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector peak (packed), FLOP/s
 PEAK_FP32_NONPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_FP64 = 78.6e12           # MI355X FP64 (vector and MFMA), FLOP/s
+# vector instruction issue: one wave64 VALU instruction per SIMD every 4 cycles
+# (16 lanes a cycle), 256 CU x 4 SIMD x 2.4 GHz / 4
+PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4
 
 
 def cpu_baseline(sc, pp, threads, min_s=10.0, max_plans=5):
@@ -537,6 +540,19 @@ def counter_flops_per_launch(mapping, K, H):
     return None if v is None else 64.0 * v
 
 
+def counter_valu_insts_per_launch(mapping, K, H):
+    """Wave-level VALU instructions per rollout launch (SQ_INSTS_VALU in the
+    committed summary), under the same conditions as traffic_per_launch."""
+    path = os.path.join(ROOT, "profiles", "rollout_traffic_c2.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("sources_sha256") != sources_hash() or rec.get("mapping") != mapping or \
+            rec.get("K") != K or rec.get("H") != H:
+        return None
+    return rec.get("valu_insts_per_dispatch")
+
+
 def sources_hash():
     import hashlib
     d = os.path.join(ROOT, "paper_2511_21264_amd", "csrc")
@@ -835,6 +851,7 @@ def main():
     avg_launch_s = float(np.mean(roll_ms)) * 1e-3
     achieved = float(np.mean(flops)) / avg_launch_s
     cf_launch = counter_flops_per_launch(used, K, H)
+    vi_launch = counter_valu_insts_per_launch(used, K, H)
     out = {
         "metric": METRIC,
         "value": env_steps / elapsed,
@@ -871,6 +888,12 @@ def main():
             "counter_frac": None if cf_launch is None else cf_launch / avg_launch_s / PEAK_FP32,
             "avg_launch_ms": avg_launch_s * 1e3,
             "flop_per_launch": float(np.mean(flops)),
+            # vector instruction issue (SQ_INSTS_VALU): what bounds this kernel in practice
+            "valu_insts_per_launch": vi_launch,
+            "valu_issue_achieved": None if vi_launch is None else vi_launch / avg_launch_s / 1e9,
+            "valu_issue_peak": PEAK_VALU_ISSUE / 1e9,
+            "valu_issue_unit": "G wave64 VALU instructions/s",
+            "valu_issue_frac": None if vi_launch is None else vi_launch / avg_launch_s / PEAK_VALU_ISSUE,
         },
         "stats": {"ess": st["ess"], "c_min": st["c_min"], "contacts_per_substep":
                   st["contacts"] / (M * K * H * int(sc["n_sub"]))},
