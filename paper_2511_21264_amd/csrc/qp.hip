@@ -154,8 +154,9 @@ __device__ __forceinline__ void apply_At2(const float yI[2], const float y1[2], 
 }  // namespace
 
 // NH horizon steps per lane (1: H <= 64, 2: H <= 128); waves 0 .. 4 NH - 1
-// hold the 16-row blocks of P
-template <int NH>
+// hold the 16-row blocks of P.  FULL: H = 64 NH, so every lane holds a step
+// and the masks of absent steps fold away.
+template <int NH, bool FULL>
 __global__ void __launch_bounds__(14 * 64) project_kernel(ProjectArgs a)
 {
     constexpr int QS = 64 * NH + 4;  // LDS row stride of the right-hand sides and results (floats)
@@ -167,7 +168,7 @@ __global__ void __launch_bounds__(14 * 64) project_kernel(ProjectArgs a)
     const int d = threadIdx.x >> 6, k = threadIdx.x & 63;
     bool act[NH];
 #pragma unroll
-    for (int h = 0; h < NH; ++h) act[h] = k + 64 * h < H;
+    for (int h = 0; h < NH; ++h) act[h] = FULL || k + 64 * h < H;  // FULL: H = 64 NH, every lane holds a step
     if (d < 2) {
 #pragma unroll
         for (int h = 0; h < NH; ++h) R[14 + d][k + 64 * h] = 0.f;
@@ -294,10 +295,17 @@ __global__ void __launch_bounds__(14 * 64) project_kernel(ProjectArgs a)
 
 void launch_project(const ProjectArgs &a, hipStream_t s)
 {
-    if (a.H <= 64)
-        hipLaunchKernelGGL(project_kernel<1>, dim3(a.K), dim3(14 * 64), 0, s, a);
-    else
-        hipLaunchKernelGGL(project_kernel<2>, dim3(a.K), dim3(14 * 64), 0, s, a);
+    if (a.H <= 64) {
+        if (a.H == 64)
+            hipLaunchKernelGGL((project_kernel<1, true>), dim3(a.K), dim3(14 * 64), 0, s, a);
+        else
+            hipLaunchKernelGGL((project_kernel<1, false>), dim3(a.K), dim3(14 * 64), 0, s, a);
+    } else {
+        if (a.H == 128)
+            hipLaunchKernelGGL((project_kernel<2, true>), dim3(a.K), dim3(14 * 64), 0, s, a);
+        else
+            hipLaunchKernelGGL((project_kernel<2, false>), dim3(a.K), dim3(14 * 64), 0, s, a);
+    }
 }
 
 }  // namespace mppi
