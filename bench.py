@@ -572,6 +572,85 @@ PROFILE_ARGS_NEXT = ("--steps 1 --warmup 0 --no-cpu-baseline --packed-steps 0 --
                      "--replans 0 --no-episodes")
 
 
+# SQ counters of the rollout kernel, two passes of at most eight
+STALL_PASS1 = ("SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_ACTIVE_INST_VALU "
+               "SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_SCA")
+STALL_PASS2 = ("SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_SMEM SQ_WAIT_INST_LDS SQ_INSTS_BRANCH SQ_INSTS_VMEM "
+               "SQ_WAVES")
+
+
+def summarize_stalls(base, meta):
+    """Where the rollout kernel's wave cycles go (SQ counters of the two
+    stall passes) and its vector issue rate, against the launch time of the
+    kernel trace taken with the same arguments."""
+    import sqlite3
+    import glob
+    v = {}
+    for sub in ("stall1", "stall2"):
+        g = glob.glob(os.path.join(base, sub, "**", "*results.db"), recursive=True)
+        if not g:
+            return
+        c = sqlite3.connect(g[0])
+        for k, n, val, cnt in c.execute("select kernel_name, counter_name, avg(value), count(*) from counters_collection "
+                                        "group by kernel_name, counter_name"):
+            if "rollout_split" in k:
+                v[n] = (val, cnt)
+    g = glob.glob(os.path.join(base, "trace", "**", "*results.db"), recursive=True)
+    if not g or "SQ_INSTS_VALU" not in v or "SQ_WAVE_CYCLES" not in v:
+        return
+    c = sqlite3.connect(g[0])
+    avg_us = [a for n, a in c.execute("select name, average from top_kernels") if "rollout_split" in n][0]
+    launch_s = avg_us * 1e-6
+    waves = v["SQ_WAVES"][0]
+    busy = v["SQ_BUSY_CYCLES"][0] / 32.0  # per shader engine: 8 XCDs x 4
+    clk = busy / launch_s
+    wc = v["SQ_WAVE_CYCLES"][0] * 4  # quad-cycles
+
+    def share(n):
+        return v[n][0] * 4 / wc
+    valu = v["SQ_INSTS_VALU"][0]
+    simd_cycles = valu * 4 / 1024
+    md = ["# rollout_split_kernel<4>, K=1024, H=64 obstacle workload: where the wave cycles go (SQ counters)", "",
+          "Commands (run from the repository root, TMPDIR=/tmp; two passes, at most eight SQ counters each):", ""]
+    md += [f"    {c}" for c in meta["stall_commands"]]
+    md += ["", f"Kernel sources: sha256 {sources_hash()[:16]} (the csrc tree as `bench.sources_hash` reads it). "
+               f"Averages over {v['SQ_WAVES'][1]} dispatches;",
+           f"launch time {avg_us / 1e3:.3f} ms from the kernel trace in `rollout_split_c2.md` (same sources, same "
+           "arguments).", "",
+           "| counter (per dispatch) | value | reading |", "|---|---|---|",
+           f"| SQ_WAVES | {waves:.0f} | two waves per sample |",
+           f"| SQ_BUSY_CYCLES | {v['SQ_BUSY_CYCLES'][0]:.4g} | summed over 32 shader engines: {busy / 1e6:.2f} M cycles "
+           f"each, so the clock ran at {clk / 1e9:.2f} GHz over the {avg_us / 1e3:.3f} ms launch |",
+           f"| SQ_WAVE_CYCLES | {v['SQ_WAVE_CYCLES'][0]:.4g} quad-cycles | {wc / waves / 1e6:.2f} M cycles per wave, "
+           f"{wc / waves / busy:.0%} of the launch |",
+           f"| SQ_ACTIVE_INST_ANY | {v['SQ_ACTIVE_INST_ANY'][0]:.4g} | {share('SQ_ACTIVE_INST_ANY'):.1%} of wave cycles "
+           "working on an instruction |",
+           f"| SQ_ACTIVE_INST_VALU | {v['SQ_ACTIVE_INST_VALU'][0]:.4g} | {share('SQ_ACTIVE_INST_VALU'):.1%} (one "
+           "quad-cycle per VALU instruction) |",
+           f"| SQ_ACTIVE_INST_SCA | {v['SQ_ACTIVE_INST_SCA'][0]:.4g} | {share('SQ_ACTIVE_INST_SCA'):.1%} scalar ALU and "
+           "scalar memory |",
+           f"| SQ_ACTIVE_INST_LDS | {v['SQ_ACTIVE_INST_LDS'][0]:.4g} | {share('SQ_ACTIVE_INST_LDS'):.1%} |",
+           f"| SQ_WAIT_ANY | {v['SQ_WAIT_ANY'][0]:.4g} | {share('SQ_WAIT_ANY'):.1%} of wave cycles waiting "
+           "(dependencies, barriers, memory) |",
+           f"| SQ_WAIT_INST_ANY | {v['SQ_WAIT_INST_ANY'][0]:.4g} | {share('SQ_WAIT_INST_ANY'):.1%} waiting for issue |",
+           f"| SQ_INSTS_VALU | {valu / 1e6:.1f} M | wave64 vector instructions |",
+           f"| SQ_INSTS_SALU | {v['SQ_INSTS_SALU'][0] / 1e6:.1f} M | |",
+           f"| SQ_INSTS_BRANCH | {v['SQ_INSTS_BRANCH'][0] / 1e6:.1f} M | |",
+           f"| SQ_INSTS_LDS | {v['SQ_INSTS_LDS'][0] / 1e6:.1f} M | |",
+           f"| SQ_INSTS_SMEM | {v['SQ_INSTS_SMEM'][0] / 1e6:.2f} M | scalar loads of the scene model |",
+           f"| SQ_INSTS_VMEM | {v['SQ_INSTS_VMEM'][0] / 1e6:.2f} M | |",
+           f"| SQ_WAIT_INST_LDS | {v['SQ_WAIT_INST_LDS'][0]:.4g} | |", "",
+           f"Vector issue bound: {valu / 1e6:.0f} M wave64 VALU instructions at one per SIMD every 4 cycles occupy "
+           f"each of the 1024 SIMDs for {simd_cycles / 1e6:.2f} M cycles = {simd_cycles / clk * 1e3:.2f} ms at the "
+           f"measured {clk / 1e9:.2f} GHz, {simd_cycles / clk / launch_s:.0%} of the launch; against the 2.4 GHz issue "
+           f"peak ({PEAK_VALU_ISSUE / 1e9:.1f} G wave instructions/s) the launch reaches {valu / launch_s / 1e9:.0f} G/s "
+           f"= {valu / launch_s / PEAK_VALU_ISSUE:.0%}. The vector units are mostly busy: the gap to the FP32 peak is in "
+           "what the instructions do (moves, selects, DPP broadcasts, integer and compare work, lanes idle under a "
+           "mask or repeating a team's value), not in idle issue slots."]
+    open(os.path.join(ROOT, "profiles", "rollout_stalls_c2.md"), "w").write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def profile_meta():
     b = f"python3 bench.py {PROFILE_ARGS_MAIN}"
     bn = f"python3 bench.py {PROFILE_ARGS_NEXT}"
@@ -590,6 +669,11 @@ def profile_meta():
             "--calib-copy-mb 256",
             "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/cwrite -o run -- python3 bench.py "
             "--calib-copy-mb 256",
+            "python3 bench.py --summarize-profiles gpurun_out/prof",
+        ],
+        "stall_commands": [
+            f"timeout -s KILL 90 rocprofv3 --pmc {STALL_PASS1} -d gpurun_out/prof/stall1 -o run -- {b}",
+            f"timeout -s KILL 90 rocprofv3 --pmc {STALL_PASS2} -d gpurun_out/prof/stall2 -o run -- {b}",
             "python3 bench.py --summarize-profiles gpurun_out/prof",
         ],
         "next_commands": [
@@ -687,6 +771,7 @@ def summarize_profiles(base):
 
     meta = profile_meta()
     summarize_next(base, meta)
+    summarize_stalls(base, meta)
     lines = []
     tr = db("trace")
     if tr:
