@@ -138,6 +138,7 @@ def lib():
             "oracle_substep": (None, [_S, _D, _D, _D, C.POINTER(C.c_int)]),
             "oracle_tangents": (None, [_D, _D, _D]),
             "oracle_lcp": (C.c_int, [_S, _D, _D, _D, _D, _D, _D]),
+            "oracle_point_jac": (None, [_S, _D, C.c_int, _D, _D]),
             "oracle_rollout": (C.c_double, [_S, _D, _D, C.c_int, C.c_void_p, C.c_void_p]),
             "oracle_stage_terms": (None, [_S, _D, _D]),
             "oracle_cost_dist": (None, [_S, _D, _D]),
@@ -290,6 +291,13 @@ class Oracle:
         t1, t2 = np.zeros(3), np.zeros(3)
         lib().oracle_tangents(_d(n), t1, t2)
         return t1, t2
+
+    def point_jac(self, x, gid, p):
+        """3 x 20 Jacobian of a point p rigidly attached to geom gid (global
+        geom ids: 0 ball, 1 table, 2 + 7 arm + g arm geoms, 16 + b boxes)."""
+        J = np.zeros(60)
+        self.L.oracle_point_jac(self.ps, _d(x), int(gid), _d(p), J)
+        return J.reshape(3, 20)
 
     def lcp(self, x, u):
         A, b, f, vf = np.zeros(64 * 64), np.zeros(64), np.zeros(64), np.zeros(20)

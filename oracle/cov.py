@@ -94,27 +94,25 @@ def diagonal_sigma(sigma, H):
     return np.diag(s * s)
 
 
-def plan(o, x0, nominal, K, H, beta, Sigma0, M, seed, eta, eps, u_max, n_elite=None, project=None,
-         nu_rounding=np.float32):
+def plan(o, x0, nominal, K, H, beta, Sigma0, M, seed, eta, eps, u_max, n_elite=None, project=None):
     """Alg. 1 with the full covariance: per iteration m, draw z (the Philox
     normals of iteration m), u_j = clip(nu + L z_j), optionally smooth them
     (`project(U[K,H,14]) -> U`), roll them out, weight them, update nu then
-    Sigma.  nu is rounded through `nu_rounding` before sampling, as a
-    single-precision mean is stored between iterations.  Returns nu[H,14],
-    Sigma, the last costs, weights and samples."""
+    Sigma (nu and Sigma stay FP64 between iterations, Eqs. mean_update and
+    cov_update).  Returns nu[H,14], Sigma, the last costs, weights and
+    samples."""
     nu = np.asarray(nominal, dtype=np.float64).reshape(-1).copy()
     S = np.asarray(Sigma0, dtype=np.float64).copy()
     x0 = np.asarray(x0, dtype=np.float64)
     c = w = U = None
     for m in range(M):
         z = o.noise(seed, K, H, m)
-        nus = nu.astype(nu_rounding).astype(np.float64) if nu_rounding else nu
-        U = sample(nus, factor(S), z, u_max).reshape(K, H, 14)
+        U = sample(nu, factor(S), z, u_max).reshape(K, H, 14)
         if project is not None:
             U = project(U)
         c = o.rollout_batch(x0, U)
         c = c[0] if isinstance(c, tuple) else c
         w = weights(c, beta, n_elite)
-        nu = mean_update(U, w, nus, eta)
+        nu = mean_update(U, w, nu, eta)
         S = cov_update(U, w, nu, S, eta, eps)
     return dict(nu=nu.reshape(H, 14), Sigma=S, costs=c, weights=w, U=U)

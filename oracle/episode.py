@@ -102,12 +102,11 @@ def best_sequence_qp(o, x, nominal, K, H, lam, sigma, M, seed, eta, n_elite, pro
     sig = np.broadcast_to(np.asarray(sigma, dtype=np.float64).reshape(-1, 14), (H, 14))
     U = c = None
     for m in range(M):
-        nus = nu.astype(np.float32).astype(np.float64)
-        U = project(nus[None] + sig.astype(np.float32).astype(np.float64)[None] * o.noise(seed, K, H, m))
+        U = project(nu[None] + sig[None] * o.noise(seed, K, H, m))
         c = o.rollout_batch(x, U)
         c = c[0] if isinstance(c, tuple) else c
         w = cov.weights(c, lam, n_elite)
-        nu = cov.mean_update(U, w, nus, eta).reshape(H, 14)
+        nu = cov.mean_update(U, w, nu, eta).reshape(H, 14)
     c = np.asarray(c, dtype=np.float64)
     fin = np.isfinite(c)
     best = int(np.flatnonzero(fin)[np.argmin(c[fin])]) if fin.any() else -1

@@ -290,3 +290,16 @@ int oracle_lcp(const OScene *s, const double *x, const double *u, double *Aout, 
         }
     return m;
 }
+
+/* 3 x 20 Jacobian (row-major) of a point p rigidly attached to geom gid at
+ * state x: its world velocity is J qd (arm joints, ball v, ball w). */
+void oracle_point_jac(const OScene *s, const double *x, int gid, const double *p, double *Jout)
+{
+    OArmKin kin[2];
+    or_fk(s, 0, x, &kin[0]);
+    or_fk(s, 1, x + 7, &kin[1]);
+    double J[3][OR_NDOF];
+    memset(J, 0, sizeof(J));
+    point_jac(s, kin, x + 42, gid, p, J, 1.0);
+    memcpy(Jout, J, sizeof(J));
+}

@@ -176,7 +176,7 @@ def test_plan_with_diagonal_sigma_and_eta_one_matches_the_c_oracle_plan_mean(eta
     x0 = W.initial_state(sc)
     sig = np.asarray(pp["sigma"], dtype=np.float64)
     r = cov.plan(o, x0, np.zeros((H, 14)), K, H, pp["lam"], cov.diagonal_sigma(sig, H), 1, 77, eta, 0.0,
-                 float(sc["u_max"]), nu_rounding=None)
+                 float(sc["u_max"]))
     ref = o.plan(x0, np.zeros((H, 14)), K, H, pp["lam"], sig, 1, 77, eta=eta, nthreads=4)
     np.testing.assert_allclose(r["costs"], ref["costs"], rtol=1e-12, atol=0)
     np.testing.assert_allclose(r["nu"], ref["nu"], rtol=0, atol=1e-13)
