@@ -24,7 +24,10 @@
  *     enqueue on it; with host pointers they also synchronize it before
  *     returning.  Device-pointer calls return once enqueued, except that
  *     mppi_plan synchronizes when `stats` is non-NULL (to fill it) or when
- *     MPPI_SYNC is set.
+ *     MPPI_SYNC is set.  Calls on one context share its scratch buffers and
+ *     run in call order whatever streams they name: a call on a stream other
+ *     than the previous call's first makes its stream wait for the work the
+ *     previous call enqueued (an event, no host synchronisation).
  *   * State layout (MPPI_NX = 55 floats): q[14], qd[14], q_des[14] (PD
  *     target), ball p[3], ball quaternion (w, x, y, z)[4], ball v[3], ball
  *     angular velocity (world frame)[3].  Joint order: arm 1 joints 1..7,
@@ -69,8 +72,11 @@ extern "C" {
 #define MPPI_MAP_SPLIT 2048u    /* rollout mapping: two waves per sample, dynamics and contact sweep /
                                    cost concurrently (shortest steps at small K); results equal
                                    MPPI_MAP_WAVE's bit for bit */
-                                /* none of the three: the mapping mppi_autotune measured for K's size
-                                   class on this context, else chosen from K */
+                                /* none of the four: the mapping mppi_autotune measured for K's size
+                                   class on this context, else chosen from K.  In packed batches and
+                                   served requests each request keeps the family of the mapping it
+                                   would get alone (lane, or team/wave/split, which agree bit for bit),
+                                   so its results do not depend on what it is batched with */
 #define MPPI_FP32_WEIGHTS 512u  /* mppi_plan, mppi_update: the weights of Eq. s_formula, their sums and the
                                    weighted mean of Eq. mean_update in FP32 instead of FP64 (precision
                                    study; the default keeps them in FP64) */
@@ -510,7 +516,8 @@ int mppi_server_query(mppi_server *srv, mppi_server_info *info);
  * (ceil(log2 K)) in the context.  Later calls on the context that pin no
  * mapping use the recorded one for that class.  *mapping (nullable)
  * receives the MPPI_MAP_* flag chosen, ms[4] (nullable) the times of the
- * lane, team, wave and split launches.  Synchronous; uses a private stream. */
+ * lane, team, wave and split launches.  Synchronous; uses a private stream
+ * that first waits for the context's previous call (whose scratch it reuses). */
 int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *sigma, int K, int H,
                   int *mapping, float *ms);
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,7 +42,12 @@ int ensure(mppi_ctx *c, int slot, size_t bytes, void **out)
     Buf &b = c->buf[slot];
     if (bytes == 0) bytes = 16;
     if (b.cap < bytes) {
-        if (b.p) (void)hipFree(b.p);
+        // cached graphs bake in the old address: drop them with the buffer
+        if (b.p) {
+            (void)hipDeviceSynchronize();
+            drop_graphs(c);
+            (void)hipFree(b.p);
+        }
         b.p = nullptr;
         b.cap = 0;
         size_t want = bytes + bytes / 4;
@@ -244,11 +250,31 @@ int resolve_mapping(const mppi_ctx *c, long K, unsigned flags)
     return pick_mapping(Kc, MAP_AUTO);
 }
 
+int family_launch_mapping(const mppi_ctx *c, int family, long total_k, unsigned flags)
+{
+    const int pinned = mapping_of(flags);
+    if (pinned != MAP_AUTO) return pinned;
+    if (family == MAP_LANE) return MAP_LANE;
+    const int m = resolve_mapping(c, total_k, flags);
+    return m == MAP_LANE ? MAP_TEAM : m;  // the team family's form for the most samples
+}
+
 int set_device(mppi_ctx *c)
 {
     HIPCHK(hipSetDevice(c->device));
     return MPPI_OK;
 }
+
+void drop_graphs(mppi_ctx *c)
+{
+    for (auto &g : c->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
+std::atomic<uint64_t> g_scene_gen{0};
 
 bool all_finite(const float *p, size_t n)
 {
@@ -273,7 +299,9 @@ int mppi_ctx_create(int device, mppi_ctx **out)
     if (device >= n) return fail(MPPI_E_INVAL, "device %d not present (%d devices)", device, n);
     mppi_ctx *c = new mppi_ctx();
     c->device = device;
-    if (hipSetDevice(device) != hipSuccess || hipMalloc((void **)&c->st, sizeof(PlanStats)) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || hipMalloc((void **)&c->st, sizeof(PlanStats)) != hipSuccess ||
+        hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess) {
+        if (c->st) (void)hipFree(c->st);
         delete c;
         return fail(MPPI_E_NOMEM, "context allocation failed");
     }
@@ -290,11 +318,9 @@ void mppi_ctx_destroy(mppi_ctx *c)
         if (b.p) (void)hipFree(b.p);
     if (c->st) (void)hipFree(c->st);
     for (auto e : c->ev) (void)hipEventDestroy(e);
+    if (c->order_ev) (void)hipEventDestroy(c->order_ev);
     if (c->host_tab) (void)hipHostFree(c->host_tab);
-    for (auto &g : c->graphs) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
-    }
+    drop_graphs(c);
     if (c->capture) (void)hipStreamDestroy(c->capture);
     delete c;
 }
@@ -305,6 +331,7 @@ int mppi_scene_create(mppi_ctx *ctx, const mppi_scene_desc *desc, mppi_scene **o
     *out = nullptr;
     mppi_scene *s = new mppi_scene();
     s->ctx = ctx;
+    s->gen = ++g_scene_gen;
     s->desc = *desc;
     int rc = build_model(desc, s->host);
     if (rc) {
@@ -329,6 +356,17 @@ void mppi_scene_destroy(mppi_scene *s)
     if (!s) return;
     (void)hipSetDevice(s->ctx->device);
     (void)hipDeviceSynchronize();
+    // graphs of this scene's plans read its model: evict them
+    auto &gs = s->ctx->graphs;
+    for (size_t i = 0; i < gs.size();) {
+        if (gs[i].key[0] == (uintptr_t)s->gen) {
+            (void)hipGraphExecDestroy(gs[i].exec);
+            (void)hipGraphDestroy(gs[i].graph);
+            gs.erase(gs.begin() + i);
+        } else {
+            ++i;
+        }
+    }
     if (s->dev) (void)hipFree(s->dev);
     delete s;
 }
@@ -466,6 +504,8 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const void *dx0, *dsig, *dnom;
     if ((rc = stage_in(ctx, S_X0, x0, NX * sizeof(float), dev, s, &dx0))) return rc;
     if ((rc = stage_in(ctx, S_SIGMA, sigma, nsig * sizeof(float), dev, s, &dsig))) return rc;
@@ -607,7 +647,9 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
         uintptr_t lb, eb;
         std::memcpy(&lb, &lam_bits, sizeof lb);
         std::memcpy(&eb, &eta_bits, sizeof eb);
-        const std::vector<uintptr_t> key = {(uintptr_t)scene->dev, (uintptr_t)K, (uintptr_t)H, (uintptr_t)M, lb, eb,
+        // key[0]: the scene's generation (its host scalars, such as u_max, are
+        // baked into the update nodes; a later scene may reuse its address)
+        const std::vector<uintptr_t> key = {(uintptr_t)scene->gen, (uintptr_t)scene->dev, (uintptr_t)K, (uintptr_t)H, (uintptr_t)M, lb, eb,
                                             (uintptr_t)opts->seed, (uintptr_t)n_elite, (uintptr_t)sps,
                                             (uintptr_t)mapping, (uintptr_t)f32, (uintptr_t)scene->host.n_cmax,
                                             (uintptr_t)dx0, (uintptr_t)dsig, (uintptr_t)dnom, (uintptr_t)dnu,
@@ -779,6 +821,8 @@ int mppi_cov_update(mppi_ctx *ctx, const float *U, const double *w, const double
     }
     if ((rc = set_device(ctx))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const void *dU, *dw, *dnu, *dSin;
     if ((rc = stage_in(ctx, S_IN0, U, (size_t)K * n * sizeof(float), dev, s, &dU)) ||
         (rc = stage_in(ctx, S_IN1, w, (size_t)K * sizeof(double), dev, s, &dw)) ||
@@ -805,6 +849,8 @@ int mppi_cholesky(mppi_ctx *ctx, const double *Sigma, double *L, int n, unsigned
     const size_t nn = (size_t)n * n;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const void *dS;
     if ((rc = stage_in(ctx, S_COVS, Sigma, nn * sizeof(double), dev, s, &dS))) return rc;
     void *dA, *dLi, *dL;
@@ -838,6 +884,8 @@ int mppi_sample_full(mppi_ctx *ctx, const float *nu, const double *L, uint64_t s
     const size_t nn = (size_t)n * n;
     if ((rc = set_device(ctx))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const void *dnu, *dL;
     if ((rc = stage_in(ctx, S_IN0, nu, (size_t)n * sizeof(float), dev, s, &dnu)) ||
         (rc = stage_in(ctx, S_COVL, L, nn * sizeof(double), dev, s, &dL)))
@@ -872,6 +920,8 @@ int mppi_project(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0
     if (!dev && (!all_finite(X0, nx0) || !all_finite(U_in, nu_n))) return fail(MPPI_E_INVAL, "non-finite input");
     if ((rc = set_device(ctx))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const float *dP;
     int S;
     if ((rc = qp_matrix(ctx, H, qp->rho, s, &dP, &S))) return rc;
@@ -898,7 +948,7 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
     if (!ctx || !reqs || n < 1) return fail(MPPI_E_INVAL, "NULL context/requests or n < 1");
     const bool dev = flags & MPPI_DEVICE_PTRS, timing = flags & MPPI_TIME_KERNELS;
     long total_k = 0;
-    int maxM = 0, ncmax = 0;
+    int maxM = 0;
     for (int i = 0; i < n; ++i) {
         mppi_request &r = reqs[i];
         if (!r.scene || !r.x0 || !r.nominal_U || !r.sigma || !r.U_new) return fail(MPPI_E_INVAL, "request %d: NULL argument", i);
@@ -916,18 +966,31 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
         r.status = MPPI_OK;
         total_k += r.K;
         maxM = std::max(maxM, r.opts.M);
-        ncmax = std::max(ncmax, r.scene->host.n_cmax);
     }
     if (total_k > MPPI_MAX_K) return fail(MPPI_E_INVAL, "batch has more than %d samples", MPPI_MAX_K);
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const int map = resolve_mapping(ctx, total_k, flags);
-    const int per = samples_per_block(map);
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     // requests in order of decreasing M: the ones still iterating form a prefix
     std::vector<int> ord(n);
     for (int i = 0; i < n; ++i) ord[i] = i;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return reqs[a].opts.M > reqs[b].opts.M; });
+    // One rollout launch per group of requests that share the family of the
+    // mapping they would run alone and the contact-list instantiation (n_cmax
+    // up to 4, or up to 8): each request's results then equal its plan alone
+    // bit for bit, whatever it is batched with.
+    std::vector<int> grp(n);
+    long grp_k[4] = {0, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        const mppi_request &r = reqs[ord[i]];
+        const int fam = request_family(ctx, r.K, flags) == MAP_LANE ? 0 : 1;
+        grp[i] = 2 * fam + (r.scene->host.n_cmax > 4 ? 1 : 0);
+        grp_k[grp[i]] += r.K;
+    }
+    int gmap[4];
+    for (int g = 0; g < 4; ++g) gmap[g] = family_launch_mapping(ctx, g < 2 ? MAP_LANE : MAP_TEAM, grp_k[g], flags);
     // offsets of every request's slices in the packed buffers
     std::vector<size_t> o_k(n), o_h(n), o_sig(n), o_x0(n);
     size_t nk = 0, nh = 0, nsig_tot = 0;
@@ -941,15 +1004,25 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
         nsig_tot += (r.opts.flags & MPPI_SIGMA_PER_STEP) ? (size_t)r.H * NU : NU;
         o_x0[i] = (size_t)i * NX;
     }
-    // block tables
-    std::vector<int> blk, ublk, blk_prefix(n + 1, 0), ublk_prefix(n + 1, 0);
+    // block tables: the rollout blocks of each group (in request order, so the
+    // requests still iterating give a prefix of every group's table), then
+    // the update blocks
+    std::vector<int> gblk[4], ublk, ublk_prefix(n + 1, 0);
+    std::vector<std::vector<int>> blk_prefix(4, std::vector<int>(n + 1, 0));
     for (int i = 0; i < n; ++i) {
         const mppi_request &r = reqs[ord[i]];
+        const int g = grp[i], per = samples_per_block(gmap[g]);
         const int nb = (r.K + per - 1) / per;
-        for (int b = 0; b < nb; ++b) { blk.push_back(i); blk.push_back(b); }
+        for (int b = 0; b < nb; ++b) { gblk[g].push_back(i); gblk[g].push_back(b); }
         for (int k = 0; k < r.H; ++k) { ublk.push_back(i); ublk.push_back(k); }
-        blk_prefix[i + 1] = (int)blk.size() / 2;
+        for (int q = 0; q < 4; ++q) blk_prefix[q][i + 1] = (int)gblk[q].size() / 2;
         ublk_prefix[i + 1] = (int)ublk.size() / 2;
+    }
+    std::vector<int> blk;
+    size_t goff[4];
+    for (int g = 0; g < 4; ++g) {
+        goff[g] = blk.size();
+        blk.insert(blk.end(), gblk[g].begin(), gblk[g].end());
     }
     // device buffers
     void *d_nu, *d_cost, *d_w, *d_cnt, *d_dist, *d_st, *d_in;
@@ -1039,7 +1112,9 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
         while (act < n && reqs[ord[act]].opts.M > m) ++act;
         // stats entries carry the iteration index for the per-iteration minima
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], s));
-        launch_rollout_batch(d_rt, d_blk, blk_prefix[act], ncmax, m, map, s);
+        for (int g = 0; g < 4; ++g)
+            if (blk_prefix[g][act] > 0)
+                launch_rollout_batch(d_rt, d_blk + goff[g], blk_prefix[g][act], (g & 1) ? 8 : 4, m, gmap[g], s);
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], s));
         launch_stats_batch(d_sst, act, m, s);
         launch_update_batch(d_ut, d_ublk, ublk_prefix[act], m, s);
@@ -1102,6 +1177,8 @@ int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const size_t nx0 = x0_shared ? NX : (size_t)n * NX;
     if (!dev && (!all_finite(X0, nx0) || !all_finite(U, (size_t)n * H * NU))) return fail(MPPI_E_INVAL, "non-finite input");
     const void *dx0, *dU;
@@ -1146,6 +1223,8 @@ int mppi_sample(mppi_ctx *ctx, const mppi_scene *scene, const float *nu, const f
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const size_t nsig = sps ? (size_t)H * NU : NU;
     const void *dnu, *dsig;
     if ((rc = stage_in(ctx, S_IN0, nu, (size_t)H * NU * sizeof(float), dev, s, &dnu))) return rc;
@@ -1176,6 +1255,8 @@ int mppi_update(mppi_ctx *ctx, const mppi_scene *scene, const float *costs, cons
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const size_t nsig = sps ? (size_t)H * NU : NU;
     const void *dc, *dnu, *dsig;
     if ((rc = stage_in(ctx, S_IN0, costs, (size_t)K * sizeof(float), dev, s, &dc))) return rc;
@@ -1229,11 +1310,18 @@ int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const
     HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto done = [&](int code) {
+        // every launch below has completed (each is waited for), and with it
+        // the context's earlier work that the stream waited for first
+        (void)hipStreamSynchronize(s);
+        ctx->has_last = false;
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         (void)hipStreamDestroy(s);
         return code;
     };
+    // the scratch buffers below may still serve the context's previous call
+    if (ctx->has_last && hipStreamWaitEvent(s, ctx->order_ev, 0) != hipSuccess)
+        return done(fail(MPPI_E_DEVICE, "ordering after the previous call failed"));
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return done(fail(MPPI_E_DEVICE, "event creation failed"));
     const void *dx0, *dsig;
@@ -1294,6 +1382,8 @@ int mppi_broadphase(mppi_ctx *ctx, const mppi_scene *scene, const float *lo, con
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const int ng = G_BOX + scene->host.n_box, np = scene->host.n_pairs;
     const size_t nb = (size_t)n * ng * 3 * sizeof(float);
     const void *dlo, *dhi;
@@ -1318,6 +1408,8 @@ int mppi_narrowphase(mppi_ctx *ctx, const mppi_scene *scene, const float *X, int
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
     const int np = scene->host.n_pairs, ng = G_BOX + scene->host.n_box;
     const void *dX;
     if ((rc = stage_in(ctx, S_IN0, X, (size_t)n * NX * sizeof(float), dev, s, &dX))) return rc;

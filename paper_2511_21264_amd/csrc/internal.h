@@ -36,6 +36,20 @@ int mapping_of(unsigned flags);
 // the mapping of a launch over K samples: pinned by the flags, else the
 // context's measured choice for K's class, else the built-in rule
 int resolve_mapping(const mppi_ctx *c, long K, unsigned flags);
+// Mappings whose rollouts agree bit for bit form one family: the 16-lane
+// team, the one-wave and the two-wave forms evaluate every value by the
+// same operations; the one-lane form rounds differently.  A request's
+// results are those of its own mapping's family, whatever it is batched with.
+inline int map_family(int map) { return map == mppi::MAP_LANE ? mppi::MAP_LANE : mppi::MAP_TEAM; }
+// the family of a request of K samples planned alone with these flags
+inline int request_family(const mppi_ctx *c, long K, unsigned flags)
+{
+    return map_family(resolve_mapping(c, K, flags));
+}
+// the mapping of a packed launch of total_k samples whose requests all belong
+// to `family` (a pinned mapping wins; else the measured or built-in choice
+// for total_k, kept inside the family)
+int family_launch_mapping(const mppi_ctx *c, int family, long total_k, unsigned flags);
 int k_class(long K);
 bool all_finite(const float *p, size_t n);
 
@@ -51,6 +65,13 @@ struct PlanGraph {
 
 struct mppi_ctx {
     int device = 0;
+    // Calls on one context share its scratch buffers.  Each call records
+    // order_ev on its stream when it has enqueued its work; a call on another
+    // stream than the previous one first waits for that event, so calls on one
+    // context run in call order whatever streams they name.
+    hipEvent_t order_ev = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
     // measured rollout mapping per sample-count class (MPPI_MAP_* of the
     // fastest launch); index: ceil(log2 K)), 0 = not tuned
     int tuned_map[21] = {0};
@@ -71,6 +92,7 @@ struct mppi_ctx {
 
 struct mppi_scene {
     mppi_ctx *ctx = nullptr;
+    uint64_t gen = 0;  // unique per scene created in this process (keys of cached graphs)
     mppi_scene_desc desc;
     mppi::DevModel host;
     mppi::DevModel *dev = nullptr;
@@ -78,6 +100,37 @@ struct mppi_scene {
 
 namespace mppi_host {
 int set_device(mppi_ctx *c);
+
+// Orders a call on stream s after the context's previous call (see
+// mppi_ctx::order_ev): begin() before the first enqueue; the destructor
+// records the call's end on s.
+class CtxStream {
+public:
+    CtxStream(mppi_ctx *c, hipStream_t s) : c_(c), s_(s) {}
+    int begin()
+    {
+        if (c_->has_last && c_->last_stream != s_) HIPCHK(hipStreamWaitEvent(s_, c_->order_ev, 0));
+        began_ = true;
+        return MPPI_OK;
+    }
+    ~CtxStream()
+    {
+        if (!began_) return;
+        if (hipEventRecord(c_->order_ev, s_) == hipSuccess) {
+            c_->last_stream = s_;
+            c_->has_last = true;
+        }
+    }
+    CtxStream(const CtxStream &) = delete;
+    CtxStream &operator=(const CtxStream &) = delete;
+
+private:
+    mppi_ctx *c_;
+    hipStream_t s_;
+    bool began_ = false;
+};
+// drops every cached graph of the context (their nodes bake in buffer addresses)
+void drop_graphs(mppi_ctx *c);
 // a plan with any of the options (qp, cov nullable) and the best sequence of
 // the final iteration in U_best (nullable), as the public entry points run it
 int plan_with(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,

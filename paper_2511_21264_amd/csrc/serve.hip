@@ -247,29 +247,45 @@ int launch_iteration(mppi_server *S, int b, const std::vector<Req *> &act, const
 {
     hipStream_t s = S->s;
     const int n = (int)act.size(), nf = (int)fin.size();
-    long total_k = 0;
-    int ncmax = 0;
-    for (Req *R : act) {
-        total_k += R->K;
-        ncmax = std::max(ncmax, R->scene->host.n_cmax);
-    }
-    const int map = resolve_mapping(S->ctx, total_k, S->o.flags);
-    const int per = samples_per_block(map);
-    std::vector<int> blk, ublk, ablk;
+    // One rollout launch per group of requests that share the family of the
+    // mapping they would run alone and the contact-list instantiation (n_cmax
+    // up to 4, or up to 8), so a request's results and its cell's advance do
+    // not depend on what else is in flight.
+    auto group_of = [&](const Req *R) {
+        const int fam = request_family(S->ctx, R->K, S->o.flags) == MAP_LANE ? 0 : 1;
+        return 2 * fam + (R->scene->host.n_cmax > 4 ? 1 : 0);
+    };
+    long grp_k[4] = {0, 0, 0, 0};
+    for (Req *R : act) grp_k[group_of(R)] += R->K;
+    int gmap[4];
+    for (int g = 0; g < 4; ++g)
+        gmap[g] = family_launch_mapping(S->ctx, g < 2 ? MAP_LANE : MAP_TEAM, grp_k[g], S->o.flags);
+    std::vector<int> gblk[4], gablk[4], ublk;
     for (int i = 0; i < n; ++i) {
+        const int g = group_of(act[i]), per = samples_per_block(gmap[g]);
         const int nb = (act[i]->K + per - 1) / per;
-        for (int q = 0; q < nb; ++q) { blk.push_back(i); blk.push_back(q); }
+        for (int q = 0; q < nb; ++q) { gblk[g].push_back(i); gblk[g].push_back(q); }
         for (int k = 0; k < act[i]->H; ++k) { ublk.push_back(i); ublk.push_back(k); }
     }
+    // the plant advance of finished requests' cells: one sample each, in the
+    // mapping family of the request (its own K decides, as when alone)
     std::vector<Req *> adv;
-    int adv_ncmax = 0;
     for (Req *R : fin)
         if (R->cell >= 0 && R->advance > 0) {
-            ablk.push_back((int)adv.size());
-            ablk.push_back(0);
+            gablk[group_of(R)].push_back((int)adv.size());
+            gablk[group_of(R)].push_back(0);
             adv.push_back(R);
-            adv_ncmax = std::max(adv_ncmax, R->scene->host.n_cmax);
         }
+    int amap[4];
+    for (int g = 0; g < 4; ++g) amap[g] = family_launch_mapping(S->ctx, g < 2 ? MAP_LANE : MAP_TEAM, 1, S->o.flags);
+    std::vector<int> blk, ablk;
+    size_t goff[4], gaoff[4];
+    for (int g = 0; g < 4; ++g) {
+        goff[g] = blk.size();
+        blk.insert(blk.end(), gblk[g].begin(), gblk[g].end());
+        gaoff[g] = ablk.size();
+        ablk.insert(ablk.end(), gablk[g].begin(), gablk[g].end());
+    }
     const int na = (int)adv.size();
     const size_t bytes = al(n * sizeof(RolloutArgs)) + al(n * sizeof(StatsArgs)) + al(n * sizeof(UpdateArgs)) +
                          al(nf * sizeof(FinishArgs)) + al(na * sizeof(RolloutArgs)) + al(blk.size() * sizeof(int)) +
@@ -343,13 +359,17 @@ int launch_iteration(mppi_server *S, int b, const std::vector<Req *> &act, const
     std::memcpy(h + o_ub, ublk.data(), ublk.size() * sizeof(int));
     std::memcpy(h + o_ab, ablk.data(), ablk.size() * sizeof(int));
     HIPCHK(hipMemcpyAsync(d, h, o, hipMemcpyHostToDevice, s));
-    launch_rollout_batch((const RolloutArgs *)(d + o_r), (const int *)(d + o_b), (int)blk.size() / 2, ncmax, -1, map,
-                         s);
+    for (int g = 0; g < 4; ++g)
+        if (!gblk[g].empty())
+            launch_rollout_batch((const RolloutArgs *)(d + o_r), (const int *)(d + o_b) + goff[g],
+                                 (int)gblk[g].size() / 2, (g & 1) ? 8 : 4, -1, gmap[g], s);
     launch_stats_batch((const StatsArgs *)(d + o_s), n, -1, s);
     launch_update_batch((const UpdateArgs *)(d + o_u), (const int *)(d + o_ub), (int)ublk.size() / 2, -1, s);
     if (nf) launch_finish_batch((const FinishArgs *)(d + o_f), nf, s);
-    if (na)
-        launch_rollout_batch((const RolloutArgs *)(d + o_a), (const int *)(d + o_ab), na, adv_ncmax, 0, map, s);
+    for (int g = 0; g < 4; ++g)
+        if (!gablk[g].empty())
+            launch_rollout_batch((const RolloutArgs *)(d + o_a), (const int *)(d + o_ab) + gaoff[g],
+                                 (int)gablk[g].size() / 2, (g & 1) ? 8 : 4, 0, amap[g], s);
     HIPCHK(hipGetLastError());
     for (Req *R : fin) {
         const size_t nH = (size_t)R->H * NU * sizeof(float);

@@ -387,9 +387,25 @@ def _batch_items(mp, ctx, n=5):
     return items
 
 
-@pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split"])
+def _big_item(mp, ctx, K=33000, H=3, M=1):
+    """A request large enough that, alone, the built-in rule runs it one
+    sample per lane, while the small requests beside it run in the team
+    family: under default flags the batch must keep each one's own family."""
+    sc = W.make_scene(4, 9)
+    pp = W.plan_params(4, K=K, H=H, M=M, seed=1009)
+    return dict(scene=mp.Scene(ctx, sc), x0=T(W.initial_state(sc)), K=K, H=H, lam=pp["lam"], sigma=T(pp["sigma"]),
+                sigma_per_step=False, M=M, seed=pp["seed"], nominal_U=T(np.zeros((H, 14))), eta=1.0, n_elite=0,
+                U_new=torch.zeros((H, 14), device=DEV), costs=torch.zeros(K, device=DEV))
+
+
+@pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split", None])
 def test_batch_equals_each_plan_alone(mp, ctx, mapping):
+    """Each request of a packed batch equals the same plan run alone, bit for
+    bit: with a pinned mapping, and under default flags (mapping None), where
+    a large request beside small ones must not change their mapping family."""
     items = _batch_items(mp, ctx)
+    if mapping is None:
+        items.append(_big_item(mp, ctx))
     sts = mp.mppi_plan_batch(ctx, items, mapping=mapping)
     torch.cuda.synchronize()
     for it, st in zip(items, sts):

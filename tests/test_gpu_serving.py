@@ -55,9 +55,16 @@ def _items(mp, ctx, shapes, base=0):
     return out
 
 
-@pytest.mark.parametrize("mapping", ["team", "lane", "wave", "split"])
+@pytest.mark.parametrize("mapping", ["team", "lane", "wave", "split", None])
 def test_served_requests_equal_plans_alone(mp, ctx, mapping):
-    items = _items(mp, ctx, [(70, 6, 3), (5, 4, 1), (130, 9, 4), (33, 3, 2), (64, 5, 6), (200, 7, 2)])
+    """Served requests equal the same plans alone bit for bit, with a pinned
+    mapping and under default flags (None), where one request is large
+    enough to run one sample per lane alone while the others run in the
+    team family."""
+    shapes = [(70, 6, 3), (5, 4, 1), (130, 9, 4), (33, 3, 2), (64, 5, 6), (200, 7, 2)]
+    if mapping is None:
+        shapes.append((33000, 3, 2))
+    items = _items(mp, ctx, shapes)
     srv = mp.Server(ctx, mapping=mapping)
     tickets = [srv.submit(it) for it in items]
     res = [srv.wait(t) for t in tickets]
