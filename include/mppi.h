@@ -188,6 +188,36 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
               double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs,
               mppi_stats *stats, void *stream);
 
+/* Bytes of the static device array that serves as mppi_plan_noalloc's
+ * working memory (one copy per GPU, held until the process ends). */
+#define MPPI_NOALLOC_SCRATCH_BYTES (8u << 20)
+
+/* mppi_plan for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc.  The
+ * same plan as mppi_plan (same kernels, bit-identical U_new, costs and
+ * stats), but its working memory -- the mean, weights, statistics record,
+ * per-sample counters, the collision-distance history and, when costs is
+ * NULL, the costs -- lives in a file-scope device array of
+ * MPPI_NOALLOC_SCRATCH_BYTES per GPU, whose address the library looks up
+ * once per device when a context is created.  It calls no hipMalloc,
+ * hipFree or other allocating routine.
+ *   Arguments as mppi_plan; every array is a device pointer (MPPI_DEVICE_PTRS
+ *   must be set); MPPI_GRAPH and MPPI_TIME_KERNELS are rejected.
+ *   Size limit: 256-byte aligned pieces of sizeof(stats record) + 56 H +
+ *   K (8 + 16 + 4 n_cost + 4) bytes must fit (n_cost = 49 + 14 boxes:
+ *   about K <= 21000 at H = 64 with 3 boxes, K <= 7400 with 16 boxes);
+ *   larger calls return MPPI_E_INVAL with the sizes in the message.
+ *   The array is shared by every call on that GPU and keeps the last call's
+ *   contents (the statistics record is cleared by a kernel at the start of
+ *   each call): calls on one context run in call order (see Streams above),
+ *   but calls from different contexts or threads that overlap on one GPU
+ *   race on it.
+ * Errors: as mppi_plan (MPPI_E_DIVERGED only when the call synchronizes,
+ * i.e. with stats or MPPI_SYNC). */
+int mppi_plan_noalloc(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                      double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs,
+                      mppi_stats *stats, void *stream);
+
 /* One request of a packed batch. */
 typedef struct mppi_request {
     const mppi_scene *scene;  /* scene of this request (same context) */

@@ -166,6 +166,8 @@ def lib():
             "mppi_scene_num_pairs": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
             "mppi_plan": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts), _P, _P,
                                     C.POINTER(Stats), _P]),
+            "mppi_plan_noalloc": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, C.c_double, _P, C.POINTER(Opts), _P,
+                                            _P, C.POINTER(Stats), _P]),
             "mppi_simulate": (C.c_int, [_P, _P, _P, C.c_int, _P, C.c_int, C.c_int, C.c_int, _P, _P, _P, C.c_uint,
                                         _P]),
             "mppi_plan_batch": (C.c_int, [_P, C.c_int, C.POINTER(Request), C.c_uint, _P]),
@@ -338,6 +340,33 @@ class Scene:
             self.close()
         except Exception:
             pass
+
+
+def mppi_plan_noalloc(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, M=1, seed=0, eta=1.0,
+                      n_elite=0, sigma_per_step=False, want_stats=True, sync=False, stream=None, mapping=None,
+                      fp32_weights=False):
+    """mppi_plan whose working memory is the library's static device array
+    (no device allocation); every array must be a torch tensor on the GPU."""
+    (px0, pnom, psig, pU, pc), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32), (sigma, np.float32),
+                                             (U_new, np.float32), (costs, np.float32)])
+    if not dev:
+        raise ValueError("mppi_plan_noalloc takes device arrays")
+    flags = DEVICE_PTRS | (SIGMA_PER_STEP if sigma_per_step else 0) | (SYNC if sync else 0) | _MAPS[mapping] | \
+        (FP32_WEIGHTS if fp32_weights else 0)
+    o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
+    st = Stats()
+    rc = lib().mppi_plan_noalloc(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), pU, pc,
+                                 C.byref(st) if want_stats else None, _stream(dev, stream))
+    if rc == E_DIVERGED:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    _check(rc)
+    if want_stats:
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+    return None
 
 
 def mppi_plan(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, M=1, seed=0, eta=1.0,

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -285,6 +286,59 @@ bool all_finite(const float *p, size_t n)
 
 }  // namespace mppi_host
 
+namespace {
+
+// Working memory of mppi_plan_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never names it except to look
+// up its device address (kept per device in g_scratch_dev); kernels receive
+// that address like any other buffer.
+static __device__ __align__(256) unsigned char scratch[MPPI_NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+void *g_scratch_dev[MAX_DEVICES] = {nullptr};
+std::mutex g_scratch_mu;
+
+// with `device` current: look up the array's address on it (once per device)
+int scratch_init(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return fail(MPPI_E_INVAL, "device %d beyond %d", device, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return MPPI_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(MPPI_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_dev[device] = p;
+    return MPPI_OK;
+}
+
+// byte offsets of mppi_plan_noalloc's buffers in the array
+struct NoallocLayout {
+    size_t st, nu, w, cnt, dist, costs, total;
+};
+
+NoallocLayout noalloc_layout(long K, long H, long n_cost)
+{
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    NoallocLayout L;
+    size_t o = 0;
+    L.st = o;
+    o += al(sizeof(PlanStats));
+    L.nu = o;
+    o += al((size_t)H * NU * sizeof(float));
+    L.w = o;
+    o += al((size_t)K * sizeof(double));
+    L.cnt = o;
+    o += al((size_t)K * 4 * sizeof(int));
+    L.dist = o;  // the collision-distance history, [n_cost][K]
+    o += al((size_t)K * n_cost * sizeof(float));
+    L.costs = o;
+    o += al((size_t)K * sizeof(float));
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *mppi_last_error(void) { return mppi_host::g_err.c_str(); }
@@ -304,6 +358,11 @@ int mppi_ctx_create(int device, mppi_ctx **out)
         if (c->st) (void)hipFree(c->st);
         delete c;
         return fail(MPPI_E_NOMEM, "context allocation failed");
+    }
+    const int rc = scratch_init(device);  // the device is current
+    if (rc) {
+        mppi_ctx_destroy(c);
+        return rc;
     }
     *out = c;
     return MPPI_OK;
@@ -757,6 +816,98 @@ int mppi_plan(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const flo
 {
     return plan_impl(ctx, scene, x0, nominal_U, K, H, lambda, sigma, opts, nullptr, nullptr, U_new, costs, stats,
                      stream, nullptr);
+}
+
+int mppi_plan_noalloc(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
+                      double lambda, const float *sigma, const mppi_opts *opts, float *U_new, float *costs,
+                      mppi_stats *stats, void *stream)
+{
+    if (!ctx || !scene || !x0 || !nominal_U || !sigma || !opts || !U_new) return fail(MPPI_E_INVAL, "NULL argument");
+    if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
+    if (K < 1 || K > MPPI_MAX_K || H < 1 || H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "K=%d or H=%d out of range", K, H);
+    if (!(lambda > 0) || !std::isfinite(lambda)) return fail(MPPI_E_INVAL, "lambda must be finite and > 0");
+    if (opts->M < 1 || opts->M > 100000) return fail(MPPI_E_INVAL, "M=%d out of range", opts->M);
+    if (!std::isfinite(opts->eta)) return fail(MPPI_E_INVAL, "eta must be finite");
+    const unsigned fl = opts->flags;
+    if (!(fl & MPPI_DEVICE_PTRS)) return fail(MPPI_E_INVAL, "mppi_plan_noalloc takes device pointers (MPPI_DEVICE_PTRS)");
+    if (fl & (MPPI_GRAPH | MPPI_TIME_KERNELS)) return fail(MPPI_E_INVAL, "MPPI_GRAPH and MPPI_TIME_KERNELS are not supported here");
+    const NoallocLayout L = noalloc_layout(K, H, scene->host.n_cost);
+    if (L.total > (size_t)MPPI_NOALLOC_SCRATCH_BYTES)
+        return fail(MPPI_E_INVAL, "K=%d, H=%d with %d cost pairs need %zu bytes of scratch, above MPPI_NOALLOC_SCRATCH_BYTES (%zu)",
+                    K, H, scene->host.n_cost, L.total, (size_t)MPPI_NOALLOC_SCRATCH_BYTES);
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    char *base = (char *)g_scratch_dev[ctx->device];
+    if (!base) return fail(MPPI_E_DEVICE, "scratch of device %d not set up", ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    CtxStream order_guard(ctx, s);
+    if ((rc = order_guard.begin())) return rc;
+    PlanStats *st = (PlanStats *)(base + L.st);
+    float *dnu = (float *)(base + L.nu);
+    double *dw = (double *)(base + L.w);
+    int *dcnt = (int *)(base + L.cnt);
+    float *ddist = (float *)(base + L.dist);
+    float *dcost = costs ? costs : (float *)(base + L.costs);
+    const bool sps = fl & MPPI_SIGMA_PER_STEP;
+    const uint32_t k0 = (uint32_t)(opts->seed & 0xffffffffu), k1 = (uint32_t)(opts->seed >> 32);
+    const int n_elite = (opts->n_elite <= 0 || opts->n_elite >= K) ? K : opts->n_elite;
+    const int f32 = (fl & MPPI_FP32_WEIGHTS) ? 1 : 0;
+    const int mapping = resolve_mapping(ctx, K, fl);
+    // nu = nominal; the statistics record cleared by a kernel (no memset, so
+    // the sequence may be captured into a graph); then M x (rollout, stats, update)
+    HIPCHK(hipMemcpyAsync(dnu, nominal_U, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
+    launch_reset_stats(st, s);
+    for (int m = 0; m < opts->M; ++m) {
+        RolloutArgs ra = {};
+        ra.md = scene->dev;
+        ra.x0 = x0;
+        ra.x0_shared = 1;
+        ra.nu = dnu;
+        ra.sigma = sigma;
+        ra.sigma_per_step = sps;
+        ra.key0 = k0;
+        ra.key1 = k1;
+        ra.m = m;
+        ra.K = K;
+        ra.H = H;
+        ra.costs = dcost;
+        ra.counters = dcnt;
+        ra.diverged = &st->diverged;
+        ra.dist = ddist;
+        launch_rollout(ra, scene->host.n_cmax, s, mapping);
+        StatsArgs sa = {dcost, K, 1.0 / lambda, n_elite, dw, st, m, dcnt, f32};
+        launch_stats(sa, s);
+        UpdateArgs ua = {dw, K, H, dnu, sigma, sps, scene->host.u_max, k0, k1, m, opts->eta, st, dnu, nullptr, f32,
+                         nullptr};
+        launch_update(ua, s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(U_new, dnu, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (!stats && !(fl & MPPI_SYNC)) return MPPI_OK;
+    PlanStats hs;
+    HIPCHK(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->ess = hs.ess;
+        stats->c_min = hs.cmin;
+        stats->best = hs.best;
+        stats->n_nonfinite = K - hs.n_finite;
+        stats->diverged = hs.diverged;
+        stats->iterations = opts->M;
+        for (int i = 0; i < 64 && i < opts->M; ++i) stats->cmin_iter[i] = hs.cmin_iter[i];
+        stats->contacts = (double)hs.counters[0];
+        stats->np_tests = (double)hs.counters[1];
+        stats->box_tests = (double)hs.counters[2];
+        stats->overflow = (double)hs.counters[3];
+        stats->rollout_launches = opts->M;
+    }
+    if (hs.diverged) {
+        HIPCHK(hipMemcpyAsync(U_new, nominal_U, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return fail(MPPI_E_DIVERGED, "every sample diverged in some iteration");
+    }
+    return MPPI_OK;
 }
 
 int mppi_plan_best(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const float *nominal_U, int K, int H,
