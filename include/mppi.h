@@ -85,6 +85,11 @@ extern "C" {
                                    replayed while shapes, scalars and device buffers stay the same (a
                                    small per-context cache); MPPI_TIME_KERNELS is then ignored */
 
+#define MPPI_PER_STEP 4096u     /* mppi_plan and its variants: the plain form -- one rollout launch per
+                                   control step (one sample per lane; state, previous control, cost
+                                   sums and distance history carried in device memory between the
+                                   launches), no graph; results equal MPPI_MAP_LANE's */
+
 /* Global geom ids (pair tables and AABB arrays use them): 0 ball,
  * 1 table, 2 + 7*arm + g (g = 0..5 capsule of link g+1, g = 6 pad sphere on
  * link 7), 16 + b box b. */
@@ -467,6 +472,7 @@ typedef struct mppi_server mppi_server;
 
 #define MPPI_PENDING 1          /* mppi_poll: not finished yet */
 #define MPPI_E_CANCELLED (-7)   /* request status after mppi_cancel or supersession */
+#define MPPI_E_LATE (-9)        /* request status: shed unrun, it could not end by its deadline */
 
 #define MPPI_SUPERSEDE 128u     /* submit: cancel this cell's requests still queued (not yet admitted) */
 
@@ -474,16 +480,31 @@ typedef struct mppi_server_opts {
     uint64_t mem_budget;  /* device bytes for in-flight requests (0: 1 GiB) */
     int max_active;       /* requests iterating together (0: 256; at most 4096) */
     int max_pending;      /* queued requests; mppi_submit returns MPPI_E_BUSY beyond (0: 4096) */
-    unsigned flags;       /* MPPI_MAP_LANE, _TEAM, _WAVE or _SPLIT: mapping of every launch (else per
-                             iteration by total sample count) */
+    unsigned flags;       /* MPPI_MAP_LANE, _TEAM, _WAVE or _SPLIT: mapping of every launch (else each
+                             request keeps the family of the mapping it would get alone) */
+    /* Deadlines (the control period of the replanning cells).  deadline_ms > 0:
+     * every request must end within deadline_ms of its submission.  The queue
+     * is then served earliest deadline first; a request is admitted only when
+     * the predicted end of its M iterations (plus the packed iteration in
+     * flight), at the load it would join, is within its deadline and no
+     * active request predicted on time would become late (otherwise it waits
+     * and nothing overtakes it); a queued request that cannot end in time even
+     * alone is shed (status MPPI_E_LATE).  The prediction of one packed
+     * iteration is iter_base_ms + iter_ms_per_menv * W / 1e6, W the sum of
+     * K * H over the active requests; with both 0 the server fits them by least
+     * squares to its own measured iterations (the last 64). */
+    double deadline_ms;
+    double iter_base_ms;
+    double iter_ms_per_menv;
 } mppi_server_opts;
 
 typedef struct mppi_ticket_info {
-    int status;           /* MPPI_OK, MPPI_E_DIVERGED or MPPI_E_CANCELLED */
+    int status;           /* MPPI_OK, MPPI_E_DIVERGED, MPPI_E_CANCELLED or MPPI_E_LATE */
     int iterations;       /* iterations run */
     double t_submit_ms;   /* host steady clock, ms since the server was created */
     double t_admit_ms;    /* admitted into the active set (negative if never) */
     double t_done_ms;     /* completion observed by the worker */
+    double t_deadline_ms; /* t_submit_ms + deadline_ms (infinite without a deadline) */
 } mppi_ticket_info;
 
 typedef struct mppi_server_info {
@@ -493,6 +514,9 @@ typedef struct mppi_server_info {
     uint64_t env_steps;         /* sum of K * H over request iterations */
     uint64_t mem_high_water;    /* device bytes */
     int active, pending;
+    uint64_t shed;              /* requests dropped unrun because they could not end by their deadline */
+    uint64_t late;              /* requests completed after their deadline */
+    double model_base_ms, model_ms_per_menv;  /* the iteration model in use */
 } mppi_server_info;
 
 /* Create a server on `ctx` with its own non-blocking stream and worker

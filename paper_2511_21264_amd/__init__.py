@@ -21,10 +21,11 @@ MAX_BOXES = 16
 
 OK, E_INVAL, E_NOMEM, E_MODEL, E_DIVERGED, E_DEVICE, E_BUSY, E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
 E_NOTPD = -8
+E_LATE = -9
 COV_MAX_N = 3584
 PENDING = 1
 DEVICE_PTRS, SIGMA_PER_STEP, SYNC, TIME_KERNELS, TRAJ, MAP_LANE, MAP_TEAM, SUPERSEDE = 1, 2, 4, 8, 16, 32, 64, 128
-MAP_WAVE, FP32_WEIGHTS, GRAPH, MAP_SPLIT = 256, 512, 1024, 2048
+MAP_WAVE, FP32_WEIGHTS, GRAPH, MAP_SPLIT, PER_STEP = 256, 512, 1024, 2048, 4096
 _MAPS = {None: 0, "auto": 0, "lane": MAP_LANE, "team": MAP_TEAM, "wave": MAP_WAVE, "split": MAP_SPLIT}
 
 
@@ -131,19 +132,21 @@ class Request(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("mem_budget", C.c_uint64), ("max_active", C.c_int), ("max_pending", C.c_int), ("flags", C.c_uint)]
+    _fields_ = [("mem_budget", C.c_uint64), ("max_active", C.c_int), ("max_pending", C.c_int), ("flags", C.c_uint),
+                ("deadline_ms", C.c_double), ("iter_base_ms", C.c_double), ("iter_ms_per_menv", C.c_double)]
 
 
 class TicketInfo(C.Structure):
     _fields_ = [("status", C.c_int), ("iterations", C.c_int), ("t_submit_ms", C.c_double),
-                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double)]
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("t_deadline_ms", C.c_double)]
 
 
 class ServerInfo(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("cancelled", C.c_uint64),
                 ("superseded", C.c_uint64), ("rejected", C.c_uint64), ("iterations", C.c_uint64),
                 ("request_iters", C.c_uint64), ("env_steps", C.c_uint64), ("mem_high_water", C.c_uint64),
-                ("active", C.c_int), ("pending", C.c_int)]
+                ("active", C.c_int), ("pending", C.c_int), ("shed", C.c_uint64), ("late", C.c_uint64),
+                ("model_base_ms", C.c_double), ("model_ms_per_menv", C.c_double)]
 
 
 _lib = None
@@ -371,15 +374,16 @@ def mppi_plan_noalloc(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=
 
 def mppi_plan(ctx, scene, x0, nominal_U, K, H, lam, sigma, U_new, costs=None, *, M=1, seed=0, eta=1.0,
               n_elite=0, sigma_per_step=False, time_kernels=False, want_stats=True, sync=False, stream=None,
-              mapping=None, fp32_weights=False, graph=False):
+              mapping=None, fp32_weights=False, graph=False, per_step=False):
     """One plan (Alg. 1).  Arrays: x0[55], nominal_U[H,14], sigma[14] or [H,14],
-    U_new[H,14] (out), costs[K] (out).  mapping: None/"auto", "lane" or "team".
+    U_new[H,14] (out), costs[K] (out).  mapping: None/"auto", "lane", "team",
+    "wave" or "split"; per_step: the plain form (one launch per control step).
     Returns a stats dict (or None)."""
     (px0, pnom, psig, pU, pc), dev = _ptrs([(x0, np.float32), (nominal_U, np.float32), (sigma, np.float32),
                                              (U_new, np.float32), (costs, np.float32)])
     flags = (DEVICE_PTRS if dev else 0) | (SIGMA_PER_STEP if sigma_per_step else 0) | \
             (TIME_KERNELS if time_kernels else 0) | (SYNC if sync else 0) | _MAPS[mapping] | \
-            (FP32_WEIGHTS if fp32_weights else 0) | (GRAPH if graph else 0)
+            (FP32_WEIGHTS if fp32_weights else 0) | (GRAPH if graph else 0) | (PER_STEP if per_step else 0)
     o = Opts(int(M), int(seed) & 0xFFFFFFFFFFFFFFFF, float(eta), int(n_elite), flags)
     st = Stats()
     rc = lib().mppi_plan(ctx._h, scene._h, px0, pnom, int(K), int(H), float(lam), psig, C.byref(o), pU, pc,
@@ -670,10 +674,12 @@ class Server:
     """Continuous-batching replanning server (mppi_server_* / mppi_submit / mppi_poll / mppi_cancel).
     Output arrays and stats of a request are kept alive here until it is polled done."""
 
-    def __init__(self, ctx, mem_budget=0, max_active=0, max_pending=0, mapping=None):
+    def __init__(self, ctx, mem_budget=0, max_active=0, max_pending=0, mapping=None, deadline_ms=0.0,
+                 iter_base_ms=0.0, iter_ms_per_menv=0.0):
         self.ctx = ctx
         self._h = _P()
-        o = ServerOpts(int(mem_budget), int(max_active), int(max_pending), _MAPS[mapping])
+        o = ServerOpts(int(mem_budget), int(max_active), int(max_pending), _MAPS[mapping], float(deadline_ms),
+                       float(iter_base_ms), float(iter_ms_per_menv))
         _check(lib().mppi_server_create(ctx._h, C.byref(o), C.byref(self._h)))
         self._keep = {}
 

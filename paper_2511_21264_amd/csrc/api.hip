@@ -606,7 +606,10 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
     // the best sequence of the last iteration goes to U_best (same side as U_new)
     void *dbest = nullptr;
     if (U_best && (rc = out_ptr(ctx, S_OUT3, U_best, (size_t)H * NU * sizeof(float), dev, &dbest))) return rc;
-    const bool use_graph = (fl & MPPI_GRAPH) && !qp && !cov && !U_best;
+    const bool per_step = fl & MPPI_PER_STEP;
+    void *dps = nullptr;
+    if (per_step && (rc = ensure(ctx, S_PLAIN, (size_t)K * PLAIN_FIELDS * sizeof(float), &dps))) return rc;
+    const bool use_graph = (fl & MPPI_GRAPH) && !qp && !cov && !U_best && !per_step;
     const bool timing = (fl & MPPI_TIME_KERNELS) && !use_graph;
     const int M = opts->M;
     if (timing) {
@@ -619,7 +622,7 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
     const uint32_t k0 = (uint32_t)(opts->seed & 0xffffffffu), k1 = (uint32_t)(opts->seed >> 32);
     const int n_elite = (opts->n_elite <= 0 || opts->n_elite >= K) ? K : opts->n_elite;
     const int f32 = (fl & MPPI_FP32_WEIGHTS) ? 1 : 0;
-    const int mapping = resolve_mapping(ctx, K, fl);
+    const int mapping = per_step ? MAP_LANE : resolve_mapping(ctx, K, fl);
     // the launch sequence of the plan: nu = nominal, stats reset, M x (rollout, stats, update)
     auto enqueue = [&](hipStream_t q) -> int {
         HIPCHK(hipMemcpyAsync(dnu, dnom, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, q));
@@ -674,7 +677,11 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
                 ra.U = Ucur;
             }
             if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], q));
-            launch_rollout(ra, scene->host.n_cmax, q, mapping);
+            if (per_step) {
+                for (int k = 0; k < H; ++k) launch_rollout_step(ra, scene->host.n_cmax, (float *)dps, k, q);
+            } else {
+                launch_rollout(ra, scene->host.n_cmax, q, mapping);
+            }
             if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], q));
             StatsArgs sa = {(const float *)dcost, K, 1.0 / lambda, n_elite, (double *)dw, ctx->st, m,
                             (const int *)dcnt, f32};

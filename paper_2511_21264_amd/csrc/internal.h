@@ -29,7 +29,7 @@ struct Buf {
 enum Slot {
     S_X0, S_SIGMA, S_NU, S_NOM, S_COSTS, S_W, S_CNT, S_DIST, S_IN0, S_IN1, S_OUT0, S_OUT1, S_OUT2, S_OUT3,
     S_BTAB, S_BST, S_BIN, S_BNU, S_BCOST, S_BW, S_BCNT, S_BDIST, S_QPP, S_QPU,
-    S_COVS, S_COVA, S_COVL, S_COVL32, S_COVLI, S_COVZ, S_COVU, S_NU64, S_N
+    S_COVS, S_COVA, S_COVL, S_COVL32, S_COVLI, S_COVZ, S_COVU, S_NU64, S_PLAIN, S_N
 };
 
 int mapping_of(unsigned flags);

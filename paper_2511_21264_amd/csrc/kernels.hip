@@ -136,6 +136,116 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a0, const Rollo
     }
 }
 
+// The plain form: one launch per control step k, one sample per lane, the
+// sample's state, previous control, cost accumulators, distance-history bits
+// and counters kept in HBM between launches ([field][K], so a wave's loads
+// and stores are coalesced).  The same device functions in the same order as
+// rollout_kernel: the step-k launch loads what launch k - 1 stored.
+constexpr int PS_X = 0, PS_UPREV = NX, PS_ACC = NX + NU, PS_HIST = NX + NU + 7, PS_CNT = PS_HIST + 16;
+
+template <int NC>
+__global__ void __launch_bounds__(64) rollout_step_kernel(RolloutArgs a, float *ps, int k)
+{
+    extern __shared__ float lds[];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.K) return;
+    const DevModel &md = *a.md;
+    if (a.diverged && *a.diverged) {
+        if (k == a.H - 1) a.costs[j] = INFINITY;
+        return;
+    }
+    const long K = a.K;
+    const LaneList LL{lds, (int)threadIdx.x, (int)blockDim.x};
+    const LanePark pk{lds + NC * CL_FIELDS * blockDim.x, (int)threadIdx.x, (int)blockDim.x};
+    float x[NX], uprev[NU];
+    CostAcc acc;
+    DistHist hist;
+    StepCounters cnt;
+    if (k == 0) {
+        const float *x0 = a.x0 + (a.x0_shared ? 0 : (long)j * NX);
+#pragma unroll
+        for (int i = 0; i < NX; ++i) x[i] = x0[i];
+#pragma unroll
+        for (int d = 0; d < NU; ++d) uprev[d] = 0.f;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
+#pragma unroll
+        for (int i = 0; i < 14; ++i) hist.box[i] = 0u;
+        hist.aa[0] = hist.aa[1] = 0u;
+        cnt = {0, 0, 0, 0};
+    } else {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) x[i] = ps[(PS_X + i) * K + j];
+#pragma unroll
+        for (int d = 0; d < NU; ++d) uprev[d] = ps[(PS_UPREV + d) * K + j];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) acc.t[i] = ps[(PS_ACC + i) * K + j];
+#pragma unroll
+        for (int i = 0; i < 14; ++i) hist.box[i] = __float_as_uint(ps[(PS_HIST + i) * K + j]);
+        hist.aa[0] = __float_as_uint(ps[(PS_HIST + 14) * K + j]);
+        hist.aa[1] = __float_as_uint(ps[(PS_HIST + 15) * K + j]);
+        cnt.contacts = __float_as_int(ps[(PS_CNT + 0) * K + j]);
+        cnt.np_tests = __float_as_int(ps[(PS_CNT + 1) * K + j]);
+        cnt.box_tests = __float_as_int(ps[(PS_CNT + 2) * K + j]);
+        cnt.overflow = __float_as_int(ps[(PS_CNT + 3) * K + j]);
+    }
+    const int nsub = a.n_sub > 0 ? a.n_sub : md.n_sub;
+    float *dist = a.dist + j;
+    float u[NU];
+    if (a.U) {
+        const float *uk = a.U + ((long)j * a.H + k) * NU;
+#pragma unroll
+        for (int d = 0; d < NU; ++d) u[d] = uk[d];
+    } else {
+        sample_u(a.nu + k * NU, a.sigma + (a.sigma_per_step ? k * NU : 0), md.u_max, a.key0, a.key1, (uint32_t)j,
+                 (uint32_t)k, (uint32_t)a.m, u);
+    }
+    for (int s = 0; s < nsub; ++s) substep<NC>(model(a.md), x, u, LL, pk, cnt);
+    stage_cost(model(a.md), x, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
+    if (a.xout && a.traj) {
+        float *o = a.xout + ((long)j * a.H + k) * NX;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) o[i] = x[i];
+    }
+    if (k < a.H - 1) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) ps[(PS_X + i) * K + j] = x[i];
+#pragma unroll
+        for (int d = 0; d < NU; ++d) ps[(PS_UPREV + d) * K + j] = u[d];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) ps[(PS_ACC + i) * K + j] = acc.t[i];
+#pragma unroll
+        for (int i = 0; i < 14; ++i) ps[(PS_HIST + i) * K + j] = __uint_as_float(hist.box[i]);
+        ps[(PS_HIST + 14) * K + j] = __uint_as_float(hist.aa[0]);
+        ps[(PS_HIST + 15) * K + j] = __uint_as_float(hist.aa[1]);
+        ps[(PS_CNT + 0) * K + j] = __int_as_float(cnt.contacts);
+        ps[(PS_CNT + 1) * K + j] = __int_as_float(cnt.np_tests);
+        ps[(PS_CNT + 2) * K + j] = __int_as_float(cnt.box_tests);
+        ps[(PS_CNT + 3) * K + j] = __int_as_float(cnt.overflow);
+        return;
+    }
+    float c = md.w_goal * acc.t[0] + md.w_eo * acc.t[1] + md.w_l * acc.t[2] + md.w_yz * acc.t[3] +
+              md.w_s * acc.t[4] + md.w_c * (acc.t[5] + acc.t[6]);
+    bool finite = isfinite(c);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) finite &= isfinite(x[i]);
+    a.costs[j] = finite ? c : INFINITY;
+    if (a.terms) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) a.terms[(long)j * 7 + i] = acc.t[i];
+    }
+    if (a.xout && !a.traj) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) a.xout[(long)j * NX + i] = x[i];
+    }
+    if (a.counters) {
+        a.counters[4 * j + 0] = cnt.contacts;
+        a.counters[4 * j + 1] = cnt.np_tests;
+        a.counters[4 * j + 2] = cnt.box_tests;
+        a.counters[4 * j + 3] = cnt.overflow;
+    }
+}
+
 // Team mappings: 16 lanes per sample.  TPW = 4: four samples per 64-lane
 // workgroup; TPW = 1: one sample per wave, its four 16-lane rows computing
 // the same values and splitting the contact sweep 64 wide.  Teams past K
@@ -525,6 +635,17 @@ void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping)
     const int map = pick_mapping(a.K, mapping);
     const int per = samples_per_block(map);
     launch_rollout_impl(a, nullptr, nullptr, (a.K + per - 1) / per, ncmax, a.m, map, s);
+}
+
+void launch_rollout_step(const RolloutArgs &a, int ncmax, float *ps, int k, hipStream_t s)
+{
+    const int nc = ncmax <= 4 ? 4 : 8;
+    const size_t lds = (size_t)(nc * CL_FIELDS + PK_FIELDS) * 64 * sizeof(float);
+    const dim3 grid((a.K + 63) / 64), block(64);
+    if (nc == 4)
+        hipLaunchKernelGGL(rollout_step_kernel<4>, grid, block, lds, s, a, ps, k);
+    else
+        hipLaunchKernelGGL(rollout_step_kernel<8>, grid, block, lds, s, a, ps, k);
 }
 
 void launch_rollout_batch(const RolloutArgs *d_tab, const int *d_blk, int nblk, int ncmax, int m, int map,

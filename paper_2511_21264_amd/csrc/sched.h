@@ -3,6 +3,8 @@
 // Nothing here touches the device; serve.hip maps arena offsets onto its
 // device and pinned regions and launches the work.
 #pragma once
+#include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <deque>
@@ -100,13 +102,32 @@ struct SchedReq {
     size_t dev_off = NO_SPACE, host_off = NO_SPACE;
     bool cancel = false;
     int state = RS_PENDING;
+    double deadline = INFINITY;  // absolute, in the caller's clock (ms); INFINITY: none
+    double work = 0.0;           // env-steps of one of its iterations (K * H)
+};
+
+// Predicted device time of one packed iteration over active requests whose
+// iterations hold W env-steps in total: base_ms + ms_per_work * W.  A zero
+// model predicts no time (admission then only orders by deadline and sheds
+// requests already past theirs).
+struct IterModel {
+    double base_ms = 0.0, ms_per_work = 0.0;
+    double time(double W) const { return base_ms + ms_per_work * W; }
 };
 
 // Admission and iteration order of the requests of a server.
-//   * Queue: FIFO.  A request waits while an earlier request of its cell is
-//     queued or active (a cell's requests run in submission order); the
-//     scan stops at the first request that does not fit in memory (no
-//     overtaking on memory, so a large request cannot starve).
+//   * Queue: earliest deadline first, ties (and requests without deadline)
+//     in submission order, so with no deadlines the queue is FIFO.  A
+//     request waits while an earlier request of its cell is queued or
+//     active (a cell's requests run in submission order); the scan stops at
+//     the first request that does not fit in memory (no overtaking on
+//     memory, so a large request cannot starve).
+//   * Deadlines: a request is admitted only when, with the iteration model
+//     at the load it would join, its M iterations (plus the one already in
+//     flight) end by its deadline, and no active request predicted on time
+//     would become late; otherwise the scan stops there (it waits for load
+//     to drain, nothing overtakes it).  A queued request that cannot end by
+//     its deadline even alone is shed: it leaves the queue unrun.
 //   * Active set: at most max_active requests; each iteration runs one
 //     MPPI iteration of every active request, each at its own index m.
 //   * A request leaves the active set when its last iteration has been
@@ -147,22 +168,63 @@ public:
         return 0;
     }
 
-    // admitted ids, in admission order
-    std::vector<uint64_t> admit()
+    // predicted end of request r admitted at `now` into a load of W: its M - m
+    // remaining iterations after the one in flight
+    static double predicted_end(const SchedReq &r, double now, const IterModel &im, double W)
+    {
+        return now + (double)(r.M - r.m + 1) * im.time(W);
+    }
+
+    // admitted ids, in admission order; requests shed (see above) go to *shed
+    // (their state becomes RS_DONE; they hold no memory)
+    std::vector<uint64_t> admit(double now = 0.0, const IterModel &im = IterModel{},
+                                std::vector<uint64_t> *shed = nullptr)
     {
         std::vector<uint64_t> out;
+        if (shed) {
+            for (auto it = pending_.begin(); it != pending_.end();) {
+                SchedReq &r = reqs_.at(*it);
+                if (predicted_end(r, now, im, r.work) > r.deadline) {
+                    shed->push_back(r.id);
+                    r.state = RS_DONE;
+                    r.cancel = true;
+                    it = pending_.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        std::vector<uint64_t> order(pending_.begin(), pending_.end());
+        std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
+            const double da = reqs_.at(a).deadline, db = reqs_.at(b).deadline;
+            return da < db || (da == db && a < b);
+        });
+        // a cell's requests run in submission order: only its oldest queued
+        // request may be admitted, and only while none of it is active
+        std::unordered_map<int, uint64_t> oldest;
+        for (uint64_t id : pending_) {
+            const int c = reqs_.at(id).cell;
+            if (c >= 0 && !oldest.count(c)) oldest[c] = id;
+        }
         std::unordered_map<int, bool> blocked;
+        double W = 0.0;
         for (uint64_t a : active_) {
             const SchedReq &r = reqs_.at(a);
             if (r.cell >= 0) blocked[r.cell] = true;
+            W += r.work;
         }
-        for (auto it = pending_.begin(); it != pending_.end();) {
+        for (uint64_t id : order) {
             if ((int)active_.size() >= max_active_) break;
-            SchedReq &r = reqs_.at(*it);
-            if (r.cell >= 0 && blocked.count(r.cell)) {
-                ++it;
-                continue;
+            SchedReq &r = reqs_.at(id);
+            if (r.cell >= 0 && (blocked.count(r.cell) || oldest.at(r.cell) != id)) continue;
+            const double W1 = W + r.work;
+            bool fits = predicted_end(r, now, im, W1) <= r.deadline;
+            for (uint64_t a : active_) {
+                const SchedReq &q = reqs_.at(a);
+                if (fits && std::isfinite(q.deadline) && predicted_end(q, now, im, W) <= q.deadline)
+                    fits = predicted_end(q, now, im, W1) <= q.deadline;
             }
+            if (!fits) break;  // wait for the load to drain; nothing overtakes it
             const size_t d = dev_.alloc(r.dev_bytes);
             if (d == NO_SPACE) break;
             const size_t h = host_.alloc(r.host_bytes);
@@ -174,9 +236,10 @@ public:
             r.host_off = h;
             r.state = RS_ACTIVE;
             if (r.cell >= 0) blocked[r.cell] = true;
+            W = W1;
             active_.push_back(r.id);
             out.push_back(r.id);
-            it = pending_.erase(it);
+            pending_.erase(std::find(pending_.begin(), pending_.end(), id));
         }
         return out;
     }

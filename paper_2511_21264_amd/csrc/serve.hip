@@ -95,7 +95,7 @@ struct Req {
     char *d = nullptr, *h = nullptr;  // arena slices (while admitted)
     int status = MPPI_OK, iters = 0;
     bool done = false, cancelled = false;
-    double t_submit = 0, t_admit = -1, t_done = -1;
+    double t_submit = 0, t_admit = -1, t_done = -1, t_deadline = INFINITY;
 
     template <class T> T *dp(size_t off) const { return (T *)(d + off); }
     template <class T> T *hp(size_t off) const { return (T *)(h + off); }
@@ -122,6 +122,14 @@ struct mppi_server {
     void *dtab[2] = {nullptr, nullptr}, *htab[2] = {nullptr, nullptr};
     size_t tcap[2] = {0, 0};
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // timing of each buffer's packed iteration, its load (sum of K * H), and
+    // the recent (load, ms) pairs the iteration model is fitted to
+    hipEvent_t tev0[2] = {nullptr, nullptr}, tev1[2] = {nullptr, nullptr};
+    double load_at[2] = {0.0, 0.0};
+    std::vector<std::pair<double, double>> meas;
+    size_t meas_next = 0;
+    IterModel model;
+    bool model_fixed = false;
     bool inflight[2] = {false, false};
     std::vector<uint64_t> fin_at[2], drop_at[2];
     int worker_rc = MPPI_OK;
@@ -153,12 +161,44 @@ void fill_stats(const Req &R, const PlanStats &p, mppi_stats *st)
 }
 
 // Wait for the work of buffer `b` and retire its requests.
+// Least-squares fit of ms = base + slope * W to the recent measured packed
+// iterations (slope 0 and base their mean when the loads do not vary; both
+// kept >= 0).
+void fit_model(mppi_server *S)
+{
+    const size_t n = S->meas.size();
+    if (n == 0) return;
+    double sw = 0, st = 0, sww = 0, swt = 0;
+    for (auto &m : S->meas) {
+        sw += m.first;
+        st += m.second;
+        sww += m.first * m.first;
+        swt += m.first * m.second;
+    }
+    const double mw = sw / n, mt = st / n, vw = sww / n - mw * mw, cwt = swt / n - mw * mt;
+    double slope = vw > 1e-9 * (mw * mw + 1.0) ? cwt / vw : 0.0;
+    slope = std::max(slope, 0.0);
+    S->model.ms_per_work = slope;
+    S->model.base_ms = std::max(mt - slope * mw, 0.0);
+}
+
 int retire(mppi_server *S, int b)
 {
     if (!S->inflight[b]) return MPPI_OK;
     HIPCHK(hipEventSynchronize(S->ev[b]));
+    float it_ms = -1.f;
+    if (S->load_at[b] > 0 && hipEventElapsedTime(&it_ms, S->tev0[b], S->tev1[b]) != hipSuccess) it_ms = -1.f;
     std::lock_guard<std::mutex> lk(S->mu);
     const double t = S->now_ms();
+    if (it_ms >= 0.f && !S->model_fixed) {
+        const std::pair<double, double> m(S->load_at[b], (double)it_ms);
+        if (S->meas.size() < 64)
+            S->meas.push_back(m);
+        else
+            S->meas[S->meas_next++ % 64] = m;
+        fit_model(S);
+    }
+    S->load_at[b] = 0.0;
     for (uint64_t id : S->fin_at[b]) {
         Req &R = S->reqs.at(id);
         const PlanStats &p = *R.hp<PlanStats>(R.L.h_st);
@@ -171,6 +211,7 @@ int retire(mppi_server *S, int b)
         R.iters = R.M;
         R.t_done = t;
         R.done = true;
+        if (t > R.t_deadline) ++S->info.late;
         S->sched.release(id);
         R.d = R.h = nullptr;
         ++S->info.completed;
@@ -399,14 +440,24 @@ int worker_loop(mppi_server *S)
         std::vector<uint64_t> dropped;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            for (uint64_t id : S->sched.admit()) {
+            std::vector<uint64_t> shed;
+            const double now = S->now_ms();
+            for (uint64_t id : S->sched.admit(now, S->model, &shed)) {
                 Req &R = S->reqs.at(id);
                 const SchedReq *q = S->sched.find(id);
                 R.d = S->dbase + q->dev_off;
                 R.h = S->hbase + q->host_off;
-                R.t_admit = S->now_ms();
+                R.t_admit = now;
                 admitted.push_back(&R);
             }
+            for (uint64_t id : shed) {
+                Req &R = S->reqs.at(id);
+                R.done = true;
+                R.status = MPPI_E_LATE;
+                R.t_done = now;
+                ++S->info.shed;
+            }
+            if (!shed.empty()) S->cv_done.notify_all();
             for (const SchedReq *q : S->sched.next_iteration(&dropped)) {
                 Req &R = S->reqs.at(q->id);
                 act.push_back(&R);
@@ -436,8 +487,13 @@ int worker_loop(mppi_server *S)
             S->cv_work.wait(lk, [&] { return S->stop || S->sched.n_pending() > 0 || S->sched.n_active() > 0; });
             continue;
         }
+        HIPCHK(hipEventRecord(S->tev0[b], S->s));
         if ((rc = launch_iteration(S, b, act, m_of, fin))) return rc;
+        HIPCHK(hipEventRecord(S->tev1[b], S->s));
         HIPCHK(hipEventRecord(S->ev[b], S->s));
+        double load = 0.0;
+        for (Req *R : act) load += (double)R->K * (double)R->H;
+        S->load_at[b] = load;
         {
             std::lock_guard<std::mutex> lk(S->mu);
             std::vector<uint64_t> done = S->sched.advance();
@@ -484,6 +540,9 @@ int mppi_server_create(mppi_ctx *ctx, const mppi_server_opts *opts, mppi_server 
     if (o.max_pending <= 0) o.max_pending = 4096;
     if (o.max_active > 4096) return fail(MPPI_E_INVAL, "max_active above 4096");
     if (o.mem_budget < (1u << 20)) return fail(MPPI_E_INVAL, "mem_budget below 1 MiB");
+    if (!(o.deadline_ms >= 0) || !(o.iter_base_ms >= 0) || !(o.iter_ms_per_menv >= 0) ||
+        !std::isfinite(o.iter_base_ms) || !std::isfinite(o.iter_ms_per_menv))
+        return fail(MPPI_E_INVAL, "deadline_ms and the iteration model must be finite and >= 0");
     int rc = set_device(ctx);
     if (rc) return rc;
     mppi_server *S = new mppi_server();
@@ -498,15 +557,23 @@ int mppi_server_create(mppi_ctx *ctx, const mppi_server_opts *opts, mppi_server 
     ok = ok && hipHostMalloc((void **)&S->hbase, host_bytes) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&S->ev[0], hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&S->ev[1], hipEventDisableTiming) == hipSuccess;
+    for (int b = 0; b < 2; ++b) {
+        ok = ok && hipEventCreate(&S->tev0[b]) == hipSuccess;
+        ok = ok && hipEventCreate(&S->tev1[b]) == hipSuccess;
+    }
     if (!ok) {
         if (S->dbase) (void)hipFree(S->dbase);
         if (S->hbase) (void)hipHostFree(S->hbase);
         if (S->s) (void)hipStreamDestroy(S->s);
-        for (auto e : S->ev)
-            if (e) (void)hipEventDestroy(e);
+        for (int b = 0; b < 2; ++b)
+            for (hipEvent_t e : {S->ev[b], S->tev0[b], S->tev1[b]})
+                if (e) (void)hipEventDestroy(e);
         delete S;
         return fail(MPPI_E_NOMEM, "server allocation failed");
     }
+    S->model.base_ms = o.iter_base_ms;
+    S->model.ms_per_work = o.iter_ms_per_menv * 1e-6;
+    S->model_fixed = o.iter_base_ms > 0 || o.iter_ms_per_menv > 0;
     S->sched = Scheduler(o.mem_budget, host_bytes, o.max_active, o.max_pending);
     S->worker = std::thread(worker_main, S);
     *out = S;
@@ -542,6 +609,8 @@ void mppi_server_destroy(mppi_server *S)
         if (S->dtab[b]) (void)hipFree(S->dtab[b]);
         if (S->htab[b]) (void)hipHostFree(S->htab[b]);
         if (S->ev[b]) (void)hipEventDestroy(S->ev[b]);
+        if (S->tev0[b]) (void)hipEventDestroy(S->tev0[b]);
+        if (S->tev1[b]) (void)hipEventDestroy(S->tev1[b]);
     }
     (void)hipFree(S->dbase);
     (void)hipHostFree(S->hbase);
@@ -648,10 +717,13 @@ int mppi_submit(mppi_server *S, const mppi_request *req, int cell, int advance, 
     std::lock_guard<std::mutex> lk(S->mu);
     R.id = S->next_id++;
     R.t_submit = S->now_ms();
+    if (S->o.deadline_ms > 0) R.t_deadline = R.t_submit + S->o.deadline_ms;
     SchedReq q;
     q.id = R.id;
     q.cell = cell;
     q.M = R.M;
+    q.deadline = R.t_deadline;
+    q.work = (double)R.K * (double)R.H;
     q.dev_bytes = R.L.dev_total;
     q.host_bytes = R.L.host_total;
     std::vector<uint64_t> sup;
@@ -697,6 +769,7 @@ int mppi_poll(mppi_server *S, uint64_t ticket, int timeout_ms, mppi_ticket_info 
         info->t_submit_ms = R.t_submit;
         info->t_admit_ms = R.t_admit;
         info->t_done_ms = R.t_done;
+        info->t_deadline_ms = R.t_deadline;
     }
     S->sched.forget(ticket);
     S->reqs.erase(it);
@@ -729,6 +802,8 @@ int mppi_server_query(mppi_server *S, mppi_server_info *info)
     info->active = S->sched.n_active();
     info->pending = S->sched.n_pending();
     info->mem_high_water = S->sched.dev().high_water();
+    info->model_base_ms = S->model.base_ms;
+    info->model_ms_per_menv = S->model.ms_per_work * 1e6;
     return MPPI_OK;
 }
 

@@ -43,6 +43,33 @@ int sched_enqueue(void *s, uint64_t id, int cell, int M, uint64_t dev, uint64_t 
     for (size_t i = 0; i < v.size(); ++i) sup[i] = v[i];
     return rc;
 }
+// enqueue with an absolute deadline (ms) and the work of one iteration
+int sched_enqueue_dl(void *s, uint64_t id, int cell, int M, uint64_t dev, double deadline, double work)
+{
+    SchedReq r;
+    r.id = id;
+    r.cell = cell;
+    r.M = M;
+    r.dev_bytes = dev;
+    r.host_bytes = 256;
+    r.deadline = deadline;
+    r.work = work;
+    return ((Scheduler *)s)->enqueue(r, false, nullptr);
+}
+// admission at time `now` with the iteration model (base_ms + slope * W);
+// shed ids in shed (count in *nshed)
+int sched_admit_dl(void *s, double now, double base_ms, double slope, uint64_t *ids, uint64_t *shed, int *nshed)
+{
+    std::vector<uint64_t> sh;
+    IterModel im;
+    im.base_ms = base_ms;
+    im.ms_per_work = slope;
+    std::vector<uint64_t> v = ((Scheduler *)s)->admit(now, im, &sh);
+    for (size_t i = 0; i < v.size(); ++i) ids[i] = v[i];
+    *nshed = (int)sh.size();
+    for (size_t i = 0; i < sh.size(); ++i) shed[i] = sh[i];
+    return (int)v.size();
+}
 int sched_admit(void *s, uint64_t *ids)
 {
     std::vector<uint64_t> v = ((Scheduler *)s)->admit();

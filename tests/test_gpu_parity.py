@@ -290,6 +290,32 @@ def test_plan_equals_its_stages(mp, ctx, mapping):
     scene.close()
 
 
+@pytest.mark.parametrize("cfg,K,H", [(1, 70, 12), (2, 130, 9)])
+def test_plain_per_step_plan_equals_lane_plan(mp, ctx, cfg, K, H):
+    """The plain form (one launch per control step; state, previous control,
+    cost sums, distance history and counters carried in device memory)
+    runs the one-lane mapping's arithmetic in the same order: plans, costs
+    and counters equal it bit for bit (two workgroups and a ragged tail)."""
+    sc = W.make_scene(cfg)
+    scene = mp.Scene(ctx, sc)
+    pp = W.plan_params(cfg, K=K, H=H, M=3)
+    x0 = T(W.initial_state(sc))
+    nom = T(np.random.default_rng(4).uniform(-0.3, 0.3, (H, 14)))
+    out = []
+    for per_step in (False, True):
+        U = torch.zeros((H, 14), device=DEV)
+        c = torch.zeros(K, device=DEV)
+        st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], T(pp["sigma"]), U, c, M=3, seed=pp["seed"],
+                          mapping="lane", per_step=per_step)
+        torch.cuda.synchronize()
+        out.append((U, c, st))
+    (U1, c1, s1), (U2, c2, s2) = out
+    assert torch.equal(U1, U2) and torch.equal(c1, c2)
+    for k in ("best", "ess", "contacts", "np_tests", "box_tests", "overflow", "cmin_iter"):
+        assert s1[k] == s2[k], k
+    scene.close()
+
+
 @pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split"])
 def test_plan_c1_against_oracle(mp, ctx, oracle_mod, mapping):
     """End-to-end plan at the small workload (K=64, H=20, 5 iterations).  The

@@ -270,3 +270,37 @@ def test_destroy_with_work_in_flight(mp, ctx):
     srv.close()  # cancels the queue, drains what runs, joins the worker
     for it in items:
         it["scene"].close()
+
+
+def test_deadlines_shed_order_and_results(mp, ctx):
+    """With a deadline, a request that cannot end in time even alone under the
+    iteration model is shed unrun (MPPI_E_LATE); the others run, carry their
+    deadline, and equal their plans alone bit for bit; the server fits its
+    own iteration model when none is given."""
+    items = _items(mp, ctx, [(64, 6, 2), (40, 5, 3), (80, 4, 2)], base=40)
+    # 10 ms per packed iteration predicted: M = 20 needs 210 ms > 100 ms
+    big = _items(mp, ctx, [(32, 4, 20)], base=50)[0]
+    srv = mp.Server(ctx, mapping="team", deadline_ms=100.0, iter_base_ms=10.0)
+    t_big = srv.submit(big)
+    ts = [srv.submit(it) for it in items]
+    r_big = srv.wait(t_big)
+    assert r_big["status"] == mp.E_LATE and r_big["iterations"] == 0
+    res = [srv.wait(t) for t in ts]
+    q = srv.query()
+    srv.close()
+    assert q["shed"] == 1 and q["completed"] == len(items)
+    assert q["model_base_ms"] == 10.0
+    for it, r in zip(items, res):
+        assert r["status"] == 0
+        assert r["t_deadline_ms"] == pytest.approx(r["t_submit_ms"] + 100.0)
+        U, c, _ = _plan_alone(mp, ctx, it, "team")
+        assert torch.equal(U, it["U_new"]) and torch.equal(c, it["costs"])
+    # no model given: the server measures its iterations and fits one
+    srv = mp.Server(ctx, mapping="team", deadline_ms=1e6)
+    for it in items:
+        srv.wait(srv.submit(it))
+    q = srv.query()
+    srv.close()
+    assert q["model_base_ms"] > 0 and q["late"] == 0 and q["shed"] == 0
+    for it in items + [big]:
+        it["scene"].close()

@@ -1,7 +1,10 @@
 """Host logic of the serving loop (csrc/sched.h), on the CPU: the first-fit
 arena against a brute-force byte map, and the admission rules of the
 scheduler (FIFO, per-cell order, memory admission without overtaking,
-active-slot limit, cancellation, supersession, release)."""
+active-slot limit, cancellation, supersession, release; with deadlines:
+earliest deadline first, admission only when the iteration model predicts
+the request and every active one on time, shedding of requests that cannot
+finish in time even alone)."""
 import ctypes as C
 import os
 import subprocess
@@ -30,6 +33,9 @@ def S(tmp_path_factory):
         "sched_enqueue": (C.c_int, [C.c_void_p, U64, C.c_int, C.c_int, U64, U64, C.c_int, C.POINTER(U64),
                                     C.POINTER(C.c_int)]),
         "sched_admit": (C.c_int, [C.c_void_p, C.POINTER(U64)]),
+        "sched_enqueue_dl": (C.c_int, [C.c_void_p, U64, C.c_int, C.c_int, U64, C.c_double, C.c_double]),
+        "sched_admit_dl": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.POINTER(U64),
+                                     C.POINTER(U64), C.POINTER(C.c_int)]),
         "sched_cancel": (C.c_int, [C.c_void_p, U64]),
         "sched_next": (C.c_int, [C.c_void_p, C.POINTER(U64), C.POINTER(C.c_int), C.POINTER(U64),
                                  C.POINTER(C.c_int)]),
@@ -60,6 +66,14 @@ class Sched:
     def admit(self):
         n = self.L.sched_admit(self.h, self.buf)
         return [self.buf[i] for i in range(n)]
+
+    def enqueue_dl(self, id, cell, M, deadline, work, dev=1000):
+        return self.L.sched_enqueue_dl(self.h, id, cell, M, dev, float(deadline), float(work))
+
+    def admit_dl(self, now, base, slope):
+        ns = C.c_int(0)
+        n = self.L.sched_admit_dl(self.h, float(now), float(base), float(slope), self.buf, self.buf2, C.byref(ns))
+        return [self.buf[i] for i in range(n)], [self.buf2[i] for i in range(ns.value)]
 
     def next(self):
         nd = C.c_int(0)
@@ -257,4 +271,121 @@ def test_random_workload_invariants(S):
         assert (i in done) != (i in cancelled) or (i in cancelled and i not in done)
         if i not in cancelled:
             assert i in done and seen[i] == M[i]
+    s.close()
+
+
+INF = float("inf")
+
+
+def test_earliest_deadline_first(S):
+    s = Sched(S, 1 << 20, 1 << 20, max_active=1, max_pending=100)
+    for i, dl in zip((1, 2, 3, 4), (30.0, 10.0, INF, 20.0)):
+        assert s.enqueue_dl(i, i, 2, dl, 100) == 0
+    order = []
+    for _ in range(4):
+        adm, shed = s.admit_dl(0.0, 0.0, 0.0)
+        assert shed == [] and len(adm) == 1
+        order += adm
+        s.next()
+        s.next()
+        s.advance()
+        s.next()
+        for f in s.advance():
+            assert S.sched_release(s.h, f) == 1
+    assert order == [2, 4, 1, 3]   # by deadline; no deadline last
+    s.close()
+
+
+def test_shed_requests_that_cannot_finish_even_alone(S):
+    """A request whose M iterations (plus the one in flight) at its own load
+    end after its deadline is shed; one that fits is admitted; a request
+    already past its deadline is shed even with no time model."""
+    s = Sched(S, 1 << 20, 1 << 20, max_active=8, max_pending=100)
+    assert s.enqueue_dl(1, 0, 10, 15.0, 100) == 0     # (10 + 1) x 2 ms = 22 > 15
+    assert s.enqueue_dl(2, 1, 10, 25.0, 100) == 0     # 22 <= 25
+    adm, shed = s.admit_dl(0.0, 2.0, 0.0)
+    assert shed == [1] and adm == [2]
+    assert s.enqueue_dl(3, 2, 1, 5.0, 100) == 0
+    adm, shed = s.admit_dl(6.0, 0.0, 0.0)            # zero model: only past deadlines shed
+    assert shed == [3] and adm == []
+    s.close()
+
+
+def test_admission_keeps_active_requests_on_time(S):
+    """Admitting a large request would stretch every packed iteration and make
+    an active request late: it waits (and nothing overtakes it) until the
+    active one has finished, then it is admitted."""
+    s = Sched(S, 1 << 20, 1 << 20, max_active=8, max_pending=100)
+    base, slope = 1.0, 0.01                           # T(W) = 1 + 0.01 W ms
+    assert s.enqueue_dl(1, 0, 5, 30.0, 100) == 0      # alone: 6 x 2 = 12 <= 30
+    assert s.admit_dl(0.0, base, slope) == ([1], [])
+    assert s.enqueue_dl(2, 1, 5, 100.0, 1000) == 0    # with 1: T = 12, 1 would end at 72 > 30
+    assert s.enqueue_dl(3, 2, 1, 200.0, 10) == 0      # later deadline: must not overtake 2
+    assert s.admit_dl(0.0, base, slope) == ([], [])
+    for _ in range(5):
+        s.next()
+        fin = s.advance()
+    assert fin == [1]
+    assert S.sched_release(s.h, 1) == 1
+    adm, shed = s.admit_dl(10.0, base, slope)         # 2 alone: 10 + 6 x 11 = 76 <= 100
+    assert shed == [] and adm == [2, 3]
+    s.close()
+
+
+def test_deadlines_keep_per_cell_order(S):
+    """A cell's later request with an earlier deadline still waits for the
+    cell's earlier one."""
+    s = Sched(S, 1 << 20, 1 << 20, max_active=8, max_pending=100)
+    assert s.enqueue_dl(1, 4, 1, 50.0, 10) == 0
+    assert s.enqueue_dl(2, 4, 1, 10.0, 10) == 0
+    assert s.enqueue_dl(3, 5, 1, 20.0, 10) == 0
+    assert s.admit_dl(0.0, 0.0, 0.0) == ([3, 1], [])
+    s.next()
+    assert sorted(s.advance()) == [1, 3]
+    assert s.admit_dl(0.0, 0.0, 0.0) == ([2], [])
+    s.close()
+
+
+def test_random_deadline_workload_predictions_hold(S):
+    """Random arrivals against a server whose iterations take exactly the
+    model's time: every admitted request finishes by its deadline (the
+    admission test is exact for that model), every request is either
+    finished or shed, and shedding happens only to requests that could not
+    finish in time even alone at the moment they were shed."""
+    rng = np.random.default_rng(3)
+    base, slope = 0.5, 0.002
+    s = Sched(S, 1 << 24, 1 << 24, max_active=16, max_pending=10000)
+    t, nid = 0.0, 1
+    info = {}
+    active_work = {}
+    finished, shed_all = {}, set()
+    for step in range(600):
+        for _ in range(rng.poisson(0.6)):
+            M, work = int(rng.integers(1, 6)), float(rng.integers(50, 800))
+            dl = t + float(rng.uniform(5.0, 40.0))
+            assert s.enqueue_dl(nid, int(rng.integers(0, 40)), M, dl, work) == 0
+            info[nid] = (M, work, dl)
+            nid += 1
+        adm, shed = s.admit_dl(t, base, slope)
+        for i in shed:
+            M, work, dl = info[i]
+            assert t + (M + 1) * (base + slope * work) > dl
+            shed_all.add(i)
+        for i in adm:
+            active_work[i] = info[i][1]
+        act, _ = s.next()
+        W = sum(active_work[i] for i, _ in act)
+        if act:
+            t += base + slope * W      # the iteration takes the model's time
+        else:
+            t += 0.5
+        for i in s.advance():
+            finished[i] = t
+            active_work.pop(i)
+            assert S.sched_release(s.h, i) == 1
+    for i, tf in finished.items():
+        # the in-flight iteration the admission budgets for is not simulated
+        # here, so every finish is strictly within the deadline
+        assert tf <= info[i][2] + 1e-9, (i, tf, info[i])
+    assert len(finished) > 100 and len(shed_all) > 0
     s.close()
