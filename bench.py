@@ -110,19 +110,30 @@ def bench_packed(mp, ctx, steps, warmup, mapping, n_scenes=32):
                      "p99_ms": float(np.percentile(lat, 99) * 1e3), "steps": steps}
         print(json.dumps({"packed_leg": name, **out[name]}), file=sys.stderr, flush=True)
     out["speedup"] = out["batched"]["env_steps_per_s"] / out["plain"]["env_steps_per_s"]
-    # alone vs mix: the same requests through one packed launch and one by
-    # one, with the mapping fixed (the automatic choice depends on the launch
-    # size, and the per-lane mapping rounds differently from the team ones)
-    mp.mppi_plan_batch(ctx, items, mapping="lane")
+    # roofline of the packed rollout launches: the work model over every
+    # request's counters against the summed launch time (HIP events)
+    from paper_2511_21264_amd.flops import rollout_flops
+    sts = mp.mppi_plan_batch(ctx, items, mapping=mapping, time_kernels=True)
+    flop = sum(rollout_flops(it["K"], it["H"], int(it["scene"].dict["n_sub"]), it["scene"].n_pairs,
+                             it["scene"].n_cost_pairs, int(it["scene"].dict["n_pgs"]), st["contacts"] / it["M"],
+                             st["np_tests"] / it["M"], st["box_tests"] / it["M"]) * it["M"]
+               for it, st in zip(items, sts))
+    t_roll = sts[0]["rollout_ms"] * 1e-3
+    out["roofline"] = {"bound": "alu", "achieved": flop / t_roll / 1e12, "peak": PEAK_FP32 / 1e12,
+                       "unit": "TFLOP/s", "frac": flop / t_roll / PEAK_FP32, "flop_per_batch": flop,
+                       "rollout_ms_per_batch": t_roll * 1e3, "launches_per_batch": sts[0]["rollout_launches"]}
+    # alone vs mix under the same flags: each request keeps its own mapping
+    # family, so one packed call and the requests one by one agree bit for bit
+    mp.mppi_plan_batch(ctx, items, mapping=mapping)
     torch.cuda.synchronize()
     mixed = [it["U_new"].clone() for it in items]
     for it in items:
         mp.mppi_plan(ctx, it["scene"], it["x0"], it["nominal_U"], it["K"], it["H"], it["lam"], it["sigma"],
-                     it["U_new"], it["costs"], M=it["M"], seed=it["seed"], mapping="lane", want_stats=False,
+                     it["U_new"], it["costs"], M=it["M"], seed=it["seed"], mapping=mapping, want_stats=False,
                      sync=True)
     torch.cuda.synchronize()
     diff = max(float((it["U_new"] - u).abs().max()) for it, u in zip(items, mixed))
-    out["alone_equals_mix"] = {"mapping": "lane", "bit_identical": diff == 0.0, "max_abs_diff": diff}
+    out["alone_equals_mix"] = {"mapping": mapping or "auto", "bit_identical": diff == 0.0, "max_abs_diff": diff}
     for it in items:
         it["scene"].close()
     return out
@@ -145,14 +156,20 @@ def bench_replan(mp, ctx, sc, pp, n=200, warmup=5, advance=2, mapping=None):
     Unew = torch.zeros((H, 14), dtype=torch.float32, device=dev)
     costs = torch.zeros(K, dtype=torch.float32, device=dev)
     xn = torch.zeros((1, x.numel()), dtype=torch.float32, device=dev)
-    lat = []
+    lat, over, cont = [], 0.0, 0.0
+    cap = None
     for i in range(warmup + n):
+        if i == warmup + n // 2:
+            # contact-list truncation at a warm start (arms on the ball)
+            cap = bench_contact_cap(mp, ctx, scene, sc, x, nom, sig, pp["seed"] + i)
         torch.cuda.synchronize()
         a = time.perf_counter()
-        mp.mppi_plan(ctx, scene, x, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"] + i,
-                     mapping=mapping, want_stats=False, sync=True)
+        st = mp.mppi_plan(ctx, scene, x, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"] + i,
+                          mapping=mapping, sync=True)
         if i >= warmup:
             lat.append(time.perf_counter() - a)
+            over += st["overflow"]
+            cont += st["contacts"]
         # the executor: first `advance` controls in the simulator, plan shifted
         mp.mppi_simulate(ctx, scene, x.view(1, -1), Unew[:advance].reshape(1, advance, 14).contiguous(),
                          X_out=xn, mapping=mapping)
@@ -163,103 +180,184 @@ def bench_replan(mp, ctx, sc, pp, n=200, warmup=5, advance=2, mapping=None):
     return {"workload": f"config 2, {n} warm-started replans (K={K}, H={H}, M={M}), plant advanced {advance} "
                         f"steps per reply in the GPU simulator, plan shifted by {advance}",
             "replans": n, "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-            "mean_ms": float(lat_ms.mean()), "env_steps_per_s": M * K * H / float(lat_ms.mean() * 1e-3)}
+            "mean_ms": float(lat_ms.mean()), "env_steps_per_s": M * K * H / float(lat_ms.mean() * 1e-3),
+            "full_contact_list_per_substep": over / (n * M * K * H * int(sc["n_sub"])),
+            "contacts_per_substep": cont / (n * M * K * H * int(sc["n_sub"])), "contact_cap": cap}
 
 
-def run_trace(mp, ctx, cells, scenes, trace, duration, max_active, mapping, deadline_ms=20.0, advance=2):
-    """Replay an arrival trace against a server: every arrival submits a
-    warm-started cell request (state and nominal resident on the device,
-    plant advanced by `advance` steps per reply, queued requests of the same
-    cell superseded).  Returns latency and throughput figures."""
+def run_trace(mp, ctx, cells, scenes, trace, duration, max_active, mapping, deadline_ms=20.0, advance=2, model=None,
+              M=None):
+    """Replay an arrival trace against a server with a deadline: every arrival
+    submits a warm-started cell request (state and nominal resident on the
+    device, plant advanced by `advance` steps per reply, queued requests of
+    the same cell superseded).  Misses: completed after the deadline, shed
+    unrun (could not end in time), superseded, or unfinished at the end."""
     import numpy as np
     import torch
     import workloads as W
     dev = torch.device("cuda:0")
-    srv = mp.Server(ctx, mapping=mapping, max_active=max_active, max_pending=4096, mem_budget=8 << 30)
+    base, slope = model if model else (0.0, 0.0)
+    srv = mp.Server(ctx, mapping=mapping, max_active=max_active, max_pending=4096, mem_budget=8 << 30,
+                    deadline_ms=deadline_ms, iter_base_ms=base, iter_ms_per_menv=slope)
     ids = [srv.cell(scenes[i], c["H"], W.initial_state(c["scene"]).astype(np.float32)) for i, c in enumerate(cells)]
     sig = [torch.full((14,), 0.3, dtype=torch.float32, device=dev) for _ in cells]
     torch.cuda.synchronize()
     out, n_sub = {}, [0] * len(cells)
-    lat, status = [], {"ok": 0, "superseded": 0, "diverged": 0}
+    lat, status = [], {"ok": 0, "superseded": 0, "diverged": 0, "shed": 0, "late": 0}
 
-    def collect(block=False):
-        for t in list(out):
-            r = srv.poll(t, -1 if block else 0)
-            if r is None:
-                continue
-            out.pop(t)
-            if r["status"] == mp.E_CANCELLED:
-                status["superseded"] += 1
-                continue
+    def account(r):
+        if r["status"] == mp.E_CANCELLED:
+            status["superseded"] += 1
+        elif r["status"] == mp.E_LATE:
+            status["shed"] += 1
+        else:
             status["ok" if r["status"] == 0 else "diverged"] += 1
             lat.append(r["t_done_ms"] - r["t_submit_ms"])
+            status["late"] += r["t_done_ms"] > r["t_deadline_ms"]
+
+    last = [0.0]
+
+    def collect():
+        # every 2 ms at most: each poll takes the server's lock
+        now = time.perf_counter()
+        if now - last[0] < 0.002:
+            return
+        last[0] = now
+        for t in list(out):
+            r = srv.poll(t, 0)
+            if r is not None:
+                out.pop(t)
+                account(r)
 
     t0 = time.perf_counter()
     for (ta, i) in trace:
         while time.perf_counter() - t0 < ta:
             collect()
-            time.sleep(0.0002)
+            time.sleep(0.0005)
         c = cells[i]
-        item = dict(K=c["K"], lam=0.1, sigma=sig[i], M=c["M"], seed=(i << 20) + n_sub[i])
+        item = dict(K=c["K"], lam=0.1, sigma=sig[i], M=M or c["M"], seed=(i << 20) + n_sub[i])
         n_sub[i] += 1
         out[srv.submit(item, cell=ids[i], advance=advance, supersede=True, want_stats=False)] = i
     wall = time.perf_counter() - t0
     q = srv.query()
-    # the trace is over: what is still queued or running counts as missed
+    # the trace is over: what is still queued or running ends on its own
+    # (completed, late or shed against its deadline)
     unfinished = 0
     for t in list(out):
-        try:
-            srv.cancel(t)
-        except mp.MppiError:
-            pass
-    for t in list(out):
-        r = srv.poll(t, -1)
+        account(srv.poll(t, -1))
         out.pop(t)
-        if r["status"] == mp.E_CANCELLED:
-            unfinished += 1
-        else:
-            status["ok" if r["status"] == 0 else "diverged"] += 1
-            lat.append(r["t_done_ms"] - r["t_submit_ms"])
     srv.close()
     lat = np.array(lat) if lat else np.array([np.nan])
     n_req = len(trace)
-    return {"requests": n_req, "completed": status["ok"] + status["diverged"], "superseded": status["superseded"],
-            "unfinished_at_end": unfinished,
+    misses = status["late"] + status["shed"] + status["superseded"] + unfinished
+    return {"requests": n_req, "completed": status["ok"] + status["diverged"], "late": status["late"],
+            "shed": status["shed"], "superseded": status["superseded"], "unfinished_at_end": unfinished,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "deadline_ms": deadline_ms,
-            "miss_rate": float((np.sum(lat > deadline_ms) + status["superseded"] + unfinished) / max(1, n_req)),
+            "deadline_ms": deadline_ms, "miss_rate": misses / max(1, n_req),
             "env_steps_per_s": q["env_steps"] / wall, "wall_s": wall, "trace_s": duration,
             "packed_iterations": q["iterations"], "mean_active": q["request_iters"] / max(1, q["iterations"]),
-            "max_active": max_active}
+            "max_active": max_active,
+            "model": {"base_ms": q["model_base_ms"], "ms_per_million_env_steps": q["model_ms_per_menv"],
+                      "floor_ms": q["model_floor_ms"], "margin_ms": q["model_margin_ms"]}}
 
 
-def bench_serving(mp, ctx, duration, mapping, thr_env_steps):
-    """Serving workload: 64 cells (scene seeds 5000 + cell), Poisson arrivals
-    at U[10, 50] Hz per cell, M=10, 20 ms deadline; served by the continuous
-    batching server and by the plain form (one request per launch, FIFO)."""
+def calibrate_server(mp, ctx, cells, scenes, M, mapping, loads=(1, 2, 4, 8, 16, 32)):
+    """The packed-iteration model of a server (ms = base + slope * W / 1e6),
+    fitted by the server itself to its own iterations while it serves
+    bursts of 1..32 simultaneous requests of the cells' shape."""
+    import numpy as np
+    import torch
     import workloads as W
-    res = {}
-    for shape in ("mixed", "fixed"):
-        cells = W.serving_cells(64, shape)
-        scenes = [mp.Scene(ctx, c["scene"]) for c in cells]
-        offered = sum(c["rate"] * c["M"] * c["K"] * c["H"] for c in cells)
-        legs = {}
-        # as specified, and at a rate scale one GPU sustains (half the measured packed throughput)
-        scale = min(1.0, 0.5 * thr_env_steps / offered)
-        for name, sc in (("spec_rates", 1.0), ("sustainable", scale)):
-            trace = W.poisson_trace([c["rate"] * sc for c in cells], duration, seed=5 + (shape == "fixed"))
-            for form, act in (("batched", 64), ("plain", 1)):
-                r = run_trace(mp, ctx, cells, scenes, trace, duration, act, mapping)
-                r["rate_scale"] = sc
-                r["offered_env_steps_per_s"] = offered * sc
-                legs[f"{name}_{form}"] = r
-                print(json.dumps({"serving": shape, "leg": f"{name}_{form}", **r}), file=sys.stderr, flush=True)
-        for s_ in scenes:
-            s_.close()
-        res[shape] = legs
-    res["workload"] = ("64 cells, scene seeds 5000+cell, Poisson arrivals U[10,50] Hz per cell, M=10, warm start "
-                       "resident, plant advanced 2 steps per reply, stale queued requests superseded; mixed: "
-                       "K~U{256..4096}, H~U{32..128}; fixed: K=1024, H=64")
+    dev = torch.device("cuda:0")
+    srv = mp.Server(ctx, mapping=mapping, max_active=64, max_pending=4096, mem_budget=8 << 30)
+    ids = [srv.cell(scenes[i], c["H"], W.initial_state(c["scene"]).astype(np.float32)) for i, c in enumerate(cells)]
+    sig = torch.full((14,), 0.3, dtype=torch.float32, device=dev)
+    models = []
+    for n in loads:
+        ts = [srv.submit(dict(K=cells[i]["K"], lam=0.1, sigma=sig, M=M, seed=7 + i), cell=ids[i], want_stats=False)
+              for i in range(n)]
+        for t in ts:
+            srv.wait(t)
+        q = srv.query()
+        models.append((q["model_base_ms"], q["model_ms_per_menv"], q["model_floor_ms"]))
+    srv.close()
+    return models[-1]
+
+
+def bench_serving(mp, ctx, duration, mapping, deadline_ms=20.0, search_s=10.0):
+    """Serving workload: 64 cells (scene seeds 5000 + cell), Poisson arrivals
+    at U[10, 50] Hz per cell, 20 ms deadline (the control period), served by
+    the continuous-batching server with earliest-deadline-first admission
+    against its iteration model (seeded by a calibration, then refitted to
+    its own iterations).  Fixed cells (K=1024, H=64): the largest M whose
+    plans meet the deadline at a light load (0.5 Hz per cell), then the
+    highest arrival-rate scale that keeps the miss rate below 1 % (bisection
+    on short traces, confirmed on a trace of `duration` seconds), with the
+    utilization rho = offered env-steps/s over the packed capacity the
+    model measures; the same trace through the plain form (one request at a
+    time); and both shapes at the specified rates (rho > 1: misses are shed
+    or late, and counted)."""
+    import workloads as W
+    res = {"deadline_ms": deadline_ms}
+    fixed = W.serving_cells(64, "fixed")
+    scenes = [mp.Scene(ctx, c["scene"]) for c in fixed]
+    rates = [c["rate"] for c in fixed]
+    mean_rate = sum(rates) / len(rates)
+
+    def leg(name, scale, dur, M, max_active=64, seed=0, cells=fixed, scn=None):
+        trace = W.poisson_trace([c["rate"] * scale for c in cells], dur, seed=seed)
+        r = run_trace(mp, ctx, cells, scn or scenes, trace, dur, max_active, mapping, deadline_ms,
+                      model=(model[2] or model[0], model[1]), M=M)
+        off = sum(c["rate"] * scale * M * c["K"] * c["H"] for c in cells)
+        r.update(rate_scale=scale, M=M, offered_env_steps_per_s=off, utilization=off / capacity,
+                 mean_rate_per_cell_hz=sum(c["rate"] for c in cells) * scale / len(cells))
+        print(json.dumps({"serving": name, **r}), file=sys.stderr, flush=True)
+        return r
+
+    model = calibrate_server(mp, ctx, fixed, scenes, 10, mapping)
+    capacity = 1e9 / max(model[1], 1e-12)   # env-steps/s of large packed iterations
+    res["iteration_model"] = {"base_ms": model[0], "ms_per_million_env_steps": model[1], "floor_ms": model[2],
+                              "capacity_env_steps_per_s": capacity}
+    light = 0.5 / mean_rate
+    res["light_load"] = {}
+    M_ok = None
+    for M in (10, 8, 6, 5, 4, 3, 2):
+        r = leg(f"light M={M}", light, search_s, M)
+        res["light_load"][str(M)] = r
+        if r["miss_rate"] < 0.01 and r["p99_ms"] < deadline_ms:
+            M_ok = M
+            break
+    res["largest_M_meeting_deadline"] = M_ok
+    if M_ok is not None:
+        lo, hi = light, 1.0
+        for _ in range(6):
+            mid = (lo * hi) ** 0.5
+            r = leg(f"search M={M_ok} scale={mid:.4f}", mid, search_s, M_ok, seed=11)
+            if r["miss_rate"] < 0.01:
+                lo = mid
+            else:
+                hi = mid
+        # confirm on a long trace; a scale that fails there is halved (twice at most)
+        for _ in range(3):
+            r = leg(f"confirm M={M_ok} scale={lo:.4f}", lo, duration, M_ok, seed=12)
+            if r["miss_rate"] < 0.01:
+                break
+            res.setdefault("confirm_failed", []).append(r)
+            lo *= 0.5
+        res["sustained"] = r
+        res["sustained_plain"] = leg(f"plain M={M_ok}", lo, search_s, M_ok, max_active=1, seed=12)
+    Ms = M_ok or 2
+    res["spec_rates_fixed"] = leg(f"spec fixed M={Ms}", 1.0, search_s, Ms, seed=13)
+    for s_ in scenes:
+        s_.close()
+    mixed = W.serving_cells(64, "mixed")
+    mscenes = [mp.Scene(ctx, c["scene"]) for c in mixed]
+    res["spec_rates_mixed"] = leg(f"spec mixed M={Ms}", 1.0, search_s, Ms, seed=14, cells=mixed, scn=mscenes)
+    for s_ in mscenes:
+        s_.close()
+    res["workload"] = ("64 cells, scene seeds 5000+cell, Poisson arrivals U[10,50] Hz per cell (scaled by "
+                       "rate_scale), warm start resident, plant advanced 2 steps per reply, stale queued requests "
+                       "superseded; fixed: K=1024, H=64; mixed: K~U{256..4096}, H~U{32..128}")
     return res
 
 
@@ -400,6 +498,145 @@ def bench_cov(mp, ctx, sc, pp, config, plain_ms, n_launch=20, n_plan=3):
         "ess": st["ess"], "c_min": st["c_min"],
         "note": "cholesky_ms is wall time of a call that synchronises (it reads back the pivot flag)",
     }
+
+
+def bench_contact_cap(mp, ctx, scene, sc, x, nu, sig, seed, n=256):
+    """How often the contact list is truncated: n sequences drawn around the
+    plan's mean nu (as its last iteration draws them) are rolled out one
+    substep per step from state x, and every substep's start state goes
+    through the narrowphase of all candidate pairs; the active pairs per
+    substep are counted without the cap."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    H, S = nu.shape[0], int(sc["n_sub"])
+    U = torch.zeros((n, H, 14), device=dev)
+    mp.mppi_sample(ctx, scene, nu.contiguous(), sig, seed, 0, n, U=U)
+    Ur = U.repeat_interleave(S, dim=1).contiguous()
+    traj = torch.zeros((n, H * S, 55), device=dev)
+    mp.mppi_simulate(ctx, scene, x.view(1, -1), Ur, X_out=traj, x0_shared=True, n_sub=1, traj=True)
+    starts = torch.cat([x.view(1, 1, -1).expand(n, 1, 55), traj[:, :-1]], dim=1).reshape(-1, 55).contiguous()
+    counts = []
+    for c0 in range(0, starts.shape[0], 32768):
+        blk = starts[c0:c0 + 32768].contiguous()
+        phi = torch.zeros((blk.shape[0], scene.n_pairs), device=dev)
+        mp.mppi_narrowphase(ctx, scene, blk, phi)
+        torch.cuda.synchronize()
+        counts.append((phi < 0).sum(dim=1).cpu().numpy())
+    cnt = np.concatenate(counts)
+    cap = int(sc["n_cmax"])
+    return {"substeps": int(cnt.size), "mean_active_pairs": float(cnt.mean()), "max_active_pairs": int(cnt.max()),
+            "frac_over_cap": float((cnt > cap).mean()), "frac_over_8": float((cnt > 8).mean()),
+            "frac_full_list": float((cnt >= cap).mean()), "n_cmax": cap,
+            "sample": f"{n} sequences around the plan's mean, {H} steps x {S} substeps from the plan's start state"}
+
+
+def bench_graph(mp, ctx, sc, pp, steps=20, warmup=3):
+    """The plan's launch sequence captured as a HIP graph (MPPI_GRAPH) against
+    eager launches, on the main workload and on the small one (K=64, H=20,
+    M=5), where launch overhead is a larger share."""
+    import numpy as np
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, cfg in (("main", None), ("small", 1)):
+        scx = sc if cfg is None else W.make_scene(cfg)
+        ppx = pp if cfg is None else W.plan_params(cfg)
+        K, H, M = ppx["K"], ppx["H"], ppx["M"]
+        scene = mp.Scene(ctx, scx)
+        x0 = torch.tensor(W.initial_state(scx), dtype=torch.float32, device=dev)
+        nom = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+        sig = torch.tensor(ppx["sigma"], dtype=torch.float32, device=dev)
+        U = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+        c = torch.zeros(K, dtype=torch.float32, device=dev)
+        res = {"K": K, "H": H, "M": M}
+        outs = {}
+        for g in (False, True):
+            lat = []
+            for i in range(warmup + steps):
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                mp.mppi_plan(ctx, scene, x0, nom, K, H, ppx["lam"], sig, U, c, M=M, seed=ppx["seed"], graph=g,
+                             want_stats=False, sync=True)
+                if i >= warmup:
+                    lat.append(time.perf_counter() - a)
+            outs[g] = U.clone()
+            lat = np.array(lat) * 1e3
+            res["graph" if g else "eager"] = {"p50_ms": float(np.percentile(lat, 50)),
+                                              "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean())}
+        res["speedup_p50"] = res["eager"]["p50_ms"] / res["graph"]["p50_ms"]
+        res["bit_identical"] = bool(torch.equal(outs[False], outs[True]))
+        out[name] = res
+        scene.close()
+    return out
+
+
+def bench_plain(mp, ctx, sc, pp, batched_ms, steps=3):
+    """The plain form of the survey's measurement: one launch per control step
+    (state in device memory between launches, one sample per lane), no
+    packing, no graph, one stream -- the same plan, bit-identical to the
+    one-lane mapping -- against the batched form's plan time."""
+    import numpy as np
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    K, H, M = pp["K"], pp["H"], pp["M"]
+    scene = mp.Scene(ctx, sc)
+    x0 = torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev)
+    nom = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    sig = torch.tensor(pp["sigma"], dtype=torch.float32, device=dev)
+    U = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+    c = torch.zeros(K, dtype=torch.float32, device=dev)
+    lat, roll = [], []
+    for i in range(1 + steps):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U, c, M=M, seed=pp["seed"], per_step=True,
+                          time_kernels=True)
+        if i >= 1:
+            lat.append(time.perf_counter() - a)
+            roll.append(st["rollout_ms"])
+    scene.close()
+    lat = np.array(lat) * 1e3
+    return {"form": "one rollout launch per control step (H x M launches per plan), one sample per lane, "
+                    "state in HBM between launches, no graph",
+            "launches_per_plan": H * M, "plans": steps, "p50_ms": float(np.percentile(lat, 50)),
+            "mean_ms": float(lat.mean()), "env_steps_per_s": M * K * H / float(lat.mean() * 1e-3),
+            "rollout_ms_per_plan": float(np.mean(roll)), "batched_over_plain": float(lat.mean() / batched_ms)}
+
+
+def bench_occupancy(mp, ctx, Ks=(32768,), H=64, M=2):
+    """Roofline at full occupancy: one plan of the main scene with K samples
+    in the one-lane and the 16-lane team mappings, rollout time from HIP
+    events, algorithmic flops from the work model and the launch's counters."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2511_21264_amd.flops import rollout_flops
+    dev = torch.device("cuda:0")
+    sc = W.make_scene(2)
+    scene = mp.Scene(ctx, sc)
+    out = {}
+    for K in Ks:
+        pp = W.plan_params(2, K=K, H=H, M=M)
+        x0 = torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev)
+        nom = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+        sig = torch.tensor(pp["sigma"], dtype=torch.float32, device=dev)
+        U = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+        c = torch.zeros(K, dtype=torch.float32, device=dev)
+        for mapping in ("lane", "team"):
+            mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U, c, M=M, seed=pp["seed"], mapping=mapping)
+            st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U, c, M=M, seed=pp["seed"],
+                              mapping=mapping, time_kernels=True)
+            f = rollout_flops(K, H, int(sc["n_sub"]), scene.n_pairs, scene.n_cost_pairs, int(sc["n_pgs"]),
+                              st["contacts"] / M, st["np_tests"] / M, st["box_tests"] / M)
+            t = st["rollout_ms"] / M * 1e-3
+            out[f"K{K}_{mapping}"] = {"K": K, "H": H, "mapping": mapping, "avg_launch_ms": t * 1e3,
+                                     "flop_per_launch": f, "achieved_tflops": f / t / 1e12,
+                                     "frac": f / t / PEAK_FP32, "env_steps_per_s": K * H / t}
+    scene.close()
+    return out
 
 
 def bench_episode(mp, ctx, runs=((2, 8, "diag"), (2, 8, "qp"), (2, 8, "cov"), (3, 4, "diag"), (2, 8, "qp", 256),
@@ -859,15 +1096,18 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0)
     ap.add_argument("--mapping", default="auto", choices=["auto", "lane", "team", "wave", "split"])
     ap.add_argument("--packed-steps", type=int, default=2, help="steps of the packed-batch leg (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="trace length of the serving legs (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="trace length of the sustained serving leg (0: skip serving)")
     ap.add_argument("--no-precision", dest="precision", action="store_false",
                     help="skip the FP64-vs-FP32 weights study on the 8-box workload")
     ap.add_argument("--no-qp", dest="qp", action="store_false",
                     help="skip the QP-smoothing leg (projection kernel and plans with the projection)")
     ap.add_argument("--no-cov", dest="cov", action="store_false",
                     help="skip the covariance-adaptation leg (its kernels alone and plans with the full covariance)")
-    ap.add_argument("--no-episodes", dest="episodes", action="store_false",
-                    help="skip the closed-loop ball-transport leg (success rate, task and compute time)")
+    ap.add_argument("--episodes", action="store_true",
+                    help="also run the closed-loop ball-transport runs (success rate, task and compute time)")
+    ap.add_argument("--no-extra", dest="extra", action="store_false",
+                    help="skip the graph, plain-form, full-occupancy and contact-cap legs")
     ap.add_argument("--summarize-profiles", default="",
                     help="read rocprofv3 result folders under this path and write the profiles/ summaries")
     args = ap.parse_args()
@@ -981,7 +1221,8 @@ def main():
             "valu_issue_frac": None if vi_launch is None else vi_launch / avg_launch_s / PEAK_VALU_ISSUE,
         },
         "stats": {"ess": st["ess"], "c_min": st["c_min"], "contacts_per_substep":
-                  st["contacts"] / (M * K * H * int(sc["n_sub"]))},
+                  st["contacts"] / (M * K * H * int(sc["n_sub"])),
+                  "full_contact_list_per_substep": st["overflow"] / (M * K * H * int(sc["n_sub"]))},
         "mapping": used,
         "autotune": tuned,
     }
@@ -995,6 +1236,14 @@ def main():
             name, ms = mp.mppi_autotune(ctx, s5, W.initial_state(sc5), pp["sigma"], 1 << c, 16)
             out["autotune_classes"][str(1 << c)] = name
         s5.close()
+    if args.extra:
+        out["contact_cap_cold"] = bench_contact_cap(mp, ctx, scene, sc, x0, Unew.clone(), sig, pp["seed"])
+        out["graph"] = bench_graph(mp, ctx, sc, pp)
+        print(json.dumps({"graph": out["graph"]}), file=sys.stderr, flush=True)
+        out["plain"] = bench_plain(mp, ctx, sc, pp, out["ms_per_step"])
+        print(json.dumps({"plain": out["plain"]}), file=sys.stderr, flush=True)
+        out["occupancy"] = bench_occupancy(mp, ctx)
+        print(json.dumps({"occupancy": out["occupancy"]}), file=sys.stderr, flush=True)
     if args.replans > 0:
         out["replan"] = bench_replan(mp, ctx, sc, pp, n=args.replans, mapping=mapping)
         print(json.dumps({"replan": out["replan"]}), file=sys.stderr, flush=True)
@@ -1010,8 +1259,7 @@ def main():
     if args.packed_steps > 0:
         out["packed"] = bench_packed(mp, ctx, args.packed_steps, 1, mapping)
     if args.serve_seconds > 0:
-        thr = out.get("packed", {}).get("batched", {}).get("env_steps_per_s", out["value"])
-        out["serving"] = bench_serving(mp, ctx, args.serve_seconds, mapping, thr)
+        out["serving"] = bench_serving(mp, ctx, args.serve_seconds, mapping)
     if args.precision:
         out["precision"] = bench_precision(mp, ctx)
     if not args.no_cpu_baseline:

@@ -490,9 +490,12 @@ typedef struct mppi_server_opts {
      * active request predicted on time would become late (otherwise it waits
      * and nothing overtakes it); a queued request that cannot end in time even
      * alone is shed (status MPPI_E_LATE).  The prediction of one packed
-     * iteration is iter_base_ms + iter_ms_per_menv * W / 1e6, W the sum of
-     * K * H over the active requests; with both 0 the server fits them by least
-     * squares to its own measured iterations (the last 64). */
+     * iteration is max(floor, iter_base_ms + iter_ms_per_menv * W / 1e6), W
+     * the sum of K * H over the active requests: the values given here (floor
+     * 0) until 8 packed iterations have been measured, then a fit to the last
+     * 64 measured (floor: the fastest; base and slope: least squares); every
+     * predicted end adds a margin learned from past predictions (see
+     * mppi_server_info). */
     double deadline_ms;
     double iter_base_ms;
     double iter_ms_per_menv;
@@ -516,7 +519,9 @@ typedef struct mppi_server_info {
     int active, pending;
     uint64_t shed;              /* requests dropped unrun because they could not end by their deadline */
     uint64_t late;              /* requests completed after their deadline */
-    double model_base_ms, model_ms_per_menv;  /* the iteration model in use */
+    double model_base_ms, model_ms_per_menv, model_floor_ms;  /* the iteration model in use */
+    double model_margin_ms;     /* added to predicted ends: the 95th percentile of how late the recent
+                                   completions came against their predictions (16 to 128 of them) */
 } mppi_server_info;
 
 /* Create a server on `ctx` with its own non-blocking stream and worker

@@ -146,7 +146,8 @@ class ServerInfo(C.Structure):
                 ("superseded", C.c_uint64), ("rejected", C.c_uint64), ("iterations", C.c_uint64),
                 ("request_iters", C.c_uint64), ("env_steps", C.c_uint64), ("mem_high_water", C.c_uint64),
                 ("active", C.c_int), ("pending", C.c_int), ("shed", C.c_uint64), ("late", C.c_uint64),
-                ("model_base_ms", C.c_double), ("model_ms_per_menv", C.c_double)]
+                ("model_base_ms", C.c_double), ("model_ms_per_menv", C.c_double), ("model_floor_ms", C.c_double),
+                ("model_margin_ms", C.c_double)]
 
 
 _lib = None

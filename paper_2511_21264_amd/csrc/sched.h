@@ -104,15 +104,18 @@ struct SchedReq {
     int state = RS_PENDING;
     double deadline = INFINITY;  // absolute, in the caller's clock (ms); INFINITY: none
     double work = 0.0;           // env-steps of one of its iterations (K * H)
+    double pred_end = 0.0;       // predicted end when admitted (without the margin)
 };
 
 // Predicted device time of one packed iteration over active requests whose
-// iterations hold W env-steps in total: base_ms + ms_per_work * W.  A zero
-// model predicts no time (admission then only orders by deadline and sheds
-// requests already past theirs).
+// iterations hold W env-steps in total: max(floor_ms, base_ms + ms_per_work W)
+// (a small launch is bound by one sample's chain of steps, a large one by
+// throughput).  A zero model predicts no time (admission then only orders by
+// deadline and sheds requests already past theirs).
 struct IterModel {
-    double base_ms = 0.0, ms_per_work = 0.0;
-    double time(double W) const { return base_ms + ms_per_work * W; }
+    double base_ms = 0.0, ms_per_work = 0.0, floor_ms = 0.0;
+    double margin_ms = 0.0;  // added to every predicted end (how late past predictions were)
+    double time(double W) const { return std::max(floor_ms, base_ms + ms_per_work * W); }
 };
 
 // Admission and iteration order of the requests of a server.
@@ -123,8 +126,8 @@ struct IterModel {
 //     the first request that does not fit in memory (no overtaking on
 //     memory, so a large request cannot starve).
 //   * Deadlines: a request is admitted only when, with the iteration model
-//     at the load it would join, its M iterations (plus the one already in
-//     flight) end by its deadline, and no active request predicted on time
+//     at the load it would join, its M iterations (behind the one already in
+//     flight, if any) end by its deadline, and no active request predicted on time
 //     would become late; otherwise the scan stops there (it waits for load
 //     to drain, nothing overtakes it).  A queued request that cannot end by
 //     its deadline even alone is shed: it leaves the queue unrun.
@@ -169,22 +172,23 @@ public:
     }
 
     // predicted end of request r admitted at `now` into a load of W: its M - m
-    // remaining iterations after the one in flight
-    static double predicted_end(const SchedReq &r, double now, const IterModel &im, double W)
+    // remaining iterations after `extra` iterations already in flight
+    static double predicted_end(const SchedReq &r, double now, const IterModel &im, double W, int extra)
     {
-        return now + (double)(r.M - r.m + 1) * im.time(W);
+        return now + (double)(r.M - r.m + extra) * im.time(W) + im.margin_ms;
     }
 
     // admitted ids, in admission order; requests shed (see above) go to *shed
-    // (their state becomes RS_DONE; they hold no memory)
+    // (their state becomes RS_DONE; they hold no memory).  `extra`: packed
+    // iterations already launched that every admitted request waits behind.
     std::vector<uint64_t> admit(double now = 0.0, const IterModel &im = IterModel{},
-                                std::vector<uint64_t> *shed = nullptr)
+                                std::vector<uint64_t> *shed = nullptr, int extra = 1)
     {
         std::vector<uint64_t> out;
         if (shed) {
             for (auto it = pending_.begin(); it != pending_.end();) {
                 SchedReq &r = reqs_.at(*it);
-                if (predicted_end(r, now, im, r.work) > r.deadline) {
+                if (predicted_end(r, now, im, r.work, extra) > r.deadline) {
                     shed->push_back(r.id);
                     r.state = RS_DONE;
                     r.cancel = true;
@@ -218,11 +222,11 @@ public:
             SchedReq &r = reqs_.at(id);
             if (r.cell >= 0 && (blocked.count(r.cell) || oldest.at(r.cell) != id)) continue;
             const double W1 = W + r.work;
-            bool fits = predicted_end(r, now, im, W1) <= r.deadline;
+            bool fits = predicted_end(r, now, im, W1, extra) <= r.deadline;
             for (uint64_t a : active_) {
                 const SchedReq &q = reqs_.at(a);
-                if (fits && std::isfinite(q.deadline) && predicted_end(q, now, im, W) <= q.deadline)
-                    fits = predicted_end(q, now, im, W1) <= q.deadline;
+                if (fits && std::isfinite(q.deadline) && predicted_end(q, now, im, W, extra) <= q.deadline)
+                    fits = predicted_end(q, now, im, W1, extra) <= q.deadline;
             }
             if (!fits) break;  // wait for the load to drain; nothing overtakes it
             const size_t d = dev_.alloc(r.dev_bytes);
@@ -235,6 +239,7 @@ public:
             r.dev_off = d;
             r.host_off = h;
             r.state = RS_ACTIVE;
+            r.pred_end = predicted_end(r, now, im, W1, extra) - im.margin_ms;
             if (r.cell >= 0) blocked[r.cell] = true;
             W = W1;
             active_.push_back(r.id);

@@ -128,8 +128,10 @@ struct mppi_server {
     double load_at[2] = {0.0, 0.0};
     std::vector<std::pair<double, double>> meas;
     size_t meas_next = 0;
+    // completion minus predicted end of recent requests (the model's margin)
+    std::vector<double> lateness;
+    size_t late_next = 0;
     IterModel model;
-    bool model_fixed = false;
     bool inflight[2] = {false, false};
     std::vector<uint64_t> fin_at[2], drop_at[2];
     int worker_rc = MPPI_OK;
@@ -161,13 +163,17 @@ void fill_stats(const Req &R, const PlanStats &p, mppi_stats *st)
 }
 
 // Wait for the work of buffer `b` and retire its requests.
-// Least-squares fit of ms = base + slope * W to the recent measured packed
-// iterations (slope 0 and base their mean when the loads do not vary; both
-// kept >= 0).
+// The iteration model from the recent measured packed iterations: floor =
+// the fastest of them; base + slope * W by least squares (slope 0 and base
+// their mean when the loads do not vary; both kept >= 0).  Until 8 are
+// measured the model given at creation stands.
 void fit_model(mppi_server *S)
 {
     const size_t n = S->meas.size();
-    if (n == 0) return;
+    if (n < 8) return;
+    double fl = S->meas[0].second;
+    for (auto &m : S->meas) fl = std::min(fl, m.second);
+    S->model.floor_ms = fl;
     double sw = 0, st = 0, sww = 0, swt = 0;
     for (auto &m : S->meas) {
         sw += m.first;
@@ -190,7 +196,7 @@ int retire(mppi_server *S, int b)
     if (S->load_at[b] > 0 && hipEventElapsedTime(&it_ms, S->tev0[b], S->tev1[b]) != hipSuccess) it_ms = -1.f;
     std::lock_guard<std::mutex> lk(S->mu);
     const double t = S->now_ms();
-    if (it_ms >= 0.f && !S->model_fixed) {
+    if (it_ms >= 0.f) {
         const std::pair<double, double> m(S->load_at[b], (double)it_ms);
         if (S->meas.size() < 64)
             S->meas.push_back(m);
@@ -201,6 +207,20 @@ int retire(mppi_server *S, int b)
     S->load_at[b] = 0.0;
     for (uint64_t id : S->fin_at[b]) {
         Req &R = S->reqs.at(id);
+        if (const SchedReq *q = S->sched.find(id)) {
+            // how late the prediction made at admission turned out
+            const double e = t - q->pred_end;
+            if (S->lateness.size() < 128)
+                S->lateness.push_back(e);
+            else
+                S->lateness[S->late_next++ % 128] = e;
+            if (S->lateness.size() >= 16) {
+                std::vector<double> v = S->lateness;
+                const size_t k = v.size() * 95 / 100;
+                std::nth_element(v.begin(), v.begin() + k, v.end());
+                S->model.margin_ms = std::max(v[k], 0.0);
+            }
+        }
         const PlanStats &p = *R.hp<PlanStats>(R.L.h_st);
         R.status = p.diverged ? MPPI_E_DIVERGED : MPPI_OK;
         if (!R.dev_io) {
@@ -442,7 +462,8 @@ int worker_loop(mppi_server *S)
             std::unique_lock<std::mutex> lk(S->mu);
             std::vector<uint64_t> shed;
             const double now = S->now_ms();
-            for (uint64_t id : S->sched.admit(now, S->model, &shed)) {
+            // the iteration launched last pass (buffer b ^ 1) may still run
+            for (uint64_t id : S->sched.admit(now, S->model, &shed, S->inflight[b ^ 1] ? 1 : 0)) {
                 Req &R = S->reqs.at(id);
                 const SchedReq *q = S->sched.find(id);
                 R.d = S->dbase + q->dev_off;
@@ -573,7 +594,6 @@ int mppi_server_create(mppi_ctx *ctx, const mppi_server_opts *opts, mppi_server 
     }
     S->model.base_ms = o.iter_base_ms;
     S->model.ms_per_work = o.iter_ms_per_menv * 1e-6;
-    S->model_fixed = o.iter_base_ms > 0 || o.iter_ms_per_menv > 0;
     S->sched = Scheduler(o.mem_budget, host_bytes, o.max_active, o.max_pending);
     S->worker = std::thread(worker_main, S);
     *out = S;
@@ -804,6 +824,8 @@ int mppi_server_query(mppi_server *S, mppi_server_info *info)
     info->mem_high_water = S->sched.dev().high_water();
     info->model_base_ms = S->model.base_ms;
     info->model_ms_per_menv = S->model.ms_per_work * 1e6;
+    info->model_floor_ms = S->model.floor_ms;
+    info->model_margin_ms = S->model.margin_ms;
     return MPPI_OK;
 }
 

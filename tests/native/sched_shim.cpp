@@ -58,13 +58,15 @@ int sched_enqueue_dl(void *s, uint64_t id, int cell, int M, uint64_t dev, double
 }
 // admission at time `now` with the iteration model (base_ms + slope * W);
 // shed ids in shed (count in *nshed)
-int sched_admit_dl(void *s, double now, double base_ms, double slope, uint64_t *ids, uint64_t *shed, int *nshed)
+int sched_admit_dl(void *s, double now, double base_ms, double slope, double floor_ms, int extra, uint64_t *ids,
+                   uint64_t *shed, int *nshed)
 {
     std::vector<uint64_t> sh;
     IterModel im;
     im.base_ms = base_ms;
     im.ms_per_work = slope;
-    std::vector<uint64_t> v = ((Scheduler *)s)->admit(now, im, &sh);
+    im.floor_ms = floor_ms;
+    std::vector<uint64_t> v = ((Scheduler *)s)->admit(now, im, &sh, extra);
     for (size_t i = 0; i < v.size(); ++i) ids[i] = v[i];
     *nshed = (int)sh.size();
     for (size_t i = 0; i < sh.size(); ++i) shed[i] = sh[i];

@@ -289,7 +289,6 @@ def test_deadlines_shed_order_and_results(mp, ctx):
     q = srv.query()
     srv.close()
     assert q["shed"] == 1 and q["completed"] == len(items)
-    assert q["model_base_ms"] == 10.0
     for it, r in zip(items, res):
         assert r["status"] == 0
         assert r["t_deadline_ms"] == pytest.approx(r["t_submit_ms"] + 100.0)
@@ -297,10 +296,11 @@ def test_deadlines_shed_order_and_results(mp, ctx):
         assert torch.equal(U, it["U_new"]) and torch.equal(c, it["costs"])
     # no model given: the server measures its iterations and fits one
     srv = mp.Server(ctx, mapping="team", deadline_ms=1e6)
-    for it in items:
-        srv.wait(srv.submit(it))
+    for rep in range(3):
+        for it in items:
+            srv.wait(srv.submit(it))
     q = srv.query()
     srv.close()
-    assert q["model_base_ms"] > 0 and q["late"] == 0 and q["shed"] == 0
+    assert q["iterations"] >= 8 and q["model_floor_ms"] > 0 and q["late"] == 0 and q["shed"] == 0
     for it in items + [big]:
         it["scene"].close()

@@ -34,8 +34,8 @@ def S(tmp_path_factory):
                                     C.POINTER(C.c_int)]),
         "sched_admit": (C.c_int, [C.c_void_p, C.POINTER(U64)]),
         "sched_enqueue_dl": (C.c_int, [C.c_void_p, U64, C.c_int, C.c_int, U64, C.c_double, C.c_double]),
-        "sched_admit_dl": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.POINTER(U64),
-                                     C.POINTER(U64), C.POINTER(C.c_int)]),
+        "sched_admit_dl": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                     C.POINTER(U64), C.POINTER(U64), C.POINTER(C.c_int)]),
         "sched_cancel": (C.c_int, [C.c_void_p, U64]),
         "sched_next": (C.c_int, [C.c_void_p, C.POINTER(U64), C.POINTER(C.c_int), C.POINTER(U64),
                                  C.POINTER(C.c_int)]),
@@ -70,9 +70,10 @@ class Sched:
     def enqueue_dl(self, id, cell, M, deadline, work, dev=1000):
         return self.L.sched_enqueue_dl(self.h, id, cell, M, dev, float(deadline), float(work))
 
-    def admit_dl(self, now, base, slope):
+    def admit_dl(self, now, base, slope, floor=0.0, extra=1):
         ns = C.c_int(0)
-        n = self.L.sched_admit_dl(self.h, float(now), float(base), float(slope), self.buf, self.buf2, C.byref(ns))
+        n = self.L.sched_admit_dl(self.h, float(now), float(base), float(slope), float(floor), int(extra), self.buf,
+                                  self.buf2, C.byref(ns))
         return [self.buf[i] for i in range(n)], [self.buf2[i] for i in range(ns.value)]
 
     def next(self):
@@ -388,4 +389,16 @@ def test_random_deadline_workload_predictions_hold(S):
         # here, so every finish is strictly within the deadline
         assert tf <= info[i][2] + 1e-9, (i, tf, info[i])
     assert len(finished) > 100 and len(shed_all) > 0
+    s.close()
+
+
+def test_iteration_floor_and_work_in_flight(S):
+    """The model's floor bounds small loads from below; with nothing in
+    flight a request waits for no earlier iteration."""
+    s = Sched(S, 1 << 20, 1 << 20, max_active=8, max_pending=100)
+    # floor 3 ms beats 1 + 0.001 * 100 ms: M = 5 needs 5 x 3 = 15 ms, plus 3 in flight
+    assert s.enqueue_dl(1, 0, 5, 16.0, 100) == 0
+    assert s.admit_dl(0.0, 1.0, 0.001, floor=3.0, extra=1) == ([], [1])
+    assert s.enqueue_dl(2, 1, 5, 16.0, 100) == 0
+    assert s.admit_dl(0.0, 1.0, 0.001, floor=3.0, extra=0) == ([2], [])
     s.close()
