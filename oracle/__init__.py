@@ -23,7 +23,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _BUILD = os.path.join(_HERE, "_build")
 _LIB_PATH = os.path.join(_BUILD, "liboracle.so")
-_SOURCES = ["philox.c", "model.c", "collide.c", "step.c", "cost.c", "plan.c"]
+_SOURCES = ["philox.c", "model.c", "collide.c", "object.c", "step.c", "cost.c", "plan.c"]
+NTERMS = 17
 
 MAXBOX = 16
 NX = 55
@@ -64,6 +65,11 @@ class OScene(C.Structure):
         ("w_goal", C.c_double), ("w_eo", C.c_double), ("w_l", C.c_double), ("w_yz", C.c_double),
         ("w_s", C.c_double), ("w_c", C.c_double), ("gamma", C.c_double), ("m_c", C.c_double),
         ("eps_frac", C.c_double),
+        ("obj_box", C.c_int), ("obj_h", C.c_double * 3),
+        ("ext", C.c_int), ("l_target", C.c_double), ("q_home", C.c_double * 14),
+        ("w_home", C.c_double), ("w_vert", C.c_double), ("w_relv", C.c_double), ("w_orot", C.c_double),
+        ("w_apos", C.c_double * 2), ("w_ax", C.c_double * 2), ("w_arot", C.c_double * 2),
+        ("apos", C.c_double * 6), ("ax_t", C.c_double * 2), ("arot", C.c_double * 8), ("orot", C.c_double * 4),
     ]
 
 
@@ -100,6 +106,19 @@ def make_oscene(sc: dict) -> OScene:
     s.gravcomp = int(sc["gravcomp"])
     s.n_pgs = int(sc["n_pgs"])
     s.n_cmax = int(sc["n_cmax"])
+    # the free object's shape and the further task-cost terms (defaults: a ball, terms off)
+    s.obj_box = int(sc.get("obj_box", 0))
+    _fill(s.obj_h, sc.get("obj_h", (0.0, 0.0, 0.0)))
+    s.ext = int(sc.get("ext", 0))
+    s.l_target = float(sc.get("l_target", 0.0))
+    _fill(s.q_home, sc.get("q_home", np.zeros(14)))
+    for k in ("w_home", "w_vert", "w_relv", "w_orot"):
+        setattr(s, k, float(sc.get(k, 0.0)))
+    for k in ("w_apos", "w_ax", "w_arot", "ax_t"):
+        _fill(getattr(s, k), sc.get(k, (0.0, 0.0)))
+    _fill(s.apos, sc.get("apos", np.zeros((2, 3))))
+    _fill(s.arot, sc.get("arot", ((1.0, 0, 0, 0), (1.0, 0, 0, 0))))
+    _fill(s.orot, sc.get("orot", (1.0, 0, 0, 0)))
     return s
 
 
@@ -139,6 +158,9 @@ def lib():
             "oracle_tangents": (None, [_D, _D, _D]),
             "oracle_lcp": (C.c_int, [_S, _D, _D, _D, _D, _D, _D]),
             "oracle_point_jac": (None, [_S, _D, C.c_int, _D, _D]),
+            "oracle_obj_prim": (None, [_S, _D, C.c_int, _D, _D, C.c_double, _D]),
+            "oracle_quat_R": (None, [_D, _D, _D]),
+            "oracle_ext_terms": (None, [_S, _D, _D]),
             "oracle_rollout": (C.c_double, [_S, _D, _D, C.c_int, C.c_void_p, C.c_void_p]),
             "oracle_stage_terms": (None, [_S, _D, _D]),
             "oracle_cost_dist": (None, [_S, _D, _D]),
@@ -316,10 +338,33 @@ class Oracle:
         self.L.oracle_cost_dist(self.ps, _d(x), d)
         return d[:n]
 
+    def obj_prim(self, xo, tb, B0, B1=None, rb=0.0):
+        """The box object (state xo: centre, quaternion) against a primitive of
+        type tb (0 sphere, 1 capsule, 2 plane, 3 axis-aligned box): phi, n, p."""
+        out = np.zeros(7)
+        B1 = B0 if B1 is None else B1
+        self.L.oracle_obj_prim(self.ps, _d(xo), int(tb), _d(B0), _d(B1), float(rb), out)
+        return out[0], out[1:4], out[4:7]
+
+    def ext_terms(self, x):
+        """The further task-cost terms 7..16 at state x (term 9 as its squared
+        summand ((p1 - p2) . (p1' - p2'))^2)."""
+        t = np.zeros(10)
+        self.L.oracle_ext_terms(self.ps, _d(x), t)
+        return t
+
+    @staticmethod
+    def quat_R(q):
+        """Rotation matrix of a unit quaternion (w, x, y, z), and the quaternion
+        recovered from it."""
+        R, qb = np.zeros(9), np.zeros(4)
+        lib().oracle_quat_R(_d(q), R, qb)
+        return R.reshape(3, 3), qb
+
     def rollout(self, x0, U, want_traj=False):
         U = _d(U)
         H = U.shape[0]
-        terms = np.zeros(7)
+        terms = np.zeros(NTERMS)
         traj = np.zeros((H, NX)) if want_traj else None
         c = self.L.oracle_rollout(self.ps, _d(x0), U, H,
                                   traj.ctypes.data_as(C.c_void_p) if want_traj else None,

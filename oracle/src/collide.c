@@ -5,11 +5,12 @@
  * distances d_k between the manipulators and the environment (and between
  * the two manipulators); its world model (MuJoCo) also produces contacts.
  * Geometry readings: arm links 1..6 are capsules (segment from joint i to
- * joint i+1), link 7 carries a spherical pad at its tip, the ball is a
- * sphere, obstacles are static axis-aligned boxes, the table is the plane
- * z = 0.  Every pair yields at most one contact: signed distance phi,
- * unit normal n pointing from geom B to geom A, and point p midway between
- * the two closest surface points.
+ * joint i+1), link 7 carries a spherical pad at its tip, the free object is
+ * a sphere (the ball) or a box (the tray, the cube; object.c), obstacles are
+ * static axis-aligned boxes, the table is the plane z = 0.  Every pair
+ * yields at most one contact (a box object on the table up to four):
+ * signed distance phi, unit normal n pointing from geom B to geom A, and
+ * point p midway between the two closest surface points.
  *
  * Canonical pair order (also the contact order and the order in which the
  * contact cap truncates):
@@ -24,7 +25,7 @@
 #include <string.h>
 #include "oracle.h"
 
-enum { SH_SPHERE = 0, SH_CAPSULE = 1, SH_PLANE = 2, SH_BOX = 3 };
+enum { SH_SPHERE = 0, SH_CAPSULE = 1, SH_PLANE = 2, SH_BOX = 3, SH_OBOX = 4 };
 
 static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 static double clamp01(double t) { return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t); }
@@ -52,10 +53,16 @@ void or_pair(const OScene *s, int idx, int *ga, int *gb)
     *gb = OG_ARM + 7 + idx % 7;
 }
 
+/* pball points at the object's state: centre, then quaternion */
 void or_geom_shape(const OScene *s, const OArmKin kin[2], const double *pball, int gid, int *type, double P0[3],
                    double P1[3], double *r)
 {
-    if (gid == OG_BALL) {
+    if (gid == OG_BALL && s->obj_box) {
+        *type = SH_OBOX;
+        memcpy(P0, pball, 3 * sizeof(double));
+        memcpy(P1, s->obj_h, 3 * sizeof(double));
+        *r = 0.0;
+    } else if (gid == OG_BALL) {
         *type = SH_SPHERE;
         memcpy(P0, pball, 3 * sizeof(double));
         memcpy(P1, pball, 3 * sizeof(double));
@@ -92,10 +99,16 @@ void or_aabb(const OScene *s, const OArmKin kin[2], const double *pball, int gid
     int type;
     double P0[3], P1[3], r;
     or_geom_shape(s, kin, pball, gid, &type, P0, P1, &r);
+    double R[3][3];
+    if (type == SH_OBOX) or_quat_to_R(pball + 3, R);
     for (int i = 0; i < 3; ++i) {
         if (type == SH_PLANE) {
             lo[i] = -INFINITY;
             hi[i] = (i == 2) ? 0.0 : INFINITY;
+        } else if (type == SH_OBOX) {
+            double e = fabs(R[i][0]) * P1[0] + fabs(R[i][1]) * P1[1] + fabs(R[i][2]) * P1[2];
+            lo[i] = P0[i] - e;
+            hi[i] = P0[i] + e;
         } else if (type == SH_BOX) {
             lo[i] = P0[i] - P1[i];
             hi[i] = P0[i] + P1[i];
@@ -314,7 +327,14 @@ static void narrow_shapes(int ta, const double A0[3], const double A1[3], double
     sphere_sphere(xa, ra, xb, rb, phi, n, p);
 }
 
-/* narrowphase for pair (ga, gb); returns 1 and fills (phi, n, p) */
+void or_narrow_prim(int ta, const double A0[3], const double A1[3], double ra, int tb, const double B0[3],
+                    const double B1[3], double rb, double *phi, double n[3], double p[3])
+{
+    narrow_shapes(ta, A0, A1, ra, tb, B0, B1, rb, phi, n, p);
+}
+
+/* narrowphase for pair (ga, gb); returns 1 and fills (phi, n, p) (a box
+ * object on the table: its deepest vertex) */
 int or_narrow(const OScene *s, const OArmKin kin[2], const double *pball, int ga, int gb, double *phi, double n[3],
               double p[3])
 {
@@ -322,7 +342,10 @@ int or_narrow(const OScene *s, const OArmKin kin[2], const double *pball, int ga
     double A0[3], A1[3], B0[3], B1[3], ra, rb;
     or_geom_shape(s, kin, pball, ga, &ta, A0, A1, &ra);
     or_geom_shape(s, kin, pball, gb, &tb, B0, B1, &rb);
-    narrow_shapes(ta, A0, A1, ra, tb, B0, B1, rb, phi, n, p);
+    if (ta == SH_OBOX)
+        or_obj_narrow(s, pball, tb, B0, B1, rb, phi, n, p);
+    else
+        narrow_shapes(ta, A0, A1, ra, tb, B0, B1, rb, phi, n, p);
     return 1;
 }
 
@@ -342,6 +365,24 @@ int or_contacts(const OScene *s, const OArmKin kin[2], const double *pball, OCon
         int ga, gb;
         double phi, n[3], p[3];
         or_pair(s, i, &ga, &gb);
+        if (ga == OG_BALL && gb == OG_TABLE && s->obj_box) {
+            /* a box object on the table: every vertex below it, in vertex order, four at most */
+            double ph[8], nn[8][3], pp[8][3];
+            or_obj_table(s, pball, ph, nn, pp);
+            int taken = 0;
+            for (int k = 0; k < 8 && nc < cap && taken < 4; ++k)
+                if (ph[k] < 0.0) {
+                    out[nc].pair = i;
+                    out[nc].ga = ga;
+                    out[nc].gb = gb;
+                    out[nc].phi = ph[k];
+                    memcpy(out[nc].n, nn[k], sizeof(nn[k]));
+                    memcpy(out[nc].p, pp[k], sizeof(pp[k]));
+                    ++nc;
+                    ++taken;
+                }
+            continue;
+        }
         or_narrow(s, kin, pball, ga, gb, &phi, n, p);
         if (phi < 0.0) {
             out[nc].pair = i;

@@ -38,6 +38,15 @@ void or_model(const OScene *s, OModel *md)
             capsule_inertia(s->density[a][i], s->link_len[i], s->link_rad[i], &md->m[a][i], &md->Ix[a][i],
                             &md->Iz[a][i]);
     md->ball_I = 0.4 * s->ball_m * s->ball_r * s->ball_r;
+    if (s->obj_box) {
+        /* solid box: m (b^2 + c^2) / 12 with full sides b = 2 h_y, c = 2 h_z, ... */
+        const double *hh = s->obj_h;
+        md->obj_I[0] = s->ball_m * (hh[1] * hh[1] + hh[2] * hh[2]) / 3.0;
+        md->obj_I[1] = s->ball_m * (hh[0] * hh[0] + hh[2] * hh[2]) / 3.0;
+        md->obj_I[2] = s->ball_m * (hh[0] * hh[0] + hh[1] * hh[1]) / 3.0;
+    } else {
+        md->obj_I[0] = md->obj_I[1] = md->obj_I[2] = md->ball_I;
+    }
     md->eps = s->eps_frac * s->ball_r;
     double rr = s->ball_r + s->pad_rad;
     md->l_ball = 2.0 * sqrt(rr * rr - md->eps * md->eps);

@@ -42,12 +42,30 @@ typedef struct {
     int n_pgs, n_cmax;
     double u_max;
     double w_goal, w_eo, w_l, w_yz, w_s, w_c, gamma, m_c, eps_frac;
+    /* free object: 0 a sphere of radius ball_r, 1 a solid box of half extents
+     * obj_h (the tray of Sec. IV-A, the cube of Sec. IV-C); mass ball_m */
+    int obj_box;
+    double obj_h[3];
+    /* the further cost terms of Sec. IV (terms 7..16 of or_rollout), evaluated
+     * when ext != 0: weights and targets */
+    int ext;
+    double l_target;          /* end-effector distance target; <= 0: l_ball */
+    double q_home[14];
+    double w_home, w_vert, w_relv, w_orot;
+    double w_apos[2], w_ax[2], w_arot[2];
+    double apos[2][3];        /* per-arm end-effector position targets */
+    double ax_t[2];           /* per-arm x targets (hand-over pass) */
+    double arot[2][4];        /* per-arm end-effector orientation targets (w, x, y, z) */
+    double orot[4];           /* object orientation target */
 } OScene;
+
+#define OR_NTERMS 17
 
 /* derived model quantities */
 typedef struct {
     double m[2][OR_NJ], Ix[2][OR_NJ], Iz[2][OR_NJ];
     double ball_I;
+    double obj_I[3];  /* principal inertias of the object about its centre (body frame) */
     double eps, l_ball;
 } OModel;
 
@@ -96,7 +114,17 @@ void or_aabb(const OScene *s, const OArmKin kin[2], const double *pball, int gid
 int or_contacts(const OScene *s, const OArmKin kin[2], const double *pball, OContact *out, int cap);
 double or_seg_box_tstar(const double A[3], const double B[3], const double c[3], const double hh[3]);
 
+/* object.c */
+void or_quat_to_R(const double q[4], double R[3][3]);
+void or_R_to_quat(const double R[3][3], double q[4]);
+double or_quat_angle(const double q[4], const double Q[4]);
+int or_obj_table(const OScene *s, const double *xo, double phi[8], double n[8][3], double p[8][3]);
+void or_obj_narrow(const OScene *s, const double *xo, int tb, const double B0[3], const double B1[3], double rb,
+                   double *phi, double n[3], double p[3]);
+
 /* step.c */
+void or_point_jac(const OScene *s, const OArmKin kin[2], const double *pball, int gid, const double p[3],
+                  double J[3][OR_NDOF], double sign);
 void or_substep(const OScene *s, const OModel *md, const double *x, const double *u, double *xn,
                 int *ncon_out);
 void or_tangents(const double n[3], double t1[3], double t2[3]);

@@ -8,7 +8,9 @@
  *   2. actuator torque tau = clamp(Kp (q_des - q) + Kd (u - qd), +-tau_max);
  *   3. free velocity from (M + diag(armature + h (Kd + b))) (qd_f - qd)
  *      = h (tau - b qd - c(q, qd)), with c from inverse dynamics (no arm
- *      gravity when gravity compensation is on); the ball falls freely;
+ *      gravity when gravity compensation is on); the object falls freely
+ *      and, when it is a box, its angular velocity takes the explicit
+ *      gyroscopic step w_f = w - h W (w x I_w w), I_w = R I R^T, W = I_w^-1;
  *   4. contacts at the current positions, four pyramid-edge rows each
  *      (n +- mu t1, n +- mu t2), solved by projected Gauss-Seidel on the
  *      explicitly assembled soft LCP (A + R) f + b >= 0, f >= 0,
@@ -42,7 +44,7 @@ void or_tangents(const double n[3], double t1[3], double t2[3])
 }
 
 /* 3 x 20 point Jacobian of the point p attached to geom gid */
-static void point_jac(const OScene *s, const OArmKin kin[2], const double *pball, int gid, const double p[3],
+void or_point_jac(const OScene *s, const OArmKin kin[2], const double *pball, int gid, const double p[3],
                       double J[3][OR_NDOF], double sign)
 {
     (void)s;
@@ -67,14 +69,49 @@ static void point_jac(const OScene *s, const OArmKin kin[2], const double *pball
     /* table and boxes are static */
 }
 
-/* x_out = Mt^-1 y for the block-diagonal Mt (two arm factors + ball) */
-static void mt_solve(const double Larm[2][OR_NJ * OR_NJ], const OScene *s, const OModel *md, const double *y,
-                     double *xo)
+/* world-frame inverse inertia W = R diag(1/I) R^T and inertia I_w = R diag(I) R^T
+ * of the object at quaternion q */
+static void obj_inertia_world(const OModel *md, const double *q, double W[3][3], double Iw[3][3])
+{
+    double R[3][3];
+    or_quat_to_R(q, R);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double w = 0.0, v = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                w += R[i][k] * R[j][k] / md->obj_I[k];
+                v += R[i][k] * R[j][k] * md->obj_I[k];
+            }
+            W[i][j] = w;
+            Iw[i][j] = v;
+        }
+}
+
+/* x_out = Mt^-1 y for the block-diagonal Mt (two arm factors + object);
+ * W: the box object's world inverse inertia (unused for the ball) */
+static void mt_solve(const double Larm[2][OR_NJ * OR_NJ], const OScene *s, const OModel *md, const double W[3][3],
+                     const double *y, double *xo)
 {
     or_chol_solve(OR_NJ, Larm[0], y, xo);
     or_chol_solve(OR_NJ, Larm[1], y + 7, xo + 7);
     for (int i = 0; i < 3; ++i) xo[14 + i] = y[14 + i] / s->ball_m;
-    for (int i = 0; i < 3; ++i) xo[17 + i] = y[17 + i] / md->ball_I;
+    if (s->obj_box) {
+        for (int i = 0; i < 3; ++i) xo[17 + i] = W[i][0] * y[17] + W[i][1] * y[18] + W[i][2] * y[19];
+    } else {
+        for (int i = 0; i < 3; ++i) xo[17 + i] = y[17 + i] / md->ball_I;
+    }
+}
+
+/* the object's free angular velocity: w, minus the explicit gyroscopic step
+ * h W (w x I_w w) for a box */
+static void obj_free_w(const OScene *s, const double W[3][3], const double Iw[3][3], const double *w, double *wf)
+{
+    for (int i = 0; i < 3; ++i) wf[i] = w[i];
+    if (!s->obj_box) return;
+    double L[3], g[3];
+    for (int i = 0; i < 3; ++i) L[i] = Iw[i][0] * w[0] + Iw[i][1] * w[1] + Iw[i][2] * w[2];
+    cross(w, L, g);
+    for (int i = 0; i < 3; ++i) wf[i] -= s->h * (W[i][0] * g[0] + W[i][1] * g[1] + W[i][2] * g[2]);
 }
 
 void or_substep(const OScene *s, const OModel *md, const double *x, const double *u, double *xn, int *ncon_out)
@@ -113,9 +150,11 @@ void or_substep(const OScene *s, const OModel *md, const double *x, const double
         or_chol_solve(OR_NJ, Larm[a], rhs, dq);
         for (int i = 0; i < OR_NJ; ++i) vfree[7 * a + i] = qd[7 * a + i] + dq[i];
     }
+    double W[3][3], Iw[3][3];
+    obj_inertia_world(md, quat, W, Iw);
     for (int i = 0; i < 3; ++i) vfree[14 + i] = vb[i];
     vfree[16] -= h * s->g;
-    for (int i = 0; i < 3; ++i) vfree[17 + i] = wb[i];
+    obj_free_w(s, W, Iw, wb, vfree + 17);
 
     OContact con[OR_MAXCON];
     int nc = or_contacts(s, kin, pb, con, s->n_cmax < OR_MAXCON ? s->n_cmax : OR_MAXCON);
@@ -130,8 +169,8 @@ void or_substep(const OScene *s, const OModel *md, const double *x, const double
         for (int c = 0; c < nc; ++c) {
             double Jp[3][OR_NDOF];
             memset(Jp, 0, sizeof(Jp));
-            point_jac(s, kin, pb, con[c].ga, con[c].p, Jp, 1.0);
-            point_jac(s, kin, pb, con[c].gb, con[c].p, Jp, -1.0);
+            or_point_jac(s, kin, pb, con[c].ga, con[c].p, Jp, 1.0);
+            or_point_jac(s, kin, pb, con[c].gb, con[c].p, Jp, -1.0);
             double t1[3], t2[3];
             or_tangents(con[c].n, t1, t2);
             double e[4][3];
@@ -151,7 +190,8 @@ void or_substep(const OScene *s, const OModel *md, const double *x, const double
                 b[row] = jv - s->kappa * pen / h;
             }
         }
-        for (int r = 0; r < m; ++r) mt_solve((const double(*)[OR_NJ * OR_NJ])Larm, s, md, J[r], MiJT[r]);
+        for (int r = 0; r < m; ++r)
+            mt_solve((const double(*)[OR_NJ * OR_NJ])Larm, s, md, (const double(*)[3])W, J[r], MiJT[r]);
         for (int r = 0; r < m; ++r)
             for (int c = 0; c < m; ++c) {
                 double acc = 0.0;
@@ -242,9 +282,11 @@ int oracle_lcp(const OScene *s, const double *x, const double *u, double *Aout, 
         or_chol_solve(OR_NJ, Larm[a], rhs, dq);
         for (int i = 0; i < OR_NJ; ++i) vfree[7 * a + i] = qd[7 * a + i] + dq[i];
     }
+    double W[3][3], Iw[3][3];
+    obj_inertia_world(&md, x + 45, W, Iw);
     for (int i = 0; i < 3; ++i) vfree[14 + i] = vb[i];
     vfree[16] -= h * s->g;
-    for (int i = 0; i < 3; ++i) vfree[17 + i] = wb[i];
+    obj_free_w(s, W, Iw, wb, vfree + 17);
     memcpy(vfree_out, vfree, sizeof(vfree));
     OContact con[16];
     int nc = or_contacts(s, kin, pb, con, 16 < s->n_cmax ? 16 : s->n_cmax);
@@ -253,8 +295,8 @@ int oracle_lcp(const OScene *s, const double *x, const double *u, double *Aout, 
     for (int c = 0; c < nc; ++c) {
         double Jp[3][OR_NDOF];
         memset(Jp, 0, sizeof(Jp));
-        point_jac(s, kin, pb, con[c].ga, con[c].p, Jp, 1.0);
-        point_jac(s, kin, pb, con[c].gb, con[c].p, Jp, -1.0);
+        or_point_jac(s, kin, pb, con[c].ga, con[c].p, Jp, 1.0);
+        or_point_jac(s, kin, pb, con[c].gb, con[c].p, Jp, -1.0);
         double t1[3], t2[3], e[4][3];
         or_tangents(con[c].n, t1, t2);
         for (int i = 0; i < 3; ++i) {
@@ -272,7 +314,8 @@ int oracle_lcp(const OScene *s, const double *x, const double *u, double *Aout, 
             bout[4 * c + r] = jv - s->kappa * (con[c].phi < 0 ? -con[c].phi : 0.0) / h;
         }
     }
-    for (int r = 0; r < m; ++r) mt_solve((const double(*)[OR_NJ * OR_NJ])Larm, s, &md, J[r], MiJT[r]);
+    for (int r = 0; r < m; ++r)
+        mt_solve((const double(*)[OR_NJ * OR_NJ])Larm, s, &md, (const double(*)[3])W, J[r], MiJT[r]);
     for (int r = 0; r < m; ++r)
         for (int c = 0; c < m; ++c) {
             double acc = 0.0;
@@ -300,6 +343,6 @@ void oracle_point_jac(const OScene *s, const double *x, int gid, const double *p
     or_fk(s, 1, x + 7, &kin[1]);
     double J[3][OR_NDOF];
     memset(J, 0, sizeof(J));
-    point_jac(s, kin, x + 42, gid, p, J, 1.0);
+    or_point_jac(s, kin, x + 42, gid, p, J, 1.0);
     memcpy(Jout, J, sizeof(J));
 }

@@ -57,6 +57,18 @@ COST = dict(
     w_goal=1.0, w_eo=1.0, w_l=10.0, w_yz=1.0, w_s=0.01, w_c=10.0,
     gamma=0.5, m_c=0.05, eps_frac=0.3,
 )
+# the free object (a ball unless a task scene makes it a box) and the further
+# task-cost terms (off unless a task scene turns them on)
+EXTRA = dict(
+    obj_box=0, obj_h=np.zeros(3), ext=0, l_target=0.0,
+    w_home=0.0, w_vert=0.0, w_relv=0.0, w_orot=0.0,
+    w_apos=np.zeros(2), w_ax=np.zeros(2), w_arot=np.zeros(2),
+    apos=np.zeros((2, 3)), ax_t=np.zeros(2), arot=np.array([[1.0, 0, 0, 0], [1.0, 0, 0, 0]]),
+    orot=np.array([1.0, 0, 0, 0]),
+)
+# task objects: the tray (held along x between the pads) and the cube
+TRAY_H, TRAY_M = (0.12, 0.10, 0.015), 0.4
+CUBE_H, CUBE_M = (0.03, 0.03, 0.03), 0.1
 
 # arm / ball corridor at home pose (xy rectangle boxes must stay clear of)
 _CORRIDOR = (-0.65, 0.65, -0.12, 0.12)
@@ -155,6 +167,7 @@ def make_scene(config: int, index: int = 0, *, n_box=None, ball_r=None,
     )
     scene.update(PHYSICS)
     scene.update(COST)
+    scene.update({k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in EXTRA.items()})
     for k, v in overrides.items():
         if k not in scene:
             raise KeyError(k)
@@ -303,3 +316,62 @@ def episode_params(config: int = 2, **overrides):
              lift_z=r + 0.05, drop_z=r + 0.01, t_max=10.0, M=3, n_elite=32, eta=0.8, use_cov=0, cov_eps=0.01)
     p.update(overrides)
     return p
+
+
+def _rot(axis, ang):
+    """Unit quaternion (w, x, y, z) of a rotation by ang about a unit axis."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    return np.concatenate([[math.cos(ang / 2)], math.sin(ang / 2) * a])
+
+
+def task_scene(task, phase, index=0, **overrides):
+    """Scenes of the tray-moving task (Sec. IV-A; phases "pick", "move") and
+    of the hand-over task (Sec. IV-C; phases "pick", "pass", "place") on the
+    3-box workload's world: the free object is a box (the tray of half
+    extents TRAY_H, mass TRAY_M, resting on the table at the origin; the
+    cube of CUBE_H, CUBE_M, resting in front of arm 1) and the cost is the
+    task's total with the phase's weights and targets (the paper switches
+    w_pick / w_move, and the hand-over's per-arm phase weights, by phase).
+    Weights are hand-set, as in the paper; the end-effector orientation
+    targets are fixed quaternions (the synthetic arms' pads are spheres, so
+    their orientation is a cost target only)."""
+    base = make_scene(2, index)
+    pad = PAD_RAD
+    q_tilt = [_rot((0, 1, 0), 0.5 * math.pi), _rot((0, 1, 0), -0.5 * math.pi)]
+    common = dict(ext=1, w_goal=0.0, w_eo=0.0, w_l=0.0, w_yz=0.0, w_s=0.01, w_c=10.0, w_home=0.1, n_cmax=8)
+    if task == "tray":
+        h = np.array(TRAY_H)
+        grasp = np.array([[-(h[0] + pad), 0.0, h[2]], [h[0] + pad, 0.0, h[2]]])
+        sc = dict(base, obj_box=1, obj_h=h, ball_m=TRAY_M, ball_r=float(h[2]), ball_p0=np.array([0.0, 0.0, h[2]]),
+                  goal=np.array([0.0, 0.3, 0.25]), l_target=2.0 * (h[0] + pad), orot=np.array([1.0, 0, 0, 0]),
+                  w_vert=1.0, w_relv=1.0, **common)
+        if phase == "pick":     # w_pick = 1: C_p,pick (1/2 per arm), C_r,pick (1/2 per arm)
+            sc.update(apos=grasp, w_apos=np.array([0.5, 0.5]), arot=np.array(q_tilt), w_arot=np.array([0.05, 0.05]))
+        elif phase == "move":   # w_move = 1: C_l, C_p,tray (term 0), C_r,tray, C_r,move (1/2 per arm)
+            sc.update(w_l=10.0, w_goal=1.0, w_orot=1.0, arot=np.array(q_tilt), w_arot=np.array([0.05, 0.05]))
+        else:
+            raise ValueError(phase)
+    elif task == "handover":
+        h = np.array(CUBE_H)
+        p_obj = np.array([-0.25, 0.0, h[2]])
+        target = np.array([0.3, 0.1, 0.15])
+        sc = dict(base, obj_box=1, obj_h=h, ball_m=CUBE_M, ball_r=float(h[2]), ball_p0=p_obj, goal=target, **common)
+        eps = float(base["eps_frac"]) * float(h[2])
+        q_phase = {"pick": _rot((0, 1, 0), 0.5 * math.pi), "pass": _rot((1, 0, 0), 0.5 * math.pi),
+                   "place": _rot((0, 1, 0), -0.5 * math.pi)}[phase]
+        sc.update(arot=np.array([q_phase, q_phase]))
+        if phase == "pick":     # arm 1 picks: C_p,1^pick, C_r,1^pick
+            sc.update(apos=np.array([p_obj + [0, 0, eps], p_obj + [0, 0, eps]]), w_apos=np.array([1.0, 0.0]),
+                      w_arot=np.array([0.1, 0.0]))
+        elif phase == "pass":   # both arms to the pass line, aligned in yz: C_p^pass, w_pass C_yz
+            sc.update(ax_t=np.array([-0.05, 0.05]), w_ax=np.array([1.0, 1.0]), w_yz=1.0,
+                      w_arot=np.array([0.1, 0.1]))
+        elif phase == "place":  # arm 2 places: C_p,2^place
+            sc.update(apos=np.array([target, target]), w_apos=np.array([0.0, 1.0]), w_arot=np.array([0.0, 0.1]))
+        else:
+            raise ValueError(phase)
+    else:
+        raise ValueError(task)
+    sc.update(overrides)
+    return sc
