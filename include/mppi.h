@@ -58,6 +58,7 @@ extern "C" {
 #define MPPI_MAX_PAIRS (76 + 15 * MPPI_MAX_BOXES)
 #define MPPI_MAX_K (1 << 20)
 #define MPPI_MAX_H 4096
+#define MPPI_NTERMS 17  /* cost terms per sample (see mppi_scene_desc and mppi_simulate) */
 
 /* flags */
 #define MPPI_DEVICE_PTRS 1u     /* array arguments are device pointers */
@@ -117,7 +118,26 @@ typedef struct mppi_scene mppi_scene;
  * contacts.  Controls are clamped to |u| <= u_max.  Cost weights: goal
  * distance, end-effector-to-ball alignment, end-effector distance, planar
  * alignment, smoothness, collision; gamma of the barrier; m_c distance
- * saturation; eps = eps_frac * ball_r vertical grasp offset. */
+ * saturation; eps = eps_frac * ball_r vertical grasp offset.
+ * The free object: obj_box = 0 the ball (sphere of radius ball_r), 1 a solid
+ * box of half extents obj_h (the tray of Sec. IV-A, the cube of Sec. IV-C;
+ * mass ball_m; on the table up to four vertex contacts, against pads and
+ * links computed in its frame, against static boxes by separating axes).
+ * ext = 1 adds the further task-cost terms of Sec. IV (terms 7..16 of
+ * mppi_simulate) with their weights and targets: joint deviation from
+ * q_home (Eq. home_cost), vertical alignment (Eq. vertical_alignment_cost),
+ * relative velocity (Eq. rel_vel_cost), per-arm end-effector position
+ * targets apos (Eqs. tray_grasp_pos_cost, the hand-over's pick and place
+ * costs), per-arm x targets ax_t (the hand-over's pass cost), per-arm
+ * end-effector orientation targets arot (Eqs. tray_grasp_ori_cost,
+ * tray_move_ori_cost, the ball's C_r, the hand-over's phase terms), the
+ * object orientation target orot (Eq. tray_ori_cost); quaternions (w, x,
+ * y, z), normalised here.  l_target > 0 replaces the ball's grasp width in
+ * the end-effector distance term (l_tray).  The paper's task totals are
+ * weightings of the 17 terms; the caller sets the phase's weights (w_pick /
+ * w_move, the hand-over's per-arm phase weights) by choosing the scene.
+ * Scenes with obj_box or ext run in the one-lane mapping only (a pinned
+ * team, wave or split mapping is rejected with MPPI_E_INVAL). */
 typedef struct mppi_scene_desc {
     double base_pos[2][3];
     double base_cs[2][2];
@@ -137,6 +157,17 @@ typedef struct mppi_scene_desc {
     int n_pgs, n_cmax;
     double u_max;
     double w_goal, w_eo, w_l, w_yz, w_s, w_c, gamma, m_c, eps_frac;
+    int obj_box;
+    double obj_h[3];
+    int ext;
+    double l_target;
+    double q_home[14];
+    double w_home, w_vert, w_relv, w_orot;
+    double w_apos[2], w_ax[2], w_arot[2];
+    double apos[2][3];
+    double ax_t[2];
+    double arot[2][4];
+    double orot[4];
 } mppi_scene_desc;
 
 /* Plan options.  M iterations of Alg. 1; seed of the Philox stream; eta
@@ -167,7 +198,9 @@ typedef struct mppi_stats {
     int rollout_launches;
 } mppi_stats;
 
-/* Create a context on HIP device `device` (or -1 = current device). */
+/* Create a context on HIP device `device` (or -1 = current device).
+ * Destroy the servers and scenes made on a context before the context:
+ * their handles refer to it and are invalid once it is gone. */
 int mppi_ctx_create(int device, mppi_ctx **out);
 void mppi_ctx_destroy(mppi_ctx *ctx);
 const char *mppi_last_error(void);
@@ -255,8 +288,12 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
  *   X0: [n][MPPI_NX] start states (one per sample), or one state shared by
  *   all samples when x0_shared != 0; U[n][H][14] controls (used as given,
  *   not clamped); n_sub: substeps per control step (<= 0: the scene's);
- *   costs[n] (nullable); terms[n][7] (nullable): unweighted sums of the cost
- *   terms (goal, eef-obj, distance, planar, smooth, barrier, indicator);
+ *   costs[n] (nullable); terms[n][MPPI_NTERMS] (nullable): unweighted sums
+ *   of the cost terms (goal, eef-obj, distance, planar, smooth, barrier,
+ *   indicator, then with ext: joint deviation, vertical alignment, relative
+ *   velocity (the root of its summed squares), position of arm 1 / arm 2, x
+ *   of arm 1 / arm 2, orientation of arm 1 / arm 2, object orientation; zero
+ *   without ext);
  *   X_out: [n][MPPI_NX] final states, or [n][H][MPPI_NX] with MPPI_TRAJ
  *   (nullable). */
 int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x0_shared, const float *U, int n,
@@ -589,7 +626,9 @@ int mppi_broadphase(mppi_ctx *ctx, const mppi_scene *scene, const float *lo, con
 
 /* Narrowphase of every candidate pair at states X[n][MPPI_NX]: phi[n][P],
  * normal[n][P][3] (from geom B to geom A), point[n][P][3]; and the geom
- * AABBs lo/hi[n][16 + n_box][3] (nullable). */
+ * AABBs lo/hi[n][16 + n_box][3] (nullable).  With a box-shaped object its
+ * pair with the table reports the deepest vertex (the lowest index on ties)
+ * and its AABB is that of the rotated box. */
 int mppi_narrowphase(mppi_ctx *ctx, const mppi_scene *scene, const float *X, int n, float *phi, float *normal,
                      float *point, float *lo, float *hi, unsigned flags, void *stream);
 

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -59,7 +60,15 @@ class SceneDesc(C.Structure):
         ("w_goal", C.c_double), ("w_eo", C.c_double), ("w_l", C.c_double), ("w_yz", C.c_double),
         ("w_s", C.c_double), ("w_c", C.c_double), ("gamma", C.c_double), ("m_c", C.c_double),
         ("eps_frac", C.c_double),
+        ("obj_box", C.c_int), ("obj_h", C.c_double * 3),
+        ("ext", C.c_int), ("l_target", C.c_double), ("q_home", C.c_double * 14),
+        ("w_home", C.c_double), ("w_vert", C.c_double), ("w_relv", C.c_double), ("w_orot", C.c_double),
+        ("w_apos", C.c_double * 2), ("w_ax", C.c_double * 2), ("w_arot", C.c_double * 2),
+        ("apos", C.c_double * 6), ("ax_t", C.c_double * 2), ("arot", C.c_double * 8), ("orot", C.c_double * 4),
     ]
+
+
+NTERMS = 17
 
 
 class Opts(C.Structure):
@@ -252,6 +261,19 @@ def scene_desc(sc: dict) -> SceneDesc:
     d.gravcomp = int(sc["gravcomp"])
     d.n_pgs = int(sc["n_pgs"])
     d.n_cmax = int(sc["n_cmax"])
+    # the free object's shape and the further task-cost terms (defaults: a ball, terms off)
+    d.obj_box = int(sc.get("obj_box", 0))
+    _fill(d.obj_h, sc.get("obj_h", (0.0, 0.0, 0.0)))
+    d.ext = int(sc.get("ext", 0))
+    d.l_target = float(sc.get("l_target", 0.0))
+    _fill(d.q_home, sc.get("q_home", np.zeros(14)))
+    for k in ("w_home", "w_vert", "w_relv", "w_orot"):
+        setattr(d, k, float(sc.get(k, 0.0)))
+    for k in ("w_apos", "w_ax", "w_arot", "ax_t"):
+        _fill(getattr(d, k), sc.get(k, (0.0, 0.0)))
+    _fill(d.apos, sc.get("apos", np.zeros((2, 3))))
+    _fill(d.arot, sc.get("arot", ((1.0, 0, 0, 0), (1.0, 0, 0, 0))))
+    _fill(d.orot, sc.get("orot", (1.0, 0, 0, 0)))
     return d
 
 
@@ -305,13 +327,22 @@ def _stream(dev, stream):
 
 
 class Context:
+    """A device context.  Closing it first closes the servers, then the
+    scenes made on it that are still open (their handles die with it)."""
+
     def __init__(self, device: int = 0):
         self._h = _P()
         _check(lib().mppi_ctx_create(device, C.byref(self._h)))
         self.device = device
+        self._servers = weakref.WeakSet()
+        self._scenes = weakref.WeakSet()
 
     def close(self):
         if self._h:
+            for srv in list(self._servers):
+                srv.close()
+            for sc in list(self._scenes):
+                sc.close()
             lib().mppi_ctx_destroy(self._h)
             self._h = _P()
 
@@ -329,6 +360,7 @@ class Scene:
         self.desc = scene_desc(scene)
         self._h = _P()
         _check(lib().mppi_scene_create(ctx._h, C.byref(self.desc), C.byref(self._h)))
+        ctx._scenes.add(self)
         a, b = C.c_int(0), C.c_int(0)
         _check(lib().mppi_scene_num_pairs(self._h, C.byref(a), C.byref(b)))
         self.n_pairs, self.n_cost_pairs = a.value, b.value
@@ -682,6 +714,7 @@ class Server:
         o = ServerOpts(int(mem_budget), int(max_active), int(max_pending), _MAPS[mapping], float(deadline_ms),
                        float(iter_base_ms), float(iter_ms_per_menv))
         _check(lib().mppi_server_create(ctx._h, C.byref(o), C.byref(self._h)))
+        ctx._servers.add(self)
         self._keep = {}
 
     def close(self):

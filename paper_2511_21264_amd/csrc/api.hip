@@ -219,6 +219,69 @@ int build_model(const mppi_scene_desc *d, DevModel &m)
         for (int g2 = 0; g2 < 7; ++g2) add(G_ARM + g, G_ARM + 7 + g2);
     m.n_pairs = n;
     m.n_cost = 14 * d->n_box + 49;
+    // the free object and the further task-cost terms
+    if (d->obj_box != 0 && d->obj_box != 1) return fail(MPPI_E_MODEL, "obj_box must be 0 (ball) or 1 (box)");
+    m.obj_box = d->obj_box;
+    m.ext = d->ext ? 1 : 0;
+    m.lane_only = m.obj_box | m.ext;
+    const double inv_I_ball = 1.0 / (0.4 * d->ball_m * d->ball_r * d->ball_r);
+    for (int i = 0; i < 3; ++i) {
+        m.obj_I[i] = (float)(0.4 * d->ball_m * d->ball_r * d->ball_r);
+        m.obj_iI[i] = (float)inv_I_ball;
+    }
+    if (m.obj_box) {
+        for (int i = 0; i < 3; ++i)
+            if (!(d->obj_h[i] > 0) || !std::isfinite(d->obj_h[i])) return fail(MPPI_E_MODEL, "obj_h must be finite and > 0");
+        const double *hh = d->obj_h;
+        const double I[3] = {d->ball_m * (hh[1] * hh[1] + hh[2] * hh[2]) / 3.0,
+                             d->ball_m * (hh[0] * hh[0] + hh[2] * hh[2]) / 3.0,
+                             d->ball_m * (hh[0] * hh[0] + hh[1] * hh[1]) / 3.0};
+        for (int i = 0; i < 3; ++i) {
+            m.obj_h[i] = (float)hh[i];
+            m.obj_I[i] = (float)I[i];
+            m.obj_iI[i] = (float)(1.0 / I[i]);
+        }
+    }
+    if (!std::isfinite(d->l_target)) return fail(MPPI_E_MODEL, "non-finite l_target");
+    m.l_cost = d->l_target > 0 ? (float)d->l_target : m.l_ball;
+    const double wx[] = {d->w_home, d->w_vert, d->w_relv, d->w_orot, d->w_apos[0], d->w_apos[1], d->w_ax[0],
+                         d->w_ax[1], d->w_arot[0], d->w_arot[1], d->ax_t[0], d->ax_t[1]};
+    for (double v : wx)
+        if (!std::isfinite(v)) return fail(MPPI_E_MODEL, "non-finite task-cost weight or target");
+    for (int i = 0; i < 14; ++i) {
+        if (!std::isfinite(d->q_home[i])) return fail(MPPI_E_MODEL, "non-finite q_home");
+        m.q_home[i] = (float)d->q_home[i];
+    }
+    m.w_home = (float)d->w_home;
+    m.w_vert = (float)d->w_vert;
+    m.w_relv = (float)d->w_relv;
+    m.w_orot = (float)d->w_orot;
+    auto unit = [](const double *q, double *o) {
+        const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        if (!(nq > 0) || !std::isfinite(nq)) return false;
+        for (int i = 0; i < 4; ++i) o[i] = q[i] / nq;
+        return true;
+    };
+    for (int a = 0; a < 2; ++a) {
+        m.w_apos[a] = (float)d->w_apos[a];
+        m.w_ax[a] = (float)d->w_ax[a];
+        m.w_arot[a] = (float)d->w_arot[a];
+        m.ax_t[a] = (float)d->ax_t[a];
+        for (int i = 0; i < 3; ++i) {
+            if (!std::isfinite(d->apos[a][i])) return fail(MPPI_E_MODEL, "non-finite apos");
+            m.apos[a][i] = (float)d->apos[a][i];
+        }
+        double q[4];
+        if (!unit(d->arot[a], q)) return fail(MPPI_E_MODEL, "arot[%d] is not a finite non-zero quaternion", a);
+        const double w = q[0], x = q[1], y = q[2], z = q[3];
+        const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                             2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                             2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+        for (int i = 0; i < 9; ++i) m.arotR[a][i] = (float)R[i];
+    }
+    double qo[4];
+    if (!unit(d->orot, qo)) return fail(MPPI_E_MODEL, "orot is not a finite non-zero quaternion");
+    for (int i = 0; i < 4; ++i) m.orot[i] = (float)qo[i];
     return MPPI_OK;
 }
 
@@ -253,6 +316,7 @@ int resolve_mapping(const mppi_ctx *c, long K, unsigned flags)
 
 int family_launch_mapping(const mppi_ctx *c, int family, long total_k, unsigned flags)
 {
+    if (family == MAP_TASK) return MAP_TASK;  // a pin can only have been the lane mapping
     const int pinned = mapping_of(flags);
     if (pinned != MAP_AUTO) return pinned;
     if (family == MAP_LANE) return MAP_LANE;
@@ -263,6 +327,19 @@ int family_launch_mapping(const mppi_ctx *c, int family, long total_k, unsigned 
 int set_device(mppi_ctx *c)
 {
     HIPCHK(hipSetDevice(c->device));
+    return MPPI_OK;
+}
+
+int scene_mapping(const mppi_ctx *c, const mppi_scene *s, long K, unsigned flags, int *map)
+{
+    const int pinned = mapping_of(flags);
+    if (s->host.lane_only) {
+        if (pinned != MAP_AUTO && pinned != MAP_LANE)
+            return fail(MPPI_E_INVAL, "scenes with a box object or the further task-cost terms run one sample per lane");
+        *map = MAP_TASK;
+        return MPPI_OK;
+    }
+    *map = resolve_mapping(c, K, flags);
     return MPPI_OK;
 }
 
@@ -622,7 +699,9 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
     const uint32_t k0 = (uint32_t)(opts->seed & 0xffffffffu), k1 = (uint32_t)(opts->seed >> 32);
     const int n_elite = (opts->n_elite <= 0 || opts->n_elite >= K) ? K : opts->n_elite;
     const int f32 = (fl & MPPI_FP32_WEIGHTS) ? 1 : 0;
-    const int mapping = per_step ? MAP_LANE : resolve_mapping(ctx, K, fl);
+    int mapping;
+    if ((rc = scene_mapping(ctx, scene, K, fl, &mapping))) return rc;
+    if (per_step) mapping = MAP_LANE;
     // the launch sequence of the plan: nu = nominal, stats reset, M x (rollout, stats, update)
     auto enqueue = [&](hipStream_t q) -> int {
         HIPCHK(hipMemcpyAsync(dnu, dnom, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, q));
@@ -678,7 +757,8 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
             }
             if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], q));
             if (per_step) {
-                for (int k = 0; k < H; ++k) launch_rollout_step(ra, scene->host.n_cmax, (float *)dps, k, q);
+                for (int k = 0; k < H; ++k)
+                    launch_rollout_step(ra, scene->host.n_cmax, (float *)dps, k, scene->host.lane_only != 0, q);
             } else {
                 launch_rollout(ra, scene->host.n_cmax, q, mapping);
             }
@@ -859,7 +939,8 @@ int mppi_plan_noalloc(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, c
     const uint32_t k0 = (uint32_t)(opts->seed & 0xffffffffu), k1 = (uint32_t)(opts->seed >> 32);
     const int n_elite = (opts->n_elite <= 0 || opts->n_elite >= K) ? K : opts->n_elite;
     const int f32 = (fl & MPPI_FP32_WEIGHTS) ? 1 : 0;
-    const int mapping = resolve_mapping(ctx, K, fl);
+    int mapping;
+    if ((rc = scene_mapping(ctx, scene, K, fl, &mapping))) return rc;
     // nu = nominal; the statistics record cleared by a kernel (no memset, so
     // the sequence may be captured into a graph); then M x (rollout, stats, update)
     HIPCHK(hipMemcpyAsync(dnu, nominal_U, (size_t)H * NU * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -1111,6 +1192,8 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
         mppi_request &r = reqs[i];
         if (!r.scene || !r.x0 || !r.nominal_U || !r.sigma || !r.U_new) return fail(MPPI_E_INVAL, "request %d: NULL argument", i);
         if (r.scene->ctx != ctx) return fail(MPPI_E_INVAL, "request %d: scene of another context", i);
+        int map_i;
+        if (scene_mapping(ctx, r.scene, r.K, flags, &map_i)) return fail(MPPI_E_INVAL, "request %d: %s", i, mppi_last_error());
         if (r.K < 1 || r.K > MPPI_MAX_K || r.H < 1 || r.H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "request %d: K or H out of range", i);
         if (!(r.lambda > 0) || !std::isfinite(r.lambda) || r.opts.M < 1 || r.opts.M > 100000 || !std::isfinite(r.opts.eta))
             return fail(MPPI_E_INVAL, "request %d: bad lambda, M or eta", i);
@@ -1140,15 +1223,14 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
     // up to 4, or up to 8): each request's results then equal its plan alone
     // bit for bit, whatever it is batched with.
     std::vector<int> grp(n);
-    long grp_k[4] = {0, 0, 0, 0};
+    long grp_k[NGROUP] = {};
     for (int i = 0; i < n; ++i) {
         const mppi_request &r = reqs[ord[i]];
-        const int fam = request_family(ctx, r.K, flags) == MAP_LANE ? 0 : 1;
-        grp[i] = 2 * fam + (r.scene->host.n_cmax > 4 ? 1 : 0);
+        grp[i] = group_index(request_family(ctx, r.scene, r.K, flags), r.scene->host.n_cmax);
         grp_k[grp[i]] += r.K;
     }
-    int gmap[4];
-    for (int g = 0; g < 4; ++g) gmap[g] = family_launch_mapping(ctx, g < 2 ? MAP_LANE : MAP_TEAM, grp_k[g], flags);
+    int gmap[NGROUP];
+    for (int g = 0; g < NGROUP; ++g) gmap[g] = family_launch_mapping(ctx, group_family(g), grp_k[g], flags);
     // offsets of every request's slices in the packed buffers
     std::vector<size_t> o_k(n), o_h(n), o_sig(n), o_x0(n);
     size_t nk = 0, nh = 0, nsig_tot = 0;
@@ -1165,20 +1247,20 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
     // block tables: the rollout blocks of each group (in request order, so the
     // requests still iterating give a prefix of every group's table), then
     // the update blocks
-    std::vector<int> gblk[4], ublk, ublk_prefix(n + 1, 0);
-    std::vector<std::vector<int>> blk_prefix(4, std::vector<int>(n + 1, 0));
+    std::vector<int> gblk[NGROUP], ublk, ublk_prefix(n + 1, 0);
+    std::vector<std::vector<int>> blk_prefix(NGROUP, std::vector<int>(n + 1, 0));
     for (int i = 0; i < n; ++i) {
         const mppi_request &r = reqs[ord[i]];
         const int g = grp[i], per = samples_per_block(gmap[g]);
         const int nb = (r.K + per - 1) / per;
         for (int b = 0; b < nb; ++b) { gblk[g].push_back(i); gblk[g].push_back(b); }
         for (int k = 0; k < r.H; ++k) { ublk.push_back(i); ublk.push_back(k); }
-        for (int q = 0; q < 4; ++q) blk_prefix[q][i + 1] = (int)gblk[q].size() / 2;
+        for (int q = 0; q < NGROUP; ++q) blk_prefix[q][i + 1] = (int)gblk[q].size() / 2;
         ublk_prefix[i + 1] = (int)ublk.size() / 2;
     }
     std::vector<int> blk;
-    size_t goff[4];
-    for (int g = 0; g < 4; ++g) {
+    size_t goff[NGROUP];
+    for (int g = 0; g < NGROUP; ++g) {
         goff[g] = blk.size();
         blk.insert(blk.end(), gblk[g].begin(), gblk[g].end());
     }
@@ -1270,7 +1352,7 @@ int mppi_plan_batch(mppi_ctx *ctx, int n, mppi_request *reqs, unsigned flags, vo
         while (act < n && reqs[ord[act]].opts.M > m) ++act;
         // stats entries carry the iteration index for the per-iteration minima
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], s));
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < NGROUP; ++g)
             if (blk_prefix[g][act] > 0)
                 launch_rollout_batch(d_rt, d_blk + goff[g], blk_prefix[g][act], (g & 1) ? 8 : 4, m, gmap[g], s);
         if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m + 1], s));
@@ -1346,7 +1428,7 @@ int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x
     const size_t nxo = traj ? (size_t)n * H * NX : (size_t)n * NX;
     if ((rc = out_ptr(ctx, S_OUT0, costs, (size_t)n * sizeof(float), dev, &dc))) return rc;
     if (!dc && (rc = ensure(ctx, S_OUT0, (size_t)n * sizeof(float), &dc))) return rc;
-    if ((rc = out_ptr(ctx, S_OUT1, terms, (size_t)n * 7 * sizeof(float), dev, &dt))) return rc;
+    if ((rc = out_ptr(ctx, S_OUT1, terms, (size_t)n * NTERMS * sizeof(float), dev, &dt))) return rc;
     if ((rc = out_ptr(ctx, S_OUT2, X_out, nxo * sizeof(float), dev, &dxo))) return rc;
     void *ddist;
     if ((rc = ensure(ctx, S_DIST, (size_t)n * MAXCOST * sizeof(float), &ddist))) return rc;
@@ -1363,10 +1445,12 @@ int mppi_simulate(mppi_ctx *ctx, const mppi_scene *scene, const float *X0, int x
     ra.terms = (float *)dt;
     ra.xout = (float *)dxo;
     ra.traj = traj;
-    launch_rollout(ra, scene->host.n_cmax, s, resolve_mapping(ctx, n, flags));
+    int map;
+    if ((rc = scene_mapping(ctx, scene, n, flags, &map))) return rc;
+    launch_rollout(ra, scene->host.n_cmax, s, map);
     HIPCHK(hipGetLastError());
     if ((rc = copy_out(costs, dc, (size_t)n * sizeof(float), dev, s))) return rc;
-    if ((rc = copy_out(terms, dt, (size_t)n * 7 * sizeof(float), dev, s))) return rc;
+    if ((rc = copy_out(terms, dt, (size_t)n * NTERMS * sizeof(float), dev, s))) return rc;
     if ((rc = copy_out(X_out, dxo, nxo * sizeof(float), dev, s))) return rc;
     if (!dev || (flags & MPPI_SYNC)) HIPCHK(hipStreamSynchronize(s));
     return MPPI_OK;
@@ -1462,6 +1546,7 @@ int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const
     if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
     if (K < 1 || K > MPPI_MAX_K || H < 1 || H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "K=%d or H=%d out of range", K, H);
     if (!all_finite(x0, NX) || !all_finite(sigma, NU)) return fail(MPPI_E_INVAL, "non-finite input");
+    if (scene->host.lane_only) return fail(MPPI_E_INVAL, "scenes with a box object or the further task-cost terms run one sample per lane: nothing to tune");
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = nullptr;

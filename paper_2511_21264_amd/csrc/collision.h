@@ -224,4 +224,131 @@ __device__ inline Contact3 narrow(const Shape &A, const Shape &B)
     return sphere_sphere(xa, A.r, xb, B.r);
 }
 
+// ---------------------------------------------------------------------------
+// The free object as a box (the tray, the cube): centre c, rotation R (from
+// its unit quaternion, row-major), half extents h.  Vertex k (0..7) sits at
+// c + R (s_x h_x, s_y h_y, s_z h_z), s_x = +1 when bit 0 of k is set, else -1
+// (bits 1, 2 for y, z).
+
+struct Rot3 {
+    float m[9];
+};
+
+__device__ __forceinline__ Rot3 quat_R(float w, float x, float y, float z)
+{
+    Rot3 R;
+    R.m[0] = 1.f - 2.f * (y * y + z * z); R.m[1] = 2.f * (x * y - w * z); R.m[2] = 2.f * (x * z + w * y);
+    R.m[3] = 2.f * (x * y + w * z); R.m[4] = 1.f - 2.f * (x * x + z * z); R.m[5] = 2.f * (y * z - w * x);
+    R.m[6] = 2.f * (x * z - w * y); R.m[7] = 2.f * (y * z + w * x); R.m[8] = 1.f - 2.f * (x * x + y * y);
+    return R;
+}
+__device__ __forceinline__ V3 mulR(const Rot3 &R, V3 v)
+{
+    return v3(R.m[0] * v.x + R.m[1] * v.y + R.m[2] * v.z, R.m[3] * v.x + R.m[4] * v.y + R.m[5] * v.z,
+              R.m[6] * v.x + R.m[7] * v.y + R.m[8] * v.z);
+}
+__device__ __forceinline__ V3 mulRt(const Rot3 &R, V3 v)
+{
+    return v3(R.m[0] * v.x + R.m[3] * v.y + R.m[6] * v.z, R.m[1] * v.x + R.m[4] * v.y + R.m[7] * v.z,
+              R.m[2] * v.x + R.m[5] * v.y + R.m[8] * v.z);
+}
+__device__ __forceinline__ V3 Rcol(const Rot3 &R, int i) { return v3(R.m[i], R.m[3 + i], R.m[6 + i]); }
+
+__device__ __forceinline__ V3 obox_vertex(V3 c, const Rot3 &R, V3 h, int k)
+{
+    return c + mulR(R, v3((k & 1) ? h.x : -h.x, (k & 2) ? h.y : -h.y, (k & 4) ? h.z : -h.z));
+}
+
+__device__ __forceinline__ AABB obox_aabb(V3 c, const Rot3 &R, V3 h)
+{
+    const V3 e = v3(fabsf(R.m[0]) * h.x + fabsf(R.m[1]) * h.y + fabsf(R.m[2]) * h.z,
+                    fabsf(R.m[3]) * h.x + fabsf(R.m[4]) * h.y + fabsf(R.m[5]) * h.z,
+                    fabsf(R.m[6]) * h.x + fabsf(R.m[7]) * h.y + fabsf(R.m[8]) * h.z);
+    AABB b;
+    b.lo = c - e;
+    b.hi = c + e;
+    return b;
+}
+
+// the box object (geom A) against a sphere or capsule B: B's core taken to
+// the box's frame, the static-box narrowphase there, the normal turned to
+// point from B towards the object
+__device__ inline Contact3 obox_core(V3 c, const Rot3 &R, V3 h, const Shape &B)
+{
+    Shape Bl = B;
+    Bl.p0 = mulRt(R, B.p0 - c);
+    Bl.p1 = mulRt(R, B.p1 - c);
+    Shape bx;
+    bx.type = SH_BOX;
+    bx.p0 = v3(0.f, 0.f, 0.f);
+    bx.p1 = h;
+    bx.r = 0.f;
+    const Contact3 cl = narrow(Bl, bx);
+    Contact3 out;
+    out.phi = cl.phi;
+    out.n = -1.0f * mulR(R, cl.n);
+    out.p = c + mulR(R, cl.p);
+    return out;
+}
+
+// vertex of the box (c, R, h) farthest along d (the lowest index on ties)
+__device__ __forceinline__ V3 obox_support(V3 c, const Rot3 &R, V3 h, V3 d)
+{
+    V3 best = obox_vertex(c, R, h, 0);
+    float be = dot(best, d);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        const V3 v = obox_vertex(c, R, h, k);
+        const float e = dot(v, d);
+        if (e > be) {
+            be = e;
+            best = v;
+        }
+    }
+    return best;
+}
+
+// the box object (geom A) against a static axis-aligned box (centre cb, half
+// extents hb) by separating axes: the object's face normals, the static
+// box's, then their cross products (shorter than 1e-9: skipped); phi the
+// largest separation, n its axis (first on ties) turned towards the object,
+// p midway between the two boxes' support vertices along -n and n
+__device__ inline Contact3 obox_box(V3 c, const Rot3 &R, V3 h, V3 cb, V3 hb)
+{
+    const V3 d = c - cb;
+    float best = -INFINITY;
+    V3 bn = v3(0.f, 0.f, 1.f);
+    auto axis = [&](V3 L) {
+        const V3 la = mulRt(R, L);
+        const float ra = h.x * fabsf(la.x) + h.y * fabsf(la.y) + h.z * fabsf(la.z);
+        const float rb = hb.x * fabsf(L.x) + hb.y * fabsf(L.y) + hb.z * fabsf(L.z);
+        const float dl = dot(d, L);
+        const float sep = fabsf(dl) - ra - rb;
+        if (sep > best) {
+            best = sep;
+            bn = dl >= 0.f ? L : -1.0f * L;
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < 3; ++i) axis(Rcol(R, i));
+    axis(v3(1.f, 0.f, 0.f));
+    axis(v3(0.f, 1.f, 0.f));
+    axis(v3(0.f, 0.f, 1.f));
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const V3 e = v3(j == 0 ? 1.f : 0.f, j == 1 ? 1.f : 0.f, j == 2 ? 1.f : 0.f);
+            const V3 x = cross(Rcol(R, i), e);
+            const float len = sqrtf(dot(x, x));
+            if (len >= 1e-9f) axis((1.0f / len) * x);
+        }
+    Contact3 out;
+    out.phi = best;
+    out.n = bn;
+    const Rot3 I3 = {{1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}};
+    out.p = 0.5f * (obox_support(c, R, h, -1.0f * bn) + obox_support(cb, I3, hb, bn));
+    return out;
+}
+
 }  // namespace mppi

@@ -16,6 +16,7 @@ constexpr int NX = MPPI_NX;
 constexpr int MAXBOX = MPPI_MAX_BOXES;
 constexpr int MAXPAIR = MPPI_MAX_PAIRS;
 constexpr int MAXCOST = 49 + 14 * MAXBOX;
+constexpr int NTERMS = MPPI_NTERMS;
 
 // state offsets
 constexpr int XQ = 0, XQD = 14, XQDES = 28, XPB = 42, XQUAT = 45, XVB = 49, XWB = 52;
@@ -45,6 +46,17 @@ struct DevModel {
     float w_goal, w_eo, w_l, w_yz, w_s, w_c, one_m_gamma, m_c, eps, l_ball;
     int n_pairs, cost_first, n_cost;
     uint8_t pa[MAXPAIR], pb[MAXPAIR];
+    // the free object as a box (obj_box): half extents, principal inertias
+    // and their inverses (body frame); ext: the further task-cost terms
+    int obj_box, ext, lane_only;
+    float obj_h[3], obj_I[3], obj_iI[3];
+    float l_cost;  // end-effector distance target of the cost (l_target or l_ball)
+    float q_home[14];
+    float w_home, w_vert, w_relv, w_orot;
+    float w_apos[2], w_ax[2], w_arot[2];
+    float apos[2][3], ax_t[2];
+    float arotR[2][9];  // per-arm orientation targets as rotation matrices, row-major
+    float orot[4];      // object orientation target (w, x, y, z), unit
 };
 
 }  // namespace mppi

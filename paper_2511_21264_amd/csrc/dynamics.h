@@ -51,11 +51,13 @@ __device__ __forceinline__ void add_pa(S3 &I, float m, V3 d)
     I.yz -= m * d.y * d.z;
 }
 
-// kinematics of one arm: joint origins o[0..6], tip o[7], joint axes, link z axes
+// kinematics of one arm: joint origins o[0..6], tip o[7], joint axes, link z
+// axes, and the x and y axes of the last link's frame (the pad's orientation)
 struct ArmKin {
     V3 o[NJ + 1];
     V3 a[NJ];
     V3 z[NJ];
+    V3 x7, y7;
 };
 
 // columns j1, j2 of R after a rotation by (c, s) about the third axis
@@ -98,6 +100,8 @@ __device__ inline void fk_arm(const DevModel &md, int arm, const float *q, ArmKi
         o = fma3(md.link_len[i], k.z[i], o);
     }
     k.o[NJ] = o;
+    k.x7 = v3(R[0][0], R[1][0], R[2][0]);
+    k.y7 = v3(R[0][1], R[1][1], R[2][1]);
 }
 
 // packed lower triangle index of (r, c), r >= c

@@ -56,7 +56,7 @@ extern "C" int mppi_episode(mppi_ctx *ctx, const mppi_scene *pick, const mppi_sc
     const mppi::EpRule rule = {eo->grasp_tol, eo->width_tol, eo->goal_tol, eo->lift_z, eo->drop_z, eo->t_max};
     mppi::EpState es;
     std::vector<float> x(x0, x0 + NX), xo(NX), nom((size_t)H * NU, 0.f), unew((size_t)H * NU),
-        ubest((size_t)H * NU), terms(7), u1(NU);
+        ubest((size_t)H * NU), terms(mppi::NTERMS), u1(NU);
     std::vector<double> tcomp;
     mppi_opts o = *opts;
     o.flags &= ~(unsigned)(MPPI_SYNC | MPPI_TIME_KERNELS | MPPI_GRAPH);

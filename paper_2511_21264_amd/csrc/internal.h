@@ -41,11 +41,22 @@ int resolve_mapping(const mppi_ctx *c, long K, unsigned flags);
 // same operations; the one-lane form rounds differently.  A request's
 // results are those of its own mapping's family, whatever it is batched with.
 inline int map_family(int map) { return map == mppi::MAP_LANE ? mppi::MAP_LANE : mppi::MAP_TEAM; }
-// the family of a request of K samples planned alone with these flags
-inline int request_family(const mppi_ctx *c, long K, unsigned flags)
+// launch groups of packed batches and of the server's iterations: mapping
+// family (lane, team, task form) x contact-list instantiation (up to 4, up to 8)
+constexpr int NGROUP = 6;
+inline int group_index(int family, int n_cmax)
 {
-    return map_family(resolve_mapping(c, K, flags));
+    const int f = family == mppi::MAP_LANE ? 0 : family == mppi::MAP_TASK ? 2 : 1;
+    return 2 * f + (n_cmax > 4 ? 1 : 0);
 }
+inline int group_family(int g)
+{
+    return (g >> 1) == 0 ? mppi::MAP_LANE : (g >> 1) == 2 ? mppi::MAP_TASK : mppi::MAP_TEAM;
+}
+// the family of a request of K samples planned alone with these flags
+// (scenes with a box object or the further task-cost terms run one sample
+// per lane)
+inline int request_family(const mppi_ctx *c, const mppi_scene *s, long K, unsigned flags);
 // the mapping of a packed launch of total_k samples whose requests all belong
 // to `family` (a pinned mapping wins; else the measured or built-in choice
 // for total_k, kept inside the family)
@@ -100,6 +111,14 @@ struct mppi_scene {
 
 namespace mppi_host {
 int set_device(mppi_ctx *c);
+
+inline int request_family(const mppi_ctx *c, const mppi_scene *s, long K, unsigned flags)
+{
+    return s->host.lane_only ? mppi::MAP_TASK : map_family(resolve_mapping(c, K, flags));
+}
+// the mapping of a launch over K samples of scene s (see resolve_mapping);
+// MPPI_E_INVAL when the flags pin a mapping the scene cannot run in
+int scene_mapping(const mppi_ctx *c, const mppi_scene *s, long K, unsigned flags, int *map);
 
 // Orders a call on stream s after the context's previous call (see
 // mppi_ctx::order_ev): begin() before the first enqueue; the destructor

@@ -83,12 +83,15 @@ struct FinishArgs {
 
 // sample-to-lane mapping of the rollout
 constexpr int MAP_AUTO = 0, MAP_LANE = 1, MAP_TEAM = 2, MAP_WAVE = 3, MAP_SPLIT = 4;
+// one lane per sample, the form that carries the box-shaped object and the
+// further task terms (scenes with obj_box or ext run only in this one)
+constexpr int MAP_TASK = 5;
 int pick_mapping(int K, int requested);
 void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping = MAP_AUTO);
 // the plain form: control step k of every sample (one sample per lane), the
 // per-sample carry in ps ([PLAIN_FIELDS][K] words) between the launches
-constexpr int PLAIN_FIELDS = NX + NU + 7 + 16 + 4;
-void launch_rollout_step(const RolloutArgs &a, int ncmax, float *ps, int k, hipStream_t s);
+constexpr int PLAIN_FIELDS = NX + NU + NTERMS + 16 + 4;
+void launch_rollout_step(const RolloutArgs &a, int ncmax, float *ps, int k, bool task, hipStream_t s);
 int samples_per_block(int mapping);
 // packed launches: tables live in device memory; block b of a rollout launch
 // covers block blk[2b+1] of scene blk[2b]; update blocks are (scene, step)

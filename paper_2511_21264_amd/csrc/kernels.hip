@@ -61,7 +61,9 @@ __device__ __forceinline__ void block_scene(const RolloutArgs &a0, const Rollout
     }
 }
 
-template <int NC>
+// TASK: the form for scenes with a box-shaped object or the further task
+// terms (both switched per scene inside); the plain ball scene runs TASK = false
+template <int NC, bool TASK>
 __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a0, const RolloutArgs *tab, const int *blk, int m)
 {
     extern __shared__ float lds[];
@@ -89,7 +91,7 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a0, const Rollo
     float *dist = a.dist + j;
     CostAcc acc;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
+    for (int i = 0; i < NTERMS; ++i) acc.t[i] = 0.f;
     StepCounters cnt = {0, 0, 0, 0};
     float uprev[NU];
 #pragma unroll
@@ -104,8 +106,8 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a0, const Rollo
             sample_u(a.nu + k * NU, a.sigma + (a.sigma_per_step ? k * NU : 0), md.u_max, a.key0, a.key1, (uint32_t)j,
                      (uint32_t)k, (uint32_t)a.m, u);
         }
-        for (int s = 0; s < nsub; ++s) substep<NC>(model(a.md), x, u, LL, pk, cnt);
-        stage_cost(model(a.md), x, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
+        for (int s = 0; s < nsub; ++s) substep<NC, TASK>(model(a.md), x, u, LL, pk, cnt);
+        stage_cost<TASK>(model(a.md), x, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
 #pragma unroll
         for (int d = 0; d < NU; ++d) uprev[d] = u[d];
         if (a.xout && a.traj) {
@@ -114,15 +116,14 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a0, const Rollo
             for (int i = 0; i < NX; ++i) o[i] = x[i];
         }
     }
-    float c = md.w_goal * acc.t[0] + md.w_eo * acc.t[1] + md.w_l * acc.t[2] + md.w_yz * acc.t[3] +
-              md.w_s * acc.t[4] + md.w_c * (acc.t[5] + acc.t[6]);
+    const float c = total_cost<TASK>(md, acc);
     bool finite = isfinite(c);
 #pragma unroll
     for (int i = 0; i < NX; ++i) finite &= isfinite(x[i]);
     a.costs[j] = finite ? c : INFINITY;
     if (a.terms) {
 #pragma unroll
-        for (int i = 0; i < 7; ++i) a.terms[(long)j * 7 + i] = acc.t[i];
+        for (int i = 0; i < NTERMS; ++i) a.terms[(long)j * NTERMS + i] = acc.t[i];
     }
     if (a.xout && !a.traj) {
 #pragma unroll
@@ -141,9 +142,10 @@ __global__ void __launch_bounds__(64) rollout_kernel(RolloutArgs a0, const Rollo
 // and counters kept in HBM between launches ([field][K], so a wave's loads
 // and stores are coalesced).  The same device functions in the same order as
 // rollout_kernel: the step-k launch loads what launch k - 1 stored.
-constexpr int PS_X = 0, PS_UPREV = NX, PS_ACC = NX + NU, PS_HIST = NX + NU + 7, PS_CNT = PS_HIST + 16;
+constexpr int PS_X = 0, PS_UPREV = NX, PS_ACC = NX + NU, PS_HIST = NX + NU + NTERMS, PS_CNT = PS_HIST + 16;
+static_assert(PS_CNT + 4 == PLAIN_FIELDS, "plain-form carry layout");
 
-template <int NC>
+template <int NC, bool TASK>
 __global__ void __launch_bounds__(64) rollout_step_kernel(RolloutArgs a, float *ps, int k)
 {
     extern __shared__ float lds[];
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(64) rollout_step_kernel(RolloutArgs a, float *
 #pragma unroll
         for (int d = 0; d < NU; ++d) uprev[d] = 0.f;
 #pragma unroll
-        for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
+        for (int i = 0; i < NTERMS; ++i) acc.t[i] = 0.f;
 #pragma unroll
         for (int i = 0; i < 14; ++i) hist.box[i] = 0u;
         hist.aa[0] = hist.aa[1] = 0u;
@@ -179,7 +181,7 @@ __global__ void __launch_bounds__(64) rollout_step_kernel(RolloutArgs a, float *
 #pragma unroll
         for (int d = 0; d < NU; ++d) uprev[d] = ps[(PS_UPREV + d) * K + j];
 #pragma unroll
-        for (int i = 0; i < 7; ++i) acc.t[i] = ps[(PS_ACC + i) * K + j];
+        for (int i = 0; i < NTERMS; ++i) acc.t[i] = TASK || i < 7 ? ps[(PS_ACC + i) * K + j] : 0.f;
 #pragma unroll
         for (int i = 0; i < 14; ++i) hist.box[i] = __float_as_uint(ps[(PS_HIST + i) * K + j]);
         hist.aa[0] = __float_as_uint(ps[(PS_HIST + 14) * K + j]);
@@ -200,8 +202,8 @@ __global__ void __launch_bounds__(64) rollout_step_kernel(RolloutArgs a, float *
         sample_u(a.nu + k * NU, a.sigma + (a.sigma_per_step ? k * NU : 0), md.u_max, a.key0, a.key1, (uint32_t)j,
                  (uint32_t)k, (uint32_t)a.m, u);
     }
-    for (int s = 0; s < nsub; ++s) substep<NC>(model(a.md), x, u, LL, pk, cnt);
-    stage_cost(model(a.md), x, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
+    for (int s = 0; s < nsub; ++s) substep<NC, TASK>(model(a.md), x, u, LL, pk, cnt);
+    stage_cost<TASK>(model(a.md), x, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
     if (a.xout && a.traj) {
         float *o = a.xout + ((long)j * a.H + k) * NX;
 #pragma unroll
@@ -213,7 +215,7 @@ __global__ void __launch_bounds__(64) rollout_step_kernel(RolloutArgs a, float *
 #pragma unroll
         for (int d = 0; d < NU; ++d) ps[(PS_UPREV + d) * K + j] = u[d];
 #pragma unroll
-        for (int i = 0; i < 7; ++i) ps[(PS_ACC + i) * K + j] = acc.t[i];
+        for (int i = 0; i < (TASK ? NTERMS : 7); ++i) ps[(PS_ACC + i) * K + j] = acc.t[i];
 #pragma unroll
         for (int i = 0; i < 14; ++i) ps[(PS_HIST + i) * K + j] = __uint_as_float(hist.box[i]);
         ps[(PS_HIST + 14) * K + j] = __uint_as_float(hist.aa[0]);
@@ -224,15 +226,14 @@ __global__ void __launch_bounds__(64) rollout_step_kernel(RolloutArgs a, float *
         ps[(PS_CNT + 3) * K + j] = __int_as_float(cnt.overflow);
         return;
     }
-    float c = md.w_goal * acc.t[0] + md.w_eo * acc.t[1] + md.w_l * acc.t[2] + md.w_yz * acc.t[3] +
-              md.w_s * acc.t[4] + md.w_c * (acc.t[5] + acc.t[6]);
+    const float c = total_cost<TASK>(md, acc);
     bool finite = isfinite(c);
 #pragma unroll
     for (int i = 0; i < NX; ++i) finite &= isfinite(x[i]);
     a.costs[j] = finite ? c : INFINITY;
     if (a.terms) {
 #pragma unroll
-        for (int i = 0; i < 7; ++i) a.terms[(long)j * 7 + i] = acc.t[i];
+        for (int i = 0; i < NTERMS; ++i) a.terms[(long)j * NTERMS + i] = acc.t[i];
     }
     if (a.xout && !a.traj) {
 #pragma unroll
@@ -367,7 +368,7 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
         a.costs[j] = finite ? c : INFINITY;
         if (a.terms) {
 #pragma unroll
-            for (int i = 0; i < 7; ++i) a.terms[(long)j * 7 + i] = t[i];
+            for (int i = 0; i < NTERMS; ++i) a.terms[(long)j * NTERMS + i] = i < 7 ? t[i] : 0.f;
         }
         if (a.counters) {
             a.counters[4 * j + 0] = cnt.contacts;
@@ -567,7 +568,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
         a.costs[j] = finite ? c : INFINITY;
         if (a.terms) {
 #pragma unroll
-            for (int i = 0; i < 7; ++i) a.terms[(long)j * 7 + i] = t[i];
+            for (int i = 0; i < NTERMS; ++i) a.terms[(long)j * NTERMS + i] = i < 7 ? t[i] : 0.f;
         }
         if (a.counters) {
             a.counters[4 * j + 0] = cnt.contacts;
@@ -580,7 +581,8 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
 
 int pick_mapping(int K, int requested)
 {
-    if (requested == MAP_LANE || requested == MAP_TEAM || requested == MAP_WAVE || requested == MAP_SPLIT)
+    if (requested == MAP_LANE || requested == MAP_TEAM || requested == MAP_WAVE || requested == MAP_SPLIT ||
+        requested == MAP_TASK)
         return requested;
     // the chip holds 1024 SIMDs: up to ~2 samples per SIMD a wave per sample
     // gives the shortest steps; up to tens of thousands a 16-lane team per
@@ -624,10 +626,17 @@ static void launch_rollout_impl(const RolloutArgs &a, const RolloutArgs *tab, co
         return;
     }
     const size_t lds = (size_t)(nc * CL_FIELDS + PK_FIELDS) * 64 * sizeof(float);
+    if (map == MAP_TASK) {
+        if (nc == 4)
+            hipLaunchKernelGGL((rollout_kernel<4, true>), grid, block, lds, s, a, tab, blk, m);
+        else
+            hipLaunchKernelGGL((rollout_kernel<8, true>), grid, block, lds, s, a, tab, blk, m);
+        return;
+    }
     if (nc == 4)
-        hipLaunchKernelGGL(rollout_kernel<4>, grid, block, lds, s, a, tab, blk, m);
+        hipLaunchKernelGGL((rollout_kernel<4, false>), grid, block, lds, s, a, tab, blk, m);
     else
-        hipLaunchKernelGGL(rollout_kernel<8>, grid, block, lds, s, a, tab, blk, m);
+        hipLaunchKernelGGL((rollout_kernel<8, false>), grid, block, lds, s, a, tab, blk, m);
 }
 
 void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping)
@@ -637,15 +646,22 @@ void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping)
     launch_rollout_impl(a, nullptr, nullptr, (a.K + per - 1) / per, ncmax, a.m, map, s);
 }
 
-void launch_rollout_step(const RolloutArgs &a, int ncmax, float *ps, int k, hipStream_t s)
+void launch_rollout_step(const RolloutArgs &a, int ncmax, float *ps, int k, bool task, hipStream_t s)
 {
     const int nc = ncmax <= 4 ? 4 : 8;
     const size_t lds = (size_t)(nc * CL_FIELDS + PK_FIELDS) * 64 * sizeof(float);
     const dim3 grid((a.K + 63) / 64), block(64);
-    if (nc == 4)
-        hipLaunchKernelGGL(rollout_step_kernel<4>, grid, block, lds, s, a, ps, k);
-    else
-        hipLaunchKernelGGL(rollout_step_kernel<8>, grid, block, lds, s, a, ps, k);
+    if (task) {
+        if (nc == 4)
+            hipLaunchKernelGGL((rollout_step_kernel<4, true>), grid, block, lds, s, a, ps, k);
+        else
+            hipLaunchKernelGGL((rollout_step_kernel<8, true>), grid, block, lds, s, a, ps, k);
+    } else {
+        if (nc == 4)
+            hipLaunchKernelGGL((rollout_step_kernel<4, false>), grid, block, lds, s, a, ps, k);
+        else
+            hipLaunchKernelGGL((rollout_step_kernel<8, false>), grid, block, lds, s, a, ps, k);
+    }
 }
 
 void launch_rollout_batch(const RolloutArgs *d_tab, const int *d_blk, int nblk, int ncmax, int m, int map,
@@ -1013,10 +1029,29 @@ __global__ void narrowphase_kernel(const DevModel *md, const float *X, int n, fl
     fk_arm(*md, 1, x + XQ + 7, kin[1]);
     const V3 pb = v3(x[XPB], x[XPB + 1], x[XPB + 2]);
     const int np = md->n_pairs;
+    // a box-shaped object: its pose, and its pairs through the box narrowphase
+    // (against the table: the deepest vertex, the lowest index on ties)
+    const bool box = md->obj_box != 0;
+    const Rot3 R = quat_R(x[XQUAT], x[XQUAT + 1], x[XQUAT + 2], x[XQUAT + 3]);
+    const V3 oh = v3(md->obj_h[0], md->obj_h[1], md->obj_h[2]);
     for (int p = 0; p < np; ++p) {
         const Shape A = geom_shape(*md, kin, pb, md->pa[p]);
         const Shape B = geom_shape(*md, kin, pb, md->pb[p]);
-        const Contact3 c = narrow(A, B);
+        Contact3 c;
+        if (box && md->pa[p] == G_BALL && B.type == SH_PLANE) {
+            V3 lowest = obox_vertex(pb, R, oh, 0);
+            for (int k = 1; k < 8; ++k) {
+                const V3 v = obox_vertex(pb, R, oh, k);
+                if (v.z < lowest.z) lowest = v;
+            }
+            c.phi = lowest.z;
+            c.n = v3(0.f, 0.f, 1.f);
+            c.p = v3(lowest.x, lowest.y, 0.5f * lowest.z);
+        } else if (box && md->pa[p] == G_BALL) {
+            c = B.type == SH_BOX ? obox_box(pb, R, oh, B.p0, B.p1) : obox_core(pb, R, oh, B);
+        } else {
+            c = narrow(A, B);
+        }
         const long o = (long)i * np + p;
         phi[o] = c.phi;
         if (nrm) { nrm[3 * o] = c.n.x; nrm[3 * o + 1] = c.n.y; nrm[3 * o + 2] = c.n.z; }
@@ -1025,7 +1060,7 @@ __global__ void narrowphase_kernel(const DevModel *md, const float *X, int n, fl
     if (lo && hi) {
         const int ng = G_BOX + md->n_box;
         for (int g = 0; g < ng; ++g) {
-            const AABB b = shape_aabb(geom_shape(*md, kin, pb, g));
+            const AABB b = box && g == G_BALL ? obox_aabb(pb, R, oh) : shape_aabb(geom_shape(*md, kin, pb, g));
             const long o = ((long)i * ng + g) * 3;
             lo[o] = b.lo.x; lo[o + 1] = b.lo.y; lo[o + 2] = b.lo.z;
             hi[o] = b.hi.x; hi[o + 1] = b.hi.y; hi[o + 2] = b.hi.z;

@@ -313,15 +313,14 @@ int launch_iteration(mppi_server *S, int b, const std::vector<Req *> &act, const
     // up to 4, or up to 8), so a request's results and its cell's advance do
     // not depend on what else is in flight.
     auto group_of = [&](const Req *R) {
-        const int fam = request_family(S->ctx, R->K, S->o.flags) == MAP_LANE ? 0 : 1;
-        return 2 * fam + (R->scene->host.n_cmax > 4 ? 1 : 0);
+        return group_index(request_family(S->ctx, R->scene, R->K, S->o.flags), R->scene->host.n_cmax);
     };
-    long grp_k[4] = {0, 0, 0, 0};
+    long grp_k[NGROUP] = {};
     for (Req *R : act) grp_k[group_of(R)] += R->K;
-    int gmap[4];
-    for (int g = 0; g < 4; ++g)
-        gmap[g] = family_launch_mapping(S->ctx, g < 2 ? MAP_LANE : MAP_TEAM, grp_k[g], S->o.flags);
-    std::vector<int> gblk[4], gablk[4], ublk;
+    int gmap[NGROUP];
+    for (int g = 0; g < NGROUP; ++g)
+        gmap[g] = family_launch_mapping(S->ctx, group_family(g), grp_k[g], S->o.flags);
+    std::vector<int> gblk[NGROUP], gablk[NGROUP], ublk;
     for (int i = 0; i < n; ++i) {
         const int g = group_of(act[i]), per = samples_per_block(gmap[g]);
         const int nb = (act[i]->K + per - 1) / per;
@@ -337,11 +336,11 @@ int launch_iteration(mppi_server *S, int b, const std::vector<Req *> &act, const
             gablk[group_of(R)].push_back(0);
             adv.push_back(R);
         }
-    int amap[4];
-    for (int g = 0; g < 4; ++g) amap[g] = family_launch_mapping(S->ctx, g < 2 ? MAP_LANE : MAP_TEAM, 1, S->o.flags);
+    int amap[NGROUP];
+    for (int g = 0; g < NGROUP; ++g) amap[g] = family_launch_mapping(S->ctx, group_family(g), 1, S->o.flags);
     std::vector<int> blk, ablk;
-    size_t goff[4], gaoff[4];
-    for (int g = 0; g < 4; ++g) {
+    size_t goff[NGROUP], gaoff[NGROUP];
+    for (int g = 0; g < NGROUP; ++g) {
         goff[g] = blk.size();
         blk.insert(blk.end(), gblk[g].begin(), gblk[g].end());
         gaoff[g] = ablk.size();
@@ -420,14 +419,14 @@ int launch_iteration(mppi_server *S, int b, const std::vector<Req *> &act, const
     std::memcpy(h + o_ub, ublk.data(), ublk.size() * sizeof(int));
     std::memcpy(h + o_ab, ablk.data(), ablk.size() * sizeof(int));
     HIPCHK(hipMemcpyAsync(d, h, o, hipMemcpyHostToDevice, s));
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < NGROUP; ++g)
         if (!gblk[g].empty())
             launch_rollout_batch((const RolloutArgs *)(d + o_r), (const int *)(d + o_b) + goff[g],
                                  (int)gblk[g].size() / 2, (g & 1) ? 8 : 4, -1, gmap[g], s);
     launch_stats_batch((const StatsArgs *)(d + o_s), n, -1, s);
     launch_update_batch((const UpdateArgs *)(d + o_u), (const int *)(d + o_ub), (int)ublk.size() / 2, -1, s);
     if (nf) launch_finish_batch((const FinishArgs *)(d + o_f), nf, s);
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < NGROUP; ++g)
         if (!gablk[g].empty())
             launch_rollout_batch((const RolloutArgs *)(d + o_a), (const int *)(d + o_ab) + gaoff[g],
                                  (int)gablk[g].size() / 2, (g & 1) ? 8 : 4, 0, amap[g], s);
@@ -716,6 +715,8 @@ int mppi_submit(mppi_server *S, const mppi_request *req, int cell, int advance, 
         R.H = req->H;
     }
     if (R.scene->ctx != S->ctx) return fail(MPPI_E_INVAL, "scene of another context");
+    int map_r;
+    if (scene_mapping(S->ctx, R.scene, req->K, S->o.flags, &map_r)) return MPPI_E_INVAL;
     if (R.K < 1 || R.K > MPPI_MAX_K || R.H < 1 || R.H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "K or H out of range");
     if (!(req->lambda > 0) || !std::isfinite(req->lambda) || R.M < 1 || R.M > 100000 || !std::isfinite(req->opts.eta))
         return fail(MPPI_E_INVAL, "bad lambda, M or eta");

@@ -11,6 +11,11 @@
 //      n_pgs sweeps from f = 0, rows in contact order;
 //   5. qd+ = qd_f + Mt^-1 J^T f, semi-implicit Euler q += h qd+, p += h v+,
 //      r <- normalize(exp(h w+/2) (x) r).
+// With a box-shaped object (the BOX forms) the object's inverse inertia is
+// W = R diag(1/I) R^T in the world frame, its free angular velocity takes
+// the explicit gyroscopic step w - h W (w x I_w w), and its contacts are the
+// box's: up to four vertices below the table (vertex order), pads and links
+// against the box in its own frame, static boxes by separating axes.
 //
 // Layout of the contact solve (impulse space).  A contact's four rows share
 // its 3-row point Jacobian J_s (relative velocity of the touching points), so
@@ -56,6 +61,20 @@ struct LaneList {
     __device__ __forceinline__ float &at(int slot, int f) const { return base[(slot * CL_FIELDS + f) * width + lane]; }
 };
 
+__device__ __forceinline__ void push_contact(const LaneList &L, int &n, int ga, int gb, const Contact3 &c)
+{
+    L.at(n, 0) = __int_as_float(ga);
+    L.at(n, 1) = __int_as_float(gb);
+    L.at(n, 2) = c.phi;
+    L.at(n, 3) = c.n.x;
+    L.at(n, 4) = c.n.y;
+    L.at(n, 5) = c.n.z;
+    L.at(n, 6) = c.p.x;
+    L.at(n, 7) = c.p.y;
+    L.at(n, 8) = c.p.z;
+    ++n;
+}
+
 __device__ __forceinline__ void try_contact(const DevModel &md, const LaneList &L, int &n, StepCounters &cnt, int ga,
                                             int gb, const Shape &A, const Shape &B, const AABB &ba, const AABB &bb)
 {
@@ -63,18 +82,26 @@ __device__ __forceinline__ void try_contact(const DevModel &md, const LaneList &
         ++cnt.np_tests;
         if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
         const Contact3 c = narrow(A, B);
-        if (c.phi < 0.f) {
-            L.at(n, 0) = __int_as_float(ga);
-            L.at(n, 1) = __int_as_float(gb);
-            L.at(n, 2) = c.phi;
-            L.at(n, 3) = c.n.x;
-            L.at(n, 4) = c.n.y;
-            L.at(n, 5) = c.n.z;
-            L.at(n, 6) = c.p.x;
-            L.at(n, 7) = c.p.y;
-            L.at(n, 8) = c.p.z;
-            ++n;
-        }
+        if (c.phi < 0.f) push_contact(L, n, ga, gb, c);
+    }
+}
+
+// pose of a box-shaped object: centre, rotation, half extents, world AABB
+struct ObjPose {
+    V3 c;
+    Rot3 R;
+    V3 h;
+    AABB bb;
+};
+
+// the box object (geom A) against a pad, a link or a static box
+__device__ __forceinline__ void try_obj_contact(const DevModel &md, const LaneList &L, int &n, StepCounters &cnt,
+                                                int gb, const ObjPose &o, const Shape &B, const AABB &bb)
+{
+    if (n < md.n_cmax && aabb_overlap(o.bb, bb, 0.f)) {
+        ++cnt.np_tests;
+        const Contact3 c = B.type == SH_BOX ? obox_box(o.c, o.R, o.h, B.p0, B.p1) : obox_core(o.c, o.R, o.h, B);
+        if (c.phi < 0.f) push_contact(L, n, G_BALL, gb, c);
     }
 }
 
@@ -113,9 +140,11 @@ __device__ __forceinline__ Shape ball_shape(const DevModel &md, V3 pb)
     return s;
 }
 
-// sweep every candidate pair in canonical order; returns the contact count
-__device__ inline int collect_contacts(const DevModel &md, const ArmKin kin[2], V3 pb, const LaneList &L,
-                                       StepCounters &cnt)
+// sweep every candidate pair in canonical order; returns the contact count.
+// BOX: the object is the box of pose o (pb unused)
+template <bool BOX>
+__device__ inline int collect_contacts(const DevModel &md, const ArmKin kin[2], V3 pb, const ObjPose &o,
+                                       const LaneList &L, StepCounters &cnt)
 {
     int n = 0;
     const Shape ball = ball_shape(md, pb), table = table_shape();
@@ -129,21 +158,53 @@ __device__ inline int collect_contacts(const DevModel &md, const ArmKin kin[2], 
             arm[a][g] = arm_shape(md, kin[a], g);
             barm[a][g] = shape_aabb(arm[a][g]);
         }
-    // 1 ball-table
-    try_contact(md, L, n, cnt, G_BALL, G_TABLE, ball, table, bball, btab);
-    // 2 ball-pads
+    if (BOX) {
+        // 1 object-table: the vertices below the plane, four at most
+        if (o.bb.lo.z < 0.f) {
+            ++cnt.np_tests;
+            int taken = 0;
 #pragma unroll
-    for (int a = 0; a < 2; ++a) try_contact(md, L, n, cnt, G_BALL, G_ARM + 7 * a + 6, ball, arm[a][6], bball, barm[a][6]);
-    // 3 ball-links
+            for (int k = 0; k < 8; ++k) {
+                const V3 v = obox_vertex(o.c, o.R, o.h, k);
+                if (v.z < 0.f && n < md.n_cmax && taken < 4) {
+                    Contact3 c;
+                    c.phi = v.z;
+                    c.n = v3(0.f, 0.f, 1.f);
+                    c.p = v3(v.x, v.y, 0.5f * v.z);
+                    push_contact(L, n, G_BALL, G_TABLE, c);
+                    ++taken;
+                }
+            }
+        }
+        // 2 object-pads, 3 object-links, 4 object-boxes
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a) try_obj_contact(md, L, n, cnt, G_ARM + 7 * a + 6, o, arm[a][6], barm[a][6]);
 #pragma unroll
-        for (int g = 0; g < 6; ++g)
-            try_contact(md, L, n, cnt, G_BALL, G_ARM + 7 * a + g, ball, arm[a][g], bball, barm[a][g]);
-    // 4 ball-boxes
-    for (int b = 0; b < md.n_box; ++b) {
-        const Shape bx = box_shape(md, b);
-        try_contact(md, L, n, cnt, G_BALL, G_BOX + b, ball, bx, bball, shape_aabb(bx));
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int g = 0; g < 6; ++g) try_obj_contact(md, L, n, cnt, G_ARM + 7 * a + g, o, arm[a][g], barm[a][g]);
+        for (int b = 0; b < md.n_box; ++b) {
+            const Shape bx = box_shape(md, b);
+            try_obj_contact(md, L, n, cnt, G_BOX + b, o, bx, shape_aabb(bx));
+        }
+    } else {
+        // 1 ball-table
+        try_contact(md, L, n, cnt, G_BALL, G_TABLE, ball, table, bball, btab);
+        // 2 ball-pads
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+            try_contact(md, L, n, cnt, G_BALL, G_ARM + 7 * a + 6, ball, arm[a][6], bball, barm[a][6]);
+        // 3 ball-links
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int g = 0; g < 6; ++g)
+                try_contact(md, L, n, cnt, G_BALL, G_ARM + 7 * a + g, ball, arm[a][g], bball, barm[a][g]);
+        // 4 ball-boxes
+        for (int b = 0; b < md.n_box; ++b) {
+            const Shape bx = box_shape(md, b);
+            try_contact(md, L, n, cnt, G_BALL, G_BOX + b, ball, bx, bball, shape_aabb(bx));
+        }
     }
     // 5 arm geoms 2..7 - table
 #pragma unroll
@@ -244,6 +305,22 @@ __device__ __forceinline__ void ball_block(const DevModel &md, V3 rs, V3 rt, flo
     G[8] += im + iI * (d - rt.z * rs.z);
 }
 
+// box part of G_st: I/m - [r_s]x W [r_t]x, column j = e_j / m - r_s x (W (r_t x e_j))
+// (W symmetric, row-major)
+__device__ __forceinline__ V3 mul9(const float G[9], V3 v);
+__device__ __forceinline__ void obj_block(const DevModel &md, const float W[9], V3 rs, V3 rt, float G[9])
+{
+    const float im = md.inv_ball_m;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const V3 e = v3(j == 0 ? 1.f : 0.f, j == 1 ? 1.f : 0.f, j == 2 ? 1.f : 0.f);
+        const V3 col = cross(rs, mul9(W, cross(rt, e)));
+        G[j] += (j == 0 ? im : 0.f) - col.x;
+        G[3 + j] += (j == 1 ? im : 0.f) - col.y;
+        G[6 + j] += (j == 2 ? im : 0.f) - col.z;
+    }
+}
+
 __device__ __forceinline__ V3 mul9(const float G[9], V3 v)
 {
     return v3(G[0] * v.x + G[1] * v.y + G[2] * v.z, G[3] * v.x + G[4] * v.y + G[5] * v.z,
@@ -269,9 +346,11 @@ struct Slots {
     float G[NC][NC][9];   // G_st for s <= t
 };
 
-template <int NC>
+// BOX: the object's inverse inertia is W (world frame, row-major), else 1/I_b
+template <int NC, bool BOX = false>
 __device__ inline void contact_solve(const DevModel &md, const ArmKin kin[2], const LanePark &pk, V3 pb,
-                                     const LaneList &LL, int nc, float v[14], V3 &vb, V3 &wb)
+                                     const LaneList &LL, int nc, float v[14], V3 &vb, V3 &wb,
+                                     const float *W = nullptr)
 {
     Slots<NC> S;
     bool any_arm = false;
@@ -302,7 +381,12 @@ __device__ inline void contact_solve(const DevModel &md, const ArmKin kin[2], co
                 if (s < nc) {
                     float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                     const Sides ss = contact_sides(S.gab[s]);
-                    if (ss.ball & st.ball) ball_block(md, S.r[s], S.r[t], G);
+                    if (ss.ball & st.ball) {
+                        if (BOX)
+                            obj_block(md, W, S.r[s], S.r[t], G);
+                        else
+                            ball_block(md, S.r[s], S.r[t], G);
+                    }
 #pragma unroll
                     for (int i = 0; i < 9; ++i) S.G[s][t][i] = G[i];
                 }
@@ -400,7 +484,10 @@ __device__ inline void contact_solve(const DevModel &md, const ArmKin kin[2], co
         if (s < nc) {
             if (contact_sides(S.gab[s]).ball) {
                 vb = fma3(md.inv_ball_m, S.P[s], vb);
-                wb = fma3(md.inv_ball_I, cross(S.r[s], S.P[s]), wb);
+                if (BOX)
+                    wb = wb + mul9(W, cross(S.r[s], S.P[s]));
+                else
+                    wb = fma3(md.inv_ball_I, cross(S.r[s], S.P[s]), wb);
             }
         }
     }
@@ -495,7 +582,7 @@ __device__ inline void ball_contact_solve(const DevModel &md, const LaneList &LL
     wb = fma3(md.inv_ball_I, cross(r, P), wb);
 }
 
-template <int NC>
+template <int NC, bool BOX = false>
 __device__ inline void substep(const DevModel &md, float x[NX], const float u[NU], const LaneList &LL,
                                const LanePark &pk, StepCounters &cnt)
 {
@@ -543,12 +630,36 @@ __device__ inline void substep(const DevModel &md, float x[NX], const float u[NU
     V3 vb = v3(x[XVB], x[XVB + 1], x[XVB + 2] - h * md.g);
     V3 wb = v3(x[XWB], x[XWB + 1], x[XWB + 2]);
 
-    const int nc = collect_contacts(md, kin, pb, LL, cnt);
-    if (nc == 1 && __float_as_int(LL.at(0, 0)) == G_BALL &&
-        (__float_as_int(LL.at(0, 1)) == G_TABLE || __float_as_int(LL.at(0, 1)) >= G_BOX))
-        ball_contact_solve(md, LL, pb, vb, wb);
-    else if (nc > 0)
-        contact_solve<NC>(md, kin, pk, pb, LL, nc, v, vb, wb);
+    if (BOX && md.obj_box) {
+        ObjPose o;
+        o.c = pb;
+        o.R = quat_R(x[XQUAT], x[XQUAT + 1], x[XQUAT + 2], x[XQUAT + 3]);
+        o.h = v3(md.obj_h[0], md.obj_h[1], md.obj_h[2]);
+        o.bb = obox_aabb(o.c, o.R, o.h);
+        // W = R diag(1/I) R^T; free w: w - h R diag(1/I) (w_b x (I w_b)), w_b = R^T w
+        float W[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                W[3 * i + j] = o.R.m[3 * i] * o.R.m[3 * j] * md.obj_iI[0] +
+                               o.R.m[3 * i + 1] * o.R.m[3 * j + 1] * md.obj_iI[1] +
+                               o.R.m[3 * i + 2] * o.R.m[3 * j + 2] * md.obj_iI[2];
+        const V3 wbb = mulRt(o.R, wb);
+        const V3 Lb = v3(md.obj_I[0] * wbb.x, md.obj_I[1] * wbb.y, md.obj_I[2] * wbb.z);
+        const V3 gb = cross(wbb, Lb);
+        wb = wb - h * mulR(o.R, v3(md.obj_iI[0] * gb.x, md.obj_iI[1] * gb.y, md.obj_iI[2] * gb.z));
+        const int nc = collect_contacts<true>(md, kin, pb, o, LL, cnt);
+        if (nc > 0) contact_solve<NC, true>(md, kin, pk, pb, LL, nc, v, vb, wb, W);
+    } else {
+        ObjPose o0;
+        const int nc = collect_contacts<false>(md, kin, pb, o0, LL, cnt);
+        if (nc == 1 && __float_as_int(LL.at(0, 0)) == G_BALL &&
+            (__float_as_int(LL.at(0, 1)) == G_TABLE || __float_as_int(LL.at(0, 1)) >= G_BOX))
+            ball_contact_solve(md, LL, pb, vb, wb);
+        else if (nc > 0)
+            contact_solve<NC>(md, kin, pk, pb, LL, nc, v, vb, wb);
+    }
 
 #pragma unroll
     for (int i = 0; i < 14; ++i) {

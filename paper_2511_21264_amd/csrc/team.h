@@ -1404,7 +1404,7 @@ __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc,
         const V3 d12 = p1 - p2;
         acc.t[0] += sqrtf(dot(dg, dg));
         acc.t[1] += sqrtf(dot(de, de));
-        const float l = sqrtf(dot(d12, d12)) - md.l_ball;
+        const float l = sqrtf(dot(d12, d12)) - md.l_cost;
         acc.t[2] += l * l;
         acc.t[3] += sqrtf(d12.y * d12.y + d12.z * d12.z);
     }

@@ -150,13 +150,13 @@ def test_collision_cost_terms_on_box_scenes(mp, ctx, oracle_mod, name, mapping):
         _ORACLE_ROLLOUTS[name] = [(o.rollout(f32(X[i]), f32(U[i]), want_traj=True),
                                    _flip_margin(o, sc, f32(X[i]), f32(U[i]))) for i in range(n)]
     costs = torch.zeros(n, device=DEV)
-    terms = torch.zeros((n, 7), device=DEV)
+    terms = torch.zeros((n, mp.NTERMS), device=DEV)
     Xo = torch.zeros((n, H, 55), device=DEV)
     mp.mppi_simulate(ctx, scene, T(X), T(U), costs=costs, terms=terms, X_out=Xo, traj=True, mapping=mapping)
     torch.cuda.synchronize()
     tg, cg, xg = terms.cpu().numpy().astype(np.float64), costs.cpu().numpy(), Xo.cpu().numpy().astype(np.float64)
     kept, n_ind, n_bar = 0, 0.0, 0
-    worst = np.zeros(7)
+    worst = np.zeros(mp.NTERMS)
     for i in range(n):
         (c, tm, traj), (m_phi, m_d) = _ORACLE_ROLLOUTS[name][i]
         if m_phi < 2e-5 or m_d < 2e-5:

@@ -195,7 +195,7 @@ def test_contact_free_rollout_20_steps(mp, ctx, oracle_mod, mapping):
     U = rng.uniform(-1.0, 1.0, (n, H, 14)).astype(np.float32)
     Xo = torch.zeros((n, H, 55), device=DEV)
     costs = torch.zeros(n, device=DEV)
-    terms = torch.zeros((n, 7), device=DEV)
+    terms = torch.zeros((n, mp.NTERMS), device=DEV)
     mp.mppi_simulate(ctx, scene, T(X), T(U), costs=costs, terms=terms, X_out=Xo, traj=True, mapping=mapping)
     torch.cuda.synchronize()
     got = Xo.cpu().numpy().astype(np.float64)
@@ -386,7 +386,7 @@ def test_lane_and_team_mappings_agree(mp, ctx):
     out = {}
     for mapping in ("lane", "team"):
         c = torch.zeros(n, device=DEV)
-        tm = torch.zeros((n, 7), device=DEV)
+        tm = torch.zeros((n, mp.NTERMS), device=DEV)
         mp.mppi_simulate(ctx, scene, x0, U, costs=c, terms=tm, x0_shared=True, mapping=mapping)
         torch.cuda.synchronize()
         out[mapping] = c.cpu().numpy()
@@ -504,7 +504,7 @@ def test_team_wave_split_mappings_bit_identical(mp, ctx):
     out = {}
     for mapping in ("team", "wave", "split"):
         c = torch.zeros(n, device=DEV)
-        tm = torch.zeros((n, 7), device=DEV)
+        tm = torch.zeros((n, mp.NTERMS), device=DEV)
         xo = torch.zeros((n, H, 55), device=DEV)
         mp.mppi_simulate(ctx, scene, X0, U, costs=c, terms=tm, X_out=xo, traj=True, mapping=mapping)
         torch.cuda.synchronize()

@@ -1,0 +1,447 @@
+"""GPU parity on the tray-moving and hand-over scenes (a box-shaped free
+object, the further task-cost terms of Sec. IV), against the FP64 oracle on
+the same inputs:
+
+* one physics substep from states with the object pressed into the table
+  (one to four vertices below it), touched by a pad, or overlapping a
+  static box, and from states where it tumbles freely (the gyroscopic step);
+* the narrowphase stage on the same states (box - table, box - pad / link,
+  box - static box by separating axes);
+* rollouts of every task phase with all 17 cost terms;
+* plans from the resting object (the oracle's plan);
+* the routing rules: these scenes run one sample per lane only, the plain
+  per-step form equals the lane form bit for bit, and packed batches and
+  served requests that mix them with ball scenes equal each plan alone.
+
+Every input state is seeded and chosen with the oracle's geometry, with
+every contact and cost switch clear of zero (FP32 and FP64 may disagree on
+which side of zero a distance of 1e-6 lies); no GPU value enters an input or
+an expected value.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+GROUPS = [(0, 7), (7, 14), (14, 21), (21, 28), (28, 35), (35, 42), (42, 45), (45, 49), (49, 52), (52, 55)]
+PHASES = [("tray", "pick"), ("tray", "move"), ("handover", "pick"), ("handover", "pass"), ("handover", "place")]
+CLEAR = 2e-4   # every |phi| and |d| at least this far from zero
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import paper_2511_21264_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mp):
+    c = mp.Context(0)
+    yield c
+    c.close()
+
+
+def T(a, dtype=torch.float32):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _scales(want, lever):
+    """Largest magnitude of each group of coordinates; the object's spin
+    error follows its linear velocity over its smallest half extent."""
+    out = []
+    for a, b in GROUPS:
+        scale = max(np.abs(want[..., a:b]).max(), 1e-3)
+        if a == 52:
+            scale = max(scale, np.abs(want[..., 49:52]).max() / lever)
+        out.append(scale)
+    return out
+
+
+def _close(got, want, rtol, lever, what=""):
+    for (a, b), scale in zip(GROUPS, _scales(want, lever)):
+        err = np.abs(got[..., a:b] - want[..., a:b]).max()
+        assert err <= rtol * scale, (what, a, b, err, scale)
+
+
+def _quat(rng):
+    q = rng.normal(size=4)
+    return q / np.linalg.norm(q)
+
+
+def _vertices(o, sc, x):
+    R, _ = o.quat_R(x[45:49])
+    h = np.asarray(sc["obj_h"], dtype=np.float64)
+    s = np.array([[1 if k & 1 else -1, 1 if k & 2 else -1, 1 if k & 4 else -1] for k in range(8)], dtype=np.float64)
+    return x[42:45] + (s * h) @ R.T
+
+
+def _margin(o, sc, x):
+    """Smallest |phi| over every pair and every vertex height (the object's
+    table contacts), and smallest gap between the object's two best support
+    vertices along each box-contact normal (a tie decides the contact point)."""
+    phi, nrm, _ = o.narrow_all(x)
+    m = min(np.abs(phi).min(), np.abs(_vertices(o, sc, x)[:, 2]).min())
+    pa, pb = o.pairs()
+    V = _vertices(o, sc, x)
+    for p in range(len(phi)):
+        if pa[p] == 0 and pb[p] >= 16 and phi[p] < 0.0:
+            e = np.sort(V @ -nrm[p])[::-1]
+            m = min(m, e[0] - e[1])
+    return m
+
+
+def _free_state(rng, sc, home_spread=0.3):
+    x = W.initial_state(sc)
+    x[0:14] = np.asarray(sc["q_home"]) + rng.uniform(-home_spread, home_spread, 14)
+    x[28:42] = x[0:14] + rng.uniform(-0.05, 0.05, 14)
+    x[14:28] = rng.uniform(-0.5, 0.5, 14)
+    return x
+
+
+def _substep_states(o, sc, n, seed):
+    """Seeded states in four kinds, in turn: the object pressed into the
+    table (tilted, 1-8 mm deep), a pad pressed into one of its faces, the
+    object overlapping a static box, the object tumbling in free flight."""
+    rng = np.random.default_rng(seed)
+    h = np.asarray(sc["obj_h"], dtype=np.float64)
+    out, kinds = [], []
+    tries = 0
+    while len(out) < n:
+        tries += 1
+        assert tries < 200 * n, "state search did not converge"
+        kind = len(out) % 4
+        x = _free_state(rng, sc)
+        x[45:49] = _quat(rng)
+        x[49:52] = rng.uniform(-0.5, 0.5, 3)
+        x[52:55] = rng.uniform(-3.0, 3.0, 3)
+        if kind == 0:
+            if len(out) % 8 == 0:  # nearly flat: all four bottom vertices below the table
+                yaw, tilt = rng.uniform(0, 2 * np.pi), rng.uniform(0.0, 0.05)
+                ax = rng.normal(size=3)
+                ax[2] = 0.0
+                ax /= np.linalg.norm(ax)
+                qy = np.array([np.cos(yaw / 2), 0.0, 0.0, np.sin(yaw / 2)])
+                qt = np.concatenate([[np.cos(tilt / 2)], np.sin(tilt / 2) * ax])
+                w1, v1, w2, v2 = qt[0], qt[1:], qy[0], qy[1:]
+                x[45:49] = np.concatenate([[w1 * w2 - v1 @ v2], w1 * v2 + w2 * v1 + np.cross(v1, v2)])
+            x[42:44] = rng.uniform(-0.2, 0.2, 2)
+            x[44] = 0.0
+            x[44] = -_vertices(o, sc, x)[:, 2].min() - rng.uniform(1e-3, 8e-3)
+        elif kind == 1:
+            arm = int(rng.integers(2))
+            _, org, _, _ = o.fk(arm, x[7 * arm:7 * arm + 7])
+            R, _ = o.quat_R(x[45:49])
+            face = int(rng.integers(3))
+            sgn = 1.0 if rng.random() < 0.5 else -1.0
+            depth = rng.uniform(1e-3, 5e-3)
+            lateral = rng.uniform(-0.6, 0.6, 3) * h
+            lateral[face] = sgn * (h[face] + float(sc["pad_rad"]) - depth)
+            x[42:45] = np.asarray(org[7]) - R @ lateral
+        elif kind == 2:
+            b = int(rng.integers(int(sc["n_box"])))
+            bc, bh = np.asarray(sc["box_c"][b]), np.asarray(sc["box_h"][b])
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            target = -rng.uniform(1e-3, 6e-3)
+            lo, hi = 0.0, 2.0
+            for _ in range(60):  # bisection on the separating-axes distance along the ray
+                t = 0.5 * (lo + hi)
+                x[42:45] = bc + t * d
+                phi = o.obj_prim(x[42:49], 3, bc, bh)[0]
+                lo, hi = (t, hi) if phi < target else (lo, t)
+            x[42:45] = bc + hi * d
+        else:
+            x[42:45] = [rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), 0.6]
+            x[52:55] = rng.uniform(-8.0, 8.0, 3)
+        if _vertices(o, sc, x)[:, 2].min() < -0.01 or o.narrow_all(x)[0].min() < -0.01:
+            continue
+        if _margin(o, sc, x) < CLEAR:
+            continue
+        nc = len(o.contacts(x)[0])
+        if kind < 3 and nc == 0 or nc > int(sc["n_cmax"]):
+            continue
+        out.append(x)
+        kinds.append(kind)
+    return np.array(out), kinds
+
+
+@pytest.mark.parametrize("task,phase", [("tray", "pick"), ("handover", "pass")])
+def test_one_substep_box_object(mp, ctx, oracle_mod, task, phase):
+    """One substep (n_sub = 1, one control step) of 96 seeded states against
+    the oracle's substep: the box's table vertices, pad and static-box
+    contacts, the solve with the world-frame inverse inertia, the gyroscopic
+    step and the quaternion update."""
+    sc = W.task_scene(task, phase)
+    o = oracle_mod.Oracle(sc)
+    scene = mp.Scene(ctx, sc)
+    n = 96
+    X, kinds = _substep_states(o, sc, n, seed=11 if task == "tray" else 12)
+    X = f32(X.astype(np.float32))
+    U = np.random.default_rng(5).uniform(-1.0, 1.0, (n, 1, 14)).astype(np.float32)
+    Xo = torch.zeros((n, 1, 55), device=DEV)
+    mp.mppi_simulate(ctx, scene, T(X), T(U), X_out=Xo, n_sub=1, traj=True)
+    torch.cuda.synchronize()
+    got = Xo.cpu().numpy()[:, 0].astype(np.float64)
+    lever = float(np.min(sc["obj_h"]))
+    ncs = []
+    for i in range(n):
+        if _margin(o, sc, X[i]) < CLEAR:
+            continue  # the FP32 copy of the state moved a switch too near zero
+        want, nc = o.substep(X[i], f32(U[i, 0]))
+        ncs.append(nc)
+        _close(got[i], want, 2e-4, lever, f"{task} state {i} kind {kinds[i]} contacts {nc}")
+    print(f"{task}/{phase}: contacts per state {np.bincount(ncs)}")
+    assert max(ncs) >= 4
+    scene.close()
+
+
+@pytest.mark.parametrize("task,phase", [("tray", "move"), ("handover", "pick")])
+def test_narrowphase_box_object(mp, ctx, oracle_mod, task, phase):
+    """Every pair's phi, normal and point, and the object's AABB, against
+    the oracle's narrowphase on the same states."""
+    sc = W.task_scene(task, phase)
+    o = oracle_mod.Oracle(sc)
+    scene = mp.Scene(ctx, sc)
+    n = 64
+    X, _ = _substep_states(o, sc, n, seed=21 if task == "tray" else 22)
+    X = f32(X.astype(np.float32))
+    P = o.num_pairs()
+    phi = torch.zeros((n, P), device=DEV)
+    nrm = torch.zeros((n, P, 3), device=DEV)
+    pt = torch.zeros((n, P, 3), device=DEV)
+    ng = 16 + int(sc["n_box"])
+    lo = torch.zeros((n, ng, 3), device=DEV)
+    hi = torch.zeros((n, ng, 3), device=DEV)
+    mp.mppi_narrowphase(ctx, scene, T(X), phi, nrm, pt, lo, hi)
+    torch.cuda.synchronize()
+    phi, nrm, pt, lo = (a.cpu().numpy().astype(np.float64) for a in (phi, nrm, pt, lo))
+    checked = 0
+    for i in range(n):
+        wphi, wn, wp = o.narrow_all(X[i])
+        assert np.allclose(phi[i], wphi, atol=2e-6), i
+        near = wphi < 0.05  # normals of touching or near pairs
+        assert np.allclose(nrm[i][near], wn[near], atol=1e-4), i
+        # points of the contacts (apart, a point can sit anywhere along a
+        # parallel edge or face); the table pair reports the deepest vertex,
+        # so its point is compared only without a near tie for deepest
+        z = np.sort(_vertices(o, sc, X[i])[:, 2])
+        touch = wphi < 0.0
+        if z[1] - z[0] < 1e-5:
+            touch[0] = False
+        assert np.allclose(pt[i][touch], wp[touch], atol=2e-5), i
+        checked += int(touch.sum())
+        wlo, _ = o.aabbs(X[i])
+        assert np.allclose(lo[i][0], wlo[0], atol=2e-6), i
+    assert checked >= n // 2  # three of the four kinds of state touch
+    scene.close()
+
+
+def _flight_states(o, sc, n, seed):
+    """Object tumbling high above the table, arms near home and clear of
+    everything: rollouts that exercise the gyroscopic step and every cost
+    term without contact switches."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        x = _free_state(rng, sc, home_spread=0.25)
+        x[42:45] = [rng.uniform(-0.2, 0.2), rng.uniform(-0.2, 0.2), 1.2]
+        x[45:49] = _quat(rng)
+        x[49:52] = rng.uniform(-0.3, 0.3, 3)
+        x[52:55] = rng.uniform(-6.0, 6.0, 3)
+        if o.narrow_all(x)[0].min() < 0.02:
+            continue
+        out.append(x)
+    return np.array(out)
+
+
+def _rollout_margin(o, sc, x0, U):
+    x = x0.copy()
+    m_phi, m_d = np.inf, np.inf
+    for k in range(U.shape[0]):
+        for _ in range(int(sc["n_sub"])):
+            m_phi = min(m_phi, _margin(o, sc, x))
+            x, _ = o.substep(x, U[k])
+        d = o.cost_dist(x)
+        d = d[d < sc["m_c"]]
+        if d.size:
+            m_d = min(m_d, np.abs(d).min())
+    return min(m_phi, m_d)
+
+
+@pytest.mark.parametrize("task,phase", PHASES)
+def test_task_rollout_terms(mp, ctx, oracle_mod, task, phase):
+    """Rollouts of 8 control steps (80 samples: a workgroup and a ragged
+    tail) with all 17 unweighted terms, the weighted total and the
+    trajectory against the oracle."""
+    sc = W.task_scene(task, phase)
+    o = oracle_mod.Oracle(sc)
+    scene = mp.Scene(ctx, sc)
+    n, H = 80, 8
+    X = f32(_flight_states(o, sc, n, seed=31 + PHASES.index((task, phase))).astype(np.float32))
+    U = np.random.default_rng(17).uniform(-0.8, 0.8, (n, H, 14)).astype(np.float32)
+    costs = torch.zeros(n, device=DEV)
+    terms = torch.zeros((n, mp.NTERMS), device=DEV)
+    Xo = torch.zeros((n, H, 55), device=DEV)
+    mp.mppi_simulate(ctx, scene, T(X), T(U), costs=costs, terms=terms, X_out=Xo, traj=True)
+    torch.cuda.synchronize()
+    tg, cg, xg = terms.cpu().numpy().astype(np.float64), costs.cpu().numpy(), Xo.cpu().numpy().astype(np.float64)
+    lever = float(np.min(sc["obj_h"]))
+    kept, worst = 0, np.zeros(mp.NTERMS)
+    for i in range(n):
+        if _rollout_margin(o, sc, X[i], f32(U[i])) < CLEAR:
+            continue
+        kept += 1
+        c, tm, traj = o.rollout(X[i], f32(U[i]), want_traj=True)
+        _close(xg[i], traj, 2e-4, lever, f"sample {i}")
+        rel = np.abs(tg[i] - tm) / np.maximum(np.abs(tm), 1e-2)
+        worst = np.maximum(worst, rel)
+        assert np.all(rel < 2e-4), (i, tg[i], tm)
+        assert tg[i, 6] == tm[6]
+        assert abs(cg[i] - c) <= 2e-4 * max(abs(c), 1.0), (i, cg[i], c)
+    print(f"{task}/{phase}: {kept}/{n} samples kept; worst term rel err {worst}")
+    assert kept >= n // 2
+    scene.close()
+
+
+@pytest.mark.parametrize("task,phase", [("tray", "pick"), ("handover", "pass")])
+def test_task_plan_against_oracle(mp, ctx, oracle_mod, task, phase):
+    """A plan from the object at rest on the table (K = 64, H = 10, M = 3)
+    against the oracle's FP64 plan: the resting object's vertex contacts sit
+    at |phi| ~ 1e-7, so the comparison is through the last iteration's costs
+    and U_new, as for the resting ball."""
+    sc = W.task_scene(task, phase)
+    o = oracle_mod.Oracle(sc)
+    scene = mp.Scene(ctx, sc)
+    pp = W.plan_params(2, K=64, H=10, M=3)
+    K, H, M = pp["K"], pp["H"], pp["M"]
+    x0 = W.initial_state(sc).astype(np.float32)
+    Unew = torch.zeros((H, 14), device=DEV)
+    costs = torch.zeros(K, device=DEV)
+    st = mp.mppi_plan(ctx, scene, T(x0), torch.zeros((H, 14), device=DEV), K, H, pp["lam"], T(pp["sigma"]), Unew,
+                      costs, M=M, seed=pp["seed"])
+    torch.cuda.synchronize()
+    r = o.plan(f32(x0), np.zeros((H, 14)), K, H, pp["lam"], f32(pp["sigma"].astype(np.float32)), M, pp["seed"])
+    cg = costs.cpu().numpy()
+    rel = np.abs(cg - r["costs"]) / np.abs(r["costs"])
+    dU = np.abs(Unew.cpu().numpy() - r["nu"]).max()
+    print(f"{task}/{phase} plan: cost rel err median {np.median(rel):.2e} max {rel.max():.2e}; |dU|max {dU:.2e}")
+    assert st["rc"] == 0 and r["rc"] == 0
+    assert np.median(rel) < 1e-3
+    assert dU < 0.05 * pp["sigma"][0]
+    scene.close()
+
+
+def test_task_scenes_run_one_lane_per_sample_only(mp, ctx):
+    """Pinned team, wave or split mappings are refused (MPPI_E_INVAL), the
+    lane pin and the default run, and the autotuner has nothing to tune."""
+    sc = W.task_scene("tray", "move")
+    scene = mp.Scene(ctx, sc)
+    x0 = T(W.initial_state(sc))
+    U = torch.zeros((3, 4, 14), device=DEV)
+    c = torch.zeros(3, device=DEV)
+    for mapping in ("team", "wave", "split"):
+        with pytest.raises(mp.MppiError):
+            mp.mppi_simulate(ctx, scene, x0, U, costs=c, x0_shared=True, mapping=mapping)
+    out = []
+    for mapping in ("lane", None):
+        mp.mppi_simulate(ctx, scene, x0, U, costs=c, x0_shared=True, mapping=mapping)
+        torch.cuda.synchronize()
+        out.append(c.clone())
+    assert torch.equal(out[0], out[1])
+    with pytest.raises(mp.MppiError):
+        mp.mppi_autotune(ctx, scene, W.initial_state(sc), np.full(14, 0.3), 256, 4)
+    scene.close()
+
+
+@pytest.mark.parametrize("task,phase", [("tray", "pick"), ("handover", "place")])
+def test_task_plain_per_step_equals_lane(mp, ctx, task, phase):
+    """The plain per-step form carries all 17 cost sums between its launches:
+    plans, costs and counters equal the lane form bit for bit."""
+    sc = W.task_scene(task, phase)
+    scene = mp.Scene(ctx, sc)
+    K, H = 130, 7
+    pp = W.plan_params(2, K=K, H=H, M=2)
+    x0 = T(W.initial_state(sc))
+    nom = T(np.random.default_rng(3).uniform(-0.3, 0.3, (H, 14)))
+    out = []
+    for per_step in (False, True):
+        U = torch.zeros((H, 14), device=DEV)
+        c = torch.zeros(K, device=DEV)
+        st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], T(pp["sigma"]), U, c, M=2, seed=pp["seed"],
+                          per_step=per_step)
+        torch.cuda.synchronize()
+        out.append((U, c, st))
+    (U1, c1, s1), (U2, c2, s2) = out
+    assert torch.equal(U1, U2) and torch.equal(c1, c2)
+    for k in ("best", "ess", "contacts", "np_tests", "overflow", "cmin_iter"):
+        assert s1[k] == s2[k], k
+    scene.close()
+
+
+def _mixed_items(mp, ctx):
+    """Task-scene requests beside ball-scene requests of the packed-batch
+    workload (different K, H, M)."""
+    items = []
+    specs = [(("tray", "pick"), 96, 8, 2), (None, 70, 6, 3), (("handover", "pass"), 65, 5, 1), (None, 200, 4, 2)]
+    for i, (tp, K, H, M) in enumerate(specs):
+        sc = W.task_scene(*tp) if tp else W.make_scene(4, i)
+        pp = W.plan_params(4, K=K, H=H, M=M, seed=4000 + i)
+        items.append(dict(scene=mp.Scene(ctx, sc), x0=T(W.initial_state(sc)), K=K, H=H, lam=pp["lam"],
+                          sigma=T(pp["sigma"]), sigma_per_step=False, M=M, seed=pp["seed"],
+                          nominal_U=T(np.random.default_rng(i).uniform(-0.2, 0.2, (H, 14))), eta=1.0, n_elite=0,
+                          U_new=torch.zeros((H, 14), device=DEV), costs=torch.zeros(K, device=DEV)))
+    return items
+
+
+def _alone(mp, ctx, it, mapping=None):
+    U = torch.zeros_like(it["U_new"])
+    c = torch.zeros_like(it["costs"])
+    st = mp.mppi_plan(ctx, it["scene"], it["x0"], it["nominal_U"], it["K"], it["H"], it["lam"], it["sigma"], U, c,
+                      M=it["M"], seed=it["seed"], mapping=mapping)
+    torch.cuda.synchronize()
+    return U, c, st
+
+
+@pytest.mark.parametrize("mapping", [None, "lane"])
+def test_mixed_batch_equals_each_plan_alone(mp, ctx, mapping):
+    """A packed batch mixing task and ball scenes: each request equals its
+    plan alone bit for bit (the task scenes form launch groups of their own)."""
+    items = _mixed_items(mp, ctx)
+    sts = mp.mppi_plan_batch(ctx, items, mapping=mapping)
+    torch.cuda.synchronize()
+    for it, st in zip(items, sts):
+        U, c, st1 = _alone(mp, ctx, it, mapping)
+        assert st["status"] == 0 and st1["rc"] == 0
+        assert torch.equal(c, it["costs"]) and torch.equal(U, it["U_new"])
+        assert st["best"] == st1["best"] and st["contacts"] == st1["contacts"]
+    with pytest.raises(mp.MppiError):
+        mp.mppi_plan_batch(ctx, items, mapping="team")
+    for it in items:
+        it["scene"].close()
+
+
+def test_served_task_requests_equal_plans_alone(mp, ctx):
+    """Served requests on task and ball scenes, in flight together, equal
+    their plans alone bit for bit."""
+    items = _mixed_items(mp, ctx)
+    srv = mp.Server(ctx)
+    tickets = [srv.submit(it) for it in items]
+    for t in tickets:
+        assert srv.wait(t)["status"] == 0
+    torch.cuda.synchronize()
+    for it in items:
+        U, c, _ = _alone(mp, ctx, it)
+        assert torch.equal(c, it["costs"]) and torch.equal(U, it["U_new"])
+    srv.close()
+    for it in items:
+        it["scene"].close()
