@@ -639,6 +639,54 @@ def bench_occupancy(mp, ctx, Ks=(32768,), H=64, M=2):
     return out
 
 
+def bench_tasks(mp, ctx, K=1024, H=64, M=10, plans=3, big_K=32768):
+    """The tray-moving and hand-over phases (box-shaped object, the further
+    task terms; one sample per lane): plan latency, rollout launch time,
+    env-steps/s and the flop-model roofline fraction at the main workload's
+    K, H and M, and at big_K samples (two iterations) for the fraction at
+    full occupancy."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2511_21264_amd.flops import rollout_flops
+    dev = torch.device("cuda:0")
+    out = {}
+    for task, phase in (("tray", "pick"), ("tray", "move"), ("handover", "pick"), ("handover", "pass"),
+                        ("handover", "place")):
+        sc = W.task_scene(task, phase)
+        scene = mp.Scene(ctx, sc)
+        x0 = torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev)
+        for k, m, n in ((K, M, plans), (big_K, 2, 1)):
+            if k == big_K and (task, phase) != ("tray", "move"):
+                continue
+            pp = W.plan_params(2, K=k, H=H, M=m)
+            nom = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+            sig = torch.tensor(pp["sigma"], dtype=torch.float32, device=dev)
+            U = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+            c = torch.zeros(k, dtype=torch.float32, device=dev)
+            mp.mppi_plan(ctx, scene, x0, nom, k, H, pp["lam"], sig, U, c, M=m, seed=pp["seed"])
+            torch.cuda.synchronize()
+            lat, roll, fl = [], [], []
+            for _ in range(n):
+                a = time.perf_counter()
+                st = mp.mppi_plan(ctx, scene, x0, nom, k, H, pp["lam"], sig, U, c, M=m, seed=pp["seed"],
+                                  time_kernels=True)
+                lat.append(time.perf_counter() - a)
+                roll.append(st["rollout_ms"] / m)
+                fl.append(rollout_flops(k, H, int(sc["n_sub"]), scene.n_pairs, scene.n_cost_pairs, int(sc["n_pgs"]),
+                                        st["contacts"] / m, st["np_tests"] / m, st["box_tests"] / m, obj_box=True,
+                                        ext=True))
+            t = float(np.mean(roll)) * 1e-3
+            out[f"{task}_{phase}_K{k}"] = {
+                "K": k, "H": H, "M": m, "plan_ms": float(np.median(lat)) * 1e3, "rollout_launch_ms": t * 1e3,
+                "env_steps_per_s": m * k * H / float(np.median(lat)), "flop_per_launch": float(np.mean(fl)),
+                "frac": float(np.mean(fl)) / t / PEAK_FP32,
+                "contacts_per_substep": st["contacts"] / (m * k * H * int(sc["n_sub"])),
+                "full_contact_list_per_substep": st["overflow"] / (m * k * H * int(sc["n_sub"])), "ess": st["ess"]}
+        scene.close()
+    return out
+
+
 def bench_episode(mp, ctx, runs=((2, 8, "diag"), (2, 8, "qp"), (2, 8, "cov"), (3, 4, "diag"), (2, 8, "qp", 256),
                                  (2, 8, "qp", 512), (2, 8, "qp", 2048)), t_max=10.0):
     """Closed-loop ball transport (receding-horizon execution; pick and move
@@ -1244,6 +1292,8 @@ def main():
         print(json.dumps({"plain": out["plain"]}), file=sys.stderr, flush=True)
         out["occupancy"] = bench_occupancy(mp, ctx)
         print(json.dumps({"occupancy": out["occupancy"]}), file=sys.stderr, flush=True)
+        out["tasks"] = bench_tasks(mp, ctx)
+        print(json.dumps({"tasks": out["tasks"]}), file=sys.stderr, flush=True)
     if args.replans > 0:
         out["replan"] = bench_replan(mp, ctx, sc, pp, n=args.replans, mapping=mapping)
         print(json.dumps({"replan": out["replan"]}), file=sys.stderr, flush=True)

@@ -18,6 +18,10 @@ HIPCC_FLAGS = [
     # root (about 1 ulp) instead of the correctly rounded sequences: these
     # sit on the per-step dependency chains (Cholesky pivots, distances)
     "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+    # multiply-adds fused only where one expression writes a * b + c: the
+    # rounding of a formula then does not depend on the code it is inlined
+    # into, which keeps the team, wave and split mappings bit-identical
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument", "-pthread",
 ]
 

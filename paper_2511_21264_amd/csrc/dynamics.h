@@ -150,7 +150,7 @@ __device__ inline void chol7(float L[28])
         float d = L[tri(j, j)];
 #pragma unroll
         for (int k2 = 0; k2 < j; ++k2) d -= L[tri(j, k2)] * L[tri(j, k2)];
-        const float inv = 1.0f / sqrtf(d);
+        const float inv = __builtin_amdgcn_rsqf(d);  // hardware 1 / sqrt (about 1 ulp)
         L[tri(j, j)] = inv;
 #pragma unroll
         for (int i = j + 1; i < NJ; ++i) {

@@ -689,7 +689,7 @@ __device__ inline void substep(const DevModel &md, float x[NX], const float u[NU
     const V3 qv = v3(x[XQUAT + 1], x[XQUAT + 2], x[XQUAT + 3]);
     const float nw = dw * qw - dot(dv, qv);
     const V3 nv = dw * qv + qw * dv + cross(dv, qv);
-    const float inv = 1.0f / sqrtf(nw * nw + dot(nv, nv));
+    const float inv = __builtin_amdgcn_rsqf(nw * nw + dot(nv, nv));
     x[XQUAT] = nw * inv;
     x[XQUAT + 1] = nv.x * inv;
     x[XQUAT + 2] = nv.y * inv;

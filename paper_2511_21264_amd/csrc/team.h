@@ -1107,7 +1107,7 @@ __device__ __forceinline__ void integrate_ball(const DevModel &md, TeamState &S,
     const V3 nv = v3(fmaf(dw, qv.x, fmaf(qw, dv.x, fmaf(dv.y, qv.z, -(dv.z * qv.y)))),
                      fmaf(dw, qv.y, fmaf(qw, dv.y, fmaf(dv.z, qv.x, -(dv.x * qv.z)))),
                      fmaf(dw, qv.z, fmaf(qw, dv.z, fmaf(dv.x, qv.y, -(dv.y * qv.x)))));
-    const float inv = 1.0f / sqrtf(fmaf(nw, nw, fmaf(nv.x, nv.x, fmaf(nv.y, nv.y, nv.z * nv.z))));
+    const float inv = __builtin_amdgcn_rsqf(fmaf(nw, nw, fmaf(nv.x, nv.x, fmaf(nv.y, nv.y, nv.z * nv.z))));
     S.quat[0] = nw * inv;
     S.quat[1] = nv.x * inv;
     S.quat[2] = nv.y * inv;

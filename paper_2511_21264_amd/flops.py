@@ -17,6 +17,13 @@ hand-counted from the stage definitions:
   Gauss-Seidel: 363 per contact per sweep (4 rows)
   per control step cost: FK 336 + stage terms 92 + AABBs 168 + 6 per cost
     pair compare + 5 per cost pair term
+  box-shaped object, per substep: rotation from the quaternion 30, world
+    inverse inertia 72, gyroscopic step 51, rotated AABB 27, the eight
+    vertex heights against the table 150 -> F_BOX_FREE = 330 (its pair
+    tests are counted at the narrowphase rates above: a lower bound)
+  further task terms, per control step: joint deviation 42, vertical 2,
+    pad velocities and relative velocity 200, position / x targets 24,
+    orientation angles 2 x 60 + 40 -> F_EXT = 428
 """
 
 F_FREE = 6478
@@ -28,9 +35,12 @@ F_ROWS = 1120
 F_PGS = 363
 F_COST_FIXED = 336 + 92 + 168
 F_COST_PAIR = 11
+F_BOX_FREE = 330
+F_EXT = 428
 
 
-def rollout_flops(K, H, n_sub, n_pairs, n_cost_pairs, n_pgs, contacts, np_tests, box_tests):
+def rollout_flops(K, H, n_sub, n_pairs, n_cost_pairs, n_pgs, contacts, np_tests, box_tests, obj_box=False,
+                  ext=False):
     """Algorithmic FP32 operations of one rollout launch.
 
     contacts / np_tests / box_tests are the launch's totals reported by the
@@ -43,4 +53,8 @@ def rollout_flops(K, H, n_sub, n_pairs, n_cost_pairs, n_pgs, contacts, np_tests,
     f += contacts * (F_ROWS + n_pgs * F_PGS)
     f += (np_tests - box_tests) * F_NP + box_tests * F_NP_BOX
     f += n_steps * (F_COST_FIXED + F_COST_PAIR * n_cost_pairs)
+    if obj_box:
+        f += n_substeps * F_BOX_FREE
+    if ext:
+        f += n_steps * F_EXT
     return float(f)

@@ -526,6 +526,32 @@ def test_team_wave_split_mappings_bit_identical(mp, ctx):
     scene.close()
 
 
+@pytest.mark.parametrize("index,M", [(13, 6), (8, 10)])
+def test_team_wave_split_bit_identical_with_full_contact_lists(mp, ctx, index, M):
+    """Packed-workload scenes whose plans fill the four-slot contact list in
+    thousands of substeps (the ball held by both pads against the table and
+    a box): the three forms of the team family still agree bit for bit over
+    whole plans, so a request's result does not depend on which of them a
+    packed launch uses."""
+    sc, pp = W.packed_scenes(index + 1, 4)[index]
+    scene = mp.Scene(ctx, sc)
+    K, H = pp["K"], pp["H"]
+    res = {}
+    for mapping in ("team", "wave", "split"):
+        Un = torch.zeros((H, 14), device=DEV)
+        cc = torch.zeros(K, device=DEV)
+        st = mp.mppi_plan(ctx, scene, T(W.initial_state(sc)), torch.zeros((H, 14), device=DEV), K, H, pp["lam"],
+                          T(pp["sigma"]), Un, cc, M=M, seed=pp["seed"], mapping=mapping)
+        torch.cuda.synchronize()
+        res[mapping] = (Un.cpu().numpy(), cc.cpu().numpy(), st["contacts"], st["overflow"])
+    assert res["team"][3] > 100  # the list was full in many substeps
+    for other in ("wave", "split"):
+        assert np.array_equal(res["team"][0], res[other][0]), other
+        assert np.array_equal(res["team"][1], res[other][1]), other
+        assert res["team"][2] == res[other][2]
+    scene.close()
+
+
 def test_precision_study_weights_fp64_vs_fp32(mp, ctx, oracle_mod):
     """The obstacle-course workload's update size (K=4096, H=100) from
     identical costs: weights, log-sum-exp normaliser and weighted mean in
