@@ -140,6 +140,28 @@ __device__ inline void crba_arm(const DevModel &md, int arm, const ArmKin &k, fl
     }
 }
 
+// cos(a / 2) and sin(a / 2) / a for a rotation angle a >= 0 (the exponential
+// map of a rotation vector of length a).  Per substep a is h |w|, far below
+// 1 rad: there the Taylor series (even in a, truncated after the a^8 term;
+// remainder below 3e-10 for a <= 1) replaces the range-reduced library call.
+__device__ __forceinline__ void half_angle_sincos(float a, float &c, float &s_over_a)
+{
+#pragma clang fp contract(off)
+    if (a <= 1.0f) {
+        const float x2 = 0.25f * a * a;  // (a / 2)^2
+        c = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 40320.0f, -1.0f / 720.0f), 1.0f / 24.0f), -0.5f), 1.0f);
+        const float sx = fmaf(x2, fmaf(x2, fmaf(x2, fmaf(x2, 1.0f / 362880.0f, -1.0f / 5040.0f), 1.0f / 120.0f),
+                                        -1.0f / 6.0f),
+                              1.0f);  // sin(a / 2) / (a / 2)
+        s_over_a = 0.5f * sx;
+    } else {
+        float sn, cs;
+        sincosf(0.5f * a, &sn, &cs);
+        c = cs;
+        s_over_a = sn / a;
+    }
+}
+
 // in-place Cholesky of a packed SPD 7x7 (lower); pivots stay > 0 because
 // the armature is on the diagonal.  The diagonal slots receive 1 / L_jj, so
 // that the solves multiply instead of dividing.

@@ -675,15 +675,7 @@ __device__ inline void substep(const DevModel &md, float x[NX], const float u[NU
     const V3 th = h * wb;
     const float ang = sqrtf(dot(th, th));
     float dw, dsc;
-    if (ang < 1e-8f) {
-        dw = 1.0f;
-        dsc = 0.5f;
-    } else {
-        float s, c;
-        sincosf(0.5f * ang, &s, &c);
-        dw = c;
-        dsc = s / ang;
-    }
+    half_angle_sincos(ang, dw, dsc);
     const V3 dv = dsc * th;
     const float qw = x[XQUAT];
     const V3 qv = v3(x[XQUAT + 1], x[XQUAT + 2], x[XQUAT + 3]);

@@ -1090,15 +1090,7 @@ __device__ __forceinline__ void integrate_ball(const DevModel &md, TeamState &S,
     const V3 th = h * wb;
     const float ang = sqrtf(fmaf(th.x, th.x, fmaf(th.y, th.y, th.z * th.z)));
     float dw, dsc;
-    if (ang < 1e-8f) {
-        dw = 1.0f;
-        dsc = 0.5f;
-    } else {
-        float sn, cs;
-        sincosf(0.5f * ang, &sn, &cs);
-        dw = cs;
-        dsc = sn / ang;
-    }
+    half_angle_sincos(ang, dw, dsc);
     const V3 dv = dsc * th;
     const float qw = S.quat[0];
     const V3 qv = v3(S.quat[1], S.quat[2], S.quat[3]);
