@@ -852,9 +852,148 @@ def sources_hash():
 # rollout kernel's time, traffic and issued operations), and the QP and
 # covariance legs (their kernels' times)
 PROFILE_ARGS_MAIN = ("--steps 3 --warmup 1 --no-cpu-baseline --packed-steps 0 --serve-seconds 0 --no-precision "
-                     "--replans 0 --no-qp --no-cov --no-episodes")
+                     "--replans 0 --no-qp --no-cov --no-episodes --no-extra")
 PROFILE_ARGS_NEXT = ("--steps 1 --warmup 0 --no-cpu-baseline --packed-steps 0 --serve-seconds 0 --no-precision "
-                     "--replans 0 --no-episodes")
+                     "--replans 0 --no-episodes --no-extra")
+# launches that fill the chip, one workload per profiled process: the main
+# scene at 32768 samples one per lane and 16 lanes per sample, the 32 packed
+# scenes of the uneven-batch workload in one batch, and the tray's move phase
+# at 32768 samples (the task form)
+OCC_RUNS = {
+    "lane32k": ("%rollout_kernel<4, false>%", "main scene, K=32768, H=64, one lane per sample"),
+    "team32k": ("%rollout_team_kernel<4, 4>%", "main scene, K=32768, H=64, 16 lanes per sample"),
+    "packed": ("%rollout_team_kernel<4, 4>%", "32 packed scenes (K 256..4096, H 32..128), one batch, team family"),
+    "task32k": ("%rollout_kernel<8, true>%", "tray move phase, K=32768, H=64, task form"),
+}
+
+
+def occupancy_profile_run(which, meta_path):
+    """One of OCC_RUNS for the profiler: a warm-up and a timed pass of the
+    workload; writes the launch's algorithmic flops (work model over the
+    library's counters) and launch time (HIP events) to meta_path."""
+    import numpy as np
+    import torch
+    import paper_2511_21264_amd as mp
+    import workloads as W
+    from paper_2511_21264_amd.flops import rollout_flops
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = mp.Context(0)
+    rec = {"run": which, "kernel_like": OCC_RUNS[which][0], "workload": OCC_RUNS[which][1]}
+    if which == "packed":
+        items = []
+        for sc, pp in W.packed_scenes(32, 4):
+            H, K = pp["H"], pp["K"]
+            items.append(dict(scene=mp.Scene(ctx, sc), K=K, H=H, lam=pp["lam"], M=pp["M"], seed=pp["seed"],
+                              x0=torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev),
+                              nominal_U=torch.zeros((H, 14), dtype=torch.float32, device=dev),
+                              sigma=torch.tensor(pp["sigma"], dtype=torch.float32, device=dev),
+                              U_new=torch.zeros((H, 14), dtype=torch.float32, device=dev),
+                              costs=torch.zeros(K, dtype=torch.float32, device=dev)))
+        mp.mppi_plan_batch(ctx, items)
+        sts = mp.mppi_plan_batch(ctx, items, time_kernels=True)
+        torch.cuda.synchronize()
+        flop = sum(rollout_flops(it["K"], it["H"], int(it["scene"].dict["n_sub"]), it["scene"].n_pairs,
+                                 it["scene"].n_cost_pairs, int(it["scene"].dict["n_pgs"]), st["contacts"] / it["M"],
+                                 st["np_tests"] / it["M"], st["box_tests"] / it["M"]) * it["M"]
+                   for it, st in zip(items, sts))
+        rec.update(launches=sts[0]["rollout_launches"], flop_per_launch=flop / sts[0]["rollout_launches"],
+                   event_ms_per_launch=sts[0]["rollout_ms"] / sts[0]["rollout_launches"])
+    else:
+        K, H, M = 32768, 64, 2
+        task = which == "task32k"
+        sc = W.task_scene("tray", "move") if task else W.make_scene(2)
+        scene = mp.Scene(ctx, sc)
+        pp = W.plan_params(2, K=K, H=H, M=M)
+        x0 = torch.tensor(W.initial_state(sc), dtype=torch.float32, device=dev)
+        nom = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+        sig = torch.tensor(pp["sigma"], dtype=torch.float32, device=dev)
+        U = torch.zeros((H, 14), dtype=torch.float32, device=dev)
+        c = torch.zeros(K, dtype=torch.float32, device=dev)
+        mapping = None if task else ("lane" if which == "lane32k" else "team")
+        mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U, c, M=M, seed=pp["seed"], mapping=mapping)
+        st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, U, c, M=M, seed=pp["seed"], mapping=mapping,
+                          time_kernels=True)
+        torch.cuda.synchronize()
+        rec.update(launches=M, flop_per_launch=rollout_flops(
+            K, H, int(sc["n_sub"]), scene.n_pairs, scene.n_cost_pairs, int(sc["n_pgs"]), st["contacts"] / M,
+            st["np_tests"] / M, st["box_tests"] / M, obj_box=task, ext=task), event_ms_per_launch=st["rollout_ms"] / M)
+    os.makedirs(os.path.dirname(meta_path) or ".", exist_ok=True)
+    json.dump(rec, open(meta_path, "w"), indent=1)
+    print(json.dumps(rec), flush=True)
+
+
+def occupancy_commands():
+    out = []
+    for w in OCC_RUNS:
+        b = f"python3 bench.py --profile-run {w} --profile-meta gpurun_out/prof/occ_{w}.json"
+        out += [f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/occ_{w}_trace -o run -- {b}",
+                f"timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE SQ_INSTS_VALU SQ_INSTS_VALU_FLOPS_FP32 "
+                f"-d gpurun_out/prof/occ_{w}_fetch -o run -- {b}",
+                f"timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/occ_{w}_write -o run -- {b}"]
+    return out + ["python3 bench.py --summarize-profiles gpurun_out/prof"]
+
+
+def summarize_occupancy(base):
+    """profiles/rollout_occupancy.md: the launches that fill the chip, each
+    from its own profiled process (kernel time, HBM bytes, issued vector
+    instructions) with the work model's flops from the same run."""
+    import sqlite3
+    import glob
+
+    def db(sub):
+        f = glob.glob(os.path.join(base, sub, "**", "*results.db"), recursive=True)
+        return sqlite3.connect(f[0]) if f else None
+
+    def cnt(sub, name, like):
+        c = db(sub)
+        if not c:
+            return None
+        return c.execute("select avg(value) from counters_collection where counter_name = ? and kernel_name like ?",
+                         (name, like)).fetchone()[0]
+
+    cf, cw = cnt("cfetch", "FETCH_SIZE", "%copyBuffer%"), cnt("cwrite", "WRITE_SIZE", "%copyBuffer%")
+    if not cf or not cw:
+        return
+    copy_kib = (256 << 20) / 1024.0
+    fs, ws = copy_kib / cf, copy_kib / cw
+    rows = []
+    for w, (like, desc) in OCC_RUNS.items():
+        mf = os.path.join(base, f"occ_{w}.json")
+        tr = db(f"occ_{w}_trace")
+        if not tr or not os.path.exists(mf):
+            continue
+        meta = json.load(open(mf))
+        r = tr.execute("select sum(total_calls), sum(total_duration) from top_kernels where name like ?",
+                       (like,)).fetchone()
+        if not r or not r[0]:
+            continue
+        avg_ms = r[1] / r[0] / 1e3
+        fetch, write = cnt(f"occ_{w}_fetch", "FETCH_SIZE", like), cnt(f"occ_{w}_write", "WRITE_SIZE", like)
+        vi, vf = cnt(f"occ_{w}_fetch", "SQ_INSTS_VALU", like), cnt(f"occ_{w}_fetch", "SQ_INSTS_VALU_FLOPS_FP32", like)
+        fl = meta["flop_per_launch"]
+        tf = fl / (avg_ms * 1e-3)
+        hbm = (fetch * fs + write * ws) * 1024 if fetch is not None and write is not None else None
+        rows.append(f"| {w} | {desc} | {like.strip('%')} | {r[0]} | {avg_ms:.3f} | {meta['event_ms_per_launch']:.3f} | "
+                    f"{fl / 1e9:.1f} | {tf / 1e12:.2f} | {tf / PEAK_FP32:.4f} | "
+                    f"{'' if hbm is None else f'{hbm / 1e6:.2f}'} | "
+                    f"{'' if vi is None else f'{vi / 1e6:.0f}'} | "
+                    f"{'' if vi is None else f'{vi / (avg_ms * 1e-3) / PEAK_VALU_ISSUE:.3f}'} | "
+                    f"{'' if vf is None else f'{64 * vf / 1e9:.0f}'} |")
+    md = ["# Rollout launches that fill the chip: kernel time, roofline fraction, HBM bytes, vector issue", "",
+          "Commands (run from the repository root, TMPDIR=/tmp):", ""]
+    md += [f"    {c}" for c in occupancy_commands()]
+    md += ["", f"Kernel sources: sha256 {sources_hash()[:16]}.", "",
+           "| run | workload | kernel | dispatches | avg ms (rocprofv3) | ms (HIP events, same run) | "
+           "algorithmic GFLOP per launch | TFLOP/s | fraction of 157.3 TF | HBM MB per launch | "
+           "wave64 VALU instructions per launch (M) | fraction of the issue peak | issued FP32 lane operations (G) |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|"] + rows
+    md += ["", "Flops from the work model (`paper_2511_21264_amd/flops.py`) over the library's contact and "
+           "narrowphase counters of the same run; HBM bytes from FETCH_SIZE and WRITE_SIZE scaled by what the "
+           "counters read for a 256 MiB device copy; the issue peak is one wave64 VALU instruction per SIMD every "
+           "4 cycles at 2.4 GHz. The packed row averages the batch's team-family launches (one per iteration)."]
+    open(os.path.join(ROOT, "profiles", "rollout_occupancy.md"), "w").write("\n".join(md) + "\n")
+    print("\n".join(md))
 
 
 # SQ counters of the rollout kernel, two passes of at most eight
@@ -1057,6 +1196,7 @@ def summarize_profiles(base):
     meta = profile_meta()
     summarize_next(base, meta)
     summarize_stalls(base, meta)
+    summarize_occupancy(base)
     lines = []
     tr = db("trace")
     if tr:
@@ -1156,6 +1296,9 @@ def main():
                     help="also run the closed-loop ball-transport runs (success rate, task and compute time)")
     ap.add_argument("--no-extra", dest="extra", action="store_false",
                     help="skip the graph, plain-form, full-occupancy and contact-cap legs")
+    ap.add_argument("--profile-run", default="", choices=[""] + list(OCC_RUNS),
+                    help="run one chip-filling workload for the profiler (see OCC_RUNS)")
+    ap.add_argument("--profile-meta", default="gpurun_out/prof/occ.json")
     ap.add_argument("--summarize-profiles", default="",
                     help="read rocprofv3 result folders under this path and write the profiles/ summaries")
     args = ap.parse_args()
@@ -1164,6 +1307,9 @@ def main():
         return
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles)
+        return
+    if args.profile_run:
+        occupancy_profile_run(args.profile_run, args.profile_meta)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -136,8 +136,9 @@ typedef struct mppi_scene mppi_scene;
  * the end-effector distance term (l_tray).  The paper's task totals are
  * weightings of the 17 terms; the caller sets the phase's weights (w_pick /
  * w_move, the hand-over's per-arm phase weights) by choosing the scene.
- * Scenes with obj_box or ext run in the one-lane mapping only (a pinned
- * team, wave or split mapping is rejected with MPPI_E_INVAL). */
+ * Scenes with obj_box or ext run one lane, one wave or two waves per sample
+ * (the last two bit for bit alike); a pinned MPPI_MAP_TEAM (four samples a
+ * wave) is rejected with MPPI_E_INVAL. */
 typedef struct mppi_scene_desc {
     double base_pos[2][3];
     double base_cs[2][2];

@@ -223,7 +223,7 @@ int build_model(const mppi_scene_desc *d, DevModel &m)
     if (d->obj_box != 0 && d->obj_box != 1) return fail(MPPI_E_MODEL, "obj_box must be 0 (ball) or 1 (box)");
     m.obj_box = d->obj_box;
     m.ext = d->ext ? 1 : 0;
-    m.lane_only = m.obj_box | m.ext;
+    m.task_form = m.obj_box | m.ext;
     const double inv_I_ball = 1.0 / (0.4 * d->ball_m * d->ball_r * d->ball_r);
     for (int i = 0; i < 3; ++i) {
         m.obj_I[i] = (float)(0.4 * d->ball_m * d->ball_r * d->ball_r);
@@ -317,6 +317,12 @@ int resolve_mapping(const mppi_ctx *c, long K, unsigned flags)
 int family_launch_mapping(const mppi_ctx *c, int family, long total_k, unsigned flags)
 {
     if (family == MAP_TASK) return MAP_TASK;  // a pin can only have been the lane mapping
+    if (family == MAP_TASK_WAVE) {
+        const int pinned = mapping_of(flags);
+        if (pinned == MAP_SPLIT) return MAP_TASK_SPLIT;
+        if (pinned == MAP_WAVE) return MAP_TASK_WAVE;
+        return resolve_mapping(c, total_k, flags) == MAP_SPLIT ? MAP_TASK_SPLIT : MAP_TASK_WAVE;
+    }
     const int pinned = mapping_of(flags);
     if (pinned != MAP_AUTO) return pinned;
     if (family == MAP_LANE) return MAP_LANE;
@@ -333,10 +339,13 @@ int set_device(mppi_ctx *c)
 int scene_mapping(const mppi_ctx *c, const mppi_scene *s, long K, unsigned flags, int *map)
 {
     const int pinned = mapping_of(flags);
-    if (s->host.lane_only) {
-        if (pinned != MAP_AUTO && pinned != MAP_LANE)
-            return fail(MPPI_E_INVAL, "scenes with a box object or the further task-cost terms run one sample per lane");
-        *map = MAP_TASK;
+    if (s->host.task_form) {
+        // the task forms: one lane, one wave or two waves per sample
+        if (pinned == MAP_TEAM)
+            return fail(MPPI_E_INVAL, "scenes with a box object or the further task-cost terms run one lane, one "
+                                      "wave or two waves per sample, not four samples a wave");
+        const int m = pinned != MAP_AUTO ? pinned : resolve_mapping(c, K, flags);
+        *map = m == MAP_LANE ? MAP_TASK : m == MAP_SPLIT ? MAP_TASK_SPLIT : MAP_TASK_WAVE;
         return MPPI_OK;
     }
     *map = resolve_mapping(c, K, flags);
@@ -758,7 +767,7 @@ static int plan_impl(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, co
             if (timing) HIPCHK(hipEventRecord(ctx->ev[2 * m], q));
             if (per_step) {
                 for (int k = 0; k < H; ++k)
-                    launch_rollout_step(ra, scene->host.n_cmax, (float *)dps, k, scene->host.lane_only != 0, q);
+                    launch_rollout_step(ra, scene->host.n_cmax, (float *)dps, k, scene->host.task_form != 0, q);
             } else {
                 launch_rollout(ra, scene->host.n_cmax, q, mapping);
             }
@@ -1546,7 +1555,9 @@ int mppi_autotune(mppi_ctx *ctx, const mppi_scene *scene, const float *x0, const
     if (scene->ctx != ctx) return fail(MPPI_E_INVAL, "scene belongs to another context");
     if (K < 1 || K > MPPI_MAX_K || H < 1 || H > MPPI_MAX_H) return fail(MPPI_E_INVAL, "K=%d or H=%d out of range", K, H);
     if (!all_finite(x0, NX) || !all_finite(sigma, NU)) return fail(MPPI_E_INVAL, "non-finite input");
-    if (scene->host.lane_only) return fail(MPPI_E_INVAL, "scenes with a box object or the further task-cost terms run one sample per lane: nothing to tune");
+    if (scene->host.task_form)
+        return fail(MPPI_E_INVAL, "the autotuner times ball scenes; scenes with a box object or the further task-cost "
+                                  "terms follow the mapping it records for their size");
     int rc = set_device(ctx);
     if (rc) return rc;
     hipStream_t s = nullptr;

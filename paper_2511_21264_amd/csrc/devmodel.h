@@ -47,8 +47,9 @@ struct DevModel {
     int n_pairs, cost_first, n_cost;
     uint8_t pa[MAXPAIR], pb[MAXPAIR];
     // the free object as a box (obj_box): half extents, principal inertias
-    // and their inverses (body frame); ext: the further task-cost terms
-    int obj_box, ext, lane_only;
+    // and their inverses (body frame); ext: the further task-cost terms;
+    // task_form: either of them (the scene runs in the task forms)
+    int obj_box, ext, task_form;
     float obj_h[3], obj_I[3], obj_iI[3];
     float l_cost;  // end-effector distance target of the cost (l_target or l_ball)
     float q_home[14];

@@ -42,16 +42,18 @@ int resolve_mapping(const mppi_ctx *c, long K, unsigned flags);
 // results are those of its own mapping's family, whatever it is batched with.
 inline int map_family(int map) { return map == mppi::MAP_LANE ? mppi::MAP_LANE : mppi::MAP_TEAM; }
 // launch groups of packed batches and of the server's iterations: mapping
-// family (lane, team, task form) x contact-list instantiation (up to 4, up to 8)
-constexpr int NGROUP = 6;
+// family (one lane; the team family; the task forms' one lane; the task
+// forms' one or two waves) x contact-list instantiation (up to 4, up to 8)
+constexpr int NGROUP = 8;
 inline int group_index(int family, int n_cmax)
 {
-    const int f = family == mppi::MAP_LANE ? 0 : family == mppi::MAP_TASK ? 2 : 1;
+    const int f = family == mppi::MAP_LANE ? 0 : family == mppi::MAP_TASK ? 2 : family == mppi::MAP_TASK_WAVE ? 3 : 1;
     return 2 * f + (n_cmax > 4 ? 1 : 0);
 }
 inline int group_family(int g)
 {
-    return (g >> 1) == 0 ? mppi::MAP_LANE : (g >> 1) == 2 ? mppi::MAP_TASK : mppi::MAP_TEAM;
+    const int f = g >> 1;
+    return f == 0 ? mppi::MAP_LANE : f == 1 ? mppi::MAP_TEAM : f == 2 ? mppi::MAP_TASK : mppi::MAP_TASK_WAVE;
 }
 // the family of a request of K samples planned alone with these flags
 // (scenes with a box object or the further task-cost terms run one sample
@@ -112,13 +114,20 @@ struct mppi_scene {
 namespace mppi_host {
 int set_device(mppi_ctx *c);
 
-inline int request_family(const mppi_ctx *c, const mppi_scene *s, long K, unsigned flags)
-{
-    return s->host.lane_only ? mppi::MAP_TASK : map_family(resolve_mapping(c, K, flags));
-}
 // the mapping of a launch over K samples of scene s (see resolve_mapping);
 // MPPI_E_INVAL when the flags pin a mapping the scene cannot run in
 int scene_mapping(const mppi_ctx *c, const mppi_scene *s, long K, unsigned flags, int *map);
+
+inline int request_family(const mppi_ctx *c, const mppi_scene *s, long K, unsigned flags)
+{
+    if (s->host.task_form) {
+        int map = mppi::MAP_TASK;
+        scene_mapping(c, s, K, flags, &map);  // the callers have validated the flags
+        return map == mppi::MAP_TASK ? mppi::MAP_TASK : mppi::MAP_TASK_WAVE;
+    }
+    return map_family(resolve_mapping(c, K, flags));
+}
+
 
 // Orders a call on stream s after the context's previous call (see
 // mppi_ctx::order_ev): begin() before the first enqueue; the destructor

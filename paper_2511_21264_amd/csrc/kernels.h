@@ -83,9 +83,10 @@ struct FinishArgs {
 
 // sample-to-lane mapping of the rollout
 constexpr int MAP_AUTO = 0, MAP_LANE = 1, MAP_TEAM = 2, MAP_WAVE = 3, MAP_SPLIT = 4;
-// one lane per sample, the form that carries the box-shaped object and the
-// further task terms (scenes with obj_box or ext run only in this one)
-constexpr int MAP_TASK = 5;
+// the forms that carry the box-shaped object and the further task terms
+// (scenes with obj_box or ext run only in these): one lane per sample, and
+// one or two waves per sample (bit-identical to each other)
+constexpr int MAP_TASK = 5, MAP_TASK_WAVE = 6, MAP_TASK_SPLIT = 7;
 int pick_mapping(int K, int requested);
 void launch_rollout(const RolloutArgs &a, int ncmax, hipStream_t s, int mapping = MAP_AUTO);
 // the plain form: control step k of every sample (one sample per lane), the

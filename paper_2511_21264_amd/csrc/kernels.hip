@@ -252,7 +252,8 @@ __global__ void __launch_bounds__(64) rollout_step_kernel(RolloutArgs a, float *
 // the same values and splitting the contact sweep 64 wide.  Teams past K
 // run on a clamped sample index so that every lane reaches every barrier;
 // they write nothing.
-template <int NC, int TPW>
+// TASK (one wave per sample only): the box object and the further terms
+template <int NC, int TPW, bool TASK = false>
 __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const RolloutArgs *tab, const int *blk, int m)
 {
     extern __shared__ float lds[];
@@ -312,9 +313,10 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
     const int nsub = a.n_sub > 0 ? a.n_sub : md0.n_sub;
     uint32_t hist = 0u;
     float *dist = a.dist + j;
+    static_assert(!TASK || TPW == 1, "the task forms run one or two waves per sample");
     CostAcc acc;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
+    for (int i = 0; i < NTERMS; ++i) acc.t[i] = 0.f;
     StepCounters cnt = {0, 0, 0, 0};
     float uprev = 0.f;
     for (int k = 0; k < a.H; ++k) {
@@ -329,8 +331,9 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
                 u = clampf(fmaf(sg, z, a.nu[k * NU + d]), -md.u_max, md.u_max);
             }
         }
-        for (int s = 0; s < nsub; ++s) team_substep<NC, TPW == 1 ? 64 : TEAM, TPW == 1>(model(a.md), jc, tc, S, u, cnt);
-        team_stage_cost(model(a.md), jc, tc, S, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
+        for (int s = 0; s < nsub; ++s)
+            team_substep<NC, TPW == 1 ? 64 : TEAM, TPW == 1, TASK>(model(a.md), jc, tc, S, u, cnt);
+        team_stage_cost<false, TASK>(model(a.md), jc, tc, S, u, uprev, k == 0, hist, dist, a.K, acc, cnt);
         uprev = u;
         if (a.xout && a.traj && active && primary) {
             float *o = a.xout + ((long)j * a.H + k) * NX;
@@ -346,11 +349,10 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
         }
     }
     const DevModel &md = model(a.md);
-    float t[7];
+    CostAcc tot;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) t[i] = team_sum(acc.t[i]);
-    float c = md.w_goal * t[0] + md.w_eo * t[1] + md.w_l * t[2] + md.w_yz * t[3] + md.w_s * t[4] +
-              md.w_c * (t[5] + t[6]);
+    for (int i = 0; i < NTERMS; ++i) tot.t[i] = (TASK || i < 7) ? team_sum(acc.t[i]) : 0.f;
+    const float c = total_cost<TASK>(md, tot);
     float bad = (isfinite(S.q) && isfinite(S.qd) && isfinite(S.qdes)) ? 0.f : 1.f;
     bad += (isfinite(S.pb.x) && isfinite(S.pb.y) && isfinite(S.pb.z) && isfinite(S.vb.x) && isfinite(S.vb.y) &&
             isfinite(S.vb.z) && isfinite(S.wb.x) && isfinite(S.wb.y) && isfinite(S.wb.z) && isfinite(S.quat[0]) &&
@@ -368,7 +370,7 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
         a.costs[j] = finite ? c : INFINITY;
         if (a.terms) {
 #pragma unroll
-            for (int i = 0; i < NTERMS; ++i) a.terms[(long)j * NTERMS + i] = i < 7 ? t[i] : 0.f;
+            for (int i = 0; i < NTERMS; ++i) a.terms[(long)j * NTERMS + i] = tot.t[i];
         }
         if (a.counters) {
             a.counters[4 * j + 0] = cnt.contacts;
@@ -400,8 +402,10 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
 // positions to wave 1 (B1) and the contact list to wave 0 (B2); both waves run
 // the same loop nest, so they meet every barrier the same number of times.
 // Every value equals the wave-per-sample mapping's bit for bit.
-constexpr int SPLIT_SA = 24;  // state handoff: q[14], ball centre[3], contact count, finite flag
-template <int NC>
+// state handoff: q[14], ball centre[3], contact count, finite flag; the
+// task form also the object's quaternion (SA_QUAT) and qd[14] (SA_QD)
+constexpr int SA_QUAT = 19, SA_QD = 24, SPLIT_SA = 40;
+template <int NC, bool TASK = false>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) rollout_split_kernel(RolloutArgs a0, const RolloutArgs *tab, const int *blk,
                                                              int m)
 {
@@ -469,7 +473,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
     float *dist = a.dist + j;
     CostAcc acc;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) acc.t[i] = 0.f;
+    for (int i = 0; i < NTERMS; ++i) acc.t[i] = 0.f;
     StepCounters cnt = {0, 0, 0, 0};
     float u1 = 0.f, u2 = 0.f;  // controls of the previous two steps (geometry wave's cost)
     for (int k = 0; k < a.H; ++k) {
@@ -493,19 +497,31 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
                 if (k > 0 || s > 0) {
                     if (tc.joint) S.q = SA[d];
                     S.pb = v3(SA[14], SA[15], SA[16]);
+                    if (TASK) {
+                        if (tc.joint) S.qd = SA[SA_QD + d];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) S.quat[i] = SA[SA_QUAT + i];
+                    }
                 }
-                team_fk(jc, S.q, tc.jt, kk);
-                const int nc = team_contacts<64>(model(a.md), tc, kk, S.pb, cnt);
+                team_fk<TASK>(jc, S.q, tc.jt, kk);
+                const int nc = team_contacts<64, TASK>(model(a.md), tc, kk, S.pb, cnt, S.quat);
                 if (lane == 0) SA[17] = __int_as_float(nc);
             } else {
-                team_dynamics<NC, true>(model(a.md), jc, tc, S, u, kk, v, vb, wb);
+                team_dynamics<NC, true, TASK>(model(a.md), jc, tc, S, u, kk, v, vb, wb);
             }
             __syncthreads();  // B2: the contact list and its count are in LDS
             if (!geo) {
                 const int nc = __float_as_int(SA[17]);
-                team_finish<NC, true, true>(model(a.md), tc, S, kk, nc, v, vb, wb);
+                team_finish<NC, true, true, TASK>(model(a.md), tc, S, kk, nc, v, vb, wb);
                 if (tc.joint) SA[d] = S.q;
                 if (lane == 0) { SA[14] = S.pb.x; SA[15] = S.pb.y; SA[16] = S.pb.z; }
+                if (TASK) {
+                    if (tc.joint) SA[SA_QD + d] = S.qd;
+                    if (lane == 0) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) SA[SA_QUAT + i] = S.quat[i];
+                    }
+                }
                 if (s == nsub - 1 && a.xout && a.traj && row == 0) {
                     float *o = a.xout + ((long)j * a.H + k) * NX;
                     if (tc.joint) {
@@ -521,7 +537,8 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
             } else if (s == 0 && k > 0) {
                 // cost of step k - 1 at its post-step state: this substep's positions,
                 // whose geometry and AABBs the contact sweep has just published
-                team_stage_cost<true>(model(a.md), jc, tc, S, u1, u2, k - 1 == 0, hist, dist, a.K, acc, cnt);
+                team_stage_cost<true, TASK>(model(a.md), jc, tc, S, u1, u2, k - 1 == 0, hist, dist, a.K, acc, cnt,
+                                            &kk);
             }
         }
         u2 = u1;
@@ -555,12 +572,16 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
     if (!geo) return;
     if (tc.joint) S.q = SA[d];
     S.pb = v3(SA[14], SA[15], SA[16]);
-    team_stage_cost(md, jc, tc, S, u1, u2, a.H - 1 == 0, hist, dist, a.K, acc, cnt);
-    float t[7];
+    if (TASK) {
+        if (tc.joint) S.qd = SA[SA_QD + d];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) t[i] = team_sum(acc.t[i]);
-    const float c = md.w_goal * t[0] + md.w_eo * t[1] + md.w_l * t[2] + md.w_yz * t[3] + md.w_s * t[4] +
-                    md.w_c * (t[5] + t[6]);
+        for (int i = 0; i < 4; ++i) S.quat[i] = SA[SA_QUAT + i];
+    }
+    team_stage_cost<false, TASK>(md, jc, tc, S, u1, u2, a.H - 1 == 0, hist, dist, a.K, acc, cnt);
+    CostAcc tot;
+#pragma unroll
+    for (int i = 0; i < NTERMS; ++i) tot.t[i] = (TASK || i < 7) ? team_sum(acc.t[i]) : 0.f;
+    const float c = total_cost<TASK>(md, tot);
     const float bad = SA[18];
     const bool finite = isfinite(c) && !(bad > 0.f) && bad == bad;
     const float np = wave_sum((float)cnt.np_tests), nbx = wave_sum((float)cnt.box_tests);
@@ -568,7 +589,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
         a.costs[j] = finite ? c : INFINITY;
         if (a.terms) {
 #pragma unroll
-            for (int i = 0; i < NTERMS; ++i) a.terms[(long)j * NTERMS + i] = i < 7 ? t[i] : 0.f;
+            for (int i = 0; i < NTERMS; ++i) a.terms[(long)j * NTERMS + i] = tot.t[i];
         }
         if (a.counters) {
             a.counters[4 * j + 0] = cnt.contacts;
@@ -582,7 +603,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
 int pick_mapping(int K, int requested)
 {
     if (requested == MAP_LANE || requested == MAP_TEAM || requested == MAP_WAVE || requested == MAP_SPLIT ||
-        requested == MAP_TASK)
+        requested == MAP_TASK || requested == MAP_TASK_WAVE || requested == MAP_TASK_SPLIT)
         return requested;
     // the chip holds 1024 SIMDs: up to ~2 samples per SIMD a wave per sample
     // gives the shortest steps; up to tens of thousands a 16-lane team per
@@ -593,7 +614,10 @@ int pick_mapping(int K, int requested)
 
 int samples_per_block(int mapping)
 {
-    return mapping == MAP_TEAM ? TEAMS_PER_WAVE : (mapping == MAP_WAVE || mapping == MAP_SPLIT) ? 1 : 64;
+    return mapping == MAP_TEAM ? TEAMS_PER_WAVE
+           : (mapping == MAP_WAVE || mapping == MAP_SPLIT || mapping == MAP_TASK_WAVE || mapping == MAP_TASK_SPLIT)
+               ? 1
+               : 64;
 }
 
 static void launch_rollout_impl(const RolloutArgs &a, const RolloutArgs *tab, const int *blk, int nblk, int ncmax,
@@ -601,12 +625,26 @@ static void launch_rollout_impl(const RolloutArgs &a, const RolloutArgs *tab, co
 {
     const int nc = ncmax <= 4 ? 4 : 8;
     const dim3 grid(nblk), block(64);
-    if (map == MAP_SPLIT) {
+    if (map == MAP_SPLIT || map == MAP_TASK_SPLIT) {
         const size_t lds = (size_t)(HD_FIELDS + 2 * team_lds_floats(nc) + SPLIT_SA) * sizeof(float);
-        if (nc == 4)
+        if (map == MAP_TASK_SPLIT) {
+            if (nc == 4)
+                hipLaunchKernelGGL((rollout_split_kernel<4, true>), grid, dim3(128), lds, s, a, tab, blk, m);
+            else
+                hipLaunchKernelGGL((rollout_split_kernel<8, true>), grid, dim3(128), lds, s, a, tab, blk, m);
+        } else if (nc == 4) {
             hipLaunchKernelGGL(rollout_split_kernel<4>, grid, dim3(128), lds, s, a, tab, blk, m);
-        else
+        } else {
             hipLaunchKernelGGL(rollout_split_kernel<8>, grid, dim3(128), lds, s, a, tab, blk, m);
+        }
+        return;
+    }
+    if (map == MAP_TASK_WAVE) {
+        const size_t lds = (size_t)(HD_FIELDS + team_lds_floats(nc)) * sizeof(float);
+        if (nc == 4)
+            hipLaunchKernelGGL((rollout_team_kernel<4, 1, true>), grid, block, lds, s, a, tab, blk, m);
+        else
+            hipLaunchKernelGGL((rollout_team_kernel<8, 1, true>), grid, block, lds, s, a, tab, blk, m);
         return;
     }
     if (map == MAP_TEAM || map == MAP_WAVE) {

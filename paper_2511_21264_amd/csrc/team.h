@@ -36,6 +36,13 @@
 // sample and compute identical values (one shared LDS block, identical
 // writes); they only split the pair sweep, four times wider.  Every
 // per-sample result equals the 4-teams-per-wave form bit for bit.
+//
+// TASK forms (one or two waves per sample): the free object may be a box
+// (its rotation published beside its centre; its vertices against the table
+// ahead of the sweep; pads, links and static boxes through the box
+// narrowphase; the contact solve with its world-frame inverse inertia and
+// the gyroscopic step of its free angular velocity) and the cost may carry
+// the further task terms; ball scenes run the forms without these paths.
 #pragma once
 #include <utility>
 #include "cost.h"
@@ -51,6 +58,10 @@ constexpr int TG_PTS = 0;             // 2 arms x 8 points x 3: joint origins o_
 constexpr int TG_BALL = 48;           // ball centre
 constexpr int TG_AABB = 52;           // dynamic geoms 0..15: lo[3], hi[3] (entry 1, the table, unused)
 constexpr int TG_CAND = TG_AABB + 96; // candidate pair indices of the sweep
+// the box object's rotation (row-major): the task forms sweep a wave wide,
+// which uses no candidate list, so it shares that area (the team block's
+// size sets how many workgroups fit a CU's LDS)
+constexpr int TG_OBJR = TG_CAND;
 constexpr int TG_FIELDS = TG_CAND + ((MPPI_MAX_PAIRS + 3) / 4) * 4;
 
 // per-workgroup LDS header (one scene per workgroup), staged once per
@@ -203,14 +214,41 @@ struct JointConst {
     float bc, bs;  // base yaw (cos, sin)
 };
 
+// the box object's world-frame inverse inertia W = R diag(1/I) R^T
+// (row-major) from its quaternion q
+__device__ __forceinline__ void obj_world_inv_inertia(const DevModel &md, const float q[4], float W[9])
+{
+    const Rot3 R = quat_R(q[0], q[1], q[2], q[3]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            W[3 * i + j] = R.m[3 * i] * R.m[3 * j] * md.obj_iI[0] + R.m[3 * i + 1] * R.m[3 * j + 1] * md.obj_iI[1] +
+                           R.m[3 * i + 2] * R.m[3 * j + 2] * md.obj_iI[2];
+}
+
+// the box object's free angular velocity: w - h R diag(1/I) (w_b x I w_b),
+// w_b = R^T w (the explicit gyroscopic step)
+__device__ __forceinline__ V3 obj_free_w(const DevModel &md, const float q[4], V3 w)
+{
+    const Rot3 R = quat_R(q[0], q[1], q[2], q[3]);
+    const V3 wbb = mulRt(R, w);
+    const V3 Lb = v3(md.obj_I[0] * wbb.x, md.obj_I[1] * wbb.y, md.obj_I[2] * wbb.z);
+    const V3 gb = cross(wbb, Lb);
+    return w - md.h * mulR(R, v3(md.obj_iI[0] * gb.x, md.obj_iI[1] * gb.y, md.obj_iI[2] * gb.z));
+}
+
 // one lane's kinematic quantities of its joint
 struct JointKin {
     V3 a;        // joint axis
     V3 z;        // link axis
     V3 o;        // joint origin
     V3 o1;       // next joint origin (tip for joint 7)
+    V3 x, y;     // link frame's x and y axes (the pad frame on the last joint's lane)
 };
 
+// FRAME: also the link frame's x and y axes (the further cost terms' pad frame)
+template <bool FRAME = false>
 __device__ inline void team_fk(const JointConst &jc, float q, int jt, JointKin &k)
 {
     const bool joint = jt < 7;
@@ -242,6 +280,10 @@ __device__ inline void team_fk(const JointConst &jc, float q, int jt, JointKin &
     const M3 B = M3{{{jc.bc, -jc.bs, 0.f}, {jc.bs, jc.bc, 0.f}, {0.f, 0.f, 1.f}}};
     R = mmul(B, R);
     k.z = v3(R.m[0][2], R.m[1][2], R.m[2][2]);
+    if (FRAME) {
+        k.x = v3(R.m[0][0], R.m[1][0], R.m[2][0]);
+        k.y = v3(R.m[0][1], R.m[1][1], R.m[2][1]);
+    }
     k.a = jc.ax == 0 ? v3(R.m[0][0], R.m[1][0], R.m[2][0]) : (jc.ax == 1 ? v3(R.m[0][1], R.m[1][1], R.m[2][1]) : k.z);
     const V3 d = (joint ? jc.len : 0.f) * k.z;
     const V3 inc = seg_prefix3(d, jt);
@@ -481,13 +523,24 @@ __device__ __forceinline__ void team_publish_geom(float *tl, const JointKin &k, 
 // (arm, jt) boxes arm geom jt (capsule jt from its own joint origin to the
 // next lane's, or the pad sphere at the tip for jt = 6), arm 0's spare lane
 // the ball; the values equal shape_aabb of the published shapes bit for bit,
-// and one wave-local sync covers both
+// and one wave-local sync covers both.  TASK: a box object's rotation (from
+// its quaternion q) is published too, and its AABB is the rotated box's.
+template <bool TASK = false>
 __device__ __forceinline__ void team_publish_geom_aabb(float *tl, const float *hd, const JointKin &k, V3 pb, int arm,
-                                                       int jt)
+                                                       int jt, const DevModel *md = nullptr,
+                                                       const float *q = nullptr)
 {
     const V3 onext = v3(dpp_shl<1>(k.o.x), dpp_shl<1>(k.o.y), dpp_shl<1>(k.o.z));  // next lane's joint origin
     team_publish_geom(tl, k, pb, arm, jt);
-    if (jt < 7 || arm == 0) {
+    if (TASK && md->obj_box && jt == 7 && arm == 0) {
+        const Rot3 R = quat_R(q[0], q[1], q[2], q[3]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) tl[TG_OBJR + i] = R.m[i];
+        const AABB b = obox_aabb(pb, R, v3(md->obj_h[0], md->obj_h[1], md->obj_h[2]));
+        float *o = tl + TG_AABB + 6 * G_BALL;
+        o[0] = b.lo.x; o[1] = b.lo.y; o[2] = b.lo.z;
+        o[3] = b.hi.x; o[4] = b.hi.y; o[5] = b.hi.z;
+    } else if (jt < 7 || arm == 0) {
         Shape sh;
         int gid;
         if (jt < 6) {
@@ -562,10 +615,11 @@ __device__ __forceinline__ uint64_t group_bits(uint64_t wm, int gshift)
 // in the team's LDS list in canonical order; returns the count.  li: lane
 // index within the sweeping group of G lanes.  A whole wave (G = 64) skips
 // the candidate list.
-template <int G>
+template <int G, bool TASK = false>
 __device__ inline int team_collect(const DevModel &md, float *tl, const float *hd, const LaneList &LL, int li,
                                    int gshift, StepCounters &cnt)
 {
+    static_assert(!TASK || G == 64, "the task forms sweep a wave wide");
     const int np = md.n_pairs;
     if constexpr (G == 64) {
         // one sweep a wave: each lane runs the narrowphase of its own
@@ -574,16 +628,54 @@ __device__ inline int team_collect(const DevModel &md, float *tl, const float *h
         // same contacts, in the same order, as the two-pass form below
         int n = 0;
         const uint64_t below = (1ull << li) - 1ull;
+        const bool box = TASK && md.obj_box;
+        Rot3 R;
+        V3 oc = v3(0.f, 0.f, 0.f), oh = v3(0.f, 0.f, 0.f);
+        if (box) {
+            // the box object: its vertices below the table first (its pair
+            // with the table comes first in canonical order), in vertex
+            // order, four at most
+#pragma unroll
+            for (int i = 0; i < 9; ++i) R.m[i] = tl[TG_OBJR + i];
+            oc = v3(tl[TG_BALL], tl[TG_BALL + 1], tl[TG_BALL + 2]);
+            oh = v3(md.obj_h[0], md.obj_h[1], md.obj_h[2]);
+            const bool low = tl[TG_AABB + 6 * G_BALL + 2] < 0.f;
+            bool vhit = false;
+            V3 v = v3(0.f, 0.f, 0.f);
+            if (low && li < 8) {
+                v = obox_vertex(oc, R, oh, li);
+                vhit = v.z < 0.f;
+            }
+            if (low && li == 0) ++cnt.np_tests;
+            const uint64_t gm = __ballot(vhit);
+            const int cap = min(4, md.n_cmax);
+            if (vhit) {
+                const int slot = __popcll(gm & below);
+                if (slot < cap) {
+                    LL.at(slot, 0) = __int_as_float(G_BALL);
+                    LL.at(slot, 1) = __int_as_float(G_TABLE);
+                    LL.at(slot, 2) = v.z;
+                    LL.at(slot, 3) = 0.f; LL.at(slot, 4) = 0.f; LL.at(slot, 5) = 1.f;
+                    LL.at(slot, 6) = v.x; LL.at(slot, 7) = v.y; LL.at(slot, 8) = 0.5f * v.z;
+                }
+            }
+            n = min((int)__popcll(gm), cap);
+        }
         auto narrow_block = [&](bool ov, int gab) {
             if (__ballot(ov) == 0ull) return;
             bool hit = false;
             Contact3 c;
             const int ga = gab & 0xff, gb = gab >> 8;
             if (ov) {
-                const Shape A = team_geom(tl, hd, ga), B = team_geom(tl, hd, gb);
                 ++cnt.np_tests;
-                if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
-                c = narrow(A, B);
+                if (box && ga == G_BALL) {
+                    const Shape B = team_geom(tl, hd, gb);
+                    c = B.type == SH_BOX ? obox_box(oc, R, oh, B.p0, B.p1) : obox_core(oc, R, oh, B);
+                } else {
+                    const Shape A = team_geom(tl, hd, ga), B = team_geom(tl, hd, gb);
+                    if (B.type == SH_BOX && A.type == SH_CAPSULE) ++cnt.box_tests;
+                    c = narrow(A, B);
+                }
                 hit = c.phi < 0.f;
             }
             const uint64_t gm = __ballot(hit);
@@ -604,8 +696,9 @@ __device__ inline int team_collect(const DevModel &md, float *tl, const float *h
             int g0 = 0, g1 = 0;
             if (p0 < np) g0 = __float_as_int(hd[HD_PAIR + p0]);
             if (p1 < np) g1 = __float_as_int(hd[HD_PAIR + p1]);
-            const bool ov0 = p0 < np && pair_overlap(tl, hd, g0 & 0xff, g0 >> 8, 0.f);
-            const bool ov1 = p1 < np && pair_overlap(tl, hd, g1 & 0xff, g1 >> 8, 0.f);
+            constexpr int OBJ_TABLE = G_BALL | (G_TABLE << 8);
+            const bool ov0 = p0 < np && !(box && g0 == OBJ_TABLE) && pair_overlap(tl, hd, g0 & 0xff, g0 >> 8, 0.f);
+            const bool ov1 = p1 < np && !(box && g1 == OBJ_TABLE) && pair_overlap(tl, hd, g1 & 0xff, g1 >> 8, 0.f);
             narrow_block(ov0, g0);
             narrow_block(ov1, g1);
         }
@@ -773,10 +866,11 @@ __device__ inline void pgs_team(const float arow_in[16], float bq, float dq, int
 // over the team).  k: this lane's joint kinematics at the contact positions;
 // v: this lane's joint velocity (free on entry, post-contact on exit); vb, wb:
 // the ball's free velocity and angular velocity, updated in place.
-template <int NC>
+template <int NC, bool TASK = false>
 __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc, const JointKin &k, V3 pb, int nc,
-                                          float &v, V3 &vb, V3 &wb)
+                                          float &v, V3 &vb, V3 &wb, const float *Wo = nullptr)
 {
+    const bool box = TASK && md.obj_box;  // Wo: the box object's world inverse inertia
     constexpr int MR = 4 * NC;
     static_assert(MR >= 16, "the lane-parallel sweeps read 16 rows of A");
     float *E = tc.tl + TG_FIELDS + NC * CL_FIELDS + PK_FIELDS4;  // 16-byte aligned
@@ -872,7 +966,10 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
                     }
                     if (ball_t && ((side_word >> (8 + s)) & 1)) {
                         const V3 rs = v3(E[20 * s + 12], E[20 * s + 13], E[20 * s + 14]);
-                        ball_block(md, rs, rt, G);
+                        if (box)
+                            obj_block(md, Wo, rs, rt, G);
+                        else
+                            ball_block(md, rs, rt, G);
                     }
                     float *g = Gb + 9 * (s * NC + t);
 #pragma unroll
@@ -982,7 +1079,10 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
             for (int q = 0; q < 4; ++q) P = fma3(f[4 * s + q], v3(es[3 * q], es[3 * q + 1], es[3 * q + 2]), P);
             if ((side_word >> (8 + s)) & 1) {
                 vb = fma3(md.inv_ball_m, P, vb);
-                wb = fma3(md.inv_ball_I, cross(v3(es[12], es[13], es[14]), P), wb);
+                if (box)
+                    wb = wb + mul9(Wo, cross(v3(es[12], es[13], es[14]), P));
+                else
+                    wb = fma3(md.inv_ball_I, cross(v3(es[12], es[13], es[14]), P), wb);
             }
             g += dot(Jc[s], P);
         }
@@ -1020,7 +1120,7 @@ __device__ __forceinline__ float *team_solve_area(float *tl) { return tl + TG_FI
 template <int NC>
 __device__ __forceinline__ float *team_row_area(float *tl) { return team_solve_area<NC>(tl) + 20 * NC + 9 * NC * NC; }
 
-template <int NC, bool ROWS = false>
+template <int NC, bool ROWS = false, bool TASK = false>
 __device__ inline void team_dynamics(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
                                      float u, JointKin &k, float &v, V3 &vb, V3 &wb)
 {
@@ -1049,7 +1149,7 @@ __device__ inline void team_dynamics(const DevModel &md, const JointConst &jc, c
     chol7_solve(Lp, xs);
     v = S.qd + pick7(xs, jt);
     vb = v3(S.vb.x, S.vb.y, S.vb.z - h * md.g);
-    wb = S.wb;
+    wb = (TASK && md.obj_box) ? obj_free_w(md, S.quat, S.wb) : S.wb;
     // park the factor for the contact solve (the team keeps the joint axes in
     // registers); it is replicated on the segment: its first lane parks it
     if (jt == 0) {
@@ -1062,12 +1162,12 @@ __device__ inline void team_dynamics(const DevModel &md, const JointConst &jc, c
 
 // Geometry half: publish the kinematics and ball centre, the geom AABBs, and
 // sweep the candidate pairs into the contact list (tc.LL); returns the count.
-template <int G>
+template <int G, bool TASK = false>
 __device__ inline int team_contacts(const DevModel &md, const TeamCtx &tc, const JointKin &k, V3 pb,
-                                    StepCounters &cnt)
+                                    StepCounters &cnt, const float *q = nullptr)
 {
-    team_publish_geom_aabb(tc.tl, tc.hd, k, pb, tc.arm, tc.jt);
-    const int nc = team_collect<G>(md, tc.tl, tc.hd, tc.LL, tc.li, tc.gshift, cnt);
+    team_publish_geom_aabb<TASK>(tc.tl, tc.hd, k, pb, tc.arm, tc.jt, &md, q);
+    const int nc = team_collect<G, TASK>(md, tc.tl, tc.hd, tc.LL, tc.li, tc.gshift, cnt);
     if (tc.t == 0) {
         cnt.contacts += nc;
         if (nc >= md.n_cmax) ++cnt.overflow;
@@ -1138,10 +1238,11 @@ __device__ __forceinline__ int row_bits(uint64_t b)
 // every lane's row of A, which the lanes read back whole.  Every value is
 // formed by the same operations as in team_contact_solve, so the two agree
 // bit for bit.
-template <int NC>
+template <int NC, bool TASK = false>
 __device__ inline void team_contact_solve_rows(const DevModel &md, const TeamCtx &tc, const JointKin &k, V3 pb, int nc,
-                                               float &v, V3 &vb, V3 &wb)
+                                               float &v, V3 &vb, V3 &wb, const float *Wo = nullptr)
 {
+    const bool box = TASK && md.obj_box;  // Wo: the box object's world inverse inertia
     constexpr int MR = 4 * NC;
     static_assert(MR >= 16, "the lane-parallel sweeps read 16 rows of A");
     float *E = tc.tl + TG_FIELDS + NC * CL_FIELDS + PK_FIELDS4;  // 16-byte aligned
@@ -1260,7 +1361,10 @@ __device__ inline void team_contact_solve_rows(const DevModel &md, const TeamCtx
                 if (((side_word >> (8 + t)) & 1) && ((side_word >> (8 + s)) & 1)) {
                     const V3 rs = v3(E[20 * s + 12], E[20 * s + 13], E[20 * s + 14]);
                     const V3 rt = v3(E[20 * t + 12], E[20 * t + 13], E[20 * t + 14]);
-                    ball_block(md, rs, rt, G);
+                    if (box)
+                        obj_block(md, Wo, rs, rt, G);
+                    else
+                        ball_block(md, rs, rt, G);
                 }
                 float *g = Gb + 9 * (s * NC + t);
 #pragma unroll
@@ -1320,7 +1424,10 @@ __device__ inline void team_contact_solve_rows(const DevModel &md, const TeamCtx
             for (int qq = 0; qq < 4; ++qq) P = fma3(f[4 * s + qq], v3(e[3 * qq], e[3 * qq + 1], e[3 * qq + 2]), P);
             if ((side_word >> (8 + s)) & 1) {
                 vb = fma3(md.inv_ball_m, P, vb);
-                wb = fma3(md.inv_ball_I, cross(v3(e[12], e[13], e[14]), P), wb);
+                if (box)
+                    wb = wb + mul9(Wo, cross(v3(e[12], e[13], e[14]), P));
+                else
+                    wb = fma3(md.inv_ball_I, cross(v3(e[12], e[13], e[14]), P), wb);
             }
             g += dot(Jc[s], P);
         }
@@ -1341,52 +1448,94 @@ __device__ inline void team_contact_solve_rows(const DevModel &md, const TeamCtx
 // priority 1 and the general solve at 2 (issue priority only; the results
 // do not change): a launch lasts as long as its slowest samples, which are
 // the ones that spend many substeps in this solve.
-template <int NC, bool ROWS = false, bool PRIO = false>
+template <int NC, bool ROWS = false, bool PRIO = false, bool TASK = false>
 __device__ inline void team_finish(const DevModel &md, const TeamCtx &tc, TeamState &S, const JointKin &k, int nc,
                                    float v, V3 vb, V3 wb)
 {
     const float h = md.h;
-    if (ball_only_contact(tc.LL, nc)) {
+    const bool box = TASK && md.obj_box;
+    float W[9];
+    if (box) obj_world_inv_inertia(md, S.quat, W);
+    if (!box && ball_only_contact(tc.LL, nc)) {
         ball_contact_solve(md, tc.LL, S.pb, vb, wb);
     } else if (ROWS && nc > 0 && nc <= 4) {
         if (PRIO) __builtin_amdgcn_s_setprio(2);
-        team_contact_solve_rows<NC>(md, tc, k, S.pb, nc, v, vb, wb);
+        team_contact_solve_rows<NC, TASK>(md, tc, k, S.pb, nc, v, vb, wb, W);
         if (PRIO) __builtin_amdgcn_s_setprio(1);
     } else if (nc > 0)
-        team_contact_solve<NC>(md, tc, k, S.pb, nc, v, vb, wb);
+        team_contact_solve<NC, TASK>(md, tc, k, S.pb, nc, v, vb, wb, W);
     S.q = fmaf(h, v, S.q);
     S.qd = v;
     integrate_ball(md, S, vb, wb);
 }
 
 // One physics substep of a team: dynamics, contacts, solve, integration.
-template <int NC, int G, bool ROWS = false>
+template <int NC, int G, bool ROWS = false, bool TASK = false>
 __device__ inline void team_substep(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
                                     float u, StepCounters &cnt)
 {
     JointKin k;
     float v;
     V3 vb, wb;
-    team_dynamics<NC, ROWS>(md, jc, tc, S, u, k, v, vb, wb);
-    const int nc = team_contacts<G>(md, tc, k, S.pb, cnt);
-    team_finish<NC, ROWS>(md, tc, S, k, nc, v, vb, wb);
+    team_dynamics<NC, ROWS, TASK>(md, jc, tc, S, u, k, v, vb, wb);
+    const int nc = team_contacts<G, TASK>(md, tc, k, S.pb, cnt, S.quat);
+    team_finish<NC, ROWS, false, TASK>(md, tc, S, k, nc, v, vb, wb);
 }
 
 // per-control-step cost at the post-step state; lane 0 accumulates the stage
 // terms, joint lanes the smoothness, every lane its share of the cost pairs.
 // PUBLISHED: the team's geometry and AABBs in LDS already belong to this
 // state (a contact sweep at the same positions wrote them).
-template <bool PUBLISHED = false>
+// TASK: the further terms too (kin: this state's joint kinematics when
+// PUBLISHED; a box object's AABB is published with the geometry).
+template <bool PUBLISHED = false, bool TASK = false>
 __device__ inline void team_stage_cost(const DevModel &md, const JointConst &jc, const TeamCtx &tc,
                                        const TeamState &S, float u, float uprev, bool first, uint32_t &hist,
-                                       float *dist, long stride, CostAcc &acc, StepCounters &cnt)
+                                       float *dist, long stride, CostAcc &acc, StepCounters &cnt,
+                                       const JointKin *kin = nullptr)
 {
+    JointKin k;
     if (!PUBLISHED) {
-        JointKin k;
-        team_fk(jc, S.q, tc.jt, k);
-        team_publish_geom_aabb(tc.tl, tc.hd, k, S.pb, tc.arm, tc.jt);
+        team_fk<TASK>(jc, S.q, tc.jt, k);
+        team_publish_geom_aabb<TASK>(tc.tl, tc.hd, k, S.pb, tc.arm, tc.jt, &md, S.quat);
+    } else if (TASK) {
+        k = *kin;
     }
     const float *tl = tc.tl;
+    if (TASK && md.ext) {
+        // joint deviation (a team sum), pad velocities v_a = sum_j qd_j a_j x
+        // (p_a - o_j) as segment contributions summed with arm 2's negated,
+        // pad orientations from the last joint lanes' frames
+        const int d = 7 * tc.arm + (tc.joint ? tc.jt : 0);
+        const float hq = tc.joint ? S.q - md.q_home[d] : 0.f;
+        const float home = team_sum(hq * hq);
+        const V3 pa = v3(tl[TG_PTS + 24 * tc.arm + 21], tl[TG_PTS + 24 * tc.arm + 22], tl[TG_PTS + 24 * tc.arm + 23]);
+        const V3 vj = (tc.joint ? (tc.arm == 0 ? S.qd : -S.qd) : 0.f) * cross(k.a, pa - k.o);
+        const V3 v12 = team_sum3(vj);
+        const float ang = rot_angle(md.arotR[tc.arm], k.x, k.y, k.z);
+        const float ang1 = row_bcast<6>(ang), ang2 = row_bcast<14>(ang);
+        if (tc.t == 0) {
+            const V3 p1 = v3(tl[TG_PTS + 21], tl[TG_PTS + 22], tl[TG_PTS + 23]);
+            const V3 p2 = v3(tl[TG_PTS + 45], tl[TG_PTS + 46], tl[TG_PTS + 47]);
+            acc.t[7] += sqrtf(home);
+            acc.t[8] += fabsf(p1.z - p2.z);
+            const float rv = dot(p1 - p2, v12);
+            acc.t[9] = fmaf(rv, rv, acc.t[9]);
+            const V3 d1 = p1 - v3(md.apos[0][0], md.apos[0][1], md.apos[0][2]);
+            const V3 d2 = p2 - v3(md.apos[1][0], md.apos[1][1], md.apos[1][2]);
+            acc.t[10] += sqrtf(dot(d1, d1));
+            acc.t[11] += sqrtf(dot(d2, d2));
+            acc.t[12] += fabsf(p1.x - md.ax_t[0]);
+            acc.t[13] += fabsf(p2.x - md.ax_t[1]);
+            acc.t[14] += ang1;
+            acc.t[15] += ang2;
+            const float qw = S.quat[0], Qw = md.orot[0];
+            const V3 qv = v3(S.quat[1], S.quat[2], S.quat[3]), Qv = v3(md.orot[1], md.orot[2], md.orot[3]);
+            const float wr = fmaf(Qw, qw, dot(Qv, qv));
+            const V3 vr = Qw * qv - qw * Qv - cross(Qv, qv);
+            acc.t[16] += 2.0f * atan2f(sqrtf(dot(vr, vr)), fabsf(wr));
+        }
+    }
     if (tc.t == 0) {
         const V3 p1 = v3(tl[TG_PTS + 21], tl[TG_PTS + 22], tl[TG_PTS + 23]);
         const V3 p2 = v3(tl[TG_PTS + 45], tl[TG_PTS + 46], tl[TG_PTS + 47]);

@@ -9,9 +9,11 @@ the same inputs:
   box - static box by separating axes);
 * rollouts of every task phase with all 17 cost terms;
 * plans from the resting object (the oracle's plan);
-* the routing rules: these scenes run one sample per lane only, the plain
-  per-step form equals the lane form bit for bit, and packed batches and
+* the routing rules: these scenes run one lane, one wave or two waves per
+  sample (the last two bit for bit alike), not four samples a wave; the
+  plain per-step form equals the lane form bit for bit; packed batches and
   served requests that mix them with ball scenes equal each plan alone.
+Every rollout test runs in the three task forms.
 
 Every input state is seeded and chosen with the oracle's geometry, with
 every contact and cost switch clear of zero (FP32 and FP64 may disagree on
@@ -29,6 +31,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 GROUPS = [(0, 7), (7, 14), (14, 21), (21, 28), (28, 35), (35, 42), (42, 45), (45, 49), (49, 52), (52, 55)]
 PHASES = [("tray", "pick"), ("tray", "move"), ("handover", "pick"), ("handover", "pass"), ("handover", "place")]
+FORMS = ["lane", "wave", "split"]
 CLEAR = 2e-4   # every |phi| and |d| at least this far from zero
 
 
@@ -175,8 +178,9 @@ def _substep_states(o, sc, n, seed):
     return np.array(out), kinds
 
 
+@pytest.mark.parametrize("mapping", FORMS)
 @pytest.mark.parametrize("task,phase", [("tray", "pick"), ("handover", "pass")])
-def test_one_substep_box_object(mp, ctx, oracle_mod, task, phase):
+def test_one_substep_box_object(mp, ctx, oracle_mod, task, phase, mapping):
     """One substep (n_sub = 1, one control step) of 96 seeded states against
     the oracle's substep: the box's table vertices, pad and static-box
     contacts, the solve with the world-frame inverse inertia, the gyroscopic
@@ -189,7 +193,7 @@ def test_one_substep_box_object(mp, ctx, oracle_mod, task, phase):
     X = f32(X.astype(np.float32))
     U = np.random.default_rng(5).uniform(-1.0, 1.0, (n, 1, 14)).astype(np.float32)
     Xo = torch.zeros((n, 1, 55), device=DEV)
-    mp.mppi_simulate(ctx, scene, T(X), T(U), X_out=Xo, n_sub=1, traj=True)
+    mp.mppi_simulate(ctx, scene, T(X), T(U), X_out=Xo, n_sub=1, traj=True, mapping=mapping)
     torch.cuda.synchronize()
     got = Xo.cpu().numpy()[:, 0].astype(np.float64)
     lever = float(np.min(sc["obj_h"]))
@@ -200,7 +204,7 @@ def test_one_substep_box_object(mp, ctx, oracle_mod, task, phase):
         want, nc = o.substep(X[i], f32(U[i, 0]))
         ncs.append(nc)
         _close(got[i], want, 2e-4, lever, f"{task} state {i} kind {kinds[i]} contacts {nc}")
-    print(f"{task}/{phase}: contacts per state {np.bincount(ncs)}")
+    print(f"{task}/{phase} {mapping}: contacts per state {np.bincount(ncs)}")
     assert max(ncs) >= 4
     scene.close()
 
@@ -278,8 +282,12 @@ def _rollout_margin(o, sc, x0, U):
     return min(m_phi, m_d)
 
 
+_ROLLOUT_ORACLE = {}
+
+
+@pytest.mark.parametrize("mapping", FORMS)
 @pytest.mark.parametrize("task,phase", PHASES)
-def test_task_rollout_terms(mp, ctx, oracle_mod, task, phase):
+def test_task_rollout_terms(mp, ctx, oracle_mod, task, phase, mapping):
     """Rollouts of 8 control steps (80 samples: a workgroup and a ragged
     tail) with all 17 unweighted terms, the weighted total and the
     trajectory against the oracle."""
@@ -292,29 +300,33 @@ def test_task_rollout_terms(mp, ctx, oracle_mod, task, phase):
     costs = torch.zeros(n, device=DEV)
     terms = torch.zeros((n, mp.NTERMS), device=DEV)
     Xo = torch.zeros((n, H, 55), device=DEV)
-    mp.mppi_simulate(ctx, scene, T(X), T(U), costs=costs, terms=terms, X_out=Xo, traj=True)
+    mp.mppi_simulate(ctx, scene, T(X), T(U), costs=costs, terms=terms, X_out=Xo, traj=True, mapping=mapping)
     torch.cuda.synchronize()
     tg, cg, xg = terms.cpu().numpy().astype(np.float64), costs.cpu().numpy(), Xo.cpu().numpy().astype(np.float64)
     lever = float(np.min(sc["obj_h"]))
     kept, worst = 0, np.zeros(mp.NTERMS)
+    if (task, phase) not in _ROLLOUT_ORACLE:  # the same inputs in every form: the oracle's side once
+        _ROLLOUT_ORACLE[(task, phase)] = [
+            (_rollout_margin(o, sc, X[i], f32(U[i])), o.rollout(X[i], f32(U[i]), want_traj=True)) for i in range(n)]
     for i in range(n):
-        if _rollout_margin(o, sc, X[i], f32(U[i])) < CLEAR:
+        margin, (c, tm, traj) = _ROLLOUT_ORACLE[(task, phase)][i]
+        if margin < CLEAR:
             continue
         kept += 1
-        c, tm, traj = o.rollout(X[i], f32(U[i]), want_traj=True)
         _close(xg[i], traj, 2e-4, lever, f"sample {i}")
         rel = np.abs(tg[i] - tm) / np.maximum(np.abs(tm), 1e-2)
         worst = np.maximum(worst, rel)
         assert np.all(rel < 2e-4), (i, tg[i], tm)
         assert tg[i, 6] == tm[6]
         assert abs(cg[i] - c) <= 2e-4 * max(abs(c), 1.0), (i, cg[i], c)
-    print(f"{task}/{phase}: {kept}/{n} samples kept; worst term rel err {worst}")
+    print(f"{task}/{phase} {mapping}: {kept}/{n} samples kept; worst term rel err {worst}")
     assert kept >= n // 2
     scene.close()
 
 
+@pytest.mark.parametrize("mapping", FORMS)
 @pytest.mark.parametrize("task,phase", [("tray", "pick"), ("handover", "pass")])
-def test_task_plan_against_oracle(mp, ctx, oracle_mod, task, phase):
+def test_task_plan_against_oracle(mp, ctx, oracle_mod, task, phase, mapping):
     """A plan from the object at rest on the table (K = 64, H = 10, M = 3)
     against the oracle's FP64 plan: the resting object's vertex contacts sit
     at |phi| ~ 1e-7, so the comparison is through the last iteration's costs
@@ -328,39 +340,58 @@ def test_task_plan_against_oracle(mp, ctx, oracle_mod, task, phase):
     Unew = torch.zeros((H, 14), device=DEV)
     costs = torch.zeros(K, device=DEV)
     st = mp.mppi_plan(ctx, scene, T(x0), torch.zeros((H, 14), device=DEV), K, H, pp["lam"], T(pp["sigma"]), Unew,
-                      costs, M=M, seed=pp["seed"])
+                      costs, M=M, seed=pp["seed"], mapping=mapping)
     torch.cuda.synchronize()
     r = o.plan(f32(x0), np.zeros((H, 14)), K, H, pp["lam"], f32(pp["sigma"].astype(np.float32)), M, pp["seed"])
     cg = costs.cpu().numpy()
     rel = np.abs(cg - r["costs"]) / np.abs(r["costs"])
     dU = np.abs(Unew.cpu().numpy() - r["nu"]).max()
-    print(f"{task}/{phase} plan: cost rel err median {np.median(rel):.2e} max {rel.max():.2e}; |dU|max {dU:.2e}")
+    print(f"{task}/{phase} {mapping} plan: cost rel err median {np.median(rel):.2e} max {rel.max():.2e}; |dU|max {dU:.2e}")
     assert st["rc"] == 0 and r["rc"] == 0
     assert np.median(rel) < 1e-3
     assert dU < 0.05 * pp["sigma"][0]
     scene.close()
 
 
-def test_task_scenes_run_one_lane_per_sample_only(mp, ctx):
-    """Pinned team, wave or split mappings are refused (MPPI_E_INVAL), the
-    lane pin and the default run, and the autotuner has nothing to tune."""
-    sc = W.task_scene("tray", "move")
-    scene = mp.Scene(ctx, sc)
-    x0 = T(W.initial_state(sc))
-    U = torch.zeros((3, 4, 14), device=DEV)
-    c = torch.zeros(3, device=DEV)
-    for mapping in ("team", "wave", "split"):
+def test_task_forms_routing_and_wave_split_identity(mp, ctx):
+    """A pinned four-samples-a-wave mapping is refused (MPPI_E_INVAL); the
+    wave and split forms agree bit for bit (costs, 17 terms, trajectories,
+    whole plans with their counters) on contact-rich rollouts of the tray
+    and the cube; the autotuner has nothing to tune."""
+    for task, phase in (("tray", "move"), ("handover", "pass")):
+        sc = W.task_scene(task, phase)
+        scene = mp.Scene(ctx, sc)
+        x0 = T(W.initial_state(sc))
+        n, H = 29, 24
+        U = T(np.random.default_rng(8).uniform(-1.0, 1.0, (n, H, 14)))
         with pytest.raises(mp.MppiError):
-            mp.mppi_simulate(ctx, scene, x0, U, costs=c, x0_shared=True, mapping=mapping)
-    out = []
-    for mapping in ("lane", None):
-        mp.mppi_simulate(ctx, scene, x0, U, costs=c, x0_shared=True, mapping=mapping)
-        torch.cuda.synchronize()
-        out.append(c.clone())
-    assert torch.equal(out[0], out[1])
-    with pytest.raises(mp.MppiError):
-        mp.mppi_autotune(ctx, scene, W.initial_state(sc), np.full(14, 0.3), 256, 4)
-    scene.close()
+            mp.mppi_simulate(ctx, scene, x0, U, costs=torch.zeros(n, device=DEV), x0_shared=True, mapping="team")
+        out = {}
+        for mapping in ("wave", "split", None):
+            c = torch.zeros(n, device=DEV)
+            tm = torch.zeros((n, mp.NTERMS), device=DEV)
+            xo = torch.zeros((n, H, 55), device=DEV)
+            mp.mppi_simulate(ctx, scene, x0, U, costs=c, terms=tm, X_out=xo, traj=True, x0_shared=True,
+                             mapping=mapping)
+            torch.cuda.synchronize()
+            out[mapping] = (c.cpu().numpy(), tm.cpu().numpy(), xo.cpu().numpy())
+        for other in ("split", None):
+            for a, b in zip(out["wave"], out[other]):
+                assert np.array_equal(a, b), (task, other)
+        pp = W.plan_params(2, K=70, H=16, M=3)
+        res = {}
+        for mapping in ("wave", "split"):
+            Un = torch.zeros((16, 14), device=DEV)
+            cc = torch.zeros(70, device=DEV)
+            st = mp.mppi_plan(ctx, scene, x0, torch.zeros((16, 14), device=DEV), 70, 16, pp["lam"], T(pp["sigma"]),
+                              Un, cc, M=3, seed=pp["seed"], mapping=mapping)
+            torch.cuda.synchronize()
+            res[mapping] = (Un.cpu().numpy(), cc.cpu().numpy(), st["contacts"], st["overflow"])
+        assert np.array_equal(res["wave"][0], res["split"][0]) and np.array_equal(res["wave"][1], res["split"][1])
+        assert res["wave"][2] == res["split"][2] and res["wave"][3] == res["split"][3]
+        with pytest.raises(mp.MppiError):
+            mp.mppi_autotune(ctx, scene, W.initial_state(sc), np.full(14, 0.3), 256, 4)
+        scene.close()
 
 
 @pytest.mark.parametrize("task,phase", [("tray", "pick"), ("handover", "place")])
@@ -378,7 +409,7 @@ def test_task_plain_per_step_equals_lane(mp, ctx, task, phase):
         U = torch.zeros((H, 14), device=DEV)
         c = torch.zeros(K, device=DEV)
         st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], T(pp["sigma"]), U, c, M=2, seed=pp["seed"],
-                          per_step=per_step)
+                          mapping="lane", per_step=per_step)
         torch.cuda.synchronize()
         out.append((U, c, st))
     (U1, c1, s1), (U2, c2, s2) = out
@@ -412,7 +443,7 @@ def _alone(mp, ctx, it, mapping=None):
     return U, c, st
 
 
-@pytest.mark.parametrize("mapping", [None, "lane"])
+@pytest.mark.parametrize("mapping", [None, "lane", "split"])
 def test_mixed_batch_equals_each_plan_alone(mp, ctx, mapping):
     """A packed batch mixing task and ball scenes: each request equals its
     plan alone bit for bit (the task scenes form launch groups of their own)."""
