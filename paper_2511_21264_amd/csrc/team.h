@@ -862,6 +862,42 @@ __device__ inline void pgs_team(const float arow_in[16], float bq, float dq, int
     });
 }
 
+// Gauss-Seidel over m <= MR rows (up to 32) for a wave that carries one team:
+// the u-form of pgs_team with lane q holding row q of C = -d_q A (zero
+// diagonal) and u_q; row r's change reaches every lane through a scalar
+// register (v_readlane), so rows beyond one 16-lane row need no LDS trips.
+// On return f[r], r < m, holds the multipliers on every lane.
+template <int MR>
+__device__ inline void pgs_wave(const float *A, const float *Bv, const float *Dv, int m, int n_pgs, int lane,
+                                float f[MR])
+{
+    static_assert(MR <= 64, "one row a lane");
+    const int mu = __builtin_amdgcn_readfirstlane(m), ns = __builtin_amdgcn_readfirstlane(n_pgs);
+    const bool mine = lane < mu;
+    const float nd = mine ? -Dv[lane] : 0.f;
+    float c[MR];
+#pragma unroll
+    for (int cc = 0; cc < MR; ++cc) c[cc] = (mine && cc < mu && cc != lane) ? nd * A[lane * MR + cc] : 0.f;
+    float u = mine ? nd * Bv[lane] : 0.f;
+    float fq = 0.f;
+    for (int sweep = 0; sweep < ns; ++sweep) {
+        static_for<MR>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            if (r < mu) {
+                const float fn = fmaxf(u, 0.f);
+                const float dl = fn - fq;
+                fq = lane == r ? fn : fq;
+                const float sd = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dl), r));
+                u = fmaf(c[r], sd, u);
+            }
+        });
+    }
+    static_for<MR>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        f[r] = r < mu ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fq), r)) : 0.f;
+    });
+}
+
 // Contact solve of one team (nc >= 1 contacts in the team's list, nc uniform
 // over the team).  k: this lane's joint kinematics at the contact positions;
 // v: this lane's joint velocity (free on entry, post-contact on exit); vb, wb:
@@ -1046,6 +1082,10 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
             Bv[r] = dot(eq, v3(es[16], es[17], es[18])) - es[15];
         }
         wave_lds_sync();
+        if (TASK) {
+            // the task forms carry one team a wave: the sweep lane-parallel
+            pgs_wave<MR>(A, Bv, Dv, m, md.n_pgs, tc.lane, f);
+        } else {
         float *F = Rv + MR;
         for (int r = 0; r < m; ++r) F[r] = 0.f;
         for (int sweep = 0; sweep < md.n_pgs; ++sweep) {
@@ -1067,6 +1107,7 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
 #pragma unroll
         for (int r = 0; r < MR; ++r)
             if (r < m) f[r] = F[r];
+        }
     }
     // impulses back: ball (geom A) directly, joints through Mt^-1 J^T
     float g = 0.f;  // generalized impulse of this lane's joint
