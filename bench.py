@@ -852,17 +852,17 @@ def sources_hash():
 # rollout kernel's time, traffic and issued operations), and the QP and
 # covariance legs (their kernels' times)
 PROFILE_ARGS_MAIN = ("--steps 3 --warmup 1 --no-cpu-baseline --packed-steps 0 --serve-seconds 0 --no-precision "
-                     "--replans 0 --no-qp --no-cov --no-episodes --no-extra")
+                     "--replans 0 --no-qp --no-cov --no-extra")
 PROFILE_ARGS_NEXT = ("--steps 1 --warmup 0 --no-cpu-baseline --packed-steps 0 --serve-seconds 0 --no-precision "
-                     "--replans 0 --no-episodes --no-extra")
+                     "--replans 0 --no-extra")
 # launches that fill the chip, one workload per profiled process: the main
 # scene at 32768 samples one per lane and 16 lanes per sample, the 32 packed
 # scenes of the uneven-batch workload in one batch, and the tray's move phase
 # at 32768 samples (the task form)
 OCC_RUNS = {
     "lane32k": ("%rollout_kernel<4, false>%", "main scene, K=32768, H=64, one lane per sample"),
-    "team32k": ("%rollout_team_kernel<4, 4>%", "main scene, K=32768, H=64, 16 lanes per sample"),
-    "packed": ("%rollout_team_kernel<4, 4>%", "32 packed scenes (K 256..4096, H 32..128), one batch, team family"),
+    "team32k": ("%rollout_team_kernel<4, 4, false>%", "main scene, K=32768, H=64, 16 lanes per sample"),
+    "packed": ("%rollout_team_kernel<4, 4, false>%", "32 packed scenes (K 256..4096, H 32..128), one batch, team family"),
     "task32k": ("%rollout_kernel<8, true>%", "tray move phase, K=32768, H=64, task form"),
 }
 
@@ -1034,7 +1034,7 @@ def summarize_stalls(base, meta):
         return v[n][0] * 4 / wc
     valu = v["SQ_INSTS_VALU"][0]
     simd_cycles = valu * 4 / 1024
-    md = ["# rollout_split_kernel<4>, K=1024, H=64 obstacle workload: where the wave cycles go (SQ counters)", "",
+    md = ["# rollout_split_kernel<4, false>, K=1024, H=64 obstacle workload: where the wave cycles go (SQ counters)", "",
           "Commands (run from the repository root, TMPDIR=/tmp; two passes, at most eight SQ counters each):", ""]
     md += [f"    {c}" for c in meta["stall_commands"]]
     md += ["", f"Kernel sources: sha256 {sources_hash()[:16]} (the csrc tree as `bench.sources_hash` reads it). "
@@ -1079,10 +1079,10 @@ def profile_meta():
     b = f"python3 bench.py {PROFILE_ARGS_MAIN}"
     bn = f"python3 bench.py {PROFILE_ARGS_NEXT}"
     return {
-        "title": "rollout_split_kernel<4> (two waves per sample), K=1024, H=64 obstacle workload: kernel time and "
+        "title": "rollout_split_kernel<4, false> (two waves per sample), K=1024, H=64 obstacle workload: kernel time and "
                  "HBM traffic",
         "file": "rollout_split_c2.md", "mapping": "split", "K": 1024, "H": 64,
-        "kernel_like": "%rollout_split_kernel<4>%", "calib_copy_bytes": 256 << 20,
+        "kernel_like": "%rollout_split_kernel<4, false>%", "calib_copy_bytes": 256 << 20,
         "commands": [
             f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run -- {b}",
             f"timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/fetch -o run -- {b}",
@@ -1344,8 +1344,8 @@ def main():
     mapping = None if args.mapping == "auto" else args.mapping
     used = tuned["chosen"] if tuned else args.mapping
     nc = 4 if int(sc["n_cmax"]) <= 4 else 8
-    kernel_name = {"lane": f"rollout_kernel<{nc}>", "team": f"rollout_team_kernel<{nc}, 4>",
-                   "wave": f"rollout_team_kernel<{nc}, 1>", "split": f"rollout_split_kernel<{nc}>"}[used]
+    kernel_name = {"lane": f"rollout_kernel<{nc}, false>", "team": f"rollout_team_kernel<{nc}, 4, false>",
+                   "wave": f"rollout_team_kernel<{nc}, 1, false>", "split": f"rollout_split_kernel<{nc}, false>"}[used]
 
     def plan():
         return mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], sig, Unew, costs, M=M, seed=pp["seed"],
