@@ -77,7 +77,9 @@ extern "C" {
                                    class on this context, else chosen from K.  In packed batches and
                                    served requests each request keeps the family of the mapping it
                                    would get alone (lane, or team/wave/split, which agree bit for bit),
-                                   so its results do not depend on what it is batched with */
+                                   so its results do not depend on what it is batched with.  Scenes
+                                   with a box object or the further cost terms run the same flags in
+                                   their task forms (lane, or wave/split; MPPI_MAP_TEAM is refused) */
 #define MPPI_FP32_WEIGHTS 512u  /* mppi_plan, mppi_update: the weights of Eq. s_formula, their sums and the
                                    weighted mean of Eq. mean_update in FP32 instead of FP64 (precision
                                    study; the default keeps them in FP64) */
