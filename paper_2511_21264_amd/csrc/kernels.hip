@@ -606,10 +606,11 @@ int pick_mapping(int K, int requested)
         requested == MAP_TASK || requested == MAP_TASK_WAVE || requested == MAP_TASK_SPLIT)
         return requested;
     // the chip holds 1024 SIMDs: up to ~2 samples per SIMD a wave per sample
-    // gives the shortest steps; up to tens of thousands a 16-lane team per
-    // sample; beyond that one lane per sample has the highest throughput
+    // gives the shortest steps; below 64 k samples a 16-lane team per sample
+    // (one lane per sample fills too few waves: at 32 k it is 1.5 x slower);
+    // from 64 k on one lane per sample has the highest throughput
     if (K <= 2048) return MAP_WAVE;
-    return K >= 32768 ? MAP_LANE : MAP_TEAM;
+    return K >= 65536 ? MAP_LANE : MAP_TEAM;
 }
 
 int samples_per_block(int mapping)

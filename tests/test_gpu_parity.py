@@ -652,3 +652,29 @@ def test_autotune_records_the_mapping_auto_uses(mp, ctx):
     scene2.close()
     c2.close()
     scene.close()
+
+
+def test_unpinned_mapping_follows_k(mp):
+    """On a context with nothing tuned, an unpinned rollout takes the built-in
+    choice for its K: a team per sample below 65536 samples (bit-identical
+    to pinning it), one lane per sample from 65536 on; scenes in the task
+    forms take the wave form at 8192 samples and one lane from 16384 on."""
+    cx = mp.Context(0)
+    H = 2
+    cases = ((W.make_scene(2), ((32768, "team"), (65536, "lane"))),
+             (W.task_scene("tray", "move"), ((8192, "wave"), (16384, "lane"))))
+    for sc, ks in cases:
+        scene = mp.Scene(cx, sc)
+        x0 = T(W.initial_state(sc))
+        for n, expect in ks:
+            print(f"unpinned mapping: K={n} expects {expect}", flush=True)
+            U = T(np.random.default_rng(n).uniform(-1.0, 1.0, (n, H, 14)))
+            out = {}
+            for mapping in (None, expect):
+                c = torch.zeros(n, device=DEV)
+                mp.mppi_simulate(cx, scene, x0, U, costs=c, x0_shared=True, mapping=mapping)
+                torch.cuda.synchronize()
+                out[mapping] = c.cpu().numpy()
+            assert np.array_equal(out[None], out[expect]), (n, expect)
+        scene.close()
+    cx.close()
