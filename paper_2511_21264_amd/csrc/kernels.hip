@@ -394,17 +394,50 @@ __global__ void __launch_bounds__(64) rollout_team_kernel(RolloutArgs a0, const 
 }
 
 // Split mapping: two waves per sample.  Wave 0 (dynamics) owns the state and
-// runs the kinematics, inertia, factorisation, bias forces and free
-// velocities, then the contact solve and the integration; wave 1 (geometry)
-// runs, concurrently with wave 0's dynamics, the kinematics again, the geom
-// AABBs and the contact sweep, and during wave 0's contact solve the cost of
-// the previous control step.  Two workgroup barriers per substep hand the
-// positions to wave 1 (B1) and the contact list to wave 0 (B2); both waves run
-// the same loop nest, so they meet every barrier the same number of times.
-// Every value equals the wave-per-sample mapping's bit for bit.
+// runs the inertia, factorisation, bias forces and free velocities, then the
+// contact solve, the integration and the kinematics at the new positions;
+// wave 1 (geometry) takes those kinematics and runs, concurrently with wave
+// 0's dynamics, the geom AABBs and the contact sweep, and during wave 0's
+// contact solve the cost of the previous control step.  Two workgroup
+// barriers per substep hand the positions and kinematics to wave 1 (B1) and
+// the contact list to wave 0 (B2); both waves run the same loop nest, so they
+// meet every barrier the same number of times.  Every value equals the
+// wave-per-sample mapping's bit for bit.
 // state handoff: q[14], ball centre[3], contact count, finite flag; the
-// task form also the object's quaternion (SA_QUAT) and qd[14] (SA_QD)
-constexpr int SA_QUAT = 19, SA_QD = 24, SPLIT_SA = 40;
+// task form also the object's quaternion (SA_QUAT) and qd[14] (SA_QD); the
+// kinematics of the team's 16 lanes, 20 floats each (SA_KIN: a, z, o, o1,
+// and the link frame's x, y)
+constexpr int SA_QUAT = 19, SA_QD = 24, SA_KIN = 40, SPLIT_SA = SA_KIN + 16 * 20;
+
+// FRAME: with the link frame's x and y axes
+template <bool FRAME>
+__device__ __forceinline__ void split_put_kin(float *p, const JointKin &k)
+{
+    float4 *o = reinterpret_cast<float4 *>(p);
+    o[0] = make_float4(k.a.x, k.a.y, k.a.z, k.z.x);
+    o[1] = make_float4(k.z.y, k.z.z, k.o.x, k.o.y);
+    o[2] = make_float4(k.o.z, k.o1.x, k.o1.y, k.o1.z);
+    if (FRAME) {
+        o[3] = make_float4(k.x.x, k.x.y, k.x.z, k.y.x);
+        o[4] = make_float4(k.y.y, k.y.z, 0.f, 0.f);
+    }
+}
+
+template <bool FRAME>
+__device__ __forceinline__ void split_get_kin(const float *p, JointKin &k)
+{
+    const float4 *i = reinterpret_cast<const float4 *>(p);
+    const float4 a = i[0], b = i[1], c = i[2];
+    k.a = v3(a.x, a.y, a.z);
+    k.z = v3(a.w, b.x, b.y);
+    k.o = v3(b.z, b.w, c.x);
+    k.o1 = v3(c.y, c.z, c.w);
+    if (FRAME) {
+        const float4 d = i[3], e = i[4];
+        k.x = v3(d.x, d.y, d.z);
+        k.y = v3(d.w, e.x, e.y);
+    }
+}
 template <int NC, bool TASK = false>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))) rollout_split_kernel(RolloutArgs a0, const RolloutArgs *tab, const int *blk,
                                                              int m)
@@ -476,6 +509,13 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int i = 0; i < NTERMS; ++i) acc.t[i] = 0.f;
     StepCounters cnt = {0, 0, 0, 0};
     float u1 = 0.f, u2 = 0.f;  // controls of the previous two steps (geometry wave's cost)
+    // the kinematics at the current positions: formed by the dynamics wave
+    // (at x0 here, then after each integration), published for the geometry wave
+    JointKin kd;
+    if (!geo) {
+        team_fk<TASK>(jc, S.q, tc.jt, kd);
+        if (row == 0) split_put_kin<TASK>(SA + SA_KIN + 20 * tc.t, kd);
+    }
     for (int k = 0; k < a.H; ++k) {
         const DevModel &md = model(a.md);
         float u = 0.f;
@@ -503,16 +543,19 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2, 2))
                         for (int i = 0; i < 4; ++i) S.quat[i] = SA[SA_QUAT + i];
                     }
                 }
-                team_fk<TASK>(jc, S.q, tc.jt, kk);
+                split_get_kin<TASK>(SA + SA_KIN + 20 * tc.t, kk);
                 const int nc = team_contacts<64, TASK>(model(a.md), tc, kk, S.pb, cnt, S.quat);
                 if (lane == 0) SA[17] = __int_as_float(nc);
             } else {
-                team_dynamics<NC, true, TASK>(model(a.md), jc, tc, S, u, kk, v, vb, wb);
+                kk = kd;
+                team_dynamics<NC, true, TASK, true>(model(a.md), jc, tc, S, u, kk, v, vb, wb);
             }
             __syncthreads();  // B2: the contact list and its count are in LDS
             if (!geo) {
                 const int nc = __float_as_int(SA[17]);
                 team_finish<NC, true, true, TASK>(model(a.md), tc, S, kk, nc, v, vb, wb);
+                team_fk<TASK>(jc, S.q, tc.jt, kd);
+                if (row == 0) split_put_kin<TASK>(SA + SA_KIN + 20 * tc.t, kd);
                 if (tc.joint) SA[d] = S.q;
                 if (lane == 0) { SA[14] = S.pb.x; SA[15] = S.pb.y; SA[16] = S.pb.z; }
                 if (TASK) {

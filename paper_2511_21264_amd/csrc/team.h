@@ -1161,7 +1161,8 @@ __device__ __forceinline__ float *team_solve_area(float *tl) { return tl + TG_FI
 template <int NC>
 __device__ __forceinline__ float *team_row_area(float *tl) { return team_solve_area<NC>(tl) + 20 * NC + 9 * NC * NC; }
 
-template <int NC, bool ROWS = false, bool TASK = false>
+// HAVE_K: k already holds the kinematics at S.q
+template <int NC, bool ROWS = false, bool TASK = false, bool HAVE_K = false>
 __device__ inline void team_dynamics(const DevModel &md, const JointConst &jc, const TeamCtx &tc, TeamState &S,
                                      float u, JointKin &k, float &v, V3 &vb, V3 &wb)
 {
@@ -1169,7 +1170,7 @@ __device__ inline void team_dynamics(const DevModel &md, const JointConst &jc, c
     const float h = md.h;
     const int jt = tc.jt, seg = tc.seg;
     S.qdes = fmaf(h, u, S.qdes);
-    team_fk(jc, S.q, jt, k);
+    if (!HAVE_K) team_fk(jc, S.q, jt, k);
     float Lp[28];
     if (ROWS) {
         team_mass_rows(md, jc, k, jt, tc.t, tc.arm, tc.lane, team_row_area<NC>(tc.tl), Lp);
