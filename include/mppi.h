@@ -74,15 +74,15 @@ extern "C" {
                                    cost concurrently (shortest steps at small K); results equal
                                    MPPI_MAP_WAVE's bit for bit */
                                 /* none of the four: the mapping mppi_autotune measured for K's size
-                                   class on this context, else chosen from K (a wave per sample up to
-                                   2048 samples, a team below 65536, one lane from there on).  In
-                                   packed batches and served requests each request keeps the family of
-                                   the mapping it would get alone (lane, or team/wave/split, which agree
-                                   bit for bit), so its results do not depend on what it is batched
-                                   with.  Scenes
-                                   with a box object or the further cost terms run the same flags in
-                                   their task forms (lane, or wave/split; MPPI_MAP_TEAM is refused;
-                                   unpinned, one lane per sample from 16384 samples on) */
+                                   class on this context, else chosen from K (two waves per sample up
+                                   to 1024 samples, one wave up to 2048, a team below 65536, one lane
+                                   from there on).  In packed batches and served requests each request
+                                   keeps the family of the mapping it would get alone (lane, or
+                                   team/wave/split, which agree bit for bit), so its results do not
+                                   depend on what it is batched with.  Scenes with a box object or the
+                                   further cost terms run the same flags in their task forms (lane, or
+                                   wave/split; MPPI_MAP_TEAM is refused; unpinned, one lane per sample
+                                   from 16384 samples on) */
 #define MPPI_FP32_WEIGHTS 512u  /* mppi_plan, mppi_update: the weights of Eq. s_formula, their sums and the
                                    weighted mean of Eq. mean_update in FP32 instead of FP64 (precision
                                    study; the default keeps them in FP64) */

@@ -648,10 +648,13 @@ int pick_mapping(int K, int requested)
     if (requested == MAP_LANE || requested == MAP_TEAM || requested == MAP_WAVE || requested == MAP_SPLIT ||
         requested == MAP_TASK || requested == MAP_TASK_WAVE || requested == MAP_TASK_SPLIT)
         return requested;
-    // the chip holds 1024 SIMDs: up to ~2 samples per SIMD a wave per sample
-    // gives the shortest steps; below 64 k samples a 16-lane team per sample
-    // (one lane per sample fills too few waves: at 32 k it is 1.5 x slower);
-    // from 64 k on one lane per sample has the highest throughput
+    // the chip holds 1024 SIMDs: up to 2 waves per SIMD two waves per sample
+    // give the shortest steps (at K = 1024, H = 64: 1.90 against 2.21 ms a
+    // wave per sample), up to ~2 samples per SIMD one wave per sample (at
+    // 2048: 2.77 against 4.14 ms); below 64 k samples a 16-lane team per
+    // sample (one lane per sample fills too few waves: at 32 k it is 1.5 x
+    // slower); from 64 k on one lane per sample has the highest throughput
+    if (K <= 1024) return MAP_SPLIT;
     if (K <= 2048) return MAP_WAVE;
     return K >= 65536 ? MAP_LANE : MAP_TEAM;
 }
