@@ -26,23 +26,26 @@ def T(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=DEV)
 
 
-def _case(sc, K, H, M, seed):
+def _case(sc, K, H, M, seed, task=False):
     pp = W.plan_params(2, K=K, H=H, M=M, seed=seed)
-    x0 = T(W.random_states(sc, 1, seed=seed, spread=0.1)[0])
+    x0 = T(W.initial_state(sc) if task else W.random_states(sc, 1, seed=seed, spread=0.1)[0])
     nom = T(np.random.default_rng(seed).uniform(-0.3, 0.3, (H, 14)))
     return pp, x0, nom
 
 
-@pytest.mark.parametrize("mapping", [None, "lane"])
-def test_noalloc_plan_equals_plan_twice(mp, mapping):
+@pytest.mark.parametrize("scene_kind,mapping", [("ball", None), ("ball", "lane"), ("tray", None)])
+def test_noalloc_plan_equals_plan_twice(mp, scene_kind, mapping):
+    """Ball scenes in the default and the one-lane mapping; the tray-moving
+    phase (box object, further cost terms) in its default task form."""
     ctx = mp.Context(0)
-    sc = W.make_scene(2)
+    task = scene_kind == "tray"
+    sc = W.task_scene("tray", "move") if task else W.make_scene(2)
     scene = mp.Scene(ctx, sc)
     cases = [(1024, 64, 3, 11), (300, 17, 2, 12)]   # the second call smaller than the first
     # warm-up: kernels loaded and the context's own buffers grown by mppi_plan
     outs = []
     for K, H, M, seed in cases:
-        pp, x0, nom = _case(sc, K, H, M, seed)
+        pp, x0, nom = _case(sc, K, H, M, seed, task)
         U = torch.zeros((H, 14), device=DEV)
         c = torch.zeros(K, device=DEV)
         st = mp.mppi_plan(ctx, scene, x0, nom, K, H, pp["lam"], T(pp["sigma"]), U, c, M=M, seed=pp["seed"],
