@@ -767,17 +767,29 @@ __device__ __forceinline__ uint32_t ordered_bits(float f)
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// Sum over the 64 lanes of a wave by an xor butterfly of wavefront shuffles:
+// every lane ends with the same bits (each pair of lanes adds the same two
+// values, and IEEE addition commutes).
 template <typename T>
+__device__ __forceinline__ T wave_allsum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over a workgroup of NT lanes: wave sums, then the NT / 64 of them in
+// wave order (sh: NT / 64 entries); every lane returns the same value.
+template <typename T, int NT = SB>
 __device__ __forceinline__ T block_sum(T v, T *sh)
 {
+    v = wave_allsum(v);
     const int t = threadIdx.x;
-    sh[t] = v;
+    if ((t & 63) == 0) sh[t >> 6] = v;
     __syncthreads();
-    for (int s = SB / 2; s > 0; s >>= 1) {
-        if (t < s) sh[t] += sh[t + s];
-        __syncthreads();
-    }
-    const T r = sh[0];
+    T r = sh[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) r += sh[w];
     __syncthreads();
     return r;
 }
@@ -794,10 +806,10 @@ __global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a0, const StatsArgs
         a = tab[blockIdx.x];
         if (m >= 0) a.iter = m;
     }
-    __shared__ double shd[SB];
-    __shared__ unsigned long long shu[SB];
-    __shared__ float shf[SB];
-    __shared__ int shi[SB];
+    __shared__ double shd[SB / 64];
+    __shared__ unsigned long long shu[SB / 64];
+    __shared__ float shf[SB / 64];
+    __shared__ int shi[SB / 64];
     const int t = threadIdx.x;
     // lowest finite cost (ties: lowest index) and finite count
     float best = INFINITY;
@@ -809,19 +821,27 @@ __global__ void __launch_bounds__(SB) stats_kernel(StatsArgs a0, const StatsArgs
             if (c < best || (c == best && j < bi)) { best = c; bi = j; }
         }
     }
-    shf[t] = best;
-    shi[t] = bi;
-    __syncthreads();
-    for (int s = SB / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            const float c2 = shf[t + s];
-            const int i2 = shi[t + s];
-            if (c2 < shf[t] || (c2 == shf[t] && i2 < shi[t])) { shf[t] = c2; shi[t] = i2; }
-        }
-        __syncthreads();
+    // (cost, index) minimum: wavefront shuffles within each wave, then the
+    // waves' results in order (the selection is exact, so every lane agrees)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float c2 = __shfl_xor(best, o, 64);
+        const int i2 = __shfl_xor(bi, o, 64);
+        if (c2 < best || (c2 == best && i2 < bi)) { best = c2; bi = i2; }
     }
-    const float cmin = shf[0];
-    const int best_j = shi[0];
+    if ((t & 63) == 0) {
+        shf[t >> 6] = best;
+        shi[t >> 6] = bi;
+    }
+    __syncthreads();
+    float cmin = shf[0];
+    int best_j = shi[0];
+#pragma unroll
+    for (int w = 1; w < SB / 64; ++w) {
+        const float c2 = shf[w];
+        const int i2 = shi[w];
+        if (c2 < cmin || (c2 == cmin && i2 < best_j)) { cmin = c2; best_j = i2; }
+    }
     __syncthreads();
     const unsigned long long nfin = block_sum<unsigned long long>((unsigned long long)nf, shu);
     // elite threshold: the n_e-th smallest key (ordered cost bits, index)
@@ -921,7 +941,7 @@ constexpr int UB = 256;
 template <typename T>
 __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateArgs *tab, const int *blk, int m)
 {
-    __shared__ T red[NU][UB];
+    __shared__ T red[NU][UB / 64];
     UpdateArgs a = a0;
     int k = blockIdx.x;
     if (tab) {
@@ -952,20 +972,22 @@ __global__ void __launch_bounds__(UB) update_kernel(UpdateArgs a0, const UpdateA
             }
         }
     }
+    // the sums over the samples: wavefront shuffles within each wave, then
+    // the waves' sums in order
 #pragma unroll
-    for (int d = 0; d < NU; ++d) red[d][t] = acc[d];
-    __syncthreads();
-    for (int s = UB / 2; s > 0; s >>= 1) {
-        if (t < s) {
+    for (int d = 0; d < NU; ++d) acc[d] = wave_allsum(acc[d]);
+    if ((t & 63) == 0) {
 #pragma unroll
-            for (int d = 0; d < NU; ++d) red[d][t] += red[d][t + s];
-        }
-        __syncthreads();
+        for (int d = 0; d < NU; ++d) red[d][t >> 6] = acc[d];
     }
+    __syncthreads();
     if (t < NU) {
+        T sum = red[t][0];
+#pragma unroll
+        for (int w = 1; w < UB / 64; ++w) sum += red[t][w];
         const T nu0 = (T)a.nu_in[k * NU + t];
         const T eta = (T)a.eta;
-        const T v = div ? nu0 : (T(1) - eta) * nu0 + eta * red[t][0];
+        const T v = div ? nu0 : (T(1) - eta) * nu0 + eta * sum;
         a.nu_out[k * NU + t] = (float)v;
         if (a.nu_out64) a.nu_out64[k * NU + t] = (double)v;
     }
