@@ -144,12 +144,22 @@ def _contact_states(sc, n, seed):
 
 
 def _group_close(got, want, rtol):
-    """|got - want| <= rtol * scale, scale = the largest magnitude of that state group."""
+    """Element by element: |got - want| <= rtol * max(|want|, floor), floor a
+    quarter of the largest magnitude in that state group: entries near zero
+    take their FP32 error from the group's larger terms.  The ball's spin is
+    held to the group's largest magnitude instead: a contact impulse changes
+    all three components through I^-1 (r x P), so each one's error follows
+    the impulse, not its own size (a component of 0.5 rad/s next to one of
+    16.6 is off by 9.7e-5)."""
     groups = [(0, 14), (14, 28), (28, 42), (42, 45), (45, 49), (49, 52), (52, 55)]
     for a, b in groups:
-        scale = max(np.abs(want[..., a:b]).max(), 1e-3)
-        err = np.abs(got[..., a:b] - want[..., a:b]).max()
-        assert err <= rtol * scale, (a, b, err, scale)
+        w = want[..., a:b]
+        scale = max(np.abs(w).max(), 1e-3)
+        err = np.abs(got[..., a:b] - w)
+        floor = scale if a == 52 else 0.25 * scale
+        bound = rtol * np.maximum(np.abs(w), floor)
+        worst = np.unravel_index(np.argmax(err / bound), err.shape)
+        assert np.all(err <= bound), (a, b, worst, err[worst], bound[worst], scale)
 
 
 @pytest.mark.parametrize("mapping", ["lane", "team", "wave", "split"])
