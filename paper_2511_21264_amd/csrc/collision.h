@@ -86,8 +86,8 @@ __device__ __forceinline__ Contact3 sphere_sphere(V3 xa, float ra, V3 xb, float 
 {
     Contact3 c;
     const V3 d = xa - xb;
-    const float dist = sqrtf(dot(d, d));
-    c.n = dist > 1e-9f ? (1.0f / dist) * d : v3(0.f, 0.f, 1.f);
+    const float dist = fsqrt(dot(d, d));
+    c.n = dist > 1e-9f ? frcp(dist) * d : v3(0.f, 0.f, 1.f);
     c.phi = dist - ra - rb;
     c.p = 0.5f * ((xa - ra * c.n) + (xb + rb * c.n));
     return c;
@@ -113,8 +113,8 @@ __device__ __forceinline__ Contact3 sphere_box(V3 x, float r, V3 c, V3 h)
     if (outside) {
         q = v3(clampf(l.x, -h.x, h.x), clampf(l.y, -h.y, h.y), clampf(l.z, -h.z, h.z));
         const V3 d = l - q;
-        const float dist = sqrtf(dot(d, d));
-        out.n = (1.0f / dist) * d;
+        const float dist = fsqrt(dot(d, d));
+        out.n = frcp(dist) * d;
         out.phi = dist - r;
     } else {
         const float ex = fabsf(l.x) - h.x, ey = fabsf(l.y) - h.y, ez = fabsf(l.z) - h.z;
@@ -136,7 +136,7 @@ __device__ __forceinline__ float seg_point_param(V3 p0, V3 p1, V3 x)
 {
     const V3 d = p1 - p0;
     const float dd = dot(d, d);
-    return dd > 0.f ? clampf(dot(x - p0, d) / dd, 0.f, 1.f) : 0.f;
+    return dd > 0.f ? clampf(dot(x - p0, d) * frcp(dd), 0.f, 1.f) : 0.f;
 }
 
 // closest points of segments P0 + s D1, Q0 + t D2
@@ -145,14 +145,14 @@ __device__ __forceinline__ void seg_seg_params(V3 p0, V3 p1, V3 q0, V3 q1, float
     const V3 d1 = p1 - p0, d2 = q1 - q0, r = p0 - q0;
     const float a = dot(d1, d1), e = dot(d2, d2), b = dot(d1, d2), c = dot(d1, r), f = dot(d2, r);
     const float den = a * e - b * b;
-    s = den > 0.f ? clampf((b * f - c * e) / den, 0.f, 1.f) : 0.f;
-    t = (b * s + f) / e;
+    s = den > 0.f ? clampf((b * f - c * e) * frcp(den), 0.f, 1.f) : 0.f;
+    t = (b * s + f) * frcp(e);
     if (t < 0.f) {
         t = 0.f;
-        s = clampf(-c / a, 0.f, 1.f);
+        s = clampf(-c * frcp(a), 0.f, 1.f);
     } else if (t > 1.f) {
         t = 1.f;
-        s = clampf((b - c) / a, 0.f, 1.f);
+        s = clampf((b - c) * frcp(a), 0.f, 1.f);
     }
 }
 
@@ -340,8 +340,8 @@ __device__ inline Contact3 obox_box(V3 c, const Rot3 &R, V3 h, V3 cb, V3 hb)
         for (int j = 0; j < 3; ++j) {
             const V3 e = v3(j == 0 ? 1.f : 0.f, j == 1 ? 1.f : 0.f, j == 2 ? 1.f : 0.f);
             const V3 x = cross(Rcol(R, i), e);
-            const float len = sqrtf(dot(x, x));
-            if (len >= 1e-9f) axis((1.0f / len) * x);
+            const float len = fsqrt(dot(x, x));
+            if (len >= 1e-9f) axis(frcp(len) * x);
         }
     Contact3 out;
     out.phi = best;

@@ -30,6 +30,14 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b)
 }
 __device__ __forceinline__ V3 fma3(float s, V3 a, V3 b) { return V3{fmaf(s, a.x, b.x), fmaf(s, a.y, b.y), fmaf(s, a.z, b.z)}; }
 
+// Hardware reciprocal and square root (v_rcp_f32, v_sqrt_f32: about 1 ulp;
+// a denormal argument flushes to zero) in place of the library sequences
+// that rescale denormal arguments: every argument they take here is a normal
+// float (masses, squared lengths of links, pivots of the contact rows) or
+// sits behind a threshold well above the denormal range.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Symmetric 3x3: xx yy zz xy xz yz
 struct S3 {
     float xx, yy, zz, xy, xz, yz;
@@ -118,7 +126,7 @@ __device__ inline void crba_arm(const DevModel &md, int arm, const ArmKin &k, fl
         const float mi = md.m[arm][j];
         const V3 ci = fma3(0.5f * md.link_len[j], k.z[j], k.o[j]);
         const float mn = mi + mc;
-        const V3 ccn = (1.0f / mn) * (mi * ci + mc * cc);
+        const V3 ccn = frcp(mn) * (mi * ci + mc * cc);
         // link inertia about its own centre: Ix (1 - z z^T) + Iz z z^T
         const float ix = md.Ix[arm][j], dz = md.Iz[arm][j] - ix;
         const V3 z = k.z[j];

@@ -38,7 +38,7 @@ namespace mppi {
 __device__ __forceinline__ void tangents(V3 n, V3 &t1, V3 &t2)
 {
     const float sg = n.z >= 0.f ? 1.f : -1.f;
-    const float a = -1.0f / (sg + n.z);
+    const float a = -frcp(sg + n.z);
     const float b = n.x * n.y * a;
     t1 = v3(1.0f + sg * n.x * n.x * a, sg * b, -sg * n.x);
     t2 = v3(b, sg + n.y * n.y * a, -n.y);
@@ -448,7 +448,7 @@ __device__ inline void contact_solve(const DevModel &md, const ArmKin kin[2], co
                 S.ge[s][q] = mul9(S.G[s][s], e);
                 const float aqq = dot(e, S.ge[s][q]);
                 S.rr[s][q] = md.eps_r * aqq;
-                S.dinv[s][q] = 1.0f / (aqq + S.rr[s][q]);
+                S.dinv[s][q] = frcp(aqq + S.rr[s][q]);
                 S.lam[s][q] = 0.f;
             }
         }
@@ -570,7 +570,7 @@ __device__ inline void ball_contact_solve(const DevModel &md, const LaneList &LL
 #pragma unroll
         for (int c = 0; c < 4; ++c) a[4 * q + c] = dot(e[q], ge[c]);
         rr[q] = md.eps_r * a[5 * q];
-        dd[q] = 1.0f / (a[5 * q] + rr[q]);
+        dd[q] = frcp(a[5 * q] + rr[q]);
         b[q] = dot(e[q], bfree) - bias;
         f[q] = 0.f;
     }

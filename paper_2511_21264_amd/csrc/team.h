@@ -314,7 +314,7 @@ __device__ inline void team_composite(const DevModel &md, const JointConst &jc, 
     const V3 h = seg_suffix3(m * cr, jt);
 #pragma unroll
     for (int i = 0; i < 6; ++i) I[i] = seg_suffix(I[i], jt);
-    const V3 cc = (joint ? 1.0f / Mc : 0.f) * h;
+    const V3 cc = (joint ? frcp(Mc) : 0.f) * h;
     const float c2 = dot(cc, cc);
     const S3 Ic = {I[0] - Mc * (c2 - cc.x * cc.x), I[1] - Mc * (c2 - cc.y * cc.y), I[2] - Mc * (c2 - cc.z * cc.z),
                    I[3] + Mc * cc.x * cc.y,        I[4] + Mc * cc.x * cc.z,        I[5] + Mc * cc.y * cc.z};
@@ -1049,7 +1049,7 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
         const float rq = md.eps_r * aqq;
 #pragma unroll
         for (int c = 0; c < 16; ++c) arow[c] += c == q ? rq : 0.f;
-        const float dq = 1.0f / (aqq + rq);
+        const float dq = frcp(aqq + rq);
         const float bq = dot(eq, v3(es[16], es[17], es[18])) - es[15];
         float f16[16];
         pgs_team(arow, bq, dq, m, q, md.n_pgs, f16);
@@ -1078,7 +1078,7 @@ __device__ inline void team_contact_solve(const DevModel &md, const TeamCtx &tc,
             const float arr = A[r * MR + r];
             const float rr = md.eps_r * arr;
             Rv[r] = rr;
-            Dv[r] = 1.0f / (arr + rr);
+            Dv[r] = frcp(arr + rr);
             Bv[r] = dot(eq, v3(es[16], es[17], es[18])) - es[15];
         }
         wave_lds_sync();
@@ -1451,7 +1451,7 @@ __device__ inline void team_contact_solve_rows(const DevModel &md, const TeamCtx
     const float rq = md.eps_r * aqq;
 #pragma unroll
     for (int c = 0; c < 16; ++c) arow[c] += c == q ? rq : 0.f;
-    const float dq = 1.0f / (aqq + rq);
+    const float dq = frcp(aqq + rq);
     const float bq = dot(eq, v3(es[16], es[17], es[18])) - es[15];
     float f[16];
     pgs_team(arow, bq, dq, m, q, md.n_pgs, f);
