@@ -112,7 +112,8 @@ typedef struct mppi_scene mppi_scene;
  * rotates about local axis axes[i] (0 x, 1 y, 2 z); links 1..6 collide as
  * capsules of radius link_rad[i], link 7 as a pad sphere of radius pad_rad at
  * its tip; each link's inertia is a solid capsule of density[arm][i].  Arm
- * bases at base_pos with yaw given as (cos, sin).  Ball: solid sphere.
+ * bases at base_pos with yaw given as (cos, sin), a unit pair (within 1e-6,
+ * else MPPI_E_MODEL).  Ball: solid sphere.
  * Boxes: static, axis-aligned (centre, half extents).  Table: plane z = 0.
  * Physics (the paper fixes none of it; these are the world-model readings):
  * substep h, n_sub substeps per control step; PD actuators (kp, kd, clamp

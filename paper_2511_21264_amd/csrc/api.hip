@@ -136,6 +136,11 @@ int build_model(const mppi_scene_desc *d, DevModel &m)
     if (d->kd < 0 || d->damp < 0 || d->kp < 0 || !(d->tau_max > 0)) return fail(MPPI_E_MODEL, "gains must be >= 0, tau_max > 0");
     if (!(d->u_max > 0) || d->mu < 0 || d->kappa < 0 || d->eps_r < 0) return fail(MPPI_E_MODEL, "bad contact or control bounds");
     if (!(d->m_c > 0) || !(d->gamma > 0 && d->gamma < 1)) return fail(MPPI_E_MODEL, "need m_c > 0 and 0 < gamma < 1");
+    for (int a = 0; a < 2; ++a) {
+        const double c = d->base_cs[a][0], s = d->base_cs[a][1];
+        if (!(std::fabs(c * c + s * s - 1.0) <= 1e-6))
+            return fail(MPPI_E_MODEL, "base_cs[%d] must be the (cos, sin) of a yaw", a);
+    }
     std::memset(&m, 0, sizeof m);
     for (int a = 0; a < 2; ++a) {
         for (int i = 0; i < 3; ++i) m.base_pos[a][i] = (float)d->base_pos[a][i];
